@@ -1,0 +1,92 @@
+"""The SCALE amplitude psi(n) = det Phi(n), evaluated from scratch in FP64
+(Sec. II.B).
+
+  embedding   H0[s]   = E[n_s]                 (Sec. II.B, embedding layer;
+                                                one table shared by all sites)
+  conv layer  H_l[s]  = H_{l-1}[s] + act(b_l + sum_{taps} K_l[tap] H_{l-1}[s+tap])
+                                               (Sec. II.B, residual conv
+                                                equation; stacked n_conv times,
+                                                padding follows the lattice
+                                                boundary: wrap on periodic axes,
+                                                zeros on open axes)
+  projection  row_s(s) = base_s[s] + H_L[s] W_s + b_s
+                                               (Sec. II.B, orbital projection,
+                                                one block per spin)
+  amplitude   psi(n) = det Phi_up * det Phi_dn, Phi_s = rows of the sites
+              occupied by spin s, in ascending site order.
+
+Kernel layout K_l[ky, kx, c_in, c_out]: tap (ky, kx) reads the neighbour at
+offset (kx - 1, ky - 1), i.e. a cross-correlation as in common conv layers.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from .lattice import neighbour
+
+
+def activation(name: str, x: np.ndarray) -> np.ndarray:
+    if name == "tanh":
+        return np.tanh(x)
+    if name == "silu":
+        return x / (1.0 + np.exp(-x))
+    raise ValueError(name)
+
+
+def tap_tables(lat) -> list:
+    """For each of the 9 taps (ky, kx) in row-major order, an int array
+    nb[s] of the neighbour site at offset (kx-1, ky-1), -1 off an open edge."""
+    tabs = []
+    for ky in range(3):
+        for kx in range(3):
+            tabs.append(np.array([neighbour(lat, s, kx - 1, ky - 1)
+                                  for s in range(lat.N)], dtype=np.int64))
+    return tabs
+
+
+def features(lat, params, occ, act: str = "tanh") -> list:
+    """[H_0, H_1, ..., H_L], each [N, C] FP64."""
+    H = params.embed[np.asarray(occ, dtype=np.int64)].astype(np.float64)
+    out = [H]
+    tabs = tap_tables(lat)
+    L = params.conv_w.shape[0]
+    for l in range(L):
+        acc = np.tile(params.conv_b[l], (lat.N, 1))
+        for t, nb in enumerate(tabs):
+            ky, kx = divmod(t, 3)
+            valid = nb >= 0
+            x = np.zeros_like(H)
+            x[valid] = H[nb[valid]]
+            acc = acc + x @ params.conv_w[l, ky, kx]
+        H = H + activation(act, acc)
+        out.append(H)
+    return out
+
+
+def orbital_rows(params, lat_index: int, HL: np.ndarray, spin: int) -> np.ndarray:
+    """All N backflow orbital rows of one spin: [N, N_spin]."""
+    return (params.base[lat_index][spin] + HL @ params.proj_w[lat_index][spin]
+            + params.proj_b[lat_index][spin][None, :])
+
+
+def occupied_sites(occ, spin: int) -> np.ndarray:
+    bit = 1 << spin
+    return np.nonzero(np.asarray(occ) & bit)[0]
+
+
+def slater_matrices(lat, params, occ, lat_index: int = 0, act: str = "tanh"):
+    HL = features(lat, params, occ, act)[-1]
+    return [orbital_rows(params, lat_index, HL, s)[occupied_sites(occ, s)]
+            for s in (0, 1)]
+
+
+def log_psi(lat, params, occ, lat_index: int = 0, act: str = "tanh"):
+    """(sign, log|psi|) with canonical (site-ascending) row order."""
+    sign, logabs = 1.0, 0.0
+    for Phi in slater_matrices(lat, params, occ, lat_index, act):
+        if Phi.shape[0] == 0:
+            continue
+        s, la = np.linalg.slogdet(Phi)
+        sign *= s
+        logabs += la
+    return sign, logabs
