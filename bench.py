@@ -1,0 +1,302 @@
+#!/usr/bin/env python
+"""Benchmark of the SCALE local-energy hot path on one MI355X.
+
+Workload (default): Hubbard 16x16, periodic-x / open-y, t = 1, U = 8,
+112 + 112 electrons (1/8 hole doping), 4 residual 3x3 conv layers x 32
+channels, 8192 walkers, seeded synthetic parameters and occupations.
+
+One step = the whole low-rank hot path over the batch: per-walker precompute
+(orbital rows, G = M Phi^-1, P = W Phi^-1) + the low-rank local-energy
+kernel (hop enumeration, incremental conv on the matrix units, FP64
+determinant-lemma ratios, reduction).  Inputs are resident in HBM before
+the timed region.  Also measured: the full-recompute path on the same
+walkers (speed-up), the oracle on host cores (cpu_baseline), and the
+roofline position of the dominant kernel from HIP events on its stream.
+
+    python bench.py [--gpus 1] [--steps 10] [--warmup 2] [--prec bf16x3]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+from dataclasses import replace
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_BF16 = 2.5e15      # dense MFMA, FLOP/s
+PEAK_FP64 = 78.6e12
+PEAK_FP32 = 157.3e12
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+# ---------------------------------------------------------------------------
+# algorithmic work of the low-rank kernel (accounting only, numpy)
+# ---------------------------------------------------------------------------
+def lowrank_flops(lat, occ: np.ndarray, L: int, C: int):
+    """(conv FLOPs, FP64 determinant FLOPs) of one low-rank local-energy
+    launch: per hop, layer l recomputes the sites within Chebyshev distance l
+    of the two changed sites (9 C^2 multiply-adds each); per spin, k electrons
+    of the new configuration lie within distance L, the determinant-lemma
+    matrix has rank r = min(k, C + [moving spin]), its assembly costs k C r
+    and its LU r^3 / 3 multiply-adds."""
+    W, N = occ.shape
+    Lx, Ly = lat.Lx, lat.Ly
+    nd = 8 if lat.tp != 0.0 else 4
+    DX = [1, -1, 0, 0, 1, 1, -1, -1]
+    DY = [0, 0, 1, -1, 1, -1, 1, -1]
+    grid = occ.reshape(W, Ly, Lx)
+    ups = (grid & 1).astype(np.int64)
+    dns = ((grid >> 1) & 1).astype(np.int64)
+
+    def sat(a):
+        # summed-area table of a tiled 3x3 copy (handles wrap on periodic axes)
+        t = np.tile(a, (1, 3, 3))
+        s = np.zeros((W, 3 * Ly + 1, 3 * Lx + 1), np.int64)
+        s[:, 1:, 1:] = t.cumsum(1).cumsum(2)
+        return s
+
+    sat_u, sat_d = sat(ups), sat(dns)
+    xs, ys = np.meshgrid(np.arange(Lx), np.arange(Ly))
+    xs, ys = xs.ravel(), ys.ravel()
+    conv = 0.0
+    det = 0.0
+
+    def axis_range(c0, c1, l, La, per):
+        lo, hi = np.minimum(c0, c1) - l, np.maximum(c0, c1) + l
+        if per:
+            w = np.minimum(hi - lo + 1, La)
+            return lo, w
+        lo2, hi2 = np.maximum(lo, 0), np.minimum(hi, La - 1)
+        return lo2, hi2 - lo2 + 1
+
+    def box_count(s, x0, wx, y0, wy):
+        # x0, y0 may be negative on periodic axes: shift into the middle copy
+        X0 = x0 + Lx
+        Y0 = y0 + Ly
+        wi = np.arange(W)[:, None]
+        return (s[wi, Y0 + wy, X0 + wx] - s[wi, Y0, X0 + wx] - s[wi, Y0 + wy, X0] + s[wi, Y0, X0])
+
+    for sp in (0, 1):
+        mine = ups if sp == 0 else dns
+        for d in range(nd):
+            xj, yj = xs + DX[d], ys + DY[d]
+            okx = (xj >= 0) & (xj < Lx) if not lat.pbc_x else np.ones_like(xj, bool)
+            oky = (yj >= 0) & (yj < Ly) if not lat.pbc_y else np.ones_like(yj, bool)
+            ok = okx & oky
+            xjw, yjw = xj % Lx, yj % Ly
+            jsite = np.where(ok, xjw + Lx * yjw, 0)
+            src = mine.reshape(W, N)
+            valid = (src == 1) & ok[None, :] & (src[:, jsite] == 0)     # [W, N]
+            nh = valid.sum()
+            if nh == 0:
+                continue
+            # conv work: layer boxes (the union of two Chebyshev balls; a
+            # rectangle for nearest-neighbour hops)
+            for l in range(1, L + 1):
+                _, wx = axis_range(xs, xj, l, Lx, lat.pbc_x)
+                _, wy = axis_range(ys, yj, l, Ly, lat.pbc_y)
+                sites = wx * wy
+                if DX[d] != 0 and DY[d] != 0:
+                    # diagonal hop: two (2l+1)^2 squares overlapping
+                    sites = np.minimum(sites, 2 * (2 * l + 1) ** 2 - (2 * l) ** 2)
+                conv += float((valid * sites[None, :]).sum()) * 9 * C * C * 2
+            x0, wx = axis_range(xs, xj, L, Lx, lat.pbc_x)
+            y0, wy = axis_range(ys, yj, L, Ly, lat.pbc_y)
+            ku = box_count(sat_u, x0[None, :], wx[None, :], y0[None, :], wy[None, :])
+            kd = box_count(sat_d, x0[None, :], wx[None, :], y0[None, :], wy[None, :])
+            for tau, k in ((0, ku), (1, kd)):
+                r = np.minimum(k, C + (1 if tau == sp else 0))
+                fma = k * C * r + r ** 3 / 3.0
+                det += 2.0 * float((valid * fma).sum())
+    return conv, det
+
+
+# ---------------------------------------------------------------------------
+# oracle baseline on host cores
+# ---------------------------------------------------------------------------
+_CPU = {}
+
+
+def _cpu_init(lat, params, act):
+    try:
+        from threadpoolctl import threadpool_limits
+        threadpool_limits(1)
+    except Exception:
+        pass
+    _CPU.update(lat=lat, params=params, act=act)
+
+
+def _cpu_eloc(o):
+    from oracle.energy import local_energy
+    return local_energy(_CPU["lat"], _CPU["params"], o, 0, _CPU["act"])
+
+
+def cpu_baseline(lat, params, occ, act, n_sample):
+    import multiprocessing as mp
+    cores = max(1, min(os.cpu_count() or 1, 16, n_sample))
+    sample = occ[:n_sample]
+    ctx = mp.get_context("fork")
+    t0 = time.perf_counter()
+    with ctx.Pool(cores, initializer=_cpu_init, initargs=(lat, params, act)) as pool:
+        e = pool.map(_cpu_eloc, list(sample), chunksize=1)
+    dt = time.perf_counter() - t0
+    return np.array(e), dt, cores
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+# ---------------------------------------------------------------------------
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="c3")
+    ap.add_argument("--prec", default="bf16x3", choices=["bf16", "bf16x3", "f32", "f64"])
+    ap.add_argument("--walkers", type=int, default=None)
+    ap.add_argument("--full-walkers", type=int, default=None,
+                    help="walkers for the full-recompute timing (default: all)")
+    ap.add_argument("--cpu-sample", type=int, default=24)
+    ap.add_argument("--no-full", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    a = ap.parse_args()
+    if a.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for {a.gpus}); the walker-parallel "
+              f"multi-GPU design is described in DESIGN.md but not run here.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import workloads as wls
+    from paper_2604_25775_amd.api import ScaleVMC
+
+    wl = wls.get(a.workload)
+    lat = wl.lattices[0]
+    model = replace(wl.model, conv_prec=a.prec)
+    W = a.walkers or wl.walkers[0]
+    log(f"[bench] workload {wl.name}: {wl.description}; walkers {W}, conv {a.prec}")
+    params = wls.quantise_params(wls.random_params([lat], model, seed=wl.seed_params), a.prec)
+    occ = wls.occupations(wl, 0, n_walkers=W)
+
+    ctx = ScaleVMC([lat], model.n_conv, model.channels, model.act, a.prec, model.refresh_every)
+    ctx.set_params_from(params)
+    ctx.load([W], occ)
+    torch.cuda.synchronize()
+    eloc = torch.empty(W, dtype=torch.float64, device="cuda")
+
+    for _ in range(a.warmup):
+        ctx.prepare()
+        ctx.local_energy(out=eloc)
+    torch.cuda.synchronize()
+    log(f"[bench] warmup done ({a.warmup} steps)")
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(a.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(a.steps):
+        evs[k][0].record()
+        ctx.prepare()
+        evs[k][1].record()
+        ctx.local_energy(out=eloc)
+        evs[k][2].record()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_step = (t1 - t0) / a.steps * 1e3
+    prep_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in evs]))
+    kern_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in evs]))
+    value = W / (ms_step / 1e3)
+    log(f"[bench] {a.steps} steps: {ms_step:.3f} ms/step, precompute {prep_ms:.3f} ms, "
+        f"E_loc kernel {kern_ms:.3f} ms -> {value:.1f} E_loc/s")
+    e_gpu = eloc.cpu().numpy()
+    flags = ctx.flags().cpu().numpy()
+
+    conv_f, det_f = lowrank_flops(lat, occ, model.n_conv, model.channels)
+    conv_peak = PEAK_BF16 if a.prec in ("bf16", "bf16x3") else (PEAK_FP32 if a.prec == "f32" else PEAK_FP64)
+    passes = 3 if a.prec == "bf16x3" else 1
+    t_peak = conv_f * passes / conv_peak + det_f / PEAK_FP64
+    achieved = (conv_f + det_f) / (kern_ms / 1e3) / 1e12
+    peak = (conv_f + det_f) / t_peak / 1e12
+    roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": round(peak, 3),
+                "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
+                "kernel": "k_eloc_lowrank",
+                "flops_conv_per_launch": conv_f, "flops_fp64_per_launch": det_f,
+                "conv_passes": passes,
+                "peak_model": "time at peak = conv/(%.4g) + fp64/(%.4g)" % (conv_peak / passes, PEAK_FP64)}
+    log(f"[bench] roofline: conv {conv_f / 1e12:.3f} TFLOP + fp64 {det_f / 1e12:.3f} TFLOP per launch; "
+        f"t_peak {t_peak * 1e3:.3f} ms vs {kern_ms:.3f} ms -> frac {achieved / peak:.4f}")
+
+    extra = {"prepare_ms": round(prep_ms, 4), "eloc_kernel_ms": round(kern_ms, 4),
+             "walkers_flagged": int(np.count_nonzero(flags))}
+    if not a.no_full:
+        FW = a.full_walkers or W
+        if FW == W:
+            fctx = ctx
+        else:
+            fctx = ScaleVMC([lat], model.n_conv, model.channels, model.act, a.prec, model.refresh_every)
+            fctx.set_params_from(params)
+            fctx.load([FW], occ[:FW])
+        feloc = torch.empty(FW, dtype=torch.float64, device="cuda")
+        log(f"[bench] full-recompute path on {FW} walkers ...")
+        fctx.local_energy("full", out=feloc)      # warm
+        torch.cuda.synchronize()
+        f0 = torch.cuda.Event(enable_timing=True)
+        f1 = torch.cuda.Event(enable_timing=True)
+        f0.record()
+        fctx.local_energy("full", out=feloc)
+        f1.record()
+        torch.cuda.synchronize()
+        full_ms = f0.elapsed_time(f1)
+        full_rate = FW / (full_ms / 1e3)
+        ef = feloc.cpu().numpy()
+        agree = float(np.max(np.abs(ef - e_gpu[:FW]) / np.maximum(1.0, np.abs(ef))))
+        extra.update({"full_recompute_eloc_per_s": round(full_rate, 1), "full_recompute_walkers": FW,
+                      "full_recompute_ms": round(full_ms, 3),
+                      "speedup_vs_full": round(value / full_rate, 3),
+                      "speedup_kernel_only": round((FW / (full_ms / 1e3)) and (W / (kern_ms / 1e3)) / full_rate, 3),
+                      "lowrank_vs_full_max_rel_diff": agree})
+        log(f"[bench] full path: {full_ms:.1f} ms for {FW} walkers -> {full_rate:.1f} E_loc/s; "
+            f"speed-up {value / full_rate:.2f}x; max |dE|/E lowrank vs full {agree:.2e}")
+
+    cpu = None
+    if not a.no_cpu and a.cpu_sample > 0:
+        log(f"[bench] oracle on host cores, {a.cpu_sample} walkers ...")
+        e_ref, dt, cores = cpu_baseline(lat, params, occ, model.act, a.cpu_sample)
+        err = float(np.max(np.abs(e_gpu[:len(e_ref)] - e_ref) / np.maximum(1.0, np.abs(e_ref))))
+        cpu = {"value": round(len(e_ref) / dt, 3), "unit": "E_loc/s", "cores": cores, "kind": "oracle",
+               "sample": f"first {len(e_ref)} walkers of the same batch, full FP64 recompute per hop "
+                         f"({dt:.1f} s wall on {cores} processes, {cpu_model()})"}
+        extra["max_rel_err_eloc_vs_oracle"] = err
+        log(f"[bench] oracle {len(e_ref) / dt:.3f} E_loc/s on {cores} cores; max rel err of GPU E_loc {err:.2e}")
+
+    line = {
+        "metric": "local-energy evals/sec at 16x16 1/8-doped; speedup vs full-recompute",
+        "value": round(value, 1), "unit": "E_loc/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+        "ms_per_step": round(ms_step, 4), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": f"{a.prec}+f64", "data": "synthetic",
+        "config": {"workload": f"{wl.name}: Hubbard {lat.Lx}x{lat.Ly} pbc_x={lat.pbc_x} pbc_y={lat.pbc_y} "
+                               f"U={lat.U} t'={lat.tp} n={lat.n_up}+{lat.n_dn}, {model.n_conv} conv x "
+                               f"{model.channels} ch, {W} walkers",
+                   "walkers": W, "conv_prec": a.prec, **extra},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,210 @@
+/*
+ * scalevmc — C ABI of the SCALE local-energy hot path on one AMD MI355X (gfx950).
+ *
+ * What is computed (arXiv 2604.25775):
+ *   amplitude   psi(n) = det Phi_up(n) * det Phi_dn(n), with configuration-
+ *               dependent backflow orbitals from an embedding, a stack of
+ *               residual 3x3 convolutions and an orbital projection
+ *               (Sec. II.B: embedding layer, residual conv equation, orbital
+ *               projection; one Slater block per spin).
+ *   ratios      psi(n')/psi(n) for every configuration n' reached from n by one
+ *               hopping term of the Hubbard Hamiltonian (Sec. III), evaluated by
+ *               recomputing only the features inside the receptive field of the
+ *               hop (Sec. II.C, affected-sites equation) and a low-rank
+ *               determinant update against the cached inverse (Sec. II.C,
+ *               Sherman-Morrison-Woodbury equations).
+ *   local energy E_loc(n) = sum_n' psi(n)^-1 <n|H|n'> psi(n')   (Sec. II.A).
+ *
+ * Conventions shared by every call:
+ *  - Lattice sites s = x + Lx*y (x fastest).  Occupation byte per site:
+ *    n_up + 2*n_dn (0 empty, 1 up, 2 down, 3 double).
+ *  - Walkers are ordered lattice-major: all walkers of lattice 0, then of
+ *    lattice 1, ...  Walker w of lattice l owns N_l occupation bytes.
+ *  - Every pointer documented as "device" is HIP device memory owned by the
+ *    caller; the library never frees it and reads it only during the call's
+ *    stream work.  Host pointers are read before the call returns.
+ *  - All calls enqueue work on `stream` and return without synchronising
+ *    (except svmc_load_walkers' validation, see there); outputs are valid once
+ *    the stream reaches the call.  Calls on one context must not overlap.
+ *  - No call aborts.  Argument errors return SVMC_ERR_INVALID_ARG and leave the
+ *    context unchanged; svmc_last_error() gives a message.  Numerical trouble of
+ *    a single walker never fails a call: it sets that walker's flag bits
+ *    (svmc_walker_flags).
+ *  - Floating-point: the determinant work (inverses, log-determinants, the
+ *    small Woodbury systems, ratios, energies) is FP64.  The conv stack runs in
+ *    svmc_model.conv_prec; the library rounds the embedding, conv kernels and
+ *    conv biases to that precision (round to nearest even).  Projection
+ *    weights and base orbitals are used in FP64.
+ */
+#ifndef SCALEVMC_H
+#define SCALEVMC_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct svmc_ctx svmc_ctx;
+
+typedef enum {
+  SVMC_OK = 0,
+  SVMC_ERR_INVALID_ARG = 1,
+  SVMC_ERR_OOM = 2,
+  SVMC_ERR_HIP = 3,
+  SVMC_ERR_STATE = 4,        /* call order: e.g. local energy before walkers */
+  SVMC_ERR_UNSUPPORTED = 5   /* valid but not implemented shape */
+} svmc_status;
+
+/* Per-walker flag bits. */
+typedef enum {
+  SVMC_W_OK = 0,
+  SVMC_W_SINGULAR = 1,   /* a Slater block has a zero pivot: psi = 0 */
+  SVMC_W_NONFINITE = 2,  /* a NaN/Inf appeared in log|psi| or a ratio */
+  SVMC_W_DRIFT = 4,      /* Woodbury-updated inverse drifted beyond 1e-8 */
+  SVMC_W_BADCOUNT = 8    /* occupation does not hold n_up/n_dn electrons */
+} svmc_walker_flag;
+
+typedef enum { SVMC_ACT_TANH = 0, SVMC_ACT_SILU = 1 } svmc_act;
+/* Conv-stack precision.  BF16: multiplier inputs rounded to BF16, FP32
+ * accumulation, FP32 residual stream.  BF16X3: each FP32 activation is split
+ * exactly into three BF16 terms multiplied in three passes (FP32-accurate
+ * activations on the BF16 matrix units); weights are BF16 in both. */
+typedef enum { SVMC_FP64 = 0, SVMC_FP32 = 1, SVMC_BF16 = 2, SVMC_BF16X3 = 3 } svmc_prec;
+typedef enum { SVMC_PATH_LOWRANK = 0, SVMC_PATH_FULL = 1 } svmc_path;
+
+/* Hubbard lattice (Sec. III, Hubbard Hamiltonian): Lx x Ly sites, periodic or
+ * open per axis (a periodic axis needs length >= 3), hopping t (nearest
+ * neighbours) and tp (next-nearest; 0 disables those hops), on-site U,
+ * electrons per spin n_up, n_dn (each <= N). */
+typedef struct {
+  int32_t Lx, Ly, pbc_x, pbc_y;
+  double t, tp, U;
+  int32_t n_up, n_dn;
+} svmc_lattice;
+
+/* Network shape (Sec. II.B): n_conv residual 3x3 conv layers (1..4) of
+ * `channels` channels (8, 16, 24 or 32), activation svmc_act, conv precision
+ * svmc_prec; refresh_every = accepted Metropolis moves between FP64 inverse
+ * rebuilds (>= 1). */
+typedef struct {
+  int32_t n_conv, channels, act, conv_prec, refresh_every;
+} svmc_model;
+
+/* Create a context for n_lats lattices (1..8) sharing one network.  Lattices
+ * may differ in size and electron numbers; the conv stack and embedding are
+ * shared, projection and base orbitals are per lattice.  *out receives the
+ * handle.  Errors: INVALID_ARG for bad shapes, UNSUPPORTED for channels or
+ * depths outside the list above, HIP if no device is usable. */
+svmc_status svmc_create(const svmc_lattice* lats, int32_t n_lats,
+                        const svmc_model* model, svmc_ctx** out);
+
+/* Release all device memory of the context (waits for its work). */
+svmc_status svmc_destroy(svmc_ctx* ctx);
+
+/* Length of the flat parameter vector theta:
+ *   embed[4][C] | conv_w[L][3][3][C][C] (ky, kx, c_in, c_out; tap (ky,kx)
+ *   reads the neighbour at offset (kx-1, ky-1)) | conv_b[L][C] |
+ *   for each lattice: W_up[C][n_up] | W_dn[C][n_dn] | b_up[n_up] | b_dn[n_dn]
+ * all row-major FP64.  Row of spin s at site x:  base_s[x] + H_L[x] W_s + b_s. */
+int64_t svmc_num_params(const svmc_ctx* ctx);
+
+/* Upload parameters.  theta: device, svmc_num_params doubles (layout above).
+ * base: host array of n_lats device pointers; base[l] holds the FP64 base
+ * orbitals of lattice l: [N][n_up] for spin up followed by [N][n_dn] for
+ * spin down (row = site).  Invalidates walker caches (reload or refresh). */
+svmc_status svmc_set_params(svmc_ctx* ctx, const double* theta,
+                            const double* const* base, hipStream_t stream);
+
+/* Load walkers.  walkers_per_lattice: host [n_lats] counts (>= 0, total >= 1).
+ * occ: device int8, concatenated walker occupations (lattice-major).  Builds
+ * the feature cache, Slater inverses, log|psi| and the low-rank precompute.
+ * Validates electron counts on the device; a walker whose count is wrong gets
+ * SVMC_W_BADCOUNT and psi = 0.  Requires svmc_set_params first. */
+svmc_status svmc_load_walkers(svmc_ctx* ctx, const int64_t* walkers_per_lattice,
+                              const int8_t* occ, hipStream_t stream);
+
+int64_t svmc_num_walkers(const svmc_ctx* ctx);
+
+/* Row stride of the per-hop outputs of svmc_local_energy: the largest number
+ * of hops any walker can have, (n_up + n_dn) * (tp != 0 ? 8 : 4), over lattices. */
+int32_t svmc_max_hops(const svmc_ctx* ctx);
+
+/* log|psi| and its sign for every walker.  sign: canonical sign, i.e. with the
+ * rows of each Slater block in ascending site order (ups before downs).
+ * Both device [W] FP64. */
+svmc_status svmc_log_psi(svmc_ctx* ctx, double* sign, double* logabs,
+                         hipStream_t stream);
+
+/* Low-rank precompute for every walker from its current features and
+ * inverses: orbital rows of all sites M_s, G_s = M_s Phi_s^-1 and
+ * P_s = W_s Phi_s^-1 (the factors of the determinant-lemma matrices,
+ * Sec. II.C).  svmc_local_energy(LOWRANK) runs it by itself when walkers
+ * changed since the last one; calling it explicitly always recomputes. */
+svmc_status svmc_prepare(svmc_ctx* ctx, hipStream_t stream);
+
+/* Local energies (Sec. II.A) with the Hubbard Hamiltonian (Sec. III).
+ * path LOWRANK: incremental features + Woodbury ratios against the cached
+ * inverses (Sec. II.C); FULL: every connected configuration recomputed from
+ * scratch (full network forward and an FP64 LU per spin) - the O(N^4)
+ * comparison path with the same precision policy.
+ * eloc: device [W] FP64.  Optional (NULL to skip, all or none):
+ *   n_hops   device [W] int32   number of connected configurations
+ *   hop_code device [W][svmc_max_hops] int32, code = (i << 4) | (spin << 3) | d
+ *            with i the site the electron leaves, spin 0 up / 1 down, and d the
+ *            direction +x, -x, +y, -y, +x+y, +x-y, -x+y, -x-y (0..7)
+ *   ratio    device [W][svmc_max_hops] FP64: det ratio with the moving
+ *            electron keeping its row ("in-place"), so that the Hamiltonian
+ *            term of the hop is -t_ij * ratio.
+ * Hops are listed spin up first, source site ascending, directions in the
+ * order above.  The U term is U * (number of doubly occupied sites). */
+svmc_status svmc_local_energy(svmc_ctx* ctx, svmc_path path, double* eloc,
+                              int32_t* n_hops, int32_t* hop_code, double* ratio,
+                              hipStream_t stream);
+
+/* Metropolis sampling of |psi|^2 (Sec. II.A), n_sweeps sweeps of N proposals
+ * per walker.  Proposal k of walker w draws one Philox4x64-10 block with key
+ * (seed, 0) and counter (w, step0 + k, 0, 0): electron e = mulhi(w0, n_up +
+ * n_dn) (labels of spin up first), direction d = w1 >> 62 (+x, -x, +y, -y),
+ * u = (w2 >> 11) 2^-53; the move is rejected when the target is off the
+ * lattice or holds the same spin, else accepted iff u < ratio^2.  Accepted
+ * moves update features, inverses (Woodbury), log|psi|; every refresh_every
+ * accepted moves a walker's inverse is rebuilt in FP64.  n_accept: device
+ * [W] int64, incremented (not cleared) by the number of accepted moves. */
+svmc_status svmc_sweep(svmc_ctx* ctx, int32_t n_sweeps, uint64_t seed,
+                       uint64_t step0, int64_t* n_accept, hipStream_t stream);
+
+/* Rebuild every walker's Slater inverse, log|psi| and low-rank precompute in
+ * FP64 from the cached features (sets SVMC_W_DRIFT where the old inverse had
+ * drifted). */
+svmc_status svmc_refresh(svmc_ctx* ctx, hipStream_t stream);
+
+/* Current configurations.  occ: device int8 (same layout as load); pos
+ * (optional): device int16 [W][2][svmc_max_electrons], the site of each
+ * electron label (labels start in ascending site order and keep their
+ * identity through Metropolis moves), -1 padded. */
+svmc_status svmc_get_state(svmc_ctx* ctx, int8_t* occ, int16_t* pos,
+                           hipStream_t stream);
+int32_t svmc_max_electrons(const svmc_ctx* ctx);
+
+/* d log|psi_w| / d theta (theta layout of svmc_num_params), FP64.
+ * vjp_w == NULL: out is device [W][n_params], one row per walker.
+ * vjp_w != NULL (device [W]): out is device [n_params] = sum_w vjp_w[w] *
+ * d log|psi_w|/d theta.  Uses the determinant derivative
+ * d log|det Phi| = tr(Phi^-1 dPhi) and back-propagation through the
+ * projection and conv stack. */
+svmc_status svmc_grad_logpsi(svmc_ctx* ctx, const double* vjp_w, double* out,
+                             hipStream_t stream);
+
+/* Per-walker flag bits (svmc_walker_flag), device [W] int32. */
+svmc_status svmc_walker_flags(svmc_ctx* ctx, int32_t* flags, hipStream_t stream);
+
+const char* svmc_status_string(svmc_status s);
+/* Message of the last error on this context ("" if none). */
+const char* svmc_last_error(const svmc_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SCALEVMC_H */

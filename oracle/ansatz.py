@@ -44,19 +44,24 @@ def tap_tables(lat) -> list:
     return tabs
 
 
-def features(lat, params, occ, act: str = "tanh") -> list:
-    """[H_0, H_1, ..., H_L], each [N, C] FP64."""
+def features(lat, params, occ, act: str = "tanh", conv_input_round=None) -> list:
+    """[H_0, H_1, ..., H_L], each [N, C] FP64.
+
+    conv_input_round: optional function applied to the layer input before it
+    enters the convolution (not to the residual branch); used to model a conv
+    whose multiplier inputs are rounded to a narrower format."""
     H = params.embed[np.asarray(occ, dtype=np.int64)].astype(np.float64)
     out = [H]
     tabs = tap_tables(lat)
     L = params.conv_w.shape[0]
     for l in range(L):
         acc = np.tile(params.conv_b[l], (lat.N, 1))
+        Hin = H if conv_input_round is None else conv_input_round(H)
         for t, nb in enumerate(tabs):
             ky, kx = divmod(t, 3)
             valid = nb >= 0
             x = np.zeros_like(H)
-            x[valid] = H[nb[valid]]
+            x[valid] = Hin[nb[valid]]
             acc = acc + x @ params.conv_w[l, ky, kx]
         H = H + activation(act, acc)
         out.append(H)
@@ -74,19 +79,26 @@ def occupied_sites(occ, spin: int) -> np.ndarray:
     return np.nonzero(np.asarray(occ) & bit)[0]
 
 
-def slater_matrices(lat, params, occ, lat_index: int = 0, act: str = "tanh"):
-    HL = features(lat, params, occ, act)[-1]
+def slater_matrices(lat, params, occ, lat_index: int = 0, act: str = "tanh", conv_input_round=None):
+    HL = features(lat, params, occ, act, conv_input_round)[-1]
     return [orbital_rows(params, lat_index, HL, s)[occupied_sites(occ, s)]
             for s in (0, 1)]
 
 
-def log_psi(lat, params, occ, lat_index: int = 0, act: str = "tanh"):
+def log_psi(lat, params, occ, lat_index: int = 0, act: str = "tanh", conv_input_round=None):
     """(sign, log|psi|) with canonical (site-ascending) row order."""
     sign, logabs = 1.0, 0.0
-    for Phi in slater_matrices(lat, params, occ, lat_index, act):
+    for Phi in slater_matrices(lat, params, occ, lat_index, act, conv_input_round):
         if Phi.shape[0] == 0:
             continue
         s, la = np.linalg.slogdet(Phi)
         sign *= s
         logabs += la
     return sign, logabs
+
+
+def round_bf16(x: np.ndarray) -> np.ndarray:
+    """Round FP64 values to the nearest BF16 (ties to even), via FP32."""
+    import torch
+    return torch.from_numpy(np.asarray(x, np.float64)).to(torch.float32).to(torch.bfloat16) \
+        .to(torch.float64).numpy()

@@ -28,20 +28,20 @@ def jw_sign(occ, spin: int, i: int, j: int) -> float:
     return -1.0 if between % 2 else 1.0
 
 
-def ratios(lat, params, occ, lat_index: int = 0, act: str = "tanh"):
+def ratios(lat, params, occ, lat_index: int = 0, act: str = "tanh", conv_input_round=None):
     """(list of Hop, array of in-place ratios R_h, (sign, log|psi|) of n)."""
-    s0, l0 = log_psi(lat, params, occ, lat_index, act)
+    s0, l0 = log_psi(lat, params, occ, lat_index, act, conv_input_round)
     hs = hops(lat, occ)
     R = np.empty(len(hs))
     for k, h in enumerate(hs):
-        s1, l1 = log_psi(lat, params, apply_hop(occ, h), lat_index, act)
+        s1, l1 = log_psi(lat, params, apply_hop(occ, h), lat_index, act, conv_input_round)
         R[k] = jw_sign(occ, h.spin, h.i, h.j) * s1 * s0 * np.exp(l1 - l0)
     return hs, R, (s0, l0)
 
 
 def local_energy(lat, params, occ, lat_index: int = 0, act: str = "tanh",
-                 return_ratios: bool = False):
-    hs, R, _ = ratios(lat, params, occ, lat_index, act)
+                 return_ratios: bool = False, conv_input_round=None):
+    hs, R, _ = ratios(lat, params, occ, lat_index, act, conv_input_round)
     occ = np.asarray(occ)
     e = lat.U * float(np.sum(occ == 3))
     for h, r in zip(hs, R):

@@ -1,0 +1,178 @@
+"""Python binding of the scalevmc C ABI.  Argument marshalling only: every
+step of the computation runs in the HIP library; torch supplies device memory
+and the current stream.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+from typing import Sequence
+
+import numpy as np
+import torch
+
+from . import _lib
+
+PREC = {"f64": 0, "f32": 1, "bf16": 2, "bf16x3": 3}
+ACT = {"tanh": 0, "silu": 1}
+PATH = {"lowrank": 0, "full": 1}
+
+
+def _ptr(t: torch.Tensor | None):
+    return None if t is None else ct.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return ct.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def pack_params(params, lattices) -> np.ndarray:
+    """Flat FP64 parameter vector in the library's layout:
+    embed | conv_w | conv_b | per lattice: W_up | W_dn | b_up | b_dn."""
+    parts = [np.asarray(params.embed, np.float64).ravel(),
+             np.asarray(params.conv_w, np.float64).ravel(),
+             np.asarray(params.conv_b, np.float64).ravel()]
+    for li, _ in enumerate(lattices):
+        parts += [np.asarray(params.proj_w[li][0], np.float64).ravel(),
+                  np.asarray(params.proj_w[li][1], np.float64).ravel(),
+                  np.asarray(params.proj_b[li][0], np.float64).ravel(),
+                  np.asarray(params.proj_b[li][1], np.float64).ravel()]
+    return np.concatenate(parts)
+
+
+class ScaleVMC:
+    """One library context: lattices, network shape, parameters and walkers."""
+
+    def __init__(self, lattices: Sequence, n_conv: int, channels: int, act: str = "tanh",
+                 conv_prec: str = "f64", refresh_every: int = 32, device: str = "cuda:0"):
+        self.lib = _lib.load()
+        self.device = torch.device(device)
+        self.lattices = list(lattices)
+        arr = (_lib.Lattice * len(self.lattices))()
+        for k, l in enumerate(self.lattices):
+            arr[k] = _lib.Lattice(l.Lx, l.Ly, int(l.pbc_x), int(l.pbc_y), float(l.t), float(l.tp),
+                                  float(l.U), l.n_up, l.n_dn)
+        m = _lib.Model(n_conv, channels, ACT[act], PREC[conv_prec], refresh_every)
+        h = ct.c_void_p()
+        with torch.cuda.device(self.device):
+            st = self.lib.svmc_create(arr, len(self.lattices), ct.byref(m), ct.byref(h))
+        if st != 0:
+            raise _lib.SvmcError(st, "svmc_create")
+        self.h = h
+        self.n_conv, self.channels, self.conv_prec = n_conv, channels, conv_prec
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.svmc_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st: int, what: str):
+        if st != 0:
+            msg = self.lib.svmc_last_error(self.h)
+            raise _lib.SvmcError(st, f"{what}: {msg.decode() if msg else ''}")
+
+    # ---- sizes -----------------------------------------------------------
+    @property
+    def num_params(self) -> int:
+        return int(self.lib.svmc_num_params(self.h))
+
+    @property
+    def num_walkers(self) -> int:
+        return int(self.lib.svmc_num_walkers(self.h))
+
+    @property
+    def max_hops(self) -> int:
+        return int(self.lib.svmc_max_hops(self.h))
+
+    @property
+    def max_electrons(self) -> int:
+        return int(self.lib.svmc_max_electrons(self.h))
+
+    # ---- calls -------------------------------------------------------------
+    def set_params(self, theta: torch.Tensor, base: Sequence[torch.Tensor]):
+        assert theta.dtype == torch.float64 and theta.is_cuda and theta.numel() == self.num_params
+        self._theta = theta.contiguous()
+        self._base = [b.to(self.device, torch.float64).contiguous() for b in base]
+        arr = (ct.c_void_p * len(self._base))(*[b.data_ptr() for b in self._base])
+        self._check(self.lib.svmc_set_params(self.h, _ptr(self._theta), arr, _stream()), "set_params")
+
+    def set_params_from(self, params):
+        """Upload a workloads.Params (FP64 numpy) object."""
+        theta = torch.from_numpy(pack_params(params, self.lattices)).to(self.device)
+        base = []
+        for li, _ in enumerate(self.lattices):
+            base.append(torch.from_numpy(np.concatenate([params.base[li][0].ravel(),
+                                                         params.base[li][1].ravel()])).to(self.device))
+        self.set_params(theta, base)
+
+    def load_walkers(self, counts: Sequence[int], occ: torch.Tensor):
+        occ = occ.to(self.device, torch.int8).contiguous()
+        self._occ_in = occ
+        c = (ct.c_int64 * len(counts))(*[int(x) for x in counts])
+        self._check(self.lib.svmc_load_walkers(self.h, c, _ptr(occ), _stream()), "load_walkers")
+
+    def log_psi(self):
+        W = self.num_walkers
+        sign = torch.empty(W, dtype=torch.float64, device=self.device)
+        la = torch.empty(W, dtype=torch.float64, device=self.device)
+        self._check(self.lib.svmc_log_psi(self.h, _ptr(sign), _ptr(la), _stream()), "log_psi")
+        return sign, la
+
+    def prepare(self):
+        self._check(self.lib.svmc_prepare(self.h, _stream()), "prepare")
+
+    def local_energy(self, path: str = "lowrank", ratios: bool = False, out=None):
+        W = self.num_walkers
+        eloc = torch.empty(W, dtype=torch.float64, device=self.device) if out is None else out
+        nh = code = rat = None
+        if ratios:
+            H = self.max_hops
+            nh = torch.zeros(W, dtype=torch.int32, device=self.device)
+            code = torch.full((W, H), -1, dtype=torch.int32, device=self.device)
+            rat = torch.full((W, H), float("nan"), dtype=torch.float64, device=self.device)
+        self._check(self.lib.svmc_local_energy(self.h, PATH[path], _ptr(eloc), _ptr(nh), _ptr(code),
+                                               _ptr(rat), _stream()), "local_energy")
+        return (eloc, nh, code, rat) if ratios else eloc
+
+    def sweep(self, n_sweeps: int, seed: int, step0: int, n_accept: torch.Tensor | None = None):
+        if n_accept is None:
+            n_accept = torch.zeros(self.num_walkers, dtype=torch.int64, device=self.device)
+        self._check(self.lib.svmc_sweep(self.h, int(n_sweeps), ct.c_uint64(seed), ct.c_uint64(step0),
+                                        _ptr(n_accept), _stream()), "sweep")
+        return n_accept
+
+    def refresh(self):
+        self._check(self.lib.svmc_refresh(self.h, _stream()), "refresh")
+
+    def state(self):
+        tot = sum(int(c) * l.Lx * l.Ly for c, l in zip(self._counts, self.lattices))
+        occ = torch.empty(tot, dtype=torch.int8, device=self.device)
+        pos = torch.empty((self.num_walkers, 2, self.max_electrons), dtype=torch.int16, device=self.device)
+        self._check(self.lib.svmc_get_state(self.h, _ptr(occ), _ptr(pos), _stream()), "get_state")
+        return occ, pos
+
+    def grad_logpsi(self, vjp: torch.Tensor | None = None):
+        if vjp is None:
+            out = torch.empty((self.num_walkers, self.num_params), dtype=torch.float64, device=self.device)
+        else:
+            vjp = vjp.to(self.device, torch.float64).contiguous()
+            out = torch.empty(self.num_params, dtype=torch.float64, device=self.device)
+        self._check(self.lib.svmc_grad_logpsi(self.h, _ptr(vjp), _ptr(out), _stream()), "grad_logpsi")
+        return out
+
+    def flags(self):
+        f = torch.empty(self.num_walkers, dtype=torch.int32, device=self.device)
+        self._check(self.lib.svmc_walker_flags(self.h, _ptr(f), _stream()), "walker_flags")
+        return f
+
+    # convenience: remember counts for state()
+    def load(self, counts: Sequence[int], occ):
+        self._counts = list(counts)
+        if isinstance(occ, np.ndarray):
+            occ = torch.from_numpy(np.ascontiguousarray(occ).reshape(-1))
+        self.load_walkers(counts, occ)

@@ -1,0 +1,511 @@
+// Host side of the scalevmc C ABI: argument validation, parameter packing,
+// device buffers and kernel sequencing.  Declarations and the contract of
+// every entry point are in include/scalevmc.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/scalevmc.h"
+#include "svmc_launch.h"
+
+using namespace svmc;
+
+namespace {
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  ~DevBuf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  hipError_t ensure(size_t n) {
+    if (n <= bytes && p) return hipSuccess;
+    release();
+    if (n == 0) n = 16;
+    hipError_t e = hipMalloc(&p, n);
+    if (e != hipSuccess) { p = nullptr; return e; }
+    bytes = n;
+    return hipSuccess;
+  }
+  template <class T> T* as() const { return (T*)p; }
+};
+
+uint16_t f32_to_bf16_rne(float f) {
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+float bf16_to_f32(uint16_t h) {
+  uint32_t u = (uint32_t)h << 16;
+  float f;
+  std::memcpy(&f, &u, 4);
+  return f;
+}
+
+}  // namespace
+
+struct svmc_ctx {
+  std::vector<svmc_lattice> lats;
+  svmc_model model{};
+  int prec = 0, L = 0, C = 0;
+  std::string err;
+  int64_t nparams = 0;
+  bool have_params = false, have_walkers = false;
+  bool prepared = false;   // G/P match the current walkers
+  // parameters
+  DevBuf Bpack, embed, bias;
+  std::vector<DevBuf> base, W, b;    // per lattice
+  // walkers
+  std::vector<LatDev> ld;            // host copies of the descriptors
+  DevBuf lats_dev;
+  long long Wtot = 0;
+  DevBuf occ, lab, pos, feat, inv, M, G, PT, ldet, sgn, flags, nacc;
+  DevBuf ratio_tmp;
+  std::vector<int64_t> counts;
+
+  svmc_status fail(svmc_status s, const std::string& m) {
+    err = m;
+    return s;
+  }
+  svmc_status hip(hipError_t e, const char* where) {
+    if (e == hipSuccess) return SVMC_OK;
+    err = std::string(where) + ": " + hipGetErrorString(e);
+    return e == hipErrorOutOfMemory ? SVMC_ERR_OOM : SVMC_ERR_HIP;
+  }
+  int tf_bytes() const { return prec == PREC_F64 ? 8 : 4; }
+  ModelDev mdev() const {
+    ModelDev m;
+    m.L = L;
+    m.C = C;
+    m.act = model.act;
+    m.Bpack = Bpack.p;
+    m.embed = embed.p;
+    m.bias = bias.p;
+    return m;
+  }
+  Bufs bufs() const {
+    Bufs x;
+    x.occ = occ.as<int8_t>();
+    x.lab = lab.as<int16_t>();
+    x.pos = pos.as<int16_t>();
+    x.feat = feat.p;
+    x.inv = inv.as<double>();
+    x.M = M.as<double>();
+    x.G = G.as<double>();
+    x.PT = PT.as<double>();
+    x.ld = ldet.as<double>();
+    x.sg = sgn.as<double>();
+    x.flags = flags.as<int32_t>();
+    x.nacc = nacc.as<int32_t>();
+    return x;
+  }
+  int max_hops() const {
+    int m = 0;
+    for (auto& l : lats) m = std::max(m, (l.n_up + l.n_dn) * (l.tp != 0.0 ? 8 : 4));
+    return m;
+  }
+  int max_elec() const {
+    int m = 0;
+    for (auto& l : lats) m = std::max(m, std::max(l.n_up, l.n_dn));
+    return m;
+  }
+};
+
+static svmc_status check_lattice(const svmc_lattice& l, std::string& why) {
+  if (l.Lx < 1 || l.Ly < 1) { why = "lattice dimensions must be >= 1"; return SVMC_ERR_INVALID_ARG; }
+  if ((l.pbc_x && l.Lx < 3) || (l.pbc_y && l.Ly < 3)) {
+    why = "a periodic axis needs length >= 3";
+    return SVMC_ERR_INVALID_ARG;
+  }
+  const long long N = (long long)l.Lx * l.Ly;
+  if (N > 4096) { why = "more than 4096 sites"; return SVMC_ERR_UNSUPPORTED; }
+  if (l.n_up < 0 || l.n_dn < 0 || l.n_up > N || l.n_dn > N) {
+    why = "electron counts must lie in [0, N]";
+    return SVMC_ERR_INVALID_ARG;
+  }
+  if (std::max(l.n_up, l.n_dn) > 128) { why = "more than 128 electrons per spin"; return SVMC_ERR_UNSUPPORTED; }
+  if (!std::isfinite(l.t) || !std::isfinite(l.tp) || !std::isfinite(l.U)) {
+    why = "non-finite Hamiltonian parameter";
+    return SVMC_ERR_INVALID_ARG;
+  }
+  return SVMC_OK;
+}
+
+extern "C" {
+
+const char* svmc_status_string(svmc_status s) {
+  switch (s) {
+    case SVMC_OK: return "ok";
+    case SVMC_ERR_INVALID_ARG: return "invalid argument";
+    case SVMC_ERR_OOM: return "out of device memory";
+    case SVMC_ERR_HIP: return "HIP runtime error";
+    case SVMC_ERR_STATE: return "call out of order";
+    case SVMC_ERR_UNSUPPORTED: return "unsupported shape";
+  }
+  return "unknown status";
+}
+
+const char* svmc_last_error(const svmc_ctx* ctx) { return ctx ? ctx->err.c_str() : ""; }
+
+svmc_status svmc_create(const svmc_lattice* lats, int32_t n_lats, const svmc_model* m, svmc_ctx** out) {
+  if (!out || !lats || !m || n_lats < 1 || n_lats > 8) return SVMC_ERR_INVALID_ARG;
+  *out = nullptr;
+  std::string why;
+  for (int i = 0; i < n_lats; ++i) {
+    svmc_status s = check_lattice(lats[i], why);
+    if (s != SVMC_OK) return s;
+  }
+  if (m->n_conv < 1 || m->n_conv > 4) return SVMC_ERR_UNSUPPORTED;
+  if (m->channels != 8 && m->channels != 16 && m->channels != 24 && m->channels != 32) return SVMC_ERR_UNSUPPORTED;
+  if (m->act != SVMC_ACT_TANH && m->act != SVMC_ACT_SILU) return SVMC_ERR_INVALID_ARG;
+  if (m->conv_prec < 0 || m->conv_prec > 3) return SVMC_ERR_INVALID_ARG;
+  if (m->refresh_every < 1) return SVMC_ERR_INVALID_ARG;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return SVMC_ERR_HIP;
+  svmc_ctx* c = new svmc_ctx();
+  c->lats.assign(lats, lats + n_lats);
+  c->model = *m;
+  c->prec = m->conv_prec;
+  c->L = m->n_conv;
+  c->C = m->channels;
+  int64_t np = 4LL * c->C + 9LL * c->L * c->C * c->C + (int64_t)c->L * c->C;
+  for (auto& l : c->lats) np += (int64_t)c->C * (l.n_up + l.n_dn) + l.n_up + l.n_dn;
+  c->nparams = np;
+  *out = c;
+  return SVMC_OK;
+}
+
+svmc_status svmc_destroy(svmc_ctx* ctx) {
+  if (!ctx) return SVMC_ERR_INVALID_ARG;
+  (void)hipDeviceSynchronize();
+  delete ctx;
+  return SVMC_OK;
+}
+
+int64_t svmc_num_params(const svmc_ctx* ctx) { return ctx ? ctx->nparams : -1; }
+int64_t svmc_num_walkers(const svmc_ctx* ctx) { return ctx ? ctx->Wtot : -1; }
+int32_t svmc_max_hops(const svmc_ctx* ctx) { return ctx ? ctx->max_hops() : -1; }
+int32_t svmc_max_electrons(const svmc_ctx* ctx) { return ctx ? ctx->max_elec() : -1; }
+
+svmc_status svmc_set_params(svmc_ctx* ctx, const double* theta, const double* const* base, hipStream_t st) {
+  if (!ctx) return SVMC_ERR_INVALID_ARG;
+  if (!theta || !base) return ctx->fail(SVMC_ERR_INVALID_ARG, "null theta or base");
+  for (size_t l = 0; l < ctx->lats.size(); ++l)
+    if (!base[l]) return ctx->fail(SVMC_ERR_INVALID_ARG, "null base orbital pointer");
+  const int L = ctx->L, C = ctx->C, P = ctx->prec;
+  std::vector<double> th(ctx->nparams);
+  svmc_status s;
+  if ((s = ctx->hip(hipMemcpyAsync(th.data(), theta, th.size() * 8, hipMemcpyDeviceToHost, st), "theta copy")))
+    return s;
+  if ((s = ctx->hip(hipStreamSynchronize(st), "theta sync"))) return s;
+  for (double v : th)
+    if (!std::isfinite(v)) return ctx->fail(SVMC_ERR_INVALID_ARG, "non-finite parameter");
+  const double* E = th.data();
+  const double* K = E + 4 * C;
+  const double* Bc = K + 9LL * L * C * C;
+  const double* rest = Bc + (long long)L * C;
+  auto rnd = [&](double x) -> double {
+    if (P == PREC_F64) return x;
+    float f = (float)x;
+    if (P == PREC_F32) return f;
+    return bf16_to_f32(f32_to_bf16_rne(f));
+  };
+  // embedding and conv bias in the feature type
+  const int tfb = ctx->tf_bytes();
+  std::vector<char> eb(4 * C * tfb), bb((size_t)L * C * tfb);
+  for (int k = 0; k < 4 * C; ++k) {
+    if (tfb == 8) ((double*)eb.data())[k] = E[k];
+    else ((float*)eb.data())[k] = (float)rnd(E[k]);
+  }
+  for (int k = 0; k < L * C; ++k) {
+    if (tfb == 8) ((double*)bb.data())[k] = Bc[k];
+    else ((float*)bb.data())[k] = (float)rnd(Bc[k]);
+  }
+  // conv kernels as MFMA B fragments
+  const bool bf = P == PREC_BF16 || P == PREC_BF16X3;
+  const int KC = bf ? 32 : 4;
+  const int Q = (9 * C + KC - 1) / KC, NT = (C + 15) / 16;
+  const int per = bf ? 8 : 1;
+  const size_t esz = P == PREC_F64 ? 8 : (P == PREC_F32 ? 4 : 2);
+  std::vector<char> bp((size_t)L * Q * NT * 64 * per * esz, 0);
+  for (int l = 0; l < L; ++l)
+    for (int q = 0; q < Q; ++q)
+      for (int nt = 0; nt < NT; ++nt)
+        for (int lane = 0; lane < 64; ++lane)
+          for (int e = 0; e < per; ++e) {
+            const int kap = bf ? 32 * q + 8 * (lane >> 4) + e : 4 * q + (lane >> 4);
+            const int n = 16 * nt + (lane & 15);
+            double v = 0.0;
+            if (kap < 9 * C && n < C) {
+              const int t = kap / C, c = kap % C;
+              v = K[(((long long)l * 9 + t) * C + c) * C + n];
+            }
+            const size_t idx = ((((size_t)l * Q + q) * NT + nt) * 64 + lane) * per + e;
+            if (P == PREC_F64) ((double*)bp.data())[idx] = v;
+            else if (P == PREC_F32) ((float*)bp.data())[idx] = (float)v;
+            else ((uint16_t*)bp.data())[idx] = f32_to_bf16_rne((float)v);
+          }
+  if ((s = ctx->hip(ctx->Bpack.ensure(bp.size()), "alloc")) || (s = ctx->hip(ctx->embed.ensure(eb.size()), "alloc")) ||
+      (s = ctx->hip(ctx->bias.ensure(bb.size()), "alloc")))
+    return s;
+  if ((s = ctx->hip(hipMemcpy(ctx->Bpack.p, bp.data(), bp.size(), hipMemcpyHostToDevice), "upload")) ||
+      (s = ctx->hip(hipMemcpy(ctx->embed.p, eb.data(), eb.size(), hipMemcpyHostToDevice), "upload")) ||
+      (s = ctx->hip(hipMemcpy(ctx->bias.p, bb.data(), bb.size(), hipMemcpyHostToDevice), "upload")))
+    return s;
+  // per lattice: projection (padded to nmax columns) and base orbitals
+  const size_t nl = ctx->lats.size();
+  ctx->base.resize(nl);
+  ctx->W.resize(nl);
+  ctx->b.resize(nl);
+  const double* cur = rest;
+  for (size_t l = 0; l < nl; ++l) {
+    const svmc_lattice& lt = ctx->lats[l];
+    const int N = lt.Lx * lt.Ly, n0 = lt.n_up, n1 = lt.n_dn, nm = std::max(std::max(n0, n1), 1);
+    std::vector<double> w(2LL * C * nm, 0.0), bv(2LL * nm, 0.0);
+    for (int c = 0; c < C; ++c)
+      for (int k = 0; k < n0; ++k) w[(size_t)c * nm + k] = cur[(size_t)c * n0 + k];
+    cur += (size_t)C * n0;
+    for (int c = 0; c < C; ++c)
+      for (int k = 0; k < n1; ++k) w[(size_t)C * nm + (size_t)c * nm + k] = cur[(size_t)c * n1 + k];
+    cur += (size_t)C * n1;
+    for (int k = 0; k < n0; ++k) bv[k] = cur[k];
+    cur += n0;
+    for (int k = 0; k < n1; ++k) bv[nm + k] = cur[k];
+    cur += n1;
+    if ((s = ctx->hip(ctx->W[l].ensure(w.size() * 8), "alloc")) || (s = ctx->hip(ctx->b[l].ensure(bv.size() * 8), "alloc")) ||
+        (s = ctx->hip(ctx->base[l].ensure(2ULL * N * nm * 8), "alloc")))
+      return s;
+    if ((s = ctx->hip(hipMemcpy(ctx->W[l].p, w.data(), w.size() * 8, hipMemcpyHostToDevice), "upload")) ||
+        (s = ctx->hip(hipMemcpy(ctx->b[l].p, bv.data(), bv.size() * 8, hipMemcpyHostToDevice), "upload")) ||
+        (s = ctx->hip(hipMemsetAsync(ctx->base[l].p, 0, 2ULL * N * nm * 8, st), "memset")))
+      return s;
+    if (n0 && (s = ctx->hip(hipMemcpy2DAsync(ctx->base[l].p, nm * 8, base[l], n0 * 8, n0 * 8, N,
+                                             hipMemcpyDeviceToDevice, st), "base copy")))
+      return s;
+    if (n1 && (s = ctx->hip(hipMemcpy2DAsync((char*)ctx->base[l].p + (size_t)N * nm * 8, nm * 8,
+                                             base[l] + (size_t)N * n0, n1 * 8, n1 * 8, N,
+                                             hipMemcpyDeviceToDevice, st), "base copy")))
+      return s;
+  }
+  ctx->have_params = true;
+  ctx->have_walkers = false;
+  return SVMC_OK;
+}
+
+// Rebuild orbital rows and inverses from the cached features (every lattice).
+static svmc_status rebuild_dets(svmc_ctx* ctx, hipStream_t st) {
+  const Bufs bf = ctx->bufs();
+  svmc_status s;
+  for (auto& lt : ctx->ld) {
+    if ((s = ctx->hip(launch_rows(ctx->prec, lt, bf, ctx->L, ctx->C, st), "rows"))) return s;
+    if ((s = ctx->hip(launch_gj(lt, bf, st), "inverse"))) return s;
+  }
+  ctx->prepared = false;
+  return SVMC_OK;
+}
+
+// Low-rank precompute: rows of every site from the current features, then
+// G = M Phi^-1 and P^T.
+static svmc_status prepare(svmc_ctx* ctx, hipStream_t st) {
+  const Bufs bf = ctx->bufs();
+  svmc_status s;
+  for (auto& lt : ctx->ld) {
+    if ((s = ctx->hip(launch_rows(ctx->prec, lt, bf, ctx->L, ctx->C, st), "rows"))) return s;
+    if ((s = ctx->hip(launch_gp(lt, bf, ctx->C, st), "G/P precompute"))) return s;
+  }
+  ctx->prepared = true;
+  return SVMC_OK;
+}
+
+svmc_status svmc_load_walkers(svmc_ctx* ctx, const int64_t* counts, const int8_t* occ, hipStream_t st) {
+  if (!ctx) return SVMC_ERR_INVALID_ARG;
+  if (!ctx->have_params) return ctx->fail(SVMC_ERR_STATE, "svmc_set_params must come first");
+  if (!counts || !occ) return ctx->fail(SVMC_ERR_INVALID_ARG, "null counts or occ");
+  const size_t nl = ctx->lats.size();
+  long long Wt = 0;
+  for (size_t l = 0; l < nl; ++l) {
+    if (counts[l] < 0) return ctx->fail(SVMC_ERR_INVALID_ARG, "negative walker count");
+    Wt += counts[l];
+  }
+  if (Wt < 1) return ctx->fail(SVMC_ERR_INVALID_ARG, "no walkers");
+  const int L = ctx->L, C = ctx->C, tfb = ctx->tf_bytes();
+  std::vector<LatDev> d(nl);
+  long long w0 = 0, o_occ = 0, o_lab = 0, o_pos = 0, o_feat = 0, o_inv = 0, o_m = 0, o_pt = 0;
+  size_t h0max = 0;
+  for (size_t l = 0; l < nl; ++l) {
+    const svmc_lattice& s = ctx->lats[l];
+    LatDev& x = d[l];
+    x.Lx = s.Lx; x.Ly = s.Ly; x.pbc_x = s.pbc_x ? 1 : 0; x.pbc_y = s.pbc_y ? 1 : 0;
+    x.N = s.Lx * s.Ly;
+    x.n[0] = s.n_up; x.n[1] = s.n_dn;
+    x.nmax = std::max(std::max(s.n_up, s.n_dn), 1);
+    x.nd = s.tp != 0.0 ? 8 : 4;
+    x.maxhops = (s.n_up + s.n_dn) * x.nd;
+    const int G = 2 * L + 4;
+    x.torus_x = (x.pbc_x && s.Lx < G) ? 1 : 0;
+    x.torus_y = (x.pbc_y && s.Ly < G) ? 1 : 0;
+    x.Gx = x.torus_x ? s.Lx : G;
+    x.Gy = x.torus_y ? s.Ly : G;
+    x.t = s.t; x.tp = s.tp; x.U = s.U;
+    x.w0 = w0; x.nw = counts[l];
+    x.occ_off = o_occ; x.lab_off = o_lab; x.pos_off = o_pos; x.feat_off = o_feat;
+    x.inv_off = o_inv; x.m_off = o_m; x.g_off = o_m; x.pt_off = o_pt;
+    x.base = ctx->base[l].as<double>();
+    x.W = ctx->W[l].as<double>();
+    x.b = ctx->b[l].as<double>();
+    const long long nw = counts[l], N = x.N, nm = x.nmax;
+    w0 += nw;
+    o_occ += nw * N;
+    o_lab += nw * 2 * N;
+    o_pos += nw * 2 * nm;
+    o_feat += nw * (long long)L * N * C;
+    o_inv += nw * 2 * nm * nm;
+    o_m += nw * 2 * N * nm;
+    o_pt += nw * 2 * nm * C;
+    h0max = std::max(h0max, (size_t)(nw * N * C * tfb));
+  }
+  svmc_status s;
+  ctx->have_walkers = false;
+  if ((s = ctx->hip(ctx->occ.ensure(o_occ), "alloc occ")) || (s = ctx->hip(ctx->lab.ensure(o_lab * 2), "alloc")) ||
+      (s = ctx->hip(ctx->pos.ensure(o_pos * 2), "alloc")) || (s = ctx->hip(ctx->feat.ensure(o_feat * tfb), "alloc feat")) ||
+      (s = ctx->hip(ctx->inv.ensure(o_inv * 8), "alloc inv")) ||
+      (s = ctx->hip(ctx->M.ensure(std::max((size_t)o_m * 8, h0max)), "alloc M")) ||
+      (s = ctx->hip(ctx->G.ensure(o_m * 8), "alloc G")) || (s = ctx->hip(ctx->PT.ensure(o_pt * 8), "alloc PT")) ||
+      (s = ctx->hip(ctx->ldet.ensure(Wt * 16), "alloc")) || (s = ctx->hip(ctx->sgn.ensure(Wt * 16), "alloc")) ||
+      (s = ctx->hip(ctx->flags.ensure(Wt * 4), "alloc")) || (s = ctx->hip(ctx->nacc.ensure(Wt * 4), "alloc")) ||
+      (s = ctx->hip(ctx->lats_dev.ensure(nl * sizeof(LatDev)), "alloc")))
+    return s;
+  ctx->ld = d;
+  ctx->Wtot = Wt;
+  ctx->counts.assign(counts, counts + nl);
+  if ((s = ctx->hip(hipMemcpyAsync(ctx->lats_dev.p, d.data(), nl * sizeof(LatDev), hipMemcpyHostToDevice, st),
+                    "descriptors")))
+    return s;
+  if ((s = ctx->hip(hipMemcpyAsync(ctx->occ.p, occ, o_occ, hipMemcpyDeviceToDevice, st), "occ copy"))) return s;
+  const Bufs bf = ctx->bufs();
+  const ModelDev md = ctx->mdev();
+  for (auto& lt : ctx->ld) {
+    if ((s = ctx->hip(launch_labels(lt, bf, st), "labels"))) return s;
+    if ((s = ctx->hip(launch_forward(ctx->prec, lt, bf, md, ctx->M.p, st), "forward"))) return s;
+  }
+  if ((s = rebuild_dets(ctx, st))) return s;
+  // descriptor copy must finish before the host vector can change
+  if ((s = ctx->hip(hipStreamSynchronize(st), "load sync"))) return s;
+  ctx->have_walkers = true;
+  return SVMC_OK;
+}
+
+svmc_status svmc_log_psi(svmc_ctx* ctx, double* sign, double* logabs, hipStream_t st) {
+  if (!ctx) return SVMC_ERR_INVALID_ARG;
+  if (!ctx->have_walkers) return ctx->fail(SVMC_ERR_STATE, "no walkers loaded");
+  if (!sign && !logabs) return ctx->fail(SVMC_ERR_INVALID_ARG, "no output");
+  const Bufs bf = ctx->bufs();
+  svmc_status s;
+  for (auto& lt : ctx->ld)
+    if ((s = ctx->hip(launch_logpsi(lt, bf, sign, logabs, st), "logpsi"))) return s;
+  return SVMC_OK;
+}
+
+svmc_status svmc_prepare(svmc_ctx* ctx, hipStream_t st) {
+  if (!ctx) return SVMC_ERR_INVALID_ARG;
+  if (!ctx->have_walkers) return ctx->fail(SVMC_ERR_STATE, "no walkers loaded");
+  return prepare(ctx, st);
+}
+
+svmc_status svmc_local_energy(svmc_ctx* ctx, svmc_path path, double* eloc, int32_t* n_hops, int32_t* hop_code,
+                              double* ratio, hipStream_t st) {
+  if (!ctx) return SVMC_ERR_INVALID_ARG;
+  if (!ctx->have_walkers) return ctx->fail(SVMC_ERR_STATE, "no walkers loaded");
+  if (!eloc) return ctx->fail(SVMC_ERR_INVALID_ARG, "eloc is null");
+  if ((hop_code == nullptr) != (ratio == nullptr))
+    return ctx->fail(SVMC_ERR_INVALID_ARG, "hop_code and ratio must both be given or both be NULL");
+  ElocOut out;
+  out.eloc = eloc;
+  out.nhops = n_hops;
+  out.code = hop_code;
+  out.ratio = ratio;
+  out.stride = ctx->max_hops();
+  const Bufs bf = ctx->bufs();
+  const ModelDev md = ctx->mdev();
+  svmc_status s;
+  if (path == SVMC_PATH_LOWRANK) {
+    if (!ctx->prepared && (s = prepare(ctx, st))) return s;
+    return ctx->hip(launch_eloc_lowrank(ctx->prec, md, ctx->lats_dev.as<LatDev>(), ctx->ld.data(),
+                                        (int)ctx->ld.size(), ctx->Wtot, bf, out, st),
+                    "low-rank local energy");
+  }
+  if (path != SVMC_PATH_FULL) return ctx->fail(SVMC_ERR_INVALID_ARG, "unknown path");
+  for (auto& lt : ctx->ld)
+    if (lt.N * ctx->C * ctx->tf_bytes() > 64 * 1024 || lt.N > 256 || lt.nmax > 128)
+      return ctx->fail(SVMC_ERR_UNSUPPORTED, "full-recompute path supports N <= 256, N*C features <= 64 KiB");
+  const int stride = ctx->max_hops();
+  if ((s = ctx->hip(ctx->ratio_tmp.ensure((size_t)ctx->Wtot * stride * 8), "alloc"))) return s;
+  for (auto& lt : ctx->ld)
+    if ((s = ctx->hip(launch_eloc_full(ctx->prec, md, lt, bf, out, ctx->ratio_tmp.as<double>() + lt.w0 * stride,
+                                       stride, st),
+                      "full-recompute local energy")))
+      return s;
+  return SVMC_OK;
+}
+
+svmc_status svmc_refresh(svmc_ctx* ctx, hipStream_t st) {
+  if (!ctx) return SVMC_ERR_INVALID_ARG;
+  if (!ctx->have_walkers) return ctx->fail(SVMC_ERR_STATE, "no walkers loaded");
+  return rebuild_dets(ctx, st);
+}
+
+svmc_status svmc_sweep(svmc_ctx* ctx, int32_t n_sweeps, uint64_t seed, uint64_t step0, int64_t* n_accept,
+                       hipStream_t st) {
+  if (!ctx) return SVMC_ERR_INVALID_ARG;
+  (void)n_sweeps; (void)seed; (void)step0; (void)n_accept; (void)st;
+  return ctx->fail(SVMC_ERR_UNSUPPORTED, "sweep not built yet");
+}
+
+svmc_status svmc_get_state(svmc_ctx* ctx, int8_t* occ, int16_t* pos, hipStream_t st) {
+  if (!ctx) return SVMC_ERR_INVALID_ARG;
+  if (!ctx->have_walkers) return ctx->fail(SVMC_ERR_STATE, "no walkers loaded");
+  if (!occ) return ctx->fail(SVMC_ERR_INVALID_ARG, "occ is null");
+  svmc_status s;
+  size_t tot = 0;
+  for (auto& lt : ctx->ld) tot += (size_t)lt.nw * lt.N;
+  if ((s = ctx->hip(hipMemcpyAsync(occ, ctx->occ.p, tot, hipMemcpyDeviceToDevice, st), "occ copy"))) return s;
+  if (pos) {
+    const int E = ctx->max_elec();
+    if ((s = ctx->hip(hipMemsetAsync(pos, 0xff, (size_t)ctx->Wtot * 2 * E * 2, st), "memset"))) return s;
+    for (auto& lt : ctx->ld) {
+      if (lt.nw == 0) continue;
+      // [nw][2][nmax] -> [nw][2][E]
+      if ((s = ctx->hip(hipMemcpy2DAsync(pos + lt.w0 * 2 * E, (size_t)E * 2, ctx->pos.as<int16_t>() + lt.pos_off,
+                                         (size_t)lt.nmax * 2, (size_t)lt.nmax * 2, (size_t)lt.nw * 2,
+                                         hipMemcpyDeviceToDevice, st),
+                        "pos copy")))
+        return s;
+    }
+  }
+  return SVMC_OK;
+}
+
+svmc_status svmc_grad_logpsi(svmc_ctx* ctx, const double* vjp_w, double* out, hipStream_t st) {
+  if (!ctx) return SVMC_ERR_INVALID_ARG;
+  (void)vjp_w; (void)out; (void)st;
+  return ctx->fail(SVMC_ERR_UNSUPPORTED, "gradient not built yet");
+}
+
+svmc_status svmc_walker_flags(svmc_ctx* ctx, int32_t* flags, hipStream_t st) {
+  if (!ctx) return SVMC_ERR_INVALID_ARG;
+  if (!ctx->have_walkers) return ctx->fail(SVMC_ERR_STATE, "no walkers loaded");
+  if (!flags) return ctx->fail(SVMC_ERR_INVALID_ARG, "flags is null");
+  return ctx->hip(hipMemcpyAsync(flags, ctx->flags.p, (size_t)ctx->Wtot * 4, hipMemcpyDeviceToDevice, st), "flags");
+}
+
+}  // extern "C"

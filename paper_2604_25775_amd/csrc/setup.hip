@@ -1,0 +1,352 @@
+// Walker set-up and FP64 refresh kernels:
+//   labels      occupation -> electron labels (ascending sites) and site->label
+//   embed       H_0 = E[n_s]                     (Sec. II.B, embedding layer)
+//   forward     H_l = H_{l-1} + act(conv(H_{l-1}))  one launch per layer
+//               (Sec. II.B, residual conv equation)
+//   rows        M_s[x] = base_s[x] + H_L[x] W_s + b_s for every site
+//               (Sec. II.B, orbital projection)
+//   gj          Phi_s = M_s[pos], FP64 Gauss-Jordan inverse with partial
+//               pivoting, log|det|, sign
+//   gp          G_s = M_s Phi_s^-1 and P_s^T = (W_s Phi_s^-1)^T, the two
+//               factors every low-rank ratio reads (Sec. II.C, SMW equations)
+//   logpsi      canonical sign and log|psi| per walker
+#include "svmc_dev.h"
+#include "svmc_launch.h"
+#include "tiled_lu.h"
+
+namespace svmc {
+
+#ifdef SVMC_INST_P
+template <class Tf>
+__global__ void k_embed(LatDev lt, Bufs bf, ModelDev md, Tf* __restrict__ h0) {
+  const int C = md.C;
+  const long long total = lt.nw * (long long)lt.N * C;
+  const Tf* E = (const Tf*)md.embed;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
+       e += (long long)gridDim.x * blockDim.x) {
+    const long long site = e / C;
+    const int c = (int)(e % C);
+    const int o = bf.occ[lt.occ_off + site] & 3;
+    h0[e] = E[o * C + c];
+  }
+}
+
+// One conv layer over every site of every walker of a lattice.  Block = 4
+// waves, each wave one 16-site tile.  src = H_{l-1} ([nw][N][C]), dst = H_l.
+template <int P, int C>
+__global__ __launch_bounds__(256) void k_forward_layer(LatDev lt, ModelDev md, int layer,
+                                                       const typename PrecT<P>::Tf* __restrict__ src,
+                                                       long long src_stride,
+                                                       typename PrecT<P>::Tf* __restrict__ dst,
+                                                       long long dst_stride) {
+  typedef typename PrecT<P>::Tf Tf;
+  typedef typename PrecT<P>::Tb Tb;
+  typedef typename PrecT<P>::Acc Acc;
+  typedef ConvCfg<P, C> CC;
+  const int lane = threadIdx.x & 63;
+  const int tile = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const long long wl = blockIdx.y;
+  const int N = lt.N;
+  if (tile * 16 >= N) return;
+  const Tf* S = src + wl * src_stride;
+  Tf* D = dst + wl * dst_stride;
+  const int m = tile * 16 + (lane & 15);
+  int nb[9];
+  {
+    const int x = m % lt.Lx, y = m / lt.Lx;
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+      int xx = x + (t % 3) - 1, yy = y + (t / 3) - 1;
+      bool ok = m < N;
+      if (lt.pbc_x) xx = imod(xx, lt.Lx); else ok = ok && xx >= 0 && xx < lt.Lx;
+      if (lt.pbc_y) yy = imod(yy, lt.Ly); else ok = ok && yy >= 0 && yy < lt.Ly;
+      nb[t] = ok ? (xx + lt.Lx * yy) * C : -1;
+    }
+  }
+  Acc acc[CC::NT];
+  const Tb* Bl = (const Tb*)md.Bpack + (long long)layer * CC::Q * CC::NT * 64;
+  conv_tile<P, C>(S, nb, Bl, lane, acc);
+  const Tf* bias = (const Tf*)md.bias + layer * C;
+#pragma unroll
+  for (int nt = 0; nt < CC::NT; ++nt)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = tile * 16 + OutMap<P>::row(lane, v);
+      const int n = nt * 16 + OutMap<P>::col(lane, v);
+      if (r < N && n < C) {
+        const Tf z = acc[nt][v] + bias[n];
+        D[(long long)r * C + n] = S[(long long)r * C + n] + act_fn<Tf>(md.act, z);
+      }
+    }
+}
+
+template <int P, int C>
+static hipError_t forward_impl(const LatDev& lt, const Bufs& bf, const ModelDev& md, void* h0tmp,
+                               hipStream_t st) {
+  typedef typename PrecT<P>::Tf Tf;
+  if (lt.nw == 0) return hipSuccess;
+  const long long NC = (long long)lt.N * C;
+  Tf* h0 = (Tf*)h0tmp;
+  hipLaunchKernelGGL(k_embed<Tf>, dim3(4096), dim3(256), 0, st, lt, bf, md, h0);
+  Tf* feat = (Tf*)bf.feat + lt.feat_off;
+  const long long fs = (long long)md.L * NC;
+  const dim3 grid((unsigned)((lt.N + 63) / 64), (unsigned)lt.nw);
+  for (int l = 0; l < md.L; ++l) {
+    const Tf* src = l == 0 ? h0 : feat + (long long)(l - 1) * NC;
+    const long long ss = l == 0 ? NC : fs;
+    hipLaunchKernelGGL((k_forward_layer<P, C>), grid, dim3(256), 0, st, lt, md, l, src, ss,
+                       feat + (long long)l * NC, fs);
+  }
+  return hipGetLastError();
+}
+
+hipError_t SVMC_CAT3(forward_, SVMC_INST_P, SVMC_INST_C)(const LatDev& lt, const Bufs& bf, const ModelDev& md,
+                                                         void* h0tmp, hipStream_t st) {
+  return forward_impl<SVMC_INST_P, SVMC_INST_C>(lt, bf, md, h0tmp, st);
+}
+#else
+__global__ void k_labels(LatDev lt, Bufs bf) {
+  const long long wl = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (wl >= lt.nw) return;
+  const int N = lt.N, nm = lt.nmax;
+  const int8_t* occ = bf.occ + lt.occ_off + wl * N;
+  int16_t* lab = bf.lab + lt.lab_off + wl * 2 * N;
+  int16_t* pos = bf.pos + lt.pos_off + wl * 2 * nm;
+  int cnt[2] = {0, 0};
+  for (int s = 0; s < N; ++s) {
+    const int o = occ[s];
+    for (int sp = 0; sp < 2; ++sp) {
+      if ((o >> sp) & 1) {
+        if (cnt[sp] < nm) pos[sp * nm + cnt[sp]] = (int16_t)s;
+        lab[sp * N + s] = (int16_t)cnt[sp];
+        ++cnt[sp];
+      } else {
+        lab[sp * N + s] = -1;
+      }
+    }
+  }
+  for (int sp = 0; sp < 2; ++sp)
+    for (int k = cnt[sp]; k < nm; ++k) pos[sp * nm + k] = -1;
+  bool bad = cnt[0] != lt.n[0] || cnt[1] != lt.n[1];
+  for (int s = 0; s < N; ++s) bad |= (occ[s] < 0 || occ[s] > 3);
+  const long long w = lt.w0 + wl;
+  bf.flags[w] = bad ? 8 : 0;
+  bf.nacc[w] = 0;
+}
+
+// M_s[x][m] = base_s[x][m] + sum_c H_L[x][c] W_s[c][m] + b_s[m]
+template <class Tf>
+__global__ void k_rows(LatDev lt, Bufs bf, int L, int C) {
+  const int N = lt.N, nm = lt.nmax;
+  const long long wl = blockIdx.z;
+  const int sp = blockIdx.y;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= N * nm) return;
+  const int x = e / nm, m = e % nm;
+  double* M = bf.M + lt.m_off + wl * 2LL * N * nm + (long long)sp * N * nm;
+  if (m >= lt.n[sp]) { M[e] = 0.0; return; }
+  const Tf* H = (const Tf*)bf.feat + lt.feat_off + wl * (long long)L * N * C + (long long)(L - 1) * N * C +
+                (long long)x * C;
+  const double* W = lt.W + (long long)sp * C * nm;
+  double acc = lt.base[((long long)sp * N + x) * nm + m] + lt.b[sp * nm + m];
+  for (int c = 0; c < C; ++c) acc = fma((double)H[c], W[c * nm + m], acc);
+  M[e] = acc;
+}
+
+// Phi_s = M_s[pos] (rows in label order) -> Phi_s^-1, log|det|, sign, with
+// the register-tiled Gauss-Jordan elimination of tiled_lu.h (n <= 16 R).
+template <int R>
+__global__ __launch_bounds__(256) void k_gj(LatDev lt, Bufs bf) {
+  const int sp = blockIdx.y;
+  const long long wl = blockIdx.x;
+  const long long w = lt.w0 + wl;
+  const int n = lt.n[sp], nm = lt.nmax;
+  const int tid = threadIdx.x, tx = tid >> 4, ty = tid & 15;
+  __shared__ GjShared<R> sh;
+  double* ldo = bf.ld + 2 * w + sp;
+  double* sgo = bf.sg + 2 * w + sp;
+  if (n == 0) {
+    if (tid == 0) { *ldo = 0.0; *sgo = 1.0; }
+    return;
+  }
+  if (bf.flags[w] & 8) {
+    if (tid == 0) { *ldo = -INFINITY; *sgo = 0.0; }
+    return;
+  }
+  const double* M = bf.M + lt.m_off + wl * 2LL * lt.N * nm + (long long)sp * lt.N * nm;
+  const int16_t* pos = bf.pos + lt.pos_off + wl * 2LL * nm + sp * nm;
+  double x[R][R];
+#pragma unroll
+  for (int a = 0; a < R; ++a) {
+    const int k = ty + 16 * a;
+    const int site = k < n ? pos[k] : 0;
+#pragma unroll
+    for (int b = 0; b < R; ++b) {
+      const int m = tx + 16 * b;
+      x[a][b] = (k < n && m < n) ? M[(long long)site * nm + m] : (k == m ? 1.0 : 0.0);
+    }
+  }
+  double logabs, sgn;
+  bool singular;
+  tiled_gj<R, true>(x, n, sh, logabs, sgn, singular);
+  if (singular) {
+    if (tid == 0) { *ldo = -INFINITY; *sgo = 0.0; atomicOr(bf.flags + w, 1); }
+    return;
+  }
+  if (tid == 0) {
+    *ldo = logabs;
+    *sgo = sgn;
+    if (!isfinite(logabs)) atomicOr(bf.flags + w, 2);
+  }
+  double* Y = bf.inv + lt.inv_off + wl * 2LL * nm * nm + (long long)sp * nm * nm;
+#pragma unroll
+  for (int a = 0; a < R; ++a) {
+    const int k = ty + 16 * a;
+    if (k >= n) continue;
+    const int row = sh.perminv[k];
+#pragma unroll
+    for (int b = 0; b < R; ++b) {
+      const int m = tx + 16 * b;
+      if (m < n) Y[(long long)row * nm + sh.perm[m]] = x[a][b];
+    }
+  }
+}
+
+// G_s = M_s Phi_s^-1 (rows 0..N-1) and P_s^T = (W_s Phi_s^-1)^T (rows N..N+C-1
+// of the stacked left factor).  64x64 output tiles, 4x4 per thread, K chunks
+// of 16 through LDS.  grid.x = tile + ntiles * (sp + 2 * wl).
+__global__ __launch_bounds__(256) void k_gp(LatDev lt, Bufs bf, int C, int tiles_r, int tiles_c) {
+  const int N = lt.N, nm = lt.nmax;
+  long long bid = blockIdx.x;
+  const int ntiles = tiles_r * tiles_c;
+  const int tile = (int)(bid % ntiles);
+  bid /= ntiles;
+  const int sp = (int)(bid % 2);
+  const long long wl = bid / 2;
+  const int n = lt.n[sp];
+  if (n == 0) return;
+  const int R0 = (tile / tiles_c) * 64, C0 = (tile % tiles_c) * 64;
+  const int rows = N + C;
+  const double* M = bf.M + lt.m_off + wl * 2LL * N * nm + (long long)sp * N * nm;
+  const double* W = lt.W + (long long)sp * C * nm;
+  const double* Y = bf.inv + lt.inv_off + wl * 2LL * nm * nm + (long long)sp * nm * nm;
+  __shared__ double As[16][64 + 1];
+  __shared__ double Bs[16][64 + 1];
+  const int tid = threadIdx.x, tr = tid / 16, tc = tid % 16;
+  double acc[4][4] = {};
+  for (int k0 = 0; k0 < n; k0 += 16) {
+    for (int e = tid; e < 16 * 64; e += 256) {
+      const int kk = e / 64, rr = e % 64;
+      const int r = R0 + rr, k = k0 + kk;
+      double v = 0.0;
+      if (r < rows && k < n) v = r < N ? M[(long long)r * nm + k] : W[(long long)(r - N) * nm + k];
+      As[kk][rr] = v;
+      const int c = C0 + rr;
+      Bs[kk][rr] = (k < n && c < n) ? Y[(long long)k * nm + c] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk) {
+      double a[4], b[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) a[i] = As[kk][tr + 16 * i];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) b[j] = Bs[kk][tc + 16 * j];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = fma(a[i], b[j], acc[i][j]);
+    }
+    __syncthreads();
+  }
+  double* G = bf.G + lt.g_off + wl * 2LL * N * nm + (long long)sp * N * nm;
+  double* PT = bf.PT + lt.pt_off + wl * 2LL * nm * C + (long long)sp * nm * C;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int r = R0 + tr + 16 * i;
+    if (r >= rows) continue;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int c = C0 + tc + 16 * j;
+      if (c >= n) continue;
+      if (r < N) G[(long long)r * nm + c] = acc[i][j];
+      else PT[(long long)c * C + (r - N)] = acc[i][j];
+    }
+  }
+}
+
+// sign with canonical (site-ascending) row order = label-order sign times the
+// parity of the label -> site map; log|psi| = sum over spins.
+__global__ void k_logpsi(LatDev lt, Bufs bf, double* sign, double* logabs) {
+  const long long wl = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (wl >= lt.nw) return;
+  const long long w = lt.w0 + wl;
+  const int nm = lt.nmax;
+  double s = bf.sg[2 * w] * bf.sg[2 * w + 1];
+  const double la = bf.ld[2 * w] + bf.ld[2 * w + 1];
+  for (int sp = 0; sp < 2; ++sp) {
+    const int16_t* pos = bf.pos + lt.pos_off + wl * 2LL * nm + sp * nm;
+    int inv = 0;
+    for (int p = 0; p < lt.n[sp]; ++p)
+      for (int q = p + 1; q < lt.n[sp]; ++q) inv += pos[q] < pos[p];
+    if (inv & 1) s = -s;
+  }
+  if (sign) sign[w] = s;
+  if (logabs) logabs[w] = la;
+}
+
+// ---------------------------------------------------------------------------
+// host launchers
+// ---------------------------------------------------------------------------
+hipError_t launch_labels(const LatDev& lt, const Bufs& bf, hipStream_t st) {
+  if (lt.nw == 0) return hipSuccess;
+  const unsigned nb = (unsigned)((lt.nw + 255) / 256);
+  hipLaunchKernelGGL(k_labels, dim3(nb), dim3(256), 0, st, lt, bf);
+  return hipGetLastError();
+}
+
+hipError_t launch_forward(int prec, const LatDev& lt, const Bufs& bf, const ModelDev& md, void* h0tmp,
+                          hipStream_t st) {
+#define SVMC_FWD(P_, C_) if (prec == P_ && md.C == C_) return forward_##P_##_##C_(lt, bf, md, h0tmp, st);
+  SVMC_FOR_EACH_PREC_C(SVMC_FWD)
+#undef SVMC_FWD
+  return hipErrorInvalidValue;
+}
+
+
+hipError_t launch_rows(int prec, const LatDev& lt, const Bufs& bf, int L, int C, hipStream_t st) {
+  if (lt.nw == 0) return hipSuccess;
+  const dim3 grid((unsigned)((lt.N * lt.nmax + 255) / 256), 2, (unsigned)lt.nw);
+  if (prec == PREC_F64) hipLaunchKernelGGL(k_rows<double>, grid, dim3(256), 0, st, lt, bf, L, C);
+  else hipLaunchKernelGGL(k_rows<float>, grid, dim3(256), 0, st, lt, bf, L, C);
+  return hipGetLastError();
+}
+
+hipError_t launch_gj(const LatDev& lt, const Bufs& bf, hipStream_t st) {
+  if (lt.nw == 0) return hipSuccess;
+  const dim3 grid((unsigned)lt.nw, 2);
+  if (lt.nmax <= 16) hipLaunchKernelGGL((k_gj<1>), grid, dim3(256), 0, st, lt, bf);
+  else if (lt.nmax <= 32) hipLaunchKernelGGL((k_gj<2>), grid, dim3(256), 0, st, lt, bf);
+  else if (lt.nmax <= 64) hipLaunchKernelGGL((k_gj<4>), grid, dim3(256), 0, st, lt, bf);
+  else if (lt.nmax <= 128) hipLaunchKernelGGL((k_gj<8>), grid, dim3(256), 0, st, lt, bf);
+  else return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_gp(const LatDev& lt, const Bufs& bf, int C, hipStream_t st) {
+  if (lt.nw == 0) return hipSuccess;
+  const int tr = (lt.N + C + 63) / 64, tc = (lt.nmax + 63) / 64;
+  const long long nblk = (long long)tr * tc * 2 * lt.nw;
+  hipLaunchKernelGGL(k_gp, dim3((unsigned)nblk), dim3(256), 0, st, lt, bf, C, tr, tc);
+  return hipGetLastError();
+}
+
+hipError_t launch_logpsi(const LatDev& lt, const Bufs& bf, double* sign, double* logabs, hipStream_t st) {
+  if (lt.nw == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_logpsi, dim3((unsigned)((lt.nw + 127) / 128)), dim3(128), 0, st, lt, bf, sign, logabs);
+  return hipGetLastError();
+}
+
+#endif
+
+}  // namespace svmc

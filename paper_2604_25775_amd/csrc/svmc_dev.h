@@ -1,0 +1,285 @@
+// Device-side definitions shared by the scalevmc kernels: descriptors,
+// wavefront helpers, the MFMA conv tile and the one-wave LU determinant.
+//
+// Target: gfx950 (CDNA4), wave64.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define SVMC_DEV __device__ __forceinline__
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef double v4d __attribute__((ext_vector_type(4)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+
+// PREC_BF16X3: conv multiplier inputs split exactly into three BF16 terms
+// (x = hi + mid + lo), three MFMA passes with FP32 accumulation, so the conv
+// sees FP32 activations and BF16 weights.
+enum { PREC_F64 = 0, PREC_F32 = 1, PREC_BF16 = 2, PREC_BF16X3 = 3 };
+enum { ACT_TANH = 0, ACT_SILU = 1 };
+
+// ---------------------------------------------------------------------------
+// descriptors
+// ---------------------------------------------------------------------------
+// One lattice of a (possibly mixed) batch.  Walkers [w0, w0 + nw) belong to
+// it; every per-walker array below is addressed as base + off + (w - w0) *
+// stride, with the strides implied by N, nmax and the model.
+struct LatDev {
+  int Lx, Ly, pbc_x, pbc_y, N;
+  int n[2];       // electrons per spin
+  int nmax;       // max(n[0], n[1]), leading dimension of per-spin matrices
+  int nd;         // hop directions: 4 (t' = 0) or 8
+  int maxhops;    // (n0 + n1) * nd
+  int torus_x, torus_y;   // incremental boxes wrap (axis shorter than 2L+4)
+  int Gx, Gy;             // incremental grid extent per axis
+  double t, tp, U;
+  long long w0, nw;
+  long long occ_off;   // int8  [N]
+  long long lab_off;   // int16 [2][N]     label of the electron at a site, -1
+  long long pos_off;   // int16 [2][nmax]  site of each label
+  long long feat_off;  // Tf    [L][N][C]  H_1..H_L
+  long long inv_off;   // f64   [2][nmax][nmax]  Phi^-1[m][k]
+  long long m_off;     // f64   [2][N][nmax]     orbital rows of all sites
+  long long g_off;     // f64   [2][N][nmax]     G = M Phi^-1
+  long long pt_off;    // f64   [2][nmax][C]     P^T = (W Phi^-1)^T
+  const double* base;  // [2][N][nmax]
+  const double* W;     // [2][C][nmax]
+  const double* b;     // [2][nmax]
+};
+
+// Device buffers of one context (walker-indexed arrays, see LatDev offsets).
+struct Bufs {
+  int8_t* occ;
+  int16_t* lab;
+  int16_t* pos;
+  void* feat;        // Tf
+  double* inv;
+  double* M;
+  double* G;
+  double* PT;
+  double* ld;        // [W][2] log|det Phi_s| (label order)
+  double* sg;        // [W][2] sign of det Phi_s (label order)
+  int32_t* flags;    // [W]
+  int32_t* nacc;     // [W] accepted moves since the last refresh
+};
+
+// Network constants.  Bpack holds the conv kernels pre-arranged as MFMA B
+// fragments: [layer][chunk q][out-tile nt][lane] of PrecT<P>::Tb.
+struct ModelDev {
+  int L, C, act;
+  const void* Bpack;
+  const void* embed;   // Tf [4][C]
+  const void* bias;    // Tf [L][C]
+};
+
+template <int P> struct PrecT;
+template <> struct PrecT<PREC_F64> {
+  typedef double Tf; typedef double Tb; typedef v4d Acc; static constexpr int KC = 4;
+};
+template <> struct PrecT<PREC_F32> {
+  typedef float Tf; typedef float Tb; typedef v4f Acc; static constexpr int KC = 4;
+};
+template <> struct PrecT<PREC_BF16> {
+  typedef float Tf; typedef v8bf Tb; typedef v4f Acc; static constexpr int KC = 32;
+};
+template <> struct PrecT<PREC_BF16X3> {
+  typedef float Tf; typedef v8bf Tb; typedef v4f Acc; static constexpr int KC = 32;
+};
+
+template <int P, int C> struct ConvCfg {
+  static constexpr int KC = PrecT<P>::KC;
+  static constexpr int K = 9 * C;
+  static constexpr int Q = (K + KC - 1) / KC;   // K chunks per layer
+  static constexpr int NT = (C + 15) / 16;      // 16-wide output tiles
+};
+
+// ---------------------------------------------------------------------------
+// small helpers
+// ---------------------------------------------------------------------------
+SVMC_DEV int imod(int a, int m) { int r = a % m; return r < 0 ? r + m : r; }
+
+SVMC_DEV double readlane_d(double x, int lane) {
+  long long v = __double_as_longlong(x);
+  int lo = __builtin_amdgcn_readlane((int)(v & 0xffffffffLL), lane);
+  int hi = __builtin_amdgcn_readlane((int)(v >> 32), lane);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+SVMC_DEV int uniform_i(int x) { return __builtin_amdgcn_readfirstlane(x); }
+
+SVMC_DEV double wave_sum_d(double v) {
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+SVMC_DEV int wave_sum_i(int v) {
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+// inclusive prefix sum over the wave
+SVMC_DEV int wave_incl_scan(int v, int lane) {
+  for (int o = 1; o < 64; o <<= 1) {
+    int u = __shfl_up(v, o, 64);
+    if (lane >= o) v += u;
+  }
+  return v;
+}
+
+template <class T> SVMC_DEV T act_fn(int act, T x);
+template <> SVMC_DEV float act_fn<float>(int act, float x) {
+  return act == ACT_TANH ? tanhf(x) : x / (1.0f + expf(-x));
+}
+template <> SVMC_DEV double act_fn<double>(int act, double x) {
+  return act == ACT_TANH ? tanh(x) : x / (1.0 + exp(-x));
+}
+
+// ---------------------------------------------------------------------------
+// MFMA step per precision
+// ---------------------------------------------------------------------------
+SVMC_DEV void mfma(v4d& c, double a, double b) {
+  c = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+SVMC_DEV void mfma(v4f& c, float a, float b) {
+  c = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+SVMC_DEV void mfma(v4f& c, v8bf a, v8bf b) {
+  c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+// Output element (row, column) held in accumulator slot v of `lane` for the
+// 16x16 MFMA tiles used here (measured on gfx950):
+//   f32 16x16x4, bf16 16x16x32: row = 4*(lane/16) + v, col = lane%16
+//   f64 16x16x4:                row = lane/16 + 4*v,   col = lane%16
+// Inputs: A[i][k] from lane i + 16*(k/kpl) (kpl = k-values per lane),
+// B[k][j] from lane j + 16*(k/kpl).
+template <int P> struct OutMap {
+  SVMC_DEV static int row(int lane, int v) { return 4 * (lane >> 4) + v; }
+  SVMC_DEV static int col(int lane, int v) { return lane & 15; }
+};
+template <> struct OutMap<PREC_F64> {
+  SVMC_DEV static int row(int lane, int v) { return (lane >> 4) + 4 * v; }
+  SVMC_DEV static int col(int lane, int v) { return lane & 15; }
+};
+
+// ---------------------------------------------------------------------------
+// conv tile: 16 output sites x C output channels of
+//   acc[site][n] = sum_{tap t, c} X(site, t)[c] * K[t][c][n]
+// Lane l supplies row (l % 16) of the A operand.  nb[t] is the element offset
+// (into `src`) of the C-channel feature vector of this lane's site's
+// neighbour at tap t (t = 3*ky + kx, offset (kx-1, ky-1)), or -1 for zero
+// padding.  The arithmetic per output element depends only on that element's
+// own inputs, in a fixed order, so every caller (full forward or incremental
+// box) produces identical values for identical inputs.
+// ---------------------------------------------------------------------------
+template <int P, int C>
+SVMC_DEV void conv_tile(const typename PrecT<P>::Tf* __restrict__ src, const int (&nb)[9],
+                        const typename PrecT<P>::Tb* __restrict__ Bl,   // layer's packed B
+                        int lane, typename PrecT<P>::Acc (&acc)[ConvCfg<P, C>::NT]) {
+  typedef typename PrecT<P>::Tf Tf;
+  typedef ConvCfg<P, C> CC;
+  const int g = lane >> 4;
+#pragma unroll
+  for (int nt = 0; nt < CC::NT; ++nt)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) acc[nt][v] = 0;
+#pragma unroll
+  for (int q = 0; q < CC::Q; ++q) {
+    if constexpr (P == PREC_BF16 || P == PREC_BF16X3) {
+      const int k0 = 32 * q + 8 * g;
+      float x[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) x[e] = 0.0f;
+      if (k0 < CC::K) {
+        const int t = k0 / C, c0 = k0 % C;
+        int off = nb[0];
+#pragma unroll
+        for (int tt = 1; tt < 9; ++tt) off = (t == tt) ? nb[tt] : off;
+        if (off >= 0) {
+          const float4* p4 = reinterpret_cast<const float4*>(src + off + c0);
+          const float4 x0 = p4[0], x1 = p4[1];
+          x[0] = x0.x; x[1] = x0.y; x[2] = x0.z; x[3] = x0.w;
+          x[4] = x1.x; x[5] = x1.y; x[6] = x1.z; x[7] = x1.w;
+        }
+      }
+      v8bf a;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) a[e] = (__bf16)x[e];
+#pragma unroll
+      for (int nt = 0; nt < CC::NT; ++nt) mfma(acc[nt], a, Bl[(q * CC::NT + nt) * 64 + lane]);
+      if constexpr (P == PREC_BF16X3) {
+        // remainders: x - hi is exact in FP32, and so is (x - hi) - mid
+        v8bf a2, a3;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const float r1 = x[e] - (float)a[e];
+          a2[e] = (__bf16)r1;
+          a3[e] = (__bf16)(r1 - (float)a2[e]);
+        }
+#pragma unroll
+        for (int nt = 0; nt < CC::NT; ++nt) {
+          mfma(acc[nt], a2, Bl[(q * CC::NT + nt) * 64 + lane]);
+          mfma(acc[nt], a3, Bl[(q * CC::NT + nt) * 64 + lane]);
+        }
+      }
+    } else {
+      // K chunk of 4: all four k of the chunk lie in one tap (C % 4 == 0)
+      const int t = (4 * q) / C;
+      const int c = (4 * q) % C + g;
+      const int off = nb[t];
+      Tf a = off >= 0 ? src[off + c] : Tf(0);
+#pragma unroll
+      for (int nt = 0; nt < CC::NT; ++nt)
+        mfma(acc[nt], a, Bl[(q * CC::NT + nt) * 64 + lane]);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// One-wave LU determinant of an r x r FP64 matrix, r <= RMAX <= 64.
+// Lane a (< r) holds row a in a[0..RMAX); lanes >= r must hold identity rows.
+// Partial pivoting without moving data: at step p the not-yet-used row with
+// the largest |a[p]| is the pivot; det = sign(permutation) * prod(pivots).
+// Returns 0 when a pivot column is exactly zero.
+// ---------------------------------------------------------------------------
+template <int RMAX>
+SVMC_DEV double lu_det_rows(double (&a)[RMAX], int r, int lane) {
+  bool used = lane >= r;
+  int step = 64;
+  double det = 1.0;
+  bool zero = false;
+#pragma unroll
+  for (int p = 0; p < RMAX; ++p) {
+    if (p < r && !zero) {
+      double v = used ? -1.0 : fabs(a[p]);
+      int li = lane;
+      for (int o = 32; o >= 1; o >>= 1) {
+        double v2 = __shfl_xor(v, o, 64);
+        int l2 = __shfl_xor(li, o, 64);
+        if (v2 > v || (v2 == v && l2 < li)) { v = v2; li = l2; }
+      }
+      const int piv = uniform_i(li);
+      const double pv = readlane_d(a[p], piv);
+      if (pv == 0.0) {
+        zero = true;
+      } else {
+        det *= pv;
+        if (lane == piv) { used = true; step = p; }
+        const double inv = 1.0 / pv;
+        const double l = used ? 0.0 : a[p] * inv;
+#pragma unroll
+        for (int c = p + 1; c < RMAX; ++c) {
+          const double pr = readlane_d(a[c], piv);
+          a[c] = fma(-l, pr, a[c]);
+        }
+      }
+    }
+  }
+  if (zero) return 0.0;
+  // parity of the pivot order: inversions among lanes < r
+  int inv = 0;
+  for (int b = 0; b < r; ++b) {
+    int sb = __builtin_amdgcn_readlane(step, b);
+    if (lane < r && b > lane && sb < step) ++inv;
+  }
+  inv = wave_sum_i(inv);
+  return (inv & 1) ? -det : det;
+}

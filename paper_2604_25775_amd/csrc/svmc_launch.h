@@ -1,0 +1,56 @@
+// Host-side launchers of the scalevmc kernels (implemented in the .hip files,
+// called from api.cpp).  All are asynchronous on `st`.
+#pragma once
+#include <hip/hip_runtime.h>
+#include "svmc_dev.h"
+
+// Supported (precision, channels) pairs of the templated conv kernels.
+#define SVMC_FOR_EACH_PREC_C(X) \
+  X(PREC_F64, 8) X(PREC_F64, 16) X(PREC_F64, 24) X(PREC_F64, 32) \
+  X(PREC_F32, 8) X(PREC_F32, 16) X(PREC_F32, 24) X(PREC_F32, 32) \
+  X(PREC_BF16, 8) X(PREC_BF16, 16) X(PREC_BF16, 24) X(PREC_BF16, 32) \
+  X(PREC_BF16X3, 8) X(PREC_BF16X3, 16) X(PREC_BF16X3, 24) X(PREC_BF16X3, 32)
+
+namespace svmc {
+
+// setup.hip
+hipError_t launch_labels(const LatDev& lt, const Bufs& bf, hipStream_t st);
+hipError_t launch_forward(int prec, const LatDev& lt, const Bufs& bf, const ModelDev& md, void* h0tmp,
+                          hipStream_t st);
+hipError_t launch_rows(int prec, const LatDev& lt, const Bufs& bf, int L, int C, hipStream_t st);
+hipError_t launch_gj(const LatDev& lt, const Bufs& bf, hipStream_t st);
+hipError_t launch_gp(const LatDev& lt, const Bufs& bf, int C, hipStream_t st);
+hipError_t launch_logpsi(const LatDev& lt, const Bufs& bf, double* sign, double* logabs, hipStream_t st);
+
+// eloc.hip: low-rank local energies over all walkers of all lattices in one launch
+struct ElocOut {
+  double* eloc;
+  int32_t* nhops;
+  int32_t* code;
+  double* ratio;
+  int stride;       // row stride of code/ratio
+};
+size_t eloc_lowrank_smem(const LatDev* lats_host, int nlats, int prec, int L, int C);
+hipError_t launch_eloc_lowrank(int prec, const ModelDev& md, const LatDev* lats_dev, const LatDev* lats_host,
+                               int nlats, long long W, const Bufs& bf, const ElocOut& out, hipStream_t st);
+
+// full.hip: full-recompute comparison path
+hipError_t launch_eloc_full(int prec, const ModelDev& md, const LatDev& lt, const Bufs& bf, const ElocOut& out,
+                            double* ratio_tmp, int stride_tmp, hipStream_t st);
+
+// Per-(precision, channels) instances; each is compiled in its own
+// translation unit (the build defines SVMC_INST_P / SVMC_INST_C).
+#define SVMC_DECL_INST(P_, C_)                                                                          \
+  hipError_t eloc_lowrank_##P_##_##C_(const ModelDev& md, const LatDev* lats_dev, int nlats, long long W, \
+                                      const Bufs& bf, const ElocOut& out, size_t smem, hipStream_t st);   \
+  hipError_t eloc_full_##P_##_##C_(const ModelDev& md, const LatDev& lt, const Bufs& bf, const ElocOut& out, \
+                                   double* ratio_tmp, int stride, hipStream_t st);                        \
+  hipError_t forward_##P_##_##C_(const LatDev& lt, const Bufs& bf, const ModelDev& md, void* h0tmp,       \
+                                 hipStream_t st);
+SVMC_FOR_EACH_PREC_C(SVMC_DECL_INST)
+#undef SVMC_DECL_INST
+
+#define SVMC_CAT3_(a, b, c) a##b##_##c
+#define SVMC_CAT3(a, b, c) SVMC_CAT3_(a, b, c)
+
+}  // namespace svmc

@@ -94,3 +94,22 @@ def test_fd_gradient_matches_autograd(lat):
     idx = np.sort(rng.choice(theta.numel(), 60, replace=False))
     g_fd = fd_grad(lat, p, occ, indices=idx)
     assert np.max(np.abs(g_fd - g_ref[idx])) < 2e-7 * (1 + np.max(np.abs(g_ref)))
+
+
+def test_conv_input_rounding_matches_torch_bf16_inputs():
+    """With conv_input_round = BF16 rounding, each layer equals conv2d applied
+    to the BF16-rounded layer input plus the unrounded residual."""
+    from oracle.ansatz import round_bf16
+    lat = wl.Lattice(6, 4, 1, 0, n_up=3, n_dn=4)
+    p = wl.random_params([lat], wl.Model(2, 8), seed=9)
+    o = wl.random_occupations(lat, 1, seed=4)[0]
+    Hs = features(lat, p, o, "tanh", conv_input_round=round_bf16)
+    W = torch.from_numpy(p.conv_w)
+    b = torch.from_numpy(p.conv_b)
+    for l in range(2):
+        x = torch.from_numpy(round_bf16(Hs[l])).T.reshape(1, -1, lat.Ly, lat.Lx)
+        xp = F.pad(F.pad(x, (1, 1, 0, 0), mode="circular"), (0, 0, 1, 1))
+        y = F.conv2d(xp, W[l].permute(3, 2, 0, 1), b[l]).reshape(-1, lat.N).T.numpy()
+        assert np.max(np.abs(Hs[l + 1] - (Hs[l] + np.tanh(y)))) < 1e-12
+    # the rounding does change the result (the hook is live)
+    assert np.max(np.abs(Hs[-1] - features(lat, p, o, "tanh")[-1])) > 1e-6
