@@ -10,7 +10,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/scalevmc.h"
+#include "scalevmc.h"
 #include "svmc_launch.h"
 
 using namespace svmc;
@@ -446,7 +446,7 @@ svmc_status svmc_local_energy(svmc_ctx* ctx, svmc_path path, double* eloc, int32
   }
   if (path != SVMC_PATH_FULL) return ctx->fail(SVMC_ERR_INVALID_ARG, "unknown path");
   for (auto& lt : ctx->ld)
-    if (lt.N * ctx->C * ctx->tf_bytes() > 64 * 1024 || lt.N > 256 || lt.nmax > 128)
+    if (lt.N * (ctx->C + 16 / ctx->tf_bytes()) * ctx->tf_bytes() > 64 * 1024 || lt.N > 256 || lt.nmax > 128)
       return ctx->fail(SVMC_ERR_UNSUPPORTED, "full-recompute path supports N <= 256, N*C features <= 64 KiB");
   const int stride = ctx->max_hops();
   if ((s = ctx->hip(ctx->ratio_tmp.ensure((size_t)ctx->Wtot * stride * 8), "alloc"))) return s;

@@ -1,11 +1,12 @@
 // Low-rank local energies (Sec. II.A definition of E_loc with the Hubbard
 // Hamiltonian of Sec. III; ratios by the local update of Sec. II.C).
 //
-// One workgroup per walker (4 wavefronts), lattices of a mixed batch in the
+// One workgroup (two wavefronts) per walker, lattices of a mixed batch in the
 // same launch.  The walker's connected configurations are enumerated into LDS
 // in canonical order (spin up first, source site ascending, directions +x,
-// -x, +y, -y, then the four diagonals when t' != 0); wavefront v evaluates
-// hops v, v+4, ...; the per-wave partial sums are combined in a fixed order.
+// -x, +y, -y, then the four diagonals when t' != 0) and evaluated one after
+// the other by both wavefronts together (conv split between them, then one
+// determinant per wavefront); the sum runs in hop order.
 #include "hop.h"
 #include "svmc_launch.h"
 
@@ -18,37 +19,42 @@ struct ElocLds {
 
 inline __host__ __device__ int align16(int x) { return (x + 15) & ~15; }
 
-__host__ __device__ inline ElocLds eloc_layout(int N, int maxhops, int Gx, int Gy, int C, int tfb) {
+constexpr int ELOC_NW = 2;     // wavefronts per workgroup
+
+__host__ __device__ inline ElocLds eloc_layout(int N, int maxhops, int Gx, int Gy, int L, int C, int tfb) {
   ElocLds o;
   o.occ = 0;
   o.lab = align16(N);
   o.hops = o.lab + align16(4 * N);
   o.red = o.hops + align16(4 * maxhops);
   o.scratch = o.red + 64;
-  o.wave_bytes = (int)(((size_t)Gx * Gy * C * tfb + 15) / 16 * 16 + (size_t)2 * Gx * Gy * sizeof(int));
+  o.wave_bytes = hop_scratch(Gx, Gy, L, C, tfb).bytes;
   return o;
 }
 
-// exclusive block scan of one int per thread (256 threads)
+// exclusive block scan of one int per thread (blockDim.x = 64 * waves)
 SVMC_DEV int block_excl_scan(int v, int* tmp, int& total) {
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nwv = blockDim.x >> 6;
   const int incl = wave_incl_scan(v, lane);
   if (lane == 63) tmp[wv] = incl;
   __syncthreads();
   int off = 0;
-  for (int k = 0; k < wv; ++k) off += tmp[k];
-  total = tmp[0] + tmp[1] + tmp[2] + tmp[3];
+  total = 0;
+  for (int k = 0; k < nwv; ++k) {
+    if (k < wv) off += tmp[k];
+    total += tmp[k];
+  }
   __syncthreads();
   return off + incl - v;
 }
 
 // Enumerate the walker's hops into `hops` (code (i << 4) | (spin << 3) | d);
 // returns the count.  At most `cap` codes are stored (a walker with a wrong
-// electron count may have more).  Needs 256 threads.
+// electron count may have more).  All threads of the block take part.
 SVMC_DEV int enumerate_hops(const LatDev& lt, const int8_t* occ_s, int* hops, int* tmp, int cap) {
   const int N = lt.N, nd = lt.nd, tid = threadIdx.x;
   const int items = 2 * N;
-  const int per = (items + 255) / 256;
+  const int per = (items + blockDim.x - 1) / blockDim.x;
   const int e0 = tid * per;
   int cnt = 0;
   for (int e = e0; e < min(items, e0 + per); ++e) {
@@ -83,10 +89,11 @@ SVMC_DEV int enumerate_hops(const LatDev& lt, const int8_t* occ_s, int* hops, in
 }
 
 #ifdef SVMC_INST_P
-template <int P, int C, int MAXT>
-__global__ __launch_bounds__(256) void k_eloc_lowrank(ModelDev md, const LatDev* __restrict__ lats, int nlats,
-                                                      Bufs bf, ElocOut out) {
+template <int P, int C>
+__global__ __launch_bounds__(64 * ELOC_NW) __attribute__((amdgpu_waves_per_eu(2))) void k_eloc_lowrank(ModelDev md, const LatDev* __restrict__ lats,
+                                                               int nlats, Bufs bf, ElocOut out) {
   typedef typename PrecT<P>::Tf Tf;
+  constexpr int NW = ELOC_NW, NTH = 64 * NW;
   extern __shared__ __attribute__((aligned(16))) char smem[];
   const long long w = blockIdx.x;
   int li = 0;
@@ -95,97 +102,95 @@ __global__ __launch_bounds__(256) void k_eloc_lowrank(ModelDev md, const LatDev*
   const long long wl = w - lt.w0;
   const int N = lt.N, nm = lt.nmax;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const ElocLds lay = eloc_layout(N, lt.maxhops, lt.Gx, lt.Gy, C, (int)sizeof(Tf));
+  const ElocLds lay = eloc_layout(N, lt.maxhops, lt.Gx, lt.Gy, md.L, C, (int)sizeof(Tf));
   int8_t* occ_s = (int8_t*)(smem + lay.occ);
   int16_t* lab_s = (int16_t*)(smem + lay.lab);
   int* hops = (int*)(smem + lay.hops);
   double* red = (double*)(smem + lay.red);
-  char* scratch = smem + lay.scratch + wv * lay.wave_bytes;
+  char* scratch = smem + lay.scratch;
 
   const int8_t* occ_g = bf.occ + lt.occ_off + wl * N;
   const int16_t* lab_g = bf.lab + lt.lab_off + wl * 2LL * N;
-  for (int s = tid; s < N; s += 256) occ_s[s] = occ_g[s];
-  for (int s = tid; s < 2 * N; s += 256) lab_s[s] = lab_g[s];
+  for (int s = tid; s < N; s += NTH) occ_s[s] = occ_g[s];
+  for (int s = tid; s < 2 * N; s += NTH) lab_s[s] = lab_g[s];
   __syncthreads();
-  const int H = min(enumerate_hops(lt, occ_s, hops, (int*)red, lt.maxhops), lt.maxhops);
+  const int H = uniform_i(min(enumerate_hops(lt, occ_s, hops, (int*)red, lt.maxhops), lt.maxhops));
   const bool bad = (bf.flags[w] & (1 | 8)) != 0;
 
   const Tf* featw = (const Tf*)bf.feat + lt.feat_off + wl * (long long)md.L * N * C;
   const double* Gw = bf.G + lt.g_off + wl * 2LL * N * nm;
   const double* PTw = bf.PT + lt.pt_off + wl * 2LL * nm * C;
   const int KM = lt.Gx * lt.Gy;
-  int* kl = (int*)(scratch + (((size_t)KM * C * sizeof(Tf) + 15) / 16 * 16));
+  const HopScratch hsc = hop_scratch(lt.Gx, lt.Gy, md.L, C, (int)sizeof(Tf));
+  int* kl = (int*)(scratch + hsc.klists) + wv * KM;
+  double* stage = (double*)(scratch + (wv == 0 ? hsc.stage0 : hsc.stage1));
+  double* misc = (double*)(scratch + hsc.misc);
 
   double part = 0.0;
   bool nonfinite = false;
   if (!bad) {
-    for (int hh = wv; hh < H; hh += 4) {
-      const int code = hops[hh];
+    for (int hh = 0; hh < H; ++hh) {
+      const int code = uniform_i(hops[hh]);
       const int i = code >> 4, sp = (code >> 3) & 1, d = code & 7;
       const HopGeom g = hop_geom(lt, md.L, sp, i, d);
       int olx, owx, oly, owy;
-      hop_features<P, C, MAXT>(md, lt, g, occ_s, featw, (Tf*)nullptr, scratch, lane, olx, owx, oly, owy);
-      int nk[2];
-      const int hpos = hop_klists(lt, g, occ_s, lab_s, olx, owx, oly, owy, kl, KM, nk, lane);
-      double R = 1.0;
-#pragma unroll
-      for (int tau = 0; tau < 2; ++tau) {
-        const double* PTt = PTw + (long long)tau * nm * C;
-        const double* Gj = Gw + ((long long)tau * N + g.j) * nm;
-        R *= hop_det<Tf, C>(kl + tau * KM, nk[tau], tau == sp, tau == sp ? hpos : -1, (const Tf*)scratch, PTt,
-                            Gj, lane);
-      }
-      const double th = d < 4 ? lt.t : lt.tp;
-      part += -th * R;
-      nonfinite |= !isfinite(R);
-      if (out.ratio && lane == 0) {
-        out.ratio[w * out.stride + hh] = R;
-        out.code[w * out.stride + hh] = code;
+      hop_features<P, C, NW>(md, lt, g, occ_s, featw, (Tf*)nullptr, scratch, hsc, olx, owx, oly, owy);
+      // wavefront wv: determinant of spin wv
+      int hpos;
+      const int K = hop_klist(lt, g, occ_s, lab_s, wv, olx, owx, oly, owy, kl, hpos, lane);
+      const double* PTt = PTw + (long long)wv * nm * C;
+      const double* Gj = Gw + ((long long)wv * N + g.j) * nm;
+      const double Rt = hop_det<Tf, C>(kl, K, wv == sp, hpos, (const Tf*)scratch, PTt, Gj, stage, lane);
+      if (lane == 0) misc[wv] = Rt;
+      __syncthreads();
+      if (tid == 0) {
+        const double R = misc[0] * misc[1];
+        part += -(d < 4 ? lt.t : lt.tp) * R;
+        nonfinite |= !isfinite(R);
+        if (out.ratio) {
+          out.ratio[w * out.stride + hh] = R;
+          out.code[w * out.stride + hh] = code;
+        }
       }
     }
   }
-  __syncthreads();
-  if (lane == 0) red[wv] = part;
-  if (lane == 0 && nonfinite) atomicOr(bf.flags + w, 2);
-  __syncthreads();
   if (tid == 0) {
+    if (nonfinite) atomicOr(bf.flags + w, 2);
     int ndbl = 0;
     for (int s = 0; s < N; ++s) ndbl += occ_s[s] == 3;
-    const double e = lt.U * ndbl + ((red[0] + red[1]) + (red[2] + red[3]));
-    out.eloc[w] = bad ? NAN : e;
+    out.eloc[w] = bad ? NAN : lt.U * ndbl + part;
     if (out.nhops) out.nhops[w] = H;
   }
   if (bad && out.ratio) {
-    for (int hh = tid; hh < H; hh += 256) {
+    for (int hh = tid; hh < H; hh += NTH) {
       out.ratio[w * out.stride + hh] = NAN;
       out.code[w * out.stride + hh] = hops[hh];
     }
   }
 }
 
-template <int P, int C, int MAXT>
+template <int P, int C>
 static hipError_t eloc_impl(const ModelDev& md, const LatDev* lats_dev, int nlats, long long W, const Bufs& bf,
                             const ElocOut& out, size_t smem, hipStream_t st) {
-  auto kern = k_eloc_lowrank<P, C, MAXT>;
+  auto kern = k_eloc_lowrank<P, C>;
   hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(kern, dim3((unsigned)W), dim3(256), smem, st, md, lats_dev, nlats, bf, out);
+  hipLaunchKernelGGL(kern, dim3((unsigned)W), dim3(64 * ELOC_NW), smem, st, md, lats_dev, nlats, bf, out);
   return hipGetLastError();
 }
 
 hipError_t SVMC_CAT3(eloc_lowrank_, SVMC_INST_P, SVMC_INST_C)(const ModelDev& md, const LatDev* lats_dev,
                                                               int nlats, long long W, const Bufs& bf,
                                                               const ElocOut& out, size_t smem, hipStream_t st) {
-  return md.L > 2 ? eloc_impl<SVMC_INST_P, SVMC_INST_C, 8>(md, lats_dev, nlats, W, bf, out, smem, st)
-                  : eloc_impl<SVMC_INST_P, SVMC_INST_C, 4>(md, lats_dev, nlats, W, bf, out, smem, st);
+  return eloc_impl<SVMC_INST_P, SVMC_INST_C>(md, lats_dev, nlats, W, bf, out, smem, st);
 }
 #else
 size_t eloc_lowrank_smem(const LatDev* lats, int nlats, int prec, int L, int C) {
   const int tfb = prec == PREC_F64 ? 8 : 4;
   size_t mx = 0;
   for (int l = 0; l < nlats; ++l) {
-    const ElocLds o = eloc_layout(lats[l].N, lats[l].maxhops, lats[l].Gx, lats[l].Gy, C, tfb);
-    mx = std::max(mx, (size_t)o.scratch + 4 * (size_t)o.wave_bytes);
+    const ElocLds o = eloc_layout(lats[l].N, lats[l].maxhops, lats[l].Gx, lats[l].Gy, L, C, tfb);
+    mx = std::max(mx, (size_t)o.scratch + (size_t)o.wave_bytes);
   }
   return mx;
 }

@@ -118,8 +118,9 @@ __global__ __launch_bounds__(256) void k_full_ratio(ModelDev md, LatDev lt, Bufs
   const int N = lt.N, nm = lt.nmax, Lx = lt.Lx;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   if (bf.flags[w] & (1 | 8)) return;
-  Tf* grid = (Tf*)smem;                                    // [N][C]
-  int8_t* occ_s = (int8_t*)(smem + (size_t)N * C * sizeof(Tf));
+  constexpr int SP = SiteStride<Tf, C>::value;            // padded site stride
+  Tf* grid = (Tf*)smem;                                    // [N][SP]
+  int8_t* occ_s = (int8_t*)(smem + (size_t)N * SP * sizeof(Tf));
   const int8_t* occ_g = bf.occ + lt.occ_off + wl * N;
   for (int s = tid; s < N; s += 256) occ_s[s] = occ_g[s];
   __syncthreads();
@@ -138,7 +139,7 @@ __global__ __launch_bounds__(256) void k_full_ratio(ModelDev md, LatDev lt, Bufs
   __syncthreads();
   // H'_0
   const Tf* E = (const Tf*)md.embed;
-  for (int e = tid; e < N * C; e += 256) grid[e] = E[occ_s[e / C] * C + (e % C)];
+  for (int e = tid; e < N * C; e += 256) grid[(e / C) * SP + (e % C)] = E[occ_s[e / C] * C + (e % C)];
   __syncthreads();
   const int T = (N + 15) >> 4;
   for (int l = 0; l < md.L; ++l) {
@@ -157,7 +158,7 @@ __global__ __launch_bounds__(256) void k_full_ratio(ModelDev md, LatDev lt, Bufs
           bool ok = m < N;
           if (lt.pbc_x) xx = imod(xx, Lx); else ok = ok && xx >= 0 && xx < Lx;
           if (lt.pbc_y) yy = imod(yy, lt.Ly); else ok = ok && yy >= 0 && yy < lt.Ly;
-          nb[tp] = ok ? (xx + Lx * yy) * C : -1;
+          nb[tp] = ok ? (xx + Lx * yy) * SP : -1;
         }
         conv_tile<P, C>(grid, nb, Bl, lane, acc[q]);
       }
@@ -173,7 +174,7 @@ __global__ __launch_bounds__(256) void k_full_ratio(ModelDev md, LatDev lt, Bufs
           for (int v = 0; v < 4; ++v) {
             const int r = 16 * t + OutMap<P>::row(lane, v);
             const int n = 16 * nt + OutMap<P>::col(lane, v);
-            if (r < N && n < C) acc[q][nt][v] = grid[r * C + n] + act_fn<Tf>(md.act, acc[q][nt][v] + bias[n]);
+            if (r < N && n < C) acc[q][nt][v] = grid[r * SP + n] + act_fn<Tf>(md.act, acc[q][nt][v] + bias[n]);
           }
       }
     }
@@ -188,7 +189,7 @@ __global__ __launch_bounds__(256) void k_full_ratio(ModelDev md, LatDev lt, Bufs
           for (int v = 0; v < 4; ++v) {
             const int r = 16 * t + OutMap<P>::row(lane, v);
             const int n = 16 * nt + OutMap<P>::col(lane, v);
-            if (r < N && n < C) grid[r * C + n] = acc[q][nt][v];
+            if (r < N && n < C) grid[r * SP + n] = acc[q][nt][v];
           }
       }
     }
@@ -214,7 +215,7 @@ __global__ __launch_bounds__(256) void k_full_ratio(ModelDev md, LatDev lt, Bufs
       const int k = ty + 16 * a;
       int site = 0;
       if (k < n) site = (tau == sp && k == kmove) ? g.j : posg[tau * nm + k];
-      const Tf* hl = grid + site * C;
+      const Tf* hl = grid + site * SP;
 #pragma unroll
       for (int bb = 0; bb < R; ++bb) {
         const int m = tx + 16 * bb;
@@ -243,7 +244,7 @@ template <int P, int C, int R>
 static hipError_t full_impl(const ModelDev& md, const LatDev& lt, const Bufs& bf, const ElocOut& out,
                             double* ratio_tmp, int stride, hipStream_t st) {
   typedef typename PrecT<P>::Tf Tf;
-  const size_t smem = (size_t)lt.N * C * sizeof(Tf) + ((lt.N + 15) & ~15);
+  const size_t smem = (size_t)lt.N * SiteStride<Tf, C>::value * sizeof(Tf) + ((lt.N + 15) & ~15);
   auto kern = k_full_ratio<P, C, R, 4>;
   hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
   if (e != hipSuccess) return e;

@@ -107,6 +107,19 @@ SVMC_DEV double readlane_d(double x, int lane) {
 
 SVMC_DEV int uniform_i(int x) { return __builtin_amdgcn_readfirstlane(x); }
 
+// Maximum of an unsigned key over the wavefront with DPP lane exchanges
+// (quad swaps, half-row and row mirrors, then row broadcasts 15 and 31);
+// lane 63 ends with the maximum, which is returned to every lane.
+SVMC_DEV unsigned wave_max_u32(unsigned v) {
+  v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, false));   // quad_perm 1,0,3,2
+  v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, false));   // quad_perm 2,3,0,1
+  v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x141, 0xF, 0xF, false));  // row_half_mirror
+  v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x140, 0xF, 0xF, false));  // row_mirror
+  v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xA, 0xF, false));  // row_bcast:15
+  v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xC, 0xF, false));  // row_bcast:31
+  return (unsigned)__builtin_amdgcn_readlane((int)v, 63);
+}
+
 SVMC_DEV double wave_sum_d(double v) {
   for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
   return v;
@@ -229,6 +242,94 @@ SVMC_DEV void conv_tile(const typename PrecT<P>::Tf* __restrict__ src, const int
 #pragma unroll
       for (int nt = 0; nt < CC::NT; ++nt)
         mfma(acc[nt], a, Bl[(q * CC::NT + nt) * 64 + lane]);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Multi-tile conv layer for one wavefront: up to MAXT tiles of 16 output sites
+// on an LDS grid [gy][gx][C].  Each tile row's neighbours are described by
+// packed grid coordinates: byte k of gxs[t] is the grid x index of offset
+// dx = k - 1 (0xFF when off the lattice), gys[t] likewise for y (a padding row
+// has all bytes 0xFF).  The loop runs chunk-major so every B fragment is read
+// once per layer and reused by all tiles; per output element the accumulation
+// order is the same as conv_tile's, so both give identical values.
+// ---------------------------------------------------------------------------
+template <int P, int C, int MAXT>
+SVMC_DEV void conv_layer_tiles(const typename PrecT<P>::Tf* __restrict__ grid, int Gx,
+                               const unsigned (&gxs)[MAXT], const unsigned (&gys)[MAXT], int T,
+                               const typename PrecT<P>::Tb* __restrict__ Bl, int lane,
+                               typename PrecT<P>::Acc (&acc)[MAXT][ConvCfg<P, C>::NT]) {
+  typedef typename PrecT<P>::Tf Tf;
+  typedef typename PrecT<P>::Tb Tb;
+  typedef ConvCfg<P, C> CC;
+  const int g = lane >> 4;
+#pragma unroll
+  for (int t = 0; t < MAXT; ++t)
+#pragma unroll
+    for (int nt = 0; nt < CC::NT; ++nt)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[t][nt][v] = 0;
+#pragma unroll
+  for (int q = 0; q < CC::Q; ++q) {
+    Tb b[CC::NT];
+#pragma unroll
+    for (int nt = 0; nt < CC::NT; ++nt) b[nt] = Bl[(q * CC::NT + nt) * 64 + lane];
+    int tap, c0;
+    bool kok;
+    if constexpr (P == PREC_BF16 || P == PREC_BF16X3) {
+      const int k0 = 32 * q + 8 * g;
+      kok = k0 < CC::K;
+      tap = kok ? k0 / C : 0;
+      c0 = k0 % C;
+    } else {
+      kok = true;
+      tap = (4 * q) / C;
+      c0 = (4 * q) % C + g;
+    }
+    const int sx = 8 * (tap % 3), sy = 8 * (tap / 3);
+#pragma unroll
+    for (int t = 0; t < MAXT; ++t) {
+      if (t < T) {
+        const unsigned gx = (gxs[t] >> sx) & 0xFFu, gy = (gys[t] >> sy) & 0xFFu;
+        const bool ok = kok && gx != 0xFFu && gy != 0xFFu;
+        const int off = ((int)gy * Gx + (int)gx) * C + c0;
+        if constexpr (P == PREC_BF16 || P == PREC_BF16X3) {
+          float x[8];
+          if (ok) {
+            const float4* p4 = reinterpret_cast<const float4*>(grid + off);
+            const float4 x0 = p4[0], x1 = p4[1];
+            x[0] = x0.x; x[1] = x0.y; x[2] = x0.z; x[3] = x0.w;
+            x[4] = x1.x; x[5] = x1.y; x[6] = x1.z; x[7] = x1.w;
+          } else {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) x[e] = 0.0f;
+          }
+          v8bf a;
+#pragma unroll
+          for (int e = 0; e < 8; ++e) a[e] = (__bf16)x[e];
+#pragma unroll
+          for (int nt = 0; nt < CC::NT; ++nt) mfma(acc[t][nt], a, b[nt]);
+          if constexpr (P == PREC_BF16X3) {
+            v8bf a2, a3;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+              const float r1 = x[e] - (float)a[e];
+              a2[e] = (__bf16)r1;
+              a3[e] = (__bf16)(r1 - (float)a2[e]);
+            }
+#pragma unroll
+            for (int nt = 0; nt < CC::NT; ++nt) {
+              mfma(acc[t][nt], a2, b[nt]);
+              mfma(acc[t][nt], a3, b[nt]);
+            }
+          }
+        } else {
+          const Tf a = ok ? grid[off] : Tf(0);
+#pragma unroll
+          for (int nt = 0; nt < CC::NT; ++nt) mfma(acc[t][nt], a, b[nt]);
+        }
+      }
     }
   }
 }
