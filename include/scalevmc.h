@@ -168,16 +168,27 @@ svmc_status svmc_local_energy(svmc_ctx* ctx, svmc_path path, double* eloc,
  * (seed, 0) and counter (w, step0 + k, 0, 0): electron e = mulhi(w0, n_up +
  * n_dn) (labels of spin up first), direction d = w1 >> 62 (+x, -x, +y, -y),
  * u = (w2 >> 11) 2^-53; the move is rejected when the target is off the
- * lattice or holds the same spin, else accepted iff u < ratio^2.  Accepted
- * moves update features, inverses (Woodbury), log|psi|; every refresh_every
- * accepted moves a walker's inverse is rebuilt in FP64.  n_accept: device
- * [W] int64, incremented (not cleared) by the number of accepted moves. */
+ * lattice or holds the same spin, else accepted iff u < ratio^2 (ratio by the
+ * local update of Sec. II.C, FP64 determinant part).  An accepted move
+ * rewrites the walker's cached features on the update box, updates
+ * G = M Phi^-1 and P = W Phi^-1 by the Sherman-Morrison-Woodbury formula
+ * (Sec. II.C) and log|psi|, sign by the ratio.  After refresh_every accepted
+ * moves a walker pauses; its rows, inverse, log|psi| and G/P are rebuilt in
+ * FP64 (SVMC_W_DRIFT set first if the maintained G had drifted by more than
+ * 1e-8 on its occupied rows) and it resumes at its next proposal, so the
+ * chain does not depend on refresh_every.  Walkers flagged SINGULAR,
+ * NONFINITE or BADCOUNT are not moved.
+ * n_accept: device [W] int64 incremented by each walker's accepted moves, or
+ * NULL.  The call waits on `stream` (the host reads how many walkers paused).
+ * Errors: SVMC_ERR_STATE without walkers, SVMC_ERR_INVALID_ARG for
+ * n_sweeps < 0 or refresh_every < 1, SVMC_ERR_UNSUPPORTED when one walker's
+ * workspace exceeds 160 KiB of LDS. */
 svmc_status svmc_sweep(svmc_ctx* ctx, int32_t n_sweeps, uint64_t seed,
                        uint64_t step0, int64_t* n_accept, hipStream_t stream);
 
 /* Rebuild every walker's Slater inverse, log|psi| and low-rank precompute in
- * FP64 from the cached features (sets SVMC_W_DRIFT where the old inverse had
- * drifted). */
+ * FP64 from the cached features (when G/P were current, SVMC_W_DRIFT is set
+ * first where G had drifted by more than 1e-8 on its occupied rows). */
 svmc_status svmc_refresh(svmc_ctx* ctx, hipStream_t stream);
 
 /* Current configurations.  occ: device int8 (same layout as load); pos

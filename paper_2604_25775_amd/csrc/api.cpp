@@ -62,6 +62,7 @@ struct svmc_ctx {
   int64_t nparams = 0;
   bool have_params = false, have_walkers = false;
   bool prepared = false;   // G/P match the current walkers
+  bool dets_fresh = false; // rows M, inverses and log|psi| rebuilt since the last move
   // parameters
   DevBuf Bpack, embed, bias;
   std::vector<DevBuf> base, W, b;    // per lattice
@@ -71,6 +72,7 @@ struct svmc_ctx {
   long long Wtot = 0;
   DevBuf occ, lab, pos, feat, inv, M, G, PT, ldet, sgn, flags, nacc;
   DevBuf ratio_tmp;
+  DevBuf sw_prog, sw_paused;         // sweep progress per walker, paused-walker counter
   std::vector<int64_t> counts;
 
   svmc_status fail(svmc_status s, const std::string& m) {
@@ -311,14 +313,16 @@ static svmc_status rebuild_dets(svmc_ctx* ctx, hipStream_t st) {
     if ((s = ctx->hip(launch_gj(lt, bf, st), "inverse"))) return s;
   }
   ctx->prepared = false;
+  ctx->dets_fresh = true;
   return SVMC_OK;
 }
 
 // Low-rank precompute: rows of every site from the current features, then
-// G = M Phi^-1 and P^T.
+// G = M Phi^-1 and P^T (inverses first rebuilt if moves made them stale).
 static svmc_status prepare(svmc_ctx* ctx, hipStream_t st) {
-  const Bufs bf = ctx->bufs();
   svmc_status s;
+  if (!ctx->dets_fresh && (s = rebuild_dets(ctx, st))) return s;
+  const Bufs bf = ctx->bufs();
   for (auto& lt : ctx->ld) {
     if ((s = ctx->hip(launch_rows(ctx->prec, lt, bf, ctx->L, ctx->C, st), "rows"))) return s;
     if ((s = ctx->hip(launch_gp(lt, bf, ctx->C, st), "G/P precompute"))) return s;
@@ -461,14 +465,67 @@ svmc_status svmc_local_energy(svmc_ctx* ctx, svmc_path path, double* eloc, int32
 svmc_status svmc_refresh(svmc_ctx* ctx, hipStream_t st) {
   if (!ctx) return SVMC_ERR_INVALID_ARG;
   if (!ctx->have_walkers) return ctx->fail(SVMC_ERR_STATE, "no walkers loaded");
-  return rebuild_dets(ctx, st);
+  const Bufs bf = ctx->bufs();
+  svmc_status s;
+  if (ctx->prepared)
+    for (auto& lt : ctx->ld)
+      if ((s = ctx->hip(launch_drift(lt, bf, 0, 0, st), "drift check"))) return s;
+  if ((s = rebuild_dets(ctx, st))) return s;
+  return prepare(ctx, st);
 }
 
 svmc_status svmc_sweep(svmc_ctx* ctx, int32_t n_sweeps, uint64_t seed, uint64_t step0, int64_t* n_accept,
                        hipStream_t st) {
   if (!ctx) return SVMC_ERR_INVALID_ARG;
-  (void)n_sweeps; (void)seed; (void)step0; (void)n_accept; (void)st;
-  return ctx->fail(SVMC_ERR_UNSUPPORTED, "sweep not built yet");
+  if (!ctx->have_walkers) return ctx->fail(SVMC_ERR_STATE, "no walkers loaded");
+  if (n_sweeps < 0) return ctx->fail(SVMC_ERR_INVALID_ARG, "negative sweep count");
+  if (n_sweeps == 0) return SVMC_OK;
+  const int every = ctx->model.refresh_every;
+  if (every < 1) return ctx->fail(SVMC_ERR_INVALID_ARG, "refresh_every must be >= 1");
+  for (auto& lt : ctx->ld)
+    if ((long long)n_sweeps * lt.N > (1LL << 40)) return ctx->fail(SVMC_ERR_INVALID_ARG, "too many sweeps");
+  const size_t smem = sweep_smem(ctx->ld.data(), (int)ctx->ld.size(), ctx->prec, ctx->L, ctx->C);
+  if (smem > 160 * 1024) return ctx->fail(SVMC_ERR_UNSUPPORTED, "sweep workspace exceeds 160 KiB of LDS");
+  svmc_status s;
+  if (!ctx->prepared && (s = prepare(ctx, st))) return s;
+  if ((s = ctx->hip(ctx->sw_prog.ensure((size_t)ctx->Wtot * 8), "alloc")) ||
+      (s = ctx->hip(ctx->sw_paused.ensure(4), "alloc")) ||
+      (s = ctx->hip(hipMemsetAsync(ctx->sw_prog.p, 0, (size_t)ctx->Wtot * 8, st), "memset")))
+    return s;
+  SweepArgs sa;
+  sa.seed = seed;
+  sa.step0 = step0;
+  sa.n_sweeps = n_sweeps;
+  sa.refresh_every = every;
+  sa.n_accept = n_accept;
+  sa.prog = ctx->sw_prog.as<int64_t>();
+  sa.paused = ctx->sw_paused.as<int>();
+  const Bufs bf = ctx->bufs();
+  const ModelDev md = ctx->mdev();
+  ctx->dets_fresh = false;
+  // Walkers stop after `every` accepted moves; the masked FP64 refresh below
+  // rebuilds exactly those and the next launch resumes them.
+  for (;;) {
+    if ((s = ctx->hip(hipMemsetAsync(sa.paused, 0, 4, st), "memset"))) return s;
+    if ((s = ctx->hip(launch_sweep(ctx->prec, md, ctx->lats_dev.as<LatDev>(), ctx->ld.data(), (int)ctx->ld.size(),
+                                   ctx->Wtot, bf, sa, st),
+                      "sweep")))
+      return s;
+    int paused = 0;
+    if ((s = ctx->hip(hipMemcpyAsync(&paused, sa.paused, 4, hipMemcpyDeviceToHost, st), "paused copy")) ||
+        (s = ctx->hip(hipStreamSynchronize(st), "sweep sync")))
+      return s;
+    if (paused == 0) break;
+    for (auto& lt : ctx->ld) {
+      if ((s = ctx->hip(launch_drift(lt, bf, 1, every, st), "drift check")) ||
+          (s = ctx->hip(launch_rows(ctx->prec, lt, bf, ctx->L, ctx->C, st, 1, every), "rows")) ||
+          (s = ctx->hip(launch_gj(lt, bf, st, 1, every), "inverse")) ||
+          (s = ctx->hip(launch_gp(lt, bf, ctx->C, st, 1, every), "G/P precompute")) ||
+          (s = ctx->hip(launch_clear_nacc(lt, bf, every, st), "clear")))
+        return s;
+    }
+  }
+  return SVMC_OK;
 }
 
 svmc_status svmc_get_state(svmc_ctx* ctx, int8_t* occ, int16_t* pos, hipStream_t st) {

@@ -188,10 +188,11 @@ SVMC_DEV void conv_tile_grid(const typename PrecT<P>::Tf* __restrict__ grid, int
 // workgroup (wave = this thread's wavefront).  On return (after a barrier)
 // the grid's first count*C entries hold D = H'_L - H_L on the layer-L box
 // (index m = ox + owx * oy).  If `commit` is non-null every new layer value is
-// also stored into the cache (accepted move).
+// also stored into the cache (accepted move); commit may equal featw (the
+// box of a layer never overlaps the ring read from the cache for the next).
 template <int P, int C, int NW>
 SVMC_DEV void hop_features(const ModelDev& md, const LatDev& lt, const HopGeom& h, const int8_t* occ_s,
-                           const typename PrecT<P>::Tf* __restrict__ featw,
+                           const typename PrecT<P>::Tf* featw,
                            typename PrecT<P>::Tf* commit, char* scratch, const HopScratch& hs,
                            int& olx, int& owx, int& oly, int& owy) {
   typedef typename PrecT<P>::Tf Tf;

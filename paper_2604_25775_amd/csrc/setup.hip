@@ -136,9 +136,10 @@ __global__ void k_labels(LatDev lt, Bufs bf) {
 
 // M_s[x][m] = base_s[x][m] + sum_c H_L[x][c] W_s[c][m] + b_s[m]
 template <class Tf>
-__global__ void k_rows(LatDev lt, Bufs bf, int L, int C) {
+__global__ void k_rows(LatDev lt, Bufs bf, int L, int C, int only_due, int refresh_every) {
   const int N = lt.N, nm = lt.nmax;
   const long long wl = blockIdx.z;
+  if (only_due && bf.nacc[lt.w0 + wl] < refresh_every) return;
   const int sp = blockIdx.y;
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= N * nm) return;
@@ -156,10 +157,11 @@ __global__ void k_rows(LatDev lt, Bufs bf, int L, int C) {
 // Phi_s = M_s[pos] (rows in label order) -> Phi_s^-1, log|det|, sign, with
 // the register-tiled Gauss-Jordan elimination of tiled_lu.h (n <= 16 R).
 template <int R>
-__global__ __launch_bounds__(256) void k_gj(LatDev lt, Bufs bf) {
+__global__ __launch_bounds__(256) void k_gj(LatDev lt, Bufs bf, int only_due, int refresh_every) {
   const int sp = blockIdx.y;
   const long long wl = blockIdx.x;
   const long long w = lt.w0 + wl;
+  if (only_due && bf.nacc[w] < refresh_every) return;
   const int n = lt.n[sp], nm = lt.nmax;
   const int tid = threadIdx.x, tx = tid >> 4, ty = tid & 15;
   __shared__ GjShared<R> sh;
@@ -215,7 +217,8 @@ __global__ __launch_bounds__(256) void k_gj(LatDev lt, Bufs bf) {
 // G_s = M_s Phi_s^-1 (rows 0..N-1) and P_s^T = (W_s Phi_s^-1)^T (rows N..N+C-1
 // of the stacked left factor).  64x64 output tiles, 4x4 per thread, K chunks
 // of 16 through LDS.  grid.x = tile + ntiles * (sp + 2 * wl).
-__global__ __launch_bounds__(256) void k_gp(LatDev lt, Bufs bf, int C, int tiles_r, int tiles_c) {
+__global__ __launch_bounds__(256) void k_gp(LatDev lt, Bufs bf, int C, int tiles_r, int tiles_c, int only_due,
+                                            int refresh_every) {
   const int N = lt.N, nm = lt.nmax;
   long long bid = blockIdx.x;
   const int ntiles = tiles_r * tiles_c;
@@ -223,6 +226,7 @@ __global__ __launch_bounds__(256) void k_gp(LatDev lt, Bufs bf, int C, int tiles
   bid /= ntiles;
   const int sp = (int)(bid % 2);
   const long long wl = bid / 2;
+  if (only_due && bf.nacc[lt.w0 + wl] < refresh_every) return;
   const int n = lt.n[sp];
   if (n == 0) return;
   const int R0 = (tile / tiles_c) * 64, C0 = (tile % tiles_c) * 64;
@@ -314,30 +318,33 @@ hipError_t launch_forward(int prec, const LatDev& lt, const Bufs& bf, const Mode
 }
 
 
-hipError_t launch_rows(int prec, const LatDev& lt, const Bufs& bf, int L, int C, hipStream_t st) {
+hipError_t launch_rows(int prec, const LatDev& lt, const Bufs& bf, int L, int C, hipStream_t st, int only_due,
+                       int refresh_every) {
   if (lt.nw == 0) return hipSuccess;
   const dim3 grid((unsigned)((lt.N * lt.nmax + 255) / 256), 2, (unsigned)lt.nw);
-  if (prec == PREC_F64) hipLaunchKernelGGL(k_rows<double>, grid, dim3(256), 0, st, lt, bf, L, C);
-  else hipLaunchKernelGGL(k_rows<float>, grid, dim3(256), 0, st, lt, bf, L, C);
+  if (prec == PREC_F64)
+    hipLaunchKernelGGL(k_rows<double>, grid, dim3(256), 0, st, lt, bf, L, C, only_due, refresh_every);
+  else
+    hipLaunchKernelGGL(k_rows<float>, grid, dim3(256), 0, st, lt, bf, L, C, only_due, refresh_every);
   return hipGetLastError();
 }
 
-hipError_t launch_gj(const LatDev& lt, const Bufs& bf, hipStream_t st) {
+hipError_t launch_gj(const LatDev& lt, const Bufs& bf, hipStream_t st, int only_due, int refresh_every) {
   if (lt.nw == 0) return hipSuccess;
   const dim3 grid((unsigned)lt.nw, 2);
-  if (lt.nmax <= 16) hipLaunchKernelGGL((k_gj<1>), grid, dim3(256), 0, st, lt, bf);
-  else if (lt.nmax <= 32) hipLaunchKernelGGL((k_gj<2>), grid, dim3(256), 0, st, lt, bf);
-  else if (lt.nmax <= 64) hipLaunchKernelGGL((k_gj<4>), grid, dim3(256), 0, st, lt, bf);
-  else if (lt.nmax <= 128) hipLaunchKernelGGL((k_gj<8>), grid, dim3(256), 0, st, lt, bf);
+  if (lt.nmax <= 16) hipLaunchKernelGGL((k_gj<1>), grid, dim3(256), 0, st, lt, bf, only_due, refresh_every);
+  else if (lt.nmax <= 32) hipLaunchKernelGGL((k_gj<2>), grid, dim3(256), 0, st, lt, bf, only_due, refresh_every);
+  else if (lt.nmax <= 64) hipLaunchKernelGGL((k_gj<4>), grid, dim3(256), 0, st, lt, bf, only_due, refresh_every);
+  else if (lt.nmax <= 128) hipLaunchKernelGGL((k_gj<8>), grid, dim3(256), 0, st, lt, bf, only_due, refresh_every);
   else return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
-hipError_t launch_gp(const LatDev& lt, const Bufs& bf, int C, hipStream_t st) {
+hipError_t launch_gp(const LatDev& lt, const Bufs& bf, int C, hipStream_t st, int only_due, int refresh_every) {
   if (lt.nw == 0) return hipSuccess;
   const int tr = (lt.N + C + 63) / 64, tc = (lt.nmax + 63) / 64;
   const long long nblk = (long long)tr * tc * 2 * lt.nw;
-  hipLaunchKernelGGL(k_gp, dim3((unsigned)nblk), dim3(256), 0, st, lt, bf, C, tr, tc);
+  hipLaunchKernelGGL(k_gp, dim3((unsigned)nblk), dim3(256), 0, st, lt, bf, C, tr, tc, only_due, refresh_every);
   return hipGetLastError();
 }
 

@@ -17,9 +17,12 @@ namespace svmc {
 hipError_t launch_labels(const LatDev& lt, const Bufs& bf, hipStream_t st);
 hipError_t launch_forward(int prec, const LatDev& lt, const Bufs& bf, const ModelDev& md, void* h0tmp,
                           hipStream_t st);
-hipError_t launch_rows(int prec, const LatDev& lt, const Bufs& bf, int L, int C, hipStream_t st);
-hipError_t launch_gj(const LatDev& lt, const Bufs& bf, hipStream_t st);
-hipError_t launch_gp(const LatDev& lt, const Bufs& bf, int C, hipStream_t st);
+// only_due != 0: only walkers with nacc >= refresh_every (refresh after sweeps)
+hipError_t launch_rows(int prec, const LatDev& lt, const Bufs& bf, int L, int C, hipStream_t st,
+                       int only_due = 0, int refresh_every = 0);
+hipError_t launch_gj(const LatDev& lt, const Bufs& bf, hipStream_t st, int only_due = 0, int refresh_every = 0);
+hipError_t launch_gp(const LatDev& lt, const Bufs& bf, int C, hipStream_t st, int only_due = 0,
+                     int refresh_every = 0);
 hipError_t launch_logpsi(const LatDev& lt, const Bufs& bf, double* sign, double* logabs, hipStream_t st);
 
 // eloc.hip: low-rank local energies over all walkers of all lattices in one launch
@@ -34,6 +37,20 @@ size_t eloc_lowrank_smem(const LatDev* lats_host, int nlats, int prec, int L, in
 hipError_t launch_eloc_lowrank(int prec, const ModelDev& md, const LatDev* lats_dev, const LatDev* lats_host,
                                int nlats, long long W, const Bufs& bf, const ElocOut& out, hipStream_t st);
 
+// sweep.hip: Metropolis sweeps with Woodbury updates
+struct SweepArgs {
+  unsigned long long seed, step0;
+  int n_sweeps, refresh_every;
+  int64_t* n_accept;     // [W] incremented by accepted moves (may be null)
+  int64_t* prog;         // [W] next proposal index of each walker
+  int* paused;           // number of walkers that stopped for a refresh
+};
+size_t sweep_smem(const LatDev* lats_host, int nlats, int prec, int L, int C);
+hipError_t launch_sweep(int prec, const ModelDev& md, const LatDev* lats_dev, const LatDev* lats_host, int nlats,
+                        long long W, const Bufs& bf, const SweepArgs& sa, hipStream_t st);
+hipError_t launch_drift(const LatDev& lt, const Bufs& bf, int only_due, int refresh_every, hipStream_t st);
+hipError_t launch_clear_nacc(const LatDev& lt, const Bufs& bf, int refresh_every, hipStream_t st);
+
 // full.hip: full-recompute comparison path
 hipError_t launch_eloc_full(int prec, const ModelDev& md, const LatDev& lt, const Bufs& bf, const ElocOut& out,
                             double* ratio_tmp, int stride_tmp, hipStream_t st);
@@ -46,7 +63,9 @@ hipError_t launch_eloc_full(int prec, const ModelDev& md, const LatDev& lt, cons
   hipError_t eloc_full_##P_##_##C_(const ModelDev& md, const LatDev& lt, const Bufs& bf, const ElocOut& out, \
                                    double* ratio_tmp, int stride, hipStream_t st);                        \
   hipError_t forward_##P_##_##C_(const LatDev& lt, const Bufs& bf, const ModelDev& md, void* h0tmp,       \
-                                 hipStream_t st);
+                                 hipStream_t st);                                                         \
+  hipError_t sweep_##P_##_##C_(const ModelDev& md, const LatDev* lats_dev, int nlats, long long W,        \
+                               const Bufs& bf, const SweepArgs& sa, size_t smem, hipStream_t st);
 SVMC_FOR_EACH_PREC_C(SVMC_DECL_INST)
 #undef SVMC_DECL_INST
 
