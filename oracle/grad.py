@@ -1,5 +1,10 @@
-"""d log|psi(n)| / d theta by central finite differences of the full FP64
-amplitude (the quantity the optimiser of Sec. II.F consumes).
+"""d log|psi(n)| / d theta (the quantity the optimiser of Sec. II.F consumes),
+two independent routes:
+
+* fd_grad: central finite differences of the full FP64 amplitude;
+* autograd_grad: the amplitude of Sec. II.B written with torch CPU FP64
+  primitives (conv2d with boundary-following padding, slogdet), differentiated
+  by torch autograd.
 
 Flat parameter order (theta):
   embed [4, C] | conv_w [L, 3, 3, C, C] | conv_b [L, C] |
@@ -11,7 +16,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from .ansatz import log_psi
+from .ansatz import log_psi, occupied_sites
 
 
 def pack(params) -> np.ndarray:
@@ -58,3 +63,53 @@ def fd_grad(lat, params, occ, lat_index: int = 0, act: str = "tanh",
         lm = log_psi(lat, unpack(tm, params), occ, lat_index, act)[1]
         g[n] = (lp - lm) / (2.0 * h)
     return g
+
+
+def _torch_log_psi(lat, theta, like, occ, lat_index: int, act: str):
+    """log|psi| as a torch graph of the flat parameter vector theta."""
+    import torch
+    import torch.nn.functional as F
+    C, L = like.embed.shape[1], like.conv_w.shape[0]
+    off = 0
+
+    def take(shape):
+        nonlocal off
+        n = int(np.prod(shape))
+        a = theta[off:off + n].reshape(shape)
+        off += n
+        return a
+    E = take((4, C))
+    K = take((L, 3, 3, C, C))
+    b = take((L, C))
+    proj = []
+    for li in range(len(like.proj_w)):
+        nu, nd = like.proj_w[li][0].shape[1], like.proj_w[li][1].shape[1]
+        proj.append((take((C, nu)), take((C, nd)), take((nu,)), take((nd,))))
+    assert off == theta.numel()
+    x = E[torch.from_numpy(np.asarray(occ, dtype=np.int64))].T.reshape(1, C, lat.Ly, lat.Lx)
+    for l in range(L):
+        # circular padding on periodic axes, zeros on open ones
+        xp = F.pad(x, (1, 1, 0, 0), mode="circular") if lat.pbc_x else F.pad(x, (1, 1, 0, 0))
+        xp = F.pad(xp, (0, 0, 1, 1), mode="circular") if lat.pbc_y else F.pad(xp, (0, 0, 1, 1))
+        y = F.conv2d(xp, K[l].permute(3, 2, 0, 1), b[l])       # weights [cout, cin, ky, kx]
+        x = x + (torch.tanh(y) if act == "tanh" else F.silu(y))
+    HL = x.reshape(C, lat.N).T
+    Wu, Wd, bu, bd = proj[lat_index]
+    tot = theta.new_zeros(())
+    for s, (W, bb) in enumerate(((Wu, bu), (Wd, bd))):
+        idx = occupied_sites(occ, s)
+        if len(idx) == 0:
+            continue
+        rows = torch.from_numpy(like.base[lat_index][s]) + HL @ W + bb[None, :]
+        tot = tot + torch.linalg.slogdet(rows[torch.from_numpy(idx)])[1]
+    return tot
+
+
+def autograd_grad(lat, params, occ, lat_index: int = 0, act: str = "tanh"):
+    """(log|psi|, d log|psi| / d theta) in the flat layout of pack(), by torch
+    autograd in FP64 on the CPU; other lattices' projection entries are 0."""
+    import torch
+    theta = torch.from_numpy(pack(params)).requires_grad_(True)
+    lp = _torch_log_psi(lat, theta, params, occ, lat_index, act)
+    lp.backward()
+    return float(lp.item()), theta.grad.numpy().copy()

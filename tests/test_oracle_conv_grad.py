@@ -14,7 +14,7 @@ import torch.nn.functional as F
 
 import workloads as wl
 from oracle.ansatz import features, log_psi, occupied_sites
-from oracle.grad import fd_grad, pack
+from oracle.grad import autograd_grad, fd_grad
 
 
 def torch_features(lat, p, occ, act="tanh"):
@@ -48,36 +48,6 @@ def test_conv_stack_matches_torch(lat, act):
         assert np.max(np.abs(ours - ref)) < 1e-12
 
 
-def torch_log_psi(lat, theta, p, occ, act="tanh"):
-    C, L = p.embed.shape[1], p.conv_w.shape[0]
-    off = 0
-
-    def take(shape):
-        nonlocal off
-        n = int(np.prod(shape))
-        a = theta[off:off + n].reshape(shape)
-        off += n
-        return a
-    E = take((4, C))
-    W = take((L, 3, 3, C, C))
-    b = take((L, C))
-    pw = [take((C, lat.n_up)), take((C, lat.n_dn))]
-    pb = [take((lat.n_up,)), take((lat.n_dn,))]
-    x = E[torch.from_numpy(np.asarray(occ, dtype=np.int64))].T.reshape(1, C, lat.Ly, lat.Lx)
-    for l in range(L):
-        xp = F.pad(x, (1, 1, 0, 0), mode="circular") if lat.pbc_x else F.pad(x, (1, 1, 0, 0))
-        xp = F.pad(xp, (0, 0, 1, 1), mode="circular") if lat.pbc_y else F.pad(xp, (0, 0, 1, 1))
-        y = F.conv2d(xp, W[l].permute(3, 2, 0, 1), b[l])
-        x = x + (torch.tanh(y) if act == "tanh" else F.silu(y))
-    HL = x.reshape(C, lat.N).T
-    tot = 0.0
-    for s in (0, 1):
-        rows = torch.from_numpy(p.base[0][s]) + HL @ pw[s] + pb[s][None, :]
-        idx = torch.from_numpy(occupied_sites(occ, s))
-        tot = tot + torch.linalg.slogdet(rows[idx])[1]
-    return tot
-
-
 @pytest.mark.parametrize("lat", [
     wl.Lattice(4, 4, 1, 1, n_up=5, n_dn=5),
     wl.Lattice(4, 3, 1, 0, n_up=3, n_dn=2),
@@ -85,15 +55,32 @@ def torch_log_psi(lat, theta, p, occ, act="tanh"):
 def test_fd_gradient_matches_autograd(lat):
     p = wl.random_params([lat], wl.Model(2, 4), seed=12, backflow=0.8)
     occ = wl.random_occupations(lat, 1, seed=3)[0]
-    theta = torch.from_numpy(pack(p)).requires_grad_(True)
-    lp = torch_log_psi(lat, theta, p, occ)
-    assert lp.item() == pytest.approx(log_psi(lat, p, occ)[1], abs=1e-12)
-    lp.backward()
-    g_ref = theta.grad.numpy()
+    lp, g_ref = autograd_grad(lat, p, occ)
+    assert lp == pytest.approx(log_psi(lat, p, occ)[1], abs=1e-12)
     rng = np.random.default_rng(1)
-    idx = np.sort(rng.choice(theta.numel(), 60, replace=False))
+    idx = np.sort(rng.choice(g_ref.size, 60, replace=False))
     g_fd = fd_grad(lat, p, occ, indices=idx)
     assert np.max(np.abs(g_fd - g_ref[idx])) < 2e-7 * (1 + np.max(np.abs(g_ref)))
+
+
+@pytest.mark.parametrize("act", ["tanh", "silu"])
+def test_autograd_gradient_mixed_lattices(act):
+    """Second lattice of a mixed set: its own projection block carries the
+    gradient (FD-checked on every projection entry and on sampled conv
+    entries), the first lattice's block is exactly zero."""
+    lats = [wl.Lattice(4, 4, 1, 1, n_up=3, n_dn=2), wl.Lattice(3, 5, 0, 1, n_up=2, n_dn=3)]
+    p = wl.random_params(lats, wl.Model(2, 4), seed=5, backflow=0.8)
+    occ = wl.random_occupations(lats[1], 1, seed=8)[0]
+    lp, g = autograd_grad(lats[1], p, occ, lat_index=1, act=act)
+    assert lp == pytest.approx(log_psi(lats[1], p, occ, 1, act)[1], abs=1e-12)
+    C, L = 4, 2
+    o1 = 4 * C + 9 * L * C * C + L * C
+    o2 = o1 + C * (3 + 2) + 3 + 2
+    assert not g[o1:o2].any()
+    rng = np.random.default_rng(2)
+    idx = np.concatenate([np.arange(o2, g.size), np.sort(rng.choice(o1, 30, replace=False))])
+    g_fd = fd_grad(lats[1], p, occ, lat_index=1, act=act, indices=idx)
+    assert np.max(np.abs(g_fd - g[idx])) < 2e-7 * (1 + np.max(np.abs(g)))
 
 
 def test_conv_input_rounding_matches_torch_bf16_inputs():
