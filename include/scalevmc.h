@@ -199,12 +199,20 @@ svmc_status svmc_get_state(svmc_ctx* ctx, int8_t* occ, int16_t* pos,
                            hipStream_t stream);
 int32_t svmc_max_electrons(const svmc_ctx* ctx);
 
-/* d log|psi_w| / d theta (theta layout of svmc_num_params), FP64.
- * vjp_w == NULL: out is device [W][n_params], one row per walker.
+/* d log|psi_w| / d theta (theta layout of svmc_num_params), FP64, for the
+ * network of Sec. II.B whose parameters Sec. II.F optimises.
+ * vjp_w == NULL: out is device [W][n_params], one row per walker (entries of
+ * other lattices' projection blocks are 0).
  * vjp_w != NULL (device [W]): out is device [n_params] = sum_w vjp_w[w] *
- * d log|psi_w|/d theta.  Uses the determinant derivative
- * d log|det Phi| = tr(Phi^-1 dPhi) and back-propagation through the
- * projection and conv stack. */
+ * d log|psi_w|/d theta, summed in walker order (deterministic).
+ * Uses d log|det Phi| = tr(Phi^-1 dPhi) for the projection, dH_L = P = W Phi^-1
+ * at the occupied sites, and back-propagation through the residual conv stack
+ * (pre-activations recomputed from the cached features) to the embedding.
+ * Conv weights enter at the values the forward uses; with BF16 conv inputs the
+ * activation rounding is not differentiated.  Inverses are rebuilt first if
+ * Metropolis moves made them stale.  Walkers flagged SINGULAR, NONFINITE or
+ * BADCOUNT get a NaN row and are left out of the VJP sum.  Scratch: up to
+ * 4096 walkers x (N C) doubles, plus 1024 x n_params doubles for the VJP. */
 svmc_status svmc_grad_logpsi(svmc_ctx* ctx, const double* vjp_w, double* out,
                              hipStream_t stream);
 

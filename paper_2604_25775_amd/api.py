@@ -170,9 +170,41 @@ class ScaleVMC:
         self._check(self.lib.svmc_walker_flags(self.h, _ptr(f), _stream()), "walker_flags")
         return f
 
+    def update_params(self, theta: torch.Tensor):
+        """Upload a new flat parameter vector (same base orbitals) and rebuild
+        the walkers' caches at their current configurations."""
+        occ = None
+        if getattr(self, "_counts", None):
+            occ, _ = self.state()
+        self.set_params(theta.detach().to(self.device, torch.float64), self._base)
+        if occ is not None:
+            self.load_walkers(self._counts, occ)
+
     # convenience: remember counts for state()
     def load(self, counts: Sequence[int], occ):
         self._counts = list(counts)
         if isinstance(occ, np.ndarray):
             occ = torch.from_numpy(np.ascontiguousarray(occ).reshape(-1))
         self.load_walkers(counts, occ)
+
+
+class LogPsi(torch.autograd.Function):
+    """log|psi| [W] of the walkers held by a ScaleVMC as a differentiable
+    function of the flat parameter vector theta (layout of pack_params).
+    Forward uploads theta and rebuilds the caches at the walkers' current
+    configurations; backward asks the library for sum_w g[w] d log|psi_w| /
+    d theta (svmc_grad_logpsi with VJP weights g).
+
+        la = LogPsi.apply(theta, vmc)
+    """
+
+    @staticmethod
+    def forward(ctx, theta, vmc):
+        vmc.update_params(theta)
+        _, la = vmc.log_psi()
+        ctx.vmc = vmc
+        return la
+
+    @staticmethod
+    def backward(ctx, g):
+        return ctx.vmc.grad_logpsi(g.contiguous()).to(g.dtype), None

@@ -73,6 +73,8 @@ struct svmc_ctx {
   DevBuf occ, lab, pos, feat, inv, M, G, PT, ldet, sgn, flags, nacc;
   DevBuf ratio_tmp;
   DevBuf sw_prog, sw_paused;         // sweep progress per walker, paused-walker counter
+  DevBuf gK, gB, gE;                 // conv weights, conv bias, embedding (FP64, forward's rounding)
+  DevBuf g_rows, g_dH, g_hs, g_dzs;  // gradient scratch
   std::vector<int64_t> counts;
 
   svmc_status fail(svmc_status s, const std::string& m) {
@@ -257,6 +259,17 @@ svmc_status svmc_set_params(svmc_ctx* ctx, const double* theta, const double* co
             else if (P == PREC_F32) ((float*)bp.data())[idx] = (float)v;
             else ((uint16_t*)bp.data())[idx] = f32_to_bf16_rne((float)v);
           }
+  // FP64 copies of what the forward uses, for the backward
+  std::vector<double> gk(9ULL * L * C * C), gbias((size_t)L * C), ge(4ULL * C);
+  for (size_t k = 0; k < gk.size(); ++k) gk[k] = rnd(K[k]);
+  for (size_t k = 0; k < gbias.size(); ++k) gbias[k] = rnd(Bc[k]);
+  for (size_t k = 0; k < ge.size(); ++k) ge[k] = rnd(E[k]);
+  if ((s = ctx->hip(ctx->gK.ensure(gk.size() * 8), "alloc")) || (s = ctx->hip(ctx->gB.ensure(gbias.size() * 8), "alloc")) ||
+      (s = ctx->hip(ctx->gE.ensure(ge.size() * 8), "alloc")) ||
+      (s = ctx->hip(hipMemcpy(ctx->gK.p, gk.data(), gk.size() * 8, hipMemcpyHostToDevice), "upload")) ||
+      (s = ctx->hip(hipMemcpy(ctx->gB.p, gbias.data(), gbias.size() * 8, hipMemcpyHostToDevice), "upload")) ||
+      (s = ctx->hip(hipMemcpy(ctx->gE.p, ge.data(), ge.size() * 8, hipMemcpyHostToDevice), "upload")))
+    return s;
   if ((s = ctx->hip(ctx->Bpack.ensure(bp.size()), "alloc")) || (s = ctx->hip(ctx->embed.ensure(eb.size()), "alloc")) ||
       (s = ctx->hip(ctx->bias.ensure(bb.size()), "alloc")))
     return s;
@@ -345,6 +358,7 @@ svmc_status svmc_load_walkers(svmc_ctx* ctx, const int64_t* counts, const int8_t
   const int L = ctx->L, C = ctx->C, tfb = ctx->tf_bytes();
   std::vector<LatDev> d(nl);
   long long w0 = 0, o_occ = 0, o_lab = 0, o_pos = 0, o_feat = 0, o_inv = 0, o_m = 0, o_pt = 0;
+  long long poff = 4LL * C + 9LL * L * C * C + (long long)L * C;
   size_t h0max = 0;
   for (size_t l = 0; l < nl; ++l) {
     const svmc_lattice& s = ctx->lats[l];
@@ -367,6 +381,8 @@ svmc_status svmc_load_walkers(svmc_ctx* ctx, const int64_t* counts, const int8_t
     x.base = ctx->base[l].as<double>();
     x.W = ctx->W[l].as<double>();
     x.b = ctx->b[l].as<double>();
+    x.poff = poff;
+    poff += (long long)C * (s.n_up + s.n_dn) + s.n_up + s.n_dn;
     const long long nw = counts[l], N = x.N, nm = x.nmax;
     w0 += nw;
     o_occ += nw * N;
@@ -554,8 +570,52 @@ svmc_status svmc_get_state(svmc_ctx* ctx, int8_t* occ, int16_t* pos, hipStream_t
 
 svmc_status svmc_grad_logpsi(svmc_ctx* ctx, const double* vjp_w, double* out, hipStream_t st) {
   if (!ctx) return SVMC_ERR_INVALID_ARG;
-  (void)vjp_w; (void)out; (void)st;
-  return ctx->fail(SVMC_ERR_UNSUPPORTED, "gradient not built yet");
+  if (!ctx->have_walkers) return ctx->fail(SVMC_ERR_STATE, "no walkers loaded");
+  if (!out) return ctx->fail(SVMC_ERR_INVALID_ARG, "out is null");
+  svmc_status s;
+  // fresh inverses (rows, Phi^-1) and P = W Phi^-1 of the current walkers
+  if (!ctx->dets_fresh && (s = rebuild_dets(ctx, st))) return s;
+  if (!ctx->prepared && (s = prepare(ctx, st))) return s;
+  long long ncmax = 0;
+  for (auto& lt : ctx->ld) ncmax = std::max(ncmax, (long long)lt.N * ctx->C);
+  const long long W = ctx->Wtot, np = ctx->nparams;
+  const bool jac = vjp_w == nullptr;
+  // walkers per launch: bounded scratch (rows only in the VJP mode)
+  long long chunk = std::min<long long>(W, jac ? 4096 : 1024);
+  const size_t smem = grad_smem(ncmax);
+  GradArgs ga;
+  ga.L = ctx->L;
+  ga.C = ctx->C;
+  ga.act = ctx->model.act;
+  ga.lds = smem > 0 ? 1 : 0;
+  ga.K = ctx->gK.as<double>();
+  ga.B = ctx->gB.as<double>();
+  ga.E = ctx->gE.as<double>();
+  ga.nparams = np;
+  ga.off_convw = 4LL * ctx->C;
+  ga.off_convb = ga.off_convw + 9LL * ctx->L * ctx->C * ctx->C;
+  ga.ncmax = ncmax;
+  if ((s = ctx->hip(ctx->g_dH.ensure((size_t)chunk * ncmax * 8), "alloc gradient scratch"))) return s;
+  if (!ga.lds && ((s = ctx->hip(ctx->g_hs.ensure((size_t)chunk * ncmax * 8), "alloc gradient scratch")) ||
+                  (s = ctx->hip(ctx->g_dzs.ensure((size_t)chunk * ncmax * 8), "alloc gradient scratch"))))
+    return s;
+  if (!jac && (s = ctx->hip(ctx->g_rows.ensure((size_t)chunk * np * 8), "alloc gradient rows"))) return s;
+  ga.dH = ctx->g_dH.as<double>();
+  ga.hs = ga.lds ? nullptr : ctx->g_hs.as<double>();
+  ga.dzs = ga.lds ? nullptr : ctx->g_dzs.as<double>();
+  const Bufs bf = ctx->bufs();
+  for (long long b0 = 0; b0 < W; b0 += chunk) {
+    const long long cnt = std::min(chunk, W - b0);
+    ga.w_begin = b0;
+    ga.rows = jac ? out + b0 * np : ctx->g_rows.as<double>();
+    if ((s = ctx->hip(launch_grad(ctx->prec, ctx->lats_dev.as<LatDev>(), (int)ctx->ld.size(), cnt, bf, ga, st),
+                      "gradient")))
+      return s;
+    if (!jac && (s = ctx->hip(launch_grad_reduce(ga.rows, cnt, np, vjp_w + b0, bf.flags + b0, out, b0 == 0, st),
+                              "gradient reduction")))
+      return s;
+  }
+  return SVMC_OK;
 }
 
 svmc_status svmc_walker_flags(svmc_ctx* ctx, int32_t* flags, hipStream_t st) {

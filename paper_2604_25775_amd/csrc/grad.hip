@@ -1,0 +1,205 @@
+// Gradient of log|psi| with respect to the network parameters (the amplitude
+// of Sec. II.B; Sec. II.F optimises these parameters by gradients).
+//
+// Projection (per spin, Phi[k] = base[pos_k] + H_L[pos_k] W + b):
+//   d log|det Phi| = tr(Phi^-1 dPhi), so
+//     dW[c][m] = sum_k H_L[pos_k][c] Phi^-1[m][k],   db[m] = sum_k Phi^-1[m][k],
+//     dH_L[pos_k] += (W Phi^-1)[:, k] = P[:, k]      (P is the low-rank precompute).
+// Conv stack, l = L .. 1, with H_l = H_{l-1} + act(z_l), z_l = conv_l(H_{l-1}) + b_l:
+//     dz = dH_l * act'(z_l)                 (z_l recomputed from the cached H_{l-1})
+//     dK_l[t][ci][co] = sum_s dz[s][co] H_{l-1}[s + off_t][ci],   db_l = sum_s dz[s]
+//     dH_{l-1}[s] = dH_l[s] + sum_t K_l[t] dz[s - off_t]          (transposed conv)
+// Embedding: dE[o] = sum over sites with occupation o of dH_0.
+//
+// All arithmetic in FP64 on the cached features (FP32 or FP64); the conv
+// weights are the values the forward uses (rounded to its precision).  With
+// BF16 conv inputs the rounding of the activations is not differentiated
+// (its derivative is zero almost everywhere); the gradient is the one of the
+// unrounded network at the same weights.
+//
+// One workgroup per walker: H_{l-1} and dz of the walker live in LDS when
+// 2 N C doubles fit, else in a global scratch; dH is a global scratch.
+#include "svmc_launch.h"
+
+namespace svmc {
+
+SVMC_DEV int grad_nbr(const LatDev& lt, int s, int dx, int dy) {
+  int x = s % lt.Lx + dx, y = s / lt.Lx + dy;
+  if (lt.pbc_x) x = imod(x, lt.Lx); else if (x < 0 || x >= lt.Lx) return -1;
+  if (lt.pbc_y) y = imod(y, lt.Ly); else if (y < 0 || y >= lt.Ly) return -1;
+  return x + lt.Lx * y;
+}
+
+SVMC_DEV double act_deriv(int act, double z) {
+  if (act == ACT_TANH) {
+    const double t = tanh(z);
+    return 1.0 - t * t;
+  }
+  const double sg = 1.0 / (1.0 + exp(-z));
+  return sg * (1.0 + z * (1.0 - sg));
+}
+
+template <class Tf>
+__global__ __launch_bounds__(256) void k_grad(const LatDev* __restrict__ lats, int nlats, Bufs bf, GradArgs ga) {
+  constexpr int NTH = 256;
+  const long long w = ga.w_begin + blockIdx.x;
+  int li = 0;
+  while (li + 1 < nlats && w >= lats[li + 1].w0) ++li;
+  const LatDev lt = lats[li];
+  const long long wl = w - lt.w0;
+  const int N = lt.N, nm = lt.nmax, C = ga.C, L = ga.L, NC = N * C;
+  const int tid = threadIdx.x;
+  double* row = ga.rows + (long long)blockIdx.x * ga.nparams;
+  extern __shared__ __attribute__((aligned(16))) double glds[];
+  double* hp = ga.lds ? glds : ga.hs + (long long)blockIdx.x * ga.ncmax;
+  double* dz = ga.lds ? glds + NC : ga.dzs + (long long)blockIdx.x * ga.ncmax;
+  double* dH = ga.dH + (long long)blockIdx.x * ga.ncmax;
+  const bool bad = (bf.flags[w] & (1 | 2 | 8)) != 0;
+  for (long long p = tid; p < ga.nparams; p += NTH) row[p] = bad ? NAN : 0.0;
+  if (bad) return;
+  const int8_t* occ = bf.occ + lt.occ_off + wl * N;
+  const int16_t* lab = bf.lab + lt.lab_off + wl * 2LL * N;
+  const int16_t* pos = bf.pos + lt.pos_off + wl * 2LL * nm;
+  const Tf* feat = (const Tf*)bf.feat + lt.feat_off + wl * (long long)L * NC;
+  const Tf* HL = feat + (long long)(L - 1) * NC;
+  const double* PTw = bf.PT + lt.pt_off + wl * 2LL * nm * C;
+  const int n0 = lt.n[0], n1 = lt.n[1];
+  __syncthreads();
+
+  // ---- projection and dH_L
+  for (int sp = 0; sp < 2; ++sp) {
+    const int n = lt.n[sp];
+    const double* Y = bf.inv + lt.inv_off + wl * 2LL * nm * nm + (long long)sp * nm * nm;
+    const int16_t* ps = pos + sp * nm;
+    double* dW = row + lt.poff + (sp ? (long long)C * n0 : 0LL);
+    double* db = row + lt.poff + (long long)C * (n0 + n1) + (sp ? n0 : 0);
+    for (int e = tid; e < C * n; e += NTH) {
+      const int c = e / n, m = e % n;
+      const double* Ym = Y + (long long)m * nm;
+      double acc = 0.0;
+      for (int k = 0; k < n; ++k) acc = fma((double)HL[(long long)ps[k] * C + c], Ym[k], acc);
+      dW[e] = acc;
+    }
+    for (int m = tid; m < n; m += NTH) {
+      const double* Ym = Y + (long long)m * nm;
+      double acc = 0.0;
+      for (int k = 0; k < n; ++k) acc += Ym[k];
+      db[m] = acc;
+    }
+  }
+  for (int e = tid; e < NC; e += NTH) {
+    const int s = e / C, c = e % C;
+    double v = 0.0;
+    for (int sp = 0; sp < 2; ++sp) {
+      const int k = lab[sp * N + s];
+      if (k >= 0) v += PTw[((long long)sp * nm + k) * C + c];
+    }
+    dH[e] = v;
+  }
+  __syncthreads();
+
+  // ---- conv stack, last layer first
+  for (int l = L; l >= 1; --l) {
+    const double* Kl = ga.K + (long long)(l - 1) * 9 * C * C;
+    const double* bl = ga.B + (long long)(l - 1) * C;
+    for (int e = tid; e < NC; e += NTH)
+      hp[e] = l >= 2 ? (double)feat[(long long)(l - 2) * NC + e] : ga.E[occ[e / C] * C + e % C];
+    __syncthreads();
+    for (int e = tid; e < NC; e += NTH) {
+      const int s = e / C, co = e % C;
+      double z = bl[co];
+      for (int t = 0; t < 9; ++t) {
+        const int nb = grad_nbr(lt, s, t % 3 - 1, t / 3 - 1);
+        if (nb < 0) continue;
+        const double* kt = Kl + (long long)t * C * C + co;
+        const double* h = hp + nb * C;
+        for (int ci = 0; ci < C; ++ci) z = fma(kt[ci * C], h[ci], z);
+      }
+      dz[e] = dH[e] * act_deriv(ga.act, z);
+    }
+    __syncthreads();
+    double* dK = row + ga.off_convw + (long long)(l - 1) * 9 * C * C;
+    for (int e = tid; e < 9 * C * C; e += NTH) {
+      const int t = e / (C * C), ci = (e / C) % C, co = e % C;
+      const int dx = t % 3 - 1, dy = t / 3 - 1;
+      double acc = 0.0;
+      for (int s = 0; s < N; ++s) {
+        const int nb = grad_nbr(lt, s, dx, dy);
+        if (nb >= 0) acc = fma(dz[s * C + co], hp[nb * C + ci], acc);
+      }
+      dK[e] = acc;
+    }
+    for (int co = tid; co < C; co += NTH) {
+      double acc = 0.0;
+      for (int s = 0; s < N; ++s) acc += dz[s * C + co];
+      row[ga.off_convb + (long long)(l - 1) * C + co] = acc;
+    }
+    for (int e = tid; e < NC; e += NTH) {
+      const int s = e / C, ci = e % C;
+      double acc = dH[e];
+      for (int t = 0; t < 9; ++t) {
+        const int src = grad_nbr(lt, s, 1 - t % 3, 1 - t / 3);
+        if (src < 0) continue;
+        const double* kt = Kl + (long long)t * C * C + ci * C;
+        const double* d = dz + src * C;
+        for (int co = 0; co < C; ++co) acc = fma(kt[co], d[co], acc);
+      }
+      dH[e] = acc;
+    }
+    __syncthreads();
+  }
+
+  // ---- embedding
+  for (int e = tid; e < 4 * C; e += NTH) {
+    const int o = e / C, c = e % C;
+    double acc = 0.0;
+    for (int s = 0; s < N; ++s)
+      if (occ[s] == o) acc += dH[s * C + c];
+    row[e] = acc;
+  }
+}
+
+// out[p] (+)= sum_w vjp[w] rows[w][p] over the walkers of one chunk, walker
+// order fixed; flagged walkers are skipped.
+__global__ void k_grad_reduce(const double* __restrict__ rows, long long cnt, long long nparams,
+                              const double* __restrict__ vjp, const int32_t* __restrict__ flags, double* out,
+                              int first) {
+  const long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (p >= nparams) return;
+  double acc = first ? 0.0 : out[p];
+  for (long long w = 0; w < cnt; ++w)
+    if (!(flags[w] & (1 | 2 | 8))) acc = fma(vjp[w], rows[w * nparams + p], acc);
+  out[p] = acc;
+}
+
+size_t grad_smem(long long ncmax) {
+  const size_t b = (size_t)ncmax * 2 * sizeof(double);
+  return b <= 160 * 1024 ? b : 0;
+}
+
+hipError_t launch_grad(int prec, const LatDev* lats_dev, int nlats, long long cnt, const Bufs& bf,
+                       const GradArgs& ga, hipStream_t st) {
+  if (cnt == 0) return hipSuccess;
+  const size_t smem = ga.lds ? grad_smem(ga.ncmax) : 0;
+  if (prec == PREC_F64) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_grad<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)smem);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_grad<double>, dim3((unsigned)cnt), dim3(256), smem, st, lats_dev, nlats, bf, ga);
+  } else {
+    hipError_t e = hipFuncSetAttribute((const void*)k_grad<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)smem);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_grad<float>, dim3((unsigned)cnt), dim3(256), smem, st, lats_dev, nlats, bf, ga);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_grad_reduce(const double* rows, long long cnt, long long nparams, const double* vjp,
+                              const int32_t* flags, double* out, int first, hipStream_t st) {
+  const unsigned nb = (unsigned)((nparams + 255) / 256);
+  hipLaunchKernelGGL(k_grad_reduce, dim3(nb), dim3(256), 0, st, rows, cnt, nparams, vjp, flags, out, first);
+  return hipGetLastError();
+}
+
+}  // namespace svmc

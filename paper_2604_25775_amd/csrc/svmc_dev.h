@@ -45,6 +45,7 @@ struct LatDev {
   const double* base;  // [2][N][nmax]
   const double* W;     // [2][C][nmax]
   const double* b;     // [2][nmax]
+  long long poff;      // offset of this lattice's W_up in the flat parameter vector
 };
 
 // Device buffers of one context (walker-indexed arrays, see LatDev offsets).

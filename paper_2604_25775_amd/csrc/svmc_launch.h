@@ -51,6 +51,26 @@ hipError_t launch_sweep(int prec, const ModelDev& md, const LatDev* lats_dev, co
 hipError_t launch_drift(const LatDev& lt, const Bufs& bf, int only_due, int refresh_every, hipStream_t st);
 hipError_t launch_clear_nacc(const LatDev& lt, const Bufs& bf, int refresh_every, hipStream_t st);
 
+// grad.hip: d log|psi| / d theta, one row per walker
+struct GradArgs {
+  int L, C, act, lds;     // lds: H_{l-1} and dz of a walker in LDS (else hs / dzs)
+  const double* K;        // [L][9][C][C] conv weights as the forward uses them
+  const double* B;        // [L][C]
+  const double* E;        // [4][C]
+  long long nparams, off_convw, off_convb;
+  long long w_begin;      // first walker of the launch
+  long long ncmax;        // per-walker scratch stride (max N * C)
+  double* rows;           // [cnt][nparams]
+  double* dH;             // [cnt][ncmax]
+  double* hs;             // [cnt][ncmax] when !lds
+  double* dzs;            // [cnt][ncmax] when !lds
+};
+size_t grad_smem(long long ncmax);   // 0 when H_{l-1} and dz do not fit in LDS
+hipError_t launch_grad(int prec, const LatDev* lats_dev, int nlats, long long cnt, const Bufs& bf,
+                       const GradArgs& ga, hipStream_t st);
+hipError_t launch_grad_reduce(const double* rows, long long cnt, long long nparams, const double* vjp,
+                              const int32_t* flags, double* out, int first, hipStream_t st);
+
 // full.hip: full-recompute comparison path
 hipError_t launch_eloc_full(int prec, const ModelDev& md, const LatDev& lt, const Bufs& bf, const ElocOut& out,
                             double* ratio_tmp, int stride_tmp, hipStream_t st);
