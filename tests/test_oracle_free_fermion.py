@@ -47,19 +47,24 @@ def no_backflow(lat, C=4, L=2, seed=3):
     return p
 
 
-# Values derived by hand from the closed form above (they are also recomputed
-# by closed_form_e0 in the test):
-#  4x4 PBC, 5 per spin: -4 + 4*(-2) = -12 per spin            -> -24
-#  2x4 open-x/periodic-y, 4 per spin: -3 + 3*(-1) = -6         -> -12
-#  4x4 PBC t'=-0.2, 5 per spin: -3.2 + 4*(-2) = -11.2          -> -22.4
-#  2x4 open-x/periodic-y t'=0.3, 3 per spin: -3.6 + 2*(-1) + .. -> -11.2
-CASES = [
-    (wl.Lattice(4, 4, 1, 1, 1.0, 0.0, 0.0, 5, 5), -24.0),
-    (wl.Lattice(2, 4, 0, 1, 1.0, 0.0, 0.0, 4, 4), -12.0),
-    (wl.Lattice(4, 4, 1, 1, 1.0, -0.2, 0.0, 5, 5), -22.4),
-    (wl.Lattice(2, 4, 0, 1, 1.0, 0.3, 0.0, 3, 3), -11.2),
-    (wl.Lattice(6, 6, 1, 1, 1.0, 0.0, 0.0, 13, 13), -56.0),
-]
+def golden_cases():
+    """Closed-form values of tests/golden/free_fermion_e0.txt."""
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "free_fermion_e0.txt")
+    out = []
+    for line in open(path):
+        line = line.split("#", 1)[0].split()
+        if not line:
+            continue
+        Lx, Ly, px, py = (int(v) for v in line[:4])
+        t, tp = float(line[4]), float(line[5])
+        nu, nd = int(line[6]), int(line[7])
+        out.append((wl.Lattice(Lx, Ly, px, py, t, tp, 0.0, nu, nd), float(line[8])))
+    return out
+
+
+GOLDEN = golden_cases()
+CASES = [c for c in GOLDEN if c[0].N <= 64]
 
 
 @pytest.mark.parametrize("lat,e0", CASES)
@@ -76,9 +81,9 @@ def test_zero_variance_small(lat, e0):
 def test_zero_variance_16x16_open_y():
     """The headline lattice: 16x16 periodic-x / open-y, 112 per spin; the
     shell is closed (gap 9.1e-3), E0 = -405.312933627526."""
-    lat = wl.Lattice(16, 16, 1, 0, 1.0, 0.0, 0.0, 112, 112)
+    lat, e_gold = [c for c in GOLDEN if c[0].N == 256][0]
     e0 = closed_form_e0(lat)
-    assert e0 == pytest.approx(-405.312933627526, abs=1e-9)
+    assert e0 == pytest.approx(e_gold, abs=1e-9)
     p = no_backflow(lat, C=4, L=1)
     occ = nonzero_configs(lat, p, wl.random_occupations(lat, 2, seed=11))
     assert len(occ) == 2
