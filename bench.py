@@ -5,13 +5,16 @@ Workload (default): Hubbard 16x16, periodic-x / open-y, t = 1, U = 8,
 112 + 112 electrons (1/8 hole doping), 4 residual 3x3 conv layers x 32
 channels, 8192 walkers, seeded synthetic parameters and occupations.
 
-One step = the whole low-rank hot path over the batch: per-walker precompute
-(orbital rows, G = M Phi^-1, P = W Phi^-1) + the low-rank local-energy
-kernel (hop enumeration, incremental conv on the matrix units, FP64
-determinant-lemma ratios, reduction).  Inputs are resident in HBM before
-the timed region.  Also measured: the full-recompute path on the same
-walkers (speed-up), the oracle on host cores (cpu_baseline), and the
-roofline position of the dominant kernel from HIP events on its stream.
+Before timing, --therm Metropolis sweeps (default 8) move the walkers from
+the random start and leave the caches (features, G, P) as sampling does.
+One timed step = one local-energy evaluation of the whole batch: per-walker
+precompute (orbital rows, G = M Phi^-1, P = W Phi^-1) + the low-rank
+local-energy kernel (hop enumeration, incremental conv on the matrix units,
+FP64 determinant-lemma ratios, reduction).  Inputs are resident in HBM
+before the timed region.  Also measured: the time per sweep, one gradient
+VJP of log|psi| over the batch, the full-recompute path on the same walkers
+(speed-up), the oracle on host cores (cpu_baseline), and the roofline
+position of the dominant kernel from HIP events on its stream.
 
     python bench.py [--gpus 1] [--steps 10] [--warmup 2] [--prec bf16x3]
 """
@@ -173,9 +176,11 @@ def main():
     ap.add_argument("--walkers", type=int, default=None)
     ap.add_argument("--full-walkers", type=int, default=None,
                     help="walkers for the full-recompute timing (default: all)")
-    ap.add_argument("--cpu-sample", type=int, default=24)
+    ap.add_argument("--cpu-sample", type=int, default=192)
+    ap.add_argument("--therm", type=int, default=8, help="thermalising sweeps before timing (untimed)")
     ap.add_argument("--no-full", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-grad", action="store_true")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py measures one GPU only (asked for {a.gpus}); the walker-parallel "
@@ -199,6 +204,21 @@ def main():
     ctx.load([W], occ)
     torch.cuda.synchronize()
     eloc = torch.empty(W, dtype=torch.float64, device="cuda")
+    extra = {}
+    if a.therm > 0:
+        # Metropolis sweeps from the random start; E_loc is then measured on
+        # the caches the sweeps leave (features, G and P maintained in place)
+        t0 = time.perf_counter()
+        nacc = ctx.sweep(a.therm, wl.seed_mc, 0)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        rate = float(nacc.double().mean().item()) / (a.therm * lat.N)
+        extra.update({"therm_sweeps": a.therm, "therm_sweep_ms": round(dt * 1e3 / a.therm, 2),
+                      "accept_rate": round(rate, 4)})
+        log(f"[bench] {a.therm} sweeps: {dt * 1e3 / a.therm:.1f} ms per sweep of {W} walkers, "
+            f"accept rate {rate:.3f}")
+        occ_t, _ = ctx.state()
+        occ = occ_t.cpu().numpy().reshape(W, lat.N)
 
     for _ in range(a.warmup):
         ctx.prepare()
@@ -240,8 +260,22 @@ def main():
     log(f"[bench] roofline: conv {conv_f / 1e12:.3f} TFLOP + fp64 {det_f / 1e12:.3f} TFLOP per launch; "
         f"t_peak {t_peak * 1e3:.3f} ms vs {kern_ms:.3f} ms -> frac {achieved / peak:.4f}")
 
-    extra = {"prepare_ms": round(prep_ms, 4), "eloc_kernel_ms": round(kern_ms, 4),
-             "walkers_flagged": int(np.count_nonzero(flags))}
+    extra.update({"prepare_ms": round(prep_ms, 4), "eloc_kernel_ms": round(kern_ms, 4),
+                  "walkers_flagged": {"singular": int(np.count_nonzero(flags & 1)),
+                                      "nonfinite": int(np.count_nonzero(flags & 2)),
+                                      "drift": int(np.count_nonzero(flags & 4)),
+                                      "badcount": int(np.count_nonzero(flags & 8))}})
+    if not a.no_grad:
+        v = torch.ones(W, dtype=torch.float64, device="cuda")
+        ctx.grad_logpsi(v)
+        g0 = torch.cuda.Event(enable_timing=True)
+        g1 = torch.cuda.Event(enable_timing=True)
+        g0.record()
+        ctx.grad_logpsi(v)
+        g1.record()
+        torch.cuda.synchronize()
+        extra["grad_vjp_ms"] = round(g0.elapsed_time(g1), 3)
+        log(f"[bench] gradient VJP over {W} walkers: {extra['grad_vjp_ms']:.1f} ms")
     if not a.no_full:
         FW = a.full_walkers or W
         if FW == W:
