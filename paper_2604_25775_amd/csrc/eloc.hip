@@ -123,7 +123,7 @@ __global__ __launch_bounds__(64 * ELOC_NW) __attribute__((amdgpu_waves_per_eu(2)
   const int KM = lt.Gx * lt.Gy;
   const HopScratch hsc = hop_scratch(lt.Gx, lt.Gy, md.L, C, (int)sizeof(Tf));
   int* kl = (int*)(scratch + hsc.klists) + wv * KM;
-  double* stage = (double*)(scratch + (wv == 0 ? hsc.stage0 : hsc.stage1));
+  double* prow = (double*)(scratch + hsc.prow) + wv * 64;
   double* misc = (double*)(scratch + hsc.misc);
 
   double part = 0.0;
@@ -140,7 +140,7 @@ __global__ __launch_bounds__(64 * ELOC_NW) __attribute__((amdgpu_waves_per_eu(2)
       const int K = hop_klist(lt, g, occ_s, lab_s, wv, olx, owx, oly, owy, kl, hpos, lane);
       const double* PTt = PTw + (long long)wv * nm * C;
       const double* Gj = Gw + ((long long)wv * N + g.j) * nm;
-      const double Rt = hop_det<Tf, C>(kl, K, wv == sp, hpos, (const Tf*)scratch, PTt, Gj, stage, lane);
+      const double Rt = hop_det<Tf, C>(kl, K, wv == sp, hpos, (const Tf*)scratch, PTt, Gj, prow, lane);
       if (lane == 0) misc[wv] = Rt;
       __syncthreads();
       if (tid == 0) {

@@ -19,15 +19,33 @@ namespace svmc {
 SVMC_DEV int dir_dx(int d) { return (d == 0 || d == 4 || d == 5) ? 1 : ((d == 1 || d == 6 || d == 7) ? -1 : 0); }
 SVMC_DEV int dir_dy(int d) { return (d == 2 || d == 4 || d == 6) ? 1 : ((d == 3 || d == 5 || d == 7) ? -1 : 0); }
 
+// q / w for 0 <= q < 1087 and 1 <= w <= 64 as (q * m) >> 16 with
+// m = 65536 / w + 1 (checked exhaustively over that range).  Box widths are
+// at most 2L + 4 and box sizes at most (2L + 4)^2 sites.
+__constant__ const int kMagic16[65] = {
+    0,     65537, 32769, 21846, 16385, 13108, 10923, 9363, 8193, 7282, 6554, 5958, 5462, 5042, 4682, 4370, 4097,
+    3856,  3641,  3450,  3277,  3121,  2979,  2850,  2731, 2622, 2521, 2428, 2341, 2260, 2185, 2115, 2049,
+    1986,  1928,  1873,  1821,  1772,  1725,  1681,  1639, 1599, 1561, 1525, 1490, 1457, 1425, 1395, 1366,
+    1338,  1311,  1286,  1261,  1237,  1214,  1192,  1171, 1150, 1130, 1111, 1093, 1075, 1058, 1041, 1025};
+SVMC_DEV int fdiv16(int q, int m) { return (q * m) >> 16; }
+
 // One lattice axis as seen from a hop.  Coordinates u are "unwrapped"
-// (may leave [0, La) on periodic axes).  Window mode: grid index u - go.
-// Torus mode (periodic axis shorter than the largest box): grid index u mod La.
+// (may leave [0, La) on periodic axes, by at most L + 2).  Window mode: grid
+// index u - go.  Torus mode (periodic axis shorter than the largest box,
+// La < 2L + 4): grid index u mod La.
 struct Axis {
-  int La, per, torus, go;
+  int La, per, torus, go, m;    // m = kMagic16[La] (torus mode)
 };
-SVMC_DEV int gidx(const Axis& a, int u) { return a.torus ? imod(u, a.La) : u - a.go; }
+// u mod La: torus axes (La <= 2L + 3, u >= -8 La) by the magic division,
+// window-mode periodic axes (u in [-La, 2 La)) by one conditional step.
+SVMC_DEV int wrapt(const Axis& a, int u) {
+  const int v = u + 8 * a.La;
+  return v - a.La * fdiv16(v, a.m);
+}
+SVMC_DEV int wrapw(const Axis& a, int u) { return u < 0 ? u + a.La : (u >= a.La ? u - a.La : u); }
+SVMC_DEV int gidx(const Axis& a, int u) { return a.torus ? wrapt(a, u) : u - a.go; }
 SVMC_DEV bool inlat(const Axis& a, int u) { return a.per || (u >= 0 && u < a.La); }
-SVMC_DEV int latc(const Axis& a, int u) { return a.per ? imod(u, a.La) : u; }
+SVMC_DEV int latc(const Axis& a, int u) { return a.per ? (a.torus ? wrapt(a, u) : wrapw(a, u)) : u; }
 // Sites within distance l of {x_i, x_i + dx} along the axis, clipped at open
 // edges and capped at the axis length on periodic ones: [lo, lo + w).
 SVMC_DEV void box1(const Axis& a, int xi, int dx, int l, int& lo, int& w) {
@@ -38,7 +56,13 @@ SVMC_DEV void box1(const Axis& a, int xi, int dx, int l, int& lo, int& w) {
   lo = L0;
 }
 SVMC_DEV bool inbox(const Axis& a, int lo, int w, int u) {
-  return a.torus ? imod(u - lo, a.La) < w : (u >= lo && u < lo + w);
+  return a.torus ? wrapt(a, u - lo) < w : (u >= lo && u < lo + w);
+}
+// Box site q (x fastest) -> unwrapped coordinates; m = kMagic16[w].
+SVMC_DEV void box_site(int q, int lx, int w, int m, int ly, int& ux, int& uy) {
+  const int qy = fdiv16(q, m);
+  ux = lx + q - qy * w;
+  uy = ly + qy;
 }
 
 
@@ -56,8 +80,8 @@ SVMC_DEV HopGeom hop_geom(const LatDev& lt, int L, int sigma, int i, int d) {
   const int xj = lt.pbc_x ? imod(h.xi + h.dx, lt.Lx) : h.xi + h.dx;
   const int yj = lt.pbc_y ? imod(h.yi + h.dy, lt.Ly) : h.yi + h.dy;
   h.j = xj + lt.Lx * yj;
-  h.ax = Axis{lt.Lx, lt.pbc_x, lt.torus_x, h.xi + min(0, h.dx) - L - 1};
-  h.ay = Axis{lt.Ly, lt.pbc_y, lt.torus_y, h.yi + min(0, h.dy) - L - 1};
+  h.ax = Axis{lt.Lx, lt.pbc_x, lt.torus_x, h.xi + min(0, h.dx) - L - 1, kMagic16[lt.torus_x ? lt.Lx : 1]};
+  h.ay = Axis{lt.Ly, lt.pbc_y, lt.torus_y, h.yi + min(0, h.dy) - L - 1, kMagic16[lt.torus_y ? lt.Ly : 1]};
   return h;
 }
 
@@ -67,33 +91,23 @@ SVMC_DEV HopGeom hop_geom(const LatDev& lt, int L, int sigma, int i, int d) {
 template <class Tf, int C> struct SiteStride {
   static constexpr int value = C + 16 / (int)sizeof(Tf);
 };
-constexpr int KSP = 50;   // row stride (doubles) of the transposed P^T staging
 
 // LDS scratch of one hop, in bytes:
 //   grid   [Gy][Gx][SP] Tf  features of one layer on the update box; after the
 //                           last layer, D = H'_L - H_L densely as [m][SP]
-//   stage0 max(OUT box x C Tf, P^T staging)  layer outputs before they
-//                           replace the grid; later spin 0's staged P^T rows,
-//                           G values and LU pivot row
-//   stage1 P^T staging of spin 1
+//   prow   [2][64] f64      pivot-row broadcast of the two determinant waves
 //   klists [2][Gx Gy] int   changed-row lists per spin
 //   misc   64 bytes         per-spin results
-constexpr int KSTAGE = 48;
 struct HopScratch {
-  int stage0, stage1, klists, misc, bytes;
+  int prow, klists, misc, bytes;
 };
 __host__ __device__ inline int align16i(int x) { return (x + 15) & ~15; }
 __host__ __device__ inline HopScratch hop_scratch(int Gx, int Gy, int L, int C, int tfb) {
   HopScratch h;
   const int SP = C + 16 / tfb;
-  const int grid = align16i(Gx * Gy * SP * tfb);
-  const int ox = Gx < 2 * L + 2 ? Gx : 2 * L + 2, oy = Gy < 2 * L + 2 ? Gy : 2 * L + 2;
-  const int outb = ox * oy * SP * tfb;
-  const int pkc = (C * KSP > KSTAGE * C ? C * KSP : KSTAGE * C);
-  const int pkb = (pkc + KSTAGE + 64) * 8;
-  h.stage0 = grid;
-  h.stage1 = h.stage0 + align16i(outb > pkb ? outb : pkb);
-  h.klists = h.stage1 + align16i(pkb);
+  (void)L;
+  h.prow = align16i(Gx * Gy * SP * tfb);
+  h.klists = h.prow + 2 * 64 * 8;
   h.misc = h.klists + align16i(2 * Gx * Gy * 4);
   h.bytes = h.misc + 64;
   return h;
@@ -205,8 +219,10 @@ SVMC_DEV void hop_features(const ModelDev& md, const LatDev& lt, const HopGeom& 
   const int L = md.L, N = lt.N, Lx = lt.Lx, Gx = lt.Gx;
   const Axis ax = h.ax, ay = h.ay;
   Tf* grid = (Tf*)scratch;
-  Tf* obuf = (Tf*)(scratch + hs.stage0);
+  (void)hs;
   const int bit = 1 << h.sigma;
+  constexpr int V = 16 / sizeof(Tf);          // elements per 16-byte vector
+  constexpr int CV = C / V;
   // layer-1 input: embedding of the new configuration on the layer-1 input
   // box (layer-1 output box grown by one site)
   {
@@ -214,25 +230,27 @@ SVMC_DEV void hop_features(const ModelDev& md, const LatDev& lt, const HopGeom& 
     box1(ax, h.xi, h.dx, 2, lx, wx);
     box1(ay, h.yi, h.dy, 2, ly, wy);
     const Tf* E = (const Tf*)md.embed;
-    const int tot = wx * wy * C;
+    const int mw = kMagic16[wx];
+    const int tot = wx * wy * CV;
     for (int e = tid; e < tot; e += NT_) {
-      const int c = e % C, q = e / C;
-      const int ux = lx + q % wx, uy = ly + q / wx;
+      const int q = e / CV, cv = e - q * CV;
+      int ux, uy;
+      box_site(q, lx, wx, mw, ly, ux, uy);
       const int s = latc(ax, ux) + Lx * latc(ay, uy);
       int o = occ_s[s];
       if (s == h.i) o -= bit;
       if (s == h.j) o += bit;
-      grid[(gidx(ay, uy) * Gx + gidx(ax, ux)) * SP + c] = E[o * C + c];
+      *reinterpret_cast<float4*>(grid + (gidx(ay, uy) * Gx + gidx(ax, ux)) * SP + cv * V) =
+          *reinterpret_cast<const float4*>(E + o * C + cv * V);
     }
   }
   __syncthreads();
   constexpr int QB = RegB<P, C>::value ? CC::Q : 1;
-  constexpr int V = 16 / sizeof(Tf);          // elements per 16-byte vector
-  constexpr int CV = C / V;
   for (int l = 1; l <= L; ++l) {
     box1(ax, h.xi, h.dx, l, olx, owx);
     box1(ay, h.yi, h.dy, l, oly, owy);
     const int cnt = uniform_i(owx * owy);
+    const int mow = kMagic16[owx];
     const int T = (cnt + 15) >> 4;
     const Tb* Bl = (const Tb*)md.Bpack + (long long)(l - 1) * CC::Q * CC::NT * 64;
     Tb breg[QB][CC::NT];
@@ -245,11 +263,20 @@ SVMC_DEV void hop_features(const ModelDev& md, const LatDev& lt, const HopGeom& 
       }
     }
     const Tf* bias = (const Tf*)md.bias + (l - 1) * C;
-    for (int t = wave; t < T; t += NW) {
+    // Each wave keeps its tiles' new values in registers until every wave
+    // has finished reading the grid of this layer (at most 7 tiles: the
+    // layer-L box of L <= 4 has at most 10 x 10 sites).
+    constexpr int MAXT = (7 + NW - 1) / NW;
+    Tf outv[MAXT][CC::NT][4];
+#pragma unroll
+    for (int ti = 0; ti < MAXT; ++ti) {
+      const int t = wave + NW * ti;
+      if (t >= T) break;
       const int m = 16 * t + (lane & 15);
       unsigned px = 0xFFFFFFu, py = 0xFFFFFFu;
       if (m < cnt) {
-        const int ux = olx + m % owx, uy = oly + m / owx;
+        int ux, uy;
+        box_site(m, olx, owx, mow, oly, ux, uy);
         px = 0;
         py = 0;
 #pragma unroll
@@ -261,39 +288,68 @@ SVMC_DEV void hop_features(const ModelDev& md, const LatDev& lt, const HopGeom& 
       }
       Acc acc[CC::NT];
       conv_tile_grid<P, C>(grid, Gx, px, py, breg, Bl, lane, acc);
-      // epilogue: H'_l = H'_{l-1} + act(conv + b); residual read from the grid
+      // H'_l = H'_{l-1} + act(conv + b); the residual is this site's own grid value
 #pragma unroll
-      for (int nt = 0; nt < CC::NT; ++nt)
+      for (int v = 0; v < 4; ++v) {
+        const int r = 16 * t + OutMap<P>::row(lane, v);
+        int ux, uy;
+        box_site(r, olx, owx, mow, oly, ux, uy);
+        const int gofs = r < cnt ? (gidx(ay, uy) * Gx + gidx(ax, ux)) * SP : 0;
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int r = 16 * t + OutMap<P>::row(lane, v);
+        for (int nt = 0; nt < CC::NT; ++nt) {
           const int n = 16 * nt + OutMap<P>::col(lane, v);
-          if (r < cnt && n < C) {
-            const int ux = olx + r % owx, uy = oly + r / owx;
-            const Tf z = acc[nt][v] + bias[n];
-            obuf[r * SP + n] = grid[(gidx(ay, uy) * Gx + gidx(ax, ux)) * SP + n] + act_fn<Tf>(md.act, z);
-          }
-        }
-    }
-    __syncthreads();
-    if (l < L) {
-      // H'_l replaces H'_{l-1} on the box ...
-      for (int e = tid; e < cnt * CV; e += NT_) {
-        const int r = e / CV, cv = e % CV;
-        const int ux = olx + r % owx, uy = oly + r / owx;
-        const float4 val = *reinterpret_cast<const float4*>(obuf + r * SP + cv * V);
-        *reinterpret_cast<float4*>(grid + (gidx(ay, uy) * Gx + gidx(ax, ux)) * SP + cv * V) = val;
-        if (commit) {
-          const int s = latc(ax, ux) + Lx * latc(ay, uy);
-          *reinterpret_cast<float4*>(commit + ((long long)(l - 1) * N + s) * C + cv * V) = val;
+          Tf val = Tf(0);
+          if (r < cnt && n < C) val = grid[gofs + n] + act_fn<Tf>(md.act, Tf(acc[nt][v] + bias[n]));
+          outv[ti][nt][v] = val;
         }
       }
-      // ... and the ring of the next input box (output box at distance l+1
-      // grown by one) gets the cached H_l
+    }
+    __syncthreads();
+    const Tf* HL = featw + (long long)(L - 1) * N * C;
+#pragma unroll
+    for (int ti = 0; ti < MAXT; ++ti) {
+      const int t = wave + NW * ti;
+      if (t >= T) break;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = 16 * t + OutMap<P>::row(lane, v);
+        if (r >= cnt) continue;
+        int ux, uy;
+        box_site(r, olx, owx, mow, oly, ux, uy);
+        const int s = latc(ax, ux) + Lx * latc(ay, uy);
+        if (l < L) {
+          // H'_l replaces H'_{l-1} on the box (and goes to the cache on accept)
+          const int gofs = (gidx(ay, uy) * Gx + gidx(ax, ux)) * SP;
+#pragma unroll
+          for (int nt = 0; nt < CC::NT; ++nt) {
+            const int n = 16 * nt + OutMap<P>::col(lane, v);
+            if (n >= C) continue;
+            grid[gofs + n] = outv[ti][nt][v];
+            if (commit) commit[((long long)(l - 1) * N + s) * C + n] = outv[ti][nt][v];
+          }
+        } else {
+          // D = H'_L - H_L, densely [m][SP] at the start of the grid
+#pragma unroll
+          for (int nt = 0; nt < CC::NT; ++nt) {
+            const int n = 16 * nt + OutMap<P>::col(lane, v);
+            if (n >= C) continue;
+            const long long gi = (long long)s * C + n;
+            const Tf old = HL[gi];
+            grid[r * SP + n] = outv[ti][nt][v] - old;
+            if (commit) commit[(long long)(L - 1) * N * C + gi] = outv[ti][nt][v];
+          }
+        }
+      }
+    }
+    if (l < L) {
+      // the ring of the next input box (output box at distance l+1 grown by
+      // one) gets the cached H_l; ring sites lie outside this layer's box, so
+      // they are never written above
       int ilx, iwx, ily, iwy;
       box1(ax, h.xi, h.dx, l + 2, ilx, iwx);
       box1(ay, h.yi, h.dy, l + 2, ily, iwy);
       const Tf* Hl = featw + (long long)(l - 1) * N * C;
+      const int miw = kMagic16[iwx];
       const int tot = iwx * iwy * CV;
       constexpr int U = 4;          // loads in flight per thread
       for (int e0 = 0; e0 < tot; e0 += NT_ * U) {
@@ -302,8 +358,9 @@ SVMC_DEV void hop_features(const ModelDev& md, const LatDev& lt, const HopGeom& 
 #pragma unroll
         for (int u = 0; u < U; ++u) {
           const int e = e0 + NT_ * u + tid;
-          const int q = e / CV, cv = e % CV;
-          const int ux = ilx + q % iwx, uy = ily + q / iwx;
+          const int q = e / CV, cv = e - q * CV;
+          int ux, uy;
+          box_site(q, ilx, iwx, miw, ily, ux, uy);
           const bool ok = e < tot && !(inbox(ax, olx, owx, ux) && inbox(ay, oly, owy, uy));
           const int s = ok ? latc(ax, ux) + Lx * latc(ay, uy) : 0;
           dst[u] = ok ? (gidx(ay, uy) * Gx + gidx(ax, ux)) * SP + cv * V : -1;
@@ -312,38 +369,6 @@ SVMC_DEV void hop_features(const ModelDev& md, const LatDev& lt, const HopGeom& 
 #pragma unroll
         for (int u = 0; u < U; ++u)
           if (dst[u] >= 0) *reinterpret_cast<float4*>(grid + dst[u]) = val[u];
-      }
-    } else {
-      // D = H'_L - H_L, densely [m][C] at the start of the grid
-      const Tf* HL = featw + (long long)(L - 1) * N * C;
-      const int tot = cnt * CV;
-      constexpr int U = 4;
-      for (int e0 = 0; e0 < tot; e0 += NT_ * U) {
-        float4 old[U];
-        int ok[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-          const int e = e0 + NT_ * u + tid;
-          ok[u] = e < tot;
-          const int r = e / CV, cv = e % CV;
-          const int ux = olx + r % owx, uy = oly + r / owx;
-          const int s = ok[u] ? latc(ax, ux) + Lx * latc(ay, uy) : 0;
-          old[u] = ok[u] ? *reinterpret_cast<const float4*>(HL + (long long)s * C + cv * V) : float4{0, 0, 0, 0};
-          if (ok[u] && commit)
-            *reinterpret_cast<float4*>(commit + ((long long)(L - 1) * N + s) * C + cv * V) =
-                *reinterpret_cast<const float4*>(obuf + r * SP + cv * V);
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-          if (!ok[u]) continue;
-          const int e = e0 + NT_ * u + tid;
-          const int r = e / CV, cv = e % CV;
-          Tf* d = grid + r * SP + cv * V;
-          const Tf* nv = obuf + r * SP + cv * V;
-          const Tf* ov = reinterpret_cast<const Tf*>(&old[u]);
-#pragma unroll
-          for (int k = 0; k < V; ++k) d[k] = nv[k] - ov[k];
-        }
       }
     }
     __syncthreads();
@@ -358,6 +383,7 @@ SVMC_DEV int hop_klist(const LatDev& lt, const HopGeom& h, const int8_t* occ_s, 
                        int olx, int owx, int oly, int owy, int* kl, int& hpos, int lane) {
   const int N = lt.N, Lx = lt.Lx;
   const int cnt = owx * owy;
+  const int mow = kMagic16[owx];
   const int bit = 1 << h.sigma;
   int nk = 0;
   hpos = -1;
@@ -365,7 +391,8 @@ SVMC_DEV int hop_klist(const LatDev& lt, const HopGeom& h, const int8_t* occ_s, 
     const int m = base + lane;
     int s = 0, o = 0;
     if (m < cnt) {
-      const int ux = olx + m % owx, uy = oly + m / owx;
+      int ux, uy;
+      box_site(m, olx, owx, mow, oly, ux, uy);
       s = latc(h.ax, ux) + Lx * latc(h.ay, uy);
       o = occ_s[s];
       if (s == h.i) o -= bit;
@@ -386,18 +413,29 @@ SVMC_DEV int hop_klist(const LatDev& lt, const HopGeom& h, const int8_t* occ_s, 
   return nk;
 }
 
+// FP64 reciprocal: hardware estimate refined by two Newton steps (error
+// below one ulp of the IEEE quotient, enough for an elimination multiplier).
+SVMC_DEV double rcp_d(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(fma(-x, r, 1.0), r, r);
+  r = fma(fma(-x, r, 1.0), r, r);
+  return r;
+}
+
 // One-wave LU determinant of an r x r FP64 matrix, r <= RM <= 64.
 // Lane a (< r) holds row a in a[0..RM).  Columns rotate: at every step the
 // current pivot column is a[0] and the remaining columns shift left, so all
 // register indices stay static in a runtime step loop.  Partial pivoting
 // without moving rows: the unused row with the largest |a[0]| pivots (the
 // search compares |a| rounded to FP32, ties to the lower lane; pivots below
-// FP32's smallest denormal count as zero).  The pivot row reaches the other
-// lanes through v_readlane (scalar registers), eight columns at a time, and
-// only the columns still in play are updated.
+// FP32's smallest denormal count as zero).  The pivot lane writes its row to
+// `prow` (LDS, RM doubles of this wavefront) and every lane reads it back as
+// a broadcast; only the columns still in play are written and updated, eight
+// at a time.  LDS operations of one wavefront complete in order, so no wait
+// is needed between the write and the reads.
 // det = sign(permutation) * prod(pivots).
 template <int RM>
-SVMC_DEV double lu_det_rot(double (&a)[RM], int r_in, int lane) {
+SVMC_DEV double lu_det_rot(double (&a)[RM], int r_in, int lane, double* prow) {
   const int r = uniform_i(r_in);
   bool used = lane >= r;
   int step = 64;
@@ -410,16 +448,28 @@ SVMC_DEV double lu_det_rot(double (&a)[RM], int r_in, int lane) {
     const int piv = 63 - (int)(key & 63u);
     const double pv = readlane_d(cp, piv);
     det *= pv;
-    if (lane == piv) { used = true; step = p; }
-    const double l = used ? 0.0 : cp * (1.0 / pv);
     const int live = r - 1 - p;               // columns right of the pivot
+    if (lane == piv) {
+      used = true;
+      step = p;
+#pragma unroll
+      for (int c0 = 1; c0 < RM; c0 += 8) {
+        if (c0 <= live) {
+#pragma unroll
+          for (int c = c0; c < c0 + 8 && c < RM; ++c) prow[c - 1] = a[c];
+        }
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
+    const double l = used ? 0.0 : cp * rcp_d(pv);
 #pragma unroll
     for (int c0 = 1; c0 < RM; c0 += 8) {
       if (c0 <= live) {
 #pragma unroll
-        for (int c = c0; c < c0 + 8 && c < RM; ++c) a[c - 1] = fma(-l, readlane_d(a[c], piv), a[c]);
+        for (int c = c0; c < c0 + 8 && c < RM; ++c) a[c - 1] = fma(-l, prow[c - 1], a[c]);
       }
     }
+    __builtin_amdgcn_wave_barrier();
   }
   int inv = 0;
   for (int b = 0; b < r; ++b) {
@@ -430,91 +480,43 @@ SVMC_DEV double lu_det_rot(double (&a)[RM], int r_in, int lane) {
   return (inv & 1) ? -det : det;
 }
 
-// det of the Woodbury/determinant-lemma matrix of spin tau for one hop
-// (one wavefront).
-//   row form (|K| <= C):  A[a][b] = delta_ab + D(m_a) . P[:, k_b]
-//                         + [a = mover] (G[j][k_b] - delta_ab)
-//   column form (|K| > C): det(I + V U) with U = [D_K, e_h], V = [P_K; g - e_h]
-// Both equal det(Phi'[K] Phi^-1[:, K]).  All in FP64.  The P^T rows (and G
-// values) of the K labels are first copied into LDS with coalesced loads
-// (row form: transposed [c][b]; column form [b][c] when |K| <= KSTAGE).
+// det of the Woodbury / determinant-lemma matrix of spin tau for one hop
+// (one wavefront), in the column form
+//   det(I + V U),  U = [D_K, e_h] (changed rows K carry D(m_a); the mover's
+//   row also e_h),  V = [P_K; g_K - e_h]  (P = W Phi^-1, g = G[j] = M[j] Phi^-1)
+// of size C + [tau = moving spin], which equals det(Phi'[K] Phi^-1[:, K]).
+// Lane c < C accumulates row c from P^T[k_q][c] (one coalesced row load per
+// changed label); lane C from G[j][k_q].  All in FP64.
 template <class Tf, int C>
 SVMC_DEV double hop_det(const int* kl, int K_in, bool hopspin, int hpos_in, const Tf* Dbuf,
-                        const double* __restrict__ PTt, const double* __restrict__ Gj, double* stage, int lane) {
+                        const double* __restrict__ PTt, const double* __restrict__ Gj, double* prow, int lane) {
   const int K = uniform_i(K_in), hpos = uniform_i(hpos_in);
   if (K == 0) return 1.0;
   constexpr int RM = C + 1;
-  const bool rowform = K <= C;
-  const bool staged = K <= KSTAGE;
   constexpr int SP = SiteStride<Tf, C>::value;
-  constexpr int PKN = (C * KSP > KSTAGE * C ? C * KSP : KSTAGE * C);
-  double* pk = stage;                 // row form [C][KSP], column form [K][C]
-  double* gk = stage + PKN;           // [KSTAGE]
-  if (staged) {
-    constexpr int U = 4;
-    const int tot = K * C;
-    for (int e0 = 0; e0 < tot; e0 += 64 * U) {
-      double v[U];
-      int dst[U];
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int e = e0 + 64 * u + lane;
-        const bool ok = e < tot;
-        const int b = e / C, c = e % C;
-        const int kb = ok ? (kl[b] & 0xffff) : 0;
-        dst[u] = ok ? (rowform ? c * KSP + b : e) : -1;
-        v[u] = ok ? PTt[kb * C + c] : 0.0;
-      }
-#pragma unroll
-      for (int u = 0; u < U; ++u)
-        if (dst[u] >= 0) pk[dst[u]] = v[u];
-    }
-    if (hopspin && lane < K) gk[lane] = Gj[kl[lane] & 0xffff];
-    __builtin_amdgcn_wave_barrier();
-  }
   double a[RM];
 #pragma unroll
   for (int c = 0; c < RM; ++c) a[c] = 0.0;
-  int rdim;
-  if (rowform) {
-    const int ma = lane < K ? (kl[lane] >> 16) : 0;
-    for (int c = 0; c < C; ++c) {
-      const double dc = lane < K ? (double)Dbuf[ma * SP + c] : 0.0;
-      const double* pr = pk + c * KSP;
+  const bool rowp = lane < C, rowg = hopspin && lane == C;
+  for (int q = 0; q < K; ++q) {
+    const int e = kl[q];
+    const int mq = e >> 16, kq = e & 0xffff;
+    double p = 0.0;
+    if (rowp) p = PTt[kq * C + lane];
+    else if (rowg) p = Gj[kq] - (q == hpos ? 1.0 : 0.0);
+    const Tf* Dq = Dbuf + mq * SP;
 #pragma unroll
-      for (int b = 0; b < RM; ++b) a[b] = fma(dc, pr[b], a[b]);
-    }
-    const bool hrow = hopspin && lane == hpos;
-#pragma unroll
-    for (int b = 0; b < RM; ++b) {
-      double x = (b < K) ? a[b] : 0.0;
-      if (lane == b) x += 1.0;
-      if (hrow && b < K) x += gk[b] - (b == hpos ? 1.0 : 0.0);
-      a[b] = x;
-    }
-    rdim = K;
-  } else {
-    for (int q = 0; q < K; ++q) {
-      const int e = kl[q];
-      const int mq = e >> 16, kq = e & 0xffff;
-      double p = 0.0;
-      if (lane < C) p = staged ? pk[q * C + lane] : PTt[kq * C + lane];
-      else if (hopspin && lane == C) p = (staged ? gk[q] : Gj[kq]) - (q == hpos ? 1.0 : 0.0);
-      const Tf* Dq = Dbuf + mq * SP;
-#pragma unroll
-      for (int c = 0; c < C; ++c) a[c] = fma(p, (double)Dq[c], a[c]);
-    }
-    const int kh = hopspin ? (kl[hpos] & 0xffff) : 0;
-#pragma unroll
-    for (int c = 0; c < C; ++c) {
-      if (lane == c) a[c] += 1.0;
-      if (lane > C || (!hopspin && lane == C)) a[c] = 0.0;
-    }
-    if (hopspin) a[C] = lane < C ? PTt[kh * C + lane] : (lane == C ? Gj[kh] : 0.0);
-    else a[C] = lane == C ? 1.0 : 0.0;
-    rdim = C + (hopspin ? 1 : 0);
+    for (int c = 0; c < C; ++c) a[c] = fma(p, (double)Dq[c], a[c]);
   }
-  return lu_det_rot<RM>(a, rdim, lane);
+  const int kh = hopspin ? (kl[hpos] & 0xffff) : 0;
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    if (lane == c) a[c] += 1.0;
+    if (lane > C || (!hopspin && lane == C)) a[c] = 0.0;
+  }
+  if (hopspin) a[C] = rowp ? PTt[kh * C + lane] : (lane == C ? Gj[kh] : 0.0);
+  else a[C] = lane == C ? 1.0 : 0.0;
+  return lu_det_rot<RM>(a, C + (hopspin ? 1 : 0), lane, prow);
 }
 
 }  // namespace svmc

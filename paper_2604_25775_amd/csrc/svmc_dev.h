@@ -139,8 +139,17 @@ SVMC_DEV int wave_incl_scan(int v, int lane) {
 }
 
 template <class T> SVMC_DEV T act_fn(int act, T x);
+// FP32: from the hardware exp2 and reciprocal, tanh(x) = sign(x) (1 - t) / (1 + t)
+// with t = exp(-2|x|) (absolute error a few 1e-8, the rounding level of the
+// FP32 residual stream it is added to); SiLU(x) = x / (1 + exp(-x)).
 template <> SVMC_DEV float act_fn<float>(int act, float x) {
-  return act == ACT_TANH ? tanhf(x) : x / (1.0f + expf(-x));
+  constexpr float kLog2e = 1.4426950408889634f;
+  if (act == ACT_TANH) {
+    const float t = __builtin_amdgcn_exp2f(-2.0f * kLog2e * fabsf(x));
+    const float r = (1.0f - t) * __builtin_amdgcn_rcpf(1.0f + t);
+    return copysignf(r, x);
+  }
+  return x * __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(-kLog2e * x));
 }
 template <> SVMC_DEV double act_fn<double>(int act, double x) {
   return act == ACT_TANH ? tanh(x) : x / (1.0 + exp(-x));

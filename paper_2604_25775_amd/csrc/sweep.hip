@@ -194,10 +194,10 @@ __global__ __launch_bounds__(64 * SW_NW) void k_sweep(ModelDev md, const LatDev*
     int K = 0, hpos = -1;
     if (wv < 2) {
       K = hop_klist(lt, g, occ_s, lab_s, wv, olx, owx, oly, owy, klb + wv * KM, hpos, lane);
-      double* stage = (double*)(scratch + (wv == 0 ? hsc.stage0 : hsc.stage1));
+      double* prow = (double*)(scratch + hsc.prow) + wv * 64;
       const double* PTt = PTw + (long long)wv * nm * C;
       const double* Gj = Gw + ((long long)wv * N + g.j) * nm;
-      const double Rt = hop_det<Tf, C>(klb + wv * KM, K, wv == sp, hpos, Dbuf, PTt, Gj, stage, lane);
+      const double Rt = hop_det<Tf, C>(klb + wv * KM, K, wv == sp, hpos, Dbuf, PTt, Gj, prow, lane);
       if (lane == 0) {
         misc[wv] = Rt;
         misc[2 + wv] = (double)K;
