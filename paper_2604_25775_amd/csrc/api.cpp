@@ -71,7 +71,7 @@ struct svmc_ctx {
   DevBuf lats_dev;
   long long Wtot = 0;
   DevBuf occ, lab, pos, feat, inv, M, G, PT, ldet, sgn, flags, nacc;
-  DevBuf ratio_tmp;
+  DevBuf ratio_tmp, eloc_part;
   DevBuf sw_prog, sw_paused;         // sweep progress per walker, paused-walker counter
   DevBuf gK, gB, gE;                 // conv weights, conv bias, embedding (FP64, forward's rounding)
   DevBuf g_rows, g_dH, g_hs, g_dzs;  // gradient scratch
@@ -455,11 +455,16 @@ svmc_status svmc_local_energy(svmc_ctx* ctx, svmc_path path, double* eloc, int32
   out.code = hop_code;
   out.ratio = ratio;
   out.stride = ctx->max_hops();
+  out.part = nullptr;
+  out.slices = 1;
   const Bufs bf = ctx->bufs();
   const ModelDev md = ctx->mdev();
   svmc_status s;
   if (path == SVMC_PATH_LOWRANK) {
     if (!ctx->prepared && (s = prepare(ctx, st))) return s;
+    out.slices = 8;
+    if ((s = ctx->hip(ctx->eloc_part.ensure((size_t)ctx->Wtot * out.slices * 8), "alloc"))) return s;
+    out.part = ctx->eloc_part.as<double>();
     return ctx->hip(launch_eloc_lowrank(ctx->prec, md, ctx->lats_dev.as<LatDev>(), ctx->ld.data(),
                                         (int)ctx->ld.size(), ctx->Wtot, bf, out, st),
                     "low-rank local energy");

@@ -1,12 +1,13 @@
 // Low-rank local energies (Sec. II.A definition of E_loc with the Hubbard
 // Hamiltonian of Sec. III; ratios by the local update of Sec. II.C).
 //
-// One workgroup (two wavefronts) per walker, lattices of a mixed batch in the
-// same launch.  The walker's connected configurations are enumerated into LDS
-// in canonical order (spin up first, source site ascending, directions +x,
-// -x, +y, -y, then the four diagonals when t' != 0) and evaluated one after
-// the other by both wavefronts together (conv split between them, then one
-// determinant per wavefront); the sum runs in hop order.
+// A walker's connected configurations are enumerated in canonical order (spin
+// up first, source site ascending, directions +x, -x, +y, -y, then the four
+// diagonals when t' != 0) and split into `slices` contiguous ranges; one
+// workgroup (two wavefronts) evaluates one range, hop after hop (conv split
+// between the wavefronts, then one determinant per wavefront).  Lattices of
+// a mixed batch share the launch.  Partial sums are added per walker in
+// slice order by a second small kernel (deterministic).
 #include "hop.h"
 #include "svmc_launch.h"
 
@@ -89,13 +90,25 @@ SVMC_DEV int enumerate_hops(const LatDev& lt, const int8_t* occ_s, int* hops, in
 }
 
 #ifdef SVMC_INST_P
+// Block b -> (walker, slice).  Blocks are dealt to the 8 XCDs round-robin
+// (XCD = b mod 8); the slices of one walker get consecutive positions on the
+// same XCD so that walker's features, P^T and G stay in that XCD's L2.
+SVMC_DEV void eloc_block(long long b, int S, long long& w, int& slice) {
+  const long long xcd = b & 7, r = b >> 3;
+  slice = (int)(r % S);
+  w = (r / S) * 8 + xcd;
+}
+
 template <int P, int C>
-__global__ __launch_bounds__(64 * ELOC_NW) __attribute__((amdgpu_waves_per_eu(2))) void k_eloc_lowrank(ModelDev md, const LatDev* __restrict__ lats,
-                                                               int nlats, Bufs bf, ElocOut out) {
+__global__ __launch_bounds__(64 * ELOC_NW) __attribute__((amdgpu_waves_per_eu(2))) void k_eloc_lowrank(
+    ModelDev md, const LatDev* __restrict__ lats, int nlats, Bufs bf, ElocOut out, long long Wtot) {
   typedef typename PrecT<P>::Tf Tf;
   constexpr int NW = ELOC_NW, NTH = 64 * NW;
   extern __shared__ __attribute__((aligned(16))) char smem[];
-  const long long w = blockIdx.x;
+  long long w;
+  int slice;
+  eloc_block(blockIdx.x, out.slices, w, slice);
+  if (w >= Wtot) return;
   int li = 0;
   while (li + 1 < nlats && w >= lats[li + 1].w0) ++li;
   const LatDev lt = lats[li];
@@ -116,6 +129,8 @@ __global__ __launch_bounds__(64 * ELOC_NW) __attribute__((amdgpu_waves_per_eu(2)
   __syncthreads();
   const int H = uniform_i(min(enumerate_hops(lt, occ_s, hops, (int*)red, lt.maxhops), lt.maxhops));
   const bool bad = (bf.flags[w] & (1 | 8)) != 0;
+  // this block's hops: a contiguous slice of the canonical order
+  const int h0 = (int)(((long long)H * slice) / out.slices), h1 = (int)(((long long)H * (slice + 1)) / out.slices);
 
   const Tf* featw = (const Tf*)bf.feat + lt.feat_off + wl * (long long)md.L * N * C;
   const double* Gw = bf.G + lt.g_off + wl * 2LL * N * nm;
@@ -129,7 +144,7 @@ __global__ __launch_bounds__(64 * ELOC_NW) __attribute__((amdgpu_waves_per_eu(2)
   double part = 0.0;
   bool nonfinite = false;
   if (!bad) {
-    for (int hh = 0; hh < H; ++hh) {
+    for (int hh = h0; hh < h1; ++hh) {
       const int code = uniform_i(hops[hh]);
       const int i = code >> 4, sp = (code >> 3) & 1, d = code & 7;
       const HopGeom g = hop_geom(lt, md.L, sp, i, d);
@@ -140,7 +155,7 @@ __global__ __launch_bounds__(64 * ELOC_NW) __attribute__((amdgpu_waves_per_eu(2)
       const int K = hop_klist(lt, g, occ_s, lab_s, wv, olx, owx, oly, owy, kl, hpos, lane);
       const double* PTt = PTw + (long long)wv * nm * C;
       const double* Gj = Gw + ((long long)wv * N + g.j) * nm;
-      const double Rt = hop_det<Tf, C>(kl, K, wv == sp, hpos, (const Tf*)scratch, PTt, Gj, prow, lane);
+      const double Rt = hop_det<C>(kl, K, wv == sp, hpos, (const double*)scratch, PTt, Gj, prow, lane);
       if (lane == 0) misc[wv] = Rt;
       __syncthreads();
       if (tid == 0) {
@@ -156,12 +171,16 @@ __global__ __launch_bounds__(64 * ELOC_NW) __attribute__((amdgpu_waves_per_eu(2)
   }
   if (tid == 0) {
     if (nonfinite) atomicOr(bf.flags + w, 2);
-    int ndbl = 0;
-    for (int s = 0; s < N; ++s) ndbl += occ_s[s] == 3;
-    out.eloc[w] = bad ? NAN : lt.U * ndbl + part;
-    if (out.nhops) out.nhops[w] = H;
+    if (slice == 0) {
+      // the U term and the per-walker outputs go with slice 0
+      int ndbl = 0;
+      for (int s = 0; s < N; ++s) ndbl += occ_s[s] == 3;
+      part += lt.U * ndbl;
+      if (out.nhops) out.nhops[w] = H;
+    }
+    out.part[w * out.slices + slice] = bad ? NAN : part;
   }
-  if (bad && out.ratio) {
+  if (bad && out.ratio && slice == 0) {
     for (int hh = tid; hh < H; hh += NTH) {
       out.ratio[w * out.stride + hh] = NAN;
       out.code[w * out.stride + hh] = hops[hh];
@@ -175,7 +194,8 @@ static hipError_t eloc_impl(const ModelDev& md, const LatDev* lats_dev, int nlat
   auto kern = k_eloc_lowrank<P, C>;
   hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(kern, dim3((unsigned)W), dim3(64 * ELOC_NW), smem, st, md, lats_dev, nlats, bf, out);
+  const long long nblk = ((W + 7) / 8) * 8 * out.slices;
+  hipLaunchKernelGGL(kern, dim3((unsigned)nblk), dim3(64 * ELOC_NW), smem, st, md, lats_dev, nlats, bf, out, W);
   return hipGetLastError();
 }
 
@@ -195,15 +215,28 @@ size_t eloc_lowrank_smem(const LatDev* lats, int nlats, int prec, int L, int C) 
   return mx;
 }
 
+// E_loc[w] = sum over the walker's slices of the partial sums, in slice order.
+__global__ void k_eloc_sum(const double* __restrict__ part, int S, long long W, double* eloc) {
+  const long long w = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (w >= W) return;
+  double e = 0.0;
+  for (int k = 0; k < S; ++k) e += part[w * S + k];
+  eloc[w] = e;
+}
+
 hipError_t launch_eloc_lowrank(int prec, const ModelDev& md, const LatDev* lats_dev, const LatDev* lats_host,
                                int nlats, long long W, const Bufs& bf, const ElocOut& out, hipStream_t st) {
   const size_t smem = eloc_lowrank_smem(lats_host, nlats, prec, md.L, md.C);
   if (smem > 160 * 1024) return hipErrorInvalidValue;
+  hipError_t e = hipErrorInvalidValue;
 #define SVMC_EL(P_, C_) \
-  if (prec == P_ && md.C == C_) return eloc_lowrank_##P_##_##C_(md, lats_dev, nlats, W, bf, out, smem, st);
+  if (prec == P_ && md.C == C_) e = eloc_lowrank_##P_##_##C_(md, lats_dev, nlats, W, bf, out, smem, st);
   SVMC_FOR_EACH_PREC_C(SVMC_EL)
 #undef SVMC_EL
-  return hipErrorInvalidValue;
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_eloc_sum, dim3((unsigned)((W + 255) / 256)), dim3(256), 0, st, out.part, out.slices, W,
+                     out.eloc);
+  return hipGetLastError();
 }
 
 #endif

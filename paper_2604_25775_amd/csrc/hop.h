@@ -92,9 +92,14 @@ template <class Tf, int C> struct SiteStride {
   static constexpr int value = C + 16 / (int)sizeof(Tf);
 };
 
+// Row stride (doubles) of the dense FP64 difference D = H'_L - H_L.
+template <int C> struct DStride {
+  static constexpr int value = C + 2;
+};
+
 // LDS scratch of one hop, in bytes:
 //   grid   [Gy][Gx][SP] Tf  features of one layer on the update box; after the
-//                           last layer, D = H'_L - H_L densely as [m][SP]
+//                           last layer, D = H'_L - H_L densely as FP64 [m][C + 2]
 //   prow   [2][64] f64      pivot-row broadcast of the two determinant waves
 //   klists [2][Gx Gy] int   changed-row lists per spin
 //   misc   64 bytes         per-spin results
@@ -105,8 +110,9 @@ __host__ __device__ inline int align16i(int x) { return (x + 15) & ~15; }
 __host__ __device__ inline HopScratch hop_scratch(int Gx, int Gy, int L, int C, int tfb) {
   HopScratch h;
   const int SP = C + 16 / tfb;
-  (void)L;
-  h.prow = align16i(Gx * Gy * SP * tfb);
+  const int ox = Gx < 2 * L + 2 ? Gx : 2 * L + 2, oy = Gy < 2 * L + 2 ? Gy : 2 * L + 2;
+  const int gb = Gx * Gy * SP * tfb, db = ox * oy * (C + 2) * 8;
+  h.prow = align16i(gb > db ? gb : db);
   h.klists = h.prow + 2 * 64 * 8;
   h.misc = h.klists + align16i(2 * Gx * Gy * 4);
   h.bytes = h.misc + 64;
@@ -200,8 +206,8 @@ SVMC_DEV void conv_tile_grid(const typename PrecT<P>::Tf* __restrict__ grid, int
 
 // Incremental conv stack for one hop, computed by the NW wavefronts of the
 // workgroup (wave = this thread's wavefront).  On return (after a barrier)
-// the grid's first count*C entries hold D = H'_L - H_L on the layer-L box
-// (index m = ox + owx * oy).  If `commit` is non-null every new layer value is
+// the scratch starts with D = H'_L - H_L on the layer-L box as FP64
+// [m][C + 2] (index m = ox + owx * oy).  If `commit` is non-null every new layer value is
 // also stored into the cache (accepted move); commit may equal featw (the
 // box of a layer never overlaps the ring read from the cache for the next).
 template <int P, int C, int NW>
@@ -328,14 +334,16 @@ SVMC_DEV void hop_features(const ModelDev& md, const LatDev& lt, const HopGeom& 
             if (commit) commit[((long long)(l - 1) * N + s) * C + n] = outv[ti][nt][v];
           }
         } else {
-          // D = H'_L - H_L, densely [m][SP] at the start of the grid
+          // D = H'_L - H_L in FP64 (exact for FP32 features), densely
+          // [m][C + 2] at the start of the scratch
+          double* D = reinterpret_cast<double*>(grid);
 #pragma unroll
           for (int nt = 0; nt < CC::NT; ++nt) {
             const int n = 16 * nt + OutMap<P>::col(lane, v);
             if (n >= C) continue;
             const long long gi = (long long)s * C + n;
             const Tf old = HL[gi];
-            grid[r * SP + n] = outv[ti][nt][v] - old;
+            D[r * DStride<C>::value + n] = (double)outv[ti][nt][v] - (double)old;
             if (commit) commit[(long long)(L - 1) * N * C + gi] = outv[ti][nt][v];
           }
         }
@@ -487,26 +495,42 @@ SVMC_DEV double lu_det_rot(double (&a)[RM], int r_in, int lane, double* prow) {
 // of size C + [tau = moving spin], which equals det(Phi'[K] Phi^-1[:, K]).
 // Lane c < C accumulates row c from P^T[k_q][c] (one coalesced row load per
 // changed label); lane C from G[j][k_q].  All in FP64.
-template <class Tf, int C>
-SVMC_DEV double hop_det(const int* kl, int K_in, bool hopspin, int hpos_in, const Tf* Dbuf,
+template <int C>
+SVMC_DEV double hop_det(const int* kl, int K_in, bool hopspin, int hpos_in, const double* Dbuf,
                         const double* __restrict__ PTt, const double* __restrict__ Gj, double* prow, int lane) {
   const int K = uniform_i(K_in), hpos = uniform_i(hpos_in);
   if (K == 0) return 1.0;
   constexpr int RM = C + 1;
-  constexpr int SP = SiteStride<Tf, C>::value;
+  constexpr int SD = DStride<C>::value;
   double a[RM];
 #pragma unroll
   for (int c = 0; c < RM; ++c) a[c] = 0.0;
   const bool rowp = lane < C, rowg = hopspin && lane == C;
-  for (int q = 0; q < K; ++q) {
-    const int e = kl[q];
-    const int mq = e >> 16, kq = e & 0xffff;
-    double p = 0.0;
-    if (rowp) p = PTt[kq * C + lane];
-    else if (rowg) p = Gj[kq] - (q == hpos ? 1.0 : 0.0);
-    const Tf* Dq = Dbuf + mq * SP;
+  // eight changed rows at a time: their P^T / G loads are in flight together
+  constexpr int B = 8;
+  for (int q0 = 0; q0 < K; q0 += B) {
+    double p[B];
+    int mo[B];
 #pragma unroll
-    for (int c = 0; c < C; ++c) a[c] = fma(p, (double)Dq[c], a[c]);
+    for (int u = 0; u < B; ++u) {
+      const int q = q0 + u;
+      const int e = q < K ? kl[q] : 0;
+      const int kq = e & 0xffff;
+      mo[u] = (e >> 16) * SD;
+      double v = 0.0;
+      if (q < K) {
+        if (rowp) v = PTt[kq * C + lane];
+        else if (rowg) v = Gj[kq] - (q == hpos ? 1.0 : 0.0);
+      }
+      p[u] = v;
+    }
+#pragma unroll
+    for (int u = 0; u < B; ++u) {
+      if (q0 + u >= K) break;
+      const double* Dq = Dbuf + mo[u];
+#pragma unroll
+      for (int c = 0; c < C; ++c) a[c] = fma(p[u], Dq[c], a[c]);
+    }
   }
   const int kh = hopspin ? (kl[hpos] & 0xffff) : 0;
 #pragma unroll

@@ -32,6 +32,8 @@ struct ElocOut {
   int32_t* code;
   double* ratio;
   int stride;       // row stride of code/ratio
+  double* part;     // [W][slices] partial sums (scratch)
+  int slices;       // workgroups per walker
 };
 size_t eloc_lowrank_smem(const LatDev* lats_host, int nlats, int prec, int L, int C);
 hipError_t launch_eloc_lowrank(int prec, const ModelDev& md, const LatDev* lats_dev, const LatDev* lats_host,
