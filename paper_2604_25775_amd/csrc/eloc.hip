@@ -100,7 +100,7 @@ SVMC_DEV void eloc_block(long long b, int S, long long& w, int& slice) {
 }
 
 template <int P, int C>
-__global__ __launch_bounds__(64 * ELOC_NW) __attribute__((amdgpu_waves_per_eu(2))) void k_eloc_lowrank(
+__global__ __launch_bounds__(64 * ELOC_NW) __attribute__((amdgpu_waves_per_eu(3))) void k_eloc_lowrank(
     ModelDev md, const LatDev* __restrict__ lats, int nlats, Bufs bf, ElocOut out, long long Wtot) {
   typedef typename PrecT<P>::Tf Tf;
   constexpr int NW = ELOC_NW, NTH = 64 * NW;
@@ -155,7 +155,7 @@ __global__ __launch_bounds__(64 * ELOC_NW) __attribute__((amdgpu_waves_per_eu(2)
       const int K = hop_klist(lt, g, occ_s, lab_s, wv, olx, owx, oly, owy, kl, hpos, lane);
       const double* PTt = PTw + (long long)wv * nm * C;
       const double* Gj = Gw + ((long long)wv * N + g.j) * nm;
-      const double Rt = hop_det<C>(kl, K, wv == sp, hpos, (const double*)scratch, PTt, Gj, prow, lane);
+      const double Rt = hop_det<C>(kl, K, wv == sp, hpos, (const typename DType<P>::type*)scratch, PTt, Gj, prow, lane);
       if (lane == 0) misc[wv] = Rt;
       __syncthreads();
       if (tid == 0) {

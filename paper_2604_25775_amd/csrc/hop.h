@@ -92,14 +92,20 @@ template <class Tf, int C> struct SiteStride {
   static constexpr int value = C + 16 / (int)sizeof(Tf);
 };
 
-// Row stride (doubles) of the dense FP64 difference D = H'_L - H_L.
+// Storage of the dense difference D = H'_L - H_L that the determinant
+// assembly reads: the feature type (the difference is formed in FP64 and
+// rounded once), row stride C + 4 elements.  FP32 storage keeps the hop's
+// LDS at the size of its feature grid.
+template <int P> struct DType {
+  typedef typename PrecT<P>::Tf type;
+};
 template <int C> struct DStride {
-  static constexpr int value = C + 2;
+  static constexpr int value = C + 4;
 };
 
 // LDS scratch of one hop, in bytes:
 //   grid   [Gy][Gx][SP] Tf  features of one layer on the update box; after the
-//                           last layer, D = H'_L - H_L densely as FP64 [m][C + 2]
+//                           last layer, D = H'_L - H_L densely as Tf [m][C + 4]
 //   prow   [2][64] f64      pivot-row broadcast of the two determinant waves
 //   klists [2][Gx Gy] int   changed-row lists per spin
 //   misc   64 bytes         per-spin results
@@ -111,7 +117,7 @@ __host__ __device__ inline HopScratch hop_scratch(int Gx, int Gy, int L, int C, 
   HopScratch h;
   const int SP = C + 16 / tfb;
   const int ox = Gx < 2 * L + 2 ? Gx : 2 * L + 2, oy = Gy < 2 * L + 2 ? Gy : 2 * L + 2;
-  const int gb = Gx * Gy * SP * tfb, db = ox * oy * (C + 2) * 8;
+  const int gb = Gx * Gy * SP * tfb, db = ox * oy * (C + 4) * tfb;
   h.prow = align16i(gb > db ? gb : db);
   h.klists = h.prow + 2 * 64 * 8;
   h.misc = h.klists + align16i(2 * Gx * Gy * 4);
@@ -206,8 +212,8 @@ SVMC_DEV void conv_tile_grid(const typename PrecT<P>::Tf* __restrict__ grid, int
 
 // Incremental conv stack for one hop, computed by the NW wavefronts of the
 // workgroup (wave = this thread's wavefront).  On return (after a barrier)
-// the scratch starts with D = H'_L - H_L on the layer-L box as FP64
-// [m][C + 2] (index m = ox + owx * oy).  If `commit` is non-null every new layer value is
+// the scratch starts with D = H'_L - H_L on the layer-L box as Tf
+// [m][C + 4] (index m = ox + owx * oy).  If `commit` is non-null every new layer value is
 // also stored into the cache (accepted move); commit may equal featw (the
 // box of a layer never overlaps the ring read from the cache for the next).
 template <int P, int C, int NW>
@@ -334,16 +340,16 @@ SVMC_DEV void hop_features(const ModelDev& md, const LatDev& lt, const HopGeom& 
             if (commit) commit[((long long)(l - 1) * N + s) * C + n] = outv[ti][nt][v];
           }
         } else {
-          // D = H'_L - H_L in FP64 (exact for FP32 features), densely
-          // [m][C + 2] at the start of the scratch
-          double* D = reinterpret_cast<double*>(grid);
+          // D = H'_L - H_L, densely [m][C + 4] at the start of the scratch
+          typedef typename DType<P>::type DT;
+          DT* D = reinterpret_cast<DT*>(grid);
 #pragma unroll
           for (int nt = 0; nt < CC::NT; ++nt) {
             const int n = 16 * nt + OutMap<P>::col(lane, v);
             if (n >= C) continue;
             const long long gi = (long long)s * C + n;
             const Tf old = HL[gi];
-            D[r * DStride<C>::value + n] = (double)outv[ti][nt][v] - (double)old;
+            D[r * DStride<C>::value + n] = (DT)((double)outv[ti][nt][v] - (double)old);
             if (commit) commit[(long long)(L - 1) * N * C + gi] = outv[ti][nt][v];
           }
         }
@@ -495,8 +501,8 @@ SVMC_DEV double lu_det_rot(double (&a)[RM], int r_in, int lane, double* prow) {
 // of size C + [tau = moving spin], which equals det(Phi'[K] Phi^-1[:, K]).
 // Lane c < C accumulates row c from P^T[k_q][c] (one coalesced row load per
 // changed label); lane C from G[j][k_q].  All in FP64.
-template <int C>
-SVMC_DEV double hop_det(const int* kl, int K_in, bool hopspin, int hpos_in, const double* Dbuf,
+template <int C, class DT>
+SVMC_DEV double hop_det(const int* kl, int K_in, bool hopspin, int hpos_in, const DT* Dbuf,
                         const double* __restrict__ PTt, const double* __restrict__ Gj, double* prow, int lane) {
   const int K = uniform_i(K_in), hpos = uniform_i(hpos_in);
   if (K == 0) return 1.0;
@@ -527,9 +533,9 @@ SVMC_DEV double hop_det(const int* kl, int K_in, bool hopspin, int hpos_in, cons
 #pragma unroll
     for (int u = 0; u < B; ++u) {
       if (q0 + u >= K) break;
-      const double* Dq = Dbuf + mo[u];
+      const DT* Dq = Dbuf + mo[u];
 #pragma unroll
-      for (int c = 0; c < C; ++c) a[c] = fma(p[u], Dq[c], a[c]);
+      for (int c = 0; c < C; ++c) a[c] = fma(p[u], (double)Dq[c], a[c]);
     }
   }
   const int kh = hopspin ? (kl[hpos] & 0xffff) : 0;

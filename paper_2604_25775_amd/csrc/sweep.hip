@@ -153,7 +153,7 @@ __global__ __launch_bounds__(64 * SW_NW) void k_sweep(ModelDev md, const LatDev*
   const HopScratch hsc = hop_scratch(lt.Gx, lt.Gy, md.L, C, (int)sizeof(Tf));
   const int KM = lt.Gx * lt.Gy;
   int* klb = (int*)(scratch + hsc.klists);
-  const double* Dbuf = (const double*)scratch;
+  const typename DType<P>::type* Dbuf = (const typename DType<P>::type*)scratch;
   constexpr int SD = DStride<C>::value;
 
   int8_t* occ_g = bf.occ + lt.occ_off + wl * N;
@@ -231,7 +231,7 @@ __global__ __launch_bounds__(64 * SW_NW) void k_sweep(ModelDev md, const LatDev*
         if (c < C) {
           for (int a = 0; a < r; ++a) {
             const int ka = kl[a] & 0xffff, ma = kl[a] >> 16;
-            v = fma(PTt[(long long)ka * C + cp], Dbuf[ma * SD + c], v);
+            v = fma(PTt[(long long)ka * C + cp], (double)Dbuf[ma * SD + c], v);
           }
         } else if (hs) {
           v = PTt[(long long)k * C + cp];
@@ -244,7 +244,7 @@ __global__ __launch_bounds__(64 * SW_NW) void k_sweep(ModelDev md, const LatDev*
           if (c < C) {
             for (int a = 0; a < r; ++a) {
               const int ka = kl[a] & 0xffff, ma = kl[a] >> 16;
-              v = fma(Gj[ka] - (ka == k ? 1.0 : 0.0), Dbuf[ma * SD + c], v);
+              v = fma(Gj[ka] - (ka == k ? 1.0 : 0.0), (double)Dbuf[ma * SD + c], v);
             }
           } else {
             v = Gj[k] - 1.0;
@@ -313,15 +313,15 @@ __global__ __launch_bounds__(64 * SW_NW) void k_sweep(ModelDev md, const LatDev*
           if (c < C) {
             for (int a = 0; a < r; ++a) {
               const int ka = kl[a] & 0xffff, ma = kl[a] >> 16;
-              v = fma(grow[sl * nm + ka], Dbuf[ma * SD + c], v);
+              v = fma(grow[sl * nm + ka], (double)Dbuf[ma * SD + c], v);
             }
           } else if (hs) {
             v = grow[sl * nm + k];
           }
           const int mb = box_index(lt, s, olx, owx, oly, owy);
           if (mb >= 0 && (c < C || hs)) {
-            const double* Dm = Dbuf + mb * SD;
-            for (int c2 = 0; c2 < C; ++c2) v = fma(Dm[c2], pu[c2 * RA + c], v);
+            const typename DType<P>::type* Dm = Dbuf + mb * SD;
+            for (int c2 = 0; c2 < C; ++c2) v = fma((double)Dm[c2], pu[c2 * RA + c], v);
           }
           gu[sl * RA + c] = v;
         }
@@ -332,9 +332,9 @@ __global__ __launch_bounds__(64 * SW_NW) void k_sweep(ModelDev md, const LatDev*
             double v = grow[sl * nm + tid];
             const int mb = box_index(lt, s, olx, owx, oly, owy);
             if (mb >= 0) {
-              const double* Dm = Dbuf + mb * SD;
+              const typename DType<P>::type* Dm = Dbuf + mb * SD;
 #pragma unroll
-              for (int c = 0; c < C; ++c) v = fma(Dm[c], pt[c], v);
+              for (int c = 0; c < C; ++c) v = fma((double)Dm[c], pt[c], v);
             }
 #pragma unroll
             for (int c = 0; c < RA; ++c) v = fma(-gu[sl * RA + c], z[c], v);
