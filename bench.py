@@ -172,7 +172,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="c3")
-    ap.add_argument("--prec", default="bf16x3", choices=["bf16", "bf16x3", "f32", "f64"])
+    ap.add_argument("--prec", default="bf16x3", choices=["bf16", "bf16x3", "f16x2", "f32", "f64"])
     ap.add_argument("--walkers", type=int, default=None)
     ap.add_argument("--full-walkers", type=int, default=None,
                     help="walkers for the full-recompute timing (default: all)")
@@ -246,8 +246,8 @@ def main():
     flags = ctx.flags().cpu().numpy()
 
     conv_f, det_f = lowrank_flops(lat, occ, model.n_conv, model.channels)
-    conv_peak = PEAK_BF16 if a.prec in ("bf16", "bf16x3") else (PEAK_FP32 if a.prec == "f32" else PEAK_FP64)
-    passes = 3 if a.prec == "bf16x3" else 1
+    conv_peak = PEAK_BF16 if a.prec in ("bf16", "bf16x3", "f16x2") else (PEAK_FP32 if a.prec == "f32" else PEAK_FP64)
+    passes = {"bf16x3": 3, "f16x2": 2}.get(a.prec, 1)
     t_peak = conv_f * passes / conv_peak + det_f / PEAK_FP64
     achieved = (conv_f + det_f) / (kern_ms / 1e3) / 1e12
     peak = (conv_f + det_f) / t_peak / 1e12

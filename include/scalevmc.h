@@ -70,8 +70,12 @@ typedef enum { SVMC_ACT_TANH = 0, SVMC_ACT_SILU = 1 } svmc_act;
 /* Conv-stack precision.  BF16: multiplier inputs rounded to BF16, FP32
  * accumulation, FP32 residual stream.  BF16X3: each FP32 activation is split
  * exactly into three BF16 terms multiplied in three passes (FP32-accurate
- * activations on the BF16 matrix units); weights are BF16 in both. */
-typedef enum { SVMC_FP64 = 0, SVMC_FP32 = 1, SVMC_BF16 = 2, SVMC_BF16X3 = 3 } svmc_prec;
+ * activations on the BF16 matrix units); weights are BF16 in both.  F16X2:
+ * each FP32 activation split into two FP16 terms (round toward zero; the
+ * pair carries it to 2^-20 relative, |activation| < 65504), two passes on the
+ * FP16 matrix units, weights rounded to FP16.  All 16-bit modes accumulate in
+ * FP32 with an FP32 residual stream. */
+typedef enum { SVMC_FP64 = 0, SVMC_FP32 = 1, SVMC_BF16 = 2, SVMC_BF16X3 = 3, SVMC_F16X2 = 4 } svmc_prec;
 typedef enum { SVMC_PATH_LOWRANK = 0, SVMC_PATH_FULL = 1 } svmc_path;
 
 /* Hubbard lattice (Sec. III, Hubbard Hamiltonian): Lx x Ly sites, periodic or

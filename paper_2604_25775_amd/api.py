@@ -12,7 +12,7 @@ import torch
 
 from . import _lib
 
-PREC = {"f64": 0, "f32": 1, "bf16": 2, "bf16x3": 3}
+PREC = {"f64": 0, "f32": 1, "bf16": 2, "bf16x3": 3, "f16x2": 4}
 ACT = {"tanh": 0, "silu": 1}
 PATH = {"lowrank": 0, "full": 1}
 

@@ -31,7 +31,7 @@ DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
 # (precision, channels) instances of the templated conv kernels; must match
 # SVMC_FOR_EACH_PREC_C in csrc/svmc_launch.h.
-INSTANCES = [(p, c) for p in ("PREC_F64", "PREC_F32", "PREC_BF16", "PREC_BF16X3") for c in (8, 16, 24, 32)]
+INSTANCES = [(p, c) for p in ("PREC_F64", "PREC_F32", "PREC_BF16", "PREC_BF16X3", "PREC_F16X2") for c in (8, 16, 24, 32)]
 
 
 def units():

@@ -172,7 +172,7 @@ svmc_status svmc_create(const svmc_lattice* lats, int32_t n_lats, const svmc_mod
   if (m->n_conv < 1 || m->n_conv > 4) return SVMC_ERR_UNSUPPORTED;
   if (m->channels != 8 && m->channels != 16 && m->channels != 24 && m->channels != 32) return SVMC_ERR_UNSUPPORTED;
   if (m->act != SVMC_ACT_TANH && m->act != SVMC_ACT_SILU) return SVMC_ERR_INVALID_ARG;
-  if (m->conv_prec < 0 || m->conv_prec > 3) return SVMC_ERR_INVALID_ARG;
+  if (m->conv_prec < 0 || m->conv_prec > 4) return SVMC_ERR_INVALID_ARG;
   if (m->refresh_every < 1) return SVMC_ERR_INVALID_ARG;
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return SVMC_ERR_HIP;
@@ -218,11 +218,17 @@ svmc_status svmc_set_params(svmc_ctx* ctx, const double* theta, const double* co
   const double* K = E + 4 * C;
   const double* Bc = K + 9LL * L * C * C;
   const double* rest = Bc + (long long)L * C;
+  // values the device uses: rnd for the embedding and conv bias (feature
+  // type; BF16 in the BF16 modes), rnd_w for the conv weights (FP16 in F16X2)
   auto rnd = [&](double x) -> double {
     if (P == PREC_F64) return x;
     float f = (float)x;
-    if (P == PREC_F32) return f;
+    if (P == PREC_F32 || P == PREC_F16X2) return f;
     return bf16_to_f32(f32_to_bf16_rne(f));
+  };
+  auto rnd_w = [&](double x) -> double {
+    if (P == PREC_F16X2) return (double)(float)(_Float16)(float)x;
+    return rnd(x);
   };
   // embedding and conv bias in the feature type
   const int tfb = ctx->tf_bytes();
@@ -236,7 +242,7 @@ svmc_status svmc_set_params(svmc_ctx* ctx, const double* theta, const double* co
     else ((float*)bb.data())[k] = (float)rnd(Bc[k]);
   }
   // conv kernels as MFMA B fragments
-  const bool bf = P == PREC_BF16 || P == PREC_BF16X3;
+  const bool bf = P == PREC_BF16 || P == PREC_BF16X3 || P == PREC_F16X2;
   const int KC = bf ? 32 : 4;
   const int Q = (9 * C + KC - 1) / KC, NT = (C + 15) / 16;
   const int per = bf ? 8 : 1;
@@ -257,11 +263,12 @@ svmc_status svmc_set_params(svmc_ctx* ctx, const double* theta, const double* co
             const size_t idx = ((((size_t)l * Q + q) * NT + nt) * 64 + lane) * per + e;
             if (P == PREC_F64) ((double*)bp.data())[idx] = v;
             else if (P == PREC_F32) ((float*)bp.data())[idx] = (float)v;
+            else if (P == PREC_F16X2) ((_Float16*)bp.data())[idx] = (_Float16)(float)v;
             else ((uint16_t*)bp.data())[idx] = f32_to_bf16_rne((float)v);
           }
   // FP64 copies of what the forward uses, for the backward
   std::vector<double> gk(9ULL * L * C * C), gbias((size_t)L * C), ge(4ULL * C);
-  for (size_t k = 0; k < gk.size(); ++k) gk[k] = rnd(K[k]);
+  for (size_t k = 0; k < gk.size(); ++k) gk[k] = rnd_w(K[k]);
   for (size_t k = 0; k < gbias.size(); ++k) gbias[k] = rnd(Bc[k]);
   for (size_t k = 0; k < ge.size(); ++k) ge[k] = rnd(E[k]);
   if ((s = ctx->hip(ctx->gK.ensure(gk.size() * 8), "alloc")) || (s = ctx->hip(ctx->gB.ensure(gbias.size() * 8), "alloc")) ||

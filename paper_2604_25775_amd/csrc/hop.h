@@ -159,7 +159,7 @@ SVMC_DEV void conv_tile_grid(const typename PrecT<P>::Tf* __restrict__ grid, int
     }
     int tap, c0;
     bool kok;
-    if constexpr (P == PREC_BF16 || P == PREC_BF16X3) {
+    if constexpr (Mma16<P>::value) {
       const int k0 = 32 * q + 8 * g;
       kok = k0 < CC::K;
       tap = kok ? k0 / C : 0;
@@ -172,7 +172,7 @@ SVMC_DEV void conv_tile_grid(const typename PrecT<P>::Tf* __restrict__ grid, int
     const unsigned gx = (px >> (8 * (tap % 3))) & 0xFFu, gy = (py >> (8 * (tap / 3))) & 0xFFu;
     const bool ok = kok && gx != 0xFFu && gy != 0xFFu;
     const int off = ((int)gy * Gx + (int)gx) * SiteStride<Tf, C>::value + c0;
-    if constexpr (P == PREC_BF16 || P == PREC_BF16X3) {
+    if constexpr (Mma16<P>::value) {
       float x[8];
       if (ok) {
         const float4* p4 = reinterpret_cast<const float4*>(grid + off);
@@ -183,25 +183,7 @@ SVMC_DEV void conv_tile_grid(const typename PrecT<P>::Tf* __restrict__ grid, int
 #pragma unroll
         for (int e = 0; e < 8; ++e) x[e] = 0.0f;
       }
-      v8bf a;
-#pragma unroll
-      for (int e = 0; e < 8; ++e) a[e] = (__bf16)x[e];
-#pragma unroll
-      for (int nt = 0; nt < CC::NT; ++nt) mfma(acc[nt], a, b[nt]);
-      if constexpr (P == PREC_BF16X3) {
-        v8bf a2, a3;
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          const float r1 = x[e] - (float)a[e];
-          a2[e] = (__bf16)r1;
-          a3[e] = (__bf16)(r1 - (float)a2[e]);
-        }
-#pragma unroll
-        for (int nt = 0; nt < CC::NT; ++nt) {
-          mfma(acc[nt], a2, b[nt]);
-          mfma(acc[nt], a3, b[nt]);
-        }
-      }
+      mma_chunk16<P, CC::NT>(acc, x, b);
     } else {
       const Tf a = ok ? grid[off] : Tf(0);
 #pragma unroll

@@ -11,11 +11,20 @@
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef double v4d __attribute__((ext_vector_type(4)));
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+typedef _Float16 v8h __attribute__((ext_vector_type(8)));
+typedef _Float16 v2h __attribute__((ext_vector_type(2)));
 
 // PREC_BF16X3: conv multiplier inputs split exactly into three BF16 terms
 // (x = hi + mid + lo), three MFMA passes with FP32 accumulation, so the conv
 // sees FP32 activations and BF16 weights.
-enum { PREC_F64 = 0, PREC_F32 = 1, PREC_BF16 = 2, PREC_BF16X3 = 3 };
+// PREC_F16X2: conv multiplier inputs split into two FP16 terms by round-
+// toward-zero conversions (x = hi + lo + e, |e| < 2^-20 |x|), two MFMA passes
+// with FP32 accumulation, FP16 weights.
+enum { PREC_F64 = 0, PREC_F32 = 1, PREC_BF16 = 2, PREC_BF16X3 = 3, PREC_F16X2 = 4 };
+// conv on the 16-bit matrix-core instructions (K chunks of 32)
+template <int P> struct Mma16 {
+  static constexpr bool value = P == PREC_BF16 || P == PREC_BF16X3 || P == PREC_F16X2;
+};
 enum { ACT_TANH = 0, ACT_SILU = 1 };
 
 // ---------------------------------------------------------------------------
@@ -85,6 +94,9 @@ template <> struct PrecT<PREC_BF16> {
 };
 template <> struct PrecT<PREC_BF16X3> {
   typedef float Tf; typedef v8bf Tb; typedef v4f Acc; static constexpr int KC = 32;
+};
+template <> struct PrecT<PREC_F16X2> {
+  typedef float Tf; typedef v8h Tb; typedef v4f Acc; static constexpr int KC = 32;
 };
 
 template <int P, int C> struct ConvCfg {
@@ -164,8 +176,54 @@ SVMC_DEV void mfma(v4d& c, double a, double b) {
 SVMC_DEV void mfma(v4f& c, float a, float b) {
   c = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
+SVMC_DEV void mfma(v4f& c, v8h a, v8h b) {
+  c = __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+}
 SVMC_DEV void mfma(v4f& c, v8bf a, v8bf b) {
   c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+// One K chunk of a 16-bit mode: this lane's 8 activations x (FP32) times the
+// B fragments b[nt], accumulated into acc[nt].  Every conv kernel goes
+// through here, so the arithmetic per output element is the same in all of
+// them.
+template <int P, int NT>
+SVMC_DEV void mma_chunk16(v4f (&acc)[NT], const float (&x)[8], const typename PrecT<P>::Tb (&b)[NT]) {
+  if constexpr (P == PREC_F16X2) {
+    v8h hi, lo;
+#pragma unroll
+    for (int e = 0; e < 8; e += 2) {
+      const v2h h = __builtin_bit_cast(v2h, __builtin_amdgcn_cvt_pkrtz(x[e], x[e + 1]));
+      const v2h l = __builtin_bit_cast(v2h, __builtin_amdgcn_cvt_pkrtz(x[e] - (float)h[0], x[e + 1] - (float)h[1]));
+      hi[e] = h[0]; hi[e + 1] = h[1];
+      lo[e] = l[0]; lo[e + 1] = l[1];
+    }
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) mfma(acc[nt], hi, b[nt]);
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) mfma(acc[nt], lo, b[nt]);
+  } else {
+    v8bf a;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) a[e] = (__bf16)x[e];
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) mfma(acc[nt], a, b[nt]);
+    if constexpr (P == PREC_BF16X3) {
+      // remainders: x - hi is exact in FP32, and so is (x - hi) - mid
+      v8bf a2, a3;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const float r1 = x[e] - (float)a[e];
+        a2[e] = (__bf16)r1;
+        a3[e] = (__bf16)(r1 - (float)a2[e]);
+      }
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) {
+        mfma(acc[nt], a2, b[nt]);
+        mfma(acc[nt], a3, b[nt]);
+      }
+    }
+  }
 }
 
 // Output element (row, column) held in accumulator slot v of `lane` for the
@@ -206,7 +264,7 @@ SVMC_DEV void conv_tile(const typename PrecT<P>::Tf* __restrict__ src, const int
     for (int v = 0; v < 4; ++v) acc[nt][v] = 0;
 #pragma unroll
   for (int q = 0; q < CC::Q; ++q) {
-    if constexpr (P == PREC_BF16 || P == PREC_BF16X3) {
+    if constexpr (Mma16<P>::value) {
       const int k0 = 32 * q + 8 * g;
       float x[8];
 #pragma unroll
@@ -223,26 +281,10 @@ SVMC_DEV void conv_tile(const typename PrecT<P>::Tf* __restrict__ src, const int
           x[4] = x1.x; x[5] = x1.y; x[6] = x1.z; x[7] = x1.w;
         }
       }
-      v8bf a;
+      typename PrecT<P>::Tb b[CC::NT];
 #pragma unroll
-      for (int e = 0; e < 8; ++e) a[e] = (__bf16)x[e];
-#pragma unroll
-      for (int nt = 0; nt < CC::NT; ++nt) mfma(acc[nt], a, Bl[(q * CC::NT + nt) * 64 + lane]);
-      if constexpr (P == PREC_BF16X3) {
-        // remainders: x - hi is exact in FP32, and so is (x - hi) - mid
-        v8bf a2, a3;
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          const float r1 = x[e] - (float)a[e];
-          a2[e] = (__bf16)r1;
-          a3[e] = (__bf16)(r1 - (float)a2[e]);
-        }
-#pragma unroll
-        for (int nt = 0; nt < CC::NT; ++nt) {
-          mfma(acc[nt], a2, Bl[(q * CC::NT + nt) * 64 + lane]);
-          mfma(acc[nt], a3, Bl[(q * CC::NT + nt) * 64 + lane]);
-        }
-      }
+      for (int nt = 0; nt < CC::NT; ++nt) b[nt] = Bl[(q * CC::NT + nt) * 64 + lane];
+      mma_chunk16<P, CC::NT>(acc, x, b);
     } else {
       // K chunk of 4: all four k of the chunk lie in one tap (C % 4 == 0)
       const int t = (4 * q) / C;
@@ -287,7 +329,7 @@ SVMC_DEV void conv_layer_tiles(const typename PrecT<P>::Tf* __restrict__ grid, i
     for (int nt = 0; nt < CC::NT; ++nt) b[nt] = Bl[(q * CC::NT + nt) * 64 + lane];
     int tap, c0;
     bool kok;
-    if constexpr (P == PREC_BF16 || P == PREC_BF16X3) {
+    if constexpr (Mma16<P>::value) {
       const int k0 = 32 * q + 8 * g;
       kok = k0 < CC::K;
       tap = kok ? k0 / C : 0;
@@ -304,7 +346,7 @@ SVMC_DEV void conv_layer_tiles(const typename PrecT<P>::Tf* __restrict__ grid, i
         const unsigned gx = (gxs[t] >> sx) & 0xFFu, gy = (gys[t] >> sy) & 0xFFu;
         const bool ok = kok && gx != 0xFFu && gy != 0xFFu;
         const int off = ((int)gy * Gx + (int)gx) * C + c0;
-        if constexpr (P == PREC_BF16 || P == PREC_BF16X3) {
+        if constexpr (Mma16<P>::value) {
           float x[8];
           if (ok) {
             const float4* p4 = reinterpret_cast<const float4*>(grid + off);
@@ -315,25 +357,7 @@ SVMC_DEV void conv_layer_tiles(const typename PrecT<P>::Tf* __restrict__ grid, i
 #pragma unroll
             for (int e = 0; e < 8; ++e) x[e] = 0.0f;
           }
-          v8bf a;
-#pragma unroll
-          for (int e = 0; e < 8; ++e) a[e] = (__bf16)x[e];
-#pragma unroll
-          for (int nt = 0; nt < CC::NT; ++nt) mfma(acc[t][nt], a, b[nt]);
-          if constexpr (P == PREC_BF16X3) {
-            v8bf a2, a3;
-#pragma unroll
-            for (int e = 0; e < 8; ++e) {
-              const float r1 = x[e] - (float)a[e];
-              a2[e] = (__bf16)r1;
-              a3[e] = (__bf16)(r1 - (float)a2[e]);
-            }
-#pragma unroll
-            for (int nt = 0; nt < CC::NT; ++nt) {
-              mfma(acc[t][nt], a2, b[nt]);
-              mfma(acc[t][nt], a3, b[nt]);
-            }
-          }
+          mma_chunk16<P, CC::NT>(acc[t], x, b);
         } else {
           const Tf a = ok ? grid[off] : Tf(0);
 #pragma unroll

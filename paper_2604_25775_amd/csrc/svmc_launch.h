@@ -9,7 +9,8 @@
   X(PREC_F64, 8) X(PREC_F64, 16) X(PREC_F64, 24) X(PREC_F64, 32) \
   X(PREC_F32, 8) X(PREC_F32, 16) X(PREC_F32, 24) X(PREC_F32, 32) \
   X(PREC_BF16, 8) X(PREC_BF16, 16) X(PREC_BF16, 24) X(PREC_BF16, 32) \
-  X(PREC_BF16X3, 8) X(PREC_BF16X3, 16) X(PREC_BF16X3, 24) X(PREC_BF16X3, 32)
+  X(PREC_BF16X3, 8) X(PREC_BF16X3, 16) X(PREC_BF16X3, 24) X(PREC_BF16X3, 32) \
+  X(PREC_F16X2, 8) X(PREC_F16X2, 16) X(PREC_F16X2, 24) X(PREC_F16X2, 32)
 
 namespace svmc {
 

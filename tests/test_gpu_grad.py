@@ -81,7 +81,7 @@ def test_gradient_after_sweeps_and_vjp():
     assert torch.allclose(la, la_ref)
 
 
-@pytest.mark.parametrize("prec", ["f32", "bf16x3"])
+@pytest.mark.parametrize("prec", ["f32", "bf16x3", "f16x2"])
 def test_jacobian_fp32_features(prec):
     lat = wl.Lattice(6, 6, 1, 0, 1.0, 0.0, 8.0, 15, 15)
     model = wl.Model(3, 16, "tanh", prec)

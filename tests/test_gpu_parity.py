@@ -100,6 +100,17 @@ def test_bf16x3_conv_headline_lattice():
     say(f"  worst {worst}")
 
 
+def test_f16x2_conv_headline_lattice():
+    """Two-term FP16 split conv (round toward zero, 2^-20 relative on the
+    activations; FP16 weights) on the headline lattice against the plain
+    FP64 oracle with the same FP16-rounded weights: E_loc within 1e-4."""
+    model = wl.Model(4, 32, "tanh", "f16x2")
+    say("[parity f16x2] 16x16 L4 C32, 2 walkers")
+    ctx, params, occs = build([HEADLINE], model, [2])
+    worst = check_walkers(ctx, [HEADLINE], params, occs, model, 1e-3, 1e-4, tol_logpsi=1e-6)
+    say(f"  worst {worst}")
+
+
 def test_bad_count_flag():
     lat = wl.Lattice(4, 4, 1, 1, 1.0, 0.0, 4.0, 5, 5)
     model = wl.Model(2, 8, "tanh", "f64")

@@ -51,7 +51,7 @@ class Model:
     n_conv: int = 2
     channels: int = 8
     act: str = "tanh"
-    conv_prec: str = "f64"          # f64 | f32 | bf16 | bf16x3
+    conv_prec: str = "f64"          # f64 | f32 | bf16 | bf16x3 | f16x2
     refresh_every: int = 32
 
 
@@ -219,10 +219,13 @@ def quantise_params(p: Params, prec: str) -> Params:
     q = p.copy()
     if prec == "f64":
         return q
-    dt = {"f32": torch.float32, "bf16": torch.bfloat16, "bf16x3": torch.bfloat16}[prec]
+    dt = {"f32": torch.float32, "bf16": torch.bfloat16, "bf16x3": torch.bfloat16, "f16x2": torch.float32}[prec]
     for name in ("embed", "conv_w", "conv_b"):
         a = torch.from_numpy(getattr(q, name)).to(dt).to(torch.float64).numpy()
         setattr(q, name, a)
+    if prec == "f16x2":
+        # FP16 conv weights (from their FP32 value), FP32 embedding and bias
+        q.conv_w = torch.from_numpy(q.conv_w).to(torch.float16).to(torch.float64).numpy()
     return q
 
 
