@@ -181,6 +181,8 @@ def main():
     ap.add_argument("--no-full", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-grad", action="store_true")
+    ap.add_argument("--tune-cache", default=None,
+                    help="autotuner cache file (default: tune, do not store)")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py measures one GPU only (asked for {a.gpus}); the walker-parallel "
@@ -220,6 +222,9 @@ def main():
         occ_t, _ = ctx.state()
         occ = occ_t.cpu().numpy().reshape(W, lat.N)
 
+    slices = ctx.tune(a.tune_cache)
+    extra["eloc_slices_per_walker"] = slices
+    log(f"[bench] autotuner: {slices} workgroups per walker")
     for _ in range(a.warmup):
         ctx.prepare()
         ctx.local_energy(out=eloc)

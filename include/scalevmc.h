@@ -223,6 +223,16 @@ svmc_status svmc_grad_logpsi(svmc_ctx* ctx, const double* vjp_w, double* out,
 /* Per-walker flag bits (svmc_walker_flag), device [W] int32. */
 svmc_status svmc_walker_flags(svmc_ctx* ctx, int32_t* flags, hipStream_t stream);
 
+/* Autotuner of the low-rank local-energy launch shape (not a step of the
+ * method): each walker's hops are split over `slices` workgroups.  Times
+ * svmc_local_energy(LOWRANK) on the loaded walkers for slices in
+ * {1, 2, 4, 8, 16} and keeps the fastest for this context.  cache_path
+ * (may be NULL): a text file; a line for the same shape key (lattices,
+ * network, precision, walker count, device name) is reused without timing,
+ * otherwise the result is appended.  *slices_out (may be NULL) receives the
+ * choice.  Synchronises `stream`.  Errors: SVMC_ERR_STATE without walkers. */
+svmc_status svmc_tune(svmc_ctx* ctx, const char* cache_path, int32_t* slices_out, hipStream_t stream);
+
 const char* svmc_status_string(svmc_status s);
 /* Message of the last error on this context ("" if none). */
 const char* svmc_last_error(const svmc_ctx* ctx);

@@ -170,6 +170,14 @@ class ScaleVMC:
         self._check(self.lib.svmc_walker_flags(self.h, _ptr(f), _stream()), "walker_flags")
         return f
 
+    def tune(self, cache_path: str | None = None) -> int:
+        """Pick the fastest local-energy launch shape for the loaded walkers
+        (svmc_tune); returns the chosen slices per walker."""
+        out = ct.c_int32(0)
+        path = cache_path.encode() if cache_path else None
+        self._check(self.lib.svmc_tune(self.h, path, ct.byref(out), _stream()), "tune")
+        return int(out.value)
+
     def update_params(self, theta: torch.Tensor):
         """Upload a new flat parameter vector (same base orbitals) and rebuild
         the walkers' caches at their current configurations."""

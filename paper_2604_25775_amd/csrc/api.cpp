@@ -7,6 +7,8 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <fstream>
+#include <sstream>
 #include <string>
 #include <vector>
 
@@ -63,6 +65,7 @@ struct svmc_ctx {
   bool have_params = false, have_walkers = false;
   bool prepared = false;   // G/P match the current walkers
   bool dets_fresh = false; // rows M, inverses and log|psi| rebuilt since the last move
+  int eloc_slices = 8;     // workgroups per walker in the low-rank E_loc launch
   // parameters
   DevBuf Bpack, embed, bias;
   std::vector<DevBuf> base, W, b;    // per lattice
@@ -137,7 +140,7 @@ static svmc_status check_lattice(const svmc_lattice& l, std::string& why) {
     why = "electron counts must lie in [0, N]";
     return SVMC_ERR_INVALID_ARG;
   }
-  if (std::max(l.n_up, l.n_dn) > 128) { why = "more than 128 electrons per spin"; return SVMC_ERR_UNSUPPORTED; }
+  if (std::max(l.n_up, l.n_dn) > 512) { why = "more than 512 electrons per spin"; return SVMC_ERR_UNSUPPORTED; }
   if (!std::isfinite(l.t) || !std::isfinite(l.tp) || !std::isfinite(l.U)) {
     why = "non-finite Hamiltonian parameter";
     return SVMC_ERR_INVALID_ARG;
@@ -469,7 +472,7 @@ svmc_status svmc_local_energy(svmc_ctx* ctx, svmc_path path, double* eloc, int32
   svmc_status s;
   if (path == SVMC_PATH_LOWRANK) {
     if (!ctx->prepared && (s = prepare(ctx, st))) return s;
-    out.slices = 8;
+    out.slices = ctx->eloc_slices;
     if ((s = ctx->hip(ctx->eloc_part.ensure((size_t)ctx->Wtot * out.slices * 8), "alloc"))) return s;
     out.part = ctx->eloc_part.as<double>();
     return ctx->hip(launch_eloc_lowrank(ctx->prec, md, ctx->lats_dev.as<LatDev>(), ctx->ld.data(),
@@ -635,6 +638,77 @@ svmc_status svmc_walker_flags(svmc_ctx* ctx, int32_t* flags, hipStream_t st) {
   if (!ctx->have_walkers) return ctx->fail(SVMC_ERR_STATE, "no walkers loaded");
   if (!flags) return ctx->fail(SVMC_ERR_INVALID_ARG, "flags is null");
   return ctx->hip(hipMemcpyAsync(flags, ctx->flags.p, (size_t)ctx->Wtot * 4, hipMemcpyDeviceToDevice, st), "flags");
+}
+
+svmc_status svmc_tune(svmc_ctx* ctx, const char* cache_path, int32_t* slices_out, hipStream_t st) {
+  if (!ctx) return SVMC_ERR_INVALID_ARG;
+  if (!ctx->have_walkers) return ctx->fail(SVMC_ERR_STATE, "no walkers loaded");
+  // shape key
+  std::ostringstream key;
+  hipDeviceProp_t prop;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
+    return ctx->fail(SVMC_ERR_HIP, "device query");
+  key << "dev=" << prop.gcnArchName << " L=" << ctx->L << " C=" << ctx->C << " prec=" << ctx->prec;
+  for (size_t l = 0; l < ctx->lats.size(); ++l) {
+    const svmc_lattice& a = ctx->lats[l];
+    key << " lat=" << a.Lx << "x" << a.Ly << ":" << a.pbc_x << a.pbc_y << ":" << a.n_up << "+" << a.n_dn
+        << ":" << (a.tp != 0.0 ? 8 : 4) << ":" << ctx->counts[l];
+  }
+  const std::string k = key.str();
+  if (cache_path) {
+    std::ifstream in(cache_path);
+    std::string line;
+    while (std::getline(in, line)) {
+      const std::string tag = "scalevmc-tune v1 | " + k + " | slices=";
+      if (line.compare(0, tag.size(), tag) == 0) {
+        const int s = std::atoi(line.c_str() + tag.size());
+        if (s >= 1 && s <= 64) {
+          ctx->eloc_slices = s;
+          if (slices_out) *slices_out = s;
+          return SVMC_OK;
+        }
+      }
+    }
+  }
+  svmc_status s;
+  DevBuf eo;
+  if ((s = ctx->hip(eo.ensure((size_t)ctx->Wtot * 8), "alloc"))) return s;
+  hipEvent_t e0, e1;
+  if ((s = ctx->hip(hipEventCreate(&e0), "event")) || (s = ctx->hip(hipEventCreate(&e1), "event"))) return s;
+  const int cand[5] = {1, 2, 4, 8, 16};
+  int best = ctx->eloc_slices;
+  float best_ms = 1e30f;
+  std::ostringstream times;
+  for (int c : cand) {
+    ctx->eloc_slices = c;
+    // one untimed call, then two timed
+    if ((s = svmc_local_energy(ctx, SVMC_PATH_LOWRANK, eo.as<double>(), nullptr, nullptr, nullptr, st))) break;
+    if ((s = ctx->hip(hipEventRecord(e0, st), "event"))) break;
+    for (int r = 0; r < 2 && !s; ++r)
+      s = svmc_local_energy(ctx, SVMC_PATH_LOWRANK, eo.as<double>(), nullptr, nullptr, nullptr, st);
+    if (s) break;
+    if ((s = ctx->hip(hipEventRecord(e1, st), "event")) || (s = ctx->hip(hipEventSynchronize(e1), "event sync")))
+      break;
+    float ms = 0.0f;
+    if ((s = ctx->hip(hipEventElapsedTime(&ms, e0, e1), "event time"))) break;
+    ms *= 0.5f;
+    times << " " << c << ":" << ms;
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = c;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  ctx->eloc_slices = best;
+  if (s) return s;
+  if (slices_out) *slices_out = best;
+  if (cache_path) {
+    std::ofstream out(cache_path, std::ios::app);
+    if (out) out << "scalevmc-tune v1 | " << k << " | slices=" << best << " | ms" << times.str() << "\n";
+  }
+  return SVMC_OK;
 }
 
 }  // extern "C"

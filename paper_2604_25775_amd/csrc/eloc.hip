@@ -27,7 +27,7 @@ __host__ __device__ inline ElocLds eloc_layout(int N, int maxhops, int Gx, int G
   o.occ = 0;
   o.lab = align16(N);
   o.hops = o.lab + align16(4 * N);
-  o.red = o.hops + align16(4 * maxhops);
+  o.red = o.hops + align16(2 * maxhops);
   o.scratch = o.red + 64;
   o.wave_bytes = hop_scratch(Gx, Gy, L, C, tfb).bytes;
   return o;
@@ -49,10 +49,11 @@ SVMC_DEV int block_excl_scan(int v, int* tmp, int& total) {
   return off + incl - v;
 }
 
-// Enumerate the walker's hops into `hops` (code (i << 4) | (spin << 3) | d);
-// returns the count.  At most `cap` codes are stored (a walker with a wrong
-// electron count may have more).  All threads of the block take part.
-SVMC_DEV int enumerate_hops(const LatDev& lt, const int8_t* occ_s, int* hops, int* tmp, int cap) {
+// Enumerate the walker's hops into `hops` (16-bit code (i << 4) | (spin << 3)
+// | d, N <= 4096); returns the count.  At most `cap` codes are stored (a
+// walker with a wrong electron count may have more).  All threads of the
+// block take part.
+SVMC_DEV int enumerate_hops(const LatDev& lt, const int8_t* occ_s, uint16_t* hops, int* tmp, int cap) {
   const int N = lt.N, nd = lt.nd, tid = threadIdx.x;
   const int items = 2 * N;
   const int per = (items + blockDim.x - 1) / blockDim.x;
@@ -81,7 +82,7 @@ SVMC_DEV int enumerate_hops(const LatDev& lt, const int8_t* occ_s, int* hops, in
       if (lt.pbc_x) x = imod(x, lt.Lx); else if (x < 0 || x >= lt.Lx) continue;
       if (lt.pbc_y) y = imod(y, lt.Ly); else if (y < 0 || y >= lt.Ly) continue;
       if ((occ_s[x + lt.Lx * y] >> sp) & 1) continue;
-      if (off < cap) hops[off] = (i << 4) | (sp << 3) | d;
+      if (off < cap) hops[off] = (uint16_t)((i << 4) | (sp << 3) | d);
       ++off;
     }
   }
@@ -118,7 +119,7 @@ __global__ __launch_bounds__(64 * ELOC_NW) __attribute__((amdgpu_waves_per_eu(3)
   const ElocLds lay = eloc_layout(N, lt.maxhops, lt.Gx, lt.Gy, md.L, C, (int)sizeof(Tf));
   int8_t* occ_s = (int8_t*)(smem + lay.occ);
   int16_t* lab_s = (int16_t*)(smem + lay.lab);
-  int* hops = (int*)(smem + lay.hops);
+  uint16_t* hops = (uint16_t*)(smem + lay.hops);
   double* red = (double*)(smem + lay.red);
   char* scratch = smem + lay.scratch;
 

@@ -214,6 +214,114 @@ __global__ __launch_bounds__(256) void k_gj(LatDev lt, Bufs bf, int only_due, in
   }
 }
 
+// Gauss-Jordan inverse of one Slater block for N_sigma > 128 (up to 512):
+// Phi (rows in label order) is gathered into the walker's inverse slot and
+// inverted in place with partial pivoting; rows are swapped physically and
+// the swaps undone as column swaps at the end.  One workgroup of 256 threads
+// per (walker, spin); the pivot row and the pivot column are staged in LDS,
+// each step then updates the whole block (rows in order, columns across
+// threads).  log|det| and its sign come from the pivots and the swaps.
+__global__ __launch_bounds__(256) void k_gj_big(LatDev lt, Bufs bf, int only_due, int refresh_every) {
+  const int sp = blockIdx.y;
+  const long long wl = blockIdx.x;
+  const long long w = lt.w0 + wl;
+  if (only_due && bf.nacc[w] < refresh_every) return;
+  const int n = lt.n[sp], nm = lt.nmax, tid = threadIdx.x;
+  double* ldo = bf.ld + 2 * w + sp;
+  double* sgo = bf.sg + 2 * w + sp;
+  if (n == 0) {
+    if (tid == 0) { *ldo = 0.0; *sgo = 1.0; }
+    return;
+  }
+  if (bf.flags[w] & 8) {
+    if (tid == 0) { *ldo = -INFINITY; *sgo = 0.0; }
+    return;
+  }
+  const double* M = bf.M + lt.m_off + wl * 2LL * lt.N * nm + (long long)sp * lt.N * nm;
+  const int16_t* pos = bf.pos + lt.pos_off + wl * 2LL * nm + sp * nm;
+  double* Y = bf.inv + lt.inv_off + wl * 2LL * nm * nm + (long long)sp * nm * nm;
+  __shared__ double prow[512], fcol[512], rv[256];
+  __shared__ int ri[256];
+  __shared__ int16_t sw[512];
+  for (int k = 0; k < n; ++k) {
+    const double* src = M + (long long)pos[k] * nm;
+    for (int c = tid; c < n; c += 256) Y[(long long)k * nm + c] = src[c];
+  }
+  __syncthreads();
+  double logabs = 0.0, sgn = 1.0;
+  bool singular = false;
+  for (int p = 0; p < n; ++p) {
+    // pivot: largest |Y[r][p]| over r >= p, ties to the lower row
+    double best = -1.0;
+    int bi = n;
+    for (int r = p + tid; r < n; r += 256) {
+      const double v = fabs(Y[(long long)r * nm + p]);
+      if (v > best) { best = v; bi = r; }
+    }
+    rv[tid] = best;
+    ri[tid] = bi;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+      if (tid < o) {
+        const double a = rv[tid], b = rv[tid + o];
+        if (b > a || (b == a && ri[tid + o] < ri[tid])) { rv[tid] = b; ri[tid] = ri[tid + o]; }
+      }
+      __syncthreads();
+    }
+    const int piv = ri[0];
+    const double pmax = rv[0];
+    __syncthreads();
+    if (!(pmax > 0.0)) { singular = true; break; }
+    if (piv != p)
+      for (int c = tid; c < n; c += 256) {
+        const double a = Y[(long long)p * nm + c];
+        Y[(long long)p * nm + c] = Y[(long long)piv * nm + c];
+        Y[(long long)piv * nm + c] = a;
+      }
+    if (tid == 0) sw[p] = (int16_t)piv;
+    __syncthreads();
+    const double pv = Y[(long long)p * nm + p];
+    logabs += log(fabs(pv));
+    if (pv < 0.0) sgn = -sgn;
+    if (piv != p) sgn = -sgn;
+    const double ipv = 1.0 / pv;
+    for (int c = tid; c < n; c += 256) {
+      prow[c] = c == p ? ipv : Y[(long long)p * nm + c] * ipv;
+      fcol[c] = Y[(long long)c * nm + p];
+    }
+    __syncthreads();
+    for (int r = 0; r < n; ++r) {
+      double* yr = Y + (long long)r * nm;
+      const double f = fcol[r];
+      for (int c = tid; c < n; c += 256) {
+        if (r == p) yr[c] = prow[c];
+        else yr[c] = c == p ? -f * prow[p] : fma(-f, prow[c], yr[c]);
+      }
+    }
+    __syncthreads();
+  }
+  if (singular) {
+    if (tid == 0) { *ldo = -INFINITY; *sgo = 0.0; atomicOr(bf.flags + w, 1); }
+    return;
+  }
+  // the row swaps of Phi become column swaps of its inverse, undone in reverse
+  for (int p = n - 1; p >= 0; --p) {
+    const int q = sw[p];
+    if (q != p)
+      for (int r = tid; r < n; r += 256) {
+        const double a = Y[(long long)r * nm + p];
+        Y[(long long)r * nm + p] = Y[(long long)r * nm + q];
+        Y[(long long)r * nm + q] = a;
+      }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    *ldo = logabs;
+    *sgo = sgn;
+    if (!isfinite(logabs)) atomicOr(bf.flags + w, 2);
+  }
+}
+
 // G_s = M_s Phi_s^-1 (rows 0..N-1) and P_s^T = (W_s Phi_s^-1)^T (rows N..N+C-1
 // of the stacked left factor).  64x64 output tiles, 4x4 per thread, K chunks
 // of 16 through LDS.  grid.x = tile + ntiles * (sp + 2 * wl).
@@ -336,6 +444,7 @@ hipError_t launch_gj(const LatDev& lt, const Bufs& bf, hipStream_t st, int only_
   else if (lt.nmax <= 32) hipLaunchKernelGGL((k_gj<2>), grid, dim3(256), 0, st, lt, bf, only_due, refresh_every);
   else if (lt.nmax <= 64) hipLaunchKernelGGL((k_gj<4>), grid, dim3(256), 0, st, lt, bf, only_due, refresh_every);
   else if (lt.nmax <= 128) hipLaunchKernelGGL((k_gj<8>), grid, dim3(256), 0, st, lt, bf, only_due, refresh_every);
+  else if (lt.nmax <= 512) hipLaunchKernelGGL(k_gj_big, grid, dim3(256), 0, st, lt, bf, only_due, refresh_every);
   else return hipErrorInvalidValue;
   return hipGetLastError();
 }

@@ -27,22 +27,25 @@
 namespace svmc {
 
 constexpr int SW_NW = 4;        // wavefronts per workgroup
-constexpr int SWC = 16;         // sites per chunk of the G update
 // nacc value of a walker whose update matrix was singular: its G and P were
 // not updated, so the refresh rebuilds it without a drift check
 constexpr int SW_REBUILD = 0x7fffffff;
 
 struct SweepLds {
-  int occ, lab, pos, misc, pu, rowc, ainv, grow, gu, perm, scratch, bytes;
+  int occ, lab, pos, misc, pu, rowc, ainv, grow, gu, perm, corder, scratch, bytes, swc;
 };
 __host__ __device__ inline int al16(int x) { return (x + 15) & ~15; }
 // LDS of one walker: configuration, labels, positions, per-hop results, the
 // update matrices of one spin (PU [C][C+1], row C of A, A^-1 [C+1][C+1], a
-// chunk of G rows [SWC][nmax] and of G_old' U [SWC][C+1], pivot order) and the
-// hop scratch.
+// chunk of G rows [swc][nmax] and of G_old' U [swc][C+1], pivot order, label
+// order [2 nmax]) and the hop scratch.  swc (sites per chunk of the G update)
+// keeps the G-row chunk at 16 KB or less.
 __host__ __device__ inline SweepLds sweep_layout(int N, int nmax, int Gx, int Gy, int L, int C, int tfb) {
   const int ra = C + 1;
   SweepLds o;
+  o.swc = 16384 / (8 * nmax);
+  if (o.swc > 16) o.swc = 16;
+  if (o.swc < 1) o.swc = 1;
   o.occ = 0;
   o.lab = al16(N);
   o.pos = o.lab + al16(4 * N);
@@ -51,9 +54,10 @@ __host__ __device__ inline SweepLds sweep_layout(int N, int nmax, int Gx, int Gy
   o.rowc = o.pu + al16(8 * C * ra);
   o.ainv = o.rowc + al16(8 * ra);
   o.grow = o.ainv + al16(8 * ra * ra);
-  o.gu = o.grow + al16(8 * SWC * nmax);
-  o.perm = o.gu + al16(8 * SWC * ra);
-  o.scratch = o.perm + al16(4 * ra);
+  o.gu = o.grow + al16(8 * o.swc * nmax);
+  o.perm = o.gu + al16(8 * o.swc * ra);
+  o.corder = o.perm + al16(4 * ra);
+  o.scratch = o.corder + al16(2 * 2 * nmax);
   o.bytes = o.scratch + hop_scratch(Gx, Gy, L, C, tfb).bytes;
   return o;
 }
@@ -149,6 +153,8 @@ __global__ __launch_bounds__(64 * SW_NW) void k_sweep(ModelDev md, const LatDev*
   double* grow = (double*)(smem + lay.grow);
   double* gu = (double*)(smem + lay.gu);
   int* perm = (int*)(smem + lay.perm);
+  int16_t* corder = (int16_t*)(smem + lay.corder);
+  const int swc = lay.swc;
   char* scratch = smem + lay.scratch;
   const HopScratch hsc = hop_scratch(lt.Gx, lt.Gy, md.L, C, (int)sizeof(Tf));
   const int KM = lt.Gx * lt.Gy;
@@ -282,78 +288,98 @@ __global__ __launch_bounds__(64 * SW_NW) void k_sweep(ModelDev md, const LatDev*
       }
       __syncthreads();
       if (misc[6] == 0.0) { fallback = true; continue; }                 // uniform
-      // (3) thread k' < n: z = A^-1 (V Phi^-1)[:, k'] with V Phi^-1 = [P; G[j] - e_k]
-      const bool col = tid < n;
-      double pt[C], z[RA];
-      if (col) {
-#pragma unroll
-        for (int c = 0; c < C; ++c) pt[c] = PTt[(long long)tid * C + c];
-        const double vc = hs ? Gj[tid] - (tid == k ? 1.0 : 0.0) : 0.0;
-#pragma unroll
-        for (int c = 0; c < RA; ++c) {
-          double acc = ainv[c * RA + C] * vc;
-#pragma unroll
-          for (int c2 = 0; c2 < C; ++c2) acc = fma(ainv[c * RA + c2], pt[c2], acc);
-          z[c] = acc;
+      // Columns (labels) go in blocks of NTH, one per thread; with more than
+      // one block the labels of K come last, so that no block changes a
+      // column G[:, k_a] that a later block still reads through G_old' U.
+      const int nblk = (n + NTH - 1) / NTH;
+      if (nblk > 1) {
+        for (int kk = tid; kk < n; kk += NTH) corder[kk] = 0;
+        __syncthreads();
+        for (int a = tid; a < r; a += NTH) corder[kl[a] & 0xffff] = 1;
+        __syncthreads();
+        if (tid == 0) {
+          int lo = 0, hi = n;
+          for (int kk = 0; kk < n; ++kk) {
+            if (corder[kk] == 0) corder[n + lo++] = (int16_t)kk;
+            else corder[n + --hi] = (int16_t)kk;
+          }
         }
+        __syncthreads();
       }
-      __syncthreads();            // every read of G[j] done before G changes
-      // (4) G' = G_old' - (G_old' U) z, G_old' = G + D P on the box; SWC sites at a time
-      for (int s0 = 0; s0 < N; s0 += SWC) {
-        const int ns = min(SWC, N - s0);
-        for (int e2 = tid; e2 < ns * n; e2 += NTH) {
-          const int sl = e2 / n, kk = e2 % n;
-          grow[sl * nm + kk] = Gt[(long long)(s0 + sl) * nm + kk];
-        }
-        __syncthreads();
-        for (int e2 = tid; e2 < ns * RA; e2 += NTH) {
-          const int sl = e2 / RA, c = e2 % RA;
-          const int s = s0 + sl;
-          double v = 0.0;
-          if (c < C) {
-            for (int a = 0; a < r; ++a) {
-              const int ka = kl[a] & 0xffff, ma = kl[a] >> 16;
-              v = fma(grow[sl * nm + ka], (double)Dbuf[ma * SD + c], v);
-            }
-          } else if (hs) {
-            v = grow[sl * nm + k];
-          }
-          const int mb = box_index(lt, s, olx, owx, oly, owy);
-          if (mb >= 0 && (c < C || hs)) {
-            const typename DType<P>::type* Dm = Dbuf + mb * SD;
-            for (int c2 = 0; c2 < C; ++c2) v = fma((double)Dm[c2], pu[c2 * RA + c], v);
-          }
-          gu[sl * RA + c] = v;
-        }
-        __syncthreads();
+      for (int b = 0; b < nblk; ++b) {
+        const int slot = b * NTH + tid;
+        const bool col = slot < n;
+        const int kc = !col ? 0 : (nblk > 1 ? (int)corder[n + slot] : slot);
+        // (3) z = A^-1 (V Phi^-1)[:, kc] with V Phi^-1 = [P; G[j] - e_k]
+        double pt[C], z[RA];
         if (col) {
-          for (int sl = 0; sl < ns; ++sl) {
+#pragma unroll
+          for (int c = 0; c < C; ++c) pt[c] = PTt[(long long)kc * C + c];
+          const double vc = hs ? Gj[kc] - (kc == k ? 1.0 : 0.0) : 0.0;
+#pragma unroll
+          for (int c = 0; c < RA; ++c) {
+            double acc = ainv[c * RA + C] * vc;
+#pragma unroll
+            for (int c2 = 0; c2 < C; ++c2) acc = fma(ainv[c * RA + c2], pt[c2], acc);
+            z[c] = acc;
+          }
+        }
+        __syncthreads();            // every read of G[j] done before G changes
+        // (4) G' = G_old' - (G_old' U) z, G_old' = G + D P on the box; swc sites at a time
+        for (int s0 = 0; s0 < N; s0 += swc) {
+          const int ns = min(swc, N - s0);
+          for (int sl = 0; sl < ns; ++sl)
+            for (int kk = tid; kk < n; kk += NTH) grow[sl * nm + kk] = Gt[(long long)(s0 + sl) * nm + kk];
+          __syncthreads();
+          for (int e2 = tid; e2 < ns * RA; e2 += NTH) {
+            const int sl = e2 / RA, c = e2 - sl * RA;
             const int s = s0 + sl;
-            double v = grow[sl * nm + tid];
-            const int mb = box_index(lt, s, olx, owx, oly, owy);
-            if (mb >= 0) {
-              const typename DType<P>::type* Dm = Dbuf + mb * SD;
-#pragma unroll
-              for (int c = 0; c < C; ++c) v = fma((double)Dm[c], pt[c], v);
+            double v = 0.0;
+            if (c < C) {
+              for (int a = 0; a < r; ++a) {
+                const int ka = kl[a] & 0xffff, ma = kl[a] >> 16;
+                v = fma(grow[sl * nm + ka], (double)Dbuf[ma * SD + c], v);
+              }
+            } else if (hs) {
+              v = grow[sl * nm + k];
             }
+            const int mb = box_index(lt, s, olx, owx, oly, owy);
+            if (mb >= 0 && (c < C || hs)) {
+              const typename DType<P>::type* Dm = Dbuf + mb * SD;
+              for (int c2 = 0; c2 < C; ++c2) v = fma((double)Dm[c2], pu[c2 * RA + c], v);
+            }
+            gu[sl * RA + c] = v;
+          }
+          __syncthreads();
+          if (col) {
+            for (int sl = 0; sl < ns; ++sl) {
+              const int s = s0 + sl;
+              double v = grow[sl * nm + kc];
+              const int mb = box_index(lt, s, olx, owx, oly, owy);
+              if (mb >= 0) {
+                const typename DType<P>::type* Dm = Dbuf + mb * SD;
 #pragma unroll
-            for (int c = 0; c < RA; ++c) v = fma(-gu[sl * RA + c], z[c], v);
-            Gt[(long long)s * nm + tid] = v;
+                for (int c = 0; c < C; ++c) v = fma((double)Dm[c], pt[c], v);
+              }
+#pragma unroll
+              for (int c = 0; c < RA; ++c) v = fma(-gu[sl * RA + c], z[c], v);
+              Gt[(long long)s * nm + kc] = v;
+            }
+          }
+          __syncthreads();
+        }
+        // (5) P' = P - (P U) z
+        if (col) {
+#pragma unroll
+          for (int cp = 0; cp < C; ++cp) {
+            double v = pt[cp];
+#pragma unroll
+            for (int c = 0; c < RA; ++c) v = fma(-pu[cp * RA + c], z[c], v);
+            PTt[(long long)kc * C + cp] = v;
           }
         }
         __syncthreads();
       }
-      // (5) P' = P - (P U) z
-      if (col) {
-#pragma unroll
-        for (int cp = 0; cp < C; ++cp) {
-          double v = pt[cp];
-#pragma unroll
-          for (int c = 0; c < RA; ++c) v = fma(-pu[cp * RA + c], z[c], v);
-          PTt[(long long)tid * C + cp] = v;
-        }
-      }
-      __syncthreads();
     }
     // ---- configuration, labels, log|psi|
     if (tid == 0) {
