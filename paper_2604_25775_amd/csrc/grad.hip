@@ -68,7 +68,7 @@ __global__ __launch_bounds__(256) void k_grad(const LatDev* __restrict__ lats, i
 
   // ---- projection and dH_L
   for (int sp = 0; sp < 2; ++sp) {
-    const int n = lt.n[sp];
+    const int n = sp == 0 ? n0 : n1;
     const double* Y = bf.inv + lt.inv_off + wl * 2LL * nm * nm + (long long)sp * nm * nm;
     const int16_t* ps = pos + sp * nm;
     double* dW = row + lt.poff + (sp ? (long long)C * n0 : 0LL);

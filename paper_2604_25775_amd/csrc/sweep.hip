@@ -11,10 +11,13 @@
 //             U = [rows K carry D(m_a) (C columns), e_k for the mover],
 //             V = [W; M[j] - M[i]],
 //           so with A = I + V Phi^-1 U ((C+1) x (C+1), det A = ratio) and
-//           Z = A^-1 V Phi^-1 (V Phi^-1 = [P; G[j] - e_k]):
+//           Z = A^-1 V Phi^-1 (V Phi^-1 = [P; G[j] - e_k], column w_k):
 //             G' = G_old' - (G_old' U) Z,   P' = P - (P U) Z,
-//           where G_old' = M' Phi^-1 = G + D P on the box sites.  log|psi| and
-//           the sign take the ratio per spin.
+//           where G_old' = M' Phi^-1 = G + D P on the box sites.  Evaluated
+//           as G'[s][k] = G[s][k] + e_s . w_k with one coefficient vector per
+//           site, e_s = [[s in box] D(s) - A^-T (G_old' U)[s]; -(G_old' U)[s]
+//           . A^-1[:, C]], and P' = P - (PU A^-1) w_k.  log|psi| and the sign
+//           take the ratio per spin.
 //
 // Proposal q of walker w uses one Philox4x64-10 block (key (seed, 0), counter
 // (w, step0 + q, 0, 0)), written from the published definition (Salmon et
@@ -27,24 +30,26 @@
 namespace svmc {
 
 constexpr int SW_NW = 4;        // wavefronts per workgroup
+constexpr int SWC_MAX = 16;     // most sites per chunk of the G update
 // nacc value of a walker whose update matrix was singular: its G and P were
 // not updated, so the refresh rebuilds it without a drift check
 constexpr int SW_REBUILD = 0x7fffffff;
 
 struct SweepLds {
-  int occ, lab, pos, misc, pu, rowc, ainv, grow, gu, perm, corder, scratch, bytes, swc;
+  int occ, lab, pos, misc, pu, rowc, ainv, qm, grow, gu, ef, mbs, perm, corder, pk, gk, mk, scratch, bytes, swc;
 };
 __host__ __device__ inline int al16(int x) { return (x + 15) & ~15; }
 // LDS of one walker: configuration, labels, positions, per-hop results, the
-// update matrices of one spin (PU [C][C+1], row C of A, A^-1 [C+1][C+1], a
-// chunk of G rows [swc][nmax] and of G_old' U [swc][C+1], pivot order, label
-// order [2 nmax]) and the hop scratch.  swc (sites per chunk of the G update)
+// update matrices of one spin (PU [C][C+1], row C of A, A^-1 [C+1][C+1],
+// Q = PU A^-1 [C][C+1], a chunk of G rows [swc][nmax], of G_old' U and of
+// the site coefficients e_s [swc][C+1], box indices of the chunk, pivot
+// order, label order [2 nmax]) and the hop scratch.  swc (sites per chunk of the G update)
 // keeps the G-row chunk at 16 KB or less.
 __host__ __device__ inline SweepLds sweep_layout(int N, int nmax, int Gx, int Gy, int L, int C, int tfb) {
   const int ra = C + 1;
   SweepLds o;
   o.swc = 16384 / (8 * nmax);
-  if (o.swc > 16) o.swc = 16;
+  if (o.swc > SWC_MAX) o.swc = SWC_MAX;
   if (o.swc < 1) o.swc = 1;
   o.occ = 0;
   o.lab = al16(N);
@@ -53,11 +58,19 @@ __host__ __device__ inline SweepLds sweep_layout(int N, int nmax, int Gx, int Gy
   o.pu = o.misc + 128;
   o.rowc = o.pu + al16(8 * C * ra);
   o.ainv = o.rowc + al16(8 * ra);
-  o.grow = o.ainv + al16(8 * ra * ra);
+  o.qm = o.ainv + al16(8 * ra * ra);
+  o.grow = o.qm + al16(8 * C * ra);
   o.gu = o.grow + al16(8 * o.swc * nmax);
-  o.perm = o.gu + al16(8 * o.swc * ra);
+  o.ef = o.gu + al16(8 * o.swc * ra);
+  o.mbs = o.ef + al16(8 * o.swc * ra);
+  o.perm = o.mbs + al16(4 * o.swc);
   o.corder = o.perm + al16(4 * ra);
-  o.scratch = o.corder + al16(2 * 2 * nmax);
+  // changed rows per spin: at most the layer-L box, (2L+2)^2 sites capped by the grid
+  const int kmax = (Gx < 2 * L + 2 ? Gx : 2 * L + 2) * (Gy < 2 * L + 2 ? Gy : 2 * L + 2);
+  o.pk = o.corder + al16(2 * 2 * nmax);
+  o.gk = o.pk + al16(8 * kmax * C);
+  o.mk = o.gk + al16(8 * kmax);
+  o.scratch = o.mk + al16(4 * kmax);
   o.bytes = o.scratch + hop_scratch(Gx, Gy, L, C, tfb).bytes;
   return o;
 }
@@ -154,6 +167,12 @@ __global__ __launch_bounds__(64 * SW_NW) void k_sweep(ModelDev md, const LatDev*
   double* gu = (double*)(smem + lay.gu);
   int* perm = (int*)(smem + lay.perm);
   int16_t* corder = (int16_t*)(smem + lay.corder);
+  double* qm = (double*)(smem + lay.qm);
+  double* pk = (double*)(smem + lay.pk);
+  double* gk = (double*)(smem + lay.gk);
+  int* mk = (int*)(smem + lay.mk);
+  double* ef = (double*)(smem + lay.ef);
+  int* mbs = (int*)(smem + lay.mbs);
   const int swc = lay.swc;
   char* scratch = smem + lay.scratch;
   const HopScratch hsc = hop_scratch(lt.Gx, lt.Gy, md.L, C, (int)sizeof(Tf));
@@ -171,7 +190,10 @@ __global__ __launch_bounds__(64 * SW_NW) void k_sweep(ModelDev md, const LatDev*
   Tf* featw = (Tf*)bf.feat + lt.feat_off + wl * (long long)md.L * N * C;
   double* Gw = bf.G + lt.g_off + wl * 2LL * N * nm;
   double* PTw = bf.PT + lt.pt_off + wl * 2LL * nm * C;
-  const int ne = lt.n[0] + lt.n[1];
+  // electron counts as scalars: indexing the local descriptor copy with a
+  // runtime spin would move it to scratch memory
+  const int n_up = lt.n[0], n_dn = lt.n[1];
+  const int ne = n_up + n_dn;
   int nacc = bf.nacc[w];
   long long accepted = 0;
   bool stop_refresh = false;
@@ -184,8 +206,8 @@ __global__ __launch_bounds__(64 * SW_NW) void k_sweep(ModelDev md, const LatDev*
     const int e = (int)__umul64hi(ctr[0], (unsigned long long)ne);
     const int d = (int)(ctr[1] >> 62);
     const double u = (double)(ctr[2] >> 11) * 0x1.0p-53;
-    const int sp = e < lt.n[0] ? 0 : 1;
-    const int k = sp == 0 ? e : e - lt.n[0];
+    const int sp = e < n_up ? 0 : 1;
+    const int k = sp == 0 ? e : e - n_up;
     const int i = uniform_i(pos_s[sp * nm + k]);
     const int bit = 1 << sp;
     {
@@ -220,7 +242,7 @@ __global__ __launch_bounds__(64 * SW_NW) void k_sweep(ModelDev md, const LatDev*
     hop_features<P, C, NW>(md, lt, g, occ_s, featw, featw, scratch, hsc, olx, owx, oly, owy);
     bool fallback = false;
     for (int tau = 0; tau < 2; ++tau) {
-      const int n = lt.n[tau];
+      const int n = tau == 0 ? n_up : n_dn;
       if (n == 0) continue;
       const int r = (int)misc[2 + tau];
       const bool hs = tau == sp;
@@ -229,16 +251,38 @@ __global__ __launch_bounds__(64 * SW_NW) void k_sweep(ModelDev md, const LatDev*
       double* Gt = Gw + (long long)tau * N * nm;
       double* PTt = PTw + (long long)tau * nm * C;
       const double* Gj = Gt + (long long)g.j * nm;
+      // (0) stage the changed labels' P^T rows, G[j] entries and box rows:
+      //     pk[a][c] = P^T[k_a][c], gk[a] = G[j][k_a] - [k_a = k], mk[a] = m_a
+      for (int a = tid; a < r; a += NTH) {
+        const int e = kl[a];
+        mk[a] = (e >> 16) * SD;
+        gk[a] = hs ? Gj[e & 0xffff] - ((e & 0xffff) == k ? 1.0 : 0.0) : 0.0;
+      }
+      {
+        const int tot = r * C;
+        for (int e0 = 0; e0 < tot; e0 += NTH * 4) {
+          double v[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int e2 = e0 + NTH * u + tid;
+            v[u] = e2 < tot ? PTt[(long long)(kl[e2 / C] & 0xffff) * C + (e2 % C)] : 0.0;
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int e2 = e0 + NTH * u + tid;
+            if (e2 < tot) pk[e2] = v[u];
+          }
+        }
+      }
+      __syncthreads();
       // (1) PU = P U: PU[c'][c] = sum_a P^T[k_a][c'] D(m_a)[c] (c < C), PU[c'][C] = P^T[k][c'];
       //     row C of A - I (hop spin): sum_a (G[j][k_a] - [k_a = k]) D(m_a)[c], G[j][k] - 1
       for (int e2 = tid; e2 < C * RA; e2 += NTH) {
-        const int cp = e2 / RA, c = e2 % RA;
+        const int cp = e2 / RA, c = e2 - cp * RA;
         double v = 0.0;
         if (c < C) {
-          for (int a = 0; a < r; ++a) {
-            const int ka = kl[a] & 0xffff, ma = kl[a] >> 16;
-            v = fma(PTt[(long long)ka * C + cp], (double)Dbuf[ma * SD + c], v);
-          }
+#pragma unroll 8
+          for (int a = 0; a < r; ++a) v = fma(pk[a * C + cp], (double)Dbuf[mk[a] + c], v);
         } else if (hs) {
           v = PTt[(long long)k * C + cp];
         }
@@ -248,10 +292,8 @@ __global__ __launch_bounds__(64 * SW_NW) void k_sweep(ModelDev md, const LatDev*
         double v = 0.0;
         if (hs) {
           if (c < C) {
-            for (int a = 0; a < r; ++a) {
-              const int ka = kl[a] & 0xffff, ma = kl[a] >> 16;
-              v = fma(Gj[ka] - (ka == k ? 1.0 : 0.0), (double)Dbuf[ma * SD + c], v);
-            }
+#pragma unroll 8
+            for (int a = 0; a < r; ++a) v = fma(gk[a], (double)Dbuf[mk[a] + c], v);
           } else {
             v = Gj[k] - 1.0;
           }
@@ -288,6 +330,13 @@ __global__ __launch_bounds__(64 * SW_NW) void k_sweep(ModelDev md, const LatDev*
       }
       __syncthreads();
       if (misc[6] == 0.0) { fallback = true; continue; }                 // uniform
+      // Q = PU A^-1 (C x RA): P' = P - PU A^-1 w_k = P - Q w_k
+      for (int e2 = tid; e2 < C * RA; e2 += NTH) {
+        const int cp = e2 / RA, c = e2 - cp * RA;
+        double v = 0.0;
+        for (int c1 = 0; c1 < R; ++c1) v = fma(pu[cp * RA + c1], ainv[c1 * RA + c], v);
+        qm[e2] = v;
+      }
       // Columns (labels) go in blocks of NTH, one per thread; with more than
       // one block the labels of K come last, so that no block changes a
       // column G[:, k_a] that a later block still reads through G_old' U.
@@ -304,46 +353,48 @@ __global__ __launch_bounds__(64 * SW_NW) void k_sweep(ModelDev md, const LatDev*
             else corder[n + --hi] = (int16_t)kk;
           }
         }
-        __syncthreads();
       }
+      __syncthreads();
       for (int b = 0; b < nblk; ++b) {
         const int slot = b * NTH + tid;
         const bool col = slot < n;
         const int kc = !col ? 0 : (nblk > 1 ? (int)corder[n + slot] : slot);
-        // (3) z = A^-1 (V Phi^-1)[:, kc] with V Phi^-1 = [P; G[j] - e_k]
-        double pt[C], z[RA];
+        // w_kc = (V Phi^-1)[:, kc] = [P^T[kc]; G[j][kc] - [kc = k]]
+        double pt[C];
+        double vc = 0.0;
         if (col) {
 #pragma unroll
           for (int c = 0; c < C; ++c) pt[c] = PTt[(long long)kc * C + c];
-          const double vc = hs ? Gj[kc] - (kc == k ? 1.0 : 0.0) : 0.0;
-#pragma unroll
-          for (int c = 0; c < RA; ++c) {
-            double acc = ainv[c * RA + C] * vc;
-#pragma unroll
-            for (int c2 = 0; c2 < C; ++c2) acc = fma(ainv[c * RA + c2], pt[c2], acc);
-            z[c] = acc;
-          }
+          if (hs) vc = Gj[kc] - (kc == k ? 1.0 : 0.0);
         }
         __syncthreads();            // every read of G[j] done before G changes
-        // (4) G' = G_old' - (G_old' U) z, G_old' = G + D P on the box; swc sites at a time
+        // G' = G_old' - (G_old' U) A^-1 w = G + e_s . w  (swc sites at a time),
+        //   e_s = [[s in box] D(s) - A^-1^T GU[s];  -GU[s] . A^-1[:, C]]
         for (int s0 = 0; s0 < N; s0 += swc) {
           const int ns = min(swc, N - s0);
-          for (int sl = 0; sl < ns; ++sl)
-            for (int kk = tid; kk < n; kk += NTH) grow[sl * nm + kk] = Gt[(long long)(s0 + sl) * nm + kk];
+          // stage the chunk's G rows: every load of a thread in flight at once
+          for (int kk = tid; kk < n; kk += NTH) {
+            double v[SWC_MAX];
+#pragma unroll
+            for (int sl = 0; sl < SWC_MAX; ++sl)
+              if (sl < ns) v[sl] = Gt[(long long)(s0 + sl) * nm + kk];
+#pragma unroll
+            for (int sl = 0; sl < SWC_MAX; ++sl)
+              if (sl < ns) grow[sl * nm + kk] = v[sl];
+          }
+          if (tid < ns) mbs[tid] = box_index(lt, s0 + tid, olx, owx, oly, owy);
           __syncthreads();
           for (int e2 = tid; e2 < ns * RA; e2 += NTH) {
             const int sl = e2 / RA, c = e2 - sl * RA;
-            const int s = s0 + sl;
             double v = 0.0;
             if (c < C) {
-              for (int a = 0; a < r; ++a) {
-                const int ka = kl[a] & 0xffff, ma = kl[a] >> 16;
-                v = fma(grow[sl * nm + ka], (double)Dbuf[ma * SD + c], v);
-              }
+              const double* gr = grow + sl * nm;
+#pragma unroll 8
+              for (int a = 0; a < r; ++a) v = fma(gr[kl[a] & 0xffff], (double)Dbuf[mk[a] + c], v);
             } else if (hs) {
               v = grow[sl * nm + k];
             }
-            const int mb = box_index(lt, s, olx, owx, oly, owy);
+            const int mb = mbs[sl];
             if (mb >= 0 && (c < C || hs)) {
               const typename DType<P>::type* Dm = Dbuf + mb * SD;
               for (int c2 = 0; c2 < C; ++c2) v = fma((double)Dm[c2], pu[c2 * RA + c], v);
@@ -351,30 +402,33 @@ __global__ __launch_bounds__(64 * SW_NW) void k_sweep(ModelDev md, const LatDev*
             gu[sl * RA + c] = v;
           }
           __syncthreads();
+          for (int e2 = tid; e2 < ns * RA; e2 += NTH) {
+            const int sl = e2 / RA, c2 = e2 - sl * RA;
+            const int mb = mbs[sl];
+            double v = (c2 < C && mb >= 0) ? (double)Dbuf[mb * SD + c2] : 0.0;
+            for (int c = 0; c < R; ++c) v = fma(-gu[sl * RA + c], ainv[c * RA + c2], v);
+            ef[sl * RA + c2] = v;
+          }
+          __syncthreads();
           if (col) {
             for (int sl = 0; sl < ns; ++sl) {
-              const int s = s0 + sl;
-              double v = grow[sl * nm + kc];
-              const int mb = box_index(lt, s, olx, owx, oly, owy);
-              if (mb >= 0) {
-                const typename DType<P>::type* Dm = Dbuf + mb * SD;
+              const double* es = ef + sl * RA;
+              double v = fma(es[C], vc, grow[sl * nm + kc]);
 #pragma unroll
-                for (int c = 0; c < C; ++c) v = fma((double)Dm[c], pt[c], v);
-              }
-#pragma unroll
-              for (int c = 0; c < RA; ++c) v = fma(-gu[sl * RA + c], z[c], v);
-              Gt[(long long)s * nm + kc] = v;
+              for (int c = 0; c < C; ++c) v = fma(es[c], pt[c], v);
+              Gt[(long long)(s0 + sl) * nm + kc] = v;
             }
           }
           __syncthreads();
         }
-        // (5) P' = P - (P U) z
+        // P' = P - Q w
         if (col) {
 #pragma unroll
           for (int cp = 0; cp < C; ++cp) {
-            double v = pt[cp];
+            const double* qr = qm + cp * RA;
+            double v = fma(-qr[C], vc, pt[cp]);
 #pragma unroll
-            for (int c = 0; c < RA; ++c) v = fma(-pu[cp * RA + c], z[c], v);
+            for (int c = 0; c < C; ++c) v = fma(-qr[c], pt[c], v);
             PTt[(long long)kc * C + cp] = v;
           }
         }
