@@ -190,6 +190,22 @@ svmc_status svmc_local_energy(svmc_ctx* ctx, svmc_path path, double* eloc,
 svmc_status svmc_sweep(svmc_ctx* ctx, int32_t n_sweeps, uint64_t seed,
                        uint64_t step0, int64_t* n_accept, hipStream_t stream);
 
+/* Form of svmc_sweep that can be recorded into a HIP graph and replayed: no
+ * host synchronisation, no allocation, no memset node.  Runs `rounds` rounds
+ * of [sweep kernel: each walker proposes until it finishes or pauses for a
+ * refresh; masked FP64 refresh of the paused walkers].  svmc_sweep_rounds()
+ * gives a number of rounds that lets every walker finish unless an update
+ * matrix turns singular (each such walker needs one more round); walkers not
+ * done after the last round keep the configuration they reached.  step0 is
+ * read at run time from the device scalar *step0_dev (uint64), so replays can
+ * advance the chain by updating it between replays.  The first call must be
+ * made outside a capture (it allocates the progress buffer).  Same chain as
+ * svmc_sweep for the same seed and step0 when it runs to completion. */
+svmc_status svmc_sweep_async(svmc_ctx* ctx, int32_t n_sweeps, uint64_t seed,
+                             const uint64_t* step0_dev, int64_t* n_accept,
+                             int32_t rounds, hipStream_t stream);
+int32_t svmc_sweep_rounds(const svmc_ctx* ctx, int32_t n_sweeps);
+
 /* Rebuild every walker's Slater inverse, log|psi| and low-rank precompute in
  * FP64 from the cached features (when G/P were current, SVMC_W_DRIFT is set
  * first where G had drifted by more than 1e-8 on its occupied rows). */

@@ -526,6 +526,7 @@ svmc_status svmc_sweep(svmc_ctx* ctx, int32_t n_sweeps, uint64_t seed, uint64_t 
   SweepArgs sa;
   sa.seed = seed;
   sa.step0 = step0;
+  sa.step0_dev = nullptr;
   sa.n_sweeps = n_sweeps;
   sa.refresh_every = every;
   sa.n_accept = n_accept;
@@ -557,6 +558,68 @@ svmc_status svmc_sweep(svmc_ctx* ctx, int32_t n_sweeps, uint64_t seed, uint64_t 
     }
   }
   return SVMC_OK;
+}
+
+svmc_status svmc_sweep_async(svmc_ctx* ctx, int32_t n_sweeps, uint64_t seed, const uint64_t* step0_dev,
+                             int64_t* n_accept, int32_t rounds, hipStream_t st) {
+  if (!ctx) return SVMC_ERR_INVALID_ARG;
+  if (!ctx->have_walkers) return ctx->fail(SVMC_ERR_STATE, "no walkers loaded");
+  if (n_sweeps < 0 || rounds < 0) return ctx->fail(SVMC_ERR_INVALID_ARG, "negative sweep or round count");
+  if (!step0_dev) return ctx->fail(SVMC_ERR_INVALID_ARG, "step0_dev is null");
+  const int every = ctx->model.refresh_every;
+  const size_t smem = sweep_smem(ctx->ld.data(), (int)ctx->ld.size(), ctx->prec, ctx->L, ctx->C);
+  if (smem > 160 * 1024) return ctx->fail(SVMC_ERR_UNSUPPORTED, "sweep workspace exceeds 160 KiB of LDS");
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(st, &cap) != hipSuccess) return ctx->fail(SVMC_ERR_HIP, "capture query");
+  const bool capturing = cap != hipStreamCaptureStatusNone;
+  svmc_status s;
+  if (ctx->sw_prog.bytes < (size_t)ctx->Wtot * 8 || !ctx->sw_prog.p) {
+    if (capturing) return ctx->fail(SVMC_ERR_STATE, "call svmc_sweep_async once outside capture first (allocates)");
+    if ((s = ctx->hip(ctx->sw_prog.ensure((size_t)ctx->Wtot * 8), "alloc"))) return s;
+  }
+  // G and P must be current when the work runs: a captured precompute would
+  // be replayed against stale inverses, so capture needs them ready
+  if (!ctx->prepared) {
+    if (capturing) return ctx->fail(SVMC_ERR_STATE, "call svmc_prepare before capturing svmc_sweep_async");
+    if ((s = prepare(ctx, st))) return s;
+  }
+  if (n_sweeps == 0 || rounds == 0) return SVMC_OK;
+  SweepArgs sa;
+  sa.seed = seed;
+  sa.step0 = 0;
+  sa.step0_dev = (const unsigned long long*)step0_dev;
+  sa.n_sweeps = n_sweeps;
+  sa.refresh_every = every;
+  sa.n_accept = n_accept;
+  sa.prog = ctx->sw_prog.as<int64_t>();
+  sa.paused = nullptr;
+  const Bufs bf = ctx->bufs();
+  const ModelDev md = ctx->mdev();
+  ctx->dets_fresh = false;
+  if ((s = ctx->hip(launch_fill_i64(sa.prog, ctx->Wtot, 0, st), "progress reset"))) return s;
+  for (int r = 0; r < rounds; ++r) {
+    if ((s = ctx->hip(launch_sweep(ctx->prec, md, ctx->lats_dev.as<LatDev>(), ctx->ld.data(), (int)ctx->ld.size(),
+                                   ctx->Wtot, bf, sa, st),
+                      "sweep")))
+      return s;
+    for (auto& lt : ctx->ld) {
+      if ((s = ctx->hip(launch_drift(lt, bf, 1, every, st), "drift check")) ||
+          (s = ctx->hip(launch_rows(ctx->prec, lt, bf, ctx->L, ctx->C, st, 1, every), "rows")) ||
+          (s = ctx->hip(launch_gj(lt, bf, st, 1, every), "inverse")) ||
+          (s = ctx->hip(launch_gp(lt, bf, ctx->C, st, 1, every), "G/P precompute")) ||
+          (s = ctx->hip(launch_clear_nacc(lt, bf, every, st), "clear")))
+        return s;
+    }
+  }
+  return SVMC_OK;
+}
+
+int32_t svmc_sweep_rounds(const svmc_ctx* ctx, int32_t n_sweeps) {
+  if (!ctx || n_sweeps < 0) return -1;
+  long long nmax = 0;
+  for (auto& l : ctx->lats) nmax = std::max(nmax, (long long)l.Lx * l.Ly);
+  const long long every = std::max(1, ctx->model.refresh_every);
+  return (int32_t)std::min<long long>(1 << 20, (n_sweeps * nmax + every - 1) / every + 1);
 }
 
 svmc_status svmc_get_state(svmc_ctx* ctx, int8_t* occ, int16_t* pos, hipStream_t st) {

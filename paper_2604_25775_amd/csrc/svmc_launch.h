@@ -43,16 +43,18 @@ hipError_t launch_eloc_lowrank(int prec, const ModelDev& md, const LatDev* lats_
 // sweep.hip: Metropolis sweeps with Woodbury updates
 struct SweepArgs {
   unsigned long long seed, step0;
+  const unsigned long long* step0_dev;   // if non-null, step0 is read from here
   int n_sweeps, refresh_every;
   int64_t* n_accept;     // [W] incremented by accepted moves (may be null)
   int64_t* prog;         // [W] next proposal index of each walker
-  int* paused;           // number of walkers that stopped for a refresh
+  int* paused;           // number of walkers that stopped for a refresh (may be null)
 };
 size_t sweep_smem(const LatDev* lats_host, int nlats, int prec, int L, int C);
 hipError_t launch_sweep(int prec, const ModelDev& md, const LatDev* lats_dev, const LatDev* lats_host, int nlats,
                         long long W, const Bufs& bf, const SweepArgs& sa, hipStream_t st);
 hipError_t launch_drift(const LatDev& lt, const Bufs& bf, int only_due, int refresh_every, hipStream_t st);
 hipError_t launch_clear_nacc(const LatDev& lt, const Bufs& bf, int refresh_every, hipStream_t st);
+hipError_t launch_fill_i64(int64_t* p, long long n, int64_t v, hipStream_t st);
 
 // grad.hip: d log|psi| / d theta, one row per walker
 struct GradArgs {

@@ -151,6 +151,7 @@ __global__ __launch_bounds__(64 * SW_NW) void k_sweep(ModelDev md, const LatDev*
   const long long qend = (long long)sa.n_sweeps * N;
   long long q = sa.prog[w];
   if (q >= qend) return;
+  const unsigned long long step0 = sa.step0_dev ? *sa.step0_dev : sa.step0;
   if (bf.flags[w] & (1 | 2 | 8)) {
     if (tid == 0) sa.prog[w] = qend;
     return;
@@ -201,7 +202,7 @@ __global__ __launch_bounds__(64 * SW_NW) void k_sweep(ModelDev md, const LatDev*
 
   for (; q < qend && ne > 0; ++q) {
     // ---- draw (identical in every thread)
-    unsigned long long ctr[4] = {(unsigned long long)w, sa.step0 + (unsigned long long)q, 0ULL, 0ULL};
+    unsigned long long ctr[4] = {(unsigned long long)w, step0 + (unsigned long long)q, 0ULL, 0ULL};
     philox4x64_10(ctr, sa.seed, 0ULL);
     const int e = (int)__umul64hi(ctr[0], (unsigned long long)ne);
     const int d = (int)(ctr[1] >> 62);
@@ -466,7 +467,7 @@ __global__ __launch_bounds__(64 * SW_NW) void k_sweep(ModelDev md, const LatDev*
     sa.prog[w] = (ne > 0) ? q : qend;
     bf.nacc[w] = nacc;
     if (sa.n_accept) sa.n_accept[w] += accepted;
-    if (stop_refresh) atomicAdd(sa.paused, 1);
+    if (stop_refresh && sa.paused) atomicAdd(sa.paused, 1);
   }
 }
 
@@ -522,6 +523,17 @@ __global__ void k_clear_nacc(LatDev lt, Bufs bf, int refresh_every) {
   if (wl >= lt.nw) return;
   const long long w = lt.w0 + wl;
   if (bf.nacc[w] >= refresh_every) bf.nacc[w] = 0;
+}
+
+__global__ void k_fill_i64(int64_t* p, long long n, int64_t v) {
+  const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+hipError_t launch_fill_i64(int64_t* p, long long n, int64_t v, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_i64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, n, v);
+  return hipGetLastError();
 }
 
 size_t sweep_smem(const LatDev* lats, int nlats, int prec, int L, int C) {
