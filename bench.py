@@ -129,6 +129,29 @@ def lowrank_flops(lat, occ: np.ndarray, L: int, C: int):
 _CPU = {}
 
 
+def ctx_hops(lat, occ):
+    """Number of connected configurations (hops) per walker, counted on the host."""
+    W, N = occ.shape
+    nd = 8 if lat.tp != 0.0 else 4
+    DX = [1, -1, 0, 0, 1, 1, -1, -1]
+    DY = [0, 0, 1, -1, 1, -1, 1, -1]
+    xs, ys = np.meshgrid(np.arange(lat.Lx), np.arange(lat.Ly))
+    xs, ys = xs.ravel(), ys.ravel()
+    cnt = np.zeros(W, np.int64)
+    for sp in (0, 1):
+        mine = ((occ >> sp) & 1).astype(bool)
+        for d in range(nd):
+            xj, yj = xs + DX[d], ys + DY[d]
+            ok = np.ones(N, bool)
+            if not lat.pbc_x:
+                ok &= (xj >= 0) & (xj < lat.Lx)
+            if not lat.pbc_y:
+                ok &= (yj >= 0) & (yj < lat.Ly)
+            j = (xj % lat.Lx) + lat.Lx * (yj % lat.Ly)
+            cnt += np.sum(mine & ok[None, :] & ~mine[:, j], axis=1)
+    return cnt
+
+
 def _cpu_init(lat, params, act):
     try:
         from threadpoolctl import threadpool_limits
@@ -181,6 +204,7 @@ def main():
     ap.add_argument("--no-full", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-grad", action="store_true")
+    ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--tune-cache", default=None,
                     help="autotuner cache file (default: tune, do not store)")
     a = ap.parse_args()
@@ -270,6 +294,20 @@ def main():
                                       "nonfinite": int(np.count_nonzero(flags & 2)),
                                       "drift": int(np.count_nonzero(flags & 4)),
                                       "badcount": int(np.count_nonzero(flags & 8))}})
+    if not a.no_graph:
+        # the same step recorded once as a HIP graph and replayed
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            ctx.prepare()
+            ctx.local_energy(out=eloc)
+        g.replay()
+        torch.cuda.synchronize()
+        t0g = time.perf_counter()
+        for _ in range(a.steps):
+            g.replay()
+        torch.cuda.synchronize()
+        extra["graph_ms_per_step"] = round((time.perf_counter() - t0g) / a.steps * 1e3, 4)
+        log(f"[bench] graph replay: {extra['graph_ms_per_step']:.3f} ms/step")
     if not a.no_grad:
         v = torch.ones(W, dtype=torch.float64, device="cuda")
         ctx.grad_logpsi(v)
@@ -303,6 +341,18 @@ def main():
         full_rate = FW / (full_ms / 1e3)
         ef = feloc.cpu().numpy()
         agree = float(np.max(np.abs(ef - e_gpu[:FW]) / np.maximum(1.0, np.abs(ef))))
+        # the full path's own algorithmic work: per hop a full forward of all
+        # N sites (conv passes as above), both spins' N_s rows (C MACs each
+        # per orbital) and an LU of each N_s x N_s block
+        occ_f = occ[:FW]
+        nhop = float(np.sum(ctx_hops(lat, occ_f)))
+        N = lat.N
+        conv_full = nhop * model.n_conv * N * 9 * model.channels ** 2 * 2
+        fp64_full = nhop * sum(2.0 * n * n * model.channels + 2.0 / 3.0 * n ** 3 for n in (lat.n_up, lat.n_dn))
+        tpk_full = conv_full * passes / conv_peak + fp64_full / PEAK_FP64
+        tpk_low = t_peak * FW / W
+        extra.update({"full_recompute_roofline_frac": round(tpk_full / (full_ms / 1e3), 4),
+                      "speedup_at_equal_roofline_frac": round(tpk_full / tpk_low, 2)})
         extra.update({"full_recompute_eloc_per_s": round(full_rate, 1), "full_recompute_walkers": FW,
                       "full_recompute_ms": round(full_ms, 3),
                       "speedup_vs_full": round(value / full_rate, 3),

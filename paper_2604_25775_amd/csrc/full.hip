@@ -121,6 +121,7 @@ __global__ __launch_bounds__(256) void k_full_ratio(ModelDev md, LatDev lt, Bufs
   constexpr int SP = SiteStride<Tf, C>::value;            // padded site stride
   Tf* grid = (Tf*)smem;                                    // [N][SP]
   int8_t* occ_s = (int8_t*)(smem + (size_t)N * SP * sizeof(Tf));
+  double* wlds = (double*)(smem + (size_t)N * SP * sizeof(Tf) + ((N + 15) & ~15));   // [C][nmax]
   const int8_t* occ_g = bf.occ + lt.occ_off + wl * N;
   for (int s = tid; s < N; s += 256) occ_s[s] = occ_g[s];
   __syncthreads();
@@ -207,8 +208,15 @@ __global__ __launch_bounds__(256) void k_full_ratio(ModelDev md, LatDev lt, Bufs
     const int n = lt.n[tau];
     if (n == 0) continue;
     const double* base = lt.base + (long long)tau * N * nm;
-    const double* W = lt.W + (long long)tau * C * nm;
+    const double* Wg = lt.W + (long long)tau * C * nm;
     const double* b = lt.b + tau * nm;
+    // this spin's projection W [C][n] into LDS (after the feature grid)
+    double* W = wlds;
+    for (int e = tid; e < C * n; e += 256) {
+      const int c = e / n, m = e - c * n;
+      W[c * n + m] = Wg[(long long)c * nm + m];
+    }
+    __syncthreads();
     double x[R][R];
 #pragma unroll
     for (int a = 0; a < R; ++a) {
@@ -222,7 +230,7 @@ __global__ __launch_bounds__(256) void k_full_ratio(ModelDev md, LatDev lt, Bufs
         double v;
         if (k < n && m < n) {
           v = base[(long long)site * nm + m] + b[m];
-          for (int c = 0; c < C; ++c) v = fma((double)hl[c], W[c * nm + m], v);
+          for (int c = 0; c < C; ++c) v = fma((double)hl[c], W[c * n + m], v);
         } else {
           v = (k == m) ? 1.0 : 0.0;
         }
@@ -244,7 +252,8 @@ template <int P, int C, int R>
 static hipError_t full_impl(const ModelDev& md, const LatDev& lt, const Bufs& bf, const ElocOut& out,
                             double* ratio_tmp, int stride, hipStream_t st) {
   typedef typename PrecT<P>::Tf Tf;
-  const size_t smem = (size_t)lt.N * SiteStride<Tf, C>::value * sizeof(Tf) + ((lt.N + 15) & ~15);
+  const size_t smem = (size_t)lt.N * SiteStride<Tf, C>::value * sizeof(Tf) + ((lt.N + 15) & ~15) +
+                      (size_t)C * lt.nmax * sizeof(double);
   auto kern = k_full_ratio<P, C, R, 4>;
   hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
   if (e != hipSuccess) return e;
