@@ -30,27 +30,25 @@
 namespace svmc {
 
 constexpr int SW_NW = 4;        // wavefronts per workgroup
-constexpr int SWC_MAX = 16;     // most sites per chunk of the G update
+constexpr int SCH = 16;         // sites per chunk of the G update
 // nacc value of a walker whose update matrix was singular: its G and P were
 // not updated, so the refresh rebuilds it without a drift check
 constexpr int SW_REBUILD = 0x7fffffff;
 
 struct SweepLds {
-  int occ, lab, pos, misc, pu, rowc, ainv, qm, grow, gu, ef, mbs, perm, corder, pk, gk, mk, scratch, bytes, swc;
+  int occ, lab, pos, misc, pu, rowc, ainv, qm, perm, corder, pkbm, gk, mk, gkc, ec, mbs, scratch, bytes, kmax;
 };
 __host__ __device__ inline int al16(int x) { return (x + 15) & ~15; }
 // LDS of one walker: configuration, labels, positions, per-hop results, the
-// update matrices of one spin (PU [C][C+1], row C of A, A^-1 [C+1][C+1],
-// Q = PU A^-1 [C][C+1], a chunk of G rows [swc][nmax], of G_old' U and of
-// the site coefficients e_s [swc][C+1], box indices of the chunk, pivot
-// order, label order [2 nmax]) and the hop scratch.  swc (sites per chunk of the G update)
-// keeps the G-row chunk at 16 KB or less.
+// update matrices of one spin (PU [C][C+1], row C of A, A^-1 and Q = PU A^-1,
+// pivot order, label order [2 nmax], the changed rows' P^T [kmax][C] which
+// later holds B = U A^-1 [kmax][C+1], their G[j] entries and box offsets, a
+// chunk's G[s, K] [SCH][kmax] and E rows [SCH][C+1]) and the hop scratch.
+// kmax = changed rows per spin at most = sites of the layer-L box.
 __host__ __device__ inline SweepLds sweep_layout(int N, int nmax, int Gx, int Gy, int L, int C, int tfb) {
   const int ra = C + 1;
   SweepLds o;
-  o.swc = 16384 / (8 * nmax);
-  if (o.swc > SWC_MAX) o.swc = SWC_MAX;
-  if (o.swc < 1) o.swc = 1;
+  o.kmax = (Gx < 2 * L + 2 ? Gx : 2 * L + 2) * (Gy < 2 * L + 2 ? Gy : 2 * L + 2);
   o.occ = 0;
   o.lab = al16(N);
   o.pos = o.lab + al16(4 * N);
@@ -59,18 +57,15 @@ __host__ __device__ inline SweepLds sweep_layout(int N, int nmax, int Gx, int Gy
   o.rowc = o.pu + al16(8 * C * ra);
   o.ainv = o.rowc + al16(8 * ra);
   o.qm = o.ainv + al16(8 * ra * ra);
-  o.grow = o.qm + al16(8 * C * ra);
-  o.gu = o.grow + al16(8 * o.swc * nmax);
-  o.ef = o.gu + al16(8 * o.swc * ra);
-  o.mbs = o.ef + al16(8 * o.swc * ra);
-  o.perm = o.mbs + al16(4 * o.swc);
+  o.perm = o.qm + al16(8 * C * ra);
   o.corder = o.perm + al16(4 * ra);
-  // changed rows per spin: at most the layer-L box, (2L+2)^2 sites capped by the grid
-  const int kmax = (Gx < 2 * L + 2 ? Gx : 2 * L + 2) * (Gy < 2 * L + 2 ? Gy : 2 * L + 2);
-  o.pk = o.corder + al16(2 * 2 * nmax);
-  o.gk = o.pk + al16(8 * kmax * C);
-  o.mk = o.gk + al16(8 * kmax);
-  o.scratch = o.mk + al16(4 * kmax);
+  o.pkbm = o.corder + al16(2 * 2 * nmax);
+  o.gk = o.pkbm + al16(8 * o.kmax * ra);
+  o.mk = o.gk + al16(8 * o.kmax);
+  o.gkc = o.mk + al16(4 * o.kmax);
+  o.ec = o.gkc + al16(8 * SCH * o.kmax);
+  o.mbs = o.ec + al16(8 * SCH * ra);
+  o.scratch = o.mbs + al16(4 * SCH);
   o.bytes = o.scratch + hop_scratch(Gx, Gy, L, C, tfb).bytes;
   return o;
 }
@@ -164,17 +159,17 @@ __global__ __launch_bounds__(64 * SW_NW) void k_sweep(ModelDev md, const LatDev*
   double* pu = (double*)(smem + lay.pu);
   double* rowc = (double*)(smem + lay.rowc);
   double* ainv = (double*)(smem + lay.ainv);
-  double* grow = (double*)(smem + lay.grow);
-  double* gu = (double*)(smem + lay.gu);
+  double* qm = (double*)(smem + lay.qm);
   int* perm = (int*)(smem + lay.perm);
   int16_t* corder = (int16_t*)(smem + lay.corder);
-  double* qm = (double*)(smem + lay.qm);
-  double* pk = (double*)(smem + lay.pk);
+  double* pk = (double*)(smem + lay.pkbm);
+  double* bm = pk;                  // B = U A^-1 replaces P^T_K once PU is formed
   double* gk = (double*)(smem + lay.gk);
   int* mk = (int*)(smem + lay.mk);
-  double* ef = (double*)(smem + lay.ef);
+  double* gkc = (double*)(smem + lay.gkc);
+  double* ec = (double*)(smem + lay.ec);
   int* mbs = (int*)(smem + lay.mbs);
-  const int swc = lay.swc;
+  const int kmax = lay.kmax;
   char* scratch = smem + lay.scratch;
   const HopScratch hsc = hop_scratch(lt.Gx, lt.Gy, md.L, C, (int)sizeof(Tf));
   const int KM = lt.Gx * lt.Gy;
@@ -331,18 +326,30 @@ __global__ __launch_bounds__(64 * SW_NW) void k_sweep(ModelDev md, const LatDev*
       }
       __syncthreads();
       if (misc[6] == 0.0) { fallback = true; continue; }                 // uniform
-      // Q = PU A^-1 (C x RA): P' = P - PU A^-1 w_k = P - Q w_k
+      // Q = PU A^-1 (C x RA) and B = U A^-1 (r x RA), U[a] = [D(m_a), [k_a = k]]:
+      //   G' = G + E W,  E[s] = [s in box] (D_ext(s) - D(s) Q) - G[s, K] B,
+      //   P^T' = P^T - (Q W)^T,  W[:, k'] = [P^T[k']; G[j][k'] - [k' = k]]
       for (int e2 = tid; e2 < C * RA; e2 += NTH) {
         const int cp = e2 / RA, c = e2 - cp * RA;
         double v = 0.0;
         for (int c1 = 0; c1 < R; ++c1) v = fma(pu[cp * RA + c1], ainv[c1 * RA + c], v);
         qm[e2] = v;
       }
-      // Columns (labels) go in blocks of NTH, one per thread; with more than
-      // one block the labels of K come last, so that no block changes a
-      // column G[:, k_a] that a later block still reads through G_old' U.
-      const int nblk = (n + NTH - 1) / NTH;
-      if (nblk > 1) {
+      for (int e2 = tid; e2 < r * RA; e2 += NTH) {
+        const int a = e2 / RA, c2 = e2 - a * RA;
+        const typename DType<P>::type* Da = Dbuf + mk[a];
+        double v = (hs && (kl[a] & 0xffff) == k) ? ainv[C * RA + c2] : 0.0;
+#pragma unroll 8
+        for (int c = 0; c < C; ++c) v = fma((double)Da[c], ainv[c * RA + c2], v);
+        bm[e2] = v;
+      }
+      // Columns (labels) go in passes of NTH / 2, each column on two threads
+      // (even and odd sites of a chunk).  With more than one pass the labels
+      // of K come last and all fall in the last pass: E of a chunk reads the
+      // old G[s, K] of its sites.
+      constexpr int NCOL = NTH / 2;
+      const int npass = (n + NCOL - 1) / NCOL;
+      if (npass > 1) {
         for (int kk = tid; kk < n; kk += NTH) corder[kk] = 0;
         __syncthreads();
         for (int a = tid; a < r; a += NTH) corder[kl[a] & 0xffff] = 1;
@@ -356,80 +363,61 @@ __global__ __launch_bounds__(64 * SW_NW) void k_sweep(ModelDev md, const LatDev*
         }
       }
       __syncthreads();
-      for (int b = 0; b < nblk; ++b) {
-        const int slot = b * NTH + tid;
-        const bool col = slot < n;
-        const int kc = !col ? 0 : (nblk > 1 ? (int)corder[n + slot] : slot);
-        // w_kc = (V Phi^-1)[:, kc] = [P^T[kc]; G[j][kc] - [kc = k]]
-        double pt[C];
-        double vc = 0.0;
-        if (col) {
+      const int half = tid / NCOL, tcol = tid - half * NCOL;
+      for (int b = 0; b < npass; ++b) {
+        // passes are cut from the end of the order, so the last one holds the
+        // final NCOL labels and with them all of K (r <= (2L+2)^2 <= NCOL)
+        const int slot = n - (npass - b) * NCOL + tcol;
+        const bool col = slot >= 0;
+        const int kc = !col ? 0 : (npass > 1 ? (int)corder[n + slot] : slot);
+        double wcol[RA];
 #pragma unroll
-          for (int c = 0; c < C; ++c) pt[c] = PTt[(long long)kc * C + c];
-          if (hs) vc = Gj[kc] - (kc == k ? 1.0 : 0.0);
-        }
-        __syncthreads();            // every read of G[j] done before G changes
-        // G' = G_old' - (G_old' U) A^-1 w = G + e_s . w  (swc sites at a time),
-        //   e_s = [[s in box] D(s) - A^-1^T GU[s];  -GU[s] . A^-1[:, C]]
-        for (int s0 = 0; s0 < N; s0 += swc) {
-          const int ns = min(swc, N - s0);
-          // stage the chunk's G rows: every load of a thread in flight at once
-          for (int kk = tid; kk < n; kk += NTH) {
-            double v[SWC_MAX];
-#pragma unroll
-            for (int sl = 0; sl < SWC_MAX; ++sl)
-              if (sl < ns) v[sl] = Gt[(long long)(s0 + sl) * nm + kk];
-#pragma unroll
-            for (int sl = 0; sl < SWC_MAX; ++sl)
-              if (sl < ns) grow[sl * nm + kk] = v[sl];
+        for (int c = 0; c < C; ++c) wcol[c] = col ? PTt[(long long)kc * C + c] : 0.0;
+        wcol[C] = (col && hs) ? Gj[kc] - (kc == k ? 1.0 : 0.0) : 0.0;
+        __syncthreads();            // every read of G[j] and P done before they change
+        for (int s0 = 0; s0 < N; s0 += SCH) {
+          const int ns = min(SCH, N - s0);
+          for (int e2 = tid; e2 < ns * r; e2 += NTH) {
+            const int sl = e2 / r, a = e2 - sl * r;
+            gkc[sl * kmax + a] = Gt[(long long)(s0 + sl) * nm + (kl[a] & 0xffff)];
           }
           if (tid < ns) mbs[tid] = box_index(lt, s0 + tid, olx, owx, oly, owy);
           __syncthreads();
           for (int e2 = tid; e2 < ns * RA; e2 += NTH) {
-            const int sl = e2 / RA, c = e2 - sl * RA;
-            double v = 0.0;
-            if (c < C) {
-              const double* gr = grow + sl * nm;
-#pragma unroll 8
-              for (int a = 0; a < r; ++a) v = fma(gr[kl[a] & 0xffff], (double)Dbuf[mk[a] + c], v);
-            } else if (hs) {
-              v = grow[sl * nm + k];
-            }
-            const int mb = mbs[sl];
-            if (mb >= 0 && (c < C || hs)) {
-              const typename DType<P>::type* Dm = Dbuf + mb * SD;
-              for (int c2 = 0; c2 < C; ++c2) v = fma((double)Dm[c2], pu[c2 * RA + c], v);
-            }
-            gu[sl * RA + c] = v;
-          }
-          __syncthreads();
-          for (int e2 = tid; e2 < ns * RA; e2 += NTH) {
             const int sl = e2 / RA, c2 = e2 - sl * RA;
             const int mb = mbs[sl];
-            double v = (c2 < C && mb >= 0) ? (double)Dbuf[mb * SD + c2] : 0.0;
-            for (int c = 0; c < R; ++c) v = fma(-gu[sl * RA + c], ainv[c * RA + c2], v);
-            ef[sl * RA + c2] = v;
+            double v = 0.0;
+            if (mb >= 0) {
+              const typename DType<P>::type* Dm = Dbuf + mb * SD;
+              v = c2 < C ? (double)Dm[c2] : 0.0;
+#pragma unroll 8
+              for (int c = 0; c < C; ++c) v = fma(-(double)Dm[c], qm[c * RA + c2], v);
+            }
+            const double* gr = gkc + sl * kmax;
+#pragma unroll 8
+            for (int a = 0; a < r; ++a) v = fma(-gr[a], bm[a * RA + c2], v);
+            ec[sl * RA + c2] = v;
           }
           __syncthreads();
           if (col) {
-            for (int sl = 0; sl < ns; ++sl) {
-              const double* es = ef + sl * RA;
-              double v = fma(es[C], vc, grow[sl * nm + kc]);
+            for (int sl = half; sl < ns; sl += 2) {
+              const double* es = ec + sl * RA;
+              double* gp = Gt + (long long)(s0 + sl) * nm + kc;
+              double v = *gp;
 #pragma unroll
-              for (int c = 0; c < C; ++c) v = fma(es[c], pt[c], v);
-              Gt[(long long)(s0 + sl) * nm + kc] = v;
+              for (int c = 0; c < RA; ++c) v = fma(es[c], wcol[c], v);
+              *gp = v;
             }
           }
           __syncthreads();
         }
-        // P' = P - Q w
-        if (col) {
+        if (col && half == 0) {
 #pragma unroll
           for (int cp = 0; cp < C; ++cp) {
             const double* qr = qm + cp * RA;
-            double v = fma(-qr[C], vc, pt[cp]);
+            double v = wcol[cp];
 #pragma unroll
-            for (int c = 0; c < C; ++c) v = fma(-qr[c], pt[c], v);
+            for (int c = 0; c < RA; ++c) v = fma(-qr[c], wcol[c], v);
             PTt[(long long)kc * C + cp] = v;
           }
         }
