@@ -54,6 +54,29 @@ float bf16_to_f32(uint16_t h) {
   return f;
 }
 
+// x rounded toward zero to FP16 (the device's round-toward-zero conversion):
+// 11 significant bits in FP16's normal range, multiples of 2^-24 below it,
+// the largest finite FP16 value above it.  x finite.
+float f16_rtz(float x) {
+  const float a = std::fabs(x);
+  float r;
+  if (a >= 0x1p-14f) {
+    uint32_t u;
+    std::memcpy(&u, &a, 4);
+    u &= 0xffffe000u;
+    std::memcpy(&r, &u, 4);
+    if (r > 65504.0f) r = 65504.0f;
+  } else {
+    r = std::trunc(a * 0x1p24f) * 0x1p-24f;
+  }
+  return std::copysign(r, x);
+}
+// FP16 pair value hi + lo of x (hi = f16_rtz(x), lo = f16_rtz(x - hi))
+float f16_pair(float x) {
+  const float h = f16_rtz(x);
+  return h + f16_rtz(x - h);
+}
+
 }  // namespace
 
 struct svmc_ctx {
@@ -233,12 +256,17 @@ svmc_status svmc_set_params(svmc_ctx* ctx, const double* theta, const double* co
     if (P == PREC_F16X2) return (double)(float)(_Float16)(float)x;
     return rnd(x);
   };
+  // the embedding is the layer-0 feature: an FP16 pair in F16X2
+  auto rnd_e = [&](double x) -> double {
+    if (P == PREC_F16X2) return (double)f16_pair((float)x);
+    return rnd(x);
+  };
   // embedding and conv bias in the feature type
   const int tfb = ctx->tf_bytes();
   std::vector<char> eb(4 * C * tfb), bb((size_t)L * C * tfb);
   for (int k = 0; k < 4 * C; ++k) {
     if (tfb == 8) ((double*)eb.data())[k] = E[k];
-    else ((float*)eb.data())[k] = (float)rnd(E[k]);
+    else ((float*)eb.data())[k] = (float)rnd_e(E[k]);
   }
   for (int k = 0; k < L * C; ++k) {
     if (tfb == 8) ((double*)bb.data())[k] = Bc[k];
@@ -273,7 +301,7 @@ svmc_status svmc_set_params(svmc_ctx* ctx, const double* theta, const double* co
   std::vector<double> gk(9ULL * L * C * C), gbias((size_t)L * C), ge(4ULL * C);
   for (size_t k = 0; k < gk.size(); ++k) gk[k] = rnd_w(K[k]);
   for (size_t k = 0; k < gbias.size(); ++k) gbias[k] = rnd(Bc[k]);
-  for (size_t k = 0; k < ge.size(); ++k) ge[k] = rnd(E[k]);
+  for (size_t k = 0; k < ge.size(); ++k) ge[k] = rnd_e(E[k]);
   if ((s = ctx->hip(ctx->gK.ensure(gk.size() * 8), "alloc")) || (s = ctx->hip(ctx->gB.ensure(gbias.size() * 8), "alloc")) ||
       (s = ctx->hip(ctx->gE.ensure(ge.size() * 8), "alloc")) ||
       (s = ctx->hip(hipMemcpy(ctx->gK.p, gk.data(), gk.size() * 8, hipMemcpyHostToDevice), "upload")) ||

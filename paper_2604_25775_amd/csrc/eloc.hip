@@ -115,7 +115,7 @@ __global__ __launch_bounds__(64 * ELOC_NW) __attribute__((amdgpu_waves_per_eu(3)
   const LatDev lt = lats[li];
   const long long wl = w - lt.w0;
   const int N = lt.N, nm = lt.nmax;
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int tid = threadIdx.x, wv = uniform_i(tid >> 6);
   const ElocLds lay = eloc_layout(N, lt.maxhops, lt.Gx, lt.Gy, md.L, C, (int)sizeof(Tf));
   int8_t* occ_s = (int8_t*)(smem + lay.occ);
   int16_t* lab_s = (int16_t*)(smem + lay.lab);
@@ -146,6 +146,9 @@ __global__ __launch_bounds__(64 * ELOC_NW) __attribute__((amdgpu_waves_per_eu(3)
   bool nonfinite = false;
   if (!bad) {
     for (int hh = h0; hh < h1; ++hh) {
+      // lane index through an opaque copy (see hop_features)
+      int lane;
+      asm volatile("v_mov_b32 %0, %1" : "=v"(lane) : "v"((int)threadIdx.x & 63));
       const int code = uniform_i(hops[hh]);
       const int i = code >> 4, sp = (code >> 3) & 1, d = code & 7;
       const HopGeom g = hop_geom(lt, md.L, sp, i, d);
@@ -156,7 +159,11 @@ __global__ __launch_bounds__(64 * ELOC_NW) __attribute__((amdgpu_waves_per_eu(3)
       const int K = hop_klist(lt, g, occ_s, lab_s, wv, olx, owx, oly, owy, kl, hpos, lane);
       const double* PTt = PTw + (long long)wv * nm * C;
       const double* Gj = Gw + ((long long)wv * N + g.j) * nm;
-      const double Rt = hop_det<C>(kl, K, wv == sp, hpos, (const typename DType<P>::type*)scratch, PTt, Gj, prow, lane);
+      v4d dacc[DetTiles<C>::I][DetTiles<C>::J];
+      hop_det_build<C>(kl, K, wv == sp, hpos, (const typename DType<P>::type*)scratch, PTt, Gj, lane, dacc);
+      __syncthreads();      // both matrices built: their staging may overwrite D
+      double* stage = (double*)scratch + wv * (C + 1) * DetTiles<C>::RS;
+      const double Rt = hop_det_finish<C>(dacc, kl, K, wv == sp, hpos, PTt, Gj, stage, prow, lane);
       if (lane == 0) misc[wv] = Rt;
       __syncthreads();
       if (tid == 0) {

@@ -173,9 +173,9 @@ __global__ __launch_bounds__(256) void k_full_ratio(ModelDev md, LatDev lt, Bufs
         for (int nt = 0; nt < CC::NT; ++nt)
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
-            const int r = 16 * t + OutMap<P>::row(lane, v);
-            const int n = 16 * nt + OutMap<P>::col(lane, v);
-            if (r < N && n < C) acc[q][nt][v] = grid[r * SP + n] + act_fn<Tf>(md.act, acc[q][nt][v] + bias[n]);
+            const int r = 16 * t + OutMap<P>::site(lane, v);
+            const int n = 16 * nt + OutMap<P>::chan(lane, v);
+            if (r < N && n < C) acc[q][nt][v] = layer_out<P, Tf>(md.act, grid[r * SP + n], acc[q][nt][v] + bias[n]);
           }
       }
     }
@@ -188,8 +188,8 @@ __global__ __launch_bounds__(256) void k_full_ratio(ModelDev md, LatDev lt, Bufs
         for (int nt = 0; nt < CC::NT; ++nt)
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
-            const int r = 16 * t + OutMap<P>::row(lane, v);
-            const int n = 16 * nt + OutMap<P>::col(lane, v);
+            const int r = 16 * t + OutMap<P>::site(lane, v);
+            const int n = 16 * nt + OutMap<P>::chan(lane, v);
             if (r < N && n < C) grid[r * SP + n] = acc[q][nt][v];
           }
       }

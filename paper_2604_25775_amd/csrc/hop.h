@@ -105,7 +105,9 @@ template <int C> struct DStride {
 
 // LDS scratch of one hop, in bytes:
 //   grid   [Gy][Gx][SP] Tf  features of one layer on the update box; after the
-//                           last layer, D = H'_L - H_L densely as Tf [m][C + 4]
+//                           last layer, D = H'_L - H_L densely as Tf [m][C + 4];
+//                           once both determinant matrices are built, their
+//                           row-major copies [2][C + 1][C + 2] f64
 //   prow   [2][64] f64      pivot-row broadcast of the two determinant waves
 //   klists [2][Gx Gy] int   changed-row lists per spin
 //   misc   64 bytes         per-spin results
@@ -118,7 +120,9 @@ __host__ __device__ inline HopScratch hop_scratch(int Gx, int Gy, int L, int C, 
   const int SP = C + 16 / tfb;
   const int ox = Gx < 2 * L + 2 ? Gx : 2 * L + 2, oy = Gy < 2 * L + 2 ? Gy : 2 * L + 2;
   const int gb = Gx * Gy * SP * tfb, db = ox * oy * (C + 4) * tfb;
-  h.prow = align16i(gb > db ? gb : db);
+  const int sb = 2 * (C + 1) * (C + 2) * 8;     // two determinant stagings
+  const int rb = gb > db ? gb : db;
+  h.prow = align16i(rb > sb ? rb : sb);
   h.klists = h.prow + 2 * 64 * 8;
   h.misc = h.klists + align16i(2 * Gx * Gy * 4);
   h.bytes = h.misc + 64;
@@ -131,10 +135,38 @@ template <int P, int C> struct RegB {
       ConvCfg<P, C>::Q * ConvCfg<P, C>::NT * (int)sizeof(typename PrecT<P>::Tb) <= 80 * 4;
 };
 
+// LDS feature grid of the hop: per site a record of SiteStride<Tf, C> Tf.
+// In PREC_F16X2 the record holds the features already split into their FP16
+// pair: hi[C] then lo[C] (FP16), then 16 bytes of padding (same size as the
+// FP32 record), so the conv reads MFMA operands directly.
+template <int P> struct GridPlanes {
+  static constexpr bool value = P == PREC_F16X2;
+};
+
+// Four consecutive channels n0 .. n0 + 3 of grid site record `rec`.
+template <int C> SVMC_DEV void planes_put4(char* rec, int n0, float a, float b, float c, float d) {
+  unsigned h0, l0, h1, l1;
+  pair_split2(a, b, h0, l0);
+  pair_split2(c, d, h1, l1);
+  *reinterpret_cast<uint2*>(rec + 2 * n0) = uint2{h0, h1};
+  *reinterpret_cast<uint2*>(rec + 2 * C + 2 * n0) = uint2{l0, l1};
+}
+template <int C> SVMC_DEV void planes_get4(const char* rec, int n0, float (&x)[4]) {
+  const uint2 h = *reinterpret_cast<const uint2*>(rec + 2 * n0);
+  const uint2 l = *reinterpret_cast<const uint2*>(rec + 2 * C + 2 * n0);
+  const v2h h0 = __builtin_bit_cast(v2h, h.x), h1 = __builtin_bit_cast(v2h, h.y);
+  const v2h l0 = __builtin_bit_cast(v2h, l.x), l1 = __builtin_bit_cast(v2h, l.y);
+  x[0] = (float)h0[0] + (float)l0[0];
+  x[1] = (float)h0[1] + (float)l0[1];
+  x[2] = (float)h1[0] + (float)l1[0];
+  x[3] = (float)h1[1] + (float)l1[1];
+}
+
 // One 16-site tile of a layer on the LDS grid.  px / py: packed grid
-// coordinates of the lane's row (byte k = offset k - 1, 0xFF = zero padding).
+// coordinates of the lane's site (byte k = offset k - 1, 0xFF = zero padding).
 // B fragments come from registers (breg) or global memory (Bl).  Per output
-// element the accumulation order equals conv_tile's.
+// element the accumulation order equals conv_tile's (chunk by chunk; in the
+// split modes all output tiles of one term before the next term).
 template <int P, int C>
 SVMC_DEV void conv_tile_grid(const typename PrecT<P>::Tf* __restrict__ grid, int Gx, unsigned px, unsigned py,
                              const typename PrecT<P>::Tb (&breg)[RegB<P, C>::value ? ConvCfg<P, C>::Q : 1]
@@ -144,6 +176,7 @@ SVMC_DEV void conv_tile_grid(const typename PrecT<P>::Tf* __restrict__ grid, int
   typedef typename PrecT<P>::Tf Tf;
   typedef typename PrecT<P>::Tb Tb;
   typedef ConvCfg<P, C> CC;
+  constexpr int SP = SiteStride<Tf, C>::value;
   const int g = lane >> 4;
 #pragma unroll
   for (int nt = 0; nt < CC::NT; ++nt)
@@ -171,8 +204,20 @@ SVMC_DEV void conv_tile_grid(const typename PrecT<P>::Tf* __restrict__ grid, int
     }
     const unsigned gx = (px >> (8 * (tap % 3))) & 0xFFu, gy = (py >> (8 * (tap / 3))) & 0xFFu;
     const bool ok = kok && gx != 0xFFu && gy != 0xFFu;
-    const int off = ((int)gy * Gx + (int)gx) * SiteStride<Tf, C>::value + c0;
-    if constexpr (Mma16<P>::value) {
+    const int site = (int)gy * Gx + (int)gx;
+    if constexpr (GridPlanes<P>::value) {
+      v8h hi = {}, lo = {};
+      if (ok) {
+        const char* rec = reinterpret_cast<const char*>(grid) + site * SP * (int)sizeof(Tf) + 2 * c0;
+        hi = *reinterpret_cast<const v8h*>(rec);
+        lo = *reinterpret_cast<const v8h*>(rec + 2 * C);
+      }
+#pragma unroll
+      for (int nt = 0; nt < CC::NT; ++nt) mfma(acc[nt], b[nt], hi);
+#pragma unroll
+      for (int nt = 0; nt < CC::NT; ++nt) mfma(acc[nt], b[nt], lo);
+    } else if constexpr (Mma16<P>::value) {
+      const int off = site * SP + c0;
       float x[8];
       if (ok) {
         const float4* p4 = reinterpret_cast<const float4*>(grid + off);
@@ -185,11 +230,23 @@ SVMC_DEV void conv_tile_grid(const typename PrecT<P>::Tf* __restrict__ grid, int
       }
       mma_chunk16<P, CC::NT>(acc, x, b);
     } else {
+      const int off = site * SP + c0;
       const Tf a = ok ? grid[off] : Tf(0);
 #pragma unroll
-      for (int nt = 0; nt < CC::NT; ++nt) mfma(acc[nt], a, b[nt]);
+      for (int nt = 0; nt < CC::NT; ++nt) mfma(acc[nt], b[nt], a);
     }
   }
+}
+
+// Writes four consecutive channels n0 .. n0 + 3 of FP32 features to grid
+// record `site` (16-byte vector loads and stores on both layouts).
+template <int P, int C>
+SVMC_DEV void grid_put4(typename PrecT<P>::Tf* grid, int site, int n0, const float4& v) {
+  constexpr int SP = SiteStride<typename PrecT<P>::Tf, C>::value;
+  if constexpr (GridPlanes<P>::value)
+    planes_put4<C>(reinterpret_cast<char*>(grid) + site * SP * 4, n0, v.x, v.y, v.z, v.w);
+  else
+    *reinterpret_cast<float4*>(grid + site * SP + n0) = v;
 }
 
 // Incremental conv stack for one hop, computed by the NW wavefronts of the
@@ -207,9 +264,15 @@ SVMC_DEV void hop_features(const ModelDev& md, const LatDev& lt, const HopGeom& 
   typedef typename PrecT<P>::Tb Tb;
   typedef typename PrecT<P>::Acc Acc;
   typedef ConvCfg<P, C> CC;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  // thread index through an opaque copy: the lane-dependent index arithmetic
+  // below is recomputed per hop instead of being hoisted out of the callers'
+  // hop loops into registers (where it would be spilled)
+  int tid;
+  asm volatile("v_mov_b32 %0, %1" : "=v"(tid) : "v"((int)threadIdx.x));
+  const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   constexpr int NT_ = 64 * NW;
   constexpr int SP = SiteStride<Tf, C>::value;
+  constexpr bool PL = GridPlanes<P>::value;
   const int L = md.L, N = lt.N, Lx = lt.Lx, Gx = lt.Gx;
   const Axis ax = h.ax, ay = h.ay;
   Tf* grid = (Tf*)scratch;
@@ -234,8 +297,11 @@ SVMC_DEV void hop_features(const ModelDev& md, const LatDev& lt, const HopGeom& 
       int o = occ_s[s];
       if (s == h.i) o -= bit;
       if (s == h.j) o += bit;
-      *reinterpret_cast<float4*>(grid + (gidx(ay, uy) * Gx + gidx(ax, ux)) * SP + cv * V) =
-          *reinterpret_cast<const float4*>(E + o * C + cv * V);
+      const int site = gidx(ay, uy) * Gx + gidx(ax, ux);
+      if constexpr (PL)
+        grid_put4<P, C>(grid, site, cv * V, *reinterpret_cast<const float4*>(E + o * C + cv * V));
+      else
+        *reinterpret_cast<float4*>(grid + site * SP + cv * V) = *reinterpret_cast<const float4*>(E + o * C + cv * V);
     }
   }
   __syncthreads();
@@ -259,7 +325,8 @@ SVMC_DEV void hop_features(const ModelDev& md, const LatDev& lt, const HopGeom& 
     const Tf* bias = (const Tf*)md.bias + (l - 1) * C;
     // Each wave keeps its tiles' new values in registers until every wave
     // has finished reading the grid of this layer (at most 7 tiles: the
-    // layer-L box of L <= 4 has at most 10 x 10 sites).
+    // layer-L box of L <= 4 has at most 10 x 10 sites).  The lane's site is
+    // the same in all four slots v (OutMap).
     constexpr int MAXT = (7 + NW - 1) / NW;
     Tf outv[MAXT][CC::NT][4];
 #pragma unroll
@@ -268,6 +335,7 @@ SVMC_DEV void hop_features(const ModelDev& md, const LatDev& lt, const HopGeom& 
       if (t >= T) break;
       const int m = 16 * t + (lane & 15);
       unsigned px = 0xFFFFFFu, py = 0xFFFFFFu;
+      int gofs = 0;
       if (m < cnt) {
         int ux, uy;
         box_site(m, olx, owx, mow, oly, ux, uy);
@@ -279,22 +347,28 @@ SVMC_DEV void hop_features(const ModelDev& md, const LatDev& lt, const HopGeom& 
           px |= (inlat(ax, nx) ? (unsigned)gidx(ax, nx) : 0xFFu) << (8 * k);
           py |= (inlat(ay, ny) ? (unsigned)gidx(ay, ny) : 0xFFu) << (8 * k);
         }
+        gofs = (gidx(ay, uy) * Gx + gidx(ax, ux)) * SP;
       }
       Acc acc[CC::NT];
       conv_tile_grid<P, C>(grid, Gx, px, py, breg, Bl, lane, acc);
       // H'_l = H'_{l-1} + act(conv + b); the residual is this site's own grid value
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int r = 16 * t + OutMap<P>::row(lane, v);
-        int ux, uy;
-        box_site(r, olx, owx, mow, oly, ux, uy);
-        const int gofs = r < cnt ? (gidx(ay, uy) * Gx + gidx(ax, ux)) * SP : 0;
+      for (int nt = 0; nt < CC::NT; ++nt) {
+        if constexpr (PL) {
+          const int n0 = 16 * nt + OutMap<P>::chan(lane, 0);
+          float x[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+          if (m < cnt && n0 < C) planes_get4<C>(reinterpret_cast<const char*>(grid + gofs), n0, x);
 #pragma unroll
-        for (int nt = 0; nt < CC::NT; ++nt) {
-          const int n = 16 * nt + OutMap<P>::col(lane, v);
-          Tf val = Tf(0);
-          if (r < cnt && n < C) val = grid[gofs + n] + act_fn<Tf>(md.act, Tf(acc[nt][v] + bias[n]));
-          outv[ti][nt][v] = val;
+          for (int v = 0; v < 4; ++v)
+            outv[ti][nt][v] = (m < cnt && n0 < C) ? layer_out<P, float>(md.act, x[v], acc[nt][v] + bias[n0 + v]) : 0.0f;
+        } else {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int n = 16 * nt + OutMap<P>::chan(lane, v);
+            Tf val = Tf(0);
+            if (m < cnt && n < C) val = layer_out<P, Tf>(md.act, grid[gofs + n], Tf(acc[nt][v] + bias[n]));
+            outv[ti][nt][v] = val;
+          }
         }
       }
     }
@@ -304,37 +378,47 @@ SVMC_DEV void hop_features(const ModelDev& md, const LatDev& lt, const HopGeom& 
     for (int ti = 0; ti < MAXT; ++ti) {
       const int t = wave + NW * ti;
       if (t >= T) break;
+      const int r = 16 * t + (lane & 15);
+      if (r >= cnt) continue;
+      int ux, uy;
+      box_site(r, olx, owx, mow, oly, ux, uy);
+      const int s = latc(ax, ux) + Lx * latc(ay, uy);
+      if (l < L) {
+        // H'_l replaces H'_{l-1} on the box (and goes to the cache on accept)
+        const int site = gidx(ay, uy) * Gx + gidx(ax, ux);
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int r = 16 * t + OutMap<P>::row(lane, v);
-        if (r >= cnt) continue;
-        int ux, uy;
-        box_site(r, olx, owx, mow, oly, ux, uy);
-        const int s = latc(ax, ux) + Lx * latc(ay, uy);
-        if (l < L) {
-          // H'_l replaces H'_{l-1} on the box (and goes to the cache on accept)
-          const int gofs = (gidx(ay, uy) * Gx + gidx(ax, ux)) * SP;
+        for (int nt = 0; nt < CC::NT; ++nt) {
+          if constexpr (PL) {
+            const int n0 = 16 * nt + OutMap<P>::chan(lane, 0);
+            if (n0 >= C) continue;
+            const float4 v4 = {outv[ti][nt][0], outv[ti][nt][1], outv[ti][nt][2], outv[ti][nt][3]};
+            grid_put4<P, C>(grid, site, n0, v4);
+            if (commit) *reinterpret_cast<float4*>(commit + ((long long)(l - 1) * N + s) * C + n0) = v4;
+          } else {
 #pragma unroll
-          for (int nt = 0; nt < CC::NT; ++nt) {
-            const int n = 16 * nt + OutMap<P>::col(lane, v);
-            if (n >= C) continue;
-            grid[gofs + n] = outv[ti][nt][v];
-            if (commit) commit[((long long)(l - 1) * N + s) * C + n] = outv[ti][nt][v];
+            for (int v = 0; v < 4; ++v) {
+              const int n = 16 * nt + OutMap<P>::chan(lane, v);
+              if (n >= C) continue;
+              grid[site * SP + n] = outv[ti][nt][v];
+              if (commit) commit[((long long)(l - 1) * N + s) * C + n] = outv[ti][nt][v];
+            }
           }
-        } else {
-          // D = H'_L - H_L, densely [m][C + 4] at the start of the scratch
-          typedef typename DType<P>::type DT;
-          DT* D = reinterpret_cast<DT*>(grid);
+        }
+      } else {
+        // D = H'_L - H_L, densely [m][C + 4] at the start of the scratch
+        typedef typename DType<P>::type DT;
+        DT* D = reinterpret_cast<DT*>(grid);
 #pragma unroll
-          for (int nt = 0; nt < CC::NT; ++nt) {
-            const int n = 16 * nt + OutMap<P>::col(lane, v);
+        for (int nt = 0; nt < CC::NT; ++nt)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int n = 16 * nt + OutMap<P>::chan(lane, v);
             if (n >= C) continue;
             const long long gi = (long long)s * C + n;
             const Tf old = HL[gi];
             D[r * DStride<C>::value + n] = (DT)((double)outv[ti][nt][v] - (double)old);
             if (commit) commit[(long long)(L - 1) * N * C + gi] = outv[ti][nt][v];
           }
-        }
       }
     }
     if (l < L) {
@@ -359,12 +443,16 @@ SVMC_DEV void hop_features(const ModelDev& md, const LatDev& lt, const HopGeom& 
           box_site(q, ilx, iwx, miw, ily, ux, uy);
           const bool ok = e < tot && !(inbox(ax, olx, owx, ux) && inbox(ay, oly, owy, uy));
           const int s = ok ? latc(ax, ux) + Lx * latc(ay, uy) : 0;
-          dst[u] = ok ? (gidx(ay, uy) * Gx + gidx(ax, ux)) * SP + cv * V : -1;
+          dst[u] = ok ? (gidx(ay, uy) * Gx + gidx(ax, ux)) * 256 + cv * V : -1;
           val[u] = ok ? *reinterpret_cast<const float4*>(Hl + (long long)s * C + cv * V) : float4{0, 0, 0, 0};
         }
 #pragma unroll
         for (int u = 0; u < U; ++u)
-          if (dst[u] >= 0) *reinterpret_cast<float4*>(grid + dst[u]) = val[u];
+          if (dst[u] >= 0) {
+            const int site = dst[u] >> 8, n0 = dst[u] & 255;
+            if constexpr (PL) grid_put4<P, C>(grid, site, n0, val[u]);
+            else *reinterpret_cast<float4*>(grid + site * SP + n0) = val[u];
+          }
       }
     }
     __syncthreads();
@@ -467,68 +555,121 @@ SVMC_DEV double lu_det_rot(double (&a)[RM], int r_in, int lane, double* prow) {
     }
     __builtin_amdgcn_wave_barrier();
   }
+  // parity of the pivot order: inversions among the lanes' pivot steps
   int inv = 0;
   for (int b = 0; b < r; ++b) {
     const int sb = __builtin_amdgcn_readlane(step, b);
     if (lane < r && b > lane && sb < step) ++inv;
   }
-  inv = wave_sum_i(inv);
-  return (inv & 1) ? -det : det;
+  const unsigned long long odd = __ballot(inv & 1);
+  return (__popcll(odd) & 1) ? -det : det;
 }
 
-// det of the Woodbury / determinant-lemma matrix of spin tau for one hop
-// (one wavefront), in the column form
-//   det(I + V U),  U = [D_K, e_h] (changed rows K carry D(m_a); the mover's
+// The Woodbury / determinant-lemma matrix of spin tau for one hop (one
+// wavefront), in the column form
+//   A = I + V U,  U = [D_K, e_h] (changed rows K carry D(m_a); the mover's
 //   row also e_h),  V = [P_K; g_K - e_h]  (P = W Phi^-1, g = G[j] = M[j] Phi^-1)
-// of size C + [tau = moving spin], which equals det(Phi'[K] Phi^-1[:, K]).
-// Lane c < C accumulates row c from P^T[k_q][c] (one coalesced row load per
-// changed label); lane C from G[j][k_q].  All in FP64.
+// of size C + [tau = moving spin]; det A = det(Phi'[K] Phi^-1[:, K]).
+// The product V U over the changed rows is a (C + 1) x r x C contraction and
+// runs on the FP64 matrix cores (16 x 16 x 4 tiles: row tiles over the C rows
+// of P plus row C = g, column tiles over the C channels of D, four changed
+// rows per step).  Lane l supplies changed row 4 s + l / 16 of step s.
+template <int C> struct DetTiles {
+  static constexpr int I = (C + 16) / 16;     // row tiles (rows 0 .. C)
+  static constexpr int J = (C + 15) / 16;     // column tiles (columns 0 .. C-1)
+  static constexpr int RS = C + 2;            // staged row stride (doubles)
+};
+
 template <int C, class DT>
-SVMC_DEV double hop_det(const int* kl, int K_in, bool hopspin, int hpos_in, const DT* Dbuf,
-                        const double* __restrict__ PTt, const double* __restrict__ Gj, double* prow, int lane) {
+SVMC_DEV void hop_det_build(const int* kl, int K_in, bool hopspin, int hpos_in, const DT* Dbuf,
+                            const double* __restrict__ PTt, const double* __restrict__ Gj, int lane,
+                            v4d (&acc)[DetTiles<C>::I][DetTiles<C>::J]) {
+  typedef DetTiles<C> T;
+  constexpr int SD = DStride<C>::value;
+  constexpr int U = 4;                         // steps whose loads are in flight together
+  const int K = uniform_i(K_in), hpos = uniform_i(hpos_in);
+  const int r16 = lane & 15, qo = lane >> 4;
+#pragma unroll
+  for (int ti = 0; ti < T::I; ++ti)
+#pragma unroll
+    for (int tj = 0; tj < T::J; ++tj) acc[ti][tj] = v4d{0.0, 0.0, 0.0, 0.0};
+  for (int q0 = 0; q0 < K; q0 += 4 * U) {
+    double x[U][T::I], y[U][T::J];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int q = q0 + 4 * u + qo;
+      const bool ok = q < K;
+      const int e = ok ? kl[q] : 0;
+      const int kq = e & 0xffff, mo = (e >> 16) * SD;
+#pragma unroll
+      for (int ti = 0; ti < T::I; ++ti) {
+        const int c = 16 * ti + r16;
+        double v = 0.0;
+        if (ok) {
+          if (c < C) v = PTt[kq * C + c];
+          else if (c == C && hopspin) v = Gj[kq] - (q == hpos ? 1.0 : 0.0);
+        }
+        x[u][ti] = v;
+      }
+#pragma unroll
+      for (int tj = 0; tj < T::J; ++tj) {
+        const int c = 16 * tj + r16;
+        y[u][tj] = (ok && c < C) ? (double)Dbuf[mo + c] : 0.0;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (q0 + 4 * u >= K) break;
+#pragma unroll
+      for (int ti = 0; ti < T::I; ++ti) {
+        if (16 * ti >= C && !hopspin) continue;          // row C only for the moving spin
+#pragma unroll
+        for (int tj = 0; tj < T::J; ++tj) mfma(acc[ti][tj], x[u][ti], y[u][tj]);
+      }
+    }
+  }
+}
+
+// Adds the identity and column C (moving spin: P^T[k_h], G[j][k_h]), stages
+// the matrix row-major in `stage` ((C + 1) x (C + 2) doubles of this
+// wavefront; the caller makes sure nothing else uses it) and returns its
+// determinant by the one-wave LU.  The 16 x 16 f64 MFMA result holds
+// A[16 ti + l / 16 + 4 v][16 tj + l % 16] in slot v of lane l.
+template <int C>
+SVMC_DEV double hop_det_finish(const v4d (&acc)[DetTiles<C>::I][DetTiles<C>::J], const int* kl, int K_in,
+                               bool hopspin, int hpos_in, const double* __restrict__ PTt,
+                               const double* __restrict__ Gj, double* stage, double* prow, int lane) {
+  typedef DetTiles<C> T;
+  constexpr int RM = C + 1, RS = T::RS;
   const int K = uniform_i(K_in), hpos = uniform_i(hpos_in);
   if (K == 0) return 1.0;
-  constexpr int RM = C + 1;
-  constexpr int SD = DStride<C>::value;
-  double a[RM];
+  const int R = C + (hopspin ? 1 : 0);
+  const int r16 = lane & 15, qo = lane >> 4;
 #pragma unroll
-  for (int c = 0; c < RM; ++c) a[c] = 0.0;
-  const bool rowp = lane < C, rowg = hopspin && lane == C;
-  // eight changed rows at a time: their P^T / G loads are in flight together
-  constexpr int B = 8;
-  for (int q0 = 0; q0 < K; q0 += B) {
-    double p[B];
-    int mo[B];
+  for (int ti = 0; ti < T::I; ++ti)
 #pragma unroll
-    for (int u = 0; u < B; ++u) {
-      const int q = q0 + u;
-      const int e = q < K ? kl[q] : 0;
-      const int kq = e & 0xffff;
-      mo[u] = (e >> 16) * SD;
-      double v = 0.0;
-      if (q < K) {
-        if (rowp) v = PTt[kq * C + lane];
-        else if (rowg) v = Gj[kq] - (q == hpos ? 1.0 : 0.0);
+    for (int tj = 0; tj < T::J; ++tj)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = 16 * ti + qo + 4 * v, c = 16 * tj + r16;
+        if (r < R && c < C) stage[r * RS + c] = acc[ti][tj][v] + (r == c ? 1.0 : 0.0);
       }
-      p[u] = v;
-    }
-#pragma unroll
-    for (int u = 0; u < B; ++u) {
-      if (q0 + u >= K) break;
-      const DT* Dq = Dbuf + mo[u];
-#pragma unroll
-      for (int c = 0; c < C; ++c) a[c] = fma(p[u], (double)Dq[c], a[c]);
-    }
+  if (hopspin) {
+    const int kh = kl[hpos] & 0xffff;
+    if (lane < C) stage[lane * RS + C] = PTt[kh * C + lane];
+    else if (lane == C) stage[C * RS + C] = Gj[kh];
   }
-  const int kh = hopspin ? (kl[hpos] & 0xffff) : 0;
+  __builtin_amdgcn_wave_barrier();
+  double a[RM];
+  const double2* rp = reinterpret_cast<const double2*>(stage + (lane < R ? lane : 0) * RS);
 #pragma unroll
-  for (int c = 0; c < C; ++c) {
-    if (lane == c) a[c] += 1.0;
-    if (lane > C || (!hopspin && lane == C)) a[c] = 0.0;
+  for (int c2 = 0; c2 < RS / 2; ++c2) {
+    const double2 v = rp[c2];
+    if (2 * c2 < RM) a[2 * c2] = (lane < R && 2 * c2 < R) ? v.x : 0.0;
+    if (2 * c2 + 1 < RM) a[2 * c2 + 1] = (lane < R && 2 * c2 + 1 < R) ? v.y : 0.0;
   }
-  if (hopspin) a[C] = rowp ? PTt[kh * C + lane] : (lane == C ? Gj[kh] : 0.0);
-  else a[C] = lane == C ? 1.0 : 0.0;
-  return lu_det_rot<RM>(a, C + (hopspin ? 1 : 0), lane, prow);
+  __builtin_amdgcn_wave_barrier();
+  return lu_det_rot<RM>(a, R, lane, prow);
 }
 
 }  // namespace svmc

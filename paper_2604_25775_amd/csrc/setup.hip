@@ -71,11 +71,11 @@ __global__ __launch_bounds__(256) void k_forward_layer(LatDev lt, ModelDev md, i
   for (int nt = 0; nt < CC::NT; ++nt)
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      const int r = tile * 16 + OutMap<P>::row(lane, v);
-      const int n = nt * 16 + OutMap<P>::col(lane, v);
+      const int r = tile * 16 + OutMap<P>::site(lane, v);
+      const int n = nt * 16 + OutMap<P>::chan(lane, v);
       if (r < N && n < C) {
         const Tf z = acc[nt][v] + bias[n];
-        D[(long long)r * C + n] = S[(long long)r * C + n] + act_fn<Tf>(md.act, z);
+        D[(long long)r * C + n] = layer_out<P, Tf>(md.act, S[(long long)r * C + n], z);
       }
     }
 }

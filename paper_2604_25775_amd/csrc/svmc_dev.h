@@ -17,9 +17,12 @@ typedef _Float16 v2h __attribute__((ext_vector_type(2)));
 // PREC_BF16X3: conv multiplier inputs split exactly into three BF16 terms
 // (x = hi + mid + lo), three MFMA passes with FP32 accumulation, so the conv
 // sees FP32 activations and BF16 weights.
-// PREC_F16X2: conv multiplier inputs split into two FP16 terms by round-
-// toward-zero conversions (x = hi + lo + e, |e| < 2^-20 |x|), two MFMA passes
-// with FP32 accumulation, FP16 weights.
+// PREC_F16X2: features carried as pairs of FP16 terms: every layer output
+// (and the embedding) is rounded to hi + lo with hi = x rounded toward zero to
+// FP16 and lo = (x - hi) rounded toward zero to FP16 (22 significant bits,
+// |x - (hi + lo)| < 2^-21 |x| in FP16's normal range), so the conv inputs
+// split exactly into two FP16 MFMA passes with FP32 accumulation; FP16
+// weights.
 enum { PREC_F64 = 0, PREC_F32 = 1, PREC_BF16 = 2, PREC_BF16X3 = 3, PREC_F16X2 = 4 };
 // conv on the 16-bit matrix-core instructions (K chunks of 32)
 template <int P> struct Mma16 {
@@ -183,31 +186,59 @@ SVMC_DEV void mfma(v4f& c, v8bf a, v8bf b) {
   c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
 }
 
-// One K chunk of a 16-bit mode: this lane's 8 activations x (FP32) times the
-// B fragments b[nt], accumulated into acc[nt].  Every conv kernel goes
-// through here, so the arithmetic per output element is the same in all of
-// them.
+// FP16 pair of an FP32 value (round toward zero twice; see PREC_F16X2): hi and
+// lo of two values packed per dword.
+SVMC_DEV void pair_split2(float a, float b, unsigned& hi, unsigned& lo) {
+  const v2h h = __builtin_bit_cast(v2h, __builtin_amdgcn_cvt_pkrtz(a, b));
+  const v2h l = __builtin_bit_cast(v2h, __builtin_amdgcn_cvt_pkrtz(a - (float)h[0], b - (float)h[1]));
+  hi = __builtin_bit_cast(unsigned, h);
+  lo = __builtin_bit_cast(unsigned, l);
+}
+// hi + lo of one value (exact in FP32)
+SVMC_DEV float pair_round(float x) {
+  const v2h h = __builtin_bit_cast(v2h, __builtin_amdgcn_cvt_pkrtz(x, 0.0f));
+  const float hf = (float)h[0];
+  const v2h l = __builtin_bit_cast(v2h, __builtin_amdgcn_cvt_pkrtz(x - hf, 0.0f));
+  return hf + (float)l[0];
+}
+
+// New feature of one layer: H_l = H_{l-1} + act(z), rounded to an FP16 pair
+// in PREC_F16X2.  Every conv kernel forms its outputs here.
+template <int P, class T> SVMC_DEV T layer_out(int act, T x, T z) {
+  const T y = x + act_fn<T>(act, z);
+  if constexpr (P == PREC_F16X2) return pair_round(y);
+  return y;
+}
+
+// One K chunk of a 16-bit mode: the B fragments b[nt] (weights, the MFMA A
+// operand) times this lane's 8 activations x (FP32, the B operand),
+// accumulated into acc[nt].  Every conv kernel goes through here or through
+// the same sequence on pre-split activations, so the arithmetic per output
+// element is the same in all of them.
 template <int P, int NT>
 SVMC_DEV void mma_chunk16(v4f (&acc)[NT], const float (&x)[8], const typename PrecT<P>::Tb (&b)[NT]) {
   if constexpr (P == PREC_F16X2) {
+    // x is an FP16 pair (hi + lo): the round-toward-zero conversions recover
+    // both terms exactly
     v8h hi, lo;
 #pragma unroll
     for (int e = 0; e < 8; e += 2) {
-      const v2h h = __builtin_bit_cast(v2h, __builtin_amdgcn_cvt_pkrtz(x[e], x[e + 1]));
-      const v2h l = __builtin_bit_cast(v2h, __builtin_amdgcn_cvt_pkrtz(x[e] - (float)h[0], x[e + 1] - (float)h[1]));
-      hi[e] = h[0]; hi[e + 1] = h[1];
-      lo[e] = l[0]; lo[e + 1] = l[1];
+      unsigned h, l;
+      pair_split2(x[e], x[e + 1], h, l);
+      const v2h h2 = __builtin_bit_cast(v2h, h), l2 = __builtin_bit_cast(v2h, l);
+      hi[e] = h2[0]; hi[e + 1] = h2[1];
+      lo[e] = l2[0]; lo[e + 1] = l2[1];
     }
 #pragma unroll
-    for (int nt = 0; nt < NT; ++nt) mfma(acc[nt], hi, b[nt]);
+    for (int nt = 0; nt < NT; ++nt) mfma(acc[nt], b[nt], hi);
 #pragma unroll
-    for (int nt = 0; nt < NT; ++nt) mfma(acc[nt], lo, b[nt]);
+    for (int nt = 0; nt < NT; ++nt) mfma(acc[nt], b[nt], lo);
   } else {
     v8bf a;
 #pragma unroll
     for (int e = 0; e < 8; ++e) a[e] = (__bf16)x[e];
 #pragma unroll
-    for (int nt = 0; nt < NT; ++nt) mfma(acc[nt], a, b[nt]);
+    for (int nt = 0; nt < NT; ++nt) mfma(acc[nt], b[nt], a);
     if constexpr (P == PREC_BF16X3) {
       // remainders: x - hi is exact in FP32, and so is (x - hi) - mid
       v8bf a2, a3;
@@ -219,32 +250,35 @@ SVMC_DEV void mma_chunk16(v4f (&acc)[NT], const float (&x)[8], const typename Pr
       }
 #pragma unroll
       for (int nt = 0; nt < NT; ++nt) {
-        mfma(acc[nt], a2, b[nt]);
-        mfma(acc[nt], a3, b[nt]);
+        mfma(acc[nt], b[nt], a2);
+        mfma(acc[nt], b[nt], a3);
       }
     }
   }
 }
 
-// Output element (row, column) held in accumulator slot v of `lane` for the
-// 16x16 MFMA tiles used here (measured on gfx950):
-//   f32 16x16x4, bf16 16x16x32: row = 4*(lane/16) + v, col = lane%16
-//   f64 16x16x4:                row = lane/16 + 4*v,   col = lane%16
+// Output element held in accumulator slot v of `lane` for the 16x16 MFMA
+// tiles used here, with the weights as the A operand (rows = output channels)
+// and the activations as the B operand (columns = sites); measured on gfx950:
+//   f32 16x16x4, bf16 / f16 16x16x32: channel = 4*(lane/16) + v, site = lane%16
+//   f64 16x16x4:                      channel = lane/16 + 4*v,  site = lane%16
 // Inputs: A[i][k] from lane i + 16*(k/kpl) (kpl = k-values per lane),
 // B[k][j] from lane j + 16*(k/kpl).
 template <int P> struct OutMap {
-  SVMC_DEV static int row(int lane, int v) { return 4 * (lane >> 4) + v; }
-  SVMC_DEV static int col(int lane, int v) { return lane & 15; }
+  SVMC_DEV static int site(int lane, int v) { return lane & 15; }
+  SVMC_DEV static int chan(int lane, int v) { return 4 * (lane >> 4) + v; }
 };
 template <> struct OutMap<PREC_F64> {
-  SVMC_DEV static int row(int lane, int v) { return (lane >> 4) + 4 * v; }
-  SVMC_DEV static int col(int lane, int v) { return lane & 15; }
+  SVMC_DEV static int site(int lane, int v) { return lane & 15; }
+  SVMC_DEV static int chan(int lane, int v) { return (lane >> 4) + 4 * v; }
 };
 
 // ---------------------------------------------------------------------------
 // conv tile: 16 output sites x C output channels of
 //   acc[site][n] = sum_{tap t, c} X(site, t)[c] * K[t][c][n]
-// Lane l supplies row (l % 16) of the A operand.  nb[t] is the element offset
+// Lane l supplies site (l % 16), a column of the B operand; the weights are
+// the A operand, so acc[nt] holds acc[site][16 nt + channel] transposed (see
+// OutMap).  nb[t] is the element offset
 // (into `src`) of the C-channel feature vector of this lane's site's
 // neighbour at tap t (t = 3*ky + kx, offset (kx-1, ky-1)), or -1 for zero
 // padding.  The arithmetic per output element depends only on that element's
@@ -293,77 +327,7 @@ SVMC_DEV void conv_tile(const typename PrecT<P>::Tf* __restrict__ src, const int
       Tf a = off >= 0 ? src[off + c] : Tf(0);
 #pragma unroll
       for (int nt = 0; nt < CC::NT; ++nt)
-        mfma(acc[nt], a, Bl[(q * CC::NT + nt) * 64 + lane]);
-    }
-  }
-}
-
-// ---------------------------------------------------------------------------
-// Multi-tile conv layer for one wavefront: up to MAXT tiles of 16 output sites
-// on an LDS grid [gy][gx][C].  Each tile row's neighbours are described by
-// packed grid coordinates: byte k of gxs[t] is the grid x index of offset
-// dx = k - 1 (0xFF when off the lattice), gys[t] likewise for y (a padding row
-// has all bytes 0xFF).  The loop runs chunk-major so every B fragment is read
-// once per layer and reused by all tiles; per output element the accumulation
-// order is the same as conv_tile's, so both give identical values.
-// ---------------------------------------------------------------------------
-template <int P, int C, int MAXT>
-SVMC_DEV void conv_layer_tiles(const typename PrecT<P>::Tf* __restrict__ grid, int Gx,
-                               const unsigned (&gxs)[MAXT], const unsigned (&gys)[MAXT], int T,
-                               const typename PrecT<P>::Tb* __restrict__ Bl, int lane,
-                               typename PrecT<P>::Acc (&acc)[MAXT][ConvCfg<P, C>::NT]) {
-  typedef typename PrecT<P>::Tf Tf;
-  typedef typename PrecT<P>::Tb Tb;
-  typedef ConvCfg<P, C> CC;
-  const int g = lane >> 4;
-#pragma unroll
-  for (int t = 0; t < MAXT; ++t)
-#pragma unroll
-    for (int nt = 0; nt < CC::NT; ++nt)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) acc[t][nt][v] = 0;
-#pragma unroll
-  for (int q = 0; q < CC::Q; ++q) {
-    Tb b[CC::NT];
-#pragma unroll
-    for (int nt = 0; nt < CC::NT; ++nt) b[nt] = Bl[(q * CC::NT + nt) * 64 + lane];
-    int tap, c0;
-    bool kok;
-    if constexpr (Mma16<P>::value) {
-      const int k0 = 32 * q + 8 * g;
-      kok = k0 < CC::K;
-      tap = kok ? k0 / C : 0;
-      c0 = k0 % C;
-    } else {
-      kok = true;
-      tap = (4 * q) / C;
-      c0 = (4 * q) % C + g;
-    }
-    const int sx = 8 * (tap % 3), sy = 8 * (tap / 3);
-#pragma unroll
-    for (int t = 0; t < MAXT; ++t) {
-      if (t < T) {
-        const unsigned gx = (gxs[t] >> sx) & 0xFFu, gy = (gys[t] >> sy) & 0xFFu;
-        const bool ok = kok && gx != 0xFFu && gy != 0xFFu;
-        const int off = ((int)gy * Gx + (int)gx) * C + c0;
-        if constexpr (Mma16<P>::value) {
-          float x[8];
-          if (ok) {
-            const float4* p4 = reinterpret_cast<const float4*>(grid + off);
-            const float4 x0 = p4[0], x1 = p4[1];
-            x[0] = x0.x; x[1] = x0.y; x[2] = x0.z; x[3] = x0.w;
-            x[4] = x1.x; x[5] = x1.y; x[6] = x1.z; x[7] = x1.w;
-          } else {
-#pragma unroll
-            for (int e = 0; e < 8; ++e) x[e] = 0.0f;
-          }
-          mma_chunk16<P, CC::NT>(acc[t], x, b);
-        } else {
-          const Tf a = ok ? grid[off] : Tf(0);
-#pragma unroll
-          for (int nt = 0; nt < CC::NT; ++nt) mfma(acc[t][nt], a, b[nt]);
-        }
-      }
+        mfma(acc[nt], Bl[(q * CC::NT + nt) * 64 + lane], a);
     }
   }
 }

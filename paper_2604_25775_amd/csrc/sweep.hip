@@ -217,12 +217,19 @@ __global__ __launch_bounds__(64 * SW_NW) void k_sweep(ModelDev md, const LatDev*
     int olx, owx, oly, owy;
     hop_features<P, C, NW>(md, lt, g, occ_s, featw, (Tf*)nullptr, scratch, hsc, olx, owx, oly, owy);
     int K = 0, hpos = -1;
+    const int wd = wv < 2 ? wv : 0;           // spin of this wavefront's determinant
+    const double* PTt = PTw + (long long)wd * nm * C;
+    const double* Gj = Gw + ((long long)wd * N + g.j) * nm;
+    v4d dacc[DetTiles<C>::I][DetTiles<C>::J];
     if (wv < 2) {
       K = hop_klist(lt, g, occ_s, lab_s, wv, olx, owx, oly, owy, klb + wv * KM, hpos, lane);
+      hop_det_build<C>(klb + wv * KM, K, wv == sp, hpos, Dbuf, PTt, Gj, lane, dacc);
+    }
+    __syncthreads();      // both matrices built: their staging may overwrite D
+    if (wv < 2) {
       double* prow = (double*)(scratch + hsc.prow) + wv * 64;
-      const double* PTt = PTw + (long long)wv * nm * C;
-      const double* Gj = Gw + ((long long)wv * N + g.j) * nm;
-      const double Rt = hop_det<C>(klb + wv * KM, K, wv == sp, hpos, Dbuf, PTt, Gj, prow, lane);
+      double* stage = (double*)scratch + wv * (C + 1) * DetTiles<C>::RS;
+      const double Rt = hop_det_finish<C>(dacc, klb + wv * KM, K, wv == sp, hpos, PTt, Gj, stage, prow, lane);
       if (lane == 0) {
         misc[wv] = Rt;
         misc[2 + wv] = (double)K;

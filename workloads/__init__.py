@@ -224,9 +224,33 @@ def quantise_params(p: Params, prec: str) -> Params:
         a = torch.from_numpy(getattr(q, name)).to(dt).to(torch.float64).numpy()
         setattr(q, name, a)
     if prec == "f16x2":
-        # FP16 conv weights (from their FP32 value), FP32 embedding and bias
-        q.conv_w = torch.from_numpy(q.conv_w).to(torch.float16).to(torch.float64).numpy()
+        # the BF16 conv weights carried in FP16 (exact in FP16's normal range),
+        # the embedding as an FP16 pair, FP32 bias
+        w16 = torch.from_numpy(p.conv_w).to(torch.bfloat16).to(torch.float16)
+        q.conv_w = w16.to(torch.float64).numpy()
+        q.embed = f16_pair(q.embed)
     return q
+
+
+def f16_rtz(x: np.ndarray) -> np.ndarray:
+    """FP32 values rounded toward zero to FP16 (11 significant bits in FP16's
+    normal range, multiples of 2^-24 below it, at most 65504), as FP32."""
+    x = np.asarray(x, dtype=np.float32)
+    a = np.abs(x)
+    bits = a.view(np.uint32) & np.uint32(0xFFFFE000)
+    r = np.minimum(bits.view(np.float32), np.float32(65504.0))
+    sub = np.trunc(a.astype(np.float64) * 2.0 ** 24) * 2.0 ** -24
+    r = np.where(a >= np.float32(2.0 ** -14), r, sub.astype(np.float32))
+    return np.copysign(r, x).astype(np.float32)
+
+
+def f16_pair(x: np.ndarray) -> np.ndarray:
+    """FP16 pair value hi + lo of FP32(x) (hi = f16_rtz(x), lo = f16_rtz(x -
+    hi)), widened to FP64: the features of the f16x2 mode."""
+    x = np.asarray(x, dtype=np.float64).astype(np.float32)
+    h = f16_rtz(x)
+    lo = f16_rtz((x - h).astype(np.float32))
+    return (h.astype(np.float64) + lo.astype(np.float64))
 
 
 # --------------------------------------------------------------------------
