@@ -139,7 +139,6 @@ __global__ __launch_bounds__(64 * ELOC_NW) __attribute__((amdgpu_waves_per_eu(3)
   const int KM = lt.Gx * lt.Gy;
   const HopScratch hsc = hop_scratch(lt.Gx, lt.Gy, md.L, C, (int)sizeof(Tf));
   int* kl = (int*)(scratch + hsc.klists) + wv * KM;
-  double* prow = (double*)(scratch + hsc.prow) + wv * 64;
   double* misc = (double*)(scratch + hsc.misc);
 
   double part = 0.0;
@@ -163,7 +162,7 @@ __global__ __launch_bounds__(64 * ELOC_NW) __attribute__((amdgpu_waves_per_eu(3)
       hop_det_build<C>(kl, K, wv == sp, hpos, (const typename DType<P>::type*)scratch, PTt, Gj, lane, dacc);
       __syncthreads();      // both matrices built: their staging may overwrite D
       double* stage = (double*)scratch + wv * (C + 1) * DetTiles<C>::RS;
-      const double Rt = hop_det_finish<C>(dacc, kl, K, wv == sp, hpos, PTt, Gj, stage, prow, lane);
+      const double Rt = hop_det_finish<C>(dacc, kl, K, wv == sp, hpos, PTt, Gj, stage, lane);
       if (lane == 0) misc[wv] = Rt;
       __syncthreads();
       if (tid == 0) {

@@ -108,11 +108,10 @@ template <int C> struct DStride {
 //                           last layer, D = H'_L - H_L densely as Tf [m][C + 4];
 //                           once both determinant matrices are built, their
 //                           row-major copies [2][C + 1][C + 2] f64
-//   prow   [2][64] f64      pivot-row broadcast of the two determinant waves
 //   klists [2][Gx Gy] int   changed-row lists per spin
 //   misc   64 bytes         per-spin results
 struct HopScratch {
-  int prow, klists, misc, bytes;
+  int klists, misc, bytes;
 };
 __host__ __device__ inline int align16i(int x) { return (x + 15) & ~15; }
 __host__ __device__ inline HopScratch hop_scratch(int Gx, int Gy, int L, int C, int tfb) {
@@ -122,8 +121,7 @@ __host__ __device__ inline HopScratch hop_scratch(int Gx, int Gy, int L, int C, 
   const int gb = Gx * Gy * SP * tfb, db = ox * oy * (C + 4) * tfb;
   const int sb = 2 * (C + 1) * (C + 2) * 8;     // two determinant stagings
   const int rb = gb > db ? gb : db;
-  h.prow = align16i(rb > sb ? rb : sb);
-  h.klists = h.prow + 2 * 64 * 8;
+  h.klists = align16i(rb > sb ? rb : sb);
   h.misc = h.klists + align16i(2 * Gx * Gy * 4);
   h.bytes = h.misc + 64;
   return h;
@@ -506,62 +504,53 @@ SVMC_DEV double rcp_d(double x) {
   return r;
 }
 
-// One-wave LU determinant of an r x r FP64 matrix, r <= RM <= 64.
-// Lane a (< r) holds row a in a[0..RM).  Columns rotate: at every step the
-// current pivot column is a[0] and the remaining columns shift left, so all
-// register indices stay static in a runtime step loop.  Partial pivoting
-// without moving rows: the unused row with the largest |a[0]| pivots (the
-// search compares |a| rounded to FP32, ties to the lower lane; pivots below
-// FP32's smallest denormal count as zero).  The pivot lane writes its row to
-// `prow` (LDS, RM doubles of this wavefront) and every lane reads it back as
-// a broadcast; only the columns still in play are written and updated, eight
-// at a time.  LDS operations of one wavefront complete in order, so no wait
-// is needed between the write and the reads.
-// det = sign(permutation) * prod(pivots).
+// One-wave LU determinant of an RM x RM FP64 matrix held one row per lane
+// (lanes < RM; lanes >= RM take no part), all RM elimination steps unrolled
+// so that column counts are static and the code has no branches on them.
+// Partial pivoting without moving rows: at step p the unused row with the
+// largest |a[p]| pivots (the search compares |a| rounded to FP32, ties to
+// the lower lane; a pivot column below FP32's smallest denormal makes the
+// matrix count as singular and the result 0).  The pivot row reaches the
+// other lanes by lane reads (its own multiplier is zero, so it does not
+// change during the step).  Each step first updates the next pivot column
+// and starts its search, then the remaining columns, so the search overlaps
+// the update.  det = sign(permutation) * prod(pivots).
+SVMC_DEV unsigned piv_key(double v, bool used, int lane) {
+  return used ? 0u : ((__float_as_uint((float)fabs(v)) & ~63u) | (unsigned)(63 - lane));
+}
 template <int RM>
-SVMC_DEV double lu_det_rot(double (&a)[RM], int r_in, int lane, double* prow) {
-  const int r = uniform_i(r_in);
-  bool used = lane >= r;
+SVMC_DEV double lu_det_unrolled(double (&a)[RM], int lane) {
+  bool used = lane >= RM;
   int step = 64;
   double det = 1.0;
-  for (int p = 0; p < r; ++p) {
-    const double cp = a[0];
-    const unsigned key0 = used ? 0u : ((__float_as_uint((float)fabs(cp)) & ~63u) | (unsigned)(63 - lane));
-    const unsigned key = wave_max_u32(key0);
-    if ((key & ~63u) == 0u) return 0.0;
-    const int piv = 63 - (int)(key & 63u);
-    const double pv = readlane_d(cp, piv);
+  bool sing = false;
+  unsigned kmax = wave_max_u32(piv_key(a[0], used, lane));
+#pragma unroll
+  for (int p = 0; p < RM; ++p) {
+    sing = sing || (kmax & ~63u) == 0u;
+    const int piv = 63 - (int)(kmax & 63u);
+    const double pv = readlane_d(a[p], piv);
     det *= pv;
-    const int live = r - 1 - p;               // columns right of the pivot
     if (lane == piv) {
       used = true;
       step = p;
-#pragma unroll
-      for (int c0 = 1; c0 < RM; c0 += 8) {
-        if (c0 <= live) {
-#pragma unroll
-          for (int c = c0; c < c0 + 8 && c < RM; ++c) prow[c - 1] = a[c];
-        }
-      }
     }
-    __builtin_amdgcn_wave_barrier();
-    const double l = used ? 0.0 : cp * rcp_d(pv);
+    if (p + 1 < RM) {
+      const double l = used ? 0.0 : a[p] * rcp_d(sing ? 1.0 : pv);
+      a[p + 1] = fma(-l, readlane_d(a[p + 1], piv), a[p + 1]);
+      kmax = wave_max_u32(piv_key(a[p + 1], used, lane));
 #pragma unroll
-    for (int c0 = 1; c0 < RM; c0 += 8) {
-      if (c0 <= live) {
-#pragma unroll
-        for (int c = c0; c < c0 + 8 && c < RM; ++c) a[c - 1] = fma(-l, prow[c - 1], a[c]);
-      }
+      for (int c = p + 2; c < RM; ++c) a[c] = fma(-l, readlane_d(a[c], piv), a[c]);
     }
-    __builtin_amdgcn_wave_barrier();
   }
-  // parity of the pivot order: inversions among the lanes' pivot steps
   int inv = 0;
-  for (int b = 0; b < r; ++b) {
+#pragma unroll 1
+  for (int b = 0; b < RM; ++b) {
     const int sb = __builtin_amdgcn_readlane(step, b);
-    if (lane < r && b > lane && sb < step) ++inv;
+    if (lane < RM && b > lane && sb < step) ++inv;
   }
   const unsigned long long odd = __ballot(inv & 1);
+  if (sing) return 0.0;
   return (__popcll(odd) & 1) ? -det : det;
 }
 
@@ -638,7 +627,7 @@ SVMC_DEV void hop_det_build(const int* kl, int K_in, bool hopspin, int hpos_in, 
 template <int C>
 SVMC_DEV double hop_det_finish(const v4d (&acc)[DetTiles<C>::I][DetTiles<C>::J], const int* kl, int K_in,
                                bool hopspin, int hpos_in, const double* __restrict__ PTt,
-                               const double* __restrict__ Gj, double* stage, double* prow, int lane) {
+                               const double* __restrict__ Gj, double* stage, int lane) {
   typedef DetTiles<C> T;
   constexpr int RM = C + 1, RS = T::RS;
   const int K = uniform_i(K_in), hpos = uniform_i(hpos_in);
@@ -660,6 +649,8 @@ SVMC_DEV double hop_det_finish(const v4d (&acc)[DetTiles<C>::I][DetTiles<C>::J],
     else if (lane == C) stage[C * RS + C] = Gj[kh];
   }
   __builtin_amdgcn_wave_barrier();
+  // rows in lanes < RM; the spin that does not move gets an identity row and
+  // column C (same determinant), so both matrices take the same RM steps
   double a[RM];
   const double2* rp = reinterpret_cast<const double2*>(stage + (lane < R ? lane : 0) * RS);
 #pragma unroll
@@ -668,8 +659,9 @@ SVMC_DEV double hop_det_finish(const v4d (&acc)[DetTiles<C>::I][DetTiles<C>::J],
     if (2 * c2 < RM) a[2 * c2] = (lane < R && 2 * c2 < R) ? v.x : 0.0;
     if (2 * c2 + 1 < RM) a[2 * c2 + 1] = (lane < R && 2 * c2 + 1 < R) ? v.y : 0.0;
   }
+  if (!hopspin && lane == C) a[C] = 1.0;
   __builtin_amdgcn_wave_barrier();
-  return lu_det_rot<RM>(a, R, lane, prow);
+  return lu_det_unrolled<RM>(a, lane);
 }
 
 }  // namespace svmc

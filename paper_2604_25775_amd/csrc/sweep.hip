@@ -227,9 +227,8 @@ __global__ __launch_bounds__(64 * SW_NW) void k_sweep(ModelDev md, const LatDev*
     }
     __syncthreads();      // both matrices built: their staging may overwrite D
     if (wv < 2) {
-      double* prow = (double*)(scratch + hsc.prow) + wv * 64;
       double* stage = (double*)scratch + wv * (C + 1) * DetTiles<C>::RS;
-      const double Rt = hop_det_finish<C>(dacc, klb + wv * KM, K, wv == sp, hpos, PTt, Gj, stage, prow, lane);
+      const double Rt = hop_det_finish<C>(dacc, klb + wv * KM, K, wv == sp, hpos, PTt, Gj, stage, lane);
       if (lane == 0) {
         misc[wv] = Rt;
         misc[2 + wv] = (double)K;
