@@ -247,12 +247,58 @@ SVMC_DEV void grid_put4(typename PrecT<P>::Tf* grid, int site, int n0, const flo
     *reinterpret_cast<float4*>(grid + site * SP + n0) = v;
 }
 
+// Per-hop coordinate table of one wavefront, one entry per lane: for the 16
+// unwrapped coordinates u = base + k of each axis (base = the hop's lower
+// changed coordinate minus L + 2, enough for the layer-(L+1) box and its
+// neighbours when L <= 4, also on axes shorter than 2L + 4), lane k holds for x and lane 16 + k for y the grid
+// indices of u - 1, u, u + 1 in bytes 0, 1, 2 (0xFF off an open edge); lanes
+// 32 + k and 48 + k hold the lattice coordinates of u.  Looked up with one
+// lane permute instead of the wrap and clip arithmetic per site; lookups run
+// with all lanes of the wavefront active.
+struct AxisTab {
+  int v;          // this lane's entry
+  int bx, by;     // base coordinates (uniform)
+};
+SVMC_DEV AxisTab axis_tab(const HopGeom& h, int L, int lane) {
+  AxisTab t;
+  t.bx = h.xi + min(0, h.dx) - (L + 2);
+  t.by = h.yi + min(0, h.dy) - (L + 2);
+  const bool isy = (lane >> 4) & 1;
+  const Axis a = isy ? h.ay : h.ax;
+  const int u = (isy ? t.by : t.bx) + (lane & 15);
+  int v;
+  if (lane < 32) {
+    v = 0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const int uu = u + k - 1;
+      // (bytes of coordinates outside the grid hold junk that no box site reads)
+      v |= ((inlat(a, uu) ? gidx(a, uu) : 0xFF) & 0xFF) << (8 * k);
+    }
+  } else {
+    v = inlat(a, u) ? latc(a, u) : 0;
+  }
+  t.v = v;
+  return t;
+}
+SVMC_DEV int tab_get(const AxisTab& t, int idx) { return __builtin_amdgcn_ds_bpermute(4 * idx, t.v); }
+// neighbour grid indices of unwrapped (ux, uy): bytes as in the table
+SVMC_DEV unsigned tab_gx(const AxisTab& t, int ux) { return (unsigned)tab_get(t, ux - t.bx) & 0xFFFFFFu; }
+SVMC_DEV unsigned tab_gy(const AxisTab& t, int uy) { return (unsigned)tab_get(t, 16 + uy - t.by) & 0xFFFFFFu; }
+SVMC_DEV int tab_site(const AxisTab& t, int ux, int uy, int Lx) {
+  return tab_get(t, 32 + ux - t.bx) + Lx * tab_get(t, 48 + uy - t.by);
+}
+
 // Incremental conv stack for one hop, computed by the NW wavefronts of the
 // workgroup (wave = this thread's wavefront).  On return (after a barrier)
 // the scratch starts with D = H'_L - H_L on the layer-L box as Tf
 // [m][C + 4] (index m = ox + owx * oy).  If `commit` is non-null every new layer value is
 // also stored into the cache (accepted move); commit may equal featw (the
 // box of a layer never overlaps the ring read from the cache for the next).
+// Each layer: the wave's tiles are convolved, the next layer's B fragments
+// are requested, the new values are formed (still in registers), a barrier,
+// then they replace the layer input on the grid and the ring of the next
+// input box is filled from the cache.
 template <int P, int C, int NW>
 SVMC_DEV void hop_features(const ModelDev& md, const LatDev& lt, const HopGeom& h, const int8_t* occ_s,
                            const typename PrecT<P>::Tf* featw,
@@ -278,6 +324,21 @@ SVMC_DEV void hop_features(const ModelDev& md, const LatDev& lt, const HopGeom& 
   const int bit = 1 << h.sigma;
   constexpr int V = 16 / sizeof(Tf);          // elements per 16-byte vector
   constexpr int CV = C / V;
+  constexpr int QB = RegB<P, C>::value ? CC::Q : 1;
+  const AxisTab tab = axis_tab(h, L, lane);
+  // B fragments of layer 1 (when held in registers), requested before the
+  // embedding fill
+  Tb breg[QB][CC::NT];
+  auto load_b = [&](int l) {
+    if constexpr (RegB<P, C>::value) {
+      const Tb* Bl = (const Tb*)md.Bpack + (long long)(l - 1) * CC::Q * CC::NT * 64;
+#pragma unroll
+      for (int q = 0; q < CC::Q; ++q)
+#pragma unroll
+        for (int nt = 0; nt < CC::NT; ++nt) breg[q][nt] = Bl[(q * CC::NT + nt) * 64 + lane];
+    }
+  };
+  load_b(1);
   // layer-1 input: embedding of the new configuration on the layer-1 input
   // box (layer-1 output box grown by one site)
   {
@@ -287,15 +348,19 @@ SVMC_DEV void hop_features(const ModelDev& md, const LatDev& lt, const HopGeom& 
     const Tf* E = (const Tf*)md.embed;
     const int mw = kMagic16[wx];
     const int tot = wx * wy * CV;
-    for (int e = tid; e < tot; e += NT_) {
+    for (int e0 = 0; e0 < tot; e0 += NT_) {
+      // table lookups with every lane active (a permute reads nothing useful
+      // from a disabled lane)
+      const int e = e0 + tid;
       const int q = e / CV, cv = e - q * CV;
       int ux, uy;
       box_site(q, lx, wx, mw, ly, ux, uy);
-      const int s = latc(ax, ux) + Lx * latc(ay, uy);
+      const int s = tab_site(tab, ux, uy, Lx);
+      const int site = (int)((tab_gy(tab, uy) >> 8) & 0xFFu) * Gx + (int)((tab_gx(tab, ux) >> 8) & 0xFFu);
+      if (e >= tot) continue;
       int o = occ_s[s];
       if (s == h.i) o -= bit;
       if (s == h.j) o += bit;
-      const int site = gidx(ay, uy) * Gx + gidx(ax, ux);
       if constexpr (PL)
         grid_put4<P, C>(grid, site, cv * V, *reinterpret_cast<const float4*>(E + o * C + cv * V));
       else
@@ -303,7 +368,6 @@ SVMC_DEV void hop_features(const ModelDev& md, const LatDev& lt, const HopGeom& 
     }
   }
   __syncthreads();
-  constexpr int QB = RegB<P, C>::value ? CC::Q : 1;
   for (int l = 1; l <= L; ++l) {
     box1(ax, h.xi, h.dx, l, olx, owx);
     box1(ay, h.yi, h.dy, l, oly, owy);
@@ -311,61 +375,56 @@ SVMC_DEV void hop_features(const ModelDev& md, const LatDev& lt, const HopGeom& 
     const int mow = kMagic16[owx];
     const int T = (cnt + 15) >> 4;
     const Tb* Bl = (const Tb*)md.Bpack + (long long)(l - 1) * CC::Q * CC::NT * 64;
-    Tb breg[QB][CC::NT];
-    if constexpr (RegB<P, C>::value) {
-      if (wave < T) {
-#pragma unroll
-        for (int q = 0; q < CC::Q; ++q)
-#pragma unroll
-          for (int nt = 0; nt < CC::NT; ++nt) breg[q][nt] = Bl[(q * CC::NT + nt) * 64 + lane];
-      }
-    }
     const Tf* bias = (const Tf*)md.bias + (l - 1) * C;
-    // Each wave keeps its tiles' new values in registers until every wave
-    // has finished reading the grid of this layer (at most 7 tiles: the
-    // layer-L box of L <= 4 has at most 10 x 10 sites).  The lane's site is
-    // the same in all four slots v (OutMap).
+    // Each wave keeps its tiles' results in registers until every wave has
+    // finished reading the grid of this layer (at most 7 tiles: the layer-L
+    // box of L <= 4 has at most 10 x 10 sites).  The lane's site is the same
+    // in all four slots v (OutMap).
     constexpr int MAXT = (7 + NW - 1) / NW;
-    Tf outv[MAXT][CC::NT][4];
+    Acc acc[MAXT][CC::NT];
+    int gsite[MAXT];               // grid record of the lane's site, -1 for padding rows
+#pragma unroll
+    for (int ti = 0; ti < MAXT; ++ti) {
+      const int t = wave + NW * ti;
+      gsite[ti] = -1;
+      if (t >= T) break;
+      const int m = 16 * t + (lane & 15);
+      unsigned px = 0xFFFFFFu, py = 0xFFFFFFu;
+      int ux, uy;
+      box_site(m, olx, owx, mow, oly, ux, uy);
+      const unsigned tx = tab_gx(tab, ux), ty = tab_gy(tab, uy);
+      if (m < cnt) {
+        px = tx;
+        py = ty;
+        gsite[ti] = (int)((ty >> 8) & 0xFFu) * Gx + (int)((tx >> 8) & 0xFFu);
+      }
+      conv_tile_grid<P, C>(grid, Gx, px, py, breg, Bl, lane, acc[ti]);
+    }
+    // the next layer's B fragments are in flight during the rest of this one
+    if (l < L) load_b(l + 1);
+    // H'_l = H'_{l-1} + act(conv + b); the residual is this site's own grid value
 #pragma unroll
     for (int ti = 0; ti < MAXT; ++ti) {
       const int t = wave + NW * ti;
       if (t >= T) break;
-      const int m = 16 * t + (lane & 15);
-      unsigned px = 0xFFFFFFu, py = 0xFFFFFFu;
-      int gofs = 0;
-      if (m < cnt) {
-        int ux, uy;
-        box_site(m, olx, owx, mow, oly, ux, uy);
-        px = 0;
-        py = 0;
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-          const int nx = ux + k - 1, ny = uy + k - 1;
-          px |= (inlat(ax, nx) ? (unsigned)gidx(ax, nx) : 0xFFu) << (8 * k);
-          py |= (inlat(ay, ny) ? (unsigned)gidx(ay, ny) : 0xFFu) << (8 * k);
-        }
-        gofs = (gidx(ay, uy) * Gx + gidx(ax, ux)) * SP;
-      }
-      Acc acc[CC::NT];
-      conv_tile_grid<P, C>(grid, Gx, px, py, breg, Bl, lane, acc);
-      // H'_l = H'_{l-1} + act(conv + b); the residual is this site's own grid value
+      const bool on = gsite[ti] >= 0;
+      const int gofs = on ? gsite[ti] * SP : 0;
 #pragma unroll
       for (int nt = 0; nt < CC::NT; ++nt) {
         if constexpr (PL) {
           const int n0 = 16 * nt + OutMap<P>::chan(lane, 0);
           float x[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-          if (m < cnt && n0 < C) planes_get4<C>(reinterpret_cast<const char*>(grid + gofs), n0, x);
+          if (on && n0 < C) planes_get4<C>(reinterpret_cast<const char*>(grid + gofs), n0, x);
 #pragma unroll
           for (int v = 0; v < 4; ++v)
-            outv[ti][nt][v] = (m < cnt && n0 < C) ? layer_out<P, float>(md.act, x[v], acc[nt][v] + bias[n0 + v]) : 0.0f;
+            acc[ti][nt][v] = (on && n0 < C) ? layer_out<P, float>(md.act, x[v], acc[ti][nt][v] + bias[n0 + v]) : 0.0f;
         } else {
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
             const int n = 16 * nt + OutMap<P>::chan(lane, v);
             Tf val = Tf(0);
-            if (m < cnt && n < C) val = layer_out<P, Tf>(md.act, grid[gofs + n], Tf(acc[nt][v] + bias[n]));
-            outv[ti][nt][v] = val;
+            if (on && n < C) val = layer_out<P, Tf>(md.act, grid[gofs + n], Tf(acc[ti][nt][v] + bias[n]));
+            acc[ti][nt][v] = val;
           }
         }
       }
@@ -377,19 +436,19 @@ SVMC_DEV void hop_features(const ModelDev& md, const LatDev& lt, const HopGeom& 
       const int t = wave + NW * ti;
       if (t >= T) break;
       const int r = 16 * t + (lane & 15);
-      if (r >= cnt) continue;
       int ux, uy;
       box_site(r, olx, owx, mow, oly, ux, uy);
-      const int s = latc(ax, ux) + Lx * latc(ay, uy);
+      const int s = tab_site(tab, ux, uy, Lx);     // every lane active
+      if (gsite[ti] < 0) continue;
       if (l < L) {
         // H'_l replaces H'_{l-1} on the box (and goes to the cache on accept)
-        const int site = gidx(ay, uy) * Gx + gidx(ax, ux);
+        const int site = gsite[ti];
 #pragma unroll
         for (int nt = 0; nt < CC::NT; ++nt) {
           if constexpr (PL) {
             const int n0 = 16 * nt + OutMap<P>::chan(lane, 0);
             if (n0 >= C) continue;
-            const float4 v4 = {outv[ti][nt][0], outv[ti][nt][1], outv[ti][nt][2], outv[ti][nt][3]};
+            const float4 v4 = {acc[ti][nt][0], acc[ti][nt][1], acc[ti][nt][2], acc[ti][nt][3]};
             grid_put4<P, C>(grid, site, n0, v4);
             if (commit) *reinterpret_cast<float4*>(commit + ((long long)(l - 1) * N + s) * C + n0) = v4;
           } else {
@@ -397,8 +456,8 @@ SVMC_DEV void hop_features(const ModelDev& md, const LatDev& lt, const HopGeom& 
             for (int v = 0; v < 4; ++v) {
               const int n = 16 * nt + OutMap<P>::chan(lane, v);
               if (n >= C) continue;
-              grid[site * SP + n] = outv[ti][nt][v];
-              if (commit) commit[((long long)(l - 1) * N + s) * C + n] = outv[ti][nt][v];
+              grid[site * SP + n] = acc[ti][nt][v];
+              if (commit) commit[((long long)(l - 1) * N + s) * C + n] = acc[ti][nt][v];
             }
           }
         }
@@ -414,8 +473,8 @@ SVMC_DEV void hop_features(const ModelDev& md, const LatDev& lt, const HopGeom& 
             if (n >= C) continue;
             const long long gi = (long long)s * C + n;
             const Tf old = HL[gi];
-            D[r * DStride<C>::value + n] = (DT)((double)outv[ti][nt][v] - (double)old);
-            if (commit) commit[(long long)(L - 1) * N * C + gi] = outv[ti][nt][v];
+            D[r * DStride<C>::value + n] = (DT)((double)acc[ti][nt][v] - (double)old);
+            if (commit) commit[(long long)(L - 1) * N * C + gi] = acc[ti][nt][v];
           }
       }
     }
@@ -439,9 +498,10 @@ SVMC_DEV void hop_features(const ModelDev& md, const LatDev& lt, const HopGeom& 
           const int q = e / CV, cv = e - q * CV;
           int ux, uy;
           box_site(q, ilx, iwx, miw, ily, ux, uy);
+          const int s = tab_site(tab, ux, uy, Lx);
+          const int site = (int)((tab_gy(tab, uy) >> 8) & 0xFFu) * Gx + (int)((tab_gx(tab, ux) >> 8) & 0xFFu);
           const bool ok = e < tot && !(inbox(ax, olx, owx, ux) && inbox(ay, oly, owy, uy));
-          const int s = ok ? latc(ax, ux) + Lx * latc(ay, uy) : 0;
-          dst[u] = ok ? (gidx(ay, uy) * Gx + gidx(ax, ux)) * 256 + cv * V : -1;
+          dst[u] = ok ? site * 256 + cv * V : -1;
           val[u] = ok ? *reinterpret_cast<const float4*>(Hl + (long long)s * C + cv * V) : float4{0, 0, 0, 0};
         }
 #pragma unroll
