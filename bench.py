@@ -16,7 +16,12 @@ VJP of log|psi| over the batch, the full-recompute path on the same walkers
 (speed-up), the oracle on host cores (cpu_baseline), and the roofline
 position of the dominant kernel from HIP events on its stream.
 
-    python bench.py [--gpus 1] [--steps 10] [--warmup 2] [--prec bf16x3]
+The conv runs in f16x2 by default: the workload's BF16 weights (exact in
+FP16) on the FP16 matrix units, features carried as FP16 pairs (22
+significant bits), FP32 accumulation; --prec bf16x3 gives exact FP32
+activations at one more pass.
+
+    python bench.py [--gpus 1] [--steps 10] [--warmup 2] [--prec f16x2]
 """
 from __future__ import annotations
 
@@ -195,7 +200,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="c3")
-    ap.add_argument("--prec", default="bf16x3", choices=["bf16", "bf16x3", "f16x2", "f32", "f64"])
+    ap.add_argument("--prec", default="f16x2", choices=["bf16", "bf16x3", "f16x2", "f32", "f64"])
     ap.add_argument("--walkers", type=int, default=None)
     ap.add_argument("--full-walkers", type=int, default=None,
                     help="walkers for the full-recompute timing (default: all)")
