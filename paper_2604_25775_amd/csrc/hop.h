@@ -104,7 +104,8 @@ template <int C> struct DStride {
 };
 
 // LDS scratch of one hop, in bytes:
-//   grid   [Gy][Gx][SP] Tf  features of one layer on the update box; after the
+//   grid   [Gy][Gx][SP] Tf  features of one layer on the update box, then one
+//                           all-zero record (the conv's zero padding); after the
 //                           last layer, D = H'_L - H_L densely as Tf [m][C + 4];
 //                           once both determinant matrices are built, their
 //                           row-major copies [2][C + 1][C + 2] f64
@@ -118,7 +119,7 @@ __host__ __device__ inline HopScratch hop_scratch(int Gx, int Gy, int L, int C, 
   HopScratch h;
   const int SP = C + 16 / tfb;
   const int ox = Gx < 2 * L + 2 ? Gx : 2 * L + 2, oy = Gy < 2 * L + 2 ? Gy : 2 * L + 2;
-  const int gb = Gx * Gy * SP * tfb, db = ox * oy * (C + 4) * tfb;
+  const int gb = (Gx * Gy + 1) * SP * tfb, db = ox * oy * (C + 4) * tfb;
   const int sb = 2 * (C + 1) * (C + 2) * 8;     // two determinant stagings
   const int rb = gb > db ? gb : db;
   h.klists = align16i(rb > sb ? rb : sb);
@@ -166,7 +167,7 @@ template <int C> SVMC_DEV void planes_get4(const char* rec, int n0, float (&x)[4
 // element the accumulation order equals conv_tile's (chunk by chunk; in the
 // split modes all output tiles of one term before the next term).
 template <int P, int C>
-SVMC_DEV void conv_tile_grid(const typename PrecT<P>::Tf* __restrict__ grid, int Gx, unsigned px, unsigned py,
+SVMC_DEV void conv_tile_grid(const typename PrecT<P>::Tf* __restrict__ grid, int Gx, int zsite, unsigned px, unsigned py,
                              const typename PrecT<P>::Tb (&breg)[RegB<P, C>::value ? ConvCfg<P, C>::Q : 1]
                                                                [ConvCfg<P, C>::NT],
                              const typename PrecT<P>::Tb* __restrict__ Bl, int lane,
@@ -201,15 +202,13 @@ SVMC_DEV void conv_tile_grid(const typename PrecT<P>::Tf* __restrict__ grid, int
       c0 = (4 * q) % C + g;
     }
     const unsigned gx = (px >> (8 * (tap % 3))) & 0xFFu, gy = (py >> (8 * (tap / 3))) & 0xFFu;
+    // zero padding reads the all-zero record: the loads need no branch
     const bool ok = kok && gx != 0xFFu && gy != 0xFFu;
-    const int site = (int)gy * Gx + (int)gx;
+    const int site = ok ? (int)gy * Gx + (int)gx : zsite;
     if constexpr (GridPlanes<P>::value) {
-      v8h hi = {}, lo = {};
-      if (ok) {
-        const char* rec = reinterpret_cast<const char*>(grid) + site * SP * (int)sizeof(Tf) + 2 * c0;
-        hi = *reinterpret_cast<const v8h*>(rec);
-        lo = *reinterpret_cast<const v8h*>(rec + 2 * C);
-      }
+      const char* rec = reinterpret_cast<const char*>(grid) + site * SP * (int)sizeof(Tf) + 2 * c0;
+      const v8h hi = *reinterpret_cast<const v8h*>(rec);
+      const v8h lo = *reinterpret_cast<const v8h*>(rec + 2 * C);
 #pragma unroll
       for (int nt = 0; nt < CC::NT; ++nt) mfma(acc[nt], b[nt], hi);
 #pragma unroll
@@ -217,19 +216,14 @@ SVMC_DEV void conv_tile_grid(const typename PrecT<P>::Tf* __restrict__ grid, int
     } else if constexpr (Mma16<P>::value) {
       const int off = site * SP + c0;
       float x[8];
-      if (ok) {
-        const float4* p4 = reinterpret_cast<const float4*>(grid + off);
-        const float4 x0 = p4[0], x1 = p4[1];
-        x[0] = x0.x; x[1] = x0.y; x[2] = x0.z; x[3] = x0.w;
-        x[4] = x1.x; x[5] = x1.y; x[6] = x1.z; x[7] = x1.w;
-      } else {
-#pragma unroll
-        for (int e = 0; e < 8; ++e) x[e] = 0.0f;
-      }
+      const float4* p4 = reinterpret_cast<const float4*>(grid + off);
+      const float4 x0 = p4[0], x1 = p4[1];
+      x[0] = x0.x; x[1] = x0.y; x[2] = x0.z; x[3] = x0.w;
+      x[4] = x1.x; x[5] = x1.y; x[6] = x1.z; x[7] = x1.w;
       mma_chunk16<P, CC::NT>(acc, x, b);
     } else {
       const int off = site * SP + c0;
-      const Tf a = ok ? grid[off] : Tf(0);
+      const Tf a = grid[off];
 #pragma unroll
       for (int nt = 0; nt < CC::NT; ++nt) mfma(acc[nt], b[nt], a);
     }
@@ -339,6 +333,9 @@ SVMC_DEV void hop_features(const ModelDev& md, const LatDev& lt, const HopGeom& 
     }
   };
   load_b(1);
+  const int zsite = Gx * lt.Gy;             // the all-zero record after the grid
+  if (tid < SP * (int)sizeof(Tf) / 16)
+    reinterpret_cast<float4*>(grid + zsite * SP)[tid] = float4{0.0f, 0.0f, 0.0f, 0.0f};
   // layer-1 input: embedding of the new configuration on the layer-1 input
   // box (layer-1 output box grown by one site)
   {
@@ -398,7 +395,7 @@ SVMC_DEV void hop_features(const ModelDev& md, const LatDev& lt, const HopGeom& 
         py = ty;
         gsite[ti] = (int)((ty >> 8) & 0xFFu) * Gx + (int)((tx >> 8) & 0xFFu);
       }
-      conv_tile_grid<P, C>(grid, Gx, px, py, breg, Bl, lane, acc[ti]);
+      conv_tile_grid<P, C>(grid, Gx, zsite, px, py, breg, Bl, lane, acc[ti]);
     }
     // the next layer's B fragments are in flight during the rest of this one
     if (l < L) load_b(l + 1);
@@ -408,13 +405,13 @@ SVMC_DEV void hop_features(const ModelDev& md, const LatDev& lt, const HopGeom& 
       const int t = wave + NW * ti;
       if (t >= T) break;
       const bool on = gsite[ti] >= 0;
-      const int gofs = on ? gsite[ti] * SP : 0;
+      const int gofs = (on ? gsite[ti] : zsite) * SP;
 #pragma unroll
       for (int nt = 0; nt < CC::NT; ++nt) {
         if constexpr (PL) {
           const int n0 = 16 * nt + OutMap<P>::chan(lane, 0);
           float x[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-          if (on && n0 < C) planes_get4<C>(reinterpret_cast<const char*>(grid + gofs), n0, x);
+          if (n0 < C) planes_get4<C>(reinterpret_cast<const char*>(grid + gofs), n0, x);
 #pragma unroll
           for (int v = 0; v < 4; ++v)
             acc[ti][nt][v] = (on && n0 < C) ? layer_out<P, float>(md.act, x[v], acc[ti][nt][v] + bias[n0 + v]) : 0.0f;
