@@ -122,6 +122,8 @@ __global__ __launch_bounds__(64 * ELOC_NW) __attribute__((amdgpu_waves_per_eu(3)
   uint16_t* hops = (uint16_t*)(smem + lay.hops);
   double* red = (double*)(smem + lay.red);
   char* scratch = smem + lay.scratch;
+  const HopScratch hsc = hop_scratch(lt.Gx, lt.Gy, md.L, C, (int)sizeof(Tf));
+  hop_scratch_init<P>(md, scratch, hsc);
 
   const int8_t* occ_g = bf.occ + lt.occ_off + wl * N;
   const int16_t* lab_g = bf.lab + lt.lab_off + wl * 2LL * N;
@@ -137,7 +139,6 @@ __global__ __launch_bounds__(64 * ELOC_NW) __attribute__((amdgpu_waves_per_eu(3)
   const double* Gw = bf.G + lt.g_off + wl * 2LL * N * nm;
   const double* PTw = bf.PT + lt.pt_off + wl * 2LL * nm * C;
   const int KM = lt.Gx * lt.Gy;
-  const HopScratch hsc = hop_scratch(lt.Gx, lt.Gy, md.L, C, (int)sizeof(Tf));
   int* kl = (int*)(scratch + hsc.klists) + wv * KM;
   double* misc = (double*)(scratch + hsc.misc);
 

@@ -111,8 +111,10 @@ template <int C> struct DStride {
 //                           row-major copies [2][C + 1][C + 2] f64
 //   klists [2][Gx Gy] int   changed-row lists per spin
 //   misc   64 bytes         per-spin results
+//   bias   [L][C] f32       conv biases (FP32 feature modes), filled once per
+//                           workgroup by hop_scratch_init
 struct HopScratch {
-  int klists, misc, bytes;
+  int klists, misc, bias, bytes;
 };
 __host__ __device__ inline int align16i(int x) { return (x + 15) & ~15; }
 __host__ __device__ inline HopScratch hop_scratch(int Gx, int Gy, int L, int C, int tfb) {
@@ -124,8 +126,22 @@ __host__ __device__ inline HopScratch hop_scratch(int Gx, int Gy, int L, int C, 
   const int rb = gb > db ? gb : db;
   h.klists = align16i(rb > sb ? rb : sb);
   h.misc = h.klists + align16i(2 * Gx * Gy * 4);
-  h.bytes = h.misc + 64;
+  h.bias = h.misc + 64;
+  h.bytes = h.bias + align16i(L * C * 4);
+  (void)tfb;
   return h;
+}
+
+// Per-workgroup set-up of the hop scratch: the conv biases into LDS (FP32
+// feature modes).  All threads of the block call it; a barrier must follow
+// before the first hop.
+template <int P>
+SVMC_DEV void hop_scratch_init(const ModelDev& md, char* scratch, const HopScratch& hs) {
+  if constexpr (sizeof(typename PrecT<P>::Tf) == 4) {
+    const float* b = (const float*)md.bias;
+    float* d = (float*)(scratch + hs.bias);
+    for (int e = threadIdx.x; e < md.L * md.C; e += blockDim.x) d[e] = b[e];
+  }
 }
 
 // B fragments of a layer kept in registers when they fit (<= 80 VGPRs).
@@ -314,7 +330,6 @@ SVMC_DEV void hop_features(const ModelDev& md, const LatDev& lt, const HopGeom& 
   const int L = md.L, N = lt.N, Lx = lt.Lx, Gx = lt.Gx;
   const Axis ax = h.ax, ay = h.ay;
   Tf* grid = (Tf*)scratch;
-  (void)hs;
   const int bit = 1 << h.sigma;
   constexpr int V = 16 / sizeof(Tf);          // elements per 16-byte vector
   constexpr int CV = C / V;
@@ -373,6 +388,8 @@ SVMC_DEV void hop_features(const ModelDev& md, const LatDev& lt, const HopGeom& 
     const int T = (cnt + 15) >> 4;
     const Tb* Bl = (const Tb*)md.Bpack + (long long)(l - 1) * CC::Q * CC::NT * 64;
     const Tf* bias = (const Tf*)md.bias + (l - 1) * C;
+    constexpr bool FULLC = C % 16 == 0;        // every channel of every output tile exists
+    const float* bias_s = (const float*)(scratch + hs.bias) + (l - 1) * C;   // the same biases in LDS
     // Each wave keeps its tiles' results in registers until every wave has
     // finished reading the grid of this layer (at most 7 tiles: the layer-L
     // box of L <= 4 has at most 10 x 10 sites).  The lane's site is the same
@@ -399,7 +416,32 @@ SVMC_DEV void hop_features(const ModelDev& md, const LatDev& lt, const HopGeom& 
     }
     // the next layer's B fragments are in flight during the rest of this one
     if (l < L) load_b(l + 1);
-    // H'_l = H'_{l-1} + act(conv + b); the residual is this site's own grid value
+    // H'_l = H'_{l-1} + act(conv + b); the residual is this site's own grid
+    // value (padding rows compute from the zero record and are not stored)
+    if constexpr (PL) {
+      auto epilogue = [&](auto actc) {
+        constexpr int A = decltype(actc)::value;
+#pragma unroll
+        for (int ti = 0; ti < MAXT; ++ti) {
+          const int t = wave + NW * ti;
+          if (t >= T) break;
+          const char* rec = reinterpret_cast<const char*>(grid + (gsite[ti] >= 0 ? gsite[ti] : zsite) * SP);
+#pragma unroll
+          for (int nt = 0; nt < CC::NT; ++nt) {
+            const int n0 = 16 * nt + OutMap<P>::chan(lane, 0);
+            if (!FULLC && n0 >= C) continue;
+            float x[4];
+            planes_get4<C>(rec, n0, x);
+            const float4 b4 = *reinterpret_cast<const float4*>(bias_s + n0);
+            const float bv[4] = {b4.x, b4.y, b4.z, b4.w};
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc[ti][nt][v] = layer_out_c<P, A>(x[v], acc[ti][nt][v] + bv[v]);
+          }
+        }
+      };
+      if (md.act == ACT_TANH) epilogue(ActC<ACT_TANH>());
+      else epilogue(ActC<ACT_SILU>());
+    } else {
 #pragma unroll
     for (int ti = 0; ti < MAXT; ++ti) {
       const int t = wave + NW * ti;
@@ -408,14 +450,7 @@ SVMC_DEV void hop_features(const ModelDev& md, const LatDev& lt, const HopGeom& 
       const int gofs = (on ? gsite[ti] : zsite) * SP;
 #pragma unroll
       for (int nt = 0; nt < CC::NT; ++nt) {
-        if constexpr (PL) {
-          const int n0 = 16 * nt + OutMap<P>::chan(lane, 0);
-          float x[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-          if (n0 < C) planes_get4<C>(reinterpret_cast<const char*>(grid + gofs), n0, x);
-#pragma unroll
-          for (int v = 0; v < 4; ++v)
-            acc[ti][nt][v] = (on && n0 < C) ? layer_out<P, float>(md.act, x[v], acc[ti][nt][v] + bias[n0 + v]) : 0.0f;
-        } else {
+        {
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
             const int n = 16 * nt + OutMap<P>::chan(lane, v);
@@ -425,6 +460,7 @@ SVMC_DEV void hop_features(const ModelDev& md, const LatDev& lt, const HopGeom& 
           }
         }
       }
+    }
     }
     __syncthreads();
     const Tf* HL = featw + (long long)(L - 1) * N * C;
@@ -462,6 +498,20 @@ SVMC_DEV void hop_features(const ModelDev& md, const LatDev& lt, const HopGeom& 
         // D = H'_L - H_L, densely [m][C + 4] at the start of the scratch
         typedef typename DType<P>::type DT;
         DT* D = reinterpret_cast<DT*>(grid);
+        if constexpr (PL) {
+#pragma unroll
+          for (int nt = 0; nt < CC::NT; ++nt) {
+            const int n0 = 16 * nt + OutMap<P>::chan(lane, 0);
+            if (!FULLC && n0 >= C) continue;
+            const long long gi = (long long)s * C + n0;
+            const float4 old = *reinterpret_cast<const float4*>(HL + gi);
+            const float4 nw = {acc[ti][nt][0], acc[ti][nt][1], acc[ti][nt][2], acc[ti][nt][3]};
+            const float4 d = {(float)((double)nw.x - (double)old.x), (float)((double)nw.y - (double)old.y),
+                              (float)((double)nw.z - (double)old.z), (float)((double)nw.w - (double)old.w)};
+            *reinterpret_cast<float4*>(D + r * DStride<C>::value + n0) = d;
+            if (commit) *reinterpret_cast<float4*>(commit + (long long)(L - 1) * N * C + gi) = nw;
+          }
+        } else
 #pragma unroll
         for (int nt = 0; nt < CC::NT; ++nt)
 #pragma unroll

@@ -157,14 +157,20 @@ template <class T> SVMC_DEV T act_fn(int act, T x);
 // FP32: from the hardware exp2 and reciprocal, tanh(x) = sign(x) (1 - t) / (1 + t)
 // with t = exp(-2|x|) (absolute error a few 1e-8, the rounding level of the
 // FP32 residual stream it is added to); SiLU(x) = x / (1 + exp(-x)).
-template <> SVMC_DEV float act_fn<float>(int act, float x) {
+// act_c<A> is the same function with the activation fixed at compile time.
+template <int A> SVMC_DEV float act_c(float x);
+template <> SVMC_DEV float act_c<ACT_TANH>(float x) {
   constexpr float kLog2e = 1.4426950408889634f;
-  if (act == ACT_TANH) {
-    const float t = __builtin_amdgcn_exp2f(-2.0f * kLog2e * fabsf(x));
-    const float r = (1.0f - t) * __builtin_amdgcn_rcpf(1.0f + t);
-    return copysignf(r, x);
-  }
+  const float t = __builtin_amdgcn_exp2f(-2.0f * kLog2e * fabsf(x));
+  const float r = (1.0f - t) * __builtin_amdgcn_rcpf(1.0f + t);
+  return copysignf(r, x);
+}
+template <> SVMC_DEV float act_c<ACT_SILU>(float x) {
+  constexpr float kLog2e = 1.4426950408889634f;
   return x * __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(-kLog2e * x));
+}
+template <> SVMC_DEV float act_fn<float>(int act, float x) {
+  return act == ACT_TANH ? act_c<ACT_TANH>(x) : act_c<ACT_SILU>(x);
 }
 template <> SVMC_DEV double act_fn<double>(int act, double x) {
   return act == ACT_TANH ? tanh(x) : x / (1.0 + exp(-x));
@@ -209,6 +215,15 @@ template <int P, class T> SVMC_DEV T layer_out(int act, T x, T z) {
   if constexpr (P == PREC_F16X2) return pair_round(y);
   return y;
 }
+// the same with the activation fixed at compile time (FP32 features)
+template <int P, int A> SVMC_DEV float layer_out_c(float x, float z) {
+  const float y = x + act_c<A>(z);
+  if constexpr (P == PREC_F16X2) return pair_round(y);
+  return y;
+}
+template <int A> struct ActC {
+  static constexpr int value = A;
+};
 
 // One K chunk of a 16-bit mode: the B fragments b[nt] (weights, the MFMA A
 // operand) times this lane's 8 activations x (FP32, the B operand),

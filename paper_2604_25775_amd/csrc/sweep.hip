@@ -193,6 +193,7 @@ __global__ __launch_bounds__(64 * SW_NW) void k_sweep(ModelDev md, const LatDev*
   int nacc = bf.nacc[w];
   long long accepted = 0;
   bool stop_refresh = false;
+  hop_scratch_init<P>(md, scratch, hsc);
   __syncthreads();
 
   for (; q < qend && ne > 0; ++q) {
