@@ -153,10 +153,11 @@ __global__ __launch_bounds__(64 * ELOC_NW) __attribute__((amdgpu_waves_per_eu(3)
       const int i = code >> 4, sp = (code >> 3) & 1, d = code & 7;
       const HopGeom g = hop_geom(lt, md.L, sp, i, d);
       int olx, owx, oly, owy;
-      hop_features<P, C, NW>(md, lt, g, occ_s, featw, (Tf*)nullptr, scratch, hsc, olx, owx, oly, owy);
+      const AxisTab tab = axis_tab(g, md.L, lane);
+      hop_features<P, C, NW>(md, lt, g, occ_s, featw, (Tf*)nullptr, scratch, hsc, tab, olx, owx, oly, owy);
       // wavefront wv: determinant of spin wv
       int hpos;
-      const int K = hop_klist(lt, g, occ_s, lab_s, wv, olx, owx, oly, owy, kl, hpos, lane);
+      const int K = hop_klist(lt, g, tab, occ_s, lab_s, wv, olx, owx, oly, owy, kl, hpos, lane);
       const double* PTt = PTw + (long long)wv * nm * C;
       const double* Gj = Gw + ((long long)wv * N + g.j) * nm;
       v4d dacc[DetTiles<C>::I][DetTiles<C>::J];

@@ -300,7 +300,7 @@ SVMC_DEV int tab_site(const AxisTab& t, int ux, int uy, int Lx) {
 }
 
 // Incremental conv stack for one hop, computed by the NW wavefronts of the
-// workgroup (wave = this thread's wavefront).  On return (after a barrier)
+// workgroup (wave = this thread's wavefront); `tab` = axis_tab of the hop.  On return (after a barrier)
 // the scratch starts with D = H'_L - H_L on the layer-L box as Tf
 // [m][C + 4] (index m = ox + owx * oy).  If `commit` is non-null every new layer value is
 // also stored into the cache (accepted move); commit may equal featw (the
@@ -313,7 +313,7 @@ template <int P, int C, int NW>
 SVMC_DEV void hop_features(const ModelDev& md, const LatDev& lt, const HopGeom& h, const int8_t* occ_s,
                            const typename PrecT<P>::Tf* featw,
                            typename PrecT<P>::Tf* commit, char* scratch, const HopScratch& hs,
-                           int& olx, int& owx, int& oly, int& owy) {
+                           const AxisTab& tab, int& olx, int& owx, int& oly, int& owy) {
   typedef typename PrecT<P>::Tf Tf;
   typedef typename PrecT<P>::Tb Tb;
   typedef typename PrecT<P>::Acc Acc;
@@ -334,7 +334,6 @@ SVMC_DEV void hop_features(const ModelDev& md, const LatDev& lt, const HopGeom& 
   constexpr int V = 16 / sizeof(Tf);          // elements per 16-byte vector
   constexpr int CV = C / V;
   constexpr int QB = RegB<P, C>::value ? CC::Q : 1;
-  const AxisTab tab = axis_tab(h, L, lane);
   // B fragments of layer 1 (when held in registers), requested before the
   // embedding fill
   Tb breg[QB][CC::NT];
@@ -568,8 +567,9 @@ SVMC_DEV void hop_features(const ModelDev& md, const LatDev& lt, const HopGeom& 
 // in the new configuration on the layer-L box, entry (m << 16) | label, m
 // indexing the box.  The moving electron keeps its label at its new site.
 // Returns the list length; *hpos gets the mover's position (tau = sigma).
-SVMC_DEV int hop_klist(const LatDev& lt, const HopGeom& h, const int8_t* occ_s, const int16_t* lab_s, int tau,
-                       int olx, int owx, int oly, int owy, int* kl, int& hpos, int lane) {
+SVMC_DEV int hop_klist(const LatDev& lt, const HopGeom& h, const AxisTab& tab, const int8_t* occ_s,
+                       const int16_t* lab_s, int tau, int olx, int owx, int oly, int owy, int* kl, int& hpos,
+                       int lane) {
   const int N = lt.N, Lx = lt.Lx;
   const int cnt = owx * owy;
   const int mow = kMagic16[owx];
@@ -578,11 +578,12 @@ SVMC_DEV int hop_klist(const LatDev& lt, const HopGeom& h, const int8_t* occ_s, 
   hpos = -1;
   for (int base = 0; base < cnt; base += 64) {
     const int m = base + lane;
+    int ux, uy;
+    box_site(m, olx, owx, mow, oly, ux, uy);
+    const int sl = tab_site(tab, ux, uy, Lx);      // every lane active
     int s = 0, o = 0;
     if (m < cnt) {
-      int ux, uy;
-      box_site(m, olx, owx, mow, oly, ux, uy);
-      s = latc(h.ax, ux) + Lx * latc(h.ay, uy);
+      s = sl;
       o = occ_s[s];
       if (s == h.i) o -= bit;
       if (s == h.j) o += bit;
@@ -755,7 +756,11 @@ SVMC_DEV double hop_det_finish(const v4d (&acc)[DetTiles<C>::I][DetTiles<C>::J],
     if (lane < C) stage[lane * RS + C] = PTt[kh * C + lane];
     else if (lane == C) stage[C * RS + C] = Gj[kh];
   }
+  // lanes read rows other lanes wrote: order the accesses for the compiler
+  // (the hardware keeps a wavefront's LDS operations in order)
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   // rows in lanes < RM; the spin that does not move gets an identity row and
   // column C (same determinant), so both matrices take the same RM steps
   double a[RM];

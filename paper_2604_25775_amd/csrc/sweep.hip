@@ -216,14 +216,15 @@ __global__ __launch_bounds__(64 * SW_NW) void k_sweep(ModelDev md, const LatDev*
     }
     const HopGeom g = hop_geom(lt, md.L, sp, i, d);
     int olx, owx, oly, owy;
-    hop_features<P, C, NW>(md, lt, g, occ_s, featw, (Tf*)nullptr, scratch, hsc, olx, owx, oly, owy);
+    const AxisTab tab = axis_tab(g, md.L, lane);
+    hop_features<P, C, NW>(md, lt, g, occ_s, featw, (Tf*)nullptr, scratch, hsc, tab, olx, owx, oly, owy);
     int K = 0, hpos = -1;
     const int wd = wv < 2 ? wv : 0;           // spin of this wavefront's determinant
     const double* PTt = PTw + (long long)wd * nm * C;
     const double* Gj = Gw + ((long long)wd * N + g.j) * nm;
     v4d dacc[DetTiles<C>::I][DetTiles<C>::J];
     if (wv < 2) {
-      K = hop_klist(lt, g, occ_s, lab_s, wv, olx, owx, oly, owy, klb + wv * KM, hpos, lane);
+      K = hop_klist(lt, g, tab, occ_s, lab_s, wv, olx, owx, oly, owy, klb + wv * KM, hpos, lane);
       hop_det_build<C>(klb + wv * KM, K, wv == sp, hpos, Dbuf, PTt, Gj, lane, dacc);
     }
     __syncthreads();      // both matrices built: their staging may overwrite D
@@ -242,7 +243,7 @@ __global__ __launch_bounds__(64 * SW_NW) void k_sweep(ModelDev md, const LatDev*
     if (!(u < R * R)) continue;                                       // uniform
 
     // ---- accepted: commit the new features (and recompute D on the box)
-    hop_features<P, C, NW>(md, lt, g, occ_s, featw, featw, scratch, hsc, olx, owx, oly, owy);
+    hop_features<P, C, NW>(md, lt, g, occ_s, featw, featw, scratch, hsc, tab, olx, owx, oly, owy);
     bool fallback = false;
     for (int tau = 0; tau < 2; ++tau) {
       const int n = tau == 0 ? n_up : n_dn;
@@ -316,7 +317,11 @@ __global__ __launch_bounds__(64 * SW_NW) void k_sweep(ModelDev md, const LatDev*
         }
         int mystep;
         const bool ok = gj_inverse_rot<RA>(arow, R, lane, perm, mystep);
+        // every lane reads the pivot order lane 0 wrote: order the accesses
+        // for the compiler (a wavefront's LDS operations stay in order)
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         if (ok && lane < R) {
 #pragma unroll
           for (int qq = 0; qq < RA; ++qq) {
