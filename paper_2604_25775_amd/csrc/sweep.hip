@@ -389,9 +389,33 @@ __global__ __launch_bounds__(64 * SW_NW) void k_sweep(ModelDev md, const LatDev*
         __syncthreads();            // every read of G[j] and P done before they change
         for (int s0 = 0; s0 < N; s0 += SCH) {
           const int ns = min(SCH, N - s0);
-          for (int e2 = tid; e2 < ns * r; e2 += NTH) {
-            const int sl = e2 / r, a = e2 - sl * r;
-            gkc[sl * kmax + a] = Gt[(long long)(s0 + sl) * nm + (kl[a] & 0xffff)];
+          // this thread's G entries of the chunk, requested first so that the
+          // loads overlap the gather and E rows below (no other thread writes
+          // them before this thread's update)
+          constexpr int SPT = SCH / 2;
+          double gv[SPT];
+#pragma unroll
+          for (int i2 = 0; i2 < SPT; ++i2) {
+            const int sl = half + 2 * i2;
+            gv[i2] = (col && sl < ns) ? Gt[(long long)(s0 + sl) * nm + kc] : 0.0;
+          }
+          {
+            // G[s, K] of the chunk's sites: all of this thread's loads first
+            // (at most SCH * kmax / NTH <= 7 of them for L <= 4)
+            constexpr int GI = (SCH * 100 + NTH - 1) / NTH;
+            double gg[GI];
+            int gd[GI];
+#pragma unroll
+            for (int u2 = 0; u2 < GI; ++u2) {
+              const int e2 = tid + u2 * NTH;
+              const bool ok = e2 < ns * r;
+              const int sl = ok ? e2 / r : 0, a = ok ? e2 - sl * r : 0;
+              gd[u2] = ok ? sl * kmax + a : -1;
+              gg[u2] = ok ? Gt[(long long)(s0 + sl) * nm + (kl[a] & 0xffff)] : 0.0;
+            }
+#pragma unroll
+            for (int u2 = 0; u2 < GI; ++u2)
+              if (gd[u2] >= 0) gkc[gd[u2]] = gg[u2];
           }
           if (tid < ns) mbs[tid] = box_index(lt, s0 + tid, olx, owx, oly, owy);
           __syncthreads();
@@ -412,13 +436,15 @@ __global__ __launch_bounds__(64 * SW_NW) void k_sweep(ModelDev md, const LatDev*
           }
           __syncthreads();
           if (col) {
-            for (int sl = half; sl < ns; sl += 2) {
+#pragma unroll
+            for (int i2 = 0; i2 < SPT; ++i2) {
+              const int sl = half + 2 * i2;
+              if (sl >= ns) break;
               const double* es = ec + sl * RA;
-              double* gp = Gt + (long long)(s0 + sl) * nm + kc;
-              double v = *gp;
+              double v = gv[i2];
 #pragma unroll
               for (int c = 0; c < RA; ++c) v = fma(es[c], wcol[c], v);
-              *gp = v;
+              Gt[(long long)(s0 + sl) * nm + kc] = v;
             }
           }
           __syncthreads();
