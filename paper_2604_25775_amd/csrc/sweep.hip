@@ -30,7 +30,7 @@
 namespace svmc {
 
 constexpr int SW_NW = 4;        // wavefronts per workgroup
-constexpr int SCH = 16;         // sites per chunk of the G update
+constexpr int SCH = 32;         // sites per chunk of the G update
 // nacc value of a walker whose update matrix was singular: its G and P were
 // not updated, so the refresh rebuilds it without a drift check
 constexpr int SW_REBUILD = 0x7fffffff;
@@ -401,7 +401,7 @@ __global__ __launch_bounds__(64 * SW_NW) void k_sweep(ModelDev md, const LatDev*
           }
           {
             // G[s, K] of the chunk's sites: all of this thread's loads first
-            // (at most SCH * kmax / NTH <= 7 of them for L <= 4)
+            // (at most SCH * kmax / NTH <= 13 of them for L <= 4)
             constexpr int GI = (SCH * 100 + NTH - 1) / NTH;
             double gg[GI];
             int gd[GI];
