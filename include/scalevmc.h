@@ -176,35 +176,34 @@ svmc_status svmc_local_energy(svmc_ctx* ctx, svmc_path path, double* eloc,
  * local update of Sec. II.C, FP64 determinant part).  An accepted move
  * rewrites the walker's cached features on the update box, updates
  * G = M Phi^-1 and P = W Phi^-1 by the Sherman-Morrison-Woodbury formula
- * (Sec. II.C) and log|psi|, sign by the ratio.  After refresh_every accepted
- * moves a walker pauses; its rows, inverse, log|psi| and G/P are rebuilt in
- * FP64 (SVMC_W_DRIFT set first if the maintained G had drifted by more than
- * 1e-8 on its occupied rows) and it resumes at its next proposal, so the
- * chain does not depend on refresh_every.  Walkers flagged SINGULAR,
- * NONFINITE or BADCOUNT are not moved.
+ * (Sec. II.C) and log|psi|, sign by the ratio.  Proposal k of all walkers is
+ * one step on the stream; after the step, walkers with refresh_every accepted
+ * moves get their rows, inverse, log|psi| and G/P rebuilt in FP64
+ * (SVMC_W_DRIFT set first if the maintained G had drifted by more than 1e-8
+ * on its occupied rows) before their next proposal, so the chain does not
+ * depend on refresh_every.  A walker whose update matrix is singular keeps
+ * the accepted configuration and is rebuilt at the same point.  Walkers
+ * flagged SINGULAR, NONFINITE or BADCOUNT are not moved.  In a mixed batch a
+ * walker of a lattice with N sites takes n_sweeps * N proposals.
  * n_accept: device [W] int64 incremented by each walker's accepted moves, or
- * NULL.  The call waits on `stream` (the host reads how many walkers paused).
+ * NULL.  Work is queued on `stream`; nothing waits on it.  The first call
+ * allocates the sweep workspace (about 35 KB per walker at 16x16, C = 32).
  * Errors: SVMC_ERR_STATE without walkers, SVMC_ERR_INVALID_ARG for
  * n_sweeps < 0 or refresh_every < 1, SVMC_ERR_UNSUPPORTED when one walker's
  * workspace exceeds 160 KiB of LDS. */
 svmc_status svmc_sweep(svmc_ctx* ctx, int32_t n_sweeps, uint64_t seed,
                        uint64_t step0, int64_t* n_accept, hipStream_t stream);
 
-/* Form of svmc_sweep that can be recorded into a HIP graph and replayed: no
- * host synchronisation, no allocation, no memset node.  Runs `rounds` rounds
- * of [sweep kernel: each walker proposes until it finishes or pauses for a
- * refresh; masked FP64 refresh of the paused walkers].  svmc_sweep_rounds()
- * gives a number of rounds that lets every walker finish unless an update
- * matrix turns singular (each such walker needs one more round); walkers not
- * done after the last round keep the configuration they reached.  step0 is
- * read at run time from the device scalar *step0_dev (uint64), so replays can
- * advance the chain by updating it between replays.  The first call must be
- * made outside a capture (it allocates the progress buffer).  Same chain as
- * svmc_sweep for the same seed and step0 when it runs to completion. */
+/* Form of svmc_sweep that can be recorded into a HIP graph and replayed: the
+ * same fixed sequence of launches per proposal step, no host synchronisation,
+ * no allocation, no memset node.  step0 is read at run time from the device
+ * scalar *step0_dev (uint64), so replays can advance the chain by updating it
+ * between replays.  The first call must be made outside a capture (it
+ * allocates the workspace), and G/P must be current (svmc_prepare) before a
+ * capture.  Same chain as svmc_sweep for the same seed and step0. */
 svmc_status svmc_sweep_async(svmc_ctx* ctx, int32_t n_sweeps, uint64_t seed,
                              const uint64_t* step0_dev, int64_t* n_accept,
-                             int32_t rounds, hipStream_t stream);
-int32_t svmc_sweep_rounds(const svmc_ctx* ctx, int32_t n_sweeps);
+                             hipStream_t stream);
 
 /* Rebuild every walker's Slater inverse, log|psi| and low-rank precompute in
  * FP64 from the cached features (when G/P were current, SVMC_W_DRIFT is set

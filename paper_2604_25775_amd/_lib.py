@@ -20,7 +20,7 @@ EXPORTS = [
     "svmc_num_walkers", "svmc_max_hops", "svmc_max_electrons", "svmc_log_psi", "svmc_prepare",
     "svmc_local_energy",
     "svmc_sweep", "svmc_refresh", "svmc_get_state", "svmc_grad_logpsi", "svmc_walker_flags",
-    "svmc_status_string", "svmc_last_error", "svmc_tune", "svmc_sweep_async", "svmc_sweep_rounds",
+    "svmc_status_string", "svmc_last_error", "svmc_tune", "svmc_sweep_async",
 ]
 
 
@@ -74,8 +74,7 @@ def load(path: str | None = None):
         "svmc_status_string": (ct.c_char_p, [i32]),
         "svmc_last_error": (ct.c_char_p, [vp]),
         "svmc_tune": (i32, [vp, ct.c_char_p, ct.POINTER(i32), vp]),
-        "svmc_sweep_async": (i32, [vp, i32, u64, vp, vp, i32, vp]),
-        "svmc_sweep_rounds": (i32, [vp, i32]),
+        "svmc_sweep_async": (i32, [vp, i32, u64, vp, vp, vp]),
     }
     for name, (res, args) in proto.items():
         f = getattr(lib, name)

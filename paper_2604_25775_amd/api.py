@@ -146,14 +146,11 @@ class ScaleVMC:
                                         _ptr(n_accept), _stream()), "sweep")
         return n_accept
 
-    def sweep_async(self, n_sweeps: int, seed: int, step0: torch.Tensor, n_accept: torch.Tensor,
-                    rounds: int | None = None):
+    def sweep_async(self, n_sweeps: int, seed: int, step0: torch.Tensor, n_accept: torch.Tensor):
         """Graph-capturable sweep (svmc_sweep_async): step0 is a device uint64
         scalar read at run time (torch.int64 tensor of one element)."""
-        if rounds is None:
-            rounds = int(self.lib.svmc_sweep_rounds(self.h, int(n_sweeps)))
         self._check(self.lib.svmc_sweep_async(self.h, int(n_sweeps), ct.c_uint64(seed), _ptr(step0),
-                                              _ptr(n_accept), int(rounds), _stream()), "sweep_async")
+                                              _ptr(n_accept), _stream()), "sweep_async")
         return n_accept
 
     def refresh(self):

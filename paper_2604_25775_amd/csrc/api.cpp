@@ -98,7 +98,7 @@ struct svmc_ctx {
   long long Wtot = 0;
   DevBuf occ, lab, pos, feat, inv, M, G, PT, ldet, sgn, flags, nacc;
   DevBuf ratio_tmp, eloc_part;
-  DevBuf sw_prog, sw_paused;         // sweep progress per walker, paused-walker counter
+  DevBuf sw_stage, sw_list, sw_count;  // sweep: accepted-move staging, accepted walkers, their counts
   DevBuf gK, gB, gE;                 // conv weights, conv bias, embedding (FP64, forward's rounding)
   DevBuf g_rows, g_dH, g_hs, g_dzs;  // gradient scratch
   std::vector<int64_t> counts;
@@ -528,9 +528,74 @@ svmc_status svmc_refresh(svmc_ctx* ctx, hipStream_t st) {
   svmc_status s;
   if (ctx->prepared)
     for (auto& lt : ctx->ld)
-      if ((s = ctx->hip(launch_drift(lt, bf, 0, 0, st), "drift check"))) return s;
+      if ((s = ctx->hip(launch_drift(lt, bf, WalkerSel{nullptr, nullptr}, st), "drift check"))) return s;
   if ((s = rebuild_dets(ctx, st))) return s;
   return prepare(ctx, st);
+}
+
+// Sweep workspace (allocated outside any capture) and the step loop shared by
+// svmc_sweep and svmc_sweep_async.
+static svmc_status sweep_workspace(svmc_ctx* ctx, bool capturing, StepSizes& z) {
+  z = step_sizes(ctx->ld.data(), (int)ctx->ld.size(), ctx->prec, ctx->L, ctx->C);
+  if (z.smem_propose > 160 * 1024 || z.smem_update > 160 * 1024)
+    return ctx->fail(SVMC_ERR_UNSUPPORTED, "sweep workspace exceeds 160 KiB of LDS");
+  const size_t stage = (size_t)ctx->Wtot * z.stage_bytes, list = (size_t)ctx->Wtot * 4;
+  if (ctx->sw_stage.bytes < stage || ctx->sw_list.bytes < 2 * list || ctx->sw_count.bytes < 16) {
+    if (capturing) return ctx->fail(SVMC_ERR_STATE, "call svmc_sweep_async once outside capture first (allocates)");
+    svmc_status s;
+    if ((s = ctx->hip(ctx->sw_stage.ensure(stage), "alloc")) ||
+        (s = ctx->hip(ctx->sw_list.ensure(2 * list), "alloc")) || (s = ctx->hip(ctx->sw_count.ensure(16), "alloc")))
+      return s;
+  }
+  return SVMC_OK;
+}
+
+static svmc_status sweep_steps(svmc_ctx* ctx, int32_t n_sweeps, uint64_t seed, uint64_t step0,
+                               const uint64_t* step0_dev, int64_t* n_accept, const StepSizes& z, hipStream_t st) {
+  const int every = ctx->model.refresh_every;
+  const Bufs bf = ctx->bufs();
+  const ModelDev md = ctx->mdev();
+  StepArgs sa;
+  sa.seed = seed;
+  sa.step0 = step0;
+  sa.step0_dev = (const unsigned long long*)step0_dev;
+  sa.n_sweeps = n_sweeps;
+  sa.n_accept = n_accept;
+  sa.stage = ctx->sw_stage.as<char>();
+  sa.stage_stride = (long long)z.stage_bytes;
+  sa.acc_list = ctx->sw_list.as<int32_t>();
+  sa.due_list = ctx->sw_list.as<int32_t>() + ctx->Wtot;
+  sa.refresh_every = every;
+  int32_t* cnt = ctx->sw_count.as<int32_t>();     // [2] accepted, [2] due (per step parity)
+  long long qmax = 0;
+  for (auto& lt : ctx->ld) qmax = std::max(qmax, (long long)n_sweeps * lt.N);
+  ctx->dets_fresh = false;
+  svmc_status s;
+  if ((s = ctx->hip(launch_fill_i32(cnt, 4, 0, st), "counter reset"))) return s;
+  // per proposal index: every walker proposes, the walkers that accepted are
+  // updated, and walkers that reached `every` accepted moves are rebuilt in
+  // FP64 before their next proposal
+  for (long long q = 0; q < qmax; ++q) {
+    sa.q = q;
+    sa.count = cnt + (q & 1);
+    sa.count_next = cnt + ((q + 1) & 1);
+    sa.due_count = cnt + 2 + (q & 1);
+    sa.due_next = cnt + 2 + ((q + 1) & 1);
+    if ((s = ctx->hip(launch_sweep_step(ctx->prec, md, ctx->lats_dev.as<LatDev>(), ctx->ld.data(),
+                                        (int)ctx->ld.size(), ctx->Wtot, bf, sa, st),
+                      "sweep step")))
+      return s;
+    const WalkerSel due{sa.due_list, sa.due_count};
+    for (auto& lt : ctx->ld) {
+      if ((s = ctx->hip(launch_drift(lt, bf, due, st), "drift check")) ||
+          (s = ctx->hip(launch_rows(ctx->prec, lt, bf, ctx->L, ctx->C, st, due), "rows")) ||
+          (s = ctx->hip(launch_gj(lt, bf, st, due), "inverse")) ||
+          (s = ctx->hip(launch_gp(lt, bf, ctx->C, st, due), "G/P precompute")) ||
+          (s = ctx->hip(launch_clear_nacc(lt, bf, every, st), "clear")))
+        return s;
+    }
+  }
+  return SVMC_OK;
 }
 
 svmc_status svmc_sweep(svmc_ctx* ctx, int32_t n_sweeps, uint64_t seed, uint64_t step0, int64_t* n_accept,
@@ -539,115 +604,37 @@ svmc_status svmc_sweep(svmc_ctx* ctx, int32_t n_sweeps, uint64_t seed, uint64_t 
   if (!ctx->have_walkers) return ctx->fail(SVMC_ERR_STATE, "no walkers loaded");
   if (n_sweeps < 0) return ctx->fail(SVMC_ERR_INVALID_ARG, "negative sweep count");
   if (n_sweeps == 0) return SVMC_OK;
-  const int every = ctx->model.refresh_every;
-  if (every < 1) return ctx->fail(SVMC_ERR_INVALID_ARG, "refresh_every must be >= 1");
+  if (ctx->model.refresh_every < 1) return ctx->fail(SVMC_ERR_INVALID_ARG, "refresh_every must be >= 1");
   for (auto& lt : ctx->ld)
     if ((long long)n_sweeps * lt.N > (1LL << 40)) return ctx->fail(SVMC_ERR_INVALID_ARG, "too many sweeps");
-  const size_t smem = sweep_smem(ctx->ld.data(), (int)ctx->ld.size(), ctx->prec, ctx->L, ctx->C);
-  if (smem > 160 * 1024) return ctx->fail(SVMC_ERR_UNSUPPORTED, "sweep workspace exceeds 160 KiB of LDS");
+  StepSizes z;
   svmc_status s;
+  if ((s = sweep_workspace(ctx, false, z))) return s;
   if (!ctx->prepared && (s = prepare(ctx, st))) return s;
-  if ((s = ctx->hip(ctx->sw_prog.ensure((size_t)ctx->Wtot * 8), "alloc")) ||
-      (s = ctx->hip(ctx->sw_paused.ensure(4), "alloc")) ||
-      (s = ctx->hip(hipMemsetAsync(ctx->sw_prog.p, 0, (size_t)ctx->Wtot * 8, st), "memset")))
-    return s;
-  SweepArgs sa;
-  sa.seed = seed;
-  sa.step0 = step0;
-  sa.step0_dev = nullptr;
-  sa.n_sweeps = n_sweeps;
-  sa.refresh_every = every;
-  sa.n_accept = n_accept;
-  sa.prog = ctx->sw_prog.as<int64_t>();
-  sa.paused = ctx->sw_paused.as<int>();
-  const Bufs bf = ctx->bufs();
-  const ModelDev md = ctx->mdev();
-  ctx->dets_fresh = false;
-  // Walkers stop after `every` accepted moves; the masked FP64 refresh below
-  // rebuilds exactly those and the next launch resumes them.
-  for (;;) {
-    if ((s = ctx->hip(hipMemsetAsync(sa.paused, 0, 4, st), "memset"))) return s;
-    if ((s = ctx->hip(launch_sweep(ctx->prec, md, ctx->lats_dev.as<LatDev>(), ctx->ld.data(), (int)ctx->ld.size(),
-                                   ctx->Wtot, bf, sa, st),
-                      "sweep")))
-      return s;
-    int paused = 0;
-    if ((s = ctx->hip(hipMemcpyAsync(&paused, sa.paused, 4, hipMemcpyDeviceToHost, st), "paused copy")) ||
-        (s = ctx->hip(hipStreamSynchronize(st), "sweep sync")))
-      return s;
-    if (paused == 0) break;
-    for (auto& lt : ctx->ld) {
-      if ((s = ctx->hip(launch_drift(lt, bf, 1, every, st), "drift check")) ||
-          (s = ctx->hip(launch_rows(ctx->prec, lt, bf, ctx->L, ctx->C, st, 1, every), "rows")) ||
-          (s = ctx->hip(launch_gj(lt, bf, st, 1, every), "inverse")) ||
-          (s = ctx->hip(launch_gp(lt, bf, ctx->C, st, 1, every), "G/P precompute")) ||
-          (s = ctx->hip(launch_clear_nacc(lt, bf, every, st), "clear")))
-        return s;
-    }
-  }
-  return SVMC_OK;
+  return sweep_steps(ctx, n_sweeps, seed, step0, nullptr, n_accept, z, st);
 }
 
 svmc_status svmc_sweep_async(svmc_ctx* ctx, int32_t n_sweeps, uint64_t seed, const uint64_t* step0_dev,
-                             int64_t* n_accept, int32_t rounds, hipStream_t st) {
+                             int64_t* n_accept, hipStream_t st) {
   if (!ctx) return SVMC_ERR_INVALID_ARG;
   if (!ctx->have_walkers) return ctx->fail(SVMC_ERR_STATE, "no walkers loaded");
-  if (n_sweeps < 0 || rounds < 0) return ctx->fail(SVMC_ERR_INVALID_ARG, "negative sweep or round count");
+  if (n_sweeps < 0) return ctx->fail(SVMC_ERR_INVALID_ARG, "negative sweep count");
   if (!step0_dev) return ctx->fail(SVMC_ERR_INVALID_ARG, "step0_dev is null");
-  const int every = ctx->model.refresh_every;
-  const size_t smem = sweep_smem(ctx->ld.data(), (int)ctx->ld.size(), ctx->prec, ctx->L, ctx->C);
-  if (smem > 160 * 1024) return ctx->fail(SVMC_ERR_UNSUPPORTED, "sweep workspace exceeds 160 KiB of LDS");
+  if (ctx->model.refresh_every < 1) return ctx->fail(SVMC_ERR_INVALID_ARG, "refresh_every must be >= 1");
   hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
   if (hipStreamIsCapturing(st, &cap) != hipSuccess) return ctx->fail(SVMC_ERR_HIP, "capture query");
   const bool capturing = cap != hipStreamCaptureStatusNone;
+  StepSizes z;
   svmc_status s;
-  if (ctx->sw_prog.bytes < (size_t)ctx->Wtot * 8 || !ctx->sw_prog.p) {
-    if (capturing) return ctx->fail(SVMC_ERR_STATE, "call svmc_sweep_async once outside capture first (allocates)");
-    if ((s = ctx->hip(ctx->sw_prog.ensure((size_t)ctx->Wtot * 8), "alloc"))) return s;
-  }
+  if ((s = sweep_workspace(ctx, capturing, z))) return s;
   // G and P must be current when the work runs: a captured precompute would
   // be replayed against stale inverses, so capture needs them ready
   if (!ctx->prepared) {
     if (capturing) return ctx->fail(SVMC_ERR_STATE, "call svmc_prepare before capturing svmc_sweep_async");
     if ((s = prepare(ctx, st))) return s;
   }
-  if (n_sweeps == 0 || rounds == 0) return SVMC_OK;
-  SweepArgs sa;
-  sa.seed = seed;
-  sa.step0 = 0;
-  sa.step0_dev = (const unsigned long long*)step0_dev;
-  sa.n_sweeps = n_sweeps;
-  sa.refresh_every = every;
-  sa.n_accept = n_accept;
-  sa.prog = ctx->sw_prog.as<int64_t>();
-  sa.paused = nullptr;
-  const Bufs bf = ctx->bufs();
-  const ModelDev md = ctx->mdev();
-  ctx->dets_fresh = false;
-  if ((s = ctx->hip(launch_fill_i64(sa.prog, ctx->Wtot, 0, st), "progress reset"))) return s;
-  for (int r = 0; r < rounds; ++r) {
-    if ((s = ctx->hip(launch_sweep(ctx->prec, md, ctx->lats_dev.as<LatDev>(), ctx->ld.data(), (int)ctx->ld.size(),
-                                   ctx->Wtot, bf, sa, st),
-                      "sweep")))
-      return s;
-    for (auto& lt : ctx->ld) {
-      if ((s = ctx->hip(launch_drift(lt, bf, 1, every, st), "drift check")) ||
-          (s = ctx->hip(launch_rows(ctx->prec, lt, bf, ctx->L, ctx->C, st, 1, every), "rows")) ||
-          (s = ctx->hip(launch_gj(lt, bf, st, 1, every), "inverse")) ||
-          (s = ctx->hip(launch_gp(lt, bf, ctx->C, st, 1, every), "G/P precompute")) ||
-          (s = ctx->hip(launch_clear_nacc(lt, bf, every, st), "clear")))
-        return s;
-    }
-  }
-  return SVMC_OK;
-}
-
-int32_t svmc_sweep_rounds(const svmc_ctx* ctx, int32_t n_sweeps) {
-  if (!ctx || n_sweeps < 0) return -1;
-  long long nmax = 0;
-  for (auto& l : ctx->lats) nmax = std::max(nmax, (long long)l.Lx * l.Ly);
-  const long long every = std::max(1, ctx->model.refresh_every);
-  return (int32_t)std::min<long long>(1 << 20, (n_sweeps * nmax + every - 1) / every + 1);
+  if (n_sweeps == 0) return SVMC_OK;
+  return sweep_steps(ctx, n_sweeps, seed, 0, step0_dev, n_accept, z, st);
 }
 
 svmc_status svmc_get_state(svmc_ctx* ctx, int8_t* occ, int16_t* pos, hipStream_t st) {

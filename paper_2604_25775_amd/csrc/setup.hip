@@ -136,12 +136,8 @@ __global__ void k_labels(LatDev lt, Bufs bf) {
 
 // M_s[x][m] = base_s[x][m] + sum_c H_L[x][c] W_s[c][m] + b_s[m]
 template <class Tf>
-__global__ void k_rows(LatDev lt, Bufs bf, int L, int C, int only_due, int refresh_every) {
+SVMC_DEV void rows_one(const LatDev& lt, const Bufs& bf, int L, int C, long long wl, int sp, int e) {
   const int N = lt.N, nm = lt.nmax;
-  const long long wl = blockIdx.z;
-  if (only_due && bf.nacc[lt.w0 + wl] < refresh_every) return;
-  const int sp = blockIdx.y;
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= N * nm) return;
   const int x = e / nm, m = e % nm;
   double* M = bf.M + lt.m_off + wl * 2LL * N * nm + (long long)sp * N * nm;
@@ -153,18 +149,25 @@ __global__ void k_rows(LatDev lt, Bufs bf, int L, int C, int only_due, int refre
   for (int c = 0; c < C; ++c) acc = fma((double)H[c], W[c * nm + m], acc);
   M[e] = acc;
 }
+template <class Tf>
+__global__ void k_rows(LatDev lt, Bufs bf, int L, int C, WalkerSel sel) {
+  const int sp = blockIdx.y;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  for (long long z = blockIdx.z;; z += gridDim.z) {
+    long long wl;
+    const int r = pick_walker(sel, lt, z, wl);
+    if (r == 0) break;
+    if (r == 1) rows_one<Tf>(lt, bf, L, C, wl, sp, e);
+  }
+}
 
 // Phi_s = M_s[pos] (rows in label order) -> Phi_s^-1, log|det|, sign, with
 // the register-tiled Gauss-Jordan elimination of tiled_lu.h (n <= 16 R).
 template <int R>
-__global__ __launch_bounds__(256) void k_gj(LatDev lt, Bufs bf, int only_due, int refresh_every) {
-  const int sp = blockIdx.y;
-  const long long wl = blockIdx.x;
+SVMC_DEV void gj_one(const LatDev& lt, const Bufs& bf, long long wl, int sp, GjShared<R>& sh) {
   const long long w = lt.w0 + wl;
-  if (only_due && bf.nacc[w] < refresh_every) return;
   const int n = lt.n[sp], nm = lt.nmax;
   const int tid = threadIdx.x, tx = tid >> 4, ty = tid & 15;
-  __shared__ GjShared<R> sh;
   double* ldo = bf.ld + 2 * w + sp;
   double* sgo = bf.sg + 2 * w + sp;
   if (n == 0) {
@@ -214,6 +217,19 @@ __global__ __launch_bounds__(256) void k_gj(LatDev lt, Bufs bf, int only_due, in
   }
 }
 
+template <int R>
+__global__ __launch_bounds__(256) void k_gj(LatDev lt, Bufs bf, WalkerSel sel) {
+  __shared__ GjShared<R> sh;
+  const int sp = blockIdx.y;
+  for (long long z = blockIdx.x;; z += gridDim.x) {
+    long long wl;
+    const int r = pick_walker(sel, lt, z, wl);    // uniform in the block
+    if (r == 0) break;
+    if (r == 1) gj_one<R>(lt, bf, wl, sp, sh);
+    __syncthreads();
+  }
+}
+
 // Gauss-Jordan inverse of one Slater block for N_sigma > 128 (up to 512):
 // Phi (rows in label order) is gathered into the walker's inverse slot and
 // inverted in place with partial pivoting; rows are swapped physically and
@@ -221,12 +237,19 @@ __global__ __launch_bounds__(256) void k_gj(LatDev lt, Bufs bf, int only_due, in
 // per (walker, spin); the pivot row and the pivot column are staged in LDS,
 // each step then updates the whole block (rows in order, columns across
 // threads).  log|det| and its sign come from the pivots and the swaps.
-__global__ __launch_bounds__(256) void k_gj_big(LatDev lt, Bufs bf, int only_due, int refresh_every) {
-  const int sp = blockIdx.y;
-  const long long wl = blockIdx.x;
+struct GjBigShared {
+  double prow[512], fcol[512], rv[256];
+  int ri[256];
+  int16_t sw[512];
+};
+SVMC_DEV void gj_big_one(const LatDev& lt, const Bufs& bf, long long wl, int sp, GjBigShared& sb) {
   const long long w = lt.w0 + wl;
-  if (only_due && bf.nacc[w] < refresh_every) return;
   const int n = lt.n[sp], nm = lt.nmax, tid = threadIdx.x;
+  double* prow = sb.prow;
+  double* fcol = sb.fcol;
+  double* rv = sb.rv;
+  int* ri = sb.ri;
+  int16_t* sw = sb.sw;
   double* ldo = bf.ld + 2 * w + sp;
   double* sgo = bf.sg + 2 * w + sp;
   if (n == 0) {
@@ -240,9 +263,6 @@ __global__ __launch_bounds__(256) void k_gj_big(LatDev lt, Bufs bf, int only_due
   const double* M = bf.M + lt.m_off + wl * 2LL * lt.N * nm + (long long)sp * lt.N * nm;
   const int16_t* pos = bf.pos + lt.pos_off + wl * 2LL * nm + sp * nm;
   double* Y = bf.inv + lt.inv_off + wl * 2LL * nm * nm + (long long)sp * nm * nm;
-  __shared__ double prow[512], fcol[512], rv[256];
-  __shared__ int ri[256];
-  __shared__ int16_t sw[512];
   for (int k = 0; k < n; ++k) {
     const double* src = M + (long long)pos[k] * nm;
     for (int c = tid; c < n; c += 256) Y[(long long)k * nm + c] = src[c];
@@ -322,19 +342,28 @@ __global__ __launch_bounds__(256) void k_gj_big(LatDev lt, Bufs bf, int only_due
   }
 }
 
+__global__ __launch_bounds__(256) void k_gj_big(LatDev lt, Bufs bf, WalkerSel sel) {
+  __shared__ GjBigShared sb;
+  const int sp = blockIdx.y;
+  for (long long z = blockIdx.x;; z += gridDim.x) {
+    long long wl;
+    const int r = pick_walker(sel, lt, z, wl);    // uniform in the block
+    if (r == 0) break;
+    if (r == 1) gj_big_one(lt, bf, wl, sp, sb);
+    __syncthreads();
+  }
+}
+
 // G_s = M_s Phi_s^-1 (rows 0..N-1) and P_s^T = (W_s Phi_s^-1)^T (rows N..N+C-1
 // of the stacked left factor).  64x64 output tiles, 4x4 per thread, K chunks
-// of 16 through LDS.  grid.x = tile + ntiles * (sp + 2 * wl).
-__global__ __launch_bounds__(256) void k_gp(LatDev lt, Bufs bf, int C, int tiles_r, int tiles_c, int only_due,
-                                            int refresh_every) {
+// of 16 through LDS.  grid.x = tile + ntiles * (sp + 2 * walker slot).
+struct GpShared {
+  double As[16][64 + 1];
+  double Bs[16][64 + 1];
+};
+SVMC_DEV void gp_one(const LatDev& lt, const Bufs& bf, int C, int tiles_c, long long wl, int sp, int tile,
+                     GpShared& sg) {
   const int N = lt.N, nm = lt.nmax;
-  long long bid = blockIdx.x;
-  const int ntiles = tiles_r * tiles_c;
-  const int tile = (int)(bid % ntiles);
-  bid /= ntiles;
-  const int sp = (int)(bid % 2);
-  const long long wl = bid / 2;
-  if (only_due && bf.nacc[lt.w0 + wl] < refresh_every) return;
   const int n = lt.n[sp];
   if (n == 0) return;
   const int R0 = (tile / tiles_c) * 64, C0 = (tile % tiles_c) * 64;
@@ -342,8 +371,8 @@ __global__ __launch_bounds__(256) void k_gp(LatDev lt, Bufs bf, int C, int tiles
   const double* M = bf.M + lt.m_off + wl * 2LL * N * nm + (long long)sp * N * nm;
   const double* W = lt.W + (long long)sp * C * nm;
   const double* Y = bf.inv + lt.inv_off + wl * 2LL * nm * nm + (long long)sp * nm * nm;
-  __shared__ double As[16][64 + 1];
-  __shared__ double Bs[16][64 + 1];
+  double (*As)[64 + 1] = sg.As;
+  double (*Bs)[64 + 1] = sg.Bs;
   const int tid = threadIdx.x, tr = tid / 16, tc = tid % 16;
   double acc[4][4] = {};
   for (int k0 = 0; k0 < n; k0 += 16) {
@@ -386,6 +415,22 @@ __global__ __launch_bounds__(256) void k_gp(LatDev lt, Bufs bf, int C, int tiles
     }
   }
 }
+__global__ __launch_bounds__(256) void k_gp(LatDev lt, Bufs bf, int C, int tiles_r, int tiles_c, WalkerSel sel,
+                                            long long slots) {
+  __shared__ GpShared sg;
+  long long bid = blockIdx.x;
+  const int ntiles = tiles_r * tiles_c;
+  const int tile = (int)(bid % ntiles);
+  bid /= ntiles;
+  const int sp = (int)(bid % 2);
+  for (long long z = bid / 2;; z += slots) {
+    long long wl;
+    const int r = pick_walker(sel, lt, z, wl);    // uniform in the block
+    if (r == 0) break;
+    if (r == 1) gp_one(lt, bf, C, tiles_c, wl, sp, tile, sg);
+    __syncthreads();
+  }
+}
 
 // sign with canonical (site-ascending) row order = label-order sign times the
 // parity of the label -> site map; log|psi| = sum over spins.
@@ -426,34 +471,40 @@ hipError_t launch_forward(int prec, const LatDev& lt, const Bufs& bf, const Mode
 }
 
 
-hipError_t launch_rows(int prec, const LatDev& lt, const Bufs& bf, int L, int C, hipStream_t st, int only_due,
-                       int refresh_every) {
+// Walker slots of a launch: every walker of the lattice (one slot each), or
+// `list_slots` slots that loop over the list.
+static long long walker_slots(const LatDev& lt, const WalkerSel& sel, int list_slots) {
+  return sel.list ? std::min<long long>(lt.nw, list_slots) : lt.nw;
+}
+
+hipError_t launch_rows(int prec, const LatDev& lt, const Bufs& bf, int L, int C, hipStream_t st, WalkerSel sel) {
   if (lt.nw == 0) return hipSuccess;
-  const dim3 grid((unsigned)((lt.N * lt.nmax + 255) / 256), 2, (unsigned)lt.nw);
+  const dim3 grid((unsigned)((lt.N * lt.nmax + 255) / 256), 2, (unsigned)walker_slots(lt, sel, 64));
   if (prec == PREC_F64)
-    hipLaunchKernelGGL(k_rows<double>, grid, dim3(256), 0, st, lt, bf, L, C, only_due, refresh_every);
+    hipLaunchKernelGGL(k_rows<double>, grid, dim3(256), 0, st, lt, bf, L, C, sel);
   else
-    hipLaunchKernelGGL(k_rows<float>, grid, dim3(256), 0, st, lt, bf, L, C, only_due, refresh_every);
+    hipLaunchKernelGGL(k_rows<float>, grid, dim3(256), 0, st, lt, bf, L, C, sel);
   return hipGetLastError();
 }
 
-hipError_t launch_gj(const LatDev& lt, const Bufs& bf, hipStream_t st, int only_due, int refresh_every) {
+hipError_t launch_gj(const LatDev& lt, const Bufs& bf, hipStream_t st, WalkerSel sel) {
   if (lt.nw == 0) return hipSuccess;
-  const dim3 grid((unsigned)lt.nw, 2);
-  if (lt.nmax <= 16) hipLaunchKernelGGL((k_gj<1>), grid, dim3(256), 0, st, lt, bf, only_due, refresh_every);
-  else if (lt.nmax <= 32) hipLaunchKernelGGL((k_gj<2>), grid, dim3(256), 0, st, lt, bf, only_due, refresh_every);
-  else if (lt.nmax <= 64) hipLaunchKernelGGL((k_gj<4>), grid, dim3(256), 0, st, lt, bf, only_due, refresh_every);
-  else if (lt.nmax <= 128) hipLaunchKernelGGL((k_gj<8>), grid, dim3(256), 0, st, lt, bf, only_due, refresh_every);
-  else if (lt.nmax <= 512) hipLaunchKernelGGL(k_gj_big, grid, dim3(256), 0, st, lt, bf, only_due, refresh_every);
+  const dim3 grid((unsigned)walker_slots(lt, sel, 256), 2);
+  if (lt.nmax <= 16) hipLaunchKernelGGL((k_gj<1>), grid, dim3(256), 0, st, lt, bf, sel);
+  else if (lt.nmax <= 32) hipLaunchKernelGGL((k_gj<2>), grid, dim3(256), 0, st, lt, bf, sel);
+  else if (lt.nmax <= 64) hipLaunchKernelGGL((k_gj<4>), grid, dim3(256), 0, st, lt, bf, sel);
+  else if (lt.nmax <= 128) hipLaunchKernelGGL((k_gj<8>), grid, dim3(256), 0, st, lt, bf, sel);
+  else if (lt.nmax <= 512) hipLaunchKernelGGL(k_gj_big, grid, dim3(256), 0, st, lt, bf, sel);
   else return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
-hipError_t launch_gp(const LatDev& lt, const Bufs& bf, int C, hipStream_t st, int only_due, int refresh_every) {
+hipError_t launch_gp(const LatDev& lt, const Bufs& bf, int C, hipStream_t st, WalkerSel sel) {
   if (lt.nw == 0) return hipSuccess;
   const int tr = (lt.N + C + 63) / 64, tc = (lt.nmax + 63) / 64;
-  const long long nblk = (long long)tr * tc * 2 * lt.nw;
-  hipLaunchKernelGGL(k_gp, dim3((unsigned)nblk), dim3(256), 0, st, lt, bf, C, tr, tc, only_due, refresh_every);
+  const long long slots = walker_slots(lt, sel, 64);
+  const long long nblk = (long long)tr * tc * 2 * slots;
+  hipLaunchKernelGGL(k_gp, dim3((unsigned)nblk), dim3(256), 0, st, lt, bf, C, tr, tc, sel, slots);
   return hipGetLastError();
 }
 

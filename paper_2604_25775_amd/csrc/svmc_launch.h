@@ -18,12 +18,30 @@ namespace svmc {
 hipError_t launch_labels(const LatDev& lt, const Bufs& bf, hipStream_t st);
 hipError_t launch_forward(int prec, const LatDev& lt, const Bufs& bf, const ModelDev& md, void* h0tmp,
                           hipStream_t st);
-// only_due != 0: only walkers with nacc >= refresh_every (refresh after sweeps)
+// Walkers a refresh launch works on: all walkers of the lattice (list null),
+// or the global walker indices list[0 .. *count) that belong to it.
+struct WalkerSel {
+  const int32_t* list;
+  const int32_t* count;
+};
+// Walker of slot z: 0 = no more slots, 1 = walker wl (lattice-local), 2 = skip.
+SVMC_DEV int pick_walker(const WalkerSel& s, const LatDev& lt, long long z, long long& wl) {
+  if (s.list) {
+    if (z >= *(const volatile int32_t*)s.count) return 0;
+    const long long w = s.list[z];
+    if (w < lt.w0 || w >= lt.w0 + lt.nw) return 2;
+    wl = w - lt.w0;
+    return 1;
+  }
+  if (z >= lt.nw) return 0;
+  wl = z;
+  return 1;
+}
 hipError_t launch_rows(int prec, const LatDev& lt, const Bufs& bf, int L, int C, hipStream_t st,
-                       int only_due = 0, int refresh_every = 0);
-hipError_t launch_gj(const LatDev& lt, const Bufs& bf, hipStream_t st, int only_due = 0, int refresh_every = 0);
-hipError_t launch_gp(const LatDev& lt, const Bufs& bf, int C, hipStream_t st, int only_due = 0,
-                     int refresh_every = 0);
+                       WalkerSel sel = WalkerSel{nullptr, nullptr});
+hipError_t launch_gj(const LatDev& lt, const Bufs& bf, hipStream_t st, WalkerSel sel = WalkerSel{nullptr, nullptr});
+hipError_t launch_gp(const LatDev& lt, const Bufs& bf, int C, hipStream_t st,
+                     WalkerSel sel = WalkerSel{nullptr, nullptr});
 hipError_t launch_logpsi(const LatDev& lt, const Bufs& bf, double* sign, double* logabs, hipStream_t st);
 
 // eloc.hip: low-rank local energies over all walkers of all lattices in one launch
@@ -40,19 +58,33 @@ size_t eloc_lowrank_smem(const LatDev* lats_host, int nlats, int prec, int L, in
 hipError_t launch_eloc_lowrank(int prec, const ModelDev& md, const LatDev* lats_dev, const LatDev* lats_host,
                                int nlats, long long W, const Bufs& bf, const ElocOut& out, hipStream_t st);
 
-// sweep.hip: Metropolis sweeps with Woodbury updates
-struct SweepArgs {
+// sweep.hip: Metropolis sweeps, step-synchronous across walkers: per proposal
+// index q one launch of the proposal kernel (all walkers) and one of the
+// Woodbury update (walkers that accepted)
+struct StepArgs {
   unsigned long long seed, step0;
   const unsigned long long* step0_dev;   // if non-null, step0 is read from here
-  int n_sweeps, refresh_every;
+  long long q;                           // proposal index of this step
+  int n_sweeps;
   int64_t* n_accept;     // [W] incremented by accepted moves (may be null)
-  int64_t* prog;         // [W] next proposal index of each walker
-  int* paused;           // number of walkers that stopped for a refresh (may be null)
+  char* stage;           // [W][stage_stride] accepted-move staging
+  long long stage_stride;
+  int32_t* acc_list;     // [W] walkers that accepted at this step
+  int32_t* count;        // their number (zero on entry)
+  int32_t* count_next;   // cleared for the next step
+  int32_t* due_list;     // [W] walkers to rebuild in FP64 after this step
+  int32_t* due_count;    // their number (zero on entry)
+  int32_t* due_next;     // cleared for the next step
+  int refresh_every;
 };
-size_t sweep_smem(const LatDev* lats_host, int nlats, int prec, int L, int C);
-hipError_t launch_sweep(int prec, const ModelDev& md, const LatDev* lats_dev, const LatDev* lats_host, int nlats,
-                        long long W, const Bufs& bf, const SweepArgs& sa, hipStream_t st);
-hipError_t launch_drift(const LatDev& lt, const Bufs& bf, int only_due, int refresh_every, hipStream_t st);
+struct StepSizes {
+  size_t smem_propose, smem_update, stage_bytes;
+};
+StepSizes step_sizes(const LatDev* lats_host, int nlats, int prec, int L, int C);
+hipError_t launch_sweep_step(int prec, const ModelDev& md, const LatDev* lats_dev, const LatDev* lats_host,
+                             int nlats, long long W, const Bufs& bf, const StepArgs& sa, hipStream_t st);
+hipError_t launch_fill_i32(int32_t* p, long long n, int32_t v, hipStream_t st);
+hipError_t launch_drift(const LatDev& lt, const Bufs& bf, WalkerSel sel, hipStream_t st);
 hipError_t launch_clear_nacc(const LatDev& lt, const Bufs& bf, int refresh_every, hipStream_t st);
 hipError_t launch_fill_i64(int64_t* p, long long n, int64_t v, hipStream_t st);
 
@@ -89,8 +121,9 @@ hipError_t launch_eloc_full(int prec, const ModelDev& md, const LatDev& lt, cons
                                    double* ratio_tmp, int stride, hipStream_t st);                        \
   hipError_t forward_##P_##_##C_(const LatDev& lt, const Bufs& bf, const ModelDev& md, void* h0tmp,       \
                                  hipStream_t st);                                                         \
-  hipError_t sweep_##P_##_##C_(const ModelDev& md, const LatDev* lats_dev, int nlats, long long W,        \
-                               const Bufs& bf, const SweepArgs& sa, size_t smem, hipStream_t st);
+  hipError_t sweep_step_##P_##_##C_(const ModelDev& md, const LatDev* lats_dev, int nlats, long long W,   \
+                                    const Bufs& bf, const StepArgs& sa, size_t smem_p, size_t smem_u,     \
+                                    int upd_blocks, hipStream_t st);
 SVMC_FOR_EACH_PREC_C(SVMC_DECL_INST)
 #undef SVMC_DECL_INST
 

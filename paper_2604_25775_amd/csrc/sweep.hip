@@ -1,73 +1,91 @@
 // Metropolis sampling of |psi|^2 with single-electron nearest-neighbour moves
 // (Sec. II.A: configurations drawn by Markov chain Monte Carlo), with the
-// local update of Sec. II.C for both the ratio and the accepted move:
-//   ratio   incremental conv on the update box + determinant-lemma matrix per
-//           spin (the same routines as the local-energy kernel);
-//   accept  the new features are written into the cache, and the inverse
-//           information kept per walker, G = M Phi^-1 (all sites) and
-//           P = W Phi^-1, is brought up to date with the Sherman-Morrison-
-//           Woodbury formula (Sec. II.C).  Per spin the change of the Slater
-//           matrix has rank <= C + 1:  Phi' - Phi = U V with
-//             U = [rows K carry D(m_a) (C columns), e_k for the mover],
-//             V = [W; M[j] - M[i]],
-//           so with A = I + V Phi^-1 U ((C+1) x (C+1), det A = ratio) and
-//           Z = A^-1 V Phi^-1 (V Phi^-1 = [P; G[j] - e_k], column w_k):
-//             G' = G_old' - (G_old' U) Z,   P' = P - (P U) Z,
-//           where G_old' = M' Phi^-1 = G + D P on the box sites.  Evaluated
-//           as G'[s][k] = G[s][k] + e_s . w_k with one coefficient vector per
-//           site, e_s = [[s in box] D(s) - A^-T (G_old' U)[s]; -(G_old' U)[s]
-//           . A^-1[:, C]], and P' = P - (PU A^-1) w_k.  log|psi| and the sign
-//           take the ratio per spin.
+// local update of Sec. II.C for both the ratio and the accepted move.
+//
+// The sweep is step-synchronous across walkers: proposal q of every walker
+// is one launch of k_step_propose (one workgroup per walker), followed by
+// one launch of k_step_update over the walkers that accepted, then the
+// masked FP64 refresh of walkers that reached `refresh_every` accepted moves.
+//   propose  incremental conv on the update box + determinant-lemma matrix A
+//            per spin (the routines of the local-energy kernel); on accept
+//            the new features are committed to the cache, A^-1 (Gauss-Jordan
+//            on the staged A), the changed-row lists, the old row G[j] and
+//            D = H'_L - H_L on the box are staged for the update, and the
+//            configuration, labels and log|psi| are updated;
+//   update   the inverse information kept per walker, G = M Phi^-1 (all
+//            sites) and P = W Phi^-1, follows the Sherman-Morrison-Woodbury
+//            formula (Sec. II.C).  Per spin Phi' - Phi = U V with
+//              U = [rows K carry D(m_a) (C columns), e_k for the mover],
+//              V = [W; M[j] - M[i]],  A = I + V Phi^-1 U = [PU; g-row] + I,
+//            so Q = PU A^-1 = (I - A^-1)[0:C] and, with B = U A^-1 and
+//            W[:, k'] = [P^T[k']; G[j][k'] - [k' = k]],
+//              G'[s][k'] = G[s][k'] + E[s] . W[:, k'],
+//              E[s] = [s in box] D(s) A^-1[0:C, :] - G[s, K] B,
+//              P^T'[k'] = A^-1[0:C, :] W[:, k'].
+//            One workgroup per (walker, spin): B once, then G in chunks of
+//            sites, then P.
 //
 // Proposal q of walker w uses one Philox4x64-10 block (key (seed, 0), counter
 // (w, step0 + q, 0, 0)), written from the published definition (Salmon et
-// al., SC'11).  A walker stops after `refresh_every` accepted moves; the host
-// rebuilds its inverse in FP64 and restarts it at the next proposal, so the
-// chain is the same as without the pause.
+// al., SC'11), so the chain does not depend on when refreshes happen.
 #include "hop.h"
 #include "svmc_launch.h"
 
 namespace svmc {
 
-constexpr int SW_NW = 4;        // wavefronts per workgroup
-constexpr int SCH = 32;         // sites per chunk of the G update
 // nacc value of a walker whose update matrix was singular: its G and P were
 // not updated, so the refresh rebuilds it without a drift check
 constexpr int SW_REBUILD = 0x7fffffff;
+constexpr int UPD_SC = 64;      // sites per chunk of the G update
 
-struct SweepLds {
-  int occ, lab, pos, misc, pu, rowc, ainv, qm, perm, corder, pkbm, gk, mk, gkc, ec, mbs, scratch, bytes, kmax;
-};
 __host__ __device__ inline int al16(int x) { return (x + 15) & ~15; }
-// LDS of one walker: configuration, labels, positions, per-hop results, the
-// update matrices of one spin (PU [C][C+1], row C of A, A^-1 and Q = PU A^-1,
-// pivot order, label order [2 nmax], the changed rows' P^T [kmax][C] which
-// later holds B = U A^-1 [kmax][C+1], their G[j] entries and box offsets, a
-// chunk's G[s, K] [SCH][kmax] and E rows [SCH][C+1]) and the hop scratch.
-// kmax = changed rows per spin at most = sites of the layer-L box.
-__host__ __device__ inline SweepLds sweep_layout(int N, int nmax, int Gx, int Gy, int L, int C, int tfb) {
-  const int ra = C + 1;
-  SweepLds o;
-  o.kmax = (Gx < 2 * L + 2 ? Gx : 2 * L + 2) * (Gy < 2 * L + 2 ? Gy : 2 * L + 2);
+// rows of the layer-L update box at most
+__host__ __device__ inline int box_kmax(int Gx, int Gy, int L) {
+  return (Gx < 2 * L + 2 ? Gx : 2 * L + 2) * (Gy < 2 * L + 2 ? Gy : 2 * L + 2);
+}
+
+// Staging record of one walker's accepted move (global memory, byte offsets):
+//   hdr   int [16]            flags and scalars (HD_*)
+//   kl    int [2][kmax]       changed-row lists per spin, (m << 16) | label
+//   D     DT  [kmax][C + 4]   D = H'_L - H_L on the layer-L box
+//   ainv  f64 [2][C+1][C+1]   A^-1 per spin (zero row / column C for the
+//                             spin that does not move)
+//   gj    f64 [2][nmax]       G[j] per spin before the update
+struct StepStage {
+  int hdr, kl, D, ainv, gj, bytes;
+};
+__host__ __device__ inline StepStage step_stage(int nmax, int Gx, int Gy, int L, int C, int dtb) {
+  const int km = box_kmax(Gx, Gy, L), ra = C + 1;
+  StepStage o;
+  o.hdr = 0;
+  o.kl = 64;
+  o.D = o.kl + al16(2 * km * 4);
+  o.ainv = o.D + al16(km * (C + 4) * dtb);
+  o.gj = o.ainv + 2 * ra * ra * 8;
+  o.bytes = o.gj + al16(2 * nmax * 8);
+  return o;
+}
+enum { HD_ACC = 0, HD_SP, HD_K, HD_J, HD_OLX, HD_OWX, HD_OLY, HD_OWY, HD_R0, HD_R1, HD_HPOS };
+
+// LDS of the proposal kernel: configuration, labels, pivot orders of the two
+// inverse wavefronts, per-hop scratch.
+struct ProposeLds {
+  int occ, lab, perm, scratch, bytes;
+};
+__host__ __device__ inline ProposeLds propose_layout(int N, int Gx, int Gy, int L, int C, int tfb) {
+  ProposeLds o;
   o.occ = 0;
   o.lab = al16(N);
-  o.pos = o.lab + al16(4 * N);
-  o.misc = o.pos + al16(4 * nmax);
-  o.pu = o.misc + 128;
-  o.rowc = o.pu + al16(8 * C * ra);
-  o.ainv = o.rowc + al16(8 * ra);
-  o.qm = o.ainv + al16(8 * ra * ra);
-  o.perm = o.qm + al16(8 * C * ra);
-  o.corder = o.perm + al16(4 * ra);
-  o.pkbm = o.corder + al16(2 * 2 * nmax);
-  o.gk = o.pkbm + al16(8 * o.kmax * ra);
-  o.mk = o.gk + al16(8 * o.kmax);
-  o.gkc = o.mk + al16(4 * o.kmax);
-  o.ec = o.gkc + al16(8 * SCH * o.kmax);
-  o.mbs = o.ec + al16(8 * SCH * ra);
-  o.scratch = o.mbs + al16(4 * SCH);
+  o.perm = o.lab + al16(4 * N);
+  o.scratch = o.perm + 2 * 64 * 4;
   o.bytes = o.scratch + hop_scratch(Gx, Gy, L, C, tfb).bytes;
   return o;
+}
+// LDS of the update kernel: A^-1, B = U A^-1, the changed-row list, E rows of
+// a chunk of sites.
+__host__ __device__ inline int update_lds_bytes(int kmax, int C) {
+  const int ra = C + 1;
+  return al16(ra * ra * 8) + al16(kmax * ra * 8) + al16(kmax * 4) + UPD_SC * (4 * ((ra + 3) / 4)) * 8;
 }
 
 // Dense index of site s in the layer-L update box (origin (olx, oly), size
@@ -128,13 +146,13 @@ SVMC_DEV bool gj_inverse_rot(double (&a)[RM], int r_in, int lane, int* perm, int
 }
 
 #ifdef SVMC_INST_P
+// Proposal sa.q of every walker (one workgroup of two wavefronts per walker).
 template <int P, int C>
-__global__ __launch_bounds__(64 * SW_NW) void k_sweep(ModelDev md, const LatDev* __restrict__ lats, int nlats,
-                                                      Bufs bf, SweepArgs sa) {
+__global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(3))) void k_step_propose(ModelDev md, const LatDev* __restrict__ lats, int nlats,
+                                                      Bufs bf, StepArgs sa) {
   typedef typename PrecT<P>::Tf Tf;
-  constexpr int NW = SW_NW, NTH = 64 * NW;
-  constexpr int SP = SiteStride<Tf, C>::value;
-  constexpr int RA = C + 1;
+  typedef typename DType<P>::type DT;
+  constexpr int NW = 2, NTH = 64 * NW, RA = C + 1;
   extern __shared__ __attribute__((aligned(16))) char smem[];
   const long long w = blockIdx.x;
   int li = 0;
@@ -142,385 +160,369 @@ __global__ __launch_bounds__(64 * SW_NW) void k_sweep(ModelDev md, const LatDev*
   const LatDev lt = lats[li];
   const long long wl = w - lt.w0;
   const int N = lt.N, nm = lt.nmax;
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63, wv = uniform_i(tid >> 6);
+  const StepStage sl = step_stage(nm, lt.Gx, lt.Gy, md.L, C, (int)sizeof(DT));
+  char* st = sa.stage + w * sa.stage_stride;
+  int* hdr = (int*)(st + sl.hdr);
+  // electron counts as scalars: indexing the local descriptor copy with a
+  // runtime spin would move it to scratch memory
+  const int n_up = lt.n[0], n_dn = lt.n[1], ne = n_up + n_dn;
   const long long qend = (long long)sa.n_sweeps * N;
-  long long q = sa.prog[w];
-  if (q >= qend) return;
-  const unsigned long long step0 = sa.step0_dev ? *sa.step0_dev : sa.step0;
-  if (bf.flags[w] & (1 | 2 | 8)) {
-    if (tid == 0) sa.prog[w] = qend;
+  if (sa.q >= qend || ne == 0 || (bf.flags[w] & (1 | 2 | 8))) {
+    if (tid == 0) hdr[HD_ACC] = 0;
     return;
   }
-  const SweepLds lay = sweep_layout(N, nm, lt.Gx, lt.Gy, md.L, C, (int)sizeof(Tf));
-  int8_t* occ_s = (int8_t*)(smem + lay.occ);
-  int16_t* lab_s = (int16_t*)(smem + lay.lab);
-  int16_t* pos_s = (int16_t*)(smem + lay.pos);
-  double* misc = (double*)(smem + lay.misc);
-  double* pu = (double*)(smem + lay.pu);
-  double* rowc = (double*)(smem + lay.rowc);
-  double* ainv = (double*)(smem + lay.ainv);
-  double* qm = (double*)(smem + lay.qm);
-  int* perm = (int*)(smem + lay.perm);
-  int16_t* corder = (int16_t*)(smem + lay.corder);
-  double* pk = (double*)(smem + lay.pkbm);
-  double* bm = pk;                  // B = U A^-1 replaces P^T_K once PU is formed
-  double* gk = (double*)(smem + lay.gk);
-  int* mk = (int*)(smem + lay.mk);
-  double* gkc = (double*)(smem + lay.gkc);
-  double* ec = (double*)(smem + lay.ec);
-  int* mbs = (int*)(smem + lay.mbs);
-  const int kmax = lay.kmax;
-  char* scratch = smem + lay.scratch;
-  const HopScratch hsc = hop_scratch(lt.Gx, lt.Gy, md.L, C, (int)sizeof(Tf));
-  const int KM = lt.Gx * lt.Gy;
-  int* klb = (int*)(scratch + hsc.klists);
-  const typename DType<P>::type* Dbuf = (const typename DType<P>::type*)scratch;
-  constexpr int SD = DStride<C>::value;
-
+  // ---- draw (identical in every thread)
+  const unsigned long long step0 = sa.step0_dev ? *sa.step0_dev : sa.step0;
+  unsigned long long ctr[4] = {(unsigned long long)w, step0 + (unsigned long long)sa.q, 0ULL, 0ULL};
+  philox4x64_10(ctr, sa.seed, 0ULL);
+  const int e = (int)__umul64hi(ctr[0], (unsigned long long)ne);
+  const int d = (int)(ctr[1] >> 62);
+  const double u = (double)(ctr[2] >> 11) * 0x1.0p-53;
+  const int sp = e < n_up ? 0 : 1;
+  const int k = sp == 0 ? e : e - n_up;
   int8_t* occ_g = bf.occ + lt.occ_off + wl * N;
   int16_t* lab_g = bf.lab + lt.lab_off + wl * 2LL * N;
   int16_t* pos_g = bf.pos + lt.pos_off + wl * 2LL * nm;
+  const int i = uniform_i(pos_g[sp * nm + k]);
+  const int bit = 1 << sp;
+  {
+    int x = i % lt.Lx + dir_dx(d), y = i / lt.Lx + dir_dy(d);
+    bool ok = true;
+    if (lt.pbc_x) x = imod(x, lt.Lx); else ok = ok && x >= 0 && x < lt.Lx;
+    if (lt.pbc_y) y = imod(y, lt.Ly); else ok = ok && y >= 0 && y < lt.Ly;
+    const int tgt = ok ? uniform_i(occ_g[x + lt.Lx * y]) : 0;
+    if (!ok || ((tgt >> sp) & 1)) {                                   // uniform
+      if (tid == 0) hdr[HD_ACC] = 0;
+      return;
+    }
+  }
+  const ProposeLds lay = propose_layout(N, lt.Gx, lt.Gy, md.L, C, (int)sizeof(Tf));
+  int8_t* occ_s = (int8_t*)(smem + lay.occ);
+  int16_t* lab_s = (int16_t*)(smem + lay.lab);
+  int* perm = (int*)(smem + lay.perm) + wv * 64;
+  char* scratch = smem + lay.scratch;
+  const HopScratch hsc = hop_scratch(lt.Gx, lt.Gy, md.L, C, (int)sizeof(Tf));
+  hop_scratch_init<P>(md, scratch, hsc);
   for (int s = tid; s < N; s += NTH) occ_s[s] = occ_g[s];
   for (int s = tid; s < 2 * N; s += NTH) lab_s[s] = lab_g[s];
-  for (int s = tid; s < 2 * nm; s += NTH) pos_s[s] = pos_g[s];
-  Tf* featw = (Tf*)bf.feat + lt.feat_off + wl * (long long)md.L * N * C;
-  double* Gw = bf.G + lt.g_off + wl * 2LL * N * nm;
-  double* PTw = bf.PT + lt.pt_off + wl * 2LL * nm * C;
-  // electron counts as scalars: indexing the local descriptor copy with a
-  // runtime spin would move it to scratch memory
-  const int n_up = lt.n[0], n_dn = lt.n[1];
-  const int ne = n_up + n_dn;
-  int nacc = bf.nacc[w];
-  long long accepted = 0;
-  bool stop_refresh = false;
-  hop_scratch_init<P>(md, scratch, hsc);
   __syncthreads();
 
-  for (; q < qend && ne > 0; ++q) {
-    // ---- draw (identical in every thread)
-    unsigned long long ctr[4] = {(unsigned long long)w, step0 + (unsigned long long)q, 0ULL, 0ULL};
-    philox4x64_10(ctr, sa.seed, 0ULL);
-    const int e = (int)__umul64hi(ctr[0], (unsigned long long)ne);
-    const int d = (int)(ctr[1] >> 62);
-    const double u = (double)(ctr[2] >> 11) * 0x1.0p-53;
-    const int sp = e < n_up ? 0 : 1;
-    const int k = sp == 0 ? e : e - n_up;
-    const int i = uniform_i(pos_s[sp * nm + k]);
-    const int bit = 1 << sp;
-    {
-      int x = i % lt.Lx + dir_dx(d), y = i / lt.Lx + dir_dy(d);
-      bool ok = true;
-      if (lt.pbc_x) x = imod(x, lt.Lx); else ok = ok && x >= 0 && x < lt.Lx;
-      if (lt.pbc_y) y = imod(y, lt.Ly); else ok = ok && y >= 0 && y < lt.Ly;
-      if (!ok || ((occ_s[x + lt.Lx * y] >> sp) & 1)) continue;   // uniform
-    }
-    const HopGeom g = hop_geom(lt, md.L, sp, i, d);
-    int olx, owx, oly, owy;
-    const AxisTab tab = axis_tab(g, md.L, lane);
-    hop_features<P, C, NW>(md, lt, g, occ_s, featw, (Tf*)nullptr, scratch, hsc, tab, olx, owx, oly, owy);
-    int K = 0, hpos = -1;
-    const int wd = wv < 2 ? wv : 0;           // spin of this wavefront's determinant
-    const double* PTt = PTw + (long long)wd * nm * C;
-    const double* Gj = Gw + ((long long)wd * N + g.j) * nm;
-    v4d dacc[DetTiles<C>::I][DetTiles<C>::J];
-    if (wv < 2) {
-      K = hop_klist(lt, g, tab, occ_s, lab_s, wv, olx, owx, oly, owy, klb + wv * KM, hpos, lane);
-      hop_det_build<C>(klb + wv * KM, K, wv == sp, hpos, Dbuf, PTt, Gj, lane, dacc);
-    }
-    __syncthreads();      // both matrices built: their staging may overwrite D
-    if (wv < 2) {
-      double* stage = (double*)scratch + wv * (C + 1) * DetTiles<C>::RS;
-      const double Rt = hop_det_finish<C>(dacc, klb + wv * KM, K, wv == sp, hpos, PTt, Gj, stage, lane);
-      if (lane == 0) {
-        misc[wv] = Rt;
-        misc[2 + wv] = (double)K;
-        misc[4 + wv] = (double)hpos;
-      }
-    }
-    __syncthreads();
-    const double R0 = misc[0], R1 = misc[1];
-    const double R = R0 * R1;
-    if (!(u < R * R)) continue;                                       // uniform
+  // ---- ratio
+  Tf* featw = (Tf*)bf.feat + lt.feat_off + wl * (long long)md.L * N * C;
+  const double* Gw = bf.G + lt.g_off + wl * 2LL * N * nm;
+  const double* PTw = bf.PT + lt.pt_off + wl * 2LL * nm * C;
+  const HopGeom g = hop_geom(lt, md.L, sp, i, d);
+  const AxisTab tab = axis_tab(g, md.L, lane);
+  int olx, owx, oly, owy;
+  hop_features<P, C, NW>(md, lt, g, occ_s, featw, (Tf*)nullptr, scratch, hsc, tab, olx, owx, oly, owy);
+  const int KM = lt.Gx * lt.Gy;
+  int* kl = (int*)(scratch + hsc.klists) + wv * KM;
+  double* misc = (double*)(scratch + hsc.misc);
+  int hpos;
+  const int K = hop_klist(lt, g, tab, occ_s, lab_s, wv, olx, owx, oly, owy, kl, hpos, lane);
+  const double* PTt = PTw + (long long)wv * nm * C;
+  const double* Gj = Gw + ((long long)wv * N + g.j) * nm;
+  v4d dacc[DetTiles<C>::I][DetTiles<C>::J];
+  hop_det_build<C>(kl, K, wv == sp, hpos, (const DT*)scratch, PTt, Gj, lane, dacc);
+  __syncthreads();      // both matrices built: their staging may overwrite D
+  double* stage = (double*)scratch + wv * (C + 1) * DetTiles<C>::RS;
+  const double Rt = hop_det_finish<C>(dacc, kl, K, wv == sp, hpos, PTt, Gj, stage, lane);
+  if (lane == 0) misc[wv] = Rt;
+  __syncthreads();
+  const double R0 = misc[0], R1 = misc[1];
+  const double R = R0 * R1;
+  if (!(u < R * R)) {                                                 // uniform
+    if (tid == 0) hdr[HD_ACC] = 0;
+    return;
+  }
 
-    // ---- accepted: commit the new features (and recompute D on the box)
-    hop_features<P, C, NW>(md, lt, g, occ_s, featw, featw, scratch, hsc, tab, olx, owx, oly, owy);
-    bool fallback = false;
-    for (int tau = 0; tau < 2; ++tau) {
-      const int n = tau == 0 ? n_up : n_dn;
-      if (n == 0) continue;
-      const int r = (int)misc[2 + tau];
-      const bool hs = tau == sp;
-      const int R = C + (hs ? 1 : 0);
-      const int* kl = klb + tau * KM;
-      double* Gt = Gw + (long long)tau * N * nm;
-      double* PTt = PTw + (long long)tau * nm * C;
-      const double* Gj = Gt + (long long)g.j * nm;
-      // (0) stage the changed labels' P^T rows, G[j] entries and box rows:
-      //     pk[a][c] = P^T[k_a][c], gk[a] = G[j][k_a] - [k_a = k], mk[a] = m_a
-      for (int a = tid; a < r; a += NTH) {
-        const int e = kl[a];
-        mk[a] = (e >> 16) * SD;
-        gk[a] = hs ? Gj[e & 0xffff] - ((e & 0xffff) == k ? 1.0 : 0.0) : 0.0;
-      }
-      {
-        const int tot = r * C;
-        for (int e0 = 0; e0 < tot; e0 += NTH * 4) {
-          double v[4];
+  // ---- accepted.  Wavefront tau: A^-1 of spin tau from the staged A (still
+  // in LDS: the LU worked on registers), its changed-row list and G[j].
+  const int kmaxb = box_kmax(lt.Gx, lt.Gy, md.L);
+  const int ntau = wv == 0 ? n_up : n_dn;
+  bool ok = true;
+  if (ntau > 0) {
+    const bool hs = wv == sp;
+    const int R_ = C + (hs ? 1 : 0);
+    double* ai = (double*)(st + sl.ainv) + (long long)wv * RA * RA;
+    if (K == 0) {
+      // no changed row of this spin (never the moving one): A = I
+      for (int e2 = lane; e2 < RA * RA; e2 += 64) ai[e2] = (e2 / RA == e2 % RA && e2 / RA < R_) ? 1.0 : 0.0;
+    } else {
+      double arow[RA];
+      const double2* rp = reinterpret_cast<const double2*>(stage + (lane < R_ ? lane : 0) * DetTiles<C>::RS);
 #pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            const int e2 = e0 + NTH * u + tid;
-            v[u] = e2 < tot ? PTt[(long long)(kl[e2 / C] & 0xffff) * C + (e2 % C)] : 0.0;
-          }
-#pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            const int e2 = e0 + NTH * u + tid;
-            if (e2 < tot) pk[e2] = v[u];
-          }
-        }
+      for (int c2 = 0; c2 < DetTiles<C>::RS / 2; ++c2) {
+        const double2 v = rp[c2];
+        if (2 * c2 < RA) arow[2 * c2] = (lane < R_ && 2 * c2 < R_) ? v.x : 0.0;
+        if (2 * c2 + 1 < RA) arow[2 * c2 + 1] = (lane < R_ && 2 * c2 + 1 < R_) ? v.y : 0.0;
       }
-      __syncthreads();
-      // (1) PU = P U: PU[c'][c] = sum_a P^T[k_a][c'] D(m_a)[c] (c < C), PU[c'][C] = P^T[k][c'];
-      //     row C of A - I (hop spin): sum_a (G[j][k_a] - [k_a = k]) D(m_a)[c], G[j][k] - 1
-      for (int e2 = tid; e2 < C * RA; e2 += NTH) {
-        const int cp = e2 / RA, c = e2 - cp * RA;
-        double v = 0.0;
-        if (c < C) {
-#pragma unroll 8
-          for (int a = 0; a < r; ++a) v = fma(pk[a * C + cp], (double)Dbuf[mk[a] + c], v);
-        } else if (hs) {
-          v = PTt[(long long)k * C + cp];
-        }
-        pu[e2] = v;
-      }
-      for (int c = tid; c < RA; c += NTH) {
-        double v = 0.0;
-        if (hs) {
-          if (c < C) {
-#pragma unroll 8
-            for (int a = 0; a < r; ++a) v = fma(gk[a], (double)Dbuf[mk[a] + c], v);
-          } else {
-            v = Gj[k] - 1.0;
-          }
-        }
-        rowc[c] = v;
-      }
-      for (int e2 = tid; e2 < RA * RA; e2 += NTH) ainv[e2] = 0.0;
-      __syncthreads();
-      // (2) A = I + V Phi^-1 U, inverted by wavefront 0
-      if (wv == 0) {
-        double arow[RA];
-#pragma unroll
-        for (int c = 0; c < RA; ++c) {
-          double v = 0.0;
-          if (lane < R && c < R) v = (lane < C ? pu[lane * RA + c] : rowc[c]) + (lane == c ? 1.0 : 0.0);
-          arow[c] = v;
-        }
-        int mystep;
-        const bool ok = gj_inverse_rot<RA>(arow, R, lane, perm, mystep);
-        // every lane reads the pivot order lane 0 wrote: order the accesses
-        // for the compiler (a wavefront's LDS operations stay in order)
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        if (ok && lane < R) {
+      int mystep;
+      ok = gj_inverse_rot<RA>(arow, R_, lane, perm, mystep);
+      // every lane reads the pivot order lane 0 wrote: order the accesses
+      // for the compiler (a wavefront's LDS operations stay in order)
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      if (ok) {
+        if (lane < R_) {
 #pragma unroll
           for (int qq = 0; qq < RA; ++qq) {
-            if (qq < R) {
-              const int slot = RA - R + qq;
+            if (qq < R_) {
+              const int slot = RA - R_ + qq;
               double v = 0.0;
 #pragma unroll
               for (int s2 = 0; s2 < RA; ++s2) v = (s2 == slot) ? arow[s2] : v;
-              ainv[mystep * RA + perm[qq]] = v;   // A^-1[p][perm[q]]
+              ai[mystep * RA + perm[qq]] = v;   // A^-1[p][perm[q]]
             }
           }
         }
-        if (lane == 0) misc[6] = ok ? 1.0 : 0.0;
-      }
-      __syncthreads();
-      if (misc[6] == 0.0) { fallback = true; continue; }                 // uniform
-      // Q = PU A^-1 (C x RA) and B = U A^-1 (r x RA), U[a] = [D(m_a), [k_a = k]]:
-      //   G' = G + E W,  E[s] = [s in box] (D_ext(s) - D(s) Q) - G[s, K] B,
-      //   P^T' = P^T - (Q W)^T,  W[:, k'] = [P^T[k']; G[j][k'] - [k' = k]]
-      for (int e2 = tid; e2 < C * RA; e2 += NTH) {
-        const int cp = e2 / RA, c = e2 - cp * RA;
-        double v = 0.0;
-        for (int c1 = 0; c1 < R; ++c1) v = fma(pu[cp * RA + c1], ainv[c1 * RA + c], v);
-        qm[e2] = v;
-      }
-      for (int e2 = tid; e2 < r * RA; e2 += NTH) {
-        const int a = e2 / RA, c2 = e2 - a * RA;
-        const typename DType<P>::type* Da = Dbuf + mk[a];
-        double v = (hs && (kl[a] & 0xffff) == k) ? ainv[C * RA + c2] : 0.0;
-#pragma unroll 8
-        for (int c = 0; c < C; ++c) v = fma((double)Da[c], ainv[c * RA + c2], v);
-        bm[e2] = v;
-      }
-      // Columns (labels) go in passes of NTH / 2, each column on two threads
-      // (even and odd sites of a chunk).  With more than one pass the labels
-      // of K come last and all fall in the last pass: E of a chunk reads the
-      // old G[s, K] of its sites.
-      constexpr int NCOL = NTH / 2;
-      const int npass = (n + NCOL - 1) / NCOL;
-      if (npass > 1) {
-        for (int kk = tid; kk < n; kk += NTH) corder[kk] = 0;
-        __syncthreads();
-        for (int a = tid; a < r; a += NTH) corder[kl[a] & 0xffff] = 1;
-        __syncthreads();
-        if (tid == 0) {
-          int lo = 0, hi = n;
-          for (int kk = 0; kk < n; ++kk) {
-            if (corder[kk] == 0) corder[n + lo++] = (int16_t)kk;
-            else corder[n + --hi] = (int16_t)kk;
-          }
+        if (R_ < RA) {   // zero row and column C
+          if (lane < RA) ai[C * RA + lane] = 0.0;
+          if (lane < C) ai[lane * RA + C] = 0.0;
         }
-      }
-      __syncthreads();
-      const int half = tid / NCOL, tcol = tid - half * NCOL;
-      for (int b = 0; b < npass; ++b) {
-        // passes are cut from the end of the order, so the last one holds the
-        // final NCOL labels and with them all of K (r <= (2L+2)^2 <= NCOL)
-        const int slot = n - (npass - b) * NCOL + tcol;
-        const bool col = slot >= 0;
-        const int kc = !col ? 0 : (npass > 1 ? (int)corder[n + slot] : slot);
-        double wcol[RA];
-#pragma unroll
-        for (int c = 0; c < C; ++c) wcol[c] = col ? PTt[(long long)kc * C + c] : 0.0;
-        wcol[C] = (col && hs) ? Gj[kc] - (kc == k ? 1.0 : 0.0) : 0.0;
-        __syncthreads();            // every read of G[j] and P done before they change
-        for (int s0 = 0; s0 < N; s0 += SCH) {
-          const int ns = min(SCH, N - s0);
-          // this thread's G entries of the chunk, requested first so that the
-          // loads overlap the gather and E rows below (no other thread writes
-          // them before this thread's update)
-          constexpr int SPT = SCH / 2;
-          double gv[SPT];
-#pragma unroll
-          for (int i2 = 0; i2 < SPT; ++i2) {
-            const int sl = half + 2 * i2;
-            gv[i2] = (col && sl < ns) ? Gt[(long long)(s0 + sl) * nm + kc] : 0.0;
-          }
-          {
-            // G[s, K] of the chunk's sites: all of this thread's loads first
-            // (at most SCH * kmax / NTH <= 13 of them for L <= 4)
-            constexpr int GI = (SCH * 100 + NTH - 1) / NTH;
-            double gg[GI];
-            int gd[GI];
-#pragma unroll
-            for (int u2 = 0; u2 < GI; ++u2) {
-              const int e2 = tid + u2 * NTH;
-              const bool ok = e2 < ns * r;
-              const int sl = ok ? e2 / r : 0, a = ok ? e2 - sl * r : 0;
-              gd[u2] = ok ? sl * kmax + a : -1;
-              gg[u2] = ok ? Gt[(long long)(s0 + sl) * nm + (kl[a] & 0xffff)] : 0.0;
-            }
-#pragma unroll
-            for (int u2 = 0; u2 < GI; ++u2)
-              if (gd[u2] >= 0) gkc[gd[u2]] = gg[u2];
-          }
-          if (tid < ns) mbs[tid] = box_index(lt, s0 + tid, olx, owx, oly, owy);
-          __syncthreads();
-          for (int e2 = tid; e2 < ns * RA; e2 += NTH) {
-            const int sl = e2 / RA, c2 = e2 - sl * RA;
-            const int mb = mbs[sl];
-            double v = 0.0;
-            if (mb >= 0) {
-              const typename DType<P>::type* Dm = Dbuf + mb * SD;
-              v = c2 < C ? (double)Dm[c2] : 0.0;
-#pragma unroll 8
-              for (int c = 0; c < C; ++c) v = fma(-(double)Dm[c], qm[c * RA + c2], v);
-            }
-            const double* gr = gkc + sl * kmax;
-#pragma unroll 8
-            for (int a = 0; a < r; ++a) v = fma(-gr[a], bm[a * RA + c2], v);
-            ec[sl * RA + c2] = v;
-          }
-          __syncthreads();
-          if (col) {
-#pragma unroll
-            for (int i2 = 0; i2 < SPT; ++i2) {
-              const int sl = half + 2 * i2;
-              if (sl >= ns) break;
-              const double* es = ec + sl * RA;
-              double v = gv[i2];
-#pragma unroll
-              for (int c = 0; c < RA; ++c) v = fma(es[c], wcol[c], v);
-              Gt[(long long)(s0 + sl) * nm + kc] = v;
-            }
-          }
-          __syncthreads();
-        }
-        if (col && half == 0) {
-#pragma unroll
-          for (int cp = 0; cp < C; ++cp) {
-            const double* qr = qm + cp * RA;
-            double v = wcol[cp];
-#pragma unroll
-            for (int c = 0; c < RA; ++c) v = fma(-qr[c], wcol[c], v);
-            PTt[(long long)kc * C + cp] = v;
-          }
-        }
-        __syncthreads();
       }
     }
-    // ---- configuration, labels, log|psi|
-    if (tid == 0) {
-      const int j = g.j;
-      occ_s[i] -= bit;
-      occ_s[j] += bit;
-      lab_s[sp * N + j] = (int16_t)k;
-      lab_s[sp * N + i] = -1;
-      pos_s[sp * nm + k] = (int16_t)j;
-      bf.ld[2 * w] += log(fabs(R0));
-      bf.ld[2 * w + 1] += log(fabs(R1));
-      if (R0 < 0) bf.sg[2 * w] = -bf.sg[2 * w];
-      if (R1 < 0) bf.sg[2 * w + 1] = -bf.sg[2 * w + 1];
+    int* klo = (int*)(st + sl.kl) + wv * kmaxb;
+    for (int a = lane; a < K; a += 64) klo[a] = kl[a];
+    double* gjo = (double*)(st + sl.gj) + (long long)wv * nm;
+    for (int kc = lane; kc < ntau; kc += 64) gjo[kc] = Gj[kc];
+  }
+  if (lane == 0) {
+    misc[2 + wv] = (double)K;
+    misc[4 + wv] = (double)hpos;
+    misc[6 + wv] = ok ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  const bool fallback = misc[6] == 0.0 || misc[7] == 0.0;
+
+  // ---- commit: the box features recomputed with write-back (D fresh in LDS)
+  hop_features<P, C, NW>(md, lt, g, occ_s, featw, featw, scratch, hsc, tab, olx, owx, oly, owy);
+  {
+    const int nv = owx * owy * (C + 4) * (int)sizeof(DT) / 16;
+    const float4* src = reinterpret_cast<const float4*>(scratch);
+    float4* dst = reinterpret_cast<float4*>(st + sl.D);
+    for (int e2 = tid; e2 < nv; e2 += NTH) dst[e2] = src[e2];
+  }
+  // ---- configuration, labels, log|psi|, counters, header
+  if (tid == 0) {
+    const int j = g.j;
+    occ_g[i] -= bit;
+    occ_g[j] += bit;
+    lab_g[sp * N + j] = (int16_t)k;
+    lab_g[sp * N + i] = -1;
+    pos_g[sp * nm + k] = (int16_t)j;
+    bf.ld[2 * w] += log(fabs(R0));
+    bf.ld[2 * w + 1] += log(fabs(R1));
+    if (R0 < 0) bf.sg[2 * w] = -bf.sg[2 * w];
+    if (R1 < 0) bf.sg[2 * w + 1] = -bf.sg[2 * w + 1];
+    const int na = fallback ? SW_REBUILD : bf.nacc[w] + 1;
+    bf.nacc[w] = na;
+    if (na >= sa.refresh_every) sa.due_list[atomicAdd(sa.due_count, 1)] = (int)w;
+    if (sa.n_accept) sa.n_accept[w] += 1;
+    hdr[HD_SP] = sp;
+    hdr[HD_K] = k;
+    hdr[HD_J] = j;
+    hdr[HD_OLX] = olx;
+    hdr[HD_OWX] = owx;
+    hdr[HD_OLY] = oly;
+    hdr[HD_OWY] = owy;
+    hdr[HD_R0] = (int)misc[2];
+    hdr[HD_R1] = (int)misc[3];
+    hdr[HD_HPOS] = (int)misc[4 + sp];
+    hdr[HD_ACC] = fallback ? 0 : 1;
+    if (!fallback) sa.acc_list[atomicAdd(sa.count, 1)] = (int)w;
+  }
+}
+
+// G and P updates of the walkers that accepted at this step: one item per
+// (walker, spin), items dealt to a persistent grid.  Block 0 clears the
+// counter of the next step.
+template <int P, int C>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_step_update(int L, const LatDev* __restrict__ lats, int nlats, Bufs bf,
+                                                     StepArgs sa) {
+  typedef typename DType<P>::type DT;
+  constexpr int NTH = 256, RA = C + 1, SC = UPD_SC, SD = DStride<C>::value;
+  constexpr int KS = (RA + 3) / 4;                          // k-steps of the 16x16x4 f64 MFMA
+  constexpr int ECS = 4 * KS;                               // E row stride (zero padded)
+  constexpr int CPT = (ECS + NTH / SC - 1) / (NTH / SC);   // E columns per thread
+  extern __shared__ __attribute__((aligned(16))) char smem[];
+  const int tid = threadIdx.x;
+  if (blockIdx.x == 0 && tid == 0) {
+    *sa.count_next = 0;
+    *sa.due_next = 0;
+  }
+  const long long items = 2LL * uniform_i(*(volatile int*)sa.count);
+  for (long long it = blockIdx.x; it < items; it += gridDim.x) {
+    const long long w = sa.acc_list[it >> 1];
+    const int tau = (int)(it & 1);
+    int li = 0;
+    while (li + 1 < nlats && w >= lats[li + 1].w0) ++li;
+    const LatDev lt = lats[li];
+    const long long wl = w - lt.w0;
+    const int N = lt.N, nm = lt.nmax;
+    const int n = tau == 0 ? lt.n[0] : lt.n[1];
+    if (n == 0) continue;                                             // uniform
+    const int kmaxb = box_kmax(lt.Gx, lt.Gy, L);
+    const StepStage sl = step_stage(nm, lt.Gx, lt.Gy, L, C, (int)sizeof(DT));
+    const char* st = sa.stage + w * sa.stage_stride;
+    const int* hdr = (const int*)(st + sl.hdr);
+    const int sp = hdr[HD_SP], kmv = hdr[HD_K], olx = hdr[HD_OLX], owx = hdr[HD_OWX], oly = hdr[HD_OLY],
+              owy = hdr[HD_OWY];
+    const int r = hdr[HD_R0 + tau], hpos = hdr[HD_HPOS];
+    const bool hs = tau == sp;
+    const int* klg = (const int*)(st + sl.kl) + tau * kmaxb;
+    const DT* Dg = (const DT*)(st + sl.D);
+    const double* aig = (const double*)(st + sl.ainv) + (long long)tau * RA * RA;
+    const double* gjs = (const double*)(st + sl.gj) + (long long)tau * nm;
+    double* Gt = bf.G + lt.g_off + wl * 2LL * N * nm + (long long)tau * N * nm;
+    double* PTt = bf.PT + lt.pt_off + wl * 2LL * nm * C + (long long)tau * nm * C;
+    double* ainv = (double*)smem;
+    double* bm = (double*)(smem + al16(RA * RA * 8));
+    int* kls = (int*)(smem + al16(RA * RA * 8) + al16(kmaxb * RA * 8));
+    double* ec = (double*)(smem + al16(RA * RA * 8) + al16(kmaxb * RA * 8) + al16(kmaxb * 4));
+    for (int e2 = tid; e2 < RA * RA; e2 += NTH) ainv[e2] = aig[e2];
+    for (int a = tid; a < r; a += NTH) kls[a] = klg[a];
+    __syncthreads();
+    // B = U A^-1: B[a][c2] = D(m_a) . A^-1[0:C, c2] + [moving spin, a = hpos] A^-1[C][c2]
+    for (int e2 = tid; e2 < r * RA; e2 += NTH) {
+      const int a = e2 / RA, c2 = e2 - a * RA;
+      const DT* Da = Dg + (kls[a] >> 16) * SD;
+      double v = (hs && a == hpos) ? ainv[C * RA + c2] : 0.0;
+#pragma unroll 8
+      for (int c = 0; c < C; ++c) v = fma((double)Da[c], ainv[c * RA + c2], v);
+      bm[e2] = v;
     }
     __syncthreads();
-    ++accepted;
-    ++nacc;
-    if (nacc >= sa.refresh_every || fallback) {
-      if (fallback) nacc = SW_REBUILD;
-      stop_refresh = true;
-      ++q;
-      break;
+    // G'[s][k'] = G[s][k'] + E[s] . W[:, k'] in chunks of SC sites
+    const int sl_ = tid % SC, part = tid / SC;
+    for (int s0 = 0; s0 < N; s0 += SC) {
+      const int ns = min(SC, N - s0);
+      if (sl_ < ns) {
+        const int s = s0 + sl_;
+        const int mb = box_index(lt, s, olx, owx, oly, owy);
+        double ev[CPT];
+#pragma unroll
+        for (int jj = 0; jj < CPT; ++jj) ev[jj] = 0.0;
+        if (mb >= 0) {
+          const DT* Dm = Dg + mb * SD;
+#pragma unroll 2
+          for (int c = 0; c < C; ++c) {
+            const double dv = (double)Dm[c];
+#pragma unroll
+            for (int jj = 0; jj < CPT; ++jj) {
+              const int c2 = part * CPT + jj;
+              if (c2 < RA) ev[jj] = fma(dv, ainv[c * RA + c2], ev[jj]);
+            }
+          }
+        }
+        const double* Gs = Gt + (long long)s * nm;
+#pragma unroll 1
+        for (int a0 = 0; a0 < r; a0 += 4) {
+          double gv[4];
+#pragma unroll
+          for (int u2 = 0; u2 < 4; ++u2) gv[u2] = a0 + u2 < r ? Gs[kls[a0 + u2] & 0xffff] : 0.0;
+#pragma unroll
+          for (int u2 = 0; u2 < 4; ++u2) {
+            if (a0 + u2 >= r) break;
+#pragma unroll
+            for (int jj = 0; jj < CPT; ++jj) {
+              const int c2 = part * CPT + jj;
+              if (c2 < RA) ev[jj] = fma(-gv[u2], bm[(a0 + u2) * RA + c2], ev[jj]);
+            }
+          }
+        }
+#pragma unroll
+        for (int jj = 0; jj < CPT; ++jj) {
+          const int c2 = part * CPT + jj;
+          if (c2 < ECS) ec[sl_ * ECS + c2] = ev[jj];     // zero for c2 >= C + 1
+        }
+      }
+      __syncthreads();
+      // G[s0 + i][16 tj + j] += sum_c2 E[i][c2] W[c2][16 tj + j] on the FP64
+      // matrix cores: A = E rows (LDS), B = W fragments, C = the G tile
+      {
+        const int wave = tid >> 6, lane = tid & 63, lj = lane & 15, lk = lane >> 4;
+        const int ntj = (n + 15) / 16;
+        for (int tj = wave; tj < ntj; tj += NTH / 64) {
+          const int kc = 16 * tj + lj;
+          double bw[KS];
+#pragma unroll
+          for (int qq = 0; qq < KS; ++qq) {
+            const int c2 = 4 * qq + lk;
+            double v = 0.0;
+            if (kc < n) {
+              if (c2 < C) v = PTt[(long long)kc * C + c2];
+              else if (c2 == C && hs) v = gjs[kc] - (kc == kmv ? 1.0 : 0.0);
+            }
+            bw[qq] = v;
+          }
+          for (int ti = 0; 16 * ti < ns; ++ti) {
+            v4d acc;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              const int sr = 16 * ti + lk + 4 * v;
+              acc[v] = (sr < ns && kc < n) ? Gt[(long long)(s0 + sr) * nm + kc] : 0.0;
+            }
+            const double* er = ec + (16 * ti + lj) * ECS + lk;
+#pragma unroll
+            for (int qq = 0; qq < KS; ++qq) mfma(acc, er[4 * qq], bw[qq]);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              const int sr = 16 * ti + lk + 4 * v;
+              if (sr < ns && kc < n) Gt[(long long)(s0 + sr) * nm + kc] = acc[v];
+            }
+          }
+        }
+      }
+      __syncthreads();
     }
-  }
-  // write back
-  for (int s = tid; s < N; s += NTH) occ_g[s] = occ_s[s];
-  for (int s = tid; s < 2 * N; s += NTH) lab_g[s] = lab_s[s];
-  for (int s = tid; s < 2 * nm; s += NTH) pos_g[s] = pos_s[s];
-  if (tid == 0) {
-    sa.prog[w] = (ne > 0) ? q : qend;
-    bf.nacc[w] = nacc;
-    if (sa.n_accept) sa.n_accept[w] += accepted;
-    if (stop_refresh && sa.paused) atomicAdd(sa.paused, 1);
+    // P^T'[k'] = A^-1[0:C, :] W[:, k'] (W from the old P^T and G[j])
+    for (int kc = tid; kc < n; kc += NTH) {
+      double wcol[RA];
+#pragma unroll
+      for (int c = 0; c < C; ++c) wcol[c] = PTt[(long long)kc * C + c];
+      wcol[C] = hs ? gjs[kc] - (kc == kmv ? 1.0 : 0.0) : 0.0;
+#pragma unroll 2
+      for (int cp = 0; cp < C; ++cp) {
+        double v = 0.0;
+#pragma unroll
+        for (int c = 0; c < RA; ++c) v = fma(ainv[cp * RA + c], wcol[c], v);
+        PTt[(long long)kc * C + cp] = v;
+      }
+    }
+    __syncthreads();
   }
 }
 
 template <int P, int C>
-static hipError_t sweep_impl(const ModelDev& md, const LatDev* lats_dev, int nlats, long long W, const Bufs& bf,
-                             const SweepArgs& sa, size_t smem, hipStream_t st) {
-  auto kern = k_sweep<P, C>;
-  hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
+static hipError_t step_impl(const ModelDev& md, const LatDev* lats_dev, int nlats, long long W, const Bufs& bf,
+                            const StepArgs& sa, size_t smem_p, size_t smem_u, int upd_blocks, hipStream_t st) {
+  auto kp = k_step_propose<P, C>;
+  auto ku = k_step_update<P, C>;
+  hipError_t e = hipFuncSetAttribute((const void*)kp, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem_p);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(kern, dim3((unsigned)W), dim3(64 * SW_NW), smem, st, md, lats_dev, nlats, bf, sa);
+  e = hipFuncSetAttribute((const void*)ku, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem_u);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(kp, dim3((unsigned)W), dim3(128), smem_p, st, md, lats_dev, nlats, bf, sa);
+  hipLaunchKernelGGL(ku, dim3((unsigned)upd_blocks), dim3(256), smem_u, st, md.L, lats_dev, nlats, bf, sa);
   return hipGetLastError();
 }
 
-hipError_t SVMC_CAT3(sweep_, SVMC_INST_P, SVMC_INST_C)(const ModelDev& md, const LatDev* lats_dev, int nlats,
-                                                       long long W, const Bufs& bf, const SweepArgs& sa,
-                                                       size_t smem, hipStream_t st) {
-  return sweep_impl<SVMC_INST_P, SVMC_INST_C>(md, lats_dev, nlats, W, bf, sa, smem, st);
+hipError_t SVMC_CAT3(sweep_step_, SVMC_INST_P, SVMC_INST_C)(const ModelDev& md, const LatDev* lats_dev, int nlats,
+                                                            long long W, const Bufs& bf, const StepArgs& sa,
+                                                            size_t smem_p, size_t smem_u, int upd_blocks,
+                                                            hipStream_t st) {
+  return step_impl<SVMC_INST_P, SVMC_INST_C>(md, lats_dev, nlats, W, bf, sa, smem_p, smem_u, upd_blocks, st);
 }
 #else
 // Drift of the maintained G before a refresh: max |G[pos_k][k'] - delta|
 // over occupied rows (these rows of M Phi^-1 are unit rows in exact
 // arithmetic); sets the DRIFT flag above 1e-8.  Only walkers due for a
 // refresh (nacc >= refresh_every) when only_due != 0.
-__global__ void k_drift(LatDev lt, Bufs bf, int only_due, int refresh_every) {
-  const long long wl = blockIdx.x;
+SVMC_DEV void drift_one(const LatDev& lt, const Bufs& bf, long long wl, double* red) {
   const long long w = lt.w0 + wl;
-  if (only_due && bf.nacc[w] < refresh_every) return;
   if (bf.nacc[w] == SW_REBUILD) return;
   const int N = lt.N, nm = lt.nmax;
   double mx = 0.0;
@@ -534,7 +536,6 @@ __global__ void k_drift(LatDev lt, Bufs bf, int only_due, int refresh_every) {
       mx = fmax(mx, fabs(v));
     }
   }
-  __shared__ double red[256];
   red[threadIdx.x] = mx;
   __syncthreads();
   for (int o = blockDim.x / 2; o > 0; o >>= 1) {
@@ -542,6 +543,16 @@ __global__ void k_drift(LatDev lt, Bufs bf, int only_due, int refresh_every) {
     __syncthreads();
   }
   if (threadIdx.x == 0 && !(red[0] <= 1e-8)) atomicOr(bf.flags + w, 4);
+}
+__global__ __launch_bounds__(256) void k_drift(LatDev lt, Bufs bf, WalkerSel sel) {
+  __shared__ double red[256];
+  for (long long z = blockIdx.x;; z += gridDim.x) {
+    long long wl;
+    const int r = pick_walker(sel, lt, z, wl);    // uniform in the block
+    if (r == 0) break;
+    if (r == 1) drift_one(lt, bf, wl, red);
+    __syncthreads();
+  }
 }
 
 __global__ void k_clear_nacc(LatDev lt, Bufs bf, int refresh_every) {
@@ -562,17 +573,32 @@ hipError_t launch_fill_i64(int64_t* p, long long n, int64_t v, hipStream_t st) {
   return hipGetLastError();
 }
 
-size_t sweep_smem(const LatDev* lats, int nlats, int prec, int L, int C) {
+// Workspace of one step: LDS of the proposal kernel, LDS of the update
+// kernel, and the staging bytes per walker.
+StepSizes step_sizes(const LatDev* lats, int nlats, int prec, int L, int C) {
   const int tfb = prec == PREC_F64 ? 8 : 4;
-  size_t mx = 0;
-  for (int l = 0; l < nlats; ++l)
-    mx = std::max(mx, (size_t)sweep_layout(lats[l].N, lats[l].nmax, lats[l].Gx, lats[l].Gy, L, C, tfb).bytes);
-  return mx;
+  StepSizes z{0, 0, 0};
+  for (int l = 0; l < nlats; ++l) {
+    const LatDev& lt = lats[l];
+    z.smem_propose = std::max(z.smem_propose, (size_t)propose_layout(lt.N, lt.Gx, lt.Gy, L, C, tfb).bytes);
+    z.smem_update = std::max(z.smem_update, (size_t)update_lds_bytes(box_kmax(lt.Gx, lt.Gy, L), C));
+    z.stage_bytes = std::max(z.stage_bytes, (size_t)step_stage(lt.nmax, lt.Gx, lt.Gy, L, C, tfb).bytes);
+  }
+  return z;
 }
-
-hipError_t launch_drift(const LatDev& lt, const Bufs& bf, int only_due, int refresh_every, hipStream_t st) {
+__global__ void k_fill_i32(int32_t* p, long long n, int32_t v) {
+  const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+hipError_t launch_fill_i32(int32_t* p, long long n, int32_t v, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, n, v);
+  return hipGetLastError();
+}
+hipError_t launch_drift(const LatDev& lt, const Bufs& bf, WalkerSel sel, hipStream_t st) {
   if (lt.nw == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_drift, dim3((unsigned)lt.nw), dim3(256), 0, st, lt, bf, only_due, refresh_every);
+  const long long slots = sel.list ? std::min<long long>(lt.nw, 256) : lt.nw;
+  hipLaunchKernelGGL(k_drift, dim3((unsigned)slots), dim3(256), 0, st, lt, bf, sel);
   return hipGetLastError();
 }
 
@@ -583,12 +609,21 @@ hipError_t launch_clear_nacc(const LatDev& lt, const Bufs& bf, int refresh_every
   return hipGetLastError();
 }
 
-hipError_t launch_sweep(int prec, const ModelDev& md, const LatDev* lats_dev, const LatDev* lats_host, int nlats,
-                        long long W, const Bufs& bf, const SweepArgs& sa, hipStream_t st) {
-  const size_t smem = sweep_smem(lats_host, nlats, prec, md.L, md.C);
-  if (smem > 160 * 1024) return hipErrorInvalidValue;
-#define SVMC_SW(P_, C_) \
-  if (prec == P_ && md.C == C_) return sweep_##P_##_##C_(md, lats_dev, nlats, W, bf, sa, smem, st);
+hipError_t launch_sweep_step(int prec, const ModelDev& md, const LatDev* lats_dev, const LatDev* lats_host,
+                             int nlats, long long W, const Bufs& bf, const StepArgs& sa, hipStream_t st) {
+  const StepSizes z = step_sizes(lats_host, nlats, prec, md.L, md.C);
+  if (z.smem_propose > 160 * 1024 || z.smem_update > 160 * 1024) return hipErrorInvalidValue;
+  // persistent update grid: as many workgroups as fit at once
+  const int per_cu = std::max(1, std::min(4, (int)((160 * 1024) / std::max<size_t>(z.smem_update, 1))));
+  int dev = 0, ncu = 256;
+  if (hipGetDevice(&dev) == hipSuccess) {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) == hipSuccess) ncu = prop.multiProcessorCount;
+  }
+  const int blocks = ncu * per_cu;
+#define SVMC_SW(P_, C_)                                                                                     \
+  if (prec == P_ && md.C == C_)                                                                           \
+    return sweep_step_##P_##_##C_(md, lats_dev, nlats, W, bf, sa, z.smem_propose, z.smem_update, blocks, st);
   SVMC_FOR_EACH_PREC_C(SVMC_SW)
 #undef SVMC_SW
   return hipErrorInvalidValue;

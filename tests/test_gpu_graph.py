@@ -3,7 +3,7 @@
 * The local-energy step (per-walker precompute + low-rank E_loc) recorded
   once and replayed several times, with other GPU work and synchronisation
   between replays: every replay equals the eager result bit for bit.
-* Metropolis sweeps by svmc_sweep_async (fixed rounds, step0 read from a
+* Metropolis sweeps by svmc_sweep_async (a fixed launch sequence, step0 read from a
   device scalar): two replays with step0 advanced in between reproduce the
   chain of two eager svmc_sweep calls exactly (configurations, electron
   positions, accept counts), and the state afterwards gives the oracle's
