@@ -389,9 +389,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     for (int e2 = tid; e2 < r * RA; e2 += NTH) {
       const int a = e2 / RA, c2 = e2 - a * RA;
       const DT* Da = Dg + (kls[a] >> 16) * SD;
+      DT dr[C];                      // the whole row requested before use
+#pragma unroll
+      for (int c = 0; c < C; ++c) dr[c] = Da[c];
       double v = (hs && a == hpos) ? ainv[C * RA + c2] : 0.0;
-#pragma unroll 8
-      for (int c = 0; c < C; ++c) v = fma((double)Da[c], ainv[c * RA + c2], v);
+#pragma unroll
+      for (int c = 0; c < C; ++c) v = fma((double)dr[c], ainv[c * RA + c2], v);
       bm[e2] = v;
     }
     __syncthreads();
@@ -407,9 +410,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
         for (int jj = 0; jj < CPT; ++jj) ev[jj] = 0.0;
         if (mb >= 0) {
           const DT* Dm = Dg + mb * SD;
+          DT dr[C];                    // the whole row requested before use
+#pragma unroll
+          for (int c = 0; c < C; ++c) dr[c] = Dm[c];
 #pragma unroll 2
           for (int c = 0; c < C; ++c) {
-            const double dv = (double)Dm[c];
+            const double dv = (double)dr[c];
 #pragma unroll
             for (int jj = 0; jj < CPT; ++jj) {
               const int c2 = part * CPT + jj;
@@ -419,12 +425,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
         }
         const double* Gs = Gt + (long long)s * nm;
 #pragma unroll 1
-        for (int a0 = 0; a0 < r; a0 += 4) {
-          double gv[4];
+        for (int a0 = 0; a0 < r; a0 += 8) {
+          double gv[8];                // eight G[s][k_a] loads in flight
 #pragma unroll
-          for (int u2 = 0; u2 < 4; ++u2) gv[u2] = a0 + u2 < r ? Gs[kls[a0 + u2] & 0xffff] : 0.0;
+          for (int u2 = 0; u2 < 8; ++u2) gv[u2] = a0 + u2 < r ? Gs[kls[a0 + u2] & 0xffff] : 0.0;
 #pragma unroll
-          for (int u2 = 0; u2 < 4; ++u2) {
+          for (int u2 = 0; u2 < 8; ++u2) {
             if (a0 + u2 >= r) break;
 #pragma unroll
             for (int jj = 0; jj < CPT; ++jj) {
