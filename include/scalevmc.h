@@ -177,12 +177,14 @@ svmc_status svmc_local_energy(svmc_ctx* ctx, svmc_path path, double* eloc,
  * rewrites the walker's cached features on the update box, updates
  * G = M Phi^-1 and P = W Phi^-1 by the Sherman-Morrison-Woodbury formula
  * (Sec. II.C) and log|psi|, sign by the ratio.  Proposal k of all walkers is
- * one step on the stream; after the step, walkers with refresh_every accepted
+ * one step on the stream.  Walkers that have made refresh_every accepted
  * moves get their rows, inverse, log|psi| and G/P rebuilt in FP64
  * (SVMC_W_DRIFT set first if the maintained G had drifted by more than 1e-8
- * on its occupied rows) before their next proposal, so the chain does not
- * depend on refresh_every.  A walker whose update matrix is singular keeps
- * the accepted configuration and is rebuilt at the same point.  Walkers
+ * on its occupied rows) at the next batch refresh, every 8 steps and after
+ * the last one; their updates stay exact meanwhile, so the chain does not
+ * depend on refresh_every.  A walker whose update matrix is numerically
+ * singular keeps the accepted configuration and is rebuilt right after that
+ * step, before its next proposal.  Walkers
  * flagged SINGULAR, NONFINITE or BADCOUNT are not moved.  In a mixed batch a
  * walker of a lattice with N sites takes n_sweeps * N proposals.
  * n_accept: device [W] int64 incremented by each walker's accepted moves, or

@@ -540,14 +540,33 @@ static svmc_status sweep_workspace(svmc_ctx* ctx, bool capturing, StepSizes& z) 
   if (z.smem_propose > 160 * 1024 || z.smem_update > 160 * 1024)
     return ctx->fail(SVMC_ERR_UNSUPPORTED, "sweep workspace exceeds 160 KiB of LDS");
   const size_t stage = (size_t)ctx->Wtot * z.stage_bytes, list = (size_t)ctx->Wtot * 4;
-  if (ctx->sw_stage.bytes < stage || ctx->sw_list.bytes < 2 * list || ctx->sw_count.bytes < 16) {
+  if (ctx->sw_stage.bytes < stage || ctx->sw_list.bytes < 3 * list || ctx->sw_count.bytes < 16) {
     if (capturing) return ctx->fail(SVMC_ERR_STATE, "call svmc_sweep_async once outside capture first (allocates)");
     svmc_status s;
     if ((s = ctx->hip(ctx->sw_stage.ensure(stage), "alloc")) ||
-        (s = ctx->hip(ctx->sw_list.ensure(2 * list), "alloc")) || (s = ctx->hip(ctx->sw_count.ensure(16), "alloc")))
+        (s = ctx->hip(ctx->sw_list.ensure(3 * list), "alloc")) || (s = ctx->hip(ctx->sw_count.ensure(16), "alloc")))
       return s;
   }
   return SVMC_OK;
+}
+
+// Proposal steps between batch refreshes: a walker that reaches
+// refresh_every accepted moves is rebuilt at most this many steps later.
+constexpr int kRefreshBatch = 8;
+
+// FP64 rebuild of the listed walkers (drift check first), their accept
+// counters cleared, then the list emptied.
+static svmc_status refresh_list(svmc_ctx* ctx, const Bufs& bf, WalkerSel sel, int32_t* count, hipStream_t st) {
+  svmc_status s;
+  for (auto& lt : ctx->ld) {
+    if ((s = ctx->hip(launch_drift(lt, bf, sel, st), "drift check")) ||
+        (s = ctx->hip(launch_rows(ctx->prec, lt, bf, ctx->L, ctx->C, st, sel), "rows")) ||
+        (s = ctx->hip(launch_gj(lt, bf, st, sel), "inverse")) ||
+        (s = ctx->hip(launch_gp(lt, bf, ctx->C, st, sel), "G/P precompute")) ||
+        (s = ctx->hip(launch_clear_nacc(lt, bf, sel, st), "clear")))
+      return s;
+  }
+  return ctx->hip(launch_fill_i32(count, 1, 0, st), "list reset");
 }
 
 static svmc_status sweep_steps(svmc_ctx* ctx, int32_t n_sweeps, uint64_t seed, uint64_t step0,
@@ -565,8 +584,11 @@ static svmc_status sweep_steps(svmc_ctx* ctx, int32_t n_sweeps, uint64_t seed, u
   sa.stage_stride = (long long)z.stage_bytes;
   sa.acc_list = ctx->sw_list.as<int32_t>();
   sa.due_list = ctx->sw_list.as<int32_t>() + ctx->Wtot;
+  sa.urgent_list = ctx->sw_list.as<int32_t>() + 2 * ctx->Wtot;
   sa.refresh_every = every;
-  int32_t* cnt = ctx->sw_count.as<int32_t>();     // [2] accepted, [2] due (per step parity)
+  int32_t* cnt = ctx->sw_count.as<int32_t>();     // [2] accepted (per step parity), due, urgent
+  sa.due_count = cnt + 2;
+  sa.urgent_count = cnt + 3;
   long long qmax = 0;
   for (auto& lt : ctx->ld) qmax = std::max(qmax, (long long)n_sweeps * lt.N);
   ctx->dets_fresh = false;
@@ -579,21 +601,15 @@ static svmc_status sweep_steps(svmc_ctx* ctx, int32_t n_sweeps, uint64_t seed, u
     sa.q = q;
     sa.count = cnt + (q & 1);
     sa.count_next = cnt + ((q + 1) & 1);
-    sa.due_count = cnt + 2 + (q & 1);
-    sa.due_next = cnt + 2 + ((q + 1) & 1);
     if ((s = ctx->hip(launch_sweep_step(ctx->prec, md, ctx->lats_dev.as<LatDev>(), ctx->ld.data(),
                                         (int)ctx->ld.size(), ctx->Wtot, bf, sa, st),
                       "sweep step")))
       return s;
-    const WalkerSel due{sa.due_list, sa.due_count};
-    for (auto& lt : ctx->ld) {
-      if ((s = ctx->hip(launch_drift(lt, bf, due, st), "drift check")) ||
-          (s = ctx->hip(launch_rows(ctx->prec, lt, bf, ctx->L, ctx->C, st, due), "rows")) ||
-          (s = ctx->hip(launch_gj(lt, bf, st, due), "inverse")) ||
-          (s = ctx->hip(launch_gp(lt, bf, ctx->C, st, due), "G/P precompute")) ||
-          (s = ctx->hip(launch_clear_nacc(lt, bf, every, st), "clear")))
-        return s;
-    }
+    // urgent rebuilds (almost always none) after every step; walkers that
+    // reached refresh_every together every kRefreshBatch steps and at the end
+    if ((s = refresh_list(ctx, bf, WalkerSel{sa.urgent_list, sa.urgent_count}, sa.urgent_count, st))) return s;
+    if ((q + 1) % kRefreshBatch == 0 || q + 1 == qmax)
+      if ((s = refresh_list(ctx, bf, WalkerSel{sa.due_list, sa.due_count}, sa.due_count, st))) return s;
   }
   return SVMC_OK;
 }

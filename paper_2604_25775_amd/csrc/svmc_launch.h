@@ -72,9 +72,10 @@ struct StepArgs {
   int32_t* acc_list;     // [W] walkers that accepted at this step
   int32_t* count;        // their number (zero on entry)
   int32_t* count_next;   // cleared for the next step
-  int32_t* due_list;     // [W] walkers to rebuild in FP64 after this step
-  int32_t* due_count;    // their number (zero on entry)
-  int32_t* due_next;     // cleared for the next step
+  int32_t* due_list;     // [W] walkers that reached refresh_every (batch refresh)
+  int32_t* due_count;    // their number since the last batch refresh
+  int32_t* urgent_list;  // [W] walkers to rebuild before their next proposal
+  int32_t* urgent_count; // their number (cleared by the host sequence each step)
   int refresh_every;
 };
 struct StepSizes {
@@ -85,7 +86,7 @@ hipError_t launch_sweep_step(int prec, const ModelDev& md, const LatDev* lats_de
                              int nlats, long long W, const Bufs& bf, const StepArgs& sa, hipStream_t st);
 hipError_t launch_fill_i32(int32_t* p, long long n, int32_t v, hipStream_t st);
 hipError_t launch_drift(const LatDev& lt, const Bufs& bf, WalkerSel sel, hipStream_t st);
-hipError_t launch_clear_nacc(const LatDev& lt, const Bufs& bf, int refresh_every, hipStream_t st);
+hipError_t launch_clear_nacc(const LatDev& lt, const Bufs& bf, WalkerSel sel, hipStream_t st);
 hipError_t launch_fill_i64(int64_t* p, long long n, int64_t v, hipStream_t st);
 
 // grad.hip: d log|psi| / d theta, one row per walker

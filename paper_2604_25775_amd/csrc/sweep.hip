@@ -317,9 +317,13 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(3))) void k
     bf.ld[2 * w + 1] += log(fabs(R1));
     if (R0 < 0) bf.sg[2 * w] = -bf.sg[2 * w];
     if (R1 < 0) bf.sg[2 * w + 1] = -bf.sg[2 * w + 1];
+    // a walker whose G and P could not be updated is rebuilt after this step
+    // (urgent list); one that reaches refresh_every accepted moves at the
+    // next batch refresh (its G and P stay current meanwhile)
     const int na = fallback ? SW_REBUILD : bf.nacc[w] + 1;
     bf.nacc[w] = na;
-    if (na >= sa.refresh_every) sa.due_list[atomicAdd(sa.due_count, 1)] = (int)w;
+    if (fallback) sa.urgent_list[atomicAdd(sa.urgent_count, 1)] = (int)w;
+    else if (na == sa.refresh_every) sa.due_list[atomicAdd(sa.due_count, 1)] = (int)w;
     if (sa.n_accept) sa.n_accept[w] += 1;
     hdr[HD_SP] = sp;
     hdr[HD_K] = k;
@@ -349,10 +353,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
   constexpr int CPT = (ECS + NTH / SC - 1) / (NTH / SC);   // E columns per thread
   extern __shared__ __attribute__((aligned(16))) char smem[];
   const int tid = threadIdx.x;
-  if (blockIdx.x == 0 && tid == 0) {
-    *sa.count_next = 0;
-    *sa.due_next = 0;
-  }
+  if (blockIdx.x == 0 && tid == 0) *sa.count_next = 0;
   const long long items = 2LL * uniform_i(*(volatile int*)sa.count);
   for (long long it = blockIdx.x; it < items; it += gridDim.x) {
     const long long w = sa.acc_list[it >> 1];
@@ -561,11 +562,14 @@ __global__ __launch_bounds__(256) void k_drift(LatDev lt, Bufs bf, WalkerSel sel
   }
 }
 
-__global__ void k_clear_nacc(LatDev lt, Bufs bf, int refresh_every) {
-  const long long wl = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-  if (wl >= lt.nw) return;
-  const long long w = lt.w0 + wl;
-  if (bf.nacc[w] >= refresh_every) bf.nacc[w] = 0;
+// accept counters of the selected walkers back to zero (after their rebuild)
+__global__ void k_clear_nacc(LatDev lt, Bufs bf, WalkerSel sel) {
+  for (long long z = blockIdx.x * (long long)blockDim.x + threadIdx.x;; z += (long long)gridDim.x * blockDim.x) {
+    long long wl;
+    const int r = pick_walker(sel, lt, z, wl);
+    if (r == 0) break;
+    if (r == 1) bf.nacc[lt.w0 + wl] = 0;
+  }
 }
 
 __global__ void k_fill_i64(int64_t* p, long long n, int64_t v) {
@@ -608,10 +612,10 @@ hipError_t launch_drift(const LatDev& lt, const Bufs& bf, WalkerSel sel, hipStre
   return hipGetLastError();
 }
 
-hipError_t launch_clear_nacc(const LatDev& lt, const Bufs& bf, int refresh_every, hipStream_t st) {
+hipError_t launch_clear_nacc(const LatDev& lt, const Bufs& bf, WalkerSel sel, hipStream_t st) {
   if (lt.nw == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_clear_nacc, dim3((unsigned)((lt.nw + 255) / 256)), dim3(256), 0, st, lt, bf,
-                     refresh_every);
+  const long long slots = sel.list ? std::min<long long>(lt.nw, 256) : lt.nw;
+  hipLaunchKernelGGL(k_clear_nacc, dim3((unsigned)((slots + 255) / 256)), dim3(256), 0, st, lt, bf, sel);
   return hipGetLastError();
 }
 
