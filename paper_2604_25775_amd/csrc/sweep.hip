@@ -350,7 +350,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
   constexpr int NTH = 256, RA = C + 1, SC = UPD_SC, SD = DStride<C>::value;
   constexpr int KS = (RA + 3) / 4;                          // k-steps of the 16x16x4 f64 MFMA
   constexpr int ECS = 4 * KS;                               // E row stride (zero padded)
-  constexpr int CPT = (ECS + NTH / SC - 1) / (NTH / SC);   // E columns per thread
+  static_assert(RA <= 48 && SC == 16 * (NTH / 64), "E product tiles: 3 column tiles, one row tile per wave");
   extern __shared__ __attribute__((aligned(16))) char smem[];
   const int tid = threadIdx.x;
   if (blockIdx.x == 0 && tid == 0) *sa.count_next = 0;
@@ -399,58 +399,64 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
       bm[e2] = v;
     }
     __syncthreads();
-    // G'[s][k'] = G[s][k'] + E[s] . W[:, k'] in chunks of SC sites
-    const int sl_ = tid % SC, part = tid / SC;
+    // G'[s][k'] = G[s][k'] + E[s] . W[:, k'] in chunks of SC sites.  E of a
+    // chunk is one product on the FP64 matrix cores,
+    //   E = [D(s) on the box | -G[s, K]] [A^-1[0:C, :]; B]   (K dim C + r),
+    // wavefront t forming the rows of sites 16 t .. 16 t + 15.
+    const int wave = tid >> 6, lane = tid & 63, lj = lane & 15, lk = lane >> 4;
+    const int ke = (C + r + 3) / 4;                 // k-steps of the E product
     for (int s0 = 0; s0 < N; s0 += SC) {
       const int ns = min(SC, N - s0);
-      if (sl_ < ns) {
-        const int s = s0 + sl_;
-        const int mb = box_index(lt, s, olx, owx, oly, owy);
-        double ev[CPT];
+      if (16 * wave < ns) {
+        const int si = 16 * wave + lj;              // this lane's A row (site)
+        const bool sok = si < ns;
+        const int s = s0 + si;
+        const int mb = sok ? box_index(lt, s, olx, owx, oly, owy) : -1;
+        const DT* Dm = Dg + (mb >= 0 ? mb : 0) * SD;
+        const double* Gs = Gt + (long long)(sok ? s : 0) * nm;
+        v4d eacc[3];
 #pragma unroll
-        for (int jj = 0; jj < CPT; ++jj) ev[jj] = 0.0;
-        if (mb >= 0) {
-          const DT* Dm = Dg + mb * SD;
-          DT dr[C];                    // the whole row requested before use
+        for (int tj = 0; tj < 3; ++tj) eacc[tj] = v4d{0.0, 0.0, 0.0, 0.0};
+        for (int q0 = 0; q0 < ke; q0 += 4) {
+          double av[4];                             // four A operands in flight
 #pragma unroll
-          for (int c = 0; c < C; ++c) dr[c] = Dm[c];
-#pragma unroll 2
-          for (int c = 0; c < C; ++c) {
-            const double dv = (double)dr[c];
+          for (int u2 = 0; u2 < 4; ++u2) {
+            const int kk = 4 * (q0 + u2) + lk;
+            double v = 0.0;
+            if (kk < C) {
+              if (mb >= 0) v = (double)Dm[kk];
+            } else if (sok && kk - C < r) {
+              v = -Gs[kls[kk - C] & 0xffff];
+            }
+            av[u2] = v;
+          }
 #pragma unroll
-            for (int jj = 0; jj < CPT; ++jj) {
-              const int c2 = part * CPT + jj;
-              if (c2 < RA) ev[jj] = fma(dv, ainv[c * RA + c2], ev[jj]);
+          for (int u2 = 0; u2 < 4; ++u2) {
+            if (q0 + u2 >= ke) break;
+            const int kk = 4 * (q0 + u2) + lk;
+            const double* brow = kk < C ? ainv + kk * RA : bm + (kk - C) * RA;
+            const bool kok = kk < C + r;
+#pragma unroll
+            for (int tj = 0; tj < 3; ++tj) {
+              const int col = 16 * tj + lj;
+              const double bv = (kok && col < RA) ? brow[col] : 0.0;
+              mfma(eacc[tj], av[u2], bv);
             }
           }
         }
-        const double* Gs = Gt + (long long)s * nm;
-#pragma unroll 1
-        for (int a0 = 0; a0 < r; a0 += 8) {
-          double gv[8];                // eight G[s][k_a] loads in flight
+        // E rows to LDS (columns C + 1 .. ECS - 1 are zero)
 #pragma unroll
-          for (int u2 = 0; u2 < 8; ++u2) gv[u2] = a0 + u2 < r ? Gs[kls[a0 + u2] & 0xffff] : 0.0;
+        for (int tj = 0; tj < 3; ++tj) {
+          const int col = 16 * tj + lj;
+          if (col >= ECS) continue;
 #pragma unroll
-          for (int u2 = 0; u2 < 8; ++u2) {
-            if (a0 + u2 >= r) break;
-#pragma unroll
-            for (int jj = 0; jj < CPT; ++jj) {
-              const int c2 = part * CPT + jj;
-              if (c2 < RA) ev[jj] = fma(-gv[u2], bm[(a0 + u2) * RA + c2], ev[jj]);
-            }
-          }
-        }
-#pragma unroll
-        for (int jj = 0; jj < CPT; ++jj) {
-          const int c2 = part * CPT + jj;
-          if (c2 < ECS) ec[sl_ * ECS + c2] = ev[jj];     // zero for c2 >= C + 1
+          for (int v = 0; v < 4; ++v) ec[(16 * wave + lk + 4 * v) * ECS + col] = eacc[tj][v];
         }
       }
       __syncthreads();
       // G[s0 + i][16 tj + j] += sum_c2 E[i][c2] W[c2][16 tj + j] on the FP64
       // matrix cores: A = E rows (LDS), B = W fragments, C = the G tile
       {
-        const int wave = tid >> 6, lane = tid & 63, lj = lane & 15, lk = lane >> 4;
         const int ntj = (n + 15) / 16;
         for (int tj = wave; tj < ntj; tj += NTH / 64) {
           const int kc = 16 * tj + lj;
