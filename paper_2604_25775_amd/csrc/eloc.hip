@@ -164,11 +164,31 @@ __global__ __launch_bounds__(64 * ELOC_NW) __attribute__((amdgpu_waves_per_eu(3)
       hop_det_build<C>(kl, K, wv == sp, hpos, (const typename DType<P>::type*)scratch, PTt, Gj, lane, dacc);
       __syncthreads();      // both matrices built: their staging may overwrite D
       double* stage = (double*)scratch + wv * (C + 1) * DetTiles<C>::RS;
-      const double Rt = hop_det_finish<C>(dacc, kl, K, wv == sp, hpos, PTt, Gj, stage, lane);
-      if (lane == 0) misc[wv] = Rt;
+      hop_det_stage<C>(dacc, kl, K, wv == sp, hpos, PTt, Gj, stage, lane);
+      // the moving spin's matrix is brought to C x C by one elimination step
+      if (wv == sp) {
+        const double f = hop_det_reduce<C>(stage, lane);
+        if (lane == 0) misc[2] = f;
+      }
+      __syncthreads();
+      // both C x C determinants by wavefront 0, one matrix per half
+      if (wv == 0) {
+        const double* sr = (const double*)scratch + (lane >> 5) * (C + 1) * DetTiles<C>::RS +
+                           ((lane & 31) < C ? (lane & 31) : 0) * DetTiles<C>::RS;
+        double a[C];
+#pragma unroll
+        for (int c2 = 0; c2 < C / 2; ++c2) {
+          const double2 v = reinterpret_cast<const double2*>(sr)[c2];
+          a[2 * c2] = (lane & 31) < C ? v.x : 0.0;
+          a[2 * c2 + 1] = (lane & 31) < C ? v.y : 0.0;
+        }
+        __builtin_amdgcn_wave_barrier();
+        const double dt = lu_det_pair<C>(a, lane);
+        if ((lane & 31) == 0) misc[lane >> 5] = dt;
+      }
       __syncthreads();
       if (tid == 0) {
-        const double R = misc[0] * misc[1];
+        const double R = misc[0] * misc[1] * misc[2];
         part += -(d < 4 ? lt.t : lt.tp) * R;
         nonfinite |= !isfinite(R);
         if (out.ratio) {

@@ -727,19 +727,19 @@ SVMC_DEV void hop_det_build(const int* kl, int K_in, bool hopspin, int hpos_in, 
   }
 }
 
-// Adds the identity and column C (moving spin: P^T[k_h], G[j][k_h]), stages
-// the matrix row-major in `stage` ((C + 1) x (C + 2) doubles of this
-// wavefront; the caller makes sure nothing else uses it) and returns its
-// determinant by the one-wave LU.  The 16 x 16 f64 MFMA result holds
+// Adds the identity and column C (moving spin: P^T[k_h], G[j][k_h]) and
+// stages the matrix row-major in `stage` ((C + 1) x (C + 2) doubles of this
+// wavefront; the caller makes sure nothing else uses it): C x C for the spin
+// that does not move, (C + 1) x (C + 1) for the moving one; with no changed
+// rows (K = 0) the identity.  The 16 x 16 f64 MFMA result holds
 // A[16 ti + l / 16 + 4 v][16 tj + l % 16] in slot v of lane l.
 template <int C>
-SVMC_DEV double hop_det_finish(const v4d (&acc)[DetTiles<C>::I][DetTiles<C>::J], const int* kl, int K_in,
-                               bool hopspin, int hpos_in, const double* __restrict__ PTt,
-                               const double* __restrict__ Gj, double* stage, int lane) {
+SVMC_DEV void hop_det_stage(const v4d (&acc)[DetTiles<C>::I][DetTiles<C>::J], const int* kl, int K_in,
+                            bool hopspin, int hpos_in, const double* __restrict__ PTt,
+                            const double* __restrict__ Gj, double* stage, int lane) {
   typedef DetTiles<C> T;
-  constexpr int RM = C + 1, RS = T::RS;
+  constexpr int RS = T::RS;
   const int K = uniform_i(K_in), hpos = uniform_i(hpos_in);
-  if (K == 0) return 1.0;
   const int R = C + (hopspin ? 1 : 0);
   const int r16 = lane & 15, qo = lane >> 4;
 #pragma unroll
@@ -749,18 +749,137 @@ SVMC_DEV double hop_det_finish(const v4d (&acc)[DetTiles<C>::I][DetTiles<C>::J],
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int r = 16 * ti + qo + 4 * v, c = 16 * tj + r16;
-        if (r < R && c < C) stage[r * RS + c] = acc[ti][tj][v] + (r == c ? 1.0 : 0.0);
+        if (r < R && c < C) stage[r * RS + c] = (K > 0 ? acc[ti][tj][v] : 0.0) + (r == c ? 1.0 : 0.0);
       }
   if (hopspin) {
-    const int kh = kl[hpos] & 0xffff;
-    if (lane < C) stage[lane * RS + C] = PTt[kh * C + lane];
-    else if (lane == C) stage[C * RS + C] = Gj[kh];
+    const int kh = K > 0 ? kl[hpos] & 0xffff : 0;
+    if (lane < C) stage[lane * RS + C] = K > 0 ? PTt[kh * C + lane] : 0.0;
+    else if (lane == C) stage[C * RS + C] = K > 0 ? Gj[kh] : 1.0;
   }
   // lanes read rows other lanes wrote: order the accesses for the compiler
   // (the hardware keeps a wavefront's LDS operations in order)
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// One elimination step on the staged (C + 1) x (C + 1) matrix of the moving
+// spin (one wavefront, one row per lane): pivot on column 0 over all rows,
+// then the C x C Schur complement (the other rows in their order, columns
+// 1 .. C) replaces the matrix at the top left of the stage.  Returns the
+// factor it takes off the determinant, (-1)^piv * pivot (the pivot row moved
+// to the top), or 0 for a zero column.
+template <int C>
+SVMC_DEV double hop_det_reduce(double* stage, int lane) {
+  constexpr int RM = C + 1, RS = DetTiles<C>::RS;
+  double a[RM];
+  const double2* rp = reinterpret_cast<const double2*>(stage + (lane < RM ? lane : 0) * RS);
+#pragma unroll
+  for (int c2 = 0; c2 < RS / 2; ++c2) {
+    const double2 v = rp[c2];
+    if (2 * c2 < RM) a[2 * c2] = lane < RM ? v.x : 0.0;
+    if (2 * c2 + 1 < RM) a[2 * c2 + 1] = lane < RM ? v.y : 0.0;
+  }
+  const bool out = lane >= RM;
+  const unsigned kmax = wave_max_u32(piv_key(a[0], out, lane));
+  const bool sing = (kmax & ~63u) == 0u;
+  const int piv = 63 - (int)(kmax & 63u);
+  const double pv = readlane_d(a[0], piv);
+  const double l = (out || lane == piv) ? 0.0 : a[0] * rcp_d(sing ? 1.0 : pv);
+#pragma unroll
+  for (int c = 1; c < RM; ++c) a[c] = fma(-l, readlane_d(a[c], piv), a[c]);
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  if (!out && lane != piv) {
+    double2* wp = reinterpret_cast<double2*>(stage + (lane - (lane > piv ? 1 : 0)) * RS);
+#pragma unroll
+    for (int c2 = 0; c2 < C / 2; ++c2) wp[c2] = double2{a[2 * c2 + 1], a[2 * c2 + 2]};
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  if (sing) return 0.0;
+  return (piv & 1) ? -pv : pv;
+}
+
+// Value of lane src of a 64-bit register (src given as byte address 4 src;
+// every lane must be active).
+SVMC_DEV double bperm_d(int addr, double x) {
+  const long long v = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_ds_bpermute(addr, (int)(v & 0xffffffffLL));
+  const int hi = __builtin_amdgcn_ds_bpermute(addr, (int)(v >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Two C x C LU determinants in one wavefront: lanes 0 .. 31 hold the rows of
+// the first matrix, lanes 32 .. 63 those of the second (row = lane mod 32,
+// rows >= C take no part).  The same steps as the one-matrix LU above, with
+// each half searching its own pivot (row maxima by DPP, the two rows of a
+// half joined by a row broadcast, read back from lanes 31 and 63) and taking
+// its pivot row by lane permutes.  The sign of each half's pivot order is
+// kept step by step: moving the pivot ahead of the unused rows before it
+// costs one transposition per such row.  Lane 0 returns the first
+// determinant, lane 32 the second.
+template <int C>
+SVMC_DEV double lu_det_pair(double (&a)[C], int lane) {
+  static_assert(C <= 32 && C % 2 == 0, "one matrix per half wavefront, rows read in pairs");
+  const bool hi_half = lane >= 32;
+  bool used = (lane & 31) >= C;
+  double det = 1.0;
+  unsigned par_lo = 0, par_hi = 0;
+  bool sing_lo = false, sing_hi = false;
+  auto half_max = [&](unsigned v, unsigned& k_lo, unsigned& k_hi) {
+    v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, false));   // quad_perm 1,0,3,2
+    v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, false));   // quad_perm 2,3,0,1
+    v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x141, 0xF, 0xF, false));  // row_half_mirror
+    v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x140, 0xF, 0xF, false));  // row_mirror
+    v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xA, 0xF, false));  // row_bcast:15
+    k_lo = (unsigned)__builtin_amdgcn_readlane((int)v, 31);
+    k_hi = (unsigned)__builtin_amdgcn_readlane((int)v, 63);
+  };
+  unsigned k_lo, k_hi;
+  half_max(piv_key(a[0], used, lane), k_lo, k_hi);
+#pragma unroll
+  for (int p = 0; p < C; ++p) {
+    sing_lo = sing_lo || (k_lo & ~63u) == 0u;
+    sing_hi = sing_hi || (k_hi & ~63u) == 0u;
+    const int piv_lo = 63 - (int)(k_lo & 63u), piv_hi = 63 - (int)(k_hi & 63u);
+    const int piv = hi_half ? piv_hi : piv_lo;
+    const int addr = piv << 2;
+    // rows of this half still unused and before the pivot
+    const unsigned long long before = __ballot(!used && lane < piv);
+    par_lo ^= (unsigned)__popcll(before & 0xffffffffULL);
+    par_hi ^= (unsigned)__popcll(before >> 32);
+    const double pv = bperm_d(addr, a[p]);
+    det *= pv;
+    if (lane == piv) used = true;
+    if (p + 1 < C) {
+      const bool sing = hi_half ? sing_hi : sing_lo;
+      const double l = used ? 0.0 : a[p] * rcp_d(sing ? 1.0 : pv);
+      a[p + 1] = fma(-l, bperm_d(addr, a[p + 1]), a[p + 1]);
+      half_max(piv_key(a[p + 1], used, lane), k_lo, k_hi);
+#pragma unroll
+      for (int c = p + 2; c < C; ++c) a[c] = fma(-l, bperm_d(addr, a[c]), a[c]);
+    }
+  }
+  const bool sing = hi_half ? sing_hi : sing_lo;
+  const bool odd = ((hi_half ? par_hi : par_lo) & 1u) != 0u;
+  if (sing) return 0.0;
+  return odd ? -det : det;
+}
+
+// Stages the matrix (hop_det_stage) and returns its determinant by the
+// one-wave LU.
+template <int C>
+SVMC_DEV double hop_det_finish(const v4d (&acc)[DetTiles<C>::I][DetTiles<C>::J], const int* kl, int K_in,
+                               bool hopspin, int hpos_in, const double* __restrict__ PTt,
+                               const double* __restrict__ Gj, double* stage, int lane) {
+  typedef DetTiles<C> T;
+  constexpr int RM = C + 1, RS = T::RS;
+  const int K = uniform_i(K_in);
+  if (K == 0) return 1.0;
+  const int R = C + (hopspin ? 1 : 0);
+  hop_det_stage<C>(acc, kl, K_in, hopspin, hpos_in, PTt, Gj, stage, lane);
   // rows in lanes < RM; the spin that does not move gets an identity row and
   // column C (same determinant), so both matrices take the same RM steps
   double a[RM];
