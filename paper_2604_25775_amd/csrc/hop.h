@@ -684,8 +684,15 @@ SVMC_DEV void hop_det_build(const int* kl, int K_in, bool hopspin, int hpos_in, 
   typedef DetTiles<C> T;
   constexpr int SD = DStride<C>::value;
   constexpr int U = 4;                         // steps whose loads are in flight together
+  // with C a multiple of 16, row C sits alone in the last row tile: it is
+  // summed on the vector units (changed row q of lane group q mod 4) instead
+  // of taking a row tile of products for one row
+  constexpr bool ROWC_V = C % 16 == 0;
   const int K = uniform_i(K_in), hpos = uniform_i(hpos_in);
   const int r16 = lane & 15, qo = lane >> 4;
+  double rc[T::J];
+#pragma unroll
+  for (int tj = 0; tj < T::J; ++tj) rc[tj] = 0.0;
 #pragma unroll
   for (int ti = 0; ti < T::I; ++ti)
 #pragma unroll
@@ -700,7 +707,7 @@ SVMC_DEV void hop_det_build(const int* kl, int K_in, bool hopspin, int hpos_in, 
       const int kq = e & 0xffff, mo = (e >> 16) * SD;
 #pragma unroll
       for (int ti = 0; ti < T::I; ++ti) {
-        const int c = 16 * ti + r16;
+        const int c = ROWC_V && ti == T::I - 1 ? C : 16 * ti + r16;
         double v = 0.0;
         if (ok) {
           if (c < C) v = PTt[kq * C + c];
@@ -720,9 +727,25 @@ SVMC_DEV void hop_det_build(const int* kl, int K_in, bool hopspin, int hpos_in, 
 #pragma unroll
       for (int ti = 0; ti < T::I; ++ti) {
         if (16 * ti >= C && !hopspin) continue;          // row C only for the moving spin
+        if (ROWC_V && ti == T::I - 1) {
+#pragma unroll
+          for (int tj = 0; tj < T::J; ++tj) rc[tj] = fma(x[u][ti], y[u][tj], rc[tj]);
+          continue;
+        }
 #pragma unroll
         for (int tj = 0; tj < T::J; ++tj) mfma(acc[ti][tj], x[u][ti], y[u][tj]);
       }
+    }
+  }
+  if constexpr (ROWC_V) {
+    // the four lane groups' partial sums of row C to lanes 0 .. 15, where the
+    // row tile's result would hold it (row 16 (I - 1) + 0 in slot 0)
+#pragma unroll
+    for (int tj = 0; tj < T::J; ++tj) {
+      double v = rc[tj];
+      v += __shfl_xor(v, 16, 64);
+      v += __shfl_xor(v, 32, 64);
+      acc[T::I - 1][tj][0] = qo == 0 ? v : 0.0;
     }
   }
 }
