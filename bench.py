@@ -47,6 +47,52 @@ def log(*a):
 
 
 # ---------------------------------------------------------------------------
+# HBM traffic of the E_loc launch from counter runs (profiles/)
+# ---------------------------------------------------------------------------
+COPY_PROBE_BYTES = 1 << 30      # the known-size copy of the traffic probe
+
+
+def kernel_src_sha1() -> str:
+    """SHA-1 over the HIP/C++ sources of the library (names and contents in
+    name order): a counter record holds for the sources it was taken on."""
+    import hashlib
+    d = os.path.join(ROOT, "paper_2604_25775_amd", "csrc")
+    h = hashlib.sha1()
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".hip", ".h", ".cpp")):
+            h.update(f.encode())
+            with open(os.path.join(d, f), "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()
+
+
+def traffic_record(workload: str, walkers: int, prec: str):
+    """HBM bytes per E_loc launch from a committed counter summary
+    (a `traffic-record:` line under profiles/): FETCH_SIZE and WRITE_SIZE of
+    the launch, each scaled by bytes / counter of a plain copy of known size
+    in the same run.  None when no record matches this workload or the
+    sources have changed since the counters were taken."""
+    d = os.path.join(ROOT, "profiles")
+    if not os.path.isdir(d):
+        return None
+    sha = kernel_src_sha1()
+    for f in sorted(os.listdir(d)):
+        if not f.endswith((".md", ".txt")):
+            continue
+        with open(os.path.join(d, f)) as fh:
+            for ln in fh:
+                if not ln.startswith("traffic-record:"):
+                    continue
+                r = json.loads(ln.split(":", 1)[1])
+                if (r.get("src_sha1") == sha and r.get("workload") == workload
+                        and r.get("walkers") == walkers and r.get("prec") == prec):
+                    fetch = r["fetch_kib"] * COPY_PROBE_BYTES / r["copy_fetch_kib"]
+                    write = r["write_kib"] * COPY_PROBE_BYTES / r["copy_write_kib"]
+                    return {"bytes": fetch + write, "fetch_bytes": fetch, "write_bytes": write, "file": f}
+    return None
+
+
+# ---------------------------------------------------------------------------
 # algorithmic work of the low-rank kernel (accounting only, numpy)
 # ---------------------------------------------------------------------------
 def lowrank_flops(lat, occ: np.ndarray, L: int, C: int):
@@ -212,6 +258,10 @@ def main():
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--tune-cache", default=None,
                     help="autotuner cache file (default: tune, do not store)")
+    ap.add_argument("--traffic-probe", action="store_true",
+                    help="after the sweeps and the tuner: one E_loc step and one copy of "
+                         "COPY_PROBE_BYTES, then exit (the program for rocprofv3 --pmc "
+                         "FETCH_SIZE / WRITE_SIZE runs)")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py measures one GPU only (asked for {a.gpus}); the walker-parallel "
@@ -254,6 +304,18 @@ def main():
     slices = ctx.tune(a.tune_cache)
     extra["eloc_slices_per_walker"] = slices
     log(f"[bench] autotuner: {slices} workgroups per walker")
+    if a.traffic_probe:
+        ctx.prepare()
+        ctx.local_energy(out=eloc)
+        torch.cuda.synchronize()
+        x = torch.ones(COPY_PROBE_BYTES // 4, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        torch.cuda.synchronize()
+        y.copy_(x)
+        torch.cuda.synchronize()
+        log(f"[bench] traffic probe: one E_loc step, then a copy of {COPY_PROBE_BYTES} bytes "
+            f"(sources {kernel_src_sha1()})")
+        return
     for _ in range(a.warmup):
         ctx.prepare()
         ctx.local_energy(out=eloc)
@@ -285,8 +347,13 @@ def main():
     t_peak = conv_f * passes / conv_peak + det_f / PEAK_FP64
     achieved = (conv_f + det_f) / (kern_ms / 1e3) / 1e12
     peak = (conv_f + det_f) / t_peak / 1e12
+    tr = traffic_record(wl.name, W, a.prec)
     roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": round(peak, 3),
-                "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
+                "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
+                "traffic": round(tr["bytes"]) if tr else None,
+                "traffic_note": (f"HBM bytes per launch, FETCH_SIZE + WRITE_SIZE scaled by a "
+                                 f"{COPY_PROBE_BYTES}-byte copy ({tr['file']})") if tr else
+                                "no counter record for these sources",
                 "kernel": "k_eloc_lowrank",
                 "flops_conv_per_launch": conv_f, "flops_fp64_per_launch": det_f,
                 "conv_passes": passes,

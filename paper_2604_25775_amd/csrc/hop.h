@@ -380,6 +380,12 @@ SVMC_DEV void hop_features(const ModelDev& md, const LatDev& lt, const HopGeom& 
   }
   __syncthreads();
   for (int l = 1; l <= L; ++l) {
+    // the thread index once more through an opaque copy per layer: the
+    // per-tile lane addresses below are then recomputed in each layer rather
+    // than hoisted out of the layer loop and spilled
+    int tid;
+    asm volatile("v_mov_b32 %0, %1" : "=v"(tid) : "v"((int)threadIdx.x));
+    const int lane = tid & 63;
     box1(ax, h.xi, h.dx, l, olx, owx);
     box1(ay, h.yi, h.dy, l, oly, owy);
     const int cnt = uniform_i(owx * owy);
