@@ -134,30 +134,71 @@ __global__ void k_labels(LatDev lt, Bufs bf) {
   bf.nacc[w] = 0;
 }
 
-// M_s[x][m] = base_s[x][m] + sum_c H_L[x][c] W_s[c][m] + b_s[m]
-template <class Tf>
-SVMC_DEV void rows_one(const LatDev& lt, const Bufs& bf, int L, int C, long long wl, int sp, int e) {
-  const int N = lt.N, nm = lt.nmax;
-  if (e >= N * nm) return;
-  const int x = e / nm, m = e % nm;
+// M_s[x][m] = base_s[x][m] + sum_c H_L[x][c] W_s[c][m] + b_s[m] (zero for
+// m >= n_s) on the FP64 matrix cores: one workgroup of four wavefronts per
+// (walker, spin), wavefront w taking the 16-row tiles w, w + 4, ...; the W_s
+// fragments of RC_CT column tiles stay in registers while the wavefront runs
+// over its row tiles.  16 x 16 x 4 tiles: A[i][k] = H_L[16 ti + i][4 q + k]
+// from lane i + 16 k, B[k][j] = W_s[4 q + k][16 tj + j] from lane j + 16 k,
+// result row 4 v + l / 16, column l % 16 in slot v of lane l.
+constexpr int RC_CT = 4;
+template <class Tf, int KS>
+SVMC_DEV void rows_one(const LatDev& lt, const Bufs& bf, int L, int C, long long wl, int sp) {
+  const int N = lt.N, nm = lt.nmax, n = lt.n[sp];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lj = lane & 15, lk = lane >> 4;
   double* M = bf.M + lt.m_off + wl * 2LL * N * nm + (long long)sp * N * nm;
-  if (m >= lt.n[sp]) { M[e] = 0.0; return; }
-  const Tf* H = (const Tf*)bf.feat + lt.feat_off + wl * (long long)L * N * C + (long long)(L - 1) * N * C +
-                (long long)x * C;
+  const Tf* H = (const Tf*)bf.feat + lt.feat_off + wl * (long long)L * N * C + (long long)(L - 1) * N * C;
   const double* W = lt.W + (long long)sp * C * nm;
-  double acc = lt.base[((long long)sp * N + x) * nm + m] + lt.b[sp * nm + m];
-  for (int c = 0; c < C; ++c) acc = fma((double)H[c], W[c * nm + m], acc);
-  M[e] = acc;
+  const double* base = lt.base + (long long)sp * N * nm;
+  const double* bb = lt.b + sp * nm;
+  const int ntr = (N + 15) / 16, ntc = (nm + 15) / 16;
+  for (int tc0 = 0; tc0 < ntc; tc0 += RC_CT) {
+    double bw[RC_CT][KS];
+#pragma unroll
+    for (int ct = 0; ct < RC_CT; ++ct)
+#pragma unroll
+      for (int q = 0; q < KS; ++q) {
+        const int col = 16 * (tc0 + ct) + lj, k = 4 * q + lk;
+        bw[ct][q] = (col < n && k < C) ? W[(long long)k * nm + col] : 0.0;
+      }
+    for (int ti = wave; ti < ntr; ti += 4) {
+      double av[KS];
+      const int row = 16 * ti + lj;
+#pragma unroll
+      for (int q = 0; q < KS; ++q) {
+        const int k = 4 * q + lk;
+        av[q] = (row < N && k < C) ? (double)H[(long long)row * C + k] : 0.0;
+      }
+#pragma unroll
+      for (int ct = 0; ct < RC_CT; ++ct) {
+        const int col = 16 * (tc0 + ct) + lj;
+        if (16 * (tc0 + ct) >= nm) break;
+        v4d acc;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int r = 16 * ti + lk + 4 * v;
+          acc[v] = (r < N && col < n) ? base[(long long)r * nm + col] + bb[col] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < KS; ++q) mfma(acc, av[q], bw[ct][q]);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int r = 16 * ti + lk + 4 * v;
+          if (r < N && col < nm) M[(long long)r * nm + col] = acc[v];
+        }
+      }
+    }
+  }
 }
-template <class Tf>
-__global__ void k_rows(LatDev lt, Bufs bf, int L, int C, WalkerSel sel) {
+template <class Tf, int KS>
+__global__ __launch_bounds__(256) void k_rows(LatDev lt, Bufs bf, int L, int C, WalkerSel sel) {
   const int sp = blockIdx.y;
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  for (long long z = blockIdx.z;; z += gridDim.z) {
+  for (long long z = blockIdx.x;; z += gridDim.x) {
     long long wl;
-    const int r = pick_walker(sel, lt, z, wl);
+    const int r = pick_walker(sel, lt, z, wl);    // uniform in the block
     if (r == 0) break;
-    if (r == 1) rows_one<Tf>(lt, bf, L, C, wl, sp, e);
+    if (r == 1) rows_one<Tf, KS>(lt, bf, L, C, wl, sp);
   }
 }
 
@@ -354,81 +395,84 @@ __global__ __launch_bounds__(256) void k_gj_big(LatDev lt, Bufs bf, WalkerSel se
   }
 }
 
-// G_s = M_s Phi_s^-1 (rows 0..N-1) and P_s^T = (W_s Phi_s^-1)^T (rows N..N+C-1
-// of the stacked left factor).  64x64 output tiles, 4x4 per thread, K chunks
-// of 16 through LDS.  grid.x = tile + ntiles * (sp + 2 * walker slot).
-struct GpShared {
-  double As[16][64 + 1];
-  double Bs[16][64 + 1];
-};
-SVMC_DEV void gp_one(const LatDev& lt, const Bufs& bf, int C, int tiles_c, long long wl, int sp, int tile,
-                     GpShared& sg) {
+// G_s = M_s Y_s (rows 0..N-1 of the stacked left factor [M_s; W_s]) and
+// P_s^T = (W_s Y_s)^T (rows N..N+C-1), Y_s = Phi_s^-1, on the FP64 matrix
+// cores: one workgroup of four wavefronts per (walker, spin); a wavefront
+// task is a 32 x 32 output block (two row tiles by two column tiles, four
+// 16 x 16 x 4 accumulators), its operands read from global memory (L2) with
+// GP_U k-steps in flight.  Columns m >= n_s are not written.
+constexpr int GP_U = 4;
+SVMC_DEV void gp_one(const LatDev& lt, const Bufs& bf, int C, long long wl, int sp) {
   const int N = lt.N, nm = lt.nmax;
   const int n = lt.n[sp];
   if (n == 0) return;
-  const int R0 = (tile / tiles_c) * 64, C0 = (tile % tiles_c) * 64;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lj = lane & 15, lk = lane >> 4;
   const int rows = N + C;
   const double* M = bf.M + lt.m_off + wl * 2LL * N * nm + (long long)sp * N * nm;
   const double* W = lt.W + (long long)sp * C * nm;
   const double* Y = bf.inv + lt.inv_off + wl * 2LL * nm * nm + (long long)sp * nm * nm;
-  double (*As)[64 + 1] = sg.As;
-  double (*Bs)[64 + 1] = sg.Bs;
-  const int tid = threadIdx.x, tr = tid / 16, tc = tid % 16;
-  double acc[4][4] = {};
-  for (int k0 = 0; k0 < n; k0 += 16) {
-    for (int e = tid; e < 16 * 64; e += 256) {
-      const int kk = e / 64, rr = e % 64;
-      const int r = R0 + rr, k = k0 + kk;
-      double v = 0.0;
-      if (r < rows && k < n) v = r < N ? M[(long long)r * nm + k] : W[(long long)(r - N) * nm + k];
-      As[kk][rr] = v;
-      const int c = C0 + rr;
-      Bs[kk][rr] = (k < n && c < n) ? Y[(long long)k * nm + c] : 0.0;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int kk = 0; kk < 16; ++kk) {
-      double a[4], b[4];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) a[i] = As[kk][tr + 16 * i];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) b[j] = Bs[kk][tc + 16 * j];
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = fma(a[i], b[j], acc[i][j]);
-    }
-    __syncthreads();
-  }
   double* G = bf.G + lt.g_off + wl * 2LL * N * nm + (long long)sp * N * nm;
   double* PT = bf.PT + lt.pt_off + wl * 2LL * nm * C + (long long)sp * nm * C;
+  const int nbr = (rows + 31) / 32, nbc = (n + 31) / 32, ksteps = (n + 3) / 4;
+  for (int task = wave; task < nbr * nbc; task += 4) {
+    const int r0 = 32 * (task / nbc), c0 = 32 * (task % nbc);
+    // this lane's A rows (one per row tile) and B columns (one per column tile)
+    const double* arow[2];
+    bool aok[2], bok[2];
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int r = R0 + tr + 16 * i;
-    if (r >= rows) continue;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int c = C0 + tc + 16 * j;
-      if (c >= n) continue;
-      if (r < N) G[(long long)r * nm + c] = acc[i][j];
-      else PT[(long long)c * C + (r - N)] = acc[i][j];
+    for (int u = 0; u < 2; ++u) {
+      const int r = r0 + 16 * u + lj;
+      aok[u] = r < rows;
+      arow[u] = r < N ? M + (long long)r * nm : W + (long long)(aok[u] ? r - N : 0) * nm;
+      bok[u] = c0 + 16 * u + lj < n;
     }
+    v4d acc[2][2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+      for (int t = 0; t < 2; ++t) acc[u][t] = v4d{0.0, 0.0, 0.0, 0.0};
+    for (int q0 = 0; q0 < ksteps; q0 += GP_U) {
+      double a[GP_U][2], b[GP_U][2];
+#pragma unroll
+      for (int uq = 0; uq < GP_U; ++uq) {
+        const int k = 4 * (q0 + uq) + lk;
+        const bool kok = k < n;
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+          a[uq][u] = (kok && aok[u]) ? arow[u][k] : 0.0;
+          b[uq][u] = (kok && bok[u]) ? Y[(long long)k * nm + c0 + 16 * u + lj] : 0.0;
+        }
+      }
+#pragma unroll
+      for (int uq = 0; uq < GP_U; ++uq)
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+#pragma unroll
+          for (int t = 0; t < 2; ++t) mfma(acc[u][t], a[uq][u], b[uq][t]);
+    }
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        const int c = c0 + 16 * t + lj;
+        if (c >= n) continue;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int r = r0 + 16 * u + lk + 4 * v;
+          if (r < N) G[(long long)r * nm + c] = acc[u][t][v];
+          else if (r < rows) PT[(long long)c * C + (r - N)] = acc[u][t][v];
+        }
+      }
   }
 }
-__global__ __launch_bounds__(256) void k_gp(LatDev lt, Bufs bf, int C, int tiles_r, int tiles_c, WalkerSel sel,
-                                            long long slots) {
-  __shared__ GpShared sg;
-  long long bid = blockIdx.x;
-  const int ntiles = tiles_r * tiles_c;
-  const int tile = (int)(bid % ntiles);
-  bid /= ntiles;
-  const int sp = (int)(bid % 2);
-  for (long long z = bid / 2;; z += slots) {
+__global__ __launch_bounds__(256) void k_gp(LatDev lt, Bufs bf, int C, WalkerSel sel) {
+  const int sp = blockIdx.y;
+  for (long long z = blockIdx.x;; z += gridDim.x) {
     long long wl;
     const int r = pick_walker(sel, lt, z, wl);    // uniform in the block
     if (r == 0) break;
-    if (r == 1) gp_one(lt, bf, C, tiles_c, wl, sp, tile, sg);
-    __syncthreads();
+    if (r == 1) gp_one(lt, bf, C, wl, sp);
   }
 }
 
@@ -479,11 +523,16 @@ static long long walker_slots(const LatDev& lt, const WalkerSel& sel, int list_s
 
 hipError_t launch_rows(int prec, const LatDev& lt, const Bufs& bf, int L, int C, hipStream_t st, WalkerSel sel) {
   if (lt.nw == 0) return hipSuccess;
-  const dim3 grid((unsigned)((lt.N * lt.nmax + 255) / 256), 2, (unsigned)walker_slots(lt, sel, 64));
-  if (prec == PREC_F64)
-    hipLaunchKernelGGL(k_rows<double>, grid, dim3(256), 0, st, lt, bf, L, C, sel);
-  else
-    hipLaunchKernelGGL(k_rows<float>, grid, dim3(256), 0, st, lt, bf, L, C, sel);
+  const dim3 grid((unsigned)walker_slots(lt, sel, 256), 2);
+  auto go = [&](auto kf) { hipLaunchKernelGGL(kf, grid, dim3(256), 0, st, lt, bf, L, C, sel); };
+  const bool f64 = prec == PREC_F64;
+  switch (C) {
+    case 8: f64 ? go(k_rows<double, 2>) : go(k_rows<float, 2>); break;
+    case 16: f64 ? go(k_rows<double, 4>) : go(k_rows<float, 4>); break;
+    case 24: f64 ? go(k_rows<double, 6>) : go(k_rows<float, 6>); break;
+    case 32: f64 ? go(k_rows<double, 8>) : go(k_rows<float, 8>); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
@@ -501,10 +550,8 @@ hipError_t launch_gj(const LatDev& lt, const Bufs& bf, hipStream_t st, WalkerSel
 
 hipError_t launch_gp(const LatDev& lt, const Bufs& bf, int C, hipStream_t st, WalkerSel sel) {
   if (lt.nw == 0) return hipSuccess;
-  const int tr = (lt.N + C + 63) / 64, tc = (lt.nmax + 63) / 64;
-  const long long slots = walker_slots(lt, sel, 64);
-  const long long nblk = (long long)tr * tc * 2 * slots;
-  hipLaunchKernelGGL(k_gp, dim3((unsigned)nblk), dim3(256), 0, st, lt, bf, C, tr, tc, sel, slots);
+  const dim3 grid((unsigned)walker_slots(lt, sel, 256), 2);
+  hipLaunchKernelGGL(k_gp, grid, dim3(256), 0, st, lt, bf, C, sel);
   return hipGetLastError();
 }
 
