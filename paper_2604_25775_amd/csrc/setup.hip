@@ -399,9 +399,8 @@ __global__ __launch_bounds__(256) void k_gj_big(LatDev lt, Bufs bf, WalkerSel se
 // P_s^T = (W_s Y_s)^T (rows N..N+C-1), Y_s = Phi_s^-1, on the FP64 matrix
 // cores: one workgroup of four wavefronts per (walker, spin); a wavefront
 // task is a 32 x 32 output block (two row tiles by two column tiles, four
-// 16 x 16 x 4 accumulators), its operands read from global memory (L2) with
-// GP_U k-steps in flight.  Columns m >= n_s are not written.
-constexpr int GP_U = 4;
+// 16 x 16 x 4 accumulators), its operands read from global memory (L2), four
+// k-steps at a time.  Columns m >= n_s are not written.
 SVMC_DEV void gp_one(const LatDev& lt, const Bufs& bf, int C, long long wl, int sp) {
   const int N = lt.N, nm = lt.nmax;
   const int n = lt.n[sp];
@@ -414,7 +413,8 @@ SVMC_DEV void gp_one(const LatDev& lt, const Bufs& bf, int C, long long wl, int 
   const double* Y = bf.inv + lt.inv_off + wl * 2LL * nm * nm + (long long)sp * nm * nm;
   double* G = bf.G + lt.g_off + wl * 2LL * N * nm + (long long)sp * N * nm;
   double* PT = bf.PT + lt.pt_off + wl * 2LL * nm * C + (long long)sp * nm * C;
-  const int nbr = (rows + 31) / 32, nbc = (n + 31) / 32, ksteps = (n + 3) / 4;
+  const int nbr = (rows + 31) / 32, nbc = (n + 31) / 32;
+  const bool vec = (nm & 1) == 0;          // rows of M and W start 16-byte aligned
   for (int task = wave; task < nbr * nbc; task += 4) {
     const int r0 = 32 * (task / nbc), c0 = 32 * (task % nbc);
     // this lane's A rows (one per row tile) and B columns (one per column tile)
@@ -432,24 +432,34 @@ SVMC_DEV void gp_one(const LatDev& lt, const Bufs& bf, int C, long long wl, int 
     for (int u = 0; u < 2; ++u)
 #pragma unroll
       for (int t = 0; t < 2; ++t) acc[u][t] = v4d{0.0, 0.0, 0.0, 0.0};
-    for (int q0 = 0; q0 < ksteps; q0 += GP_U) {
-      double a[GP_U][2], b[GP_U][2];
+    // k runs in blocks of 16; within a block lane group lk takes k = 4 lk + e
+    // in product e (any order of k is the same sum as long as A and B agree),
+    // so each lane reads four consecutive elements of its A row at once
+    for (int k0 = 0; k0 < n; k0 += 16) {
+      double a[2][4], b[4][2];
+      const int ka = k0 + 4 * lk;
 #pragma unroll
-      for (int uq = 0; uq < GP_U; ++uq) {
-        const int k = 4 * (q0 + uq) + lk;
-        const bool kok = k < n;
+      for (int u = 0; u < 2; ++u) {
+        if (vec && aok[u] && ka + 3 < n) {
+          const double2 x0 = *reinterpret_cast<const double2*>(arow[u] + ka);
+          const double2 x1 = *reinterpret_cast<const double2*>(arow[u] + ka + 2);
+          a[u][0] = x0.x; a[u][1] = x0.y; a[u][2] = x1.x; a[u][3] = x1.y;
+        } else {
 #pragma unroll
-        for (int u = 0; u < 2; ++u) {
-          a[uq][u] = (kok && aok[u]) ? arow[u][k] : 0.0;
-          b[uq][u] = (kok && bok[u]) ? Y[(long long)k * nm + c0 + 16 * u + lj] : 0.0;
+          for (int e = 0; e < 4; ++e) a[u][e] = (aok[u] && ka + e < n) ? arow[u][ka + e] : 0.0;
         }
       }
 #pragma unroll
-      for (int uq = 0; uq < GP_U; ++uq)
+      for (int e = 0; e < 4; ++e)
+#pragma unroll
+        for (int t = 0; t < 2; ++t)
+          b[e][t] = (ka + e < n && bok[t]) ? Y[(long long)(ka + e) * nm + c0 + 16 * t + lj] : 0.0;
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
 #pragma unroll
         for (int u = 0; u < 2; ++u)
 #pragma unroll
-          for (int t = 0; t < 2; ++t) mfma(acc[u][t], a[uq][u], b[uq][t]);
+          for (int t = 0; t < 2; ++t) mfma(acc[u][t], a[u][e], b[e][t]);
     }
 #pragma unroll
     for (int u = 0; u < 2; ++u)
