@@ -154,21 +154,46 @@ SVMC_DEV void rows_one(const LatDev& lt, const Bufs& bf, int L, int C, long long
   const double* bb = lt.b + sp * nm;
   const int ntr = (N + 15) / 16, ntc = (nm + 15) / 16;
   for (int tc0 = 0; tc0 < ntc; tc0 += RC_CT) {
+    // with C a multiple of 16, product q covers k = 16 (q / 4) + 4 lk + q % 4
+    // in lane group lk (the same sum in another order), so a lane's four A
+    // values of a block are consecutive in H and load as one vector
+    constexpr bool BLK = KS % 4 == 0;
+    auto kidx = [&](int q) { return BLK ? 16 * (q >> 2) + 4 * lk + (q & 3) : 4 * q + lk; };
     double bw[RC_CT][KS];
 #pragma unroll
     for (int ct = 0; ct < RC_CT; ++ct)
 #pragma unroll
       for (int q = 0; q < KS; ++q) {
-        const int col = 16 * (tc0 + ct) + lj, k = 4 * q + lk;
+        const int col = 16 * (tc0 + ct) + lj, k = kidx(q);
         bw[ct][q] = (col < n && k < C) ? W[(long long)k * nm + col] : 0.0;
       }
     for (int ti = wave; ti < ntr; ti += 4) {
       double av[KS];
       const int row = 16 * ti + lj;
+      if constexpr (BLK) {
 #pragma unroll
-      for (int q = 0; q < KS; ++q) {
-        const int k = 4 * q + lk;
-        av[q] = (row < N && k < C) ? (double)H[(long long)row * C + k] : 0.0;
+        for (int q4 = 0; q4 < KS / 4; ++q4) {
+          Tf x[4] = {Tf(0), Tf(0), Tf(0), Tf(0)};
+          if (row < N) {
+            const Tf* hp = H + (long long)row * C + 16 * q4 + 4 * lk;
+            if constexpr (sizeof(Tf) == 4) {
+              const float4 v = *reinterpret_cast<const float4*>(hp);
+              x[0] = v.x; x[1] = v.y; x[2] = v.z; x[3] = v.w;
+            } else {
+              const double2 v0 = *reinterpret_cast<const double2*>(hp);
+              const double2 v1 = *reinterpret_cast<const double2*>(hp + 2);
+              x[0] = v0.x; x[1] = v0.y; x[2] = v1.x; x[3] = v1.y;
+            }
+          }
+#pragma unroll
+          for (int e = 0; e < 4; ++e) av[4 * q4 + e] = (double)x[e];
+        }
+      } else {
+#pragma unroll
+        for (int q = 0; q < KS; ++q) {
+          const int k = kidx(q);
+          av[q] = (row < N && k < C) ? (double)H[(long long)row * C + k] : 0.0;
+        }
       }
 #pragma unroll
       for (int ct = 0; ct < RC_CT; ++ct) {
