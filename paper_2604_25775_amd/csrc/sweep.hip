@@ -39,9 +39,14 @@ constexpr int SW_REBUILD = 0x7fffffff;
 constexpr int UPD_SC = 64;      // sites per chunk of the G update
 
 __host__ __device__ inline int al16(int x) { return (x + 15) & ~15; }
-// rows of the layer-L update box at most
-__host__ __device__ inline int box_kmax(int Gx, int Gy, int L) {
-  return (Gx < 2 * L + 2 ? Gx : 2 * L + 2) * (Gy < 2 * L + 2 ? Gy : 2 * L + 2);
+// sites of the layer-L update box at most: (2L + 2) along the hop and
+// (2L + 1) across it for nearest-neighbour hops only (nd = 4), (2L + 2)
+// along both axes with diagonal hops (nd = 8); each axis capped by the grid
+__host__ __device__ inline int box_kmax(int Gx, int Gy, int L, int nd) {
+  const int ax = Gx < 2 * L + 2 ? Gx : 2 * L + 2, ay = Gy < 2 * L + 2 ? Gy : 2 * L + 2;
+  const int bx = Gx < 2 * L + 1 ? Gx : 2 * L + 1, by = Gy < 2 * L + 1 ? Gy : 2 * L + 1;
+  if (nd == 8) return ax * ay;
+  return ax * by > bx * ay ? ax * by : bx * ay;
 }
 
 // Staging record of one walker's accepted move (global memory, byte offsets):
@@ -54,8 +59,8 @@ __host__ __device__ inline int box_kmax(int Gx, int Gy, int L) {
 struct StepStage {
   int hdr, kl, D, ainv, gj, bytes;
 };
-__host__ __device__ inline StepStage step_stage(int nmax, int Gx, int Gy, int L, int C, int dtb) {
-  const int km = box_kmax(Gx, Gy, L), ra = C + 1;
+__host__ __device__ inline StepStage step_stage(int nmax, int Gx, int Gy, int L, int nd, int C, int dtb) {
+  const int km = box_kmax(Gx, Gy, L, nd), ra = C + 1;
   StepStage o;
   o.hdr = 0;
   o.kl = 64;
@@ -161,7 +166,7 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(3))) void k
   const long long wl = w - lt.w0;
   const int N = lt.N, nm = lt.nmax;
   const int tid = threadIdx.x, lane = tid & 63, wv = uniform_i(tid >> 6);
-  const StepStage sl = step_stage(nm, lt.Gx, lt.Gy, md.L, C, (int)sizeof(DT));
+  const StepStage sl = step_stage(nm, lt.Gx, lt.Gy, md.L, lt.nd, C, (int)sizeof(DT));
   char* st = sa.stage + w * sa.stage_stride;
   int* hdr = (int*)(st + sl.hdr);
   // electron counts as scalars: indexing the local descriptor copy with a
@@ -239,7 +244,7 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(3))) void k
 
   // ---- accepted.  Wavefront tau: A^-1 of spin tau from the staged A (still
   // in LDS: the LU worked on registers), its changed-row list and G[j].
-  const int kmaxb = box_kmax(lt.Gx, lt.Gy, md.L);
+  const int kmaxb = box_kmax(lt.Gx, lt.Gy, md.L, lt.nd);
   const int ntau = wv == 0 ? n_up : n_dn;
   bool ok = true;
   if (ntau > 0) {
@@ -365,8 +370,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     const int N = lt.N, nm = lt.nmax;
     const int n = tau == 0 ? lt.n[0] : lt.n[1];
     if (n == 0) continue;                                             // uniform
-    const int kmaxb = box_kmax(lt.Gx, lt.Gy, L);
-    const StepStage sl = step_stage(nm, lt.Gx, lt.Gy, L, C, (int)sizeof(DT));
+    const int kmaxb = box_kmax(lt.Gx, lt.Gy, L, lt.nd);
+    const StepStage sl = step_stage(nm, lt.Gx, lt.Gy, L, lt.nd, C, (int)sizeof(DT));
     const char* st = sa.stage + w * sa.stage_stride;
     const int* hdr = (const int*)(st + sl.hdr);
     const int sp = hdr[HD_SP], kmv = hdr[HD_K], olx = hdr[HD_OLX], owx = hdr[HD_OWX], oly = hdr[HD_OLY],
@@ -597,8 +602,8 @@ StepSizes step_sizes(const LatDev* lats, int nlats, int prec, int L, int C) {
   for (int l = 0; l < nlats; ++l) {
     const LatDev& lt = lats[l];
     z.smem_propose = std::max(z.smem_propose, (size_t)propose_layout(lt.N, lt.Gx, lt.Gy, L, C, tfb).bytes);
-    z.smem_update = std::max(z.smem_update, (size_t)update_lds_bytes(box_kmax(lt.Gx, lt.Gy, L), C));
-    z.stage_bytes = std::max(z.stage_bytes, (size_t)step_stage(lt.nmax, lt.Gx, lt.Gy, L, C, tfb).bytes);
+    z.smem_update = std::max(z.smem_update, (size_t)update_lds_bytes(box_kmax(lt.Gx, lt.Gy, L, lt.nd), C));
+    z.stage_bytes = std::max(z.stage_bytes, (size_t)step_stage(lt.nmax, lt.Gx, lt.Gy, L, lt.nd, C, tfb).bytes);
   }
   return z;
 }
