@@ -88,9 +88,9 @@ __host__ __device__ inline ProposeLds propose_layout(int N, int Gx, int Gy, int 
 }
 // LDS of the update kernel: A^-1, B = U A^-1, the changed-row list, E rows of
 // a chunk of sites.
-__host__ __device__ inline int update_lds_bytes(int kmax, int C) {
+__host__ __device__ inline int update_lds_bytes(int kmax, int C, int dtb) {
   const int ra = C + 1;
-  return al16(ra * ra * 8) + al16(kmax * ra * 8) + al16(kmax * 4) + UPD_SC * (4 * ((ra + 3) / 4)) * 8;
+  return al16(ra * ra * 8) + al16(kmax * 4) + al16(kmax * C * dtb) + UPD_SC * (4 * ((ra + 3) / 4)) * 8;
 }
 
 // Dense index of site s in the layer-L update box (origin (olx, oly), size
@@ -349,7 +349,7 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(3))) void k
 // (walker, spin), items dealt to a persistent grid.  Block 0 clears the
 // counter of the next step.
 template <int P, int C>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_step_update(int L, const LatDev* __restrict__ lats, int nlats, Bufs bf,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_step_update(int L, const LatDev* __restrict__ lats, int nlats, Bufs bf,
                                                      StepArgs sa) {
   typedef typename DType<P>::type DT;
   constexpr int NTH = 256, RA = C + 1, SC = UPD_SC, SD = DStride<C>::value;
@@ -385,77 +385,105 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     double* Gt = bf.G + lt.g_off + wl * 2LL * N * nm + (long long)tau * N * nm;
     double* PTt = bf.PT + lt.pt_off + wl * 2LL * nm * C + (long long)tau * nm * C;
     double* ainv = (double*)smem;
-    double* bm = (double*)(smem + al16(RA * RA * 8));
-    int* kls = (int*)(smem + al16(RA * RA * 8) + al16(kmaxb * RA * 8));
-    double* ec = (double*)(smem + al16(RA * RA * 8) + al16(kmaxb * RA * 8) + al16(kmaxb * 4));
+    int* kls = (int*)(smem + al16(RA * RA * 8));
+    DT* dk = (DT*)(smem + al16(RA * RA * 8) + al16(kmaxb * 4));          // D(m_a), row a
+    double* ec = (double*)(smem + al16(RA * RA * 8) + al16(kmaxb * 4) + al16(kmaxb * C * (int)sizeof(DT)));
     for (int e2 = tid; e2 < RA * RA; e2 += NTH) ainv[e2] = aig[e2];
     for (int a = tid; a < r; a += NTH) kls[a] = klg[a];
     __syncthreads();
-    // B = U A^-1: B[a][c2] = D(m_a) . A^-1[0:C, c2] + [moving spin, a = hpos] A^-1[C][c2]
-    for (int e2 = tid; e2 < r * RA; e2 += NTH) {
-      const int a = e2 / RA, c2 = e2 - a * RA;
-      const DT* Da = Dg + (kls[a] >> 16) * SD;
-      DT dr[C];                      // the whole row requested before use
-#pragma unroll
-      for (int c = 0; c < C; ++c) dr[c] = Da[c];
-      double v = (hs && a == hpos) ? ainv[C * RA + c2] : 0.0;
-#pragma unroll
-      for (int c = 0; c < C; ++c) v = fma((double)dr[c], ainv[c * RA + c2], v);
-      bm[e2] = v;
+    for (int e2 = tid; e2 < r * C; e2 += NTH) {
+      const int a = e2 / C, c = e2 - a * C;
+      dk[e2] = Dg[(kls[a] >> 16) * SD + c];
     }
     __syncthreads();
-    // G'[s][k'] = G[s][k'] + E[s] . W[:, k'] in chunks of SC sites.  E of a
-    // chunk is one product on the FP64 matrix cores,
-    //   E = [D(s) on the box | -G[s, K]] [A^-1[0:C, :]; B]   (K dim C + r),
-    // wavefront t forming the rows of sites 16 t .. 16 t + 15.
+    // G'[s][k'] = G[s][k'] + E[s] . W[:, k'] in chunks of SC sites, with
+    //   E[s] = D(s) A^-1[0:C, :] - G[s, K] B,  B = U A^-1,
+    // U[a] = [D(m_a), 1 if a is the mover's row of the moving spin].  Taken
+    // as E[s] = [Et(s) | -g(s)] A^-1 with Et(s) = D(s) - sum_a G[s, k_a] D(m_a)
+    // and g(s) = G[s, k_mover] (moving spin): two products on the FP64
+    // matrix cores per chunk, wavefront t forming the rows of sites
+    // 16 t .. 16 t + 15 (D(s) is zero off the box).
     const int wave = tid >> 6, lane = tid & 63, lj = lane & 15, lk = lane >> 4;
-    const int ke = (C + r + 3) / 4;                 // k-steps of the E product
+    constexpr int CT = (C + 15) / 16;               // column tiles of Et
+    const int ke1 = (r + 3) / 4;                    // k-steps of the first product
+    const int kmov = hs ? kls[hpos] & 0xffff : 0;
     for (int s0 = 0; s0 < N; s0 += SC) {
       const int ns = min(SC, N - s0);
+      double* ew = ec + 16 * wave * ECS;            // this wavefront's 16 rows
       if (16 * wave < ns) {
         const int si = 16 * wave + lj;              // this lane's A row (site)
         const bool sok = si < ns;
-        const int s = s0 + si;
-        const int mb = sok ? box_index(lt, s, olx, owx, oly, owy) : -1;
-        const DT* Dm = Dg + (mb >= 0 ? mb : 0) * SD;
-        const double* Gs = Gt + (long long)(sok ? s : 0) * nm;
+        const double* Gs = Gt + (long long)(s0 + (sok ? si : 0)) * nm;
+        // Et: accumulator starts at D(s) of the result rows (lk + 4 v)
+        v4d acc1[CT];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int so = 16 * wave + lk + 4 * v;
+          const int mb = so < ns ? box_index(lt, s0 + so, olx, owx, oly, owy) : -1;
+#pragma unroll
+          for (int tj = 0; tj < CT; ++tj) {
+            const int col = 16 * tj + lj;
+            acc1[tj][v] = (mb >= 0 && col < C) ? (double)Dg[mb * SD + col] : 0.0;
+          }
+        }
+        for (int q0 = 0; q0 < ke1; q0 += 4) {
+          double av[4], bv[4][CT];                  // four k-steps in flight
+#pragma unroll
+          for (int u2 = 0; u2 < 4; ++u2) {
+            const int a = 4 * (q0 + u2) + lk;
+            const bool ok = a < r;
+            const int e = ok ? kls[a] : 0;
+            av[u2] = (ok && sok) ? -Gs[e & 0xffff] : 0.0;
+#pragma unroll
+            for (int tj = 0; tj < CT; ++tj) {
+              const int col = 16 * tj + lj;
+              bv[u2][tj] = (ok && col < C) ? (double)dk[a * C + col] : 0.0;
+            }
+          }
+#pragma unroll
+          for (int u2 = 0; u2 < 4; ++u2) {
+            if (q0 + u2 >= ke1) break;
+#pragma unroll
+            for (int tj = 0; tj < CT; ++tj) mfma(acc1[tj], av[u2], bv[u2][tj]);
+          }
+        }
+        // [Et | -g | 0] to this wavefront's rows, then read back as A rows
+#pragma unroll
+        for (int tj = 0; tj < CT; ++tj) {
+          const int col = 16 * tj + lj;
+          if (col >= C) continue;
+#pragma unroll
+          for (int v = 0; v < 4; ++v) ew[(lk + 4 * v) * ECS + col] = acc1[tj][v];
+        }
+        if (lk == 0)
+          for (int c = C; c < ECS; ++c) ew[lj * ECS + c] = (c == C && hs && sok) ? -Gs[kmov] : 0.0;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         v4d eacc[3];
 #pragma unroll
         for (int tj = 0; tj < 3; ++tj) eacc[tj] = v4d{0.0, 0.0, 0.0, 0.0};
-        for (int q0 = 0; q0 < ke; q0 += 4) {
-          double av[4];                             // four A operands in flight
 #pragma unroll
-          for (int u2 = 0; u2 < 4; ++u2) {
-            const int kk = 4 * (q0 + u2) + lk;
-            double v = 0.0;
-            if (kk < C) {
-              if (mb >= 0) v = (double)Dm[kk];
-            } else if (sok && kk - C < r) {
-              v = -Gs[kls[kk - C] & 0xffff];
-            }
-            av[u2] = v;
-          }
+        for (int q = 0; q < KS; ++q) {
+          const int c2 = 4 * q + lk;
+          const double a2 = ew[lj * ECS + c2];
 #pragma unroll
-          for (int u2 = 0; u2 < 4; ++u2) {
-            if (q0 + u2 >= ke) break;
-            const int kk = 4 * (q0 + u2) + lk;
-            const double* brow = kk < C ? ainv + kk * RA : bm + (kk - C) * RA;
-            const bool kok = kk < C + r;
-#pragma unroll
-            for (int tj = 0; tj < 3; ++tj) {
-              const int col = 16 * tj + lj;
-              const double bv = (kok && col < RA) ? brow[col] : 0.0;
-              mfma(eacc[tj], av[u2], bv);
-            }
+          for (int tj = 0; tj < 3; ++tj) {
+            const int col = 16 * tj + lj;
+            const double b2 = (c2 < RA && col < RA) ? ainv[c2 * RA + col] : 0.0;
+            mfma(eacc[tj], a2, b2);
           }
         }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         // E rows to LDS (columns C + 1 .. ECS - 1 are zero)
 #pragma unroll
         for (int tj = 0; tj < 3; ++tj) {
           const int col = 16 * tj + lj;
           if (col >= ECS) continue;
 #pragma unroll
-          for (int v = 0; v < 4; ++v) ec[(16 * wave + lk + 4 * v) * ECS + col] = eacc[tj][v];
+          for (int v = 0; v < 4; ++v) ew[(lk + 4 * v) * ECS + col] = eacc[tj][v];
         }
       }
       __syncthreads();
@@ -496,18 +524,42 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
       }
       __syncthreads();
     }
-    // P^T'[k'] = A^-1[0:C, :] W[:, k'] (W from the old P^T and G[j])
-    for (int kc = tid; kc < n; kc += NTH) {
-      double wcol[RA];
+    // P^T'[k'][cp] = sum_c2 W[c2][k'] A^-1[cp][c2] (W from the old P^T and
+    // G[j]) on the FP64 matrix cores, in place: a wavefront reads all of its
+    // 16 rows of P^T before it writes them, and no other wavefront touches them
+    for (int ti = wave; 16 * ti < n; ti += NTH / 64) {
+      const int kr = 16 * ti + lj;
+      double av[KS];
 #pragma unroll
-      for (int c = 0; c < C; ++c) wcol[c] = PTt[(long long)kc * C + c];
-      wcol[C] = hs ? gjs[kc] - (kc == kmv ? 1.0 : 0.0) : 0.0;
-#pragma unroll 2
-      for (int cp = 0; cp < C; ++cp) {
+      for (int q = 0; q < KS; ++q) {
+        const int c2 = 4 * q + lk;
         double v = 0.0;
+        if (kr < n) {
+          if (c2 < C) v = PTt[(long long)kr * C + c2];
+          else if (c2 == C && hs) v = gjs[kr] - (kr == kmv ? 1.0 : 0.0);
+        }
+        av[q] = v;
+      }
+      v4d pacc[CT];
 #pragma unroll
-        for (int c = 0; c < RA; ++c) v = fma(ainv[cp * RA + c], wcol[c], v);
-        PTt[(long long)kc * C + cp] = v;
+      for (int tj = 0; tj < CT; ++tj) {
+        pacc[tj] = v4d{0.0, 0.0, 0.0, 0.0};
+        const int col = 16 * tj + lj;
+#pragma unroll
+        for (int q = 0; q < KS; ++q) {
+          const int c2 = 4 * q + lk;
+          const double b2 = (c2 < RA && col < C) ? ainv[col * RA + c2] : 0.0;
+          mfma(pacc[tj], av[q], b2);
+        }
+      }
+#pragma unroll
+      for (int tj = 0; tj < CT; ++tj) {
+        const int col = 16 * tj + lj;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int ko = 16 * ti + lk + 4 * v;
+          if (ko < n && col < C) PTt[(long long)ko * C + col] = pacc[tj][v];
+        }
       }
     }
     __syncthreads();
@@ -602,7 +654,7 @@ StepSizes step_sizes(const LatDev* lats, int nlats, int prec, int L, int C) {
   for (int l = 0; l < nlats; ++l) {
     const LatDev& lt = lats[l];
     z.smem_propose = std::max(z.smem_propose, (size_t)propose_layout(lt.N, lt.Gx, lt.Gy, L, C, tfb).bytes);
-    z.smem_update = std::max(z.smem_update, (size_t)update_lds_bytes(box_kmax(lt.Gx, lt.Gy, L, lt.nd), C));
+    z.smem_update = std::max(z.smem_update, (size_t)update_lds_bytes(box_kmax(lt.Gx, lt.Gy, L, lt.nd), C, tfb));
     z.stage_bytes = std::max(z.stage_bytes, (size_t)step_stage(lt.nmax, lt.Gx, lt.Gy, L, lt.nd, C, tfb).bytes);
   }
   return z;
