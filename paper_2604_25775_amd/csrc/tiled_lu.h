@@ -15,25 +15,31 @@
 namespace svmc {
 
 template <int R> struct GjShared {
-  double colbuf[16 * R];
-  double rowbuf[16 * R];
-  int used[16 * R];
+  double colbuf[2][16 * R];      // pivot column, by step parity
+  double rowbuf[2][16 * R];      // pivot row, by step parity
+  double pvs[16 * R];            // pivot of each step
   int perm[16 * R];
   int perminv[16 * R];
-  int piv;
+  int piv[2];
   int inv;
+  double red[4];
 };
 
+// Two barriers per step: the pivot column and row buffers alternate between
+// steps, so a step's writes never meet the previous step's reads, and each
+// thread keeps the used flags of its own rows in registers.  log|det| and
+// the sign are formed from the stored pivots after the loop.
 template <int R, bool INVERT>
 SVMC_DEV void tiled_gj(double (&x)[R][R], int n, GjShared<R>& sh, double& logabs, double& sgn, bool& singular) {
   const int tid = threadIdx.x, tx = tid >> 4, ty = tid & 15;
-  for (int k = tid; k < 16 * R; k += 256) sh.used[k] = k >= n;
-  __syncthreads();
+  bool used[R];
+#pragma unroll
+  for (int a = 0; a < R; ++a) used[a] = ty + 16 * a >= n;
   logabs = 0.0;
   sgn = 1.0;
   singular = false;
   for (int p = 0; p < n; ++p) {
-    const int bp = p >> 4;
+    const int bp = p >> 4, buf = p & 1;
     if (tx == (p & 15)) {
       double col[R];
 #pragma unroll
@@ -49,8 +55,8 @@ SVMC_DEV void tiled_gj(double (&x)[R][R], int n, GjShared<R>& sh, double& logabs
 #pragma unroll
       for (int a = 0; a < R; ++a) {
         const int k = ty + 16 * a;
-        sh.colbuf[k] = col[a];
-        if (k < n && !sh.used[k]) {
+        sh.colbuf[buf][k] = col[a];
+        if (k < n && !used[a]) {
           const double v = fabs(col[a]);
           if (v > best) { best = v; bi = k; }
         }
@@ -60,55 +66,64 @@ SVMC_DEV void tiled_gj(double (&x)[R][R], int n, GjShared<R>& sh, double& logabs
         const int i2 = __shfl_xor(bi, o, 64);
         if (b2 > best || (b2 == best && i2 < bi)) { best = b2; bi = i2; }
       }
-      if (ty == 0) sh.piv = bi;
+      if (ty == 0) sh.piv[buf] = bi;
     }
     __syncthreads();
-    const int pi = sh.piv;
-    const double pv = pi < n ? sh.colbuf[pi] : 0.0;
-    if (pv == 0.0) { singular = true; break; }
+    const int pi = sh.piv[buf];
+    const double pv = pi < n ? sh.colbuf[buf][pi] : 0.0;
+    if (pv == 0.0) { singular = true; break; }              // the same in every thread
     if (ty == (pi & 15)) {
       const int ap = pi >> 4;
 #pragma unroll
       for (int a = 0; a < R; ++a)
         if (a == ap) {
 #pragma unroll
-          for (int b = 0; b < R; ++b) sh.rowbuf[tx + 16 * b] = x[a][b];
+          for (int b = 0; b < R; ++b) sh.rowbuf[buf][tx + 16 * b] = x[a][b];
         }
     }
+    if (tid == 0) { sh.perm[p] = pi; sh.pvs[p] = pv; }
     __syncthreads();
     const double inv = 1.0 / pv;
-    logabs += log(fabs(pv));
-    if (pv < 0) sgn = -sgn;
 #pragma unroll
     for (int a = 0; a < R; ++a) {
       const int k = ty + 16 * a;
-      const double f = sh.colbuf[k] * inv;
+      const double f = sh.colbuf[buf][k] * inv;
       const bool isp = (k == pi);
-      const bool live = !sh.used[k] && !isp;
+      const bool live = !used[a] && !isp;
 #pragma unroll
       for (int b = 0; b < R; ++b) {
         const int m = tx + 16 * b;
         if (INVERT) {
           if (isp) x[a][b] = (m == p) ? inv : x[a][b] * inv;
-          else x[a][b] = (m == p) ? -f : fma(-f, sh.rowbuf[m], x[a][b]);
+          else x[a][b] = (m == p) ? -f : fma(-f, sh.rowbuf[buf][m], x[a][b]);
         } else if (live && m > p) {
-          x[a][b] = fma(-f, sh.rowbuf[m], x[a][b]);
+          x[a][b] = fma(-f, sh.rowbuf[buf][m], x[a][b]);
         }
       }
+      if (isp) used[a] = true;
     }
-    __syncthreads();
-    if (tid == 0) { sh.used[pi] = 1; sh.perm[p] = pi; }
-    __syncthreads();
   }
   if (singular) return;
+  __syncthreads();
   if (tid == 0) sh.inv = 0;
   for (int k = tid; k < n; k += 256) sh.perminv[sh.perm[k]] = k;
+  // log|det| and the number of negative pivots, summed over the block
+  double ls = 0.0;
+  int neg = 0;
+  for (int q = tid; q < n; q += 256) {
+    ls += log(fabs(sh.pvs[q]));
+    neg += sh.pvs[q] < 0.0 ? 1 : 0;
+  }
+  for (int o = 32; o >= 1; o >>= 1) ls += __shfl_xor(ls, o, 64);
+  if ((tid & 63) == 0) sh.red[tid >> 6] = ls;
   __syncthreads();
-  int cnt = 0;
-  for (int p = tid; p < n; p += 256)
-    for (int q = p + 1; q < n; ++q) cnt += sh.perm[q] < sh.perm[p];
+  // permutation inversions plus negative pivots: the sign's parity
+  int cnt = neg;
+  for (int q = tid; q < n; q += 256)
+    for (int q2 = q + 1; q2 < n; ++q2) cnt += sh.perm[q2] < sh.perm[q];
   if (cnt) atomicAdd(&sh.inv, cnt);
   __syncthreads();
+  logabs = sh.red[0] + sh.red[1] + sh.red[2] + sh.red[3];
   if (sh.inv & 1) sgn = -sgn;
 }
 
