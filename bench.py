@@ -250,7 +250,7 @@ def main():
     ap.add_argument("--walkers", type=int, default=None)
     ap.add_argument("--full-walkers", type=int, default=None,
                     help="walkers for the full-recompute timing (default: all)")
-    ap.add_argument("--cpu-sample", type=int, default=192)
+    ap.add_argument("--cpu-sample", type=int, default=288)
     ap.add_argument("--therm", type=int, default=8, help="thermalising sweeps before timing (untimed)")
     ap.add_argument("--no-full", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
