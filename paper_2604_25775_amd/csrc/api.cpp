@@ -685,13 +685,16 @@ svmc_status svmc_grad_logpsi(svmc_ctx* ctx, const double* vjp_w, double* out, hi
   // fresh inverses (rows, Phi^-1) and P = W Phi^-1 of the current walkers
   if (!ctx->dets_fresh && (s = rebuild_dets(ctx, st))) return s;
   if (!ctx->prepared && (s = prepare(ctx, st))) return s;
-  long long ncmax = 0;
-  for (auto& lt : ctx->ld) ncmax = std::max(ncmax, (long long)lt.N * ctx->C);
+  long long ncmax = 0, nsmax = 0;
+  for (auto& lt : ctx->ld) {
+    ncmax = std::max(ncmax, (long long)lt.N * ctx->C);
+    nsmax = std::max(nsmax, (long long)lt.N);
+  }
   const long long W = ctx->Wtot, np = ctx->nparams;
   const bool jac = vjp_w == nullptr;
   // walkers per launch: bounded scratch (rows only in the VJP mode)
   long long chunk = std::min<long long>(W, jac ? 4096 : 1024);
-  const size_t smem = grad_smem(ncmax);
+  const size_t smem = grad_smem(ncmax, nsmax);
   GradArgs ga;
   ga.L = ctx->L;
   ga.C = ctx->C;
@@ -704,6 +707,7 @@ svmc_status svmc_grad_logpsi(svmc_ctx* ctx, const double* vjp_w, double* out, hi
   ga.off_convw = 4LL * ctx->C;
   ga.off_convb = ga.off_convw + 9LL * ctx->L * ctx->C * ctx->C;
   ga.ncmax = ncmax;
+  ga.nsmax = nsmax;
   if ((s = ctx->hip(ctx->g_dH.ensure((size_t)chunk * ncmax * 8), "alloc gradient scratch"))) return s;
   if (!ga.lds && ((s = ctx->hip(ctx->g_hs.ensure((size_t)chunk * ncmax * 8), "alloc gradient scratch")) ||
                   (s = ctx->hip(ctx->g_dzs.ensure((size_t)chunk * ncmax * 8), "alloc gradient scratch"))))

@@ -52,8 +52,10 @@ __global__ __launch_bounds__(256) void k_grad(const LatDev* __restrict__ lats, i
   double* row = ga.rows + (long long)blockIdx.x * ga.nparams;
   extern __shared__ __attribute__((aligned(16))) double glds[];
   double* hp = ga.lds ? glds : ga.hs + (long long)blockIdx.x * ga.ncmax;
-  double* dz = ga.lds ? glds + NC : ga.dzs + (long long)blockIdx.x * ga.ncmax;
+  double* dz = ga.lds ? glds + ga.ncmax : ga.dzs + (long long)blockIdx.x * ga.ncmax;
   double* dH = ga.dH + (long long)blockIdx.x * ga.ncmax;
+  // neighbour of site s at tap t (offset (t % 3 - 1, t / 3 - 1)), -1 off an open edge
+  int16_t* nbt = (int16_t*)(ga.lds ? glds + 2 * ga.ncmax : glds);
   const bool bad = (bf.flags[w] & (1 | 2 | 8)) != 0;
   for (long long p = tid; p < ga.nparams; p += NTH) row[p] = bad ? NAN : 0.0;
   if (bad) return;
@@ -64,6 +66,10 @@ __global__ __launch_bounds__(256) void k_grad(const LatDev* __restrict__ lats, i
   const Tf* HL = feat + (long long)(L - 1) * NC;
   const double* PTw = bf.PT + lt.pt_off + wl * 2LL * nm * C;
   const int n0 = lt.n[0], n1 = lt.n[1];
+  for (int e = tid; e < 9 * N; e += NTH) {
+    const int t = e / N, s = e - t * N;
+    nbt[e] = (int16_t)grad_nbr(lt, s, t % 3 - 1, t / 3 - 1);
+  }
   __syncthreads();
 
   // ---- projection and dH_L
@@ -105,46 +111,87 @@ __global__ __launch_bounds__(256) void k_grad(const LatDev* __restrict__ lats, i
     for (int e = tid; e < NC; e += NTH)
       hp[e] = l >= 2 ? (double)feat[(long long)(l - 2) * NC + e] : ga.E[occ[e / C] * C + e % C];
     __syncthreads();
-    for (int e = tid; e < NC; e += NTH) {
-      const int s = e / C, co = e % C;
-      double z = bl[co];
+    // The three products of the layer on the FP64 matrix cores (16 x 16 x 4
+    // tiles; A[i][k] from lane i + 16 k, B[k][j] from lane j + 16 k, result
+    // row l / 16 + 4 v, column l % 16 in slot v of lane l).  Tiles are dealt
+    // to the wavefronts in the same order in (1) and (3), so the thread that
+    // writes an element of dH is the one that reads it in the next layer.
+    const int wave = tid >> 6, lane = tid & 63, lj = lane & 15, lk = lane >> 4;
+    const int nct = (C + 15) / 16, ntr = (N + 15) / 16, ksc = C / 4;
+    // (1) z = conv(H_{l-1}) + b, dz = dH * act'(z): tiles of 16 sites x 16 outputs
+    for (int tt = wave; tt < ntr * nct; tt += NTH / 64) {
+      const int ti = tt / nct, tj = tt - ti * nct;
+      const int si = 16 * ti + lj, co = 16 * tj + lj;
+      v4d acc = v4d{0.0, 0.0, 0.0, 0.0};
       for (int t = 0; t < 9; ++t) {
-        const int nb = grad_nbr(lt, s, t % 3 - 1, t / 3 - 1);
-        if (nb < 0) continue;
+        const int nb = si < N ? nbt[t * N + si] : -1;
+        const double* hrow = hp + (nb >= 0 ? nb : 0) * C;
         const double* kt = Kl + (long long)t * C * C + co;
-        const double* h = hp + nb * C;
-        for (int ci = 0; ci < C; ++ci) z = fma(kt[ci * C], h[ci], z);
+        for (int q = 0; q < ksc; ++q) {
+          const int ci = 4 * q + lk;
+          const double a = nb >= 0 ? hrow[ci] : 0.0;
+          const double b = co < C ? kt[ci * C] : 0.0;
+          mfma(acc, a, b);
+        }
       }
-      dz[e] = dH[e] * act_deriv(ga.act, z);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int so = 16 * ti + lk + 4 * v;
+        if (so < N && co < C) dz[so * C + co] = dH[so * C + co] * act_deriv(ga.act, acc[v] + bl[co]);
+      }
     }
     __syncthreads();
+    // (2) dK[t][ci][co] = sum_s H_{l-1}[nb(s, t)][ci] dz[s][co]: per tap, tiles of
+    // 16 inputs x 16 outputs, K over the sites
     double* dK = row + ga.off_convw + (long long)(l - 1) * 9 * C * C;
-    for (int e = tid; e < 9 * C * C; e += NTH) {
-      const int t = e / (C * C), ci = (e / C) % C, co = e % C;
-      const int dx = t % 3 - 1, dy = t / 3 - 1;
-      double acc = 0.0;
-      for (int s = 0; s < N; ++s) {
-        const int nb = grad_nbr(lt, s, dx, dy);
-        if (nb >= 0) acc = fma(dz[s * C + co], hp[nb * C + ci], acc);
+    for (int tt = wave; tt < 9 * nct * nct; tt += NTH / 64) {
+      const int t = tt / (nct * nct), r2 = tt - t * nct * nct, tci = r2 / nct, tco = r2 - tci * nct;
+      const int ci = 16 * tci + lj, co = 16 * tco + lj;
+      v4d acc = v4d{0.0, 0.0, 0.0, 0.0};
+      for (int s0 = 0; s0 < N; s0 += 4) {
+        const int sk = s0 + lk;
+        const int nb = sk < N ? nbt[t * N + sk] : -1;
+        const double a = (nb >= 0 && ci < C) ? hp[nb * C + ci] : 0.0;
+        const double b = (sk < N && co < C) ? dz[sk * C + co] : 0.0;
+        mfma(acc, a, b);
       }
-      dK[e] = acc;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int cio = 16 * tci + lk + 4 * v;
+        if (cio < C && co < C) dK[((long long)t * C + cio) * C + co] = acc[v];
+      }
     }
     for (int co = tid; co < C; co += NTH) {
       double acc = 0.0;
       for (int s = 0; s < N; ++s) acc += dz[s * C + co];
       row[ga.off_convb + (long long)(l - 1) * C + co] = acc;
     }
-    for (int e = tid; e < NC; e += NTH) {
-      const int s = e / C, ci = e % C;
-      double acc = dH[e];
-      for (int t = 0; t < 9; ++t) {
-        const int src = grad_nbr(lt, s, 1 - t % 3, 1 - t / 3);
-        if (src < 0) continue;
-        const double* kt = Kl + (long long)t * C * C + ci * C;
-        const double* d = dz + src * C;
-        for (int co = 0; co < C; ++co) acc = fma(kt[co], d[co], acc);
+    // (3) dH_{l-1}[s][ci] = dH_l[s][ci] + sum_t sum_co K[t][ci][co] dz[s - off_t][co]
+    for (int tt = wave; tt < ntr * nct; tt += NTH / 64) {
+      const int ti = tt / nct, tj = tt - ti * nct;
+      const int si = 16 * ti + lj, ci = 16 * tj + lj;
+      v4d acc;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int so = 16 * ti + lk + 4 * v;
+        acc[v] = (so < N && ci < C) ? dH[so * C + ci] : 0.0;
       }
-      dH[e] = acc;
+      for (int t = 0; t < 9; ++t) {
+        const int src = si < N ? nbt[(8 - t) * N + si] : -1;      // tap 8 - t: the opposite offset
+        const double* drow = dz + (src >= 0 ? src : 0) * C;
+        const double* kt = Kl + ((long long)t * C + ci) * C;
+        for (int q = 0; q < ksc; ++q) {
+          const int cq = 4 * q + lk;
+          const double a = src >= 0 ? drow[cq] : 0.0;
+          const double b = ci < C ? kt[cq] : 0.0;
+          mfma(acc, a, b);
+        }
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int so = 16 * ti + lk + 4 * v;
+        if (so < N && ci < C) dH[so * C + ci] = acc[v];
+      }
     }
     __syncthreads();
   }
@@ -172,15 +219,16 @@ __global__ void k_grad_reduce(const double* __restrict__ rows, long long cnt, lo
   out[p] = acc;
 }
 
-size_t grad_smem(long long ncmax) {
-  const size_t b = (size_t)ncmax * 2 * sizeof(double);
+size_t grad_tab_bytes(long long nsmax) { return (size_t)((9 * nsmax * 2 + 15) & ~15LL); }
+size_t grad_smem(long long ncmax, long long nsmax) {
+  const size_t b = (size_t)ncmax * 2 * sizeof(double) + grad_tab_bytes(nsmax);
   return b <= 160 * 1024 ? b : 0;
 }
 
 hipError_t launch_grad(int prec, const LatDev* lats_dev, int nlats, long long cnt, const Bufs& bf,
                        const GradArgs& ga, hipStream_t st) {
   if (cnt == 0) return hipSuccess;
-  const size_t smem = ga.lds ? grad_smem(ga.ncmax) : 0;
+  const size_t smem = ga.lds ? grad_smem(ga.ncmax, ga.nsmax) : grad_tab_bytes(ga.nsmax);
   if (prec == PREC_F64) {
     hipError_t e = hipFuncSetAttribute((const void*)k_grad<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)smem);

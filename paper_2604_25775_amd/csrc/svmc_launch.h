@@ -98,12 +98,13 @@ struct GradArgs {
   long long nparams, off_convw, off_convb;
   long long w_begin;      // first walker of the launch
   long long ncmax;        // per-walker scratch stride (max N * C)
+  long long nsmax;        // sites of the largest lattice (neighbour table in LDS)
   double* rows;           // [cnt][nparams]
   double* dH;             // [cnt][ncmax]
   double* hs;             // [cnt][ncmax] when !lds
   double* dzs;            // [cnt][ncmax] when !lds
 };
-size_t grad_smem(long long ncmax);   // 0 when H_{l-1} and dz do not fit in LDS
+size_t grad_smem(long long ncmax, long long nsmax);   // 0 when H_{l-1}, dz and the table do not fit in LDS
 hipError_t launch_grad(int prec, const LatDev* lats_dev, int nlats, long long cnt, const Bufs& bf,
                        const GradArgs& ga, hipStream_t st);
 hipError_t launch_grad_reduce(const double* rows, long long cnt, long long nparams, const double* vjp,
