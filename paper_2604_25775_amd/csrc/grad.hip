@@ -127,11 +127,17 @@ __global__ __launch_bounds__(256) void k_grad(const LatDev* __restrict__ lats, i
         const int nb = si < N ? nbt[t * N + si] : -1;
         const double* hrow = hp + (nb >= 0 ? nb : 0) * C;
         const double* kt = Kl + (long long)t * C * C + co;
-        for (int q = 0; q < ksc; ++q) {
-          const int ci = 4 * q + lk;
-          const double a = nb >= 0 ? hrow[ci] : 0.0;
-          const double b = co < C ? kt[ci * C] : 0.0;
-          mfma(acc, a, b);
+        for (int q0 = 0; q0 < ksc; q0 += 4) {
+          double a[4], b[4];                        // four k-steps' operands in flight
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int ci = 4 * (q0 + u) + lk;
+            const bool ok = q0 + u < ksc;
+            a[u] = (ok && nb >= 0) ? hrow[ci] : 0.0;
+            b[u] = (ok && co < C) ? kt[ci * C] : 0.0;
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u) mfma(acc, a[u], b[u]);
         }
       }
 #pragma unroll
@@ -148,12 +154,17 @@ __global__ __launch_bounds__(256) void k_grad(const LatDev* __restrict__ lats, i
       const int t = tt / (nct * nct), r2 = tt - t * nct * nct, tci = r2 / nct, tco = r2 - tci * nct;
       const int ci = 16 * tci + lj, co = 16 * tco + lj;
       v4d acc = v4d{0.0, 0.0, 0.0, 0.0};
-      for (int s0 = 0; s0 < N; s0 += 4) {
-        const int sk = s0 + lk;
-        const int nb = sk < N ? nbt[t * N + sk] : -1;
-        const double a = (nb >= 0 && ci < C) ? hp[nb * C + ci] : 0.0;
-        const double b = (sk < N && co < C) ? dz[sk * C + co] : 0.0;
-        mfma(acc, a, b);
+      for (int s0 = 0; s0 < N; s0 += 16) {
+        double a[4], b[4];                          // four k-steps' operands in flight
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int sk = s0 + 4 * u + lk;
+          const int nb = sk < N ? nbt[t * N + sk] : -1;
+          a[u] = (nb >= 0 && ci < C) ? hp[nb * C + ci] : 0.0;
+          b[u] = (sk < N && co < C) ? dz[sk * C + co] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) mfma(acc, a[u], b[u]);
       }
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
@@ -180,11 +191,17 @@ __global__ __launch_bounds__(256) void k_grad(const LatDev* __restrict__ lats, i
         const int src = si < N ? nbt[(8 - t) * N + si] : -1;      // tap 8 - t: the opposite offset
         const double* drow = dz + (src >= 0 ? src : 0) * C;
         const double* kt = Kl + ((long long)t * C + ci) * C;
-        for (int q = 0; q < ksc; ++q) {
-          const int cq = 4 * q + lk;
-          const double a = src >= 0 ? drow[cq] : 0.0;
-          const double b = ci < C ? kt[cq] : 0.0;
-          mfma(acc, a, b);
+        for (int q0 = 0; q0 < ksc; q0 += 4) {
+          double a[4], b[4];                        // four k-steps' operands in flight
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int cq = 4 * (q0 + u) + lk;
+            const bool ok = q0 + u < ksc;
+            a[u] = (ok && src >= 0) ? drow[cq] : 0.0;
+            b[u] = (ok && ci < C) ? kt[cq] : 0.0;
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u) mfma(acc, a[u], b[u]);
         }
       }
 #pragma unroll
