@@ -79,12 +79,33 @@ __global__ __launch_bounds__(256) void k_grad(const LatDev* __restrict__ lats, i
     const int16_t* ps = pos + sp * nm;
     double* dW = row + lt.poff + (sp ? (long long)C * n0 : 0LL);
     double* db = row + lt.poff + (long long)C * (n0 + n1) + (sp ? n0 : 0);
-    for (int e = tid; e < C * n; e += NTH) {
-      const int c = e / n, m = e % n;
-      const double* Ym = Y + (long long)m * nm;
-      double acc = 0.0;
-      for (int k = 0; k < n; ++k) acc = fma((double)HL[(long long)ps[k] * C + c], Ym[k], acc);
-      dW[e] = acc;
+    // dW[c][m] = sum_k H_L[pos_k][c] Y[m][k] on the FP64 matrix cores: tiles of
+    // 16 channels x 16 orbitals, K over the electrons, four k-steps in flight
+    {
+      const int wave = tid >> 6, lane = tid & 63, lj = lane & 15, lk = lane >> 4;
+      const int nrt = (C + 15) / 16, nmt = (n + 15) / 16;
+      for (int tt = wave; tt < nrt * nmt; tt += NTH / 64) {
+        const int tc = tt / nmt, tm = tt - tc * nmt;
+        const int c = 16 * tc + lj, m = 16 * tm + lj;
+        const double* Ym = Y + (long long)(m < n ? m : 0) * nm;
+        v4d acc = v4d{0.0, 0.0, 0.0, 0.0};
+        for (int k0 = 0; k0 < n; k0 += 16) {
+          double a[4], b[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int k = k0 + 4 * u + lk;
+            a[u] = (k < n && c < C) ? (double)HL[(long long)ps[k] * C + c] : 0.0;
+            b[u] = (k < n && m < n) ? Ym[k] : 0.0;
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u) mfma(acc, a[u], b[u]);
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int co = 16 * tc + lk + 4 * v;
+          if (co < C && m < n) dW[co * n + m] = acc[v];
+        }
+      }
     }
     for (int m = tid; m < n; m += NTH) {
       const double* Ym = Y + (long long)m * nm;
