@@ -139,27 +139,33 @@ __global__ __launch_bounds__(256) void k_grad(const LatDev* __restrict__ lats, i
     // writes an element of dH is the one that reads it in the next layer.
     const int wave = tid >> 6, lane = tid & 63, lj = lane & 15, lk = lane >> 4;
     const int nct = (C + 15) / 16, ntr = (N + 15) / 16, ksc = C / 4;
+    constexpr int GQ = 8;            // k-steps per tap at most (C <= 32)
     // (1) z = conv(H_{l-1}) + b, dz = dH * act'(z): tiles of 16 sites x 16 outputs
     for (int tt = wave; tt < ntr * nct; tt += NTH / 64) {
       const int ti = tt / nct, tj = tt - ti * nct;
       const int si = 16 * ti + lj, co = 16 * tj + lj;
       v4d acc = v4d{0.0, 0.0, 0.0, 0.0};
-      for (int t = 0; t < 9; ++t) {
+      // operands of tap t + 1 are requested before the products of tap t
+      double a[2][GQ], b[2][GQ];
+      auto load = [&](int t, double (&aa)[GQ], double (&bb)[GQ]) {
         const int nb = si < N ? nbt[t * N + si] : -1;
         const double* hrow = hp + (nb >= 0 ? nb : 0) * C;
         const double* kt = Kl + (long long)t * C * C + co;
-        for (int q0 = 0; q0 < ksc; q0 += 4) {
-          double a[4], b[4];                        // four k-steps' operands in flight
 #pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            const int ci = 4 * (q0 + u) + lk;
-            const bool ok = q0 + u < ksc;
-            a[u] = (ok && nb >= 0) ? hrow[ci] : 0.0;
-            b[u] = (ok && co < C) ? kt[ci * C] : 0.0;
-          }
-#pragma unroll
-          for (int u = 0; u < 4; ++u) mfma(acc, a[u], b[u]);
+        for (int u = 0; u < GQ; ++u) {
+          const int ci = 4 * u + lk;
+          const bool ok = u < ksc;
+          aa[u] = (ok && nb >= 0) ? hrow[ci] : 0.0;
+          bb[u] = (ok && co < C) ? kt[ci * C] : 0.0;
         }
+      };
+      load(0, a[0], b[0]);
+#pragma unroll
+      for (int t = 0; t < 9; ++t) {
+        if (t + 1 < 9) load(t + 1, a[(t + 1) & 1], b[(t + 1) & 1]);
+#pragma unroll
+        for (int u = 0; u < GQ; ++u)
+          if (u < ksc) mfma(acc, a[t & 1][u], b[t & 1][u]);
       }
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
@@ -208,22 +214,26 @@ __global__ __launch_bounds__(256) void k_grad(const LatDev* __restrict__ lats, i
         const int so = 16 * ti + lk + 4 * v;
         acc[v] = (so < N && ci < C) ? dH[so * C + ci] : 0.0;
       }
-      for (int t = 0; t < 9; ++t) {
+      double a[2][GQ], b[2][GQ];
+      auto load = [&](int t, double (&aa)[GQ], double (&bb)[GQ]) {
         const int src = si < N ? nbt[(8 - t) * N + si] : -1;      // tap 8 - t: the opposite offset
         const double* drow = dz + (src >= 0 ? src : 0) * C;
         const double* kt = Kl + ((long long)t * C + ci) * C;
-        for (int q0 = 0; q0 < ksc; q0 += 4) {
-          double a[4], b[4];                        // four k-steps' operands in flight
 #pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            const int cq = 4 * (q0 + u) + lk;
-            const bool ok = q0 + u < ksc;
-            a[u] = (ok && src >= 0) ? drow[cq] : 0.0;
-            b[u] = (ok && ci < C) ? kt[cq] : 0.0;
-          }
-#pragma unroll
-          for (int u = 0; u < 4; ++u) mfma(acc, a[u], b[u]);
+        for (int u = 0; u < GQ; ++u) {
+          const int cq = 4 * u + lk;
+          const bool ok = u < ksc;
+          aa[u] = (ok && src >= 0) ? drow[cq] : 0.0;
+          bb[u] = (ok && ci < C) ? kt[cq] : 0.0;
         }
+      };
+      load(0, a[0], b[0]);
+#pragma unroll
+      for (int t = 0; t < 9; ++t) {
+        if (t + 1 < 9) load(t + 1, a[(t + 1) & 1], b[(t + 1) & 1]);
+#pragma unroll
+        for (int u = 0; u < GQ; ++u)
+          if (u < ksc) mfma(acc, a[t & 1][u], b[t & 1][u]);
       }
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
