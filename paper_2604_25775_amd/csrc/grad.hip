@@ -51,6 +51,7 @@ __global__ __launch_bounds__(256) void k_grad(const LatDev* __restrict__ lats, i
   const int tid = threadIdx.x;
   double* row = ga.rows + (long long)blockIdx.x * ga.nparams;
   extern __shared__ __attribute__((aligned(16))) double glds[];
+  __shared__ double gred[4 * NTH];   // partial sums of the reductions below
   double* hp = ga.lds ? glds : ga.hs + (long long)blockIdx.x * ga.ncmax;
   double* dz = ga.lds ? glds + ga.ncmax : ga.dzs + (long long)blockIdx.x * ga.ncmax;
   double* dH = ga.dH + (long long)blockIdx.x * ga.ncmax;
@@ -107,11 +108,25 @@ __global__ __launch_bounds__(256) void k_grad(const LatDev* __restrict__ lats, i
         }
       }
     }
-    for (int m = tid; m < n; m += NTH) {
-      const double* Ym = Y + (long long)m * nm;
-      double acc = 0.0;
-      for (int k = 0; k < n; ++k) acc += Ym[k];
-      db[m] = acc;
+    // db[m] = sum_k Y[m][k]: each row summed in `parts` interleaved pieces
+    if (n > 0) {
+      const int parts = n < NTH ? NTH / n : 1;
+      for (int m0 = 0; m0 < n; m0 += NTH) {
+        const int m = m0 + tid % n, part = tid / n;
+        double acc = 0.0;
+        if (part < parts && m < n) {
+          const double* Ym = Y + (long long)m * nm;
+          for (int k = part; k < n; k += parts) acc += Ym[k];
+        }
+        gred[tid] = acc;
+        __syncthreads();
+        if (tid < n && m0 + tid < n) {
+          double t = 0.0;
+          for (int q = 0; q < parts; ++q) t += gred[q * n + tid];
+          db[m0 + tid] = t;
+        }
+        __syncthreads();
+      }
     }
   }
   for (int e = tid; e < NC; e += NTH) {
@@ -199,10 +214,18 @@ __global__ __launch_bounds__(256) void k_grad(const LatDev* __restrict__ lats, i
         if (cio < C && co < C) dK[((long long)t * C + cio) * C + co] = acc[v];
       }
     }
-    for (int co = tid; co < C; co += NTH) {
+    {
+      // db_l[co] = sum_s dz[s][co]: NTH / C interleaved pieces per channel
+      const int parts = NTH / C, co = tid % C, part = tid / C;
       double acc = 0.0;
-      for (int s = 0; s < N; ++s) acc += dz[s * C + co];
-      row[ga.off_convb + (long long)(l - 1) * C + co] = acc;
+      for (int s = part; s < N; s += parts) acc += dz[s * C + co];
+      gred[tid] = acc;
+      __syncthreads();
+      if (tid < C) {
+        double t = 0.0;
+        for (int q = 0; q < parts; ++q) t += gred[q * C + tid];
+        row[ga.off_convb + (long long)(l - 1) * C + tid] = t;
+      }
     }
     // (3) dH_{l-1}[s][ci] = dH_l[s][ci] + sum_t sum_co K[t][ci][co] dz[s - off_t][co]
     for (int tt = wave; tt < ntr * nct; tt += NTH / 64) {
@@ -245,12 +268,26 @@ __global__ __launch_bounds__(256) void k_grad(const LatDev* __restrict__ lats, i
   }
 
   // ---- embedding
-  for (int e = tid; e < 4 * C; e += NTH) {
-    const int o = e / C, c = e % C;
-    double acc = 0.0;
-    for (int s = 0; s < N; ++s)
-      if (occ[s] == o) acc += dH[s * C + c];
-    row[e] = acc;
+  {
+    // dE[o][c] = sum over sites with occupation o of dH_0[s][c]: NTH / C
+    // interleaved pieces of the sites per channel, four bins each
+    const int parts = NTH / C, c = tid % C, part = tid / C;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int s = part; s < N; s += parts) {
+      const double v = dH[s * C + c];
+      const int o = occ[s];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc[q] += (o == q) ? v : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) gred[q * NTH + tid] = acc[q];
+    __syncthreads();
+    if (tid < 4 * C) {
+      const int o = tid / C, cc = tid % C;
+      double t = 0.0;
+      for (int q = 0; q < parts; ++q) t += gred[o * NTH + q * C + cc];
+      row[tid] = t;
+    }
   }
 }
 
@@ -269,8 +306,9 @@ __global__ void k_grad_reduce(const double* __restrict__ rows, long long cnt, lo
 
 size_t grad_tab_bytes(long long nsmax) { return (size_t)((9 * nsmax * 2 + 15) & ~15LL); }
 size_t grad_smem(long long ncmax, long long nsmax) {
+  // k_grad also holds 4 * 256 doubles of static LDS for its reductions
   const size_t b = (size_t)ncmax * 2 * sizeof(double) + grad_tab_bytes(nsmax);
-  return b <= 160 * 1024 ? b : 0;
+  return b + 4 * 256 * sizeof(double) <= 160 * 1024 ? b : 0;
 }
 
 hipError_t launch_grad(int prec, const LatDev* lats_dev, int nlats, long long cnt, const Bufs& bf,
