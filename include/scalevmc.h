@@ -189,7 +189,7 @@ svmc_status svmc_local_energy(svmc_ctx* ctx, svmc_path path, double* eloc,
  * walker of a lattice with N sites takes n_sweeps * N proposals.
  * n_accept: device [W] int64 incremented by each walker's accepted moves, or
  * NULL.  Work is queued on `stream`; nothing waits on it.  The first call
- * allocates the sweep workspace (about 35 KB per walker at 16x16, C = 32).
+ * allocates the sweep workspace (about 32 KB per walker at 16x16, C = 32).
  * Errors: SVMC_ERR_STATE without walkers, SVMC_ERR_INVALID_ARG for
  * n_sweeps < 0 or refresh_every < 1, SVMC_ERR_UNSUPPORTED when one walker's
  * workspace exceeds 160 KiB of LDS. */

@@ -18,7 +18,11 @@
 // unrounded network at the same weights.
 //
 // One workgroup per walker: H_{l-1} and dz of the walker live in LDS when
-// 2 N C doubles fit, else in a global scratch; dH is a global scratch.
+// 2 N C doubles fit, else in a global scratch; dH is a global scratch; the
+// site neighbours per tap are a table in LDS.  dW and the three products of
+// each layer (z, dK, the transposed conv) run on the FP64 matrix cores
+// (16 x 16 x 4 tiles); the sums over sites for db, db_l and dE are spread
+// over the workgroup and combined in LDS.
 #include "svmc_launch.h"
 
 namespace svmc {
