@@ -4,8 +4,9 @@
 //
 // The sweep is step-synchronous across walkers: proposal q of every walker
 // is one launch of k_step_propose (one workgroup per walker), followed by
-// one launch of k_step_update over the walkers that accepted, then the
-// masked FP64 refresh of walkers that reached `refresh_every` accepted moves.
+// one launch of k_step_update over the walkers that accepted; every few
+// steps the FP64 refresh of the walkers that reached `refresh_every`
+// accepted moves, driven by a device-side list.
 //   propose  incremental conv on the update box + determinant-lemma matrix A
 //            per spin (the routines of the local-energy kernel); on accept
 //            the new features are committed to the cache, A^-1 (Gauss-Jordan
@@ -22,8 +23,9 @@
 //              G'[s][k'] = G[s][k'] + E[s] . W[:, k'],
 //              E[s] = [s in box] D(s) A^-1[0:C, :] - G[s, K] B,
 //              P^T'[k'] = A^-1[0:C, :] W[:, k'].
-//            One workgroup per (walker, spin): B once, then G in chunks of
-//            sites, then P.
+//            One workgroup per (walker, spin): E and G in chunks of sites,
+//            with E formed as [D(s) - G[s, K] D_K | -G[s, k_mover]] A^-1
+//            (no B), then P.
 //
 // Proposal q of walker w uses one Philox4x64-10 block (key (seed, 0), counter
 // (w, step0 + q, 0, 0)), written from the published definition (Salmon et
@@ -86,8 +88,8 @@ __host__ __device__ inline ProposeLds propose_layout(int N, int Gx, int Gy, int 
   o.bytes = o.scratch + hop_scratch(Gx, Gy, L, C, tfb).bytes;
   return o;
 }
-// LDS of the update kernel: A^-1, B = U A^-1, the changed-row list, E rows of
-// a chunk of sites.
+// LDS of the update kernel: A^-1, the changed-row list, the D rows of the
+// changed electrons, E rows of a chunk of sites.
 __host__ __device__ inline int update_lds_bytes(int kmax, int C, int dtb) {
   const int ra = C + 1;
   return al16(ra * ra * 8) + al16(kmax * 4) + al16(kmax * C * dtb) + UPD_SC * (4 * ((ra + 3) / 4)) * 8;
