@@ -243,7 +243,7 @@ svmc_status svmc_walker_flags(svmc_ctx* ctx, int32_t* flags, hipStream_t stream)
 /* Autotuner of the low-rank local-energy launch shape (not a step of the
  * method): each walker's hops are split over `slices` workgroups.  Times
  * svmc_local_energy(LOWRANK) on the loaded walkers for slices in
- * {1, 2, 4, 8, 16} and keeps the fastest for this context.  cache_path
+ * {1, 2, 4, 8, 16, 24, 32} and keeps the fastest for this context.  cache_path
  * (may be NULL): a text file; a line for the same shape key (lattices,
  * network, precision, walker count, device name) is reused without timing,
  * otherwise the result is appended.  *slices_out (may be NULL) receives the

@@ -774,7 +774,7 @@ svmc_status svmc_tune(svmc_ctx* ctx, const char* cache_path, int32_t* slices_out
   if ((s = ctx->hip(eo.ensure((size_t)ctx->Wtot * 8), "alloc"))) return s;
   hipEvent_t e0, e1;
   if ((s = ctx->hip(hipEventCreate(&e0), "event")) || (s = ctx->hip(hipEventCreate(&e1), "event"))) return s;
-  const int cand[5] = {1, 2, 4, 8, 16};
+  const int cand[7] = {1, 2, 4, 8, 16, 24, 32};
   int best = ctx->eloc_slices;
   float best_ms = 1e30f;
   std::ostringstream times;
