@@ -88,7 +88,8 @@ def traffic_record(workload: str, walkers: int, prec: str):
                         and r.get("walkers") == walkers and r.get("prec") == prec):
                     fetch = r["fetch_kib"] * COPY_PROBE_BYTES / r["copy_fetch_kib"]
                     write = r["write_kib"] * COPY_PROBE_BYTES / r["copy_write_kib"]
-                    return {"bytes": fetch + write, "fetch_bytes": fetch, "write_bytes": write, "file": f}
+                    return {"bytes": fetch + write, "fetch_bytes": fetch, "write_bytes": write, "file": f,
+                            "slices": r.get("slices")}
     return None
 
 
@@ -352,7 +353,8 @@ def main():
                 "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
                 "traffic": round(tr["bytes"]) if tr else None,
                 "traffic_note": (f"HBM bytes per launch, FETCH_SIZE + WRITE_SIZE scaled by a "
-                                 f"{COPY_PROBE_BYTES}-byte copy ({tr['file']})") if tr else
+                                 f"{COPY_PROBE_BYTES}-byte copy ({tr['file']}; counters taken at "
+                                 f"{tr['slices']} slices per walker, this run {slices})") if tr else
                                 "no counter record for these sources",
                 "kernel": "k_eloc_lowrank",
                 "flops_conv_per_launch": conv_f, "flops_fp64_per_launch": det_f,
