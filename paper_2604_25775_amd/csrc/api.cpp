@@ -709,13 +709,12 @@ svmc_status svmc_grad_logpsi(svmc_ctx* ctx, const double* vjp_w, double* out, hi
   ga.ncmax = ncmax;
   ga.nsmax = nsmax;
   if ((s = ctx->hip(ctx->g_dH.ensure((size_t)chunk * ncmax * 8), "alloc gradient scratch"))) return s;
-  if (!ga.lds && ((s = ctx->hip(ctx->g_hs.ensure((size_t)chunk * ncmax * 8), "alloc gradient scratch")) ||
-                  (s = ctx->hip(ctx->g_dzs.ensure((size_t)chunk * ncmax * 8), "alloc gradient scratch"))))
-    return s;
+  if ((s = ctx->hip(ctx->g_dzs.ensure((size_t)chunk * ncmax * 8), "alloc gradient scratch"))) return s;
+  if (!ga.lds && (s = ctx->hip(ctx->g_hs.ensure((size_t)chunk * ncmax * 8), "alloc gradient scratch"))) return s;
   if (!jac && (s = ctx->hip(ctx->g_rows.ensure((size_t)chunk * np * 8), "alloc gradient rows"))) return s;
   ga.dH = ctx->g_dH.as<double>();
   ga.hs = ga.lds ? nullptr : ctx->g_hs.as<double>();
-  ga.dzs = ga.lds ? nullptr : ctx->g_dzs.as<double>();
+  ga.dzs = ctx->g_dzs.as<double>();
   const Bufs bf = ctx->bufs();
   for (long long b0 = 0; b0 < W; b0 += chunk) {
     const long long cnt = std::min(chunk, W - b0);

@@ -17,8 +17,9 @@
 // (its derivative is zero almost everywhere); the gradient is the one of the
 // unrounded network at the same weights.
 //
-// One workgroup per walker: H_{l-1} and dz of the walker live in LDS when
-// 2 N C doubles fit, else in a global scratch; dH is a global scratch; the
+// One workgroup per walker: H_{l-1} of the walker lives in LDS when N C
+// doubles fit (two workgroups per CU at 16x16, C = 32), else in a global
+// scratch; dz and dH are global scratch (L2-resident); the
 // site neighbours per tap are a table in LDS.  dW and the three products of
 // each layer (z, dK, the transposed conv) run on the FP64 matrix cores
 // (16 x 16 x 4 tiles); the sums over sites for db, db_l and dE are spread
@@ -57,10 +58,10 @@ __global__ __launch_bounds__(256) void k_grad(const LatDev* __restrict__ lats, i
   extern __shared__ __attribute__((aligned(16))) double glds[];
   __shared__ double gred[4 * NTH];   // partial sums of the reductions below
   double* hp = ga.lds ? glds : ga.hs + (long long)blockIdx.x * ga.ncmax;
-  double* dz = ga.lds ? glds + ga.ncmax : ga.dzs + (long long)blockIdx.x * ga.ncmax;
+  double* dz = ga.dzs + (long long)blockIdx.x * ga.ncmax;
   double* dH = ga.dH + (long long)blockIdx.x * ga.ncmax;
   // neighbour of site s at tap t (offset (t % 3 - 1, t / 3 - 1)), -1 off an open edge
-  int16_t* nbt = (int16_t*)(ga.lds ? glds + 2 * ga.ncmax : glds);
+  int16_t* nbt = (int16_t*)(ga.lds ? glds + ga.ncmax : glds);
   const bool bad = (bf.flags[w] & (1 | 2 | 8)) != 0;
   for (long long p = tid; p < ga.nparams; p += NTH) row[p] = bad ? NAN : 0.0;
   if (bad) return;
@@ -311,7 +312,7 @@ __global__ void k_grad_reduce(const double* __restrict__ rows, long long cnt, lo
 size_t grad_tab_bytes(long long nsmax) { return (size_t)((9 * nsmax * 2 + 15) & ~15LL); }
 size_t grad_smem(long long ncmax, long long nsmax) {
   // k_grad also holds 4 * 256 doubles of static LDS for its reductions
-  const size_t b = (size_t)ncmax * 2 * sizeof(double) + grad_tab_bytes(nsmax);
+  const size_t b = (size_t)ncmax * sizeof(double) + grad_tab_bytes(nsmax);
   return b + 4 * 256 * sizeof(double) <= 160 * 1024 ? b : 0;
 }
 

@@ -91,7 +91,7 @@ hipError_t launch_fill_i64(int64_t* p, long long n, int64_t v, hipStream_t st);
 
 // grad.hip: d log|psi| / d theta, one row per walker
 struct GradArgs {
-  int L, C, act, lds;     // lds: H_{l-1} and dz of a walker in LDS (else hs / dzs)
+  int L, C, act, lds;     // lds: H_{l-1} of a walker in LDS (else hs)
   const double* K;        // [L][9][C][C] conv weights as the forward uses them
   const double* B;        // [L][C]
   const double* E;        // [4][C]
@@ -102,9 +102,9 @@ struct GradArgs {
   double* rows;           // [cnt][nparams]
   double* dH;             // [cnt][ncmax]
   double* hs;             // [cnt][ncmax] when !lds
-  double* dzs;            // [cnt][ncmax] when !lds
+  double* dzs;            // [cnt][ncmax]
 };
-size_t grad_smem(long long ncmax, long long nsmax);   // 0 when H_{l-1}, dz and the table do not fit in LDS
+size_t grad_smem(long long ncmax, long long nsmax);   // 0 when H_{l-1} and the table do not fit in LDS
 hipError_t launch_grad(int prec, const LatDev* lats_dev, int nlats, long long cnt, const Bufs& bf,
                        const GradArgs& ga, hipStream_t st);
 hipError_t launch_grad_reduce(const double* rows, long long cnt, long long nparams, const double* vjp,
