@@ -133,6 +133,19 @@ def lowrank_flops(lat, occ: np.ndarray, L: int, C: int):
         lo2, hi2 = np.maximum(lo, 0), np.minimum(hi, La - 1)
         return lo2, hi2 - lo2 + 1
 
+    def ball_mask(l):
+        """[N, N] bool: site s2 within Chebyshev distance l of site s (wrapped
+        on periodic axes, clipped on open ones)."""
+        dxm = np.abs(xs[:, None] - xs[None, :])
+        dym = np.abs(ys[:, None] - ys[None, :])
+        if lat.pbc_x:
+            dxm = np.minimum(dxm, Lx - dxm)
+        if lat.pbc_y:
+            dym = np.minimum(dym, Ly - dym)
+        return (dxm <= l) & (dym <= l)
+
+    balls = {}
+
     def box_count(s, x0, wx, y0, wy):
         # x0, y0 may be negative on periodic axes: shift into the middle copy
         X0 = x0 + Lx
@@ -154,20 +167,31 @@ def lowrank_flops(lat, occ: np.ndarray, L: int, C: int):
             nh = valid.sum()
             if nh == 0:
                 continue
-            # conv work: layer boxes (the union of two Chebyshev balls; a
-            # rectangle for nearest-neighbour hops)
+            # conv work: layer l recomputes the union of the two Chebyshev
+            # balls of radius l (a rectangle for nearest-neighbour hops; for
+            # diagonal hops counted from per-site masks)
+            diag = DX[d] != 0 and DY[d] != 0
             for l in range(1, L + 1):
-                _, wx = axis_range(xs, xj, l, Lx, lat.pbc_x)
-                _, wy = axis_range(ys, yj, l, Ly, lat.pbc_y)
-                sites = wx * wy
-                if DX[d] != 0 and DY[d] != 0:
-                    # diagonal hop: two (2l+1)^2 squares overlapping
-                    sites = np.minimum(sites, 2 * (2 * l + 1) ** 2 - (2 * l) ** 2)
+                if diag:
+                    if l not in balls:
+                        balls[l] = ball_mask(l)
+                    sites = (balls[l] | balls[l][jsite]).sum(axis=1)
+                else:
+                    _, wx = axis_range(xs, xj, l, Lx, lat.pbc_x)
+                    _, wy = axis_range(ys, yj, l, Ly, lat.pbc_y)
+                    sites = wx * wy
                 conv += float((valid * sites[None, :]).sum()) * 9 * C * C * 2
-            x0, wx = axis_range(xs, xj, L, Lx, lat.pbc_x)
-            y0, wy = axis_range(ys, yj, L, Ly, lat.pbc_y)
-            ku = box_count(sat_u, x0[None, :], wx[None, :], y0[None, :], wy[None, :])
-            kd = box_count(sat_d, x0[None, :], wx[None, :], y0[None, :], wy[None, :])
+            if diag:
+                if L not in balls:
+                    balls[L] = ball_mask(L)
+                uni = (balls[L] | balls[L][jsite]).astype(np.int64)          # [N(site i), N]
+                ku = ups.reshape(W, N) @ uni.T
+                kd = dns.reshape(W, N) @ uni.T
+            else:
+                x0, wx = axis_range(xs, xj, L, Lx, lat.pbc_x)
+                y0, wy = axis_range(ys, yj, L, Ly, lat.pbc_y)
+                ku = box_count(sat_u, x0[None, :], wx[None, :], y0[None, :], wy[None, :])
+                kd = box_count(sat_d, x0[None, :], wx[None, :], y0[None, :], wy[None, :])
             for tau, k in ((0, ku), (1, kd)):
                 r = np.minimum(k, C + (1 if tau == sp else 0))
                 fma = k * C * r + r ** 3 / 3.0

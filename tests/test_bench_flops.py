@@ -1,0 +1,85 @@
+"""bench.lowrank_flops, the algorithmic work behind the roofline figure,
+against a brute-force enumeration of every hop: per layer l the union of the
+two Chebyshev balls of radius l around the hop's sites (wrapped on periodic
+axes, clipped on open ones), and per spin the electrons inside the layer-L
+union.  Covers nearest-neighbour and diagonal hops, periodic and open axes,
+and axes short enough for the balls to wrap onto themselves."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+import workloads as wl  # noqa: E402
+
+DX = [1, -1, 0, 0, 1, 1, -1, -1]
+DY = [0, 0, 1, -1, 1, -1, 1, -1]
+
+
+def brute_flops(lat, occ, L, C):
+    W, N = occ.shape
+    Lx, Ly = lat.Lx, lat.Ly
+    nd = 8 if lat.tp != 0.0 else 4
+
+    def wrap(x, y):
+        if lat.pbc_x:
+            x %= Lx
+        elif not 0 <= x < Lx:
+            return None
+        if lat.pbc_y:
+            y %= Ly
+        elif not 0 <= y < Ly:
+            return None
+        return x, y
+
+    def ball(x, y, l):
+        out = set()
+        for dy in range(-l, l + 1):
+            for dx in range(-l, l + 1):
+                p = wrap(x + dx, y + dy)
+                if p is not None:
+                    out.add(p)
+        return out
+
+    conv = det = 0.0
+    for w in range(W):
+        g = occ[w].reshape(Ly, Lx)
+        for sp in (0, 1):
+            for y in range(Ly):
+                for x in range(Lx):
+                    if not (g[y, x] >> sp) & 1:
+                        continue
+                    for d in range(nd):
+                        pj = wrap(x + DX[d], y + DY[d])
+                        if pj is None or (g[pj[1], pj[0]] >> sp) & 1:
+                            continue
+                        for l in range(1, L + 1):
+                            conv += len(ball(x, y, l) | ball(*pj, l)) * 9 * C * C * 2
+                        box = ball(x, y, L) | ball(*pj, L)
+                        for tau in (0, 1):
+                            k = sum(1 for (bx, by) in box if (g[by, bx] >> tau) & 1)
+                            r = min(k, C + (1 if tau == sp else 0))
+                            det += 2.0 * (k * C * r + r ** 3 / 3.0)
+    return conv, det
+
+
+CASES = [
+    ("6x5_open_y_nn", wl.Lattice(6, 5, 1, 0, 1.0, 0.0, 4.0, 7, 6), 2, 8),
+    ("6x5_open_y_diag", wl.Lattice(6, 5, 1, 0, 1.0, 0.3, 4.0, 7, 6), 2, 8),
+    ("9x8_pbc_diag_L3", wl.Lattice(9, 8, 1, 1, 1.0, -0.2, 4.0, 20, 18), 3, 8),
+    ("5x7_open_diag_C16", wl.Lattice(5, 7, 0, 0, 1.0, 0.2, 4.0, 8, 9), 2, 16),
+    ("4x4_pbc_wrapping_L2", wl.Lattice(4, 4, 1, 1, 1.0, 0.1, 4.0, 5, 5), 2, 8),
+]
+
+
+@pytest.mark.parametrize("name,lat,L,C", CASES, ids=[c[0] for c in CASES])
+def test_lowrank_flops_match_brute_force(name, lat, L, C):
+    occ = wl.random_occupations(lat, 3, seed=4)
+    got = bench.lowrank_flops(lat, occ, L, C)
+    ref = brute_flops(lat, occ, L, C)
+    assert got[0] == pytest.approx(ref[0], rel=1e-12)
+    assert got[1] == pytest.approx(ref[1], rel=1e-12)
