@@ -26,6 +26,8 @@ F64_CASES = [
     ("8x8pbc_cform_L2C8", wl.Lattice(8, 8, 1, 1, 1.0, 0.0, 8.0, 28, 28), wl.Model(2, 8, "tanh", "f64"), 4),
     ("9x9pbc_L3C16", wl.Lattice(9, 9, 1, 1, 1.0, 0.0, 8.0, 10, 12), wl.Model(3, 16, "tanh", "f64"), 3),
     ("12x10_L4C8", wl.Lattice(12, 10, 1, 0, 1.0, 0.0, 8.0, 26, 26), wl.Model(4, 8, "tanh", "f64"), 2),
+    # fewer sites than one 16-row tile; every box covers the lattice
+    ("2x5open_x_tp_L2C8", wl.Lattice(2, 5, 0, 1, 1.0, 0.3, 6.0, 2, 2), wl.Model(2, 8, "tanh", "f64"), 6),
 ]
 
 
