@@ -88,12 +88,18 @@ typedef struct {
   int32_t n_up, n_dn;
 } svmc_lattice;
 
-/* Network shape (Sec. II.B): n_conv residual 3x3 conv layers (1..4) of
- * `channels` channels (8, 16, 24 or 32), activation svmc_act, conv precision
- * svmc_prec; refresh_every = accepted Metropolis moves between FP64 inverse
- * rebuilds (>= 1). */
+/* Network shape (Sec. II.B): an embedding layer, n_conv residual ksize x
+ * ksize conv layers (1..4) of `channels` channels (8, 16, 24 or 32),
+ * activation svmc_act, conv precision svmc_prec, then n_mlp site-wise MLP
+ * layers (Sec. II.B, site-wise MLP equation) before the orbital projection.
+ * refresh_every = accepted Metropolis moves between FP64 inverse rebuilds
+ * (>= 1).  ksize must be 3 and n_mlp 0 (other values: SVMC_ERR_UNSUPPORTED).
+ * per_site_embed = 0: one embedding table E[4][C] shared by all sites;
+ * 1: a table E_i[4][C] per site i (the embedding layer as Sec. II.B writes
+ * it), per lattice of the context. */
 typedef struct {
   int32_t n_conv, channels, act, conv_prec, refresh_every;
+  int32_t ksize, n_mlp, per_site_embed;
 } svmc_model;
 
 /* Create a context for n_lats lattices (1..8) sharing one network.  Lattices
@@ -108,10 +114,13 @@ svmc_status svmc_create(const svmc_lattice* lats, int32_t n_lats,
 svmc_status svmc_destroy(svmc_ctx* ctx);
 
 /* Length of the flat parameter vector theta:
- *   embed[4][C] | conv_w[L][3][3][C][C] (ky, kx, c_in, c_out; tap (ky,kx)
+ *   embed | conv_w[L][3][3][C][C] (ky, kx, c_in, c_out; tap (ky,kx)
  *   reads the neighbour at offset (kx-1, ky-1)) | conv_b[L][C] |
  *   for each lattice: W_up[C][n_up] | W_dn[C][n_dn] | b_up[n_up] | b_dn[n_dn]
- * all row-major FP64.  Row of spin s at site x:  base_s[x] + H_L[x] W_s + b_s. */
+ * all row-major FP64, with embed = E[4][C] (shared table) or, with
+ * per_site_embed, E_l[N_l][4][C] for each lattice l in order (site, then
+ * occupation n_up + 2 n_dn).  Row of spin s at site x:
+ * base_s[x] + H_L[x] W_s + b_s. */
 int64_t svmc_num_params(const svmc_ctx* ctx);
 
 /* Upload parameters.  theta: device, svmc_num_params doubles (layout above).
@@ -220,12 +229,15 @@ svmc_status svmc_get_state(svmc_ctx* ctx, int8_t* occ, int16_t* pos,
                            hipStream_t stream);
 int32_t svmc_max_electrons(const svmc_ctx* ctx);
 
-/* d log|psi_w| / d theta (theta layout of svmc_num_params), FP64, for the
- * network of Sec. II.B whose parameters Sec. II.F optimises.
+/* d log|psi_w| / d theta (theta layout of svmc_num_params), computed in FP64,
+ * for the network of Sec. II.B whose parameters Sec. II.F optimises.
  * vjp_w == NULL: out is device [W][n_params], one row per walker (entries of
- * other lattices' projection blocks are 0).
+ * other lattices' projection and per-site embedding blocks are 0).
  * vjp_w != NULL (device [W]): out is device [n_params] = sum_w vjp_w[w] *
  * d log|psi_w|/d theta, summed in walker order (deterministic).
+ * out_prec: element type of out, SVMC_FP64 (double) or SVMC_FP32 (float, each
+ * entry rounded once from the FP64 result; halves the Jacobian's memory);
+ * other values: SVMC_ERR_INVALID_ARG.
  * Uses d log|det Phi| = tr(Phi^-1 dPhi) for the projection, dH_L = P = W Phi^-1
  * at the occupied sites, and back-propagation through the residual conv stack
  * (pre-activations recomputed from the cached features) to the embedding.
@@ -233,9 +245,10 @@ int32_t svmc_max_electrons(const svmc_ctx* ctx);
  * activation rounding is not differentiated.  Inverses are rebuilt first if
  * Metropolis moves made them stale.  Walkers flagged SINGULAR, NONFINITE or
  * BADCOUNT get a NaN row and are left out of the VJP sum.  Scratch: up to
- * 4096 walkers x (N C) doubles, plus 1024 x n_params doubles for the VJP. */
-svmc_status svmc_grad_logpsi(svmc_ctx* ctx, const double* vjp_w, double* out,
-                             hipStream_t stream);
+ * 4096 walkers x (N C) doubles, plus 1024 x n_params doubles for the VJP or
+ * an FP32 Jacobian. */
+svmc_status svmc_grad_logpsi(svmc_ctx* ctx, const double* vjp_w, void* out,
+                             svmc_prec out_prec, hipStream_t stream);
 
 /* Per-walker flag bits (svmc_walker_flag), device [W] int32. */
 svmc_status svmc_walker_flags(svmc_ctx* ctx, int32_t* flags, hipStream_t stream);

@@ -2,7 +2,9 @@
 (Sec. II.B).
 
   embedding   H0[s]   = E[n_s]                 (Sec. II.B, embedding layer;
-                                                one table shared by all sites)
+                                                one table shared by all sites,
+              or      = E_s[n_s]                one table per site, as the
+                                                embedding layer is written there)
   conv layer  H_l[s]  = H_{l-1}[s] + act(b_l + sum_{taps} K_l[tap] H_{l-1}[s+tap])
                                                (Sec. II.B, residual conv
                                                 equation; stacked n_conv times,
@@ -44,13 +46,24 @@ def tap_tables(lat) -> list:
     return tabs
 
 
-def features(lat, params, occ, act: str = "tanh", conv_input_round=None) -> list:
+def embedding(params, occ, lat_index: int = 0) -> np.ndarray:
+    """H_0 [N, C]: the row of each site's occupation in the shared table, or
+    in that site's own table when params.embed_site is set."""
+    o = np.asarray(occ, dtype=np.int64)
+    site = getattr(params, "embed_site", None)
+    if site is None:
+        return params.embed[o].astype(np.float64)
+    E = site[lat_index]                                   # [N, 4, C]
+    return np.stack([E[s, o[s]] for s in range(len(o))]).astype(np.float64)
+
+
+def features(lat, params, occ, act: str = "tanh", conv_input_round=None, lat_index: int = 0) -> list:
     """[H_0, H_1, ..., H_L], each [N, C] FP64.
 
     conv_input_round: optional function applied to the layer input before it
     enters the convolution (not to the residual branch); used to model a conv
     whose multiplier inputs are rounded to a narrower format."""
-    H = params.embed[np.asarray(occ, dtype=np.int64)].astype(np.float64)
+    H = embedding(params, occ, lat_index)
     out = [H]
     tabs = tap_tables(lat)
     L = params.conv_w.shape[0]
@@ -80,7 +93,7 @@ def occupied_sites(occ, spin: int) -> np.ndarray:
 
 
 def slater_matrices(lat, params, occ, lat_index: int = 0, act: str = "tanh", conv_input_round=None):
-    HL = features(lat, params, occ, act, conv_input_round)[-1]
+    HL = features(lat, params, occ, act, conv_input_round, lat_index)[-1]
     return [orbital_rows(params, lat_index, HL, s)[occupied_sites(occ, s)]
             for s in (0, 1)]
 

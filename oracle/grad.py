@@ -7,7 +7,8 @@ two independent routes:
   by torch autograd.
 
 Flat parameter order (theta):
-  embed [4, C] | conv_w [L, 3, 3, C, C] | conv_b [L, C] |
+  embed [4, C] (or, with per-site tables, [N_l, 4, C] of every lattice l) |
+  conv_w [L, 3, 3, C, C] | conv_b [L, C] |
   for each lattice: proj_w up [C, N_up] | proj_w down [C, N_dn] |
                     proj_b up [N_up] | proj_b down [N_dn]
 Each block is row-major.  Base orbitals are inputs, not parameters.
@@ -20,7 +21,8 @@ from .ansatz import log_psi, occupied_sites
 
 
 def pack(params) -> np.ndarray:
-    parts = [params.embed.ravel(), params.conv_w.ravel(), params.conv_b.ravel()]
+    emb = [params.embed.ravel()] if params.embed_site is None else [e.ravel() for e in params.embed_site]
+    parts = emb + [params.conv_w.ravel(), params.conv_b.ravel()]
     for pw, pb in zip(params.proj_w, params.proj_b):
         parts += [pw[0].ravel(), pw[1].ravel(), pb[0].ravel(), pb[1].ravel()]
     return np.concatenate(parts).astype(np.float64)
@@ -37,7 +39,10 @@ def unpack(theta: np.ndarray, like):
         off += n
         return a
 
-    p.embed = take(like.embed.shape)
+    if like.embed_site is None:
+        p.embed = take(like.embed.shape)
+    else:
+        p.embed_site = [take(e.shape) for e in like.embed_site]
     p.conv_w = take(like.conv_w.shape)
     p.conv_b = take(like.conv_b.shape)
     for li in range(len(like.proj_w)):
@@ -78,7 +83,10 @@ def _torch_log_psi(lat, theta, like, occ, lat_index: int, act: str):
         a = theta[off:off + n].reshape(shape)
         off += n
         return a
-    E = take((4, C))
+    if like.embed_site is None:
+        E = take((4, C))
+    else:
+        Es = [take(e.shape) for e in like.embed_site]
     K = take((L, 3, 3, C, C))
     b = take((L, C))
     proj = []
@@ -86,7 +94,12 @@ def _torch_log_psi(lat, theta, like, occ, lat_index: int, act: str):
         nu, nd = like.proj_w[li][0].shape[1], like.proj_w[li][1].shape[1]
         proj.append((take((C, nu)), take((C, nd)), take((nu,)), take((nd,))))
     assert off == theta.numel()
-    x = E[torch.from_numpy(np.asarray(occ, dtype=np.int64))].T.reshape(1, C, lat.Ly, lat.Lx)
+    o = torch.from_numpy(np.asarray(occ, dtype=np.int64))
+    if like.embed_site is None:
+        H0 = E[o]
+    else:
+        H0 = Es[lat_index][torch.arange(lat.N), o]            # [N, C]: site s, its occupation
+    x = H0.T.reshape(1, C, lat.Ly, lat.Lx)
     for l in range(L):
         # circular padding on periodic axes, zeros on open ones
         xp = F.pad(x, (1, 1, 0, 0), mode="circular") if lat.pbc_x else F.pad(x, (1, 1, 0, 0))

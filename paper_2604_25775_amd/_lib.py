@@ -32,7 +32,8 @@ class Lattice(ct.Structure):
 
 class Model(ct.Structure):
     _fields_ = [("n_conv", ct.c_int32), ("channels", ct.c_int32), ("act", ct.c_int32),
-                ("conv_prec", ct.c_int32), ("refresh_every", ct.c_int32)]
+                ("conv_prec", ct.c_int32), ("refresh_every", ct.c_int32),
+                ("ksize", ct.c_int32), ("n_mlp", ct.c_int32), ("per_site_embed", ct.c_int32)]
 
 
 class SvmcError(RuntimeError):
@@ -69,7 +70,7 @@ def load(path: str | None = None):
         "svmc_sweep": (i32, [vp, i32, u64, u64, vp, vp]),
         "svmc_refresh": (i32, [vp, vp]),
         "svmc_get_state": (i32, [vp, vp, vp, vp]),
-        "svmc_grad_logpsi": (i32, [vp, vp, vp, vp]),
+        "svmc_grad_logpsi": (i32, [vp, vp, vp, i32, vp]),
         "svmc_walker_flags": (i32, [vp, vp, vp]),
         "svmc_status_string": (ct.c_char_p, [i32]),
         "svmc_last_error": (ct.c_char_p, [vp]),

@@ -27,8 +27,13 @@ def _stream():
 
 def pack_params(params, lattices) -> np.ndarray:
     """Flat FP64 parameter vector in the library's layout:
-    embed | conv_w | conv_b | per lattice: W_up | W_dn | b_up | b_dn."""
-    parts = [np.asarray(params.embed, np.float64).ravel(),
+    embed | conv_w | conv_b | per lattice: W_up | W_dn | b_up | b_dn, where
+    embed is the shared [4, C] table or, when params.embed_site is set, the
+    per-site tables [N_l, 4, C] of every lattice in order."""
+    site = getattr(params, "embed_site", None)
+    emb = ([np.asarray(e, np.float64).ravel() for e in site] if site is not None
+           else [np.asarray(params.embed, np.float64).ravel()])
+    parts = emb + [
              np.asarray(params.conv_w, np.float64).ravel(),
              np.asarray(params.conv_b, np.float64).ravel()]
     for li, _ in enumerate(lattices):
@@ -43,7 +48,8 @@ class ScaleVMC:
     """One library context: lattices, network shape, parameters and walkers."""
 
     def __init__(self, lattices: Sequence, n_conv: int, channels: int, act: str = "tanh",
-                 conv_prec: str = "f64", refresh_every: int = 32, device: str = "cuda:0"):
+                 conv_prec: str = "f64", refresh_every: int = 32, device: str = "cuda:0",
+                 per_site_embed: bool = False, ksize: int = 3, n_mlp: int = 0):
         self.lib = _lib.load()
         self.device = torch.device(device)
         self.lattices = list(lattices)
@@ -51,7 +57,8 @@ class ScaleVMC:
         for k, l in enumerate(self.lattices):
             arr[k] = _lib.Lattice(l.Lx, l.Ly, int(l.pbc_x), int(l.pbc_y), float(l.t), float(l.tp),
                                   float(l.U), l.n_up, l.n_dn)
-        m = _lib.Model(n_conv, channels, ACT[act], PREC[conv_prec], refresh_every)
+        m = _lib.Model(n_conv, channels, ACT[act], PREC[conv_prec], refresh_every, ksize, n_mlp,
+                       int(bool(per_site_embed)))
         h = ct.c_void_p()
         with torch.cuda.device(self.device):
             st = self.lib.svmc_create(arr, len(self.lattices), ct.byref(m), ct.byref(h))
@@ -59,6 +66,9 @@ class ScaleVMC:
             raise _lib.SvmcError(st, "svmc_create")
         self.h = h
         self.n_conv, self.channels, self.conv_prec = n_conv, channels, conv_prec
+        # bumped by every call that changes parameters or configurations
+        # (LogPsi.backward checks that its forward's state is still held)
+        self.state_version = 0
 
     def close(self):
         if getattr(self, "h", None):
@@ -99,6 +109,7 @@ class ScaleVMC:
         self._theta = theta.contiguous()
         self._base = [b.to(self.device, torch.float64).contiguous() for b in base]
         arr = (ct.c_void_p * len(self._base))(*[b.data_ptr() for b in self._base])
+        self.state_version += 1
         self._check(self.lib.svmc_set_params(self.h, _ptr(self._theta), arr, _stream()), "set_params")
 
     def set_params_from(self, params):
@@ -114,6 +125,7 @@ class ScaleVMC:
         occ = occ.to(self.device, torch.int8).contiguous()
         self._occ_in = occ
         c = (ct.c_int64 * len(counts))(*[int(x) for x in counts])
+        self.state_version += 1
         self._check(self.lib.svmc_load_walkers(self.h, c, _ptr(occ), _stream()), "load_walkers")
 
     def log_psi(self):
@@ -142,6 +154,7 @@ class ScaleVMC:
     def sweep(self, n_sweeps: int, seed: int, step0: int, n_accept: torch.Tensor | None = None):
         if n_accept is None:
             n_accept = torch.zeros(self.num_walkers, dtype=torch.int64, device=self.device)
+        self.state_version += 1
         self._check(self.lib.svmc_sweep(self.h, int(n_sweeps), ct.c_uint64(seed), ct.c_uint64(step0),
                                         _ptr(n_accept), _stream()), "sweep")
         return n_accept
@@ -149,6 +162,7 @@ class ScaleVMC:
     def sweep_async(self, n_sweeps: int, seed: int, step0: torch.Tensor, n_accept: torch.Tensor):
         """Graph-capturable sweep (svmc_sweep_async): step0 is a device uint64
         scalar read at run time (torch.int64 tensor of one element)."""
+        self.state_version += 1
         self._check(self.lib.svmc_sweep_async(self.h, int(n_sweeps), ct.c_uint64(seed), _ptr(step0),
                                               _ptr(n_accept), _stream()), "sweep_async")
         return n_accept
@@ -163,13 +177,17 @@ class ScaleVMC:
         self._check(self.lib.svmc_get_state(self.h, _ptr(occ), _ptr(pos), _stream()), "get_state")
         return occ, pos
 
-    def grad_logpsi(self, vjp: torch.Tensor | None = None):
+    def grad_logpsi(self, vjp: torch.Tensor | None = None, out_prec: str = "f64"):
+        """Per-walker Jacobian [W, n_params] (vjp None) or the VJP [n_params],
+        as float64 or float32 (out_prec "f64" | "f32")."""
+        dt = {"f64": torch.float64, "f32": torch.float32}[out_prec]
         if vjp is None:
-            out = torch.empty((self.num_walkers, self.num_params), dtype=torch.float64, device=self.device)
+            out = torch.empty((self.num_walkers, self.num_params), dtype=dt, device=self.device)
         else:
             vjp = vjp.to(self.device, torch.float64).contiguous()
-            out = torch.empty(self.num_params, dtype=torch.float64, device=self.device)
-        self._check(self.lib.svmc_grad_logpsi(self.h, _ptr(vjp), _ptr(out), _stream()), "grad_logpsi")
+            out = torch.empty(self.num_params, dtype=dt, device=self.device)
+        self._check(self.lib.svmc_grad_logpsi(self.h, _ptr(vjp), _ptr(out), PREC[out_prec], _stream()),
+                    "grad_logpsi")
         return out
 
     def flags(self):
@@ -208,7 +226,10 @@ class LogPsi(torch.autograd.Function):
     function of the flat parameter vector theta (layout of pack_params).
     Forward uploads theta and rebuilds the caches at the walkers' current
     configurations; backward asks the library for sum_w g[w] d log|psi_w| /
-    d theta (svmc_grad_logpsi with VJP weights g).
+    d theta (svmc_grad_logpsi with VJP weights g).  The gradient is taken at
+    the parameters and configurations the ScaleVMC holds, so backward raises
+    if they changed after this forward (set_params, load, sweep, or another
+    forward).
 
         la = LogPsi.apply(theta, vmc)
     """
@@ -218,8 +239,13 @@ class LogPsi(torch.autograd.Function):
         vmc.update_params(theta)
         _, la = vmc.log_psi()
         ctx.vmc = vmc
+        ctx.version = vmc.state_version
         return la
 
     @staticmethod
     def backward(ctx, g):
+        if ctx.vmc.state_version != ctx.version:
+            raise RuntimeError("LogPsi.backward: the ScaleVMC's parameters or walkers changed after this "
+                               "forward (sweep, set_params, load or another LogPsi forward); the gradient "
+                               "would belong to another state")
         return ctx.vmc.grad_logpsi(g.contiguous()).to(g.dtype), None

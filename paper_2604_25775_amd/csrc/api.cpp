@@ -83,12 +83,14 @@ struct svmc_ctx {
   std::vector<svmc_lattice> lats;
   svmc_model model{};
   int prec = 0, L = 0, C = 0;
+  long long emb_len = 0;   // length of the embedding block of theta
   std::string err;
   int64_t nparams = 0;
   bool have_params = false, have_walkers = false;
   bool prepared = false;   // G/P match the current walkers
   bool dets_fresh = false; // rows M, inverses and log|psi| rebuilt since the last move
   int eloc_slices = 8;     // workgroups per walker in the low-rank E_loc launch
+  int dev = 0;             // device current at svmc_create
   // parameters
   DevBuf Bpack, embed, bias;
   std::vector<DevBuf> base, W, b;    // per lattice
@@ -100,7 +102,7 @@ struct svmc_ctx {
   DevBuf ratio_tmp, eloc_part;
   DevBuf sw_stage, sw_list, sw_count;  // sweep: accepted-move staging, accepted walkers, their counts
   DevBuf gK, gB, gE;                 // conv weights, conv bias, embedding (FP64, forward's rounding)
-  DevBuf g_rows, g_dH, g_hs, g_dzs;  // gradient scratch
+  DevBuf g_rows, g_dH, g_hs, g_dzs, g_vjp;  // gradient scratch
   std::vector<int64_t> counts;
 
   svmc_status fail(svmc_status s, const std::string& m) {
@@ -200,15 +202,23 @@ svmc_status svmc_create(const svmc_lattice* lats, int32_t n_lats, const svmc_mod
   if (m->act != SVMC_ACT_TANH && m->act != SVMC_ACT_SILU) return SVMC_ERR_INVALID_ARG;
   if (m->conv_prec < 0 || m->conv_prec > 4) return SVMC_ERR_INVALID_ARG;
   if (m->refresh_every < 1) return SVMC_ERR_INVALID_ARG;
+  if (m->per_site_embed != 0 && m->per_site_embed != 1) return SVMC_ERR_INVALID_ARG;
+  if (m->ksize != 3 || m->n_mlp != 0) return SVMC_ERR_UNSUPPORTED;
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return SVMC_ERR_HIP;
   svmc_ctx* c = new svmc_ctx();
+  c->dev = dev;
   c->lats.assign(lats, lats + n_lats);
   c->model = *m;
   c->prec = m->conv_prec;
   c->L = m->n_conv;
   c->C = m->channels;
-  int64_t np = 4LL * c->C + 9LL * c->L * c->C * c->C + (int64_t)c->L * c->C;
+  c->emb_len = 4LL * c->C;
+  if (m->per_site_embed) {
+    c->emb_len = 0;
+    for (auto& l : c->lats) c->emb_len += 4LL * l.Lx * l.Ly * c->C;
+  }
+  int64_t np = c->emb_len + 9LL * c->L * c->C * c->C + (int64_t)c->L * c->C;
   for (auto& l : c->lats) np += (int64_t)c->C * (l.n_up + l.n_dn) + l.n_up + l.n_dn;
   c->nparams = np;
   *out = c;
@@ -241,7 +251,8 @@ svmc_status svmc_set_params(svmc_ctx* ctx, const double* theta, const double* co
   for (double v : th)
     if (!std::isfinite(v)) return ctx->fail(SVMC_ERR_INVALID_ARG, "non-finite parameter");
   const double* E = th.data();
-  const double* K = E + 4 * C;
+  const long long EL = ctx->emb_len;
+  const double* K = E + EL;
   const double* Bc = K + 9LL * L * C * C;
   const double* rest = Bc + (long long)L * C;
   // values the device uses: rnd for the embedding and conv bias (feature
@@ -263,8 +274,8 @@ svmc_status svmc_set_params(svmc_ctx* ctx, const double* theta, const double* co
   };
   // embedding and conv bias in the feature type
   const int tfb = ctx->tf_bytes();
-  std::vector<char> eb(4 * C * tfb), bb((size_t)L * C * tfb);
-  for (int k = 0; k < 4 * C; ++k) {
+  std::vector<char> eb((size_t)EL * tfb), bb((size_t)L * C * tfb);
+  for (long long k = 0; k < EL; ++k) {
     if (tfb == 8) ((double*)eb.data())[k] = E[k];
     else ((float*)eb.data())[k] = (float)rnd_e(E[k]);
   }
@@ -298,7 +309,7 @@ svmc_status svmc_set_params(svmc_ctx* ctx, const double* theta, const double* co
             else ((uint16_t*)bp.data())[idx] = f32_to_bf16_rne((float)v);
           }
   // FP64 copies of what the forward uses, for the backward
-  std::vector<double> gk(9ULL * L * C * C), gbias((size_t)L * C), ge(4ULL * C);
+  std::vector<double> gk(9ULL * L * C * C), gbias((size_t)L * C), ge((size_t)EL);
   for (size_t k = 0; k < gk.size(); ++k) gk[k] = rnd_w(K[k]);
   for (size_t k = 0; k < gbias.size(); ++k) gbias[k] = rnd(Bc[k]);
   for (size_t k = 0; k < ge.size(); ++k) ge[k] = rnd_e(E[k]);
@@ -396,7 +407,8 @@ svmc_status svmc_load_walkers(svmc_ctx* ctx, const int64_t* counts, const int8_t
   const int L = ctx->L, C = ctx->C, tfb = ctx->tf_bytes();
   std::vector<LatDev> d(nl);
   long long w0 = 0, o_occ = 0, o_lab = 0, o_pos = 0, o_feat = 0, o_inv = 0, o_m = 0, o_pt = 0;
-  long long poff = 4LL * C + 9LL * L * C * C + (long long)L * C;
+  long long poff = ctx->emb_len + 9LL * L * C * C + (long long)L * C;
+  long long emb_off = 0;
   size_t h0max = 0;
   for (size_t l = 0; l < nl; ++l) {
     const svmc_lattice& s = ctx->lats[l];
@@ -421,6 +433,9 @@ svmc_status svmc_load_walkers(svmc_ctx* ctx, const int64_t* counts, const int8_t
     x.b = ctx->b[l].as<double>();
     x.poff = poff;
     poff += (long long)C * (s.n_up + s.n_dn) + s.n_up + s.n_dn;
+    x.emb_off = ctx->model.per_site_embed ? emb_off : 0;
+    x.emb_ss = ctx->model.per_site_embed ? 4 * C : 0;
+    emb_off += 4LL * x.N * C;
     const long long nw = counts[l], N = x.N, nm = x.nmax;
     w0 += nw;
     o_occ += nw * N;
@@ -677,10 +692,14 @@ svmc_status svmc_get_state(svmc_ctx* ctx, int8_t* occ, int16_t* pos, hipStream_t
   return SVMC_OK;
 }
 
-svmc_status svmc_grad_logpsi(svmc_ctx* ctx, const double* vjp_w, double* out, hipStream_t st) {
+svmc_status svmc_grad_logpsi(svmc_ctx* ctx, const double* vjp_w, void* out_v, svmc_prec out_prec,
+                             hipStream_t st) {
   if (!ctx) return SVMC_ERR_INVALID_ARG;
   if (!ctx->have_walkers) return ctx->fail(SVMC_ERR_STATE, "no walkers loaded");
-  if (!out) return ctx->fail(SVMC_ERR_INVALID_ARG, "out is null");
+  if (!out_v) return ctx->fail(SVMC_ERR_INVALID_ARG, "out is null");
+  if (out_prec != SVMC_FP64 && out_prec != SVMC_FP32)
+    return ctx->fail(SVMC_ERR_INVALID_ARG, "out_prec must be SVMC_FP64 or SVMC_FP32");
+  const bool f32 = out_prec == SVMC_FP32;
   svmc_status s;
   // fresh inverses (rows, Phi^-1) and P = W Phi^-1 of the current walkers
   if (!ctx->dets_fresh && (s = rebuild_dets(ctx, st))) return s;
@@ -704,14 +723,18 @@ svmc_status svmc_grad_logpsi(svmc_ctx* ctx, const double* vjp_w, double* out, hi
   ga.B = ctx->gB.as<double>();
   ga.E = ctx->gE.as<double>();
   ga.nparams = np;
-  ga.off_convw = 4LL * ctx->C;
+  ga.off_convw = ctx->emb_len;
   ga.off_convb = ga.off_convw + 9LL * ctx->L * ctx->C * ctx->C;
   ga.ncmax = ncmax;
   ga.nsmax = nsmax;
   if ((s = ctx->hip(ctx->g_dH.ensure((size_t)chunk * ncmax * 8), "alloc gradient scratch"))) return s;
   if ((s = ctx->hip(ctx->g_dzs.ensure((size_t)chunk * ncmax * 8), "alloc gradient scratch"))) return s;
   if (!ga.lds && (s = ctx->hip(ctx->g_hs.ensure((size_t)chunk * ncmax * 8), "alloc gradient scratch"))) return s;
-  if (!jac && (s = ctx->hip(ctx->g_rows.ensure((size_t)chunk * np * 8), "alloc gradient rows"))) return s;
+  // rows are formed in FP64: in the caller's buffer for an FP64 Jacobian, else
+  // in scratch (then summed for the VJP, or rounded to FP32)
+  const bool direct = jac && !f32;
+  if (!direct && (s = ctx->hip(ctx->g_rows.ensure((size_t)chunk * np * 8), "alloc gradient rows"))) return s;
+  if (!jac && f32 && (s = ctx->hip(ctx->g_vjp.ensure((size_t)np * 8), "alloc gradient sum"))) return s;
   ga.dH = ctx->g_dH.as<double>();
   ga.hs = ga.lds ? nullptr : ctx->g_hs.as<double>();
   ga.dzs = ctx->g_dzs.as<double>();
@@ -719,14 +742,18 @@ svmc_status svmc_grad_logpsi(svmc_ctx* ctx, const double* vjp_w, double* out, hi
   for (long long b0 = 0; b0 < W; b0 += chunk) {
     const long long cnt = std::min(chunk, W - b0);
     ga.w_begin = b0;
-    ga.rows = jac ? out + b0 * np : ctx->g_rows.as<double>();
+    ga.rows = direct ? (double*)out_v + b0 * np : ctx->g_rows.as<double>();
     if ((s = ctx->hip(launch_grad(ctx->prec, ctx->lats_dev.as<LatDev>(), (int)ctx->ld.size(), cnt, bf, ga, st),
                       "gradient")))
       return s;
-    if (!jac && (s = ctx->hip(launch_grad_reduce(ga.rows, cnt, np, vjp_w + b0, bf.flags + b0, out, b0 == 0, st),
+    if (jac && f32 && (s = ctx->hip(launch_to_f32(ga.rows, (float*)out_v + b0 * np, cnt * np, st), "FP32 rows")))
+      return s;
+    double* sum = f32 ? ctx->g_vjp.as<double>() : (double*)out_v;
+    if (!jac && (s = ctx->hip(launch_grad_reduce(ga.rows, cnt, np, vjp_w + b0, bf.flags + b0, sum, b0 == 0, st),
                               "gradient reduction")))
       return s;
   }
+  if (!jac && f32) return ctx->hip(launch_to_f32(ctx->g_vjp.as<double>(), (float*)out_v, np, st), "FP32 sum");
   return SVMC_OK;
 }
 

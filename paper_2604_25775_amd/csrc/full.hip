@@ -140,7 +140,8 @@ __global__ __launch_bounds__(256) void k_full_ratio(ModelDev md, LatDev lt, Bufs
   __syncthreads();
   // H'_0
   const Tf* E = (const Tf*)md.embed;
-  for (int e = tid; e < N * C; e += 256) grid[(e / C) * SP + (e % C)] = E[occ_s[e / C] * C + (e % C)];
+  for (int e = tid; e < N * C; e += 256)
+    grid[(e / C) * SP + (e % C)] = E[lt.emb_off + (long long)(e / C) * lt.emb_ss + occ_s[e / C] * C + (e % C)];
   __syncthreads();
   const int T = (N + 15) >> 4;
   for (int l = 0; l < md.L; ++l) {

@@ -9,7 +9,8 @@
 //     dz = dH_l * act'(z_l)                 (z_l recomputed from the cached H_{l-1})
 //     dK_l[t][ci][co] = sum_s dz[s][co] H_{l-1}[s + off_t][ci],   db_l = sum_s dz[s]
 //     dH_{l-1}[s] = dH_l[s] + sum_t K_l[t] dz[s - off_t]          (transposed conv)
-// Embedding: dE[o] = sum over sites with occupation o of dH_0.
+// Embedding: dE[o] = sum over sites with occupation o of dH_0 (one shared
+// table), or dE_s[n_s] = dH_0[s] (per-site tables).
 //
 // All arithmetic in FP64 on the cached features (FP32 or FP64); the conv
 // weights are the values the forward uses (rounded to its precision).  With
@@ -150,7 +151,8 @@ __global__ __launch_bounds__(256) void k_grad(const LatDev* __restrict__ lats, i
     const double* Kl = ga.K + (long long)(l - 1) * 9 * C * C;
     const double* bl = ga.B + (long long)(l - 1) * C;
     for (int e = tid; e < NC; e += NTH)
-      hp[e] = l >= 2 ? (double)feat[(long long)(l - 2) * NC + e] : ga.E[occ[e / C] * C + e % C];
+      hp[e] = l >= 2 ? (double)feat[(long long)(l - 2) * NC + e]
+                     : ga.E[lt.emb_off + (long long)(e / C) * lt.emb_ss + occ[e / C] * C + e % C];
     __syncthreads();
     // The three products of the layer on the FP64 matrix cores (16 x 16 x 4
     // tiles; A[i][k] from lane i + 16 k, B[k][j] from lane j + 16 k, result
@@ -273,7 +275,13 @@ __global__ __launch_bounds__(256) void k_grad(const LatDev* __restrict__ lats, i
   }
 
   // ---- embedding
-  {
+  if (lt.emb_ss) {
+    // per-site tables: dE_s[o][c] = dH_0[s][c] for the site's own occupation o
+    for (int e = tid; e < NC; e += NTH) {
+      const int s = e / C, c = e - s * C;
+      row[lt.emb_off + (long long)s * lt.emb_ss + occ[s] * C + c] = dH[e];
+    }
+  } else {
     // dE[o][c] = sum over sites with occupation o of dH_0[s][c]: NTH / C
     // interleaved pieces of the sites per channel, four bins each
     const int parts = NTH / C, c = tid % C, part = tid / C;
@@ -307,6 +315,18 @@ __global__ void k_grad_reduce(const double* __restrict__ rows, long long cnt, lo
   for (long long w = 0; w < cnt; ++w)
     if (!(flags[w] & (1 | 2 | 8))) acc = fma(vjp[w], rows[w * nparams + p], acc);
   out[p] = acc;
+}
+
+__global__ void k_to_f32(const double* __restrict__ src, float* __restrict__ dst, long long n) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    dst[i] = (float)src[i];
+}
+
+hipError_t launch_to_f32(const double* src, float* dst, long long n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  const long long nb = (n + 255) / 256 < 8192 ? (n + 255) / 256 : 8192;
+  hipLaunchKernelGGL(k_to_f32, dim3((unsigned)nb), dim3(256), 0, st, src, dst, n);
+  return hipGetLastError();
 }
 
 size_t grad_tab_bytes(long long nsmax) { return (size_t)((9 * nsmax * 2 + 15) & ~15LL); }

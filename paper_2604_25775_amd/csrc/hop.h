@@ -372,10 +372,11 @@ SVMC_DEV void hop_features(const ModelDev& md, const LatDev& lt, const HopGeom& 
       int o = occ_s[s];
       if (s == h.i) o -= bit;
       if (s == h.j) o += bit;
+      const Tf* Es = E + lt.emb_off + (long long)s * lt.emb_ss + o * C + cv * V;
       if constexpr (PL)
-        grid_put4<P, C>(grid, site, cv * V, *reinterpret_cast<const float4*>(E + o * C + cv * V));
+        grid_put4<P, C>(grid, site, cv * V, *reinterpret_cast<const float4*>(Es));
       else
-        *reinterpret_cast<float4*>(grid + site * SP + cv * V) = *reinterpret_cast<const float4*>(E + o * C + cv * V);
+        *reinterpret_cast<float4*>(grid + site * SP + cv * V) = *reinterpret_cast<const float4*>(Es);
     }
   }
   __syncthreads();

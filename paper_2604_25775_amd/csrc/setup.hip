@@ -1,6 +1,7 @@
 // Walker set-up and FP64 refresh kernels:
 //   labels      occupation -> electron labels (ascending sites) and site->label
-//   embed       H_0 = E[n_s]                     (Sec. II.B, embedding layer)
+//   embed       H_0 = E_s[n_s]                   (Sec. II.B, embedding layer; one
+//                                                table for all sites or one per site)
 //   forward     H_l = H_{l-1} + act(conv(H_{l-1}))  one launch per layer
 //               (Sec. II.B, residual conv equation)
 //   rows        M_s[x] = base_s[x] + H_L[x] W_s + b_s for every site
@@ -27,7 +28,8 @@ __global__ void k_embed(LatDev lt, Bufs bf, ModelDev md, Tf* __restrict__ h0) {
     const long long site = e / C;
     const int c = (int)(e % C);
     const int o = bf.occ[lt.occ_off + site] & 3;
-    h0[e] = E[o * C + c];
+    const int s = (int)(site % lt.N);
+    h0[e] = E[lt.emb_off + (long long)s * lt.emb_ss + o * C + c];
   }
 }
 

@@ -58,6 +58,10 @@ struct LatDev {
   const double* W;     // [2][C][nmax]
   const double* b;     // [2][nmax]
   long long poff;      // offset of this lattice's W_up in the flat parameter vector
+  // embedding of site s with occupation o, channel c: embed[emb_off + s * emb_ss + o * C + c]
+  // (emb_ss = 0 for one table shared by all sites, 4 C for per-site tables)
+  long long emb_off;
+  int emb_ss;
 };
 
 // Device buffers of one context (walker-indexed arrays, see LatDev offsets).
@@ -81,7 +85,7 @@ struct Bufs {
 struct ModelDev {
   int L, C, act;
   const void* Bpack;
-  const void* embed;   // Tf [4][C]
+  const void* embed;   // Tf [4][C], or per lattice [N][4][C] (LatDev::emb_off)
   const void* bias;    // Tf [L][C]
 };
 

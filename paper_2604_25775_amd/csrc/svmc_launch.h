@@ -109,6 +109,8 @@ hipError_t launch_grad(int prec, const LatDev* lats_dev, int nlats, long long cn
                        const GradArgs& ga, hipStream_t st);
 hipError_t launch_grad_reduce(const double* rows, long long cnt, long long nparams, const double* vjp,
                               const int32_t* flags, double* out, int first, hipStream_t st);
+// dst[i] = (float)src[i], i < n (round to nearest)
+hipError_t launch_to_f32(const double* src, float* dst, long long n, hipStream_t st);
 
 // full.hip: full-recompute comparison path
 hipError_t launch_eloc_full(int prec, const ModelDev& md, const LatDev& lt, const Bufs& bf, const ElocOut& out,

@@ -1,5 +1,5 @@
 """Host logic of bench.py's HBM-traffic record: the counter record under
-profiles/ is used only for the sources it was taken on, and its scaling by
+profiles/ is used only for the sources and launch shape it was taken on, and its scaling by
 the copy calibration is the one documented there."""
 import json
 import os
@@ -14,7 +14,8 @@ import bench  # noqa: E402
 
 
 def _record(tmp_path, sha, **over):
-    r = {"kernel": "k_eloc_lowrank", "workload": "c3", "walkers": 8192, "prec": "f16x2", "src_sha1": sha,
+    r = {"kernel": "k_eloc_lowrank", "workload": "c3", "walkers": 8192, "prec": "f16x2", "slices": 24,
+         "src_sha1": sha,
          "fetch_kib": 1000.0, "write_kib": 300.0, "copy_fetch_kib": 524288.0, "copy_write_kib": 1048576.0}
     r.update(over)
     prof = tmp_path / "profiles"
@@ -27,7 +28,7 @@ def test_record_scaled_by_copy_calibration(tmp_path, monkeypatch):
     root = _record(tmp_path, "a" * 40)
     monkeypatch.setattr(bench, "ROOT", str(root))
     monkeypatch.setattr(bench, "kernel_src_sha1", lambda: "a" * 40)
-    tr = bench.traffic_record("c3", 8192, "f16x2")
+    tr = bench.traffic_record("c3", 8192, "f16x2", 24)
     assert tr is not None
     # FETCH_SIZE read 512 MiB for a 1 GiB copy: factor 2; WRITE_SIZE exact
     assert tr["fetch_bytes"] == pytest.approx(1000.0 * 1024 * 2.0)
@@ -39,11 +40,13 @@ def test_record_ignored_for_other_sources_or_workloads(tmp_path, monkeypatch):
     root = _record(tmp_path, "0" * 40)
     monkeypatch.setattr(bench, "ROOT", str(root))
     monkeypatch.setattr(bench, "kernel_src_sha1", lambda: "1" * 40)
-    assert bench.traffic_record("c3", 8192, "f16x2") is None
+    assert bench.traffic_record("c3", 8192, "f16x2", 24) is None
     monkeypatch.setattr(bench, "kernel_src_sha1", lambda: "0" * 40)
-    assert bench.traffic_record("c3", 8192, "f16x2") is not None
-    assert bench.traffic_record("c3", 4096, "f16x2") is None
-    assert bench.traffic_record("c3", 8192, "bf16x3") is None
+    assert bench.traffic_record("c3", 8192, "f16x2", 24) is not None
+    assert bench.traffic_record("c3", 4096, "f16x2", 24) is None
+    assert bench.traffic_record("c3", 8192, "bf16x3", 24) is None
+    # a record taken at another launch shape does not describe this launch
+    assert bench.traffic_record("c3", 8192, "f16x2", 32) is None
 
 
 def test_source_hash_covers_every_source_file():

@@ -1,0 +1,90 @@
+"""Per-walker failure flags (svmc_walker_flags) forced through the inputs.
+
+* SINGULAR: a lattice whose spin-up orbital k is identically zero (its base
+  column, projection column and bias entry are 0), so det Phi_up = 0 for
+  every configuration: its walkers load flagged, with log|psi| = -inf and
+  sign 0, a NaN local energy, no Metropolis move and a NaN gradient row left
+  out of the VJP; walkers of the other lattice in the same batch are
+  unaffected (1e-10 against the oracle).
+* DRIFT: two spin-up orbitals that differ by 1e-11 at every site (Phi
+  conditioned near 1e11), so G = M Phi^-1 misses its exact unit rows at the
+  occupied sites by far more than 1e-8: a refresh over current G flags the
+  walkers, walkers of a well-conditioned lattice in the batch stay clean.
+"""
+import numpy as np
+import pytest
+
+import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+from gpu_util import say  # noqa: E402
+
+LATS = [wl.Lattice(4, 4, 1, 1, 1.0, 0.0, 4.0, 5, 5), wl.Lattice(5, 4, 1, 0, 1.0, 0.0, 6.0, 6, 5)]
+COUNTS = [3, 4]
+
+
+def make_ctx(params, model):
+    from paper_2604_25775_amd.api import ScaleVMC
+    occs = [wl.random_occupations(l, n, seed=11 + k) for k, (l, n) in enumerate(zip(LATS, COUNTS))]
+    ctx = ScaleVMC(LATS, model.n_conv, model.channels, model.act, model.conv_prec, model.refresh_every)
+    ctx.set_params_from(params)
+    ctx.load(COUNTS, np.concatenate([o.reshape(-1) for o in occs]).astype(np.int8))
+    torch.cuda.synchronize()
+    return ctx, occs
+
+
+def test_singular_orbital_lattice_flagged():
+    model = wl.Model(2, 8, "tanh", "f64")
+    p = wl.random_params(LATS, model, seed=4, backflow=0.5)
+    k = 2
+    p.base[0][0][:, k] = 0.0
+    p.proj_w[0][0][:, k] = 0.0
+    p.proj_b[0][0][k] = 0.0
+    say("[flags] singular spin-up block on lattice 0")
+    ctx, occs = make_ctx(p, model)
+    f = ctx.flags().cpu().numpy()
+    assert (f[:3] & 1).all() and not f[3:].any(), f
+    s, la = (t.cpu().numpy() for t in ctx.log_psi())
+    assert (s[:3] == 0.0).all() and np.isneginf(la[:3]).all()
+    e = ctx.local_energy().cpu().numpy()
+    assert np.isnan(e[:3]).all() and np.isfinite(e[3:]).all()
+    # the healthy lattice's walkers against the oracle (walker offset 3)
+    from oracle.energy import local_energy
+    for kk, o in enumerate(occs[1]):
+        ref = local_energy(LATS[1], p, o, 1, model.act)
+        assert abs(e[3 + kk] - ref) <= 1e-10 * max(1.0, abs(ref))
+    J = ctx.grad_logpsi().cpu().numpy()
+    assert np.isnan(J[:3]).all() and np.isfinite(J[3:]).all()
+    v = torch.ones(sum(COUNTS), dtype=torch.float64, device="cuda")
+    g = ctx.grad_logpsi(v).cpu().numpy()
+    assert np.allclose(g, J[3:].sum(0), rtol=1e-12, atol=1e-12)
+    occ0, _ = ctx.state()
+    n_acc = ctx.sweep(2, 9, 0).cpu().numpy()
+    occ1, _ = ctx.state()
+    N0 = LATS[0].N
+    assert (n_acc[:3] == 0).all() and n_acc[3:].sum() > 0
+    assert torch.equal(occ0[:3 * N0], occ1[:3 * N0])
+    assert (ctx.flags().cpu().numpy()[:3] & 1).all()
+
+
+def test_nearly_dependent_orbitals_flag_drift():
+    model = wl.Model(2, 8, "tanh", "f64", 1000)
+    p = wl.random_params(LATS, model, seed=6, backflow=0.5)
+    rng = np.random.default_rng(3)
+    N = LATS[0].N
+    p.base[0][0][:, 1] = p.base[0][0][:, 0] + 1e-11 * rng.standard_normal(N)
+    p.proj_w[0][0][:, 1] = p.proj_w[0][0][:, 0]
+    p.proj_b[0][0][1] = p.proj_b[0][0][0]
+    say("[flags] nearly dependent spin-up orbitals on lattice 0")
+    ctx, occs = make_ctx(p, model)
+    f = ctx.flags().cpu().numpy()
+    assert not (f & (1 | 2 | 8)).any(), f
+    ctx.sweep(2, 13, 0)
+    ctx.refresh()
+    f = ctx.flags().cpu().numpy()
+    say(f"  flags after refresh {f.tolist()}")
+    assert (f[:3] & 4).any(), f
+    assert not (f[3:] & 4).any(), f

@@ -53,6 +53,7 @@ class Model:
     act: str = "tanh"
     conv_prec: str = "f64"          # f64 | f32 | bf16 | bf16x3 | f16x2
     refresh_every: int = 32
+    per_site_embed: bool = False    # one embedding table per site (else shared)
 
 
 @dataclass(frozen=True)
@@ -113,6 +114,8 @@ class Params:
     """Network parameters in FP64.
 
     embed  [4, C]            state -> feature (state = n_up + 2 n_dn)
+    embed_site  None, or per lattice [N, 4, C]: one table per site (used
+                             instead of embed)
     conv_w [L, 3, 3, C, C]   (ky, kx, c_in, c_out); tap (ky, kx) reads the
                              neighbour at offset (kx-1, ky-1)
     conv_b [L, C]
@@ -126,12 +129,14 @@ class Params:
     proj_w: List[List[np.ndarray]]
     proj_b: List[List[np.ndarray]]
     base: List[List[np.ndarray]] = field(default_factory=list)
+    embed_site: List[np.ndarray] | None = None
 
     def copy(self) -> "Params":
         return Params(self.embed.copy(), self.conv_w.copy(), self.conv_b.copy(),
                       [[a.copy() for a in p] for p in self.proj_w],
                       [[a.copy() for a in p] for p in self.proj_b],
-                      [[a.copy() for a in p] for p in self.base])
+                      [[a.copy() for a in p] for p in self.base],
+                      None if self.embed_site is None else [e.copy() for e in self.embed_site])
 
 
 def _axis_modes(L: int, periodic: bool):
@@ -190,7 +195,9 @@ def random_params(lats: Sequence[Lattice], model: Model, seed: int = 0,
                   backflow: float = 0.1) -> Params:
     """Seeded parameters.  Conv kernels and biases ~ N(0, 0.05^2), embedding
     ~ N(0, 1); the projection is scaled so that the backflow term is about
-    ``backflow`` times the magnitude of a base-orbital entry."""
+    ``backflow`` times the magnitude of a base-orbital entry.  With
+    model.per_site_embed, per-site embedding tables ~ N(0, 1) are drawn after
+    everything else (the other parameters are the same as without)."""
     rng = np.random.Generator(np.random.PCG64(seed))
     C, L = model.channels, model.n_conv
     embed = rng.standard_normal((4, C))
@@ -208,7 +215,10 @@ def random_params(lats: Sequence[Lattice], model: Model, seed: int = 0,
         proj_w.append(pw)
         proj_b.append(pb)
         base.append(bs)
-    return Params(embed, conv_w, conv_b, proj_w, proj_b, base)
+    site = None
+    if model.per_site_embed:
+        site = [rng.standard_normal((lat.N, 4, C)) for lat in lats]
+    return Params(embed, conv_w, conv_b, proj_w, proj_b, base, site)
 
 
 def quantise_params(p: Params, prec: str) -> Params:
@@ -223,12 +233,16 @@ def quantise_params(p: Params, prec: str) -> Params:
     for name in ("embed", "conv_w", "conv_b"):
         a = torch.from_numpy(getattr(q, name)).to(dt).to(torch.float64).numpy()
         setattr(q, name, a)
+    if q.embed_site is not None:
+        q.embed_site = [torch.from_numpy(e).to(dt).to(torch.float64).numpy() for e in q.embed_site]
     if prec == "f16x2":
         # the BF16 conv weights carried in FP16 (exact in FP16's normal range),
         # the embedding as an FP16 pair, FP32 bias
         w16 = torch.from_numpy(p.conv_w).to(torch.bfloat16).to(torch.float16)
         q.conv_w = w16.to(torch.float64).numpy()
         q.embed = f16_pair(q.embed)
+        if q.embed_site is not None:
+            q.embed_site = [f16_pair(e) for e in q.embed_site]
     return q
 
 
