@@ -176,6 +176,21 @@ svmc_status svmc_local_energy(svmc_ctx* ctx, svmc_path path, double* eloc,
                               int32_t* n_hops, int32_t* hop_code, double* ratio,
                               hipStream_t stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * local energies as svmc_local_energy(ctx, SVMC_PATH_LOWRANK, eloc, NULL,
+ * NULL, NULL, stream), bit for bit, with the per-slice partial sums in a
+ * fixed array of 2^20 doubles (8 MiB) per device that the library holds
+ * until the process ends, instead of a context buffer.  The call allocates
+ * nothing (no hipMalloc, no library allocation); like svmc_local_energy it
+ * first rebuilds G and P from the cached inverses if walkers changed.
+ * eloc: device [W] FP64.  The context's device must be current.  Every call
+ * on one device shares that array: calls that overlap on one device (other
+ * streams, other contexts) race and must be ordered by the caller.
+ * Errors: SVMC_ERR_UNSUPPORTED when walkers x slices per walker (svmc_tune)
+ * exceeds 2^20; SVMC_ERR_STATE without walkers. */
+svmc_status svmc_local_energy_noalloc(svmc_ctx* ctx, double* eloc, hipStream_t stream);
+
 /* Metropolis sampling of |psi|^2 (Sec. II.A), n_sweeps sweeps of N proposals
  * per walker.  Proposal k of walker w draws one Philox4x64-10 block with key
  * (seed, 0) and counter (w, step0 + k, 0, 0): electron e = mulhi(w0, n_up +

@@ -21,6 +21,7 @@ EXPORTS = [
     "svmc_local_energy",
     "svmc_sweep", "svmc_refresh", "svmc_get_state", "svmc_grad_logpsi", "svmc_walker_flags",
     "svmc_status_string", "svmc_last_error", "svmc_tune", "svmc_sweep_async",
+    "svmc_local_energy_noalloc",
 ]
 
 
@@ -76,6 +77,7 @@ def load(path: str | None = None):
         "svmc_last_error": (ct.c_char_p, [vp]),
         "svmc_tune": (i32, [vp, ct.c_char_p, ct.POINTER(i32), vp]),
         "svmc_sweep_async": (i32, [vp, i32, u64, vp, vp, vp]),
+        "svmc_local_energy_noalloc": (i32, [vp, vp, vp]),
     }
     for name, (res, args) in proto.items():
         f = getattr(lib, name)

@@ -151,6 +151,13 @@ class ScaleVMC:
                                                _ptr(rat), _stream()), "local_energy")
         return (eloc, nh, code, rat) if ratios else eloc
 
+    def local_energy_noalloc(self, out: torch.Tensor):
+        """Low-rank local energies into `out` (float64 [W]) through the
+        allocation-free entry point (svmc_local_energy_noalloc)."""
+        assert out.dtype == torch.float64 and out.is_cuda and out.numel() >= self.num_walkers
+        self._check(self.lib.svmc_local_energy_noalloc(self.h, _ptr(out), _stream()), "local_energy_noalloc")
+        return out
+
     def sweep(self, n_sweeps: int, seed: int, step0: int, n_accept: torch.Tensor | None = None):
         if n_accept is None:
             n_accept = torch.zeros(self.num_walkers, dtype=torch.int64, device=self.device)

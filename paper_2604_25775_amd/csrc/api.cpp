@@ -206,6 +206,8 @@ svmc_status svmc_create(const svmc_lattice* lats, int32_t n_lats, const svmc_mod
   if (m->ksize != 3 || m->n_mlp != 0) return SVMC_ERR_UNSUPPORTED;
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return SVMC_ERR_HIP;
+  // address of this device's partial-sum array (allocation-free entry point)
+  if (noalloc_scratch_init(dev) != hipSuccess) return SVMC_ERR_HIP;
   svmc_ctx* c = new svmc_ctx();
   c->dev = dev;
   c->lats.assign(lats, lats + n_lats);
@@ -534,6 +536,32 @@ svmc_status svmc_local_energy(svmc_ctx* ctx, svmc_path path, double* eloc, int32
                       "full-recompute local energy")))
       return s;
   return SVMC_OK;
+}
+
+svmc_status svmc_local_energy_noalloc(svmc_ctx* ctx, double* eloc, hipStream_t st) {
+  if (!ctx) return SVMC_ERR_INVALID_ARG;
+  if (!ctx->have_walkers) return ctx->fail(SVMC_ERR_STATE, "no walkers loaded");
+  if (!eloc) return ctx->fail(SVMC_ERR_INVALID_ARG, "eloc is null");
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev != ctx->dev)
+    return ctx->fail(SVMC_ERR_INVALID_ARG, "the context's device must be current");
+  double* part = noalloc_scratch(dev);
+  if (!part) return ctx->fail(SVMC_ERR_STATE, "partial-sum array not set up on this device");
+  if ((long long)ctx->Wtot * ctx->eloc_slices > kNoAllocPartials)
+    return ctx->fail(SVMC_ERR_UNSUPPORTED, "walkers x slices exceeds the fixed partial-sum array (2^20 entries)");
+  ElocOut out;
+  out.eloc = eloc;
+  out.nhops = nullptr;
+  out.code = nullptr;
+  out.ratio = nullptr;
+  out.stride = ctx->max_hops();
+  out.slices = ctx->eloc_slices;
+  out.part = part;
+  svmc_status s;
+  if (!ctx->prepared && (s = prepare(ctx, st))) return s;
+  return ctx->hip(launch_eloc_lowrank(ctx->prec, ctx->mdev(), ctx->lats_dev.as<LatDev>(), ctx->ld.data(),
+                                      (int)ctx->ld.size(), ctx->Wtot, ctx->bufs(), out, st),
+                  "low-rank local energy (no allocation)");
 }
 
 svmc_status svmc_refresh(svmc_ctx* ctx, hipStream_t st) {

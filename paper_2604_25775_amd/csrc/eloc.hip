@@ -234,6 +234,30 @@ hipError_t SVMC_CAT3(eloc_lowrank_, SVMC_INST_P, SVMC_INST_C)(const ModelDev& md
   return eloc_impl<SVMC_INST_P, SVMC_INST_C>(md, lats_dev, nlats, W, bf, out, smem, st);
 }
 #else
+// Partial sums of the allocation-free local-energy entry point: a fixed
+// array per device, shared by every call on that device (each call writes
+// every slot it reads, so nothing needs clearing; calls that overlap on one
+// device race).  Host code uses only the address hipGetSymbolAddress gives
+// for the device that was current at set-up, never the symbol itself.
+static __device__ __align__(256) double scratch[kNoAllocPartials];
+
+namespace {
+constexpr int kMaxDevices = 64;
+double* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t noalloc_scratch_init(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  if (g_scratch_ptr[dev]) return hipSuccess;
+  void* p = nullptr;
+  hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  g_scratch_ptr[dev] = (double*)p;
+  return hipSuccess;
+}
+
+double* noalloc_scratch(int dev) { return (dev >= 0 && dev < kMaxDevices) ? g_scratch_ptr[dev] : nullptr; }
+
 size_t eloc_lowrank_smem(const LatDev* lats, int nlats, int prec, int L, int C) {
   const int tfb = prec == PREC_F64 ? 8 : 4;
   size_t mx = 0;

@@ -55,6 +55,13 @@ struct ElocOut {
   int slices;       // workgroups per walker
 };
 size_t eloc_lowrank_smem(const LatDev* lats_host, int nlats, int prec, int L, int C);
+// Allocation-free local energies: the per-slice partial sums live in a fixed
+// device array of kNoAllocPartials doubles (8 MiB) per device.
+// noalloc_scratch_init looks its address up for device `dev` (which must be
+// current) once; noalloc_scratch returns it (null before the lookup).
+constexpr long long kNoAllocPartials = 1LL << 20;
+hipError_t noalloc_scratch_init(int dev);
+double* noalloc_scratch(int dev);
 hipError_t launch_eloc_lowrank(int prec, const ModelDev& md, const LatDev* lats_dev, const LatDev* lats_host,
                                int nlats, long long W, const Bufs& bf, const ElocOut& out, hipStream_t st);
 
