@@ -246,6 +246,77 @@ SVMC_DEV void conv_tile_grid(const typename PrecT<P>::Tf* __restrict__ grid, int
   }
 }
 
+// The same tile when both axes are in window mode (no torus wrap): the grid
+// is a window of unwrapped coordinates whose off-lattice records hold zeros,
+// so tap t of the lane's site is the record cen + (t/3 - 1) Gx + (t%3 - 1),
+// one add per K chunk (a uniform tap offset when a chunk holds one tap).  cen
+// must be a record whose 3 x 3 neighbourhood lies in the window (padding rows
+// pass any box site; their results are not used).  Same products in the same
+// order as conv_tile_grid.
+template <int P, int C>
+SVMC_DEV void conv_tile_win(const typename PrecT<P>::Tf* __restrict__ grid, int Gx, int cen,
+                            const typename PrecT<P>::Tb (&breg)[RegB<P, C>::value ? ConvCfg<P, C>::Q : 1]
+                                                              [ConvCfg<P, C>::NT],
+                            const typename PrecT<P>::Tb* __restrict__ Bl, int lane,
+                            typename PrecT<P>::Acc (&acc)[ConvCfg<P, C>::NT]) {
+  typedef typename PrecT<P>::Tf Tf;
+  typedef typename PrecT<P>::Tb Tb;
+  typedef ConvCfg<P, C> CC;
+  constexpr int SP = SiteStride<Tf, C>::value;
+  const int g = lane >> 4;
+#pragma unroll
+  for (int nt = 0; nt < CC::NT; ++nt)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) acc[nt][v] = 0;
+#pragma unroll
+  for (int q = 0; q < CC::Q; ++q) {
+    Tb b[CC::NT];
+#pragma unroll
+    for (int nt = 0; nt < CC::NT; ++nt) {
+      if constexpr (RegB<P, C>::value) b[nt] = breg[q][nt];
+      else b[nt] = Bl[(q * CC::NT + nt) * 64 + lane];
+    }
+    int tap, c0;
+    bool kok;
+    if constexpr (Mma16<P>::value) {
+      const int k0 = 32 * q + 8 * g;
+      kok = k0 < CC::K;
+      tap = kok ? k0 / C : 4;
+      c0 = kok ? k0 % C : 0;
+    } else {
+      kok = true;
+      tap = (4 * q) / C;
+      c0 = (4 * q) % C + g;
+    }
+    const int site = cen + (tap / 3 - 1) * Gx + (tap % 3 - 1);
+    if constexpr (GridPlanes<P>::value) {
+      const char* rec = reinterpret_cast<const char*>(grid) + site * SP * (int)sizeof(Tf) + 2 * c0;
+      v8h hi = *reinterpret_cast<const v8h*>(rec);
+      v8h lo = *reinterpret_cast<const v8h*>(rec + 2 * C);
+      if (!kok) { hi = v8h{}; lo = v8h{}; }
+#pragma unroll
+      for (int nt = 0; nt < CC::NT; ++nt) mfma(acc[nt], b[nt], hi);
+#pragma unroll
+      for (int nt = 0; nt < CC::NT; ++nt) mfma(acc[nt], b[nt], lo);
+    } else if constexpr (Mma16<P>::value) {
+      const int off = site * SP + c0;
+      float x[8];
+      const float4* p4 = reinterpret_cast<const float4*>(grid + off);
+      const float4 x0 = p4[0], x1 = p4[1];
+      x[0] = x0.x; x[1] = x0.y; x[2] = x0.z; x[3] = x0.w;
+      x[4] = x1.x; x[5] = x1.y; x[6] = x1.z; x[7] = x1.w;
+      if (!kok)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) x[e] = 0.0f;
+      mma_chunk16<P, CC::NT>(acc, x, b);
+    } else {
+      const Tf a = grid[site * SP + c0];
+#pragma unroll
+      for (int nt = 0; nt < CC::NT; ++nt) mfma(acc[nt], b[nt], a);
+    }
+  }
+}
+
 // Writes four consecutive channels n0 .. n0 + 3 of FP32 features to grid
 // record `site` (16-byte vector loads and stores on both layouts).
 template <int P, int C>
@@ -329,6 +400,10 @@ SVMC_DEV void hop_features(const ModelDev& md, const LatDev& lt, const HopGeom& 
   constexpr bool PL = GridPlanes<P>::value;
   const int L = md.L, N = lt.N, Lx = lt.Lx, Gx = lt.Gx;
   const Axis ax = h.ax, ay = h.ay;
+  // window mode on both axes: grid index = unwrapped coordinate - origin, and
+  // every tap of a box site is a fixed record offset (off-lattice records of
+  // the window hold zeros); otherwise taps go through the coordinate table
+  const bool win = !(lt.torus_x | lt.torus_y);
   Tf* grid = (Tf*)scratch;
   const int bit = 1 << h.sigma;
   constexpr int V = 16 / sizeof(Tf);          // elements per 16-byte vector
@@ -348,8 +423,20 @@ SVMC_DEV void hop_features(const ModelDev& md, const LatDev& lt, const HopGeom& 
   };
   load_b(1);
   const int zsite = Gx * lt.Gy;             // the all-zero record after the grid
-  if (tid < SP * (int)sizeof(Tf) / 16)
-    reinterpret_cast<float4*>(grid + zsite * SP)[tid] = float4{0.0f, 0.0f, 0.0f, 0.0f};
+  constexpr int RV = SP * (int)sizeof(Tf) / 16;   // 16-byte vectors per grid record
+  if (tid < RV) reinterpret_cast<float4*>(grid + zsite * SP)[tid] = float4{0.0f, 0.0f, 0.0f, 0.0f};
+  if (win) {
+    // zeros on the window's off-lattice records (open axes); the grid area
+    // held the previous hop's determinant staging
+    const int mg = kMagic16[Gx], GG = Gx * lt.Gy;
+    for (int r = tid; r < GG; r += NT_) {
+      const int gy = fdiv16(r, mg), gx = r - gy * Gx;
+      if (inlat(ax, ax.go + gx) && inlat(ay, ay.go + gy)) continue;
+      float4* d = reinterpret_cast<float4*>(grid + r * SP);
+#pragma unroll
+      for (int k = 0; k < RV; ++k) d[k] = float4{0.0f, 0.0f, 0.0f, 0.0f};
+    }
+  }
   // layer-1 input: embedding of the new configuration on the layer-1 input
   // box (layer-1 output box grown by one site)
   {
@@ -409,21 +496,31 @@ SVMC_DEV void hop_features(const ModelDev& md, const LatDev& lt, const HopGeom& 
       gsite[ti] = -1;
       if (t >= T) break;
       const int m = 16 * t + (lane & 15);
-      unsigned px = 0xFFFFFFu, py = 0xFFFFFFu;
-      int ux, uy;
-      box_site(m, olx, owx, mow, oly, ux, uy);
-      const unsigned tx = tab_gx(tab, ux), ty = tab_gy(tab, uy);
-      if (m < cnt) {
-        px = tx;
-        py = ty;
-        gsite[ti] = (int)((ty >> 8) & 0xFFu) * Gx + (int)((tx >> 8) & 0xFFu);
+      if (win) {
+        // padding rows compute from the box's last site
+        const int mm = m < cnt ? m : cnt - 1;
+        int ux, uy;
+        box_site(mm, olx, owx, mow, oly, ux, uy);
+        const int cen = (uy - ay.go) * Gx + (ux - ax.go);
+        if (m < cnt) gsite[ti] = cen;
+        conv_tile_win<P, C>(grid, Gx, cen, breg, Bl, lane, acc[ti]);
+      } else {
+        unsigned px = 0xFFFFFFu, py = 0xFFFFFFu;
+        int ux, uy;
+        box_site(m, olx, owx, mow, oly, ux, uy);
+        const unsigned tx = tab_gx(tab, ux), ty = tab_gy(tab, uy);
+        if (m < cnt) {
+          px = tx;
+          py = ty;
+          gsite[ti] = (int)((ty >> 8) & 0xFFu) * Gx + (int)((tx >> 8) & 0xFFu);
+        }
+        conv_tile_grid<P, C>(grid, Gx, zsite, px, py, breg, Bl, lane, acc[ti]);
       }
-      conv_tile_grid<P, C>(grid, Gx, zsite, px, py, breg, Bl, lane, acc[ti]);
     }
     // the next layer's B fragments are in flight during the rest of this one
     if (l < L) load_b(l + 1);
     // H'_l = H'_{l-1} + act(conv + b); the residual is this site's own grid
-    // value (padding rows compute from the zero record and are not stored)
+    // value (padding rows compute from another record and are not stored)
     if constexpr (PL) {
       auto epilogue = [&](auto actc) {
         constexpr int A = decltype(actc)::value;
@@ -534,36 +631,36 @@ SVMC_DEV void hop_features(const ModelDev& md, const LatDev& lt, const HopGeom& 
     if (l < L) {
       // the ring of the next input box (output box at distance l+1 grown by
       // one) gets the cached H_l; ring sites lie outside this layer's box, so
-      // they are never written above
+      // they are never written above.  Two threads per site, each moving half
+      // of its channels, so the site's coordinates are worked out once per
+      // half record.
       int ilx, iwx, ily, iwy;
       box1(ax, h.xi, h.dx, l + 2, ilx, iwx);
       box1(ay, h.yi, h.dy, l + 2, ily, iwy);
       const Tf* Hl = featw + (long long)(l - 1) * N * C;
       const int miw = kMagic16[iwx];
-      const int tot = iwx * iwy * CV;
-      constexpr int U = 4;          // loads in flight per thread
-      for (int e0 = 0; e0 < tot; e0 += NT_ * U) {
-        float4 val[U];
-        int dst[U];
+      constexpr int HV = CV / 2;           // 16-byte vectors per half record
+      static_assert(CV % 2 == 0, "half records of whole vectors");
+      const int tot = iwx * iwy * 2;
+      for (int e0 = 0; e0 < tot; e0 += NT_) {
+        const int e = e0 + tid;
+        const int q = e >> 1, half = e & 1;
+        int ux, uy;
+        box_site(q, ilx, iwx, miw, ily, ux, uy);
+        const int s = tab_site(tab, ux, uy, Lx);
+        const int site = (int)((tab_gy(tab, uy) >> 8) & 0xFFu) * Gx + (int)((tab_gx(tab, ux) >> 8) & 0xFFu);
+        const bool ok = e < tot && !(inbox(ax, olx, owx, ux) && inbox(ay, oly, owy, uy));
+        if (!ok) continue;
+        const Tf* src = Hl + (long long)s * C + half * HV * V;
+        float4 val[HV];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-          const int e = e0 + NT_ * u + tid;
-          const int q = e / CV, cv = e - q * CV;
-          int ux, uy;
-          box_site(q, ilx, iwx, miw, ily, ux, uy);
-          const int s = tab_site(tab, ux, uy, Lx);
-          const int site = (int)((tab_gy(tab, uy) >> 8) & 0xFFu) * Gx + (int)((tab_gx(tab, ux) >> 8) & 0xFFu);
-          const bool ok = e < tot && !(inbox(ax, olx, owx, ux) && inbox(ay, oly, owy, uy));
-          dst[u] = ok ? site * 256 + cv * V : -1;
-          val[u] = ok ? *reinterpret_cast<const float4*>(Hl + (long long)s * C + cv * V) : float4{0, 0, 0, 0};
+        for (int u = 0; u < HV; ++u) val[u] = reinterpret_cast<const float4*>(src)[u];
+#pragma unroll
+        for (int u = 0; u < HV; ++u) {
+          const int n0 = (half * HV + u) * V;
+          if constexpr (PL) grid_put4<P, C>(grid, site, n0, val[u]);
+          else *reinterpret_cast<float4*>(grid + site * SP + n0) = val[u];
         }
-#pragma unroll
-        for (int u = 0; u < U; ++u)
-          if (dst[u] >= 0) {
-            const int site = dst[u] >> 8, n0 = dst[u] & 255;
-            if constexpr (PL) grid_put4<P, C>(grid, site, n0, val[u]);
-            else *reinterpret_cast<float4*>(grid + site * SP + n0) = val[u];
-          }
       }
     }
     __syncthreads();
