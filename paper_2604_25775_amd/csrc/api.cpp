@@ -100,6 +100,9 @@ struct svmc_ctx {
   long long Wtot = 0;
   DevBuf occ, lab, pos, feat, inv, M, G, PT, ldet, sgn, flags, nacc;
   DevBuf ratio_tmp, eloc_part;
+  // full-recompute path: configuration chunks
+  DevBuf f_cnt, f_off, f_occ, f_feat, f_h0, f_cw, f_ch, f_jw, f_ld, f_sg, f_ref, f_lab, f_pos, f_M, f_inv, f_flags,
+      f_nacc;
   DevBuf sw_stage, sw_list, sw_count;  // sweep: accepted-move staging, accepted walkers, their counts
   DevBuf gK, gB, gE;                 // conv weights, conv bias, embedding (FP64, forward's rounding)
   DevBuf g_rows, g_dH, g_hs, g_dzs, g_vjp;  // gradient scratch
@@ -525,14 +528,63 @@ svmc_status svmc_local_energy(svmc_ctx* ctx, svmc_path path, double* eloc, int32
                     "low-rank local energy");
   }
   if (path != SVMC_PATH_FULL) return ctx->fail(SVMC_ERR_INVALID_ARG, "unknown path");
-  for (auto& lt : ctx->ld)
-    if (lt.N * (ctx->C + 16 / ctx->tf_bytes()) * ctx->tf_bytes() > 64 * 1024 || lt.N > 256 || lt.nmax > 128)
-      return ctx->fail(SVMC_ERR_UNSUPPORTED, "full-recompute path supports N <= 256, N*C features <= 64 KiB");
   const int stride = ctx->max_hops();
   if ((s = ctx->hip(ctx->ratio_tmp.ensure((size_t)ctx->Wtot * stride * 8), "alloc"))) return s;
+  // chunk storage: configurations per chunk from a 2 GiB budget for the
+  // largest lattice (at least one walker's worth of configurations)
+  const int tfb = ctx->tf_bytes(), L = ctx->L, C = ctx->C;
+  size_t per = 0;
+  long long nmx = 1, Nmx = 1, wmx = 1;
+  for (auto& lt : ctx->ld) {
+    per = std::max(per, full_config_bytes(lt, L, C, tfb));
+    nmx = std::max<long long>(nmx, lt.nmax);
+    Nmx = std::max<long long>(Nmx, lt.N);
+    wmx = std::max<long long>(wmx, lt.nw);
+  }
+  long long chunk = std::max<long long>((2LL << 30) / (long long)per, (long long)ctx->max_hops() + 1);
+  chunk = std::min<long long>(chunk, 1LL << 20);
+  FullScratch fs;
+  fs.chunk = chunk;
+  const bool big = nmx > 128;
+  if ((s = ctx->hip(ctx->f_cnt.ensure((size_t)wmx * 4), "alloc")) ||
+      (s = ctx->hip(ctx->f_off.ensure((size_t)(wmx + 1) * 8), "alloc")) ||
+      (s = ctx->hip(ctx->f_occ.ensure((size_t)chunk * Nmx), "alloc")) ||
+      (s = ctx->hip(ctx->f_feat.ensure((size_t)chunk * L * Nmx * C * tfb), "alloc")) ||
+      (s = ctx->hip(ctx->f_h0.ensure((size_t)chunk * Nmx * C * tfb), "alloc")) ||
+      (s = ctx->hip(ctx->f_cw.ensure((size_t)chunk * 4), "alloc")) ||
+      (s = ctx->hip(ctx->f_ch.ensure((size_t)chunk * 4), "alloc")) ||
+      (s = ctx->hip(ctx->f_jw.ensure((size_t)chunk * 8), "alloc")) ||
+      (s = ctx->hip(ctx->f_ld.ensure((size_t)chunk * 16), "alloc")) ||
+      (s = ctx->hip(ctx->f_sg.ensure((size_t)chunk * 16), "alloc")) ||
+      (s = ctx->hip(ctx->f_ref.ensure((size_t)wmx * 16), "alloc")))
+    return s;
+  if (big && ((s = ctx->hip(ctx->f_lab.ensure((size_t)chunk * 2 * Nmx * 2), "alloc")) ||
+              (s = ctx->hip(ctx->f_pos.ensure((size_t)chunk * 2 * nmx * 2), "alloc")) ||
+              (s = ctx->hip(ctx->f_M.ensure((size_t)chunk * 2 * Nmx * nmx * 8), "alloc")) ||
+              (s = ctx->hip(ctx->f_inv.ensure((size_t)chunk * 2 * nmx * nmx * 8), "alloc")) ||
+              (s = ctx->hip(ctx->f_flags.ensure((size_t)chunk * 4), "alloc")) ||
+              (s = ctx->hip(ctx->f_nacc.ensure((size_t)chunk * 4), "alloc"))))
+    return s;
+  fs.cnt = ctx->f_cnt.as<int32_t>();
+  fs.off = ctx->f_off.as<long long>();
+  fs.occ = ctx->f_occ.as<int8_t>();
+  fs.feat = ctx->f_feat.p;
+  fs.h0 = ctx->f_h0.p;
+  fs.cfg_w = ctx->f_cw.as<int32_t>();
+  fs.cfg_h = ctx->f_ch.as<int32_t>();
+  fs.cfg_jw = ctx->f_jw.as<double>();
+  fs.ld = ctx->f_ld.as<double>();
+  fs.sg = ctx->f_sg.as<double>();
+  fs.ref = ctx->f_ref.as<double>();
+  fs.lab = ctx->f_lab.as<int16_t>();
+  fs.pos = ctx->f_pos.as<int16_t>();
+  fs.M = ctx->f_M.as<double>();
+  fs.inv = ctx->f_inv.as<double>();
+  fs.flags = ctx->f_flags.as<int32_t>();
+  fs.nacc = ctx->f_nacc.as<int32_t>();
   for (auto& lt : ctx->ld)
     if ((s = ctx->hip(launch_eloc_full(ctx->prec, md, lt, bf, out, ctx->ratio_tmp.as<double>() + lt.w0 * stride,
-                                       stride, st),
+                                       stride, fs, st),
                       "full-recompute local energy")))
       return s;
   return SVMC_OK;

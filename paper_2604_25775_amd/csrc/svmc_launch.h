@@ -119,17 +119,34 @@ hipError_t launch_grad_reduce(const double* rows, long long cnt, long long npara
 // dst[i] = (float)src[i], i < n (round to nearest)
 hipError_t launch_to_f32(const double* src, float* dst, long long n, hipStream_t st);
 
-// full.hip: full-recompute comparison path
+// full.hip: full-recompute comparison path, batched over configurations
+// (each walker's own and its hop configurations) in chunks of `chunk`.
+struct FullScratch {
+  long long chunk;        // configurations per chunk
+  int32_t* cnt;           // [W] hops per walker
+  long long* off;         // [W + 1] configuration offsets
+  int8_t* occ;            // [chunk][N]
+  void* feat;             // [chunk][L][N][C] features (Tf)
+  void* h0;               // [chunk][N][C] embedding (Tf)
+  int32_t *cfg_w, *cfg_h; // [chunk] walker, hop index (-1: own configuration)
+  double* cfg_jw;         // [chunk] JW sign of the hop
+  double *ld, *sg;        // [chunk][2] log|det|, sign per spin (canonical)
+  double* ref;            // [W][2] log|psi|, sign of each walker's own configuration
+  // N_sigma > 128 (cold-setup kernels): labels, rows, inverses, flags
+  int16_t *lab, *pos;
+  double *M, *inv;
+  int32_t *flags, *nacc;
+};
+// bytes of chunk storage per configuration
+size_t full_config_bytes(const LatDev& lt, int L, int C, int tfb);
 hipError_t launch_eloc_full(int prec, const ModelDev& md, const LatDev& lt, const Bufs& bf, const ElocOut& out,
-                            double* ratio_tmp, int stride_tmp, hipStream_t st);
+                            double* ratio_tmp, int stride, const FullScratch& fs, hipStream_t st);
 
 // Per-(precision, channels) instances; each is compiled in its own
 // translation unit (the build defines SVMC_INST_P / SVMC_INST_C).
 #define SVMC_DECL_INST(P_, C_)                                                                          \
   hipError_t eloc_lowrank_##P_##_##C_(const ModelDev& md, const LatDev* lats_dev, int nlats, long long W, \
                                       const Bufs& bf, const ElocOut& out, size_t smem, hipStream_t st);   \
-  hipError_t eloc_full_##P_##_##C_(const ModelDev& md, const LatDev& lt, const Bufs& bf, const ElocOut& out, \
-                                   double* ratio_tmp, int stride, hipStream_t st);                        \
   hipError_t forward_##P_##_##C_(const LatDev& lt, const Bufs& bf, const ModelDev& md, void* h0tmp,       \
                                  hipStream_t st);                                                         \
   hipError_t sweep_step_##P_##_##C_(const ModelDev& md, const LatDev* lats_dev, int nlats, long long W,   \
