@@ -189,7 +189,7 @@ static __global__ __launch_bounds__(64) void k_full_configs(LatDev lt, Bufs bf, 
 // Both Slater blocks of one configuration, spin tau = blockIdx.y, in
 // canonical order (occupied sites ascending): rows base[s] + b + H_L[s] W
 // (FP64, sum over channels in order), then log|det| and sign by the
-// register-tiled LU with partial pivoting.  H_L of the occupied sites
+// register-tiled LU with partial pivoting (tiled_lu_det).  H_L of the occupied sites
 // ([n][C + 1] in the feature type) and W ([C][n] doubles) are staged in LDS.
 template <class Tf, int R>
 __global__ __launch_bounds__(256) void k_full_det(LatDev lt, int C, const int8_t* __restrict__ occ_h,
@@ -272,7 +272,7 @@ __global__ __launch_bounds__(256) void k_full_det(LatDev lt, int C, const int8_t
   }
   double la, sg;
   bool sing;
-  tiled_gj<R, false>(x, n, sh, la, sg, sing);
+  tiled_lu_det<R>(x, n, sh, la, sg, sing);
   if (tid == 0) {
     *ldo = (sing || bad) ? -INFINITY : la;
     *sgo = (sing || bad) ? 0.0 : sg;

@@ -14,6 +14,7 @@
 #include "svmc_dev.h"
 #include "svmc_launch.h"
 #include "tiled_lu.h"
+#include "hop.h"
 
 namespace svmc {
 
@@ -34,7 +35,11 @@ __global__ void k_embed(LatDev lt, Bufs bf, ModelDev md, Tf* __restrict__ h0) {
 }
 
 // One conv layer over every site of every walker of a lattice.  Block = 4
-// waves, each wave one 16-site tile.  src = H_{l-1} ([nw][N][C]), dst = H_l.
+// waves; each wave takes FWD_TPW consecutive 16-site tiles of one walker
+// (the tiles of a lattice are dealt to the waves of a row of blocks), so the
+// layer's weight fragments are loaded once per wave and reused.  src =
+// H_{l-1} ([nw][N][C]), dst = H_l.
+constexpr int FWD_TPW = 4;
 template <int P, int C>
 __global__ __launch_bounds__(256) void k_forward_layer(LatDev lt, ModelDev md, int layer,
                                                        const typename PrecT<P>::Tf* __restrict__ src,
@@ -46,40 +51,196 @@ __global__ __launch_bounds__(256) void k_forward_layer(LatDev lt, ModelDev md, i
   typedef typename PrecT<P>::Acc Acc;
   typedef ConvCfg<P, C> CC;
   const int lane = threadIdx.x & 63;
-  const int tile = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int tile0 = (blockIdx.x * 4 + (threadIdx.x >> 6)) * FWD_TPW;
   const long long wl = blockIdx.y;
   const int N = lt.N;
-  if (tile * 16 >= N) return;
+  if (tile0 * 16 >= N) return;
   const Tf* S = src + wl * src_stride;
   Tf* D = dst + wl * dst_stride;
-  const int m = tile * 16 + (lane & 15);
-  int nb[9];
-  {
-    const int x = m % lt.Lx, y = m / lt.Lx;
-#pragma unroll
-    for (int t = 0; t < 9; ++t) {
-      int xx = x + (t % 3) - 1, yy = y + (t / 3) - 1;
-      bool ok = m < N;
-      if (lt.pbc_x) xx = imod(xx, lt.Lx); else ok = ok && xx >= 0 && xx < lt.Lx;
-      if (lt.pbc_y) yy = imod(yy, lt.Ly); else ok = ok && yy >= 0 && yy < lt.Ly;
-      nb[t] = ok ? (xx + lt.Lx * yy) * C : -1;
-    }
-  }
-  Acc acc[CC::NT];
   const Tb* Bl = (const Tb*)md.Bpack + (long long)layer * CC::Q * CC::NT * 64;
-  conv_tile<P, C>(S, nb, Bl, lane, acc);
   const Tf* bias = (const Tf*)md.bias + layer * C;
+  // the layer's weight fragments in registers when they fit (16-bit modes),
+  // else read per tile
+  constexpr bool RB = CC::Q * CC::NT * (int)sizeof(Tb) <= 80 * 4;
+  Tb breg[RB ? CC::Q : 1][CC::NT];
+  if constexpr (RB) {
 #pragma unroll
-  for (int nt = 0; nt < CC::NT; ++nt)
+    for (int q = 0; q < CC::Q; ++q)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int r = tile * 16 + OutMap<P>::site(lane, v);
-      const int n = nt * 16 + OutMap<P>::chan(lane, v);
-      if (r < N && n < C) {
-        const Tf z = acc[nt][v] + bias[n];
-        D[(long long)r * C + n] = layer_out<P, Tf>(md.act, S[(long long)r * C + n], z);
+      for (int nt = 0; nt < CC::NT; ++nt) breg[q][nt] = Bl[(q * CC::NT + nt) * 64 + lane];
+  }
+  for (int tt = 0; tt < FWD_TPW; ++tt) {
+    const int tile = tile0 + tt;
+    if (tile * 16 >= N) break;
+    const int m = tile * 16 + (lane & 15);
+    int nb[9];
+    {
+      const int x = m % lt.Lx, y = m / lt.Lx;
+#pragma unroll
+      for (int t = 0; t < 9; ++t) {
+        int xx = x + (t % 3) - 1, yy = y + (t / 3) - 1;
+        bool ok = m < N;
+        if (lt.pbc_x) xx = imod(xx, lt.Lx); else ok = ok && xx >= 0 && xx < lt.Lx;
+        if (lt.pbc_y) yy = imod(yy, lt.Ly); else ok = ok && yy >= 0 && yy < lt.Ly;
+        nb[t] = ok ? (xx + lt.Lx * yy) * C : -1;
       }
     }
+    Acc acc[CC::NT];
+    if constexpr (RB) conv_tile_regb<P, C>(S, nb, breg, lane, acc);
+    else conv_tile<P, C>(S, nb, Bl, lane, acc);
+#pragma unroll
+    for (int nt = 0; nt < CC::NT; ++nt)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = tile * 16 + OutMap<P>::site(lane, v);
+        const int n = nt * 16 + OutMap<P>::chan(lane, v);
+        if (r < N && n < C) {
+          const Tf z = acc[nt][v] + bias[n];
+          D[(long long)r * C + n] = layer_out<P, Tf>(md.act, S[(long long)r * C + n], z);
+        }
+      }
+  }
+}
+
+// Every layer of the forward for one walker per workgroup, the lattice in
+// LDS.  The LDS grid is the lattice with a one-site halo, (Lx + 2) x (Ly + 2)
+// records of the incremental grid's layout (FP16-pair planes in F16X2):
+// halo records repeat the opposite edge on periodic axes and hold zeros on
+// open ones, so each conv tap of a site is a fixed record offset
+// (conv_tile_win).  Per layer the waves convolve their tiles, form
+// H_l = H_{l-1} + act(z + b) (layer_out, the same arithmetic as
+// k_forward_layer), hold it in registers over a barrier, then write it over
+// the layer input (with its halo copies) and to the feature cache.
+constexpr int FUSED_MAXT = 6;             // tiles per wave: N <= 4 * 16 * 6 sites
+template <int P, int C>
+__global__ __launch_bounds__(256) void k_forward_fused(LatDev lt, Bufs bf, ModelDev md) {
+  typedef typename PrecT<P>::Tf Tf;
+  typedef typename PrecT<P>::Tb Tb;
+  typedef typename PrecT<P>::Acc Acc;
+  typedef ConvCfg<P, C> CC;
+  constexpr int SP = SiteStride<Tf, C>::value;
+  constexpr bool PL = GridPlanes<P>::value;
+  constexpr int V = 16 / (int)sizeof(Tf), CV = C / V;
+  constexpr int RV = SP * (int)sizeof(Tf) / 16;
+  extern __shared__ __attribute__((aligned(16))) char smem[];
+  Tf* grid = (Tf*)smem;
+  const long long wl = blockIdx.x;
+  const int N = lt.N, Lx = lt.Lx, Ly = lt.Ly, GX = Lx + 2, GG = GX * (Ly + 2), L = md.L;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int8_t* occ = bf.occ + lt.occ_off + wl * N;
+  Tf* featw = (Tf*)bf.feat + lt.feat_off + wl * (long long)L * N * C;
+  // records of site s: itself and its halo copies (periodic axes)
+  auto records = [&](int s, int (&r)[4]) -> int {
+    const int x = s % Lx, y = s / Lx;
+    const int X = x + 1, Y = y + 1;
+    const int X2 = lt.pbc_x ? (x == 0 ? Lx + 1 : (x == Lx - 1 ? 0 : -1)) : -1;
+    const int Y2 = lt.pbc_y ? (y == 0 ? Ly + 1 : (y == Ly - 1 ? 0 : -1)) : -1;
+    int k = 0;
+    r[k++] = Y * GX + X;
+    if (X2 >= 0) r[k++] = Y * GX + X2;
+    if (Y2 >= 0) r[k++] = Y2 * GX + X;
+    if (X2 >= 0 && Y2 >= 0) r[k++] = Y2 * GX + X2;
+    return k;
+  };
+  for (int e = tid; e < GG * RV; e += 256) reinterpret_cast<float4*>(grid)[e] = float4{0.0f, 0.0f, 0.0f, 0.0f};
+  __syncthreads();
+  // layer-0 input: the embedding of each site's occupation
+  const Tf* E = (const Tf*)md.embed;
+  for (int e = tid; e < N * CV; e += 256) {
+    const int s = e / CV, cv = e - s * CV;
+    const int o = occ[s] & 3;
+    const float4 v = *reinterpret_cast<const float4*>(E + lt.emb_off + (long long)s * lt.emb_ss + o * C + cv * V);
+    int r[4];
+    const int k = records(s, r);
+    for (int u = 0; u < k; ++u) {
+      if constexpr (PL) grid_put4<P, C>(grid, r[u], cv * V, v);
+      else *reinterpret_cast<float4*>(grid + r[u] * SP + cv * V) = v;
+    }
+  }
+  __syncthreads();
+  const int T = (N + 15) >> 4;
+  const Tf* bias = (const Tf*)md.bias;
+  for (int l = 1; l <= L; ++l) {
+    const Tb* Bl = (const Tb*)md.Bpack + (long long)(l - 1) * CC::Q * CC::NT * 64;
+    constexpr int QB = RegB<P, C>::value ? CC::Q : 1;
+    Tb breg[QB][CC::NT];
+    if constexpr (RegB<P, C>::value) {
+#pragma unroll
+      for (int q = 0; q < CC::Q; ++q)
+#pragma unroll
+        for (int nt = 0; nt < CC::NT; ++nt) breg[q][nt] = Bl[(q * CC::NT + nt) * 64 + lane];
+    }
+    Acc acc[FUSED_MAXT][CC::NT];
+    int cenr[FUSED_MAXT];
+#pragma unroll
+    for (int ti = 0; ti < FUSED_MAXT; ++ti) {
+      const int t = wave + 4 * ti;
+      if (t >= T) break;
+      const int m = 16 * t + (lane & 15);
+      const int mm = m < N ? m : N - 1;             // padding rows compute from a real site
+      const int cen = (mm / Lx + 1) * GX + (mm % Lx + 1);
+      cenr[ti] = cen;
+      conv_tile_win<P, C>(grid, GX, cen, breg, Bl, lane, acc[ti]);
+    }
+#pragma unroll
+    for (int ti = 0; ti < FUSED_MAXT; ++ti) {
+      const int t = wave + 4 * ti;
+      if (t >= T) break;
+      const Tf* rec = grid + cenr[ti] * SP;
+#pragma unroll
+      for (int nt = 0; nt < CC::NT; ++nt)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int n = 16 * nt + OutMap<P>::chan(lane, v);
+          if (n >= C) continue;
+          Tf xres;
+          if constexpr (PL) {
+            float x4[4];
+            planes_get4<C>(reinterpret_cast<const char*>(rec), 16 * nt + OutMap<P>::chan(lane, 0), x4);
+            xres = x4[v];
+          } else {
+            xres = rec[n];
+          }
+          const Tf z = acc[ti][nt][v] + bias[(l - 1) * C + n];
+          acc[ti][nt][v] = layer_out<P, Tf>(md.act, xres, z);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ti = 0; ti < FUSED_MAXT; ++ti) {
+      const int t = wave + 4 * ti;
+      if (t >= T) break;
+      const int m = 16 * t + (lane & 15);
+      if (m >= N) continue;
+      int r[4];
+      const int k = records(m, r);
+#pragma unroll
+      for (int nt = 0; nt < CC::NT; ++nt) {
+        if constexpr (PL) {
+          const int n0 = 16 * nt + OutMap<P>::chan(lane, 0);
+          if (n0 >= C) continue;
+          const float4 v4 = {acc[ti][nt][0], acc[ti][nt][1], acc[ti][nt][2], acc[ti][nt][3]};
+          for (int u = 0; u < k; ++u) grid_put4<P, C>(grid, r[u], n0, v4);
+          *reinterpret_cast<float4*>(featw + ((long long)(l - 1) * N + m) * C + n0) = v4;
+        } else {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int n = 16 * nt + OutMap<P>::chan(lane, v);
+            if (n >= C) continue;
+            for (int u = 0; u < k; ++u) grid[r[u] * SP + n] = acc[ti][nt][v];
+            featw[((long long)(l - 1) * N + m) * C + n] = acc[ti][nt][v];
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+template <int P, int C>
+size_t fused_smem(const LatDev& lt) {
+  typedef typename PrecT<P>::Tf Tf;
+  return (size_t)(lt.Lx + 2) * (lt.Ly + 2) * SiteStride<Tf, C>::value * sizeof(Tf);
 }
 
 template <int P, int C>
@@ -87,12 +248,20 @@ static hipError_t forward_impl(const LatDev& lt, const Bufs& bf, const ModelDev&
                                hipStream_t st) {
   typedef typename PrecT<P>::Tf Tf;
   if (lt.nw == 0) return hipSuccess;
+  const size_t fsm = fused_smem<P, C>(lt);
+  if (fsm <= 64 * 1024 && (lt.N + 15) / 16 <= 4 * FUSED_MAXT) {
+    auto kern = k_forward_fused<P, C>;
+    hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)fsm);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(kern, dim3((unsigned)lt.nw), dim3(256), fsm, st, lt, bf, md);
+    return hipGetLastError();
+  }
   const long long NC = (long long)lt.N * C;
   Tf* h0 = (Tf*)h0tmp;
   hipLaunchKernelGGL(k_embed<Tf>, dim3(4096), dim3(256), 0, st, lt, bf, md, h0);
   Tf* feat = (Tf*)bf.feat + lt.feat_off;
   const long long fs = (long long)md.L * NC;
-  const dim3 grid((unsigned)((lt.N + 63) / 64), (unsigned)lt.nw);
+  const dim3 grid((unsigned)((lt.N + 64 * FWD_TPW - 1) / (64 * FWD_TPW)), (unsigned)lt.nw);
   for (int l = 0; l < md.L; ++l) {
     const Tf* src = l == 0 ? h0 : feat + (long long)(l - 1) * NC;
     const long long ss = l == 0 ? NC : fs;

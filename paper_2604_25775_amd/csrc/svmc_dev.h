@@ -351,6 +351,50 @@ SVMC_DEV void conv_tile(const typename PrecT<P>::Tf* __restrict__ src, const int
   }
 }
 
+// The same tile with the layer's weight fragments already in registers
+// (breg[q][nt] = Bl[(q NT + nt) 64 + lane]); identical arithmetic.
+template <int P, int C>
+SVMC_DEV void conv_tile_regb(const typename PrecT<P>::Tf* __restrict__ src, const int (&nb)[9],
+                             const typename PrecT<P>::Tb (&breg)[ConvCfg<P, C>::Q][ConvCfg<P, C>::NT], int lane,
+                             typename PrecT<P>::Acc (&acc)[ConvCfg<P, C>::NT]) {
+  typedef typename PrecT<P>::Tf Tf;
+  typedef ConvCfg<P, C> CC;
+  const int g = lane >> 4;
+#pragma unroll
+  for (int nt = 0; nt < CC::NT; ++nt)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) acc[nt][v] = 0;
+#pragma unroll
+  for (int q = 0; q < CC::Q; ++q) {
+    if constexpr (Mma16<P>::value) {
+      const int k0 = 32 * q + 8 * g;
+      float x[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) x[e] = 0.0f;
+      if (k0 < CC::K) {
+        const int t = k0 / C, c0 = k0 % C;
+        int off = nb[0];
+#pragma unroll
+        for (int tt = 1; tt < 9; ++tt) off = (t == tt) ? nb[tt] : off;
+        if (off >= 0) {
+          const float4* p4 = reinterpret_cast<const float4*>(src + off + c0);
+          const float4 x0 = p4[0], x1 = p4[1];
+          x[0] = x0.x; x[1] = x0.y; x[2] = x0.z; x[3] = x0.w;
+          x[4] = x1.x; x[5] = x1.y; x[6] = x1.z; x[7] = x1.w;
+        }
+      }
+      mma_chunk16<P, CC::NT>(acc, x, breg[q]);
+    } else {
+      const int t = (4 * q) / C;
+      const int c = (4 * q) % C + g;
+      const int off = nb[t];
+      Tf a = off >= 0 ? src[off + c] : Tf(0);
+#pragma unroll
+      for (int nt = 0; nt < CC::NT; ++nt) mfma(acc[nt], breg[q][nt], a);
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // One-wave LU determinant of an r x r FP64 matrix, r <= RMAX <= 64.
 // Lane a (< r) holds row a in a[0..RMAX); lanes >= r must hold identity rows.
