@@ -267,6 +267,86 @@ def cpu_model():
 
 
 # ---------------------------------------------------------------------------
+# low-rank vs full recompute on other workloads (same GPU, same precision)
+# ---------------------------------------------------------------------------
+SPEEDUP_ROWS = [
+    # name, workload, conv layers (None: the workload's), walkers (low-rank),
+    # walkers for the full path (a prefix of the same batch)
+    ("16x16, 1 conv layer", "c3", 1, 8192, 1024),
+    ("32x32 448+448, 4 conv layers", "c5", None, 1024, 4),
+]
+
+
+def speedup_table(prec, log):
+    """E_loc/s of the low-rank and the full-recompute path on the same GPU
+    for each row of SPEEDUP_ROWS (seeded synthetic walkers as in the main
+    workload; the full path on a prefix of the batch), with each path's
+    roofline fraction from the same FLOP models as the headline."""
+    import torch
+    import workloads as wls
+    from paper_2604_25775_amd.api import ScaleVMC
+    out = []
+    for name, wname, layers, W, FW in SPEEDUP_ROWS:
+        wl = wls.get(wname)
+        lat = wl.lattices[0]
+        model = replace(wl.model, conv_prec=prec, **({"n_conv": layers} if layers else {}))
+        params = wls.quantise_params(wls.random_params([lat], model, seed=wl.seed_params), prec)
+        occ = wls.occupations(wl, 0, n_walkers=W)
+        ctx = ScaleVMC([lat], model.n_conv, model.channels, model.act, prec, model.refresh_every)
+        ctx.set_params_from(params)
+        ctx.load([W], occ)
+        e = torch.empty(W, dtype=torch.float64, device="cuda")
+        ctx.tune()
+        ctx.local_energy(out=e)
+        t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0.record()
+        for _ in range(3):
+            ctx.prepare()
+            ctx.local_energy(out=e)
+        t1.record()
+        torch.cuda.synchronize()
+        low_ms = t0.elapsed_time(t1) / 3
+        del ctx
+        fctx = ScaleVMC([lat], model.n_conv, model.channels, model.act, prec, model.refresh_every)
+        fctx.set_params_from(params)
+        fctx.load([FW], occ[:FW])
+        fe = torch.empty(FW, dtype=torch.float64, device="cuda")
+        fctx.local_energy("full", out=fe)
+        e2 = torch.empty(FW, dtype=torch.float64, device="cuda")
+        fctx.local_energy(out=e2)
+        t0.record()
+        fctx.local_energy("full", out=fe)
+        t1.record()
+        torch.cuda.synchronize()
+        full_ms = t0.elapsed_time(t1)
+        agree = float(np.max(np.abs(fe.cpu().numpy() - e2.cpu().numpy()) / np.maximum(1.0, np.abs(e2.cpu().numpy()))))
+        del fctx
+        low_rate, full_rate = W / (low_ms / 1e3), FW / (full_ms / 1e3)
+        conv_f, det_f = lowrank_flops(lat, occ, model.n_conv, model.channels)
+        conv_peak = PEAK_BF16 if prec in ("bf16", "bf16x3", "f16x2") else (PEAK_FP32 if prec == "f32" else PEAK_FP64)
+        t_low = conv_f / conv_peak + det_f / PEAK_FP64
+        nhop = float(np.sum(ctx_hops(lat, occ[:FW])))
+        conv_full = nhop * model.n_conv * lat.N * 9 * model.channels ** 2 * 2
+        fp64_full = nhop * sum(2.0 * n * n * model.channels + 2.0 / 3.0 * n ** 3 for n in (lat.n_up, lat.n_dn))
+        t_full = conv_full / conv_peak + fp64_full / PEAK_FP64
+        row = {"workload": f"{name} ({wname}, Hubbard {lat.Lx}x{lat.Ly}, {model.channels} ch, {prec})",
+               "lowrank_eloc_per_s": round(low_rate, 1), "lowrank_walkers": W,
+               "lowrank_roofline_frac": round(t_low / (low_ms / 1e3), 4),
+               "full_recompute_eloc_per_s": round(full_rate, 2), "full_recompute_walkers": FW,
+               "full_recompute_roofline_frac": round(t_full / (full_ms / 1e3), 4),
+               "speedup_vs_full": round(low_rate / full_rate, 2),
+               "speedup_at_equal_roofline_frac": round((t_full / FW) / (t_low / W), 2),
+               "lowrank_vs_full_max_rel_diff": agree}
+        log(f"[bench] {name}: low-rank {low_rate:.1f} E_loc/s ({row['lowrank_roofline_frac']:.3f} of roofline), "
+            f"full {full_rate:.2f} E_loc/s ({row['full_recompute_roofline_frac']:.3f}), "
+            f"speed-up {row['speedup_vs_full']:.1f}x (model at equal efficiency "
+            f"{row['speedup_at_equal_roofline_frac']:.1f}x)")
+        out.append(row)
+        torch.cuda.empty_cache()
+    return out
+
+
+# ---------------------------------------------------------------------------
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -283,6 +363,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-grad", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--no-speedup-table", action="store_true",
+                    help="skip the low-rank vs full-recompute rows of the other workloads")
     ap.add_argument("--tune-cache", default=None,
                     help="autotuner cache file (default: tune, do not store)")
     ap.add_argument("--traffic-probe", action="store_true",
@@ -329,8 +411,10 @@ def main():
         occ = occ_t.cpu().numpy().reshape(W, lat.N)
 
     slices = ctx.tune(a.tune_cache)
+    rfm = ctx.get_launch()["row_form_max"]
     extra["eloc_slices_per_walker"] = slices
-    log(f"[bench] autotuner: {slices} workgroups per walker")
+    extra["eloc_row_form_max"] = rfm
+    log(f"[bench] autotuner: {slices} workgroups per walker, row form up to {rfm} changed rows")
     if a.traffic_probe:
         ctx.prepare()
         ctx.local_energy(out=eloc)
@@ -467,6 +551,9 @@ def main():
                       "lowrank_vs_full_max_rel_diff": agree})
         log(f"[bench] full path: {full_ms:.1f} ms for {FW} walkers -> {full_rate:.1f} E_loc/s; "
             f"speed-up {value / full_rate:.2f}x; max |dE|/E lowrank vs full {agree:.2e}")
+
+    if not a.no_speedup_table:
+        extra["speedup_table"] = speedup_table(a.prec, log)
 
     cpu = None
     if not a.no_cpu and a.cpu_sample > 0:

@@ -268,14 +268,32 @@ svmc_status svmc_grad_logpsi(svmc_ctx* ctx, const double* vjp_w, void* out,
 /* Per-walker flag bits (svmc_walker_flag), device [W] int32. */
 svmc_status svmc_walker_flags(svmc_ctx* ctx, int32_t* flags, hipStream_t stream);
 
-/* Autotuner of the low-rank local-energy launch shape (not a step of the
- * method): each walker's hops are split over `slices` workgroups.  Times
+/* Launch shape of the low-rank local-energy kernel (not a step of the
+ * method; results agree to rounding across shapes):
+ *   slices        workgroups each walker's hops are split over (1..64);
+ *                 a walker's slices run on one XCD, their partial sums are
+ *                 added in slice order;
+ *   row_form_max  a hop whose two spins each change at most this many
+ *                 orbital rows takes the row form of the determinant lemma,
+ *                 det(Phi'[K] Phi^-1[:, K]) of size |K| (padded to 8 or 16),
+ *                 otherwise the column form of size C + 1 (Sec. II.C; the two
+ *                 are equal by Sylvester's identity): 0 (never), 8 or 16.
+ * Defaults: slices 8, row_form_max 16.  svmc_set_launch validates
+ * (SVMC_ERR_INVALID_ARG otherwise); svmc_get_launch reports the current one. */
+typedef struct {
+  int32_t slices, row_form_max;
+} svmc_launch;
+svmc_status svmc_set_launch(svmc_ctx* ctx, const svmc_launch* launch);
+svmc_status svmc_get_launch(const svmc_ctx* ctx, svmc_launch* launch);
+
+/* Autotuner of the low-rank local-energy launch shape (svmc_launch): times
  * svmc_local_energy(LOWRANK) on the loaded walkers for slices in
- * {1, 2, 4, 8, 16, 24, 32} and keeps the fastest for this context.  cache_path
- * (may be NULL): a text file; a line for the same shape key (lattices,
- * network, precision, walker count, device name) is reused without timing,
- * otherwise the result is appended.  *slices_out (may be NULL) receives the
- * choice.  Synchronises `stream`.  Errors: SVMC_ERR_STATE without walkers. */
+ * {1, 2, 4, 8, 16, 24, 32} x row_form_max in {0, 8, 16} and keeps the
+ * fastest for this context.  cache_path (may be NULL): a text file; a line
+ * for the same shape key (lattices, network, precision, walker count,
+ * device name) is reused without timing, otherwise the result is appended.
+ * *slices_out (may be NULL) receives the chosen slice count.  Synchronises
+ * `stream`.  Errors: SVMC_ERR_STATE without walkers. */
 svmc_status svmc_tune(svmc_ctx* ctx, const char* cache_path, int32_t* slices_out, hipStream_t stream);
 
 const char* svmc_status_string(svmc_status s);

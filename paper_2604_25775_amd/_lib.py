@@ -21,7 +21,7 @@ EXPORTS = [
     "svmc_local_energy",
     "svmc_sweep", "svmc_refresh", "svmc_get_state", "svmc_grad_logpsi", "svmc_walker_flags",
     "svmc_status_string", "svmc_last_error", "svmc_tune", "svmc_sweep_async",
-    "svmc_local_energy_noalloc",
+    "svmc_local_energy_noalloc", "svmc_set_launch", "svmc_get_launch",
 ]
 
 
@@ -35,6 +35,10 @@ class Model(ct.Structure):
     _fields_ = [("n_conv", ct.c_int32), ("channels", ct.c_int32), ("act", ct.c_int32),
                 ("conv_prec", ct.c_int32), ("refresh_every", ct.c_int32),
                 ("ksize", ct.c_int32), ("n_mlp", ct.c_int32), ("per_site_embed", ct.c_int32)]
+
+
+class Launch(ct.Structure):
+    _fields_ = [("slices", ct.c_int32), ("row_form_max", ct.c_int32)]
 
 
 class SvmcError(RuntimeError):
@@ -78,6 +82,8 @@ def load(path: str | None = None):
         "svmc_tune": (i32, [vp, ct.c_char_p, ct.POINTER(i32), vp]),
         "svmc_sweep_async": (i32, [vp, i32, u64, vp, vp, vp]),
         "svmc_local_energy_noalloc": (i32, [vp, vp, vp]),
+        "svmc_set_launch": (i32, [vp, ct.POINTER(Launch)]),
+        "svmc_get_launch": (i32, [vp, ct.POINTER(Launch)]),
     }
     for name, (res, args) in proto.items():
         f = getattr(lib, name)

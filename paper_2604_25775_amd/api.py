@@ -210,6 +210,16 @@ class ScaleVMC:
         self._check(self.lib.svmc_tune(self.h, path, ct.byref(out), _stream()), "tune")
         return int(out.value)
 
+    def set_launch(self, slices: int, row_form_max: int = 16):
+        """Low-rank E_loc launch shape (svmc_set_launch)."""
+        ln = _lib.Launch(int(slices), int(row_form_max))
+        self._check(self.lib.svmc_set_launch(self.h, ct.byref(ln)), "set_launch")
+
+    def get_launch(self) -> dict:
+        ln = _lib.Launch(0, 0)
+        self._check(self.lib.svmc_get_launch(self.h, ct.byref(ln)), "get_launch")
+        return {"slices": int(ln.slices), "row_form_max": int(ln.row_form_max)}
+
     def update_params(self, theta: torch.Tensor):
         """Upload a new flat parameter vector (same base orbitals) and rebuild
         the walkers' caches at their current configurations."""

@@ -90,6 +90,7 @@ struct svmc_ctx {
   bool prepared = false;   // G/P match the current walkers
   bool dets_fresh = false; // rows M, inverses and log|psi| rebuilt since the last move
   int eloc_slices = 8;     // workgroups per walker in the low-rank E_loc launch
+  int row_form_max = 16;   // row-form determinants when both spins change at most this many rows
   int dev = 0;             // device current at svmc_create
   // parameters
   DevBuf Bpack, embed, bias;
@@ -515,6 +516,7 @@ svmc_status svmc_local_energy(svmc_ctx* ctx, svmc_path path, double* eloc, int32
   out.stride = ctx->max_hops();
   out.part = nullptr;
   out.slices = 1;
+  out.row_form_max = ctx->row_form_max;
   const Bufs bf = ctx->bufs();
   const ModelDev md = ctx->mdev();
   svmc_status s;
@@ -608,6 +610,7 @@ svmc_status svmc_local_energy_noalloc(svmc_ctx* ctx, double* eloc, hipStream_t s
   out.ratio = nullptr;
   out.stride = ctx->max_hops();
   out.slices = ctx->eloc_slices;
+  out.row_form_max = ctx->row_form_max;
   out.part = part;
   svmc_status s;
   if (!ctx->prepared && (s = prepare(ctx, st))) return s;
@@ -844,6 +847,24 @@ svmc_status svmc_walker_flags(svmc_ctx* ctx, int32_t* flags, hipStream_t st) {
   return ctx->hip(hipMemcpyAsync(flags, ctx->flags.p, (size_t)ctx->Wtot * 4, hipMemcpyDeviceToDevice, st), "flags");
 }
 
+svmc_status svmc_set_launch(svmc_ctx* ctx, const svmc_launch* ln) {
+  if (!ctx) return SVMC_ERR_INVALID_ARG;
+  if (!ln) return ctx->fail(SVMC_ERR_INVALID_ARG, "launch is null");
+  if (ln->slices < 1 || ln->slices > 64) return ctx->fail(SVMC_ERR_INVALID_ARG, "slices must lie in 1..64");
+  if (ln->row_form_max != 0 && ln->row_form_max != 8 && ln->row_form_max != 16)
+    return ctx->fail(SVMC_ERR_INVALID_ARG, "row_form_max must be 0, 8 or 16");
+  ctx->eloc_slices = ln->slices;
+  ctx->row_form_max = ln->row_form_max;
+  return SVMC_OK;
+}
+
+svmc_status svmc_get_launch(const svmc_ctx* ctx, svmc_launch* ln) {
+  if (!ctx || !ln) return SVMC_ERR_INVALID_ARG;
+  ln->slices = ctx->eloc_slices;
+  ln->row_form_max = ctx->row_form_max;
+  return SVMC_OK;
+}
+
 svmc_status svmc_tune(svmc_ctx* ctx, const char* cache_path, int32_t* slices_out, hipStream_t st) {
   if (!ctx) return SVMC_ERR_INVALID_ARG;
   if (!ctx->have_walkers) return ctx->fail(SVMC_ERR_STATE, "no walkers loaded");
@@ -864,11 +885,13 @@ svmc_status svmc_tune(svmc_ctx* ctx, const char* cache_path, int32_t* slices_out
     std::ifstream in(cache_path);
     std::string line;
     while (std::getline(in, line)) {
-      const std::string tag = "scalevmc-tune v1 | " + k + " | slices=";
+      const std::string tag = "scalevmc-tune v2 | " + k + " | slices=";
       if (line.compare(0, tag.size(), tag) == 0) {
-        const int s = std::atoi(line.c_str() + tag.size());
-        if (s >= 1 && s <= 64) {
+        int s = 0, r = -1;
+        if (std::sscanf(line.c_str() + tag.size(), "%d rowform=%d", &s, &r) == 2 && s >= 1 && s <= 64 &&
+            (r == 0 || r == 8 || r == 16)) {
           ctx->eloc_slices = s;
+          ctx->row_form_max = r;
           if (slices_out) *slices_out = s;
           return SVMC_OK;
         }
@@ -881,11 +904,14 @@ svmc_status svmc_tune(svmc_ctx* ctx, const char* cache_path, int32_t* slices_out
   hipEvent_t e0, e1;
   if ((s = ctx->hip(hipEventCreate(&e0), "event")) || (s = ctx->hip(hipEventCreate(&e1), "event"))) return s;
   const int cand[7] = {1, 2, 4, 8, 16, 24, 32};
-  int best = ctx->eloc_slices;
+  const int forms[3] = {0, 8, 16};
+  int best = ctx->eloc_slices, best_rf = ctx->row_form_max;
   float best_ms = 1e30f;
   std::ostringstream times;
-  for (int c : cand) {
+  for (int v = 0; v < 21 && !s; ++v) {
+    const int c = cand[v % 7], rf = forms[v / 7];
     ctx->eloc_slices = c;
+    ctx->row_form_max = rf;
     // one untimed call, then two timed
     if ((s = svmc_local_energy(ctx, SVMC_PATH_LOWRANK, eo.as<double>(), nullptr, nullptr, nullptr, st))) break;
     if ((s = ctx->hip(hipEventRecord(e0, st), "event"))) break;
@@ -897,20 +923,24 @@ svmc_status svmc_tune(svmc_ctx* ctx, const char* cache_path, int32_t* slices_out
     float ms = 0.0f;
     if ((s = ctx->hip(hipEventElapsedTime(&ms, e0, e1), "event time"))) break;
     ms *= 0.5f;
-    times << " " << c << ":" << ms;
+    times << " " << c << "/" << rf << ":" << ms;
     if (ms < best_ms) {
       best_ms = ms;
       best = c;
+      best_rf = rf;
     }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   ctx->eloc_slices = best;
+  ctx->row_form_max = best_rf;
   if (s) return s;
   if (slices_out) *slices_out = best;
   if (cache_path) {
     std::ofstream out(cache_path, std::ios::app);
-    if (out) out << "scalevmc-tune v1 | " << k << " | slices=" << best << " | ms" << times.str() << "\n";
+    if (out)
+      out << "scalevmc-tune v2 | " << k << " | slices=" << best << " rowform=" << best_rf << " | ms (slices/rowform)"
+          << times.str() << "\n";
   }
   return SVMC_OK;
 }

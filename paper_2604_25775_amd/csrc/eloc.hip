@@ -160,6 +160,35 @@ __global__ __launch_bounds__(64 * ELOC_NW) __attribute__((amdgpu_waves_per_eu(3)
       const int K = hop_klist(lt, g, tab, occ_s, lab_s, wv, olx, owx, oly, owy, kl, hpos, lane);
       const double* PTt = PTw + (long long)wv * nm * C;
       const double* Gj = Gw + ((long long)wv * N + g.j) * nm;
+      // few changed rows in both spins: the row form (K x K, padded to 8 or
+      // 16) instead of the column form of size C + 1
+      const int Ko = hop_kcount(lt, g, tab, occ_s, 1 - wv, olx, owx, oly, owy, lane);
+      const int KM = uniform_i(max(K, Ko));
+      if (KM <= out.row_form_max) {
+        const v4d racc = hop_det_row_build<C>(kl, K, (const typename DType<P>::type*)scratch, PTt, lane);
+        __syncthreads();    // both matrices built: their staging may overwrite D
+        double* rstage = (double*)scratch + wv * 16 * 17;
+        if (KM <= 8) hop_det_row_stage<8>(racc, kl, K, wv == sp, hpos, Gj, rstage, lane);
+        else hop_det_row_stage<16>(racc, kl, K, wv == sp, hpos, Gj, rstage, lane);
+        __syncthreads();
+        if (wv == 0) {
+          // both K x K determinants in wavefront 0, one matrix per half
+          auto pair = [&](auto ks) {
+            constexpr int KS = decltype(ks)::value;
+            const double* sr = (const double*)scratch + (lane >> 5) * 16 * 17 +
+                               ((lane & 31) < KS ? (lane & 31) : 0) * (KS + 1);
+            double a[KS];
+#pragma unroll
+            for (int c2 = 0; c2 < KS; ++c2) a[c2] = (lane & 31) < KS ? sr[c2] : 0.0;
+            __builtin_amdgcn_wave_barrier();
+            return lu_det_pair<KS>(a, lane);
+          };
+          const double dt = KM <= 8 ? pair(IntC<8>()) : pair(IntC<16>());
+          if ((lane & 31) == 0) misc[lane >> 5] = dt;
+          if (lane == 0) misc[2] = 1.0;
+        }
+        __syncthreads();
+      } else {
       v4d dacc[DetTiles<C>::I][DetTiles<C>::J];
       hop_det_build<C>(kl, K, wv == sp, hpos, (const typename DType<P>::type*)scratch, PTt, Gj, lane, dacc);
       __syncthreads();      // both matrices built: their staging may overwrite D
@@ -187,6 +216,7 @@ __global__ __launch_bounds__(64 * ELOC_NW) __attribute__((amdgpu_waves_per_eu(3)
         if ((lane & 31) == 0) misc[lane >> 5] = dt;
       }
       __syncthreads();
+      }
       if (tid == 0) {
         const double R = misc[0] * misc[1] * misc[2];
         part += -(d < 4 ? lt.t : lt.tp) * R;

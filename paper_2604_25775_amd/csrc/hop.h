@@ -122,7 +122,10 @@ __host__ __device__ inline HopScratch hop_scratch(int Gx, int Gy, int L, int C, 
   const int SP = C + 16 / tfb;
   const int ox = Gx < 2 * L + 2 ? Gx : 2 * L + 2, oy = Gy < 2 * L + 2 ? Gy : 2 * L + 2;
   const int gb = (Gx * Gy + 1) * SP * tfb, db = ox * oy * (C + 4) * tfb;
-  const int sb = 2 * (C + 1) * (C + 2) * 8;     // two determinant stagings
+  // two determinant stagings: column form (C + 1) x (C + 2) or row form
+  // 16 x 17 doubles per wavefront, whichever is larger
+  const int sc = (C + 1) * (C + 2), sr = 16 * 17;
+  const int sb = 2 * (sc > sr ? sc : sr) * 8;
   const int rb = gb > db ? gb : db;
   h.klists = align16i(rb > sb ? rb : sb);
   h.misc = h.klists + align16i(2 * Gx * Gy * 4);
@@ -707,6 +710,28 @@ SVMC_DEV int hop_klist(const LatDev& lt, const HopGeom& h, const AxisTab& tab, c
   return nk;
 }
 
+// Number of electrons of spin tau in the new configuration on the layer-L
+// box (the length hop_klist would return), one wavefront, every lane active.
+SVMC_DEV int hop_kcount(const LatDev& lt, const HopGeom& h, const AxisTab& tab, const int8_t* occ_s, int tau,
+                        int olx, int owx, int oly, int owy, int lane) {
+  const int Lx = lt.Lx, cnt = owx * owy, mow = kMagic16[owx], bit = 1 << h.sigma;
+  int nk = 0;
+  for (int base = 0; base < cnt; base += 64) {
+    const int m = base + lane;
+    int ux, uy;
+    box_site(m, olx, owx, mow, oly, ux, uy);
+    const int s = tab_site(tab, ux, uy, Lx);
+    int o = 0;
+    if (m < cnt) {
+      o = occ_s[s];
+      if (s == h.i) o -= bit;
+      if (s == h.j) o += bit;
+    }
+    nk += __popcll(__ballot(m < cnt && ((o >> tau) & 1)));
+  }
+  return nk;
+}
+
 // FP64 reciprocal: hardware estimate refined by two Newton steps (error
 // below one ulp of the IEEE quotient, enough for an elimination multiplier).
 SVMC_DEV double rcp_d(double x) {
@@ -993,6 +1018,52 @@ SVMC_DEV double lu_det_pair(double (&a)[C], int lane) {
   const bool odd = ((hi_half ? par_hi : par_lo) & 1u) != 0u;
   if (sing) return 0.0;
   return odd ? -det : det;
+}
+
+// The determinant-lemma matrix of spin tau in the row form (one wavefront),
+// for K <= 16 changed rows:
+//   A[a][b] = E[a][b] + sum_c D(m_a)[c] P[c][k_b],   a, b < K,
+// with E the identity except for the moving electron's row (a = hpos), which
+// is G[j][k_b] (its orbital row at the new site against the cached inverse);
+// det A = det(Phi'[K] Phi^-1[:, K]), the ratio the column form of size
+// C + [tau moves] gives (Sylvester's determinant identity).  The product is
+// one 16 x 16 tile on the FP64 matrix cores, C / 4 k-steps (A[i][k] from
+// lane i + 16 k, B[k][j] from lane j + 16 k); slot v of lane l then holds row
+// l / 16 + 4 v, column l % 16.
+template <int C, class DT>
+SVMC_DEV v4d hop_det_row_build(const int* kl, int K_in, const DT* Dbuf, const double* __restrict__ PTt, int lane) {
+  static_assert(C % 4 == 0, "k-steps of four channels");
+  constexpr int SD = DStride<C>::value;
+  const int K = uniform_i(K_in);
+  const int li = lane & 15, lk = lane >> 4;
+  const int e = li < K ? kl[li] : 0;
+  const int mrow = (e >> 16) * SD, kcol = e & 0xffff;
+  v4d acc = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int c0 = 0; c0 < C; c0 += 4) {
+    const double av = li < K ? (double)Dbuf[mrow + c0 + lk] : 0.0;
+    const double bv = li < K ? PTt[kcol * C + c0 + lk] : 0.0;
+    mfma(acc, av, bv);
+  }
+  return acc;
+}
+// Adds E and stages the matrix row-major [KS][KS + 1] (KS = 8 or 16 >= K);
+// rows and columns >= K hold the identity.
+template <int KS>
+SVMC_DEV void hop_det_row_stage(const v4d& acc, const int* kl, int K_in, bool hopspin, int hpos_in,
+                                const double* __restrict__ Gj, double* stage, int lane) {
+  const int K = uniform_i(K_in), hpos = uniform_i(hpos_in);
+  const int li = lane & 15, lk = lane >> 4;
+  const int kcol = li < K ? kl[li] & 0xffff : 0;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int r = lk + 4 * v, c = li;
+    if (r >= KS || c >= KS) continue;
+    double val;
+    if (r < K && c < K) val = acc[v] + ((hopspin && r == hpos) ? Gj[kcol] : (r == c ? 1.0 : 0.0));
+    else val = r == c ? 1.0 : 0.0;
+    stage[r * (KS + 1) + c] = val;
+  }
 }
 
 // Stages the matrix (hop_det_stage) and returns its determinant by the

@@ -228,6 +228,9 @@ template <int P, int A> SVMC_DEV float layer_out_c(float x, float z) {
 template <int A> struct ActC {
   static constexpr int value = A;
 };
+template <int V> struct IntC {
+  static constexpr int value = V;
+};
 
 // One K chunk of a 16-bit mode: the B fragments b[nt] (weights, the MFMA A
 // operand) times this lane's 8 activations x (FP32, the B operand),

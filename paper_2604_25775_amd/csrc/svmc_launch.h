@@ -53,6 +53,7 @@ struct ElocOut {
   int stride;       // row stride of code/ratio
   double* part;     // [W][slices] partial sums (scratch)
   int slices;       // workgroups per walker
+  int row_form_max; // hops whose spins both change at most this many rows (0, 8 or 16) use the row form
 };
 size_t eloc_lowrank_smem(const LatDev* lats_host, int nlats, int prec, int L, int C);
 // Allocation-free local energies: the per-slice partial sums live in a fixed

@@ -30,3 +30,43 @@ def test_tune_cache_and_results(tmp_path):
     ctx2, _, _ = build([lat], model, [64], backflow=0.5)
     assert ctx2.tune(str(cache)) == s1
     assert len(cache.read_text().splitlines()) == 1
+
+
+@pytest.mark.parametrize("channels", [8, 16])
+def test_every_launch_variant_same_result(channels):
+    """All launch shapes the tuner chooses from give the same hop ratios and
+    local energies: within one determinant form the ratios are bit-identical
+    for every slice count (E_loc differs only by the slice-order summation),
+    and the row form (|K| x |K|) and column form (C + 1) agree to rounding
+    (Sylvester's identity); both forms match the oracle at 1e-10 (FP64).
+    One conv layer, so most hops change few rows (row form), a few more.
+    C = 8 is the width where the row form's staging (16 x 17 per wavefront)
+    is larger than the column form's and sets the LDS size."""
+    from gpu_util import check_walkers
+    lat = wl.Lattice(10, 9, 1, 0, 1.0, -0.2, 6.0, 24, 23)
+    model = wl.Model(1, channels, "tanh", "f64")
+    ctx, params, occs = build([lat], model, [6], backflow=0.5)
+    res = {}
+    for rf in (0, 8, 16):
+        for sl in (1, 2, 8, 32):
+            ctx.set_launch(sl, rf)
+            assert ctx.get_launch() == {"slices": sl, "row_form_max": rf}
+            e, nh, code, rat = ctx.local_energy(ratios=True)
+            res[(rf, sl)] = (e.cpu().numpy(), rat.cpu().numpy())
+    for rf in (0, 8, 16):
+        for sl in (2, 8, 32):
+            assert np.array_equal(res[(rf, sl)][1], res[(rf, 1)][1], equal_nan=True), (rf, sl)
+    base = res[(0, 1)][0]
+    for key, (e, _) in res.items():
+        assert np.max(np.abs(e - base) / np.maximum(1.0, np.abs(base))) < 1e-12, key
+    # the forms really differ in arithmetic (both are exercised)
+    assert not np.array_equal(res[(0, 1)][1], res[(16, 1)][1], equal_nan=True)
+    for rf in (0, 16):
+        ctx.set_launch(8, rf)
+        worst = check_walkers(ctx, [lat], params, occs, model, 1e-10, 1e-10)
+        say(f"[launch] C {channels} row_form_max {rf}: {worst}")
+    from paper_2604_25775_amd._lib import SvmcError
+    with pytest.raises(SvmcError):
+        ctx.set_launch(0, 16)
+    with pytest.raises(SvmcError):
+        ctx.set_launch(8, 12)
