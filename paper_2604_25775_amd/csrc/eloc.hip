@@ -199,21 +199,18 @@ __global__ __launch_bounds__(64 * ELOC_NW) __attribute__((amdgpu_waves_per_eu(3)
         const double f = hop_det_reduce<C>(stage, lane);
         if (lane == 0) misc[2] = f;
       }
-      __syncthreads();
-      // both C x C determinants by wavefront 0, one matrix per half
-      if (wv == 0) {
-        const double* sr = (const double*)scratch + (lane >> 5) * (C + 1) * DetTiles<C>::RS +
-                           ((lane & 31) < C ? (lane & 31) : 0) * DetTiles<C>::RS;
-        double a[C];
+      // each wavefront factors its own spin's C x C matrix (its own staging
+      // area: no barrier with the other wavefront), two lanes per row
+      {
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const int r = lane >> 1;
+        const double* sr = stage + (r < C ? r : 0) * DetTiles<C>::RS + (lane & 1);
+        double a[C / 2];
 #pragma unroll
-        for (int c2 = 0; c2 < C / 2; ++c2) {
-          const double2 v = reinterpret_cast<const double2*>(sr)[c2];
-          a[2 * c2] = (lane & 31) < C ? v.x : 0.0;
-          a[2 * c2 + 1] = (lane & 31) < C ? v.y : 0.0;
-        }
+        for (int j = 0; j < C / 2; ++j) a[j] = r < C ? sr[2 * j] : 0.0;
         __builtin_amdgcn_wave_barrier();
-        const double dt = lu_det_pair<C>(a, lane);
-        if ((lane & 31) == 0) misc[lane >> 5] = dt;
+        const double dt = lu_det_split<C>(a, lane);
+        if (lane == 0) misc[wv] = dt;
       }
       __syncthreads();
       }

@@ -113,8 +113,10 @@ template <int C> struct DStride {
 //   misc   64 bytes         per-spin results
 //   bias   [L][C] f32       conv biases (FP32 feature modes), filled once per
 //                           workgroup by hop_scratch_init
+//   emb    [4][C] Tf        the shared embedding table (first 4 C entries of
+//                           the embedding), filled once per workgroup
 struct HopScratch {
-  int klists, misc, bias, bytes;
+  int klists, misc, bias, emb, bytes;
 };
 __host__ __device__ inline int align16i(int x) { return (x + 15) & ~15; }
 __host__ __device__ inline HopScratch hop_scratch(int Gx, int Gy, int L, int C, int tfb) {
@@ -130,21 +132,26 @@ __host__ __device__ inline HopScratch hop_scratch(int Gx, int Gy, int L, int C, 
   h.klists = align16i(rb > sb ? rb : sb);
   h.misc = h.klists + align16i(2 * Gx * Gy * 4);
   h.bias = h.misc + 64;
-  h.bytes = h.bias + align16i(L * C * 4);
-  (void)tfb;
+  h.emb = h.bias + align16i(L * C * 4);
+  h.bytes = h.emb + align16i(4 * C * tfb);
   return h;
 }
 
-// Per-workgroup set-up of the hop scratch: the conv biases into LDS (FP32
-// feature modes).  All threads of the block call it; a barrier must follow
+// Per-workgroup set-up of the hop scratch: the conv biases (FP32 feature
+// modes) and the shared embedding table into LDS (with per-site tables the
+// copy is not used).  All threads of the block call it; a barrier must follow
 // before the first hop.
 template <int P>
 SVMC_DEV void hop_scratch_init(const ModelDev& md, char* scratch, const HopScratch& hs) {
-  if constexpr (sizeof(typename PrecT<P>::Tf) == 4) {
+  typedef typename PrecT<P>::Tf Tf;
+  if constexpr (sizeof(Tf) == 4) {
     const float* b = (const float*)md.bias;
     float* d = (float*)(scratch + hs.bias);
     for (int e = threadIdx.x; e < md.L * md.C; e += blockDim.x) d[e] = b[e];
   }
+  const Tf* E = (const Tf*)md.embed;
+  Tf* de = (Tf*)(scratch + hs.emb);
+  for (int e = threadIdx.x; e < 4 * md.C; e += blockDim.x) de[e] = E[e];
 }
 
 // B fragments of a layer kept in registers when they fit (<= 80 VGPRs).
@@ -462,11 +469,14 @@ SVMC_DEV void hop_features(const ModelDev& md, const LatDev& lt, const HopGeom& 
       int o = occ_s[s];
       if (s == h.i) o -= bit;
       if (s == h.j) o += bit;
-      const Tf* Es = E + lt.emb_off + (long long)s * lt.emb_ss + o * C + cv * V;
+      // one shared table: its LDS copy; per-site tables from memory
+      const float4 ev = lt.emb_ss == 0
+                            ? *reinterpret_cast<const float4*>((const Tf*)(scratch + hs.emb) + o * C + cv * V)
+                            : *reinterpret_cast<const float4*>(E + lt.emb_off + (long long)s * lt.emb_ss + o * C + cv * V);
       if constexpr (PL)
-        grid_put4<P, C>(grid, site, cv * V, *reinterpret_cast<const float4*>(Es));
+        grid_put4<P, C>(grid, site, cv * V, ev);
       else
-        *reinterpret_cast<float4*>(grid + site * SP + cv * V) = *reinterpret_cast<const float4*>(Es);
+        *reinterpret_cast<float4*>(grid + site * SP + cv * V) = ev;
     }
   }
   __syncthreads();
@@ -1018,6 +1028,65 @@ SVMC_DEV double lu_det_pair(double (&a)[C], int lane) {
   const bool odd = ((hi_half ? par_hi : par_lo) & 1u) != 0u;
   if (sing) return 0.0;
   return odd ? -det : det;
+}
+
+// Value of the other lane of this lane's pair (lanes 2 r and 2 r + 1), by a
+// DPP quad permutation (every lane active).
+SVMC_DEV double swap_pair_d(double x) {
+  const long long v = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(v & 0xffffffffLL), 0xB1, 0xF, 0xF, false);  // quad_perm 1,0,3,2
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(v >> 32), 0xB1, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// One C x C LU determinant per wavefront, two lanes per row: lane 2 r + h
+// holds the columns of parity h of row r (a[j] = A[r][2 j + h]; rows >= C
+// take no part).  Partial pivoting as in the LUs above (FP32-rounded |a|
+// keys, ties to the lower lane, a column below FP32's smallest normal counts
+// as zero), with the pivot searched over the lanes that hold column p.  The
+// pivot value is one lane read; a row's multiplier comes from its other lane
+// by a pair swap; each lane fetches the pivot row's entries of its own
+// parity by lane permutes.  At step p the registers from (p + 1) / 2 on are
+// updated in every lane: the one or two columns at or left of p this touches
+// are never read again.  The permutation sign is kept step by step as in
+// lu_det_pair.  Every lane returns the determinant.
+template <int C>
+SVMC_DEV double lu_det_split(double (&a)[C / 2], int lane) {
+  static_assert(C % 2 == 0 && C <= 32, "two lanes per row, at most 32 rows");
+  constexpr int J = C / 2;
+  const int row = lane >> 1, par = lane & 1;
+  bool used = row >= C;
+  double det = 1.0;
+  unsigned parity = 0;
+  bool sing = false;
+  auto key = [&](double v, int p) -> unsigned {
+    return (used || par != (p & 1)) ? 0u : ((__float_as_uint((float)fabs(v)) & ~63u) | (unsigned)(63 - lane));
+  };
+  unsigned kmax = wave_max_u32(key(a[0], 0));
+#pragma unroll
+  for (int p = 0; p < C; ++p) {
+    sing = sing || (kmax & ~63u) == 0u;
+    const int pl = 63 - (int)(kmax & 63u);      // pivot lane: row pl / 2, parity p & 1
+    const int prow = pl >> 1;
+    const double pv = readlane_d(a[p >> 1], pl);
+    det *= pv;
+    parity ^= (unsigned)__popcll(__ballot(!used && par == 0 && row < prow)) & 1u;
+    if (row == prow) used = true;
+    if (p + 1 < C) {
+      const double own = a[p >> 1];
+      const double other = swap_pair_d(own);
+      const double ap = par == (p & 1) ? own : other;
+      const double l = used ? 0.0 : ap * rcp_d(sing ? 1.0 : pv);
+      const int src = (2 * prow + par) << 2;
+      const int jn = (p + 1) >> 1;
+      a[jn] = fma(-l, bperm_d(src, a[jn]), a[jn]);
+      kmax = wave_max_u32(key(a[jn], p + 1));
+#pragma unroll
+      for (int j = jn + 1; j < J; ++j) a[j] = fma(-l, bperm_d(src, a[j]), a[j]);
+    }
+  }
+  if (sing) return 0.0;
+  return (parity & 1u) ? -det : det;
 }
 
 // The determinant-lemma matrix of spin tau in the row form (one wavefront),
