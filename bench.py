@@ -347,6 +347,81 @@ def speedup_table(prec, log):
 
 
 # ---------------------------------------------------------------------------
+# one launch over a mixed batch of lattices (ragged hop counts)
+# ---------------------------------------------------------------------------
+def mixed_launch(log, wname="c4"):
+    """E_loc/s of the mixed-lattice workload in one launch (after the
+    workload's thermalising sweeps), against the same walkers evaluated one
+    lattice per launch, with the launch's roofline fraction (conv at the
+    precision's peak, determinant work at FP64 peak)."""
+    import torch
+    import workloads as wls
+    from paper_2604_25775_amd.api import ScaleVMC
+    wl = wls.get(wname)
+    lats, counts, model = list(wl.lattices), list(wl.walkers), wl.model
+    params = wls.quantise_params(wls.random_params(lats, model, seed=wl.seed_params), model.conv_prec)
+    occs = [wls.occupations(wl, k, n_walkers=n) for k, n in enumerate(counts)]
+
+    def timed(ctx, W):
+        e = torch.empty(W, dtype=torch.float64, device="cuda")
+        ctx.tune()
+        ctx.local_energy(out=e)
+        t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0.record()
+        for _ in range(3):
+            ctx.prepare()
+            ctx.local_energy(out=e)
+        t1.record()
+        torch.cuda.synchronize()
+        return t0.elapsed_time(t1) / 3, ctx.get_launch()
+
+    ctx = ScaleVMC(lats, model.n_conv, model.channels, model.act, model.conv_prec, model.refresh_every)
+    ctx.set_params_from(params)
+    ctx.load(counts, np.concatenate([o.reshape(-1) for o in occs]).astype(np.int8))
+    if wl.sweeps:
+        ctx.sweep(wl.sweeps, wl.seed_mc, 0)
+    occ_all, _ = ctx.state()
+    occ_all = occ_all.cpu().numpy()
+    mixed_ms, launch = timed(ctx, sum(counts))
+    del ctx
+    single_ms, off, conv_f, det_f, hops = [], 0, 0.0, 0.0, []
+    for k, (lat, n) in enumerate(zip(lats, counts)):
+        occ_k = occ_all[off: off + n * lat.N].reshape(n, lat.N)
+        off += n * lat.N
+        c1, d1 = lowrank_flops(lat, occ_k, model.n_conv, model.channels)
+        conv_f, det_f = conv_f + c1, det_f + d1
+        hops.append(float(np.mean(ctx_hops(lat, occ_k))))
+        sctx = ScaleVMC([lat], model.n_conv, model.channels, model.act, model.conv_prec, model.refresh_every)
+        sctx.set_params_from(params_for(params, k))
+        sctx.load([n], occ_k)
+        single_ms.append(timed(sctx, n)[0])
+        del sctx
+    conv_peak = {"f32": PEAK_FP32, "f64": PEAK_FP64}.get(model.conv_prec, PEAK_BF16)
+    t_peak = conv_f / conv_peak + det_f / PEAK_FP64
+    W = sum(counts)
+    row = {"workload": f"{wname}: " + " + ".join(f"{l.Lx}x{l.Ly} ({n} walkers, {h:.0f} hops each)"
+                                                 for l, n, h in zip(lats, counts, hops))
+           + f", {model.n_conv} conv x {model.channels} ch, conv {model.conv_prec}",
+           "eloc_per_s": round(W / (mixed_ms / 1e3), 1), "launch_ms": round(mixed_ms, 3),
+           "launch": launch, "roofline_frac": round(t_peak / (mixed_ms / 1e3), 4),
+           "one_lattice_per_launch_ms": [round(t, 3) for t in single_ms],
+           "mixed_vs_separate": round(sum(single_ms) / mixed_ms, 3)}
+    log(f"[bench] {wname} mixed batch: one launch {mixed_ms:.2f} ms ({row['eloc_per_s']:.0f} E_loc/s, "
+        f"{row['roofline_frac']:.3f} of roofline) vs {sum(single_ms):.2f} ms one lattice per launch")
+    return row
+
+
+def params_for(params, k):
+    """The parameters of a mixed batch restricted to lattice k (shared conv,
+    that lattice's projection, base orbitals and per-site embedding)."""
+    q = params.copy()
+    q.proj_w, q.proj_b, q.base = [params.proj_w[k]], [params.proj_b[k]], [params.base[k]]
+    if q.embed_site is not None:
+        q.embed_site = [params.embed_site[k]]
+    return q
+
+
+# ---------------------------------------------------------------------------
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -364,7 +439,8 @@ def main():
     ap.add_argument("--no-grad", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-speedup-table", action="store_true",
-                    help="skip the low-rank vs full-recompute rows of the other workloads")
+                    help="skip the low-rank vs full-recompute rows of the other workloads "
+                         "and the mixed-lattice launch")
     ap.add_argument("--tune-cache", default=None,
                     help="autotuner cache file (default: tune, do not store)")
     ap.add_argument("--traffic-probe", action="store_true",
@@ -554,6 +630,7 @@ def main():
 
     if not a.no_speedup_table:
         extra["speedup_table"] = speedup_table(a.prec, log)
+        extra["mixed_lattice_launch"] = mixed_launch(log)
 
     cpu = None
     if not a.no_cpu and a.cpu_sample > 0:

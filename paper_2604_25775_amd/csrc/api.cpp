@@ -906,7 +906,8 @@ svmc_status svmc_tune(svmc_ctx* ctx, const char* cache_path, int32_t* slices_out
   const int cand[7] = {1, 2, 4, 8, 16, 24, 32};
   const int forms[3] = {0, 8, 16};
   int best = ctx->eloc_slices, best_rf = ctx->row_form_max;
-  float best_ms = 1e30f;
+  float best_ms = 1e30f, tv[21];
+  int nv = 0;
   std::ostringstream times;
   for (int v = 0; v < 21 && !s; ++v) {
     const int c = cand[v % 7], rf = forms[v / 7];
@@ -924,14 +925,26 @@ svmc_status svmc_tune(svmc_ctx* ctx, const char* cache_path, int32_t* slices_out
     if ((s = ctx->hip(hipEventElapsedTime(&ms, e0, e1), "event time"))) break;
     ms *= 0.5f;
     times << " " << c << "/" << rf << ":" << ms;
-    if (ms < best_ms) {
-      best_ms = ms;
-      best = c;
-      best_rf = rf;
-    }
+    tv[nv++] = ms;
+    best_ms = std::min(best_ms, ms);
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
+  // among the shapes within 2 % of the fastest (timing noise), the fewest
+  // slices per walker, then the largest row-form limit: the choice does not
+  // flip between runs on differences the timer cannot resolve
+  if (!s) {
+    bool have = false;
+    for (int v = 0; v < nv; ++v) {
+      const int c = cand[v % 7], rf = forms[v / 7];
+      if (tv[v] > 1.02f * best_ms) continue;
+      if (!have || c < best || (c == best && rf > best_rf)) {
+        best = c;
+        best_rf = rf;
+        have = true;
+      }
+    }
+  }
   ctx->eloc_slices = best;
   ctx->row_form_max = best_rf;
   if (s) return s;

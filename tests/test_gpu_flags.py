@@ -6,6 +6,14 @@
   sign 0, a NaN local energy, no Metropolis move and a NaN gradient row left
   out of the VJP; walkers of the other lattice in the same batch are
   unaffected (1e-10 against the oracle).
+* NONFINITE: lattice 0's per-site embedding rows of the doubly occupied
+  state set to 1e300 (finite: set_params refuses NaN and infinity), walkers
+  loaded without any doubly occupied site: log|psi| is finite at load, but a
+  hop onto a site held by the other spin changes one orbital row of each
+  spin by about 1e300, so the product of the two determinant ratios
+  overflows: the local energy flags those walkers (their E_loc is not
+  finite); the lattice with an ordinary table matches the oracle, flagged
+  walkers are not moved by a sweep and stay out of the VJP.
 * DRIFT: two spin-up orbitals that differ by 1e-11 at every site (Phi
   conditioned near 1e11), so G = M Phi^-1 misses its exact unit rows at the
   occupied sites by far more than 1e-8: a refresh over current G flags the
@@ -26,10 +34,23 @@ LATS = [wl.Lattice(4, 4, 1, 1, 1.0, 0.0, 4.0, 5, 5), wl.Lattice(5, 4, 1, 0, 1.0,
 COUNTS = [3, 4]
 
 
-def make_ctx(params, model):
+def disjoint_occupations(lat, n_walkers, seed):
+    """Occupations with no doubly occupied site (n_up + n_dn <= N)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    occ = np.zeros((n_walkers, lat.N), dtype=np.int8)
+    for w in range(n_walkers):
+        perm = rng.permutation(lat.N)
+        occ[w, perm[: lat.n_up]] = 1
+        occ[w, perm[lat.n_up: lat.n_up + lat.n_dn]] = 2
+    return occ
+
+
+def make_ctx(params, model, occs=None):
     from paper_2604_25775_amd.api import ScaleVMC
-    occs = [wl.random_occupations(l, n, seed=11 + k) for k, (l, n) in enumerate(zip(LATS, COUNTS))]
-    ctx = ScaleVMC(LATS, model.n_conv, model.channels, model.act, model.conv_prec, model.refresh_every)
+    if occs is None:
+        occs = [wl.random_occupations(l, n, seed=11 + k) for k, (l, n) in enumerate(zip(LATS, COUNTS))]
+    ctx = ScaleVMC(LATS, model.n_conv, model.channels, model.act, model.conv_prec, model.refresh_every,
+                   per_site_embed=model.per_site_embed)
     ctx.set_params_from(params)
     ctx.load(COUNTS, np.concatenate([o.reshape(-1) for o in occs]).astype(np.int8))
     torch.cuda.synchronize()
@@ -68,6 +89,38 @@ def test_singular_orbital_lattice_flagged():
     assert (n_acc[:3] == 0).all() and n_acc[3:].sum() > 0
     assert torch.equal(occ0[:3 * N0], occ1[:3 * N0])
     assert (ctx.flags().cpu().numpy()[:3] & 1).all()
+
+
+def test_overflowing_ratio_flags_nonfinite():
+    model = wl.Model(2, 8, "tanh", "f64", 32, per_site_embed=True)
+    p = wl.random_params(LATS, model, seed=5, backflow=0.5)
+    p.embed_site[0][:, 3, :] = 1e300
+    occs = [disjoint_occupations(l, n, seed=21 + k) for k, (l, n) in enumerate(zip(LATS, COUNTS))]
+    say("[flags] 1e300 embedding of the doubly occupied state on lattice 0")
+    ctx, occs = make_ctx(p, model, occs)
+    f = ctx.flags().cpu().numpy()
+    assert not f.any(), f
+    s, la = (t.cpu().numpy() for t in ctx.log_psi())
+    assert np.isfinite(la).all() and (np.abs(s) == 1.0).all()
+    e = ctx.local_energy().cpu().numpy()
+    f = ctx.flags().cpu().numpy()
+    say(f"  flags after the local energy {f.tolist()}")
+    assert (f[:3] == 2).all() and not f[3:].any(), f
+    assert not np.isfinite(e[:3]).any() and np.isfinite(e[3:]).all()
+    from oracle.energy import local_energy
+    for kk, o in enumerate(occs[1]):
+        ref = local_energy(LATS[1], p, o, 1, model.act)
+        assert abs(e[3 + kk] - ref) <= 1e-10 * max(1.0, abs(ref))
+    v = torch.ones(sum(COUNTS), dtype=torch.float64, device="cuda")
+    g = ctx.grad_logpsi(v).cpu().numpy()
+    J = ctx.grad_logpsi().cpu().numpy()
+    assert np.allclose(g, J[3:].sum(0), rtol=1e-12, atol=1e-12)
+    occ0, _ = ctx.state()
+    n_acc = ctx.sweep(2, 9, 0).cpu().numpy()
+    occ1, _ = ctx.state()
+    N0 = LATS[0].N
+    assert (n_acc[:3] == 0).all() and n_acc[3:].sum() > 0
+    assert torch.equal(occ0[:3 * N0], occ1[:3 * N0])
 
 
 def test_nearly_dependent_orbitals_flag_drift():
