@@ -66,13 +66,13 @@ def kernel_src_sha1() -> str:
     return h.hexdigest()
 
 
-def traffic_record(workload: str, walkers: int, prec: str, slices: int):
+def traffic_record(workload: str, walkers: int, prec: str, slices: int, row_form_max: int = 16):
     """HBM bytes per E_loc launch from a committed counter summary
     (a `traffic-record:` line under profiles/): FETCH_SIZE and WRITE_SIZE of
     the launch, each scaled by bytes / counter of a plain copy of known size
     in the same run.  None when no record matches this workload and launch
-    shape (slices per walker), or the sources have changed since the
-    counters were taken."""
+    shape (slices per walker, row-form limit), or the sources have changed
+    since the counters were taken."""
     d = os.path.join(ROOT, "profiles")
     if not os.path.isdir(d):
         return None
@@ -87,7 +87,7 @@ def traffic_record(workload: str, walkers: int, prec: str, slices: int):
                 r = json.loads(ln.split(":", 1)[1])
                 if (r.get("src_sha1") == sha and r.get("workload") == workload
                         and r.get("walkers") == walkers and r.get("prec") == prec
-                        and r.get("slices") == slices):
+                        and r.get("slices") == slices and r.get("row_form_max", 16) == row_form_max):
                     fetch = r["fetch_kib"] * COPY_PROBE_BYTES / r["copy_fetch_kib"]
                     write = r["write_kib"] * COPY_PROBE_BYTES / r["copy_write_kib"]
                     return {"bytes": fetch + write, "fetch_bytes": fetch, "write_bytes": write, "file": f,
@@ -441,6 +441,8 @@ def main():
     ap.add_argument("--no-speedup-table", action="store_true",
                     help="skip the low-rank vs full-recompute rows of the other workloads "
                          "and the mixed-lattice launch")
+    ap.add_argument("--launch", default=None, metavar="SLICES,ROWFORM",
+                    help="fixed E_loc launch shape (svmc_set_launch) instead of the autotuner")
     ap.add_argument("--tune-cache", default=None,
                     help="autotuner cache file (default: tune, do not store)")
     ap.add_argument("--traffic-probe", action="store_true",
@@ -486,7 +488,12 @@ def main():
         occ_t, _ = ctx.state()
         occ = occ_t.cpu().numpy().reshape(W, lat.N)
 
-    slices = ctx.tune(a.tune_cache)
+    if a.launch:
+        sl_, rf_ = (int(v) for v in a.launch.split(","))
+        ctx.set_launch(sl_, rf_)
+        slices = sl_
+    else:
+        slices = ctx.tune(a.tune_cache)
     rfm = ctx.get_launch()["row_form_max"]
     extra["eloc_slices_per_walker"] = slices
     extra["eloc_row_form_max"] = rfm
@@ -538,7 +545,7 @@ def main():
     kern_s = kern_ms / 1e3
     achieved = (conv_f + det_f) / kern_s / 1e12
     peak = (conv_f + det_f) / t_peak / 1e12
-    tr = traffic_record(wl.name, W, a.prec, slices)
+    tr = traffic_record(wl.name, W, a.prec, slices, rfm)
     roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": round(peak, 3),
                 "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
                 "traffic": round(tr["bytes"]) if tr else None,

@@ -142,7 +142,11 @@ __global__ __launch_bounds__(64 * ELOC_NW) __attribute__((amdgpu_waves_per_eu(3)
   int* kl = (int*)(scratch + hsc.klists) + wv * KM;
   double* misc = (double*)(scratch + hsc.misc);
 
-  double part = 0.0;
+  // the slice's running sum sits in LDS, read and written by thread 0 only:
+  // as a register it is held by every lane through the hop loop (and spilled
+  // around the conv, one scratch store per hop)
+  double* part_s = red + 7;
+  if (tid == 0) *part_s = 0.0;
   bool nonfinite = false;
   if (!bad) {
     for (int hh = h0; hh < h1; ++hh) {
@@ -216,7 +220,7 @@ __global__ __launch_bounds__(64 * ELOC_NW) __attribute__((amdgpu_waves_per_eu(3)
       }
       if (tid == 0) {
         const double R = misc[0] * misc[1] * misc[2];
-        part += -(d < 4 ? lt.t : lt.tp) * R;
+        *part_s += -(d < 4 ? lt.t : lt.tp) * R;
         nonfinite |= !isfinite(R);
         if (out.ratio) {
           out.ratio[w * out.stride + hh] = R;
@@ -226,6 +230,7 @@ __global__ __launch_bounds__(64 * ELOC_NW) __attribute__((amdgpu_waves_per_eu(3)
     }
   }
   if (tid == 0) {
+    double part = *part_s;
     if (nonfinite) atomicOr(bf.flags + w, 2);
     if (slice == 0) {
       // the U term and the per-walker outputs go with slice 0

@@ -55,3 +55,18 @@ def test_source_hash_covers_every_source_file():
     assert srcs, "no library sources found"
     h1 = bench.kernel_src_sha1()
     assert len(h1) == 40 and h1 == bench.kernel_src_sha1()
+
+
+def test_record_keyed_by_row_form_limit(tmp_path, monkeypatch):
+    root = _record(tmp_path, "a" * 40, row_form_max=8)
+    monkeypatch.setattr(bench, "ROOT", str(root))
+    monkeypatch.setattr(bench, "kernel_src_sha1", lambda: "a" * 40)
+    assert bench.traffic_record("c3", 8192, "f16x2", 24, 8) is not None
+    assert bench.traffic_record("c3", 8192, "f16x2", 24, 16) is None
+    # a record without the field was taken at the default limit (16)
+    root2 = tmp_path / "r2"
+    root2.mkdir()
+    _record(root2, "a" * 40)
+    monkeypatch.setattr(bench, "ROOT", str(root2))
+    assert bench.traffic_record("c3", 8192, "f16x2", 24, 16) is not None
+    assert bench.traffic_record("c3", 8192, "f16x2", 24, 0) is None
