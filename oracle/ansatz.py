@@ -11,7 +11,12 @@
                                                 padding follows the lattice
                                                 boundary: wrap on periodic axes,
                                                 zeros on open axes)
-  projection  row_s(s) = base_s[s] + H_L[s] W_s + b_s
+  site-wise   H_{L+m+1}[s] = act(H_{L+m}[s] W_m + b_m),  m = 0 .. M-1
+  MLP                                          (Sec. II.B, site-wise MLP
+                                                equation, no residual, weights
+                                                C x C as that equation writes
+                                                them; absent when M = 0)
+  projection  row_s(s) = base_s[s] + H_F[s] W_s + b_s   (H_F the last of these)
                                                (Sec. II.B, orbital projection,
                                                 one block per spin)
   amplitude   psi(n) = det Phi_up * det Phi_dn, Phi_s = rows of the sites
@@ -58,7 +63,8 @@ def embedding(params, occ, lat_index: int = 0) -> np.ndarray:
 
 
 def features(lat, params, occ, act: str = "tanh", conv_input_round=None, lat_index: int = 0) -> list:
-    """[H_0, H_1, ..., H_L], each [N, C] FP64.
+    """[H_0, H_1, ..., H_L, H_{L+1}, ..., H_{L+M}], each [N, C] FP64: the
+    conv layers, then the site-wise MLP layers (params.mlp_w, when present).
 
     conv_input_round: optional function applied to the layer input before it
     enters the convolution (not to the residual branch); used to model a conv
@@ -77,6 +83,9 @@ def features(lat, params, occ, act: str = "tanh", conv_input_round=None, lat_ind
             x[valid] = Hin[nb[valid]]
             acc = acc + x @ params.conv_w[l, ky, kx]
         H = H + activation(act, acc)
+        out.append(H)
+    for W, b in zip(getattr(params, "mlp_w", None) or [], getattr(params, "mlp_b", None) or []):
+        H = activation(act, H @ W + b[None, :])
         out.append(H)
     return out
 

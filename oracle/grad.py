@@ -9,6 +9,7 @@ two independent routes:
 Flat parameter order (theta):
   embed [4, C] (or, with per-site tables, [N_l, 4, C] of every lattice l) |
   conv_w [L, 3, 3, C, C] | conv_b [L, C] |
+  mlp_w [M, C, C] | mlp_b [M, C]   (site-wise layers; absent when M = 0) |
   for each lattice: proj_w up [C, N_up] | proj_w down [C, N_dn] |
                     proj_b up [N_up] | proj_b down [N_dn]
 Each block is row-major.  Base orbitals are inputs, not parameters.
@@ -23,6 +24,7 @@ from .ansatz import log_psi, occupied_sites
 def pack(params) -> np.ndarray:
     emb = [params.embed.ravel()] if params.embed_site is None else [e.ravel() for e in params.embed_site]
     parts = emb + [params.conv_w.ravel(), params.conv_b.ravel()]
+    parts += [w.ravel() for w in (params.mlp_w or [])] + [b.ravel() for b in (params.mlp_b or [])]
     for pw, pb in zip(params.proj_w, params.proj_b):
         parts += [pw[0].ravel(), pw[1].ravel(), pb[0].ravel(), pb[1].ravel()]
     return np.concatenate(parts).astype(np.float64)
@@ -45,6 +47,9 @@ def unpack(theta: np.ndarray, like):
         p.embed_site = [take(e.shape) for e in like.embed_site]
     p.conv_w = take(like.conv_w.shape)
     p.conv_b = take(like.conv_b.shape)
+    if like.mlp_w:
+        p.mlp_w = [take(w.shape) for w in like.mlp_w]
+        p.mlp_b = [take(b.shape) for b in like.mlp_b]
     for li in range(len(like.proj_w)):
         p.proj_w[li] = [take(like.proj_w[li][0].shape), take(like.proj_w[li][1].shape)]
         p.proj_b[li] = [take(like.proj_b[li][0].shape), take(like.proj_b[li][1].shape)]
@@ -89,6 +94,9 @@ def _torch_log_psi(lat, theta, like, occ, lat_index: int, act: str):
         Es = [take(e.shape) for e in like.embed_site]
     K = take((L, 3, 3, C, C))
     b = take((L, C))
+    M = len(like.mlp_w or [])
+    MW = [take((C, C)) for _ in range(M)]
+    MB = [take((C,)) for _ in range(M)]
     proj = []
     for li in range(len(like.proj_w)):
         nu, nd = like.proj_w[li][0].shape[1], like.proj_w[li][1].shape[1]
@@ -107,6 +115,9 @@ def _torch_log_psi(lat, theta, like, occ, lat_index: int, act: str):
         y = F.conv2d(xp, K[l].permute(3, 2, 0, 1), b[l])       # weights [cout, cin, ky, kx]
         x = x + (torch.tanh(y) if act == "tanh" else F.silu(y))
     HL = x.reshape(C, lat.N).T
+    for W, bb in zip(MW, MB):
+        y = F.linear(HL, W.T, bb)                            # H W + b, site by site
+        HL = torch.tanh(y) if act == "tanh" else F.silu(y)
     Wu, Wd, bu, bd = proj[lat_index]
     tot = theta.new_zeros(())
     for s, (W, bb) in enumerate(((Wu, bu), (Wd, bd))):

@@ -54,6 +54,7 @@ class Model:
     conv_prec: str = "f64"          # f64 | f32 | bf16 | bf16x3 | f16x2
     refresh_every: int = 32
     per_site_embed: bool = False    # one embedding table per site (else shared)
+    n_mlp: int = 0                  # site-wise C x C layers after the conv stack
 
 
 @dataclass(frozen=True)
@@ -122,6 +123,8 @@ class Params:
     proj_w per lattice: [2][C, N_sigma]   (spin up, spin down)
     proj_b per lattice: [2][N_sigma]
     base   per lattice: [2][N, N_sigma]   (fixed input, not trained)
+    mlp_w  None, or [M] of [C, C]  site-wise layers after the conv stack
+    mlp_b  None, or [M] of [C]
     """
     embed: np.ndarray
     conv_w: np.ndarray
@@ -130,13 +133,17 @@ class Params:
     proj_b: List[List[np.ndarray]]
     base: List[List[np.ndarray]] = field(default_factory=list)
     embed_site: List[np.ndarray] | None = None
+    mlp_w: List[np.ndarray] | None = None
+    mlp_b: List[np.ndarray] | None = None
 
     def copy(self) -> "Params":
         return Params(self.embed.copy(), self.conv_w.copy(), self.conv_b.copy(),
                       [[a.copy() for a in p] for p in self.proj_w],
                       [[a.copy() for a in p] for p in self.proj_b],
                       [[a.copy() for a in p] for p in self.base],
-                      None if self.embed_site is None else [e.copy() for e in self.embed_site])
+                      None if self.embed_site is None else [e.copy() for e in self.embed_site],
+                      None if self.mlp_w is None else [w.copy() for w in self.mlp_w],
+                      None if self.mlp_b is None else [b.copy() for b in self.mlp_b])
 
 
 def _axis_modes(L: int, periodic: bool):
@@ -197,7 +204,9 @@ def random_params(lats: Sequence[Lattice], model: Model, seed: int = 0,
     ~ N(0, 1); the projection is scaled so that the backflow term is about
     ``backflow`` times the magnitude of a base-orbital entry.  With
     model.per_site_embed, per-site embedding tables ~ N(0, 1) are drawn after
-    everything else (the other parameters are the same as without)."""
+    everything else (the other parameters are the same as without); with
+    model.n_mlp > 0 the site-wise layers are drawn after that, weights
+    ~ N(0, 1/C) (unit-variance outputs) and biases ~ N(0, 0.05^2)."""
     rng = np.random.Generator(np.random.PCG64(seed))
     C, L = model.channels, model.n_conv
     embed = rng.standard_normal((4, C))
@@ -218,7 +227,11 @@ def random_params(lats: Sequence[Lattice], model: Model, seed: int = 0,
     site = None
     if model.per_site_embed:
         site = [rng.standard_normal((lat.N, 4, C)) for lat in lats]
-    return Params(embed, conv_w, conv_b, proj_w, proj_b, base, site)
+    mw = mb = None
+    if model.n_mlp:
+        mw = [rng.standard_normal((C, C)) / math.sqrt(C) for _ in range(model.n_mlp)]
+        mb = [0.05 * rng.standard_normal(C) for _ in range(model.n_mlp)]
+    return Params(embed, conv_w, conv_b, proj_w, proj_b, base, site, mw, mb)
 
 
 def quantise_params(p: Params, prec: str) -> Params:
@@ -235,6 +248,13 @@ def quantise_params(p: Params, prec: str) -> Params:
         setattr(q, name, a)
     if q.embed_site is not None:
         q.embed_site = [torch.from_numpy(e).to(dt).to(torch.float64).numpy() for e in q.embed_site]
+    if q.mlp_w is not None:
+        # site-wise layers: weights as the conv kernels, biases as the conv biases
+        q.mlp_w = [torch.from_numpy(w).to(dt).to(torch.float64).numpy() for w in q.mlp_w]
+        q.mlp_b = [torch.from_numpy(b).to(dt).to(torch.float64).numpy() for b in q.mlp_b]
+        if prec == "f16x2":
+            q.mlp_w = [torch.from_numpy(w).to(torch.bfloat16).to(torch.float16).to(torch.float64).numpy()
+                       for w in p.mlp_w]
     if prec == "f16x2":
         # the BF16 conv weights carried in FP16 (exact in FP16's normal range),
         # the embedding as an FP16 pair, FP32 bias
