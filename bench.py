@@ -98,10 +98,12 @@ def traffic_record(workload: str, walkers: int, prec: str, slices: int, row_form
 # ---------------------------------------------------------------------------
 # algorithmic work of the low-rank kernel (accounting only, numpy)
 # ---------------------------------------------------------------------------
-def lowrank_flops(lat, occ: np.ndarray, L: int, C: int):
+def lowrank_flops(lat, occ: np.ndarray, L: int, C: int, n_mlp: int = 0):
     """(conv FLOPs, FP64 determinant FLOPs) of one low-rank local-energy
     launch: per hop, layer l recomputes the sites within Chebyshev distance l
-    of the two changed sites (9 C^2 multiply-adds each); per spin, k electrons
+    of the two changed sites (9 C^2 multiply-adds each), and each of the
+    n_mlp site-wise layers the sites of layer L (C^2 each; counted with the
+    conv work, same precision); per spin, k electrons
     of the new configuration lie within distance L, the determinant-lemma
     matrix has rank r = min(k, C + [moving spin]), its assembly costs k C r
     and its LU r^3 / 3 multiply-adds."""
@@ -183,6 +185,8 @@ def lowrank_flops(lat, occ: np.ndarray, L: int, C: int):
                     _, wy = axis_range(ys, yj, l, Ly, lat.pbc_y)
                     sites = wx * wy
                 conv += float((valid * sites[None, :]).sum()) * 9 * C * C * 2
+                if l == L:
+                    conv += float((valid * sites[None, :]).sum()) * n_mlp * C * C * 2
             if diag:
                 if L not in balls:
                     balls[L] = ball_mask(L)
@@ -271,9 +275,10 @@ def cpu_model():
 # ---------------------------------------------------------------------------
 SPEEDUP_ROWS = [
     # name, workload, conv layers (None: the workload's), walkers (low-rank),
-    # walkers for the full path (a prefix of the same batch)
-    ("16x16, 1 conv layer", "c3", 1, 8192, 1024),
-    ("32x32 448+448, 4 conv layers", "c5", None, 1024, 4),
+    # walkers for the full path (a prefix of the same batch), other model fields
+    ("16x16, 1 conv layer", "c3", 1, 8192, 1024, {}),
+    ("16x16, 1 conv layer + 4 site-wise layers, SiLU", "c3", 1, 8192, 1024, {"n_mlp": 4, "act": "silu"}),
+    ("32x32 448+448, 4 conv layers", "c5", None, 1024, 4, {}),
 ]
 
 
@@ -286,13 +291,14 @@ def speedup_table(prec, log):
     import workloads as wls
     from paper_2604_25775_amd.api import ScaleVMC
     out = []
-    for name, wname, layers, W, FW in SPEEDUP_ROWS:
+    for name, wname, layers, W, FW, more in SPEEDUP_ROWS:
         wl = wls.get(wname)
         lat = wl.lattices[0]
-        model = replace(wl.model, conv_prec=prec, **({"n_conv": layers} if layers else {}))
+        model = replace(wl.model, conv_prec=prec, **({"n_conv": layers} if layers else {}), **more)
         params = wls.quantise_params(wls.random_params([lat], model, seed=wl.seed_params), prec)
         occ = wls.occupations(wl, 0, n_walkers=W)
-        ctx = ScaleVMC([lat], model.n_conv, model.channels, model.act, prec, model.refresh_every)
+        ctx = ScaleVMC([lat], model.n_conv, model.channels, model.act, prec, model.refresh_every,
+                       n_mlp=model.n_mlp)
         ctx.set_params_from(params)
         ctx.load([W], occ)
         e = torch.empty(W, dtype=torch.float64, device="cuda")
@@ -307,7 +313,8 @@ def speedup_table(prec, log):
         torch.cuda.synchronize()
         low_ms = t0.elapsed_time(t1) / 3
         del ctx
-        fctx = ScaleVMC([lat], model.n_conv, model.channels, model.act, prec, model.refresh_every)
+        fctx = ScaleVMC([lat], model.n_conv, model.channels, model.act, prec, model.refresh_every,
+                        n_mlp=model.n_mlp)
         fctx.set_params_from(params)
         fctx.load([FW], occ[:FW])
         fe = torch.empty(FW, dtype=torch.float64, device="cuda")
@@ -322,11 +329,11 @@ def speedup_table(prec, log):
         agree = float(np.max(np.abs(fe.cpu().numpy() - e2.cpu().numpy()) / np.maximum(1.0, np.abs(e2.cpu().numpy()))))
         del fctx
         low_rate, full_rate = W / (low_ms / 1e3), FW / (full_ms / 1e3)
-        conv_f, det_f = lowrank_flops(lat, occ, model.n_conv, model.channels)
+        conv_f, det_f = lowrank_flops(lat, occ, model.n_conv, model.channels, model.n_mlp)
         conv_peak = PEAK_BF16 if prec in ("bf16", "bf16x3", "f16x2") else (PEAK_FP32 if prec == "f32" else PEAK_FP64)
         t_low = conv_f / conv_peak + det_f / PEAK_FP64
         nhop = float(np.sum(ctx_hops(lat, occ[:FW])))
-        conv_full = nhop * model.n_conv * lat.N * 9 * model.channels ** 2 * 2
+        conv_full = nhop * (9 * model.n_conv + model.n_mlp) * lat.N * model.channels ** 2 * 2
         fp64_full = nhop * sum(2.0 * n * n * model.channels + 2.0 / 3.0 * n ** 3 for n in (lat.n_up, lat.n_dn))
         t_full = conv_full / conv_peak + fp64_full / PEAK_FP64
         row = {"workload": f"{name} ({wname}, Hubbard {lat.Lx}x{lat.Ly}, {model.channels} ch, {prec})",

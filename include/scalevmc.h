@@ -91,9 +91,13 @@ typedef struct {
 /* Network shape (Sec. II.B): an embedding layer, n_conv residual ksize x
  * ksize conv layers (1..4) of `channels` channels (8, 16, 24 or 32),
  * activation svmc_act, conv precision svmc_prec, then n_mlp site-wise MLP
- * layers (Sec. II.B, site-wise MLP equation) before the orbital projection.
- * refresh_every = accepted Metropolis moves between FP64 inverse rebuilds
- * (>= 1).  ksize must be 3 and n_mlp 0 (other values: SVMC_ERR_UNSUPPORTED).
+ * layers (Sec. II.B, site-wise MLP equation: H <- act(H W_m + b_m) at every
+ * site, no residual, W_m of size channels x channels as that equation
+ * writes it, the same activation) before the orbital projection; they
+ * leave the receptive field at n_conv, so the local update still touches
+ * only the conv layers' boxes.  refresh_every = accepted Metropolis moves
+ * between FP64 inverse rebuilds (>= 1).  ksize must be 3 and n_mlp in 0..8
+ * (ksize != 3 or n_mlp > 8: SVMC_ERR_UNSUPPORTED; n_mlp < 0: INVALID_ARG).
  * per_site_embed = 0: one embedding table E[4][C] shared by all sites;
  * 1: a table E_i[4][C] per site i (the embedding layer as Sec. II.B writes
  * it), per lattice of the context. */
@@ -116,11 +120,13 @@ svmc_status svmc_destroy(svmc_ctx* ctx);
 /* Length of the flat parameter vector theta:
  *   embed | conv_w[L][3][3][C][C] (ky, kx, c_in, c_out; tap (ky,kx)
  *   reads the neighbour at offset (kx-1, ky-1)) | conv_b[L][C] |
+ *   mlp_w[M][C][C] (c_in, c_out) | mlp_b[M][C] |
  *   for each lattice: W_up[C][n_up] | W_dn[C][n_dn] | b_up[n_up] | b_dn[n_dn]
  * all row-major FP64, with embed = E[4][C] (shared table) or, with
  * per_site_embed, E_l[N_l][4][C] for each lattice l in order (site, then
  * occupation n_up + 2 n_dn).  Row of spin s at site x:
- * base_s[x] + H_L[x] W_s + b_s. */
+ * base_s[x] + H_F[x] W_s + b_s, H_F the last site-wise layer's output (the
+ * last conv layer's when M = 0). */
 int64_t svmc_num_params(const svmc_ctx* ctx);
 
 /* Upload parameters.  theta: device, svmc_num_params doubles (layout above).

@@ -27,15 +27,18 @@ def _stream():
 
 def pack_params(params, lattices) -> np.ndarray:
     """Flat FP64 parameter vector in the library's layout:
-    embed | conv_w | conv_b | per lattice: W_up | W_dn | b_up | b_dn, where
-    embed is the shared [4, C] table or, when params.embed_site is set, the
-    per-site tables [N_l, 4, C] of every lattice in order."""
+    embed | conv_w | conv_b | mlp_w | mlp_b | per lattice: W_up | W_dn | b_up
+    | b_dn, where embed is the shared [4, C] table or, when params.embed_site
+    is set, the per-site tables [N_l, 4, C] of every lattice in order, and
+    mlp_w / mlp_b the site-wise layers ([M][C][C], [M][C]; empty when M = 0)."""
     site = getattr(params, "embed_site", None)
     emb = ([np.asarray(e, np.float64).ravel() for e in site] if site is not None
            else [np.asarray(params.embed, np.float64).ravel()])
     parts = emb + [
              np.asarray(params.conv_w, np.float64).ravel(),
              np.asarray(params.conv_b, np.float64).ravel()]
+    parts += [np.asarray(w, np.float64).ravel() for w in (getattr(params, "mlp_w", None) or [])]
+    parts += [np.asarray(b, np.float64).ravel() for b in (getattr(params, "mlp_b", None) or [])]
     for li, _ in enumerate(lattices):
         parts += [np.asarray(params.proj_w[li][0], np.float64).ravel(),
                   np.asarray(params.proj_w[li][1], np.float64).ravel(),

@@ -83,6 +83,7 @@ struct svmc_ctx {
   std::vector<svmc_lattice> lats;
   svmc_model model{};
   int prec = 0, L = 0, C = 0;
+  int nmlp = 0;            // site-wise layers after the conv stack
   long long emb_len = 0;   // length of the embedding block of theta
   std::string err;
   int64_t nparams = 0;
@@ -93,7 +94,7 @@ struct svmc_ctx {
   int row_form_max = 16;   // row-form determinants when both spins change at most this many rows
   int dev = 0;             // device current at svmc_create
   // parameters
-  DevBuf Bpack, embed, bias;
+  DevBuf Bpack, Bmlp, embed, bias;
   std::vector<DevBuf> base, W, b;    // per lattice
   // walkers
   std::vector<LatDev> ld;            // host copies of the descriptors
@@ -106,6 +107,7 @@ struct svmc_ctx {
       f_nacc;
   DevBuf sw_stage, sw_list, sw_count;  // sweep: accepted-move staging, accepted walkers, their counts
   DevBuf gK, gB, gE;                 // conv weights, conv bias, embedding (FP64, forward's rounding)
+  DevBuf gMW, gMB;                   // site-wise weights and biases (FP64, forward's rounding)
   DevBuf g_rows, g_dH, g_hs, g_dzs, g_vjp;  // gradient scratch
   std::vector<int64_t> counts;
 
@@ -119,12 +121,16 @@ struct svmc_ctx {
     return e == hipErrorOutOfMemory ? SVMC_ERR_OOM : SVMC_ERR_HIP;
   }
   int tf_bytes() const { return prec == PREC_F64 ? 8 : 4; }
+  // feature planes cached per walker: conv layers, then site-wise layers
+  int planes() const { return L + nmlp; }
   ModelDev mdev() const {
     ModelDev m;
     m.L = L;
     m.C = C;
     m.act = model.act;
+    m.M = nmlp;
     m.Bpack = Bpack.p;
+    m.Bmlp = Bmlp.p;
     m.embed = embed.p;
     m.bias = bias.p;
     return m;
@@ -207,7 +213,9 @@ svmc_status svmc_create(const svmc_lattice* lats, int32_t n_lats, const svmc_mod
   if (m->conv_prec < 0 || m->conv_prec > 4) return SVMC_ERR_INVALID_ARG;
   if (m->refresh_every < 1) return SVMC_ERR_INVALID_ARG;
   if (m->per_site_embed != 0 && m->per_site_embed != 1) return SVMC_ERR_INVALID_ARG;
-  if (m->ksize != 3 || m->n_mlp != 0) return SVMC_ERR_UNSUPPORTED;
+  if (m->ksize != 3) return SVMC_ERR_UNSUPPORTED;
+  if (m->n_mlp < 0) return SVMC_ERR_INVALID_ARG;
+  if (m->n_mlp > 8) return SVMC_ERR_UNSUPPORTED;
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return SVMC_ERR_HIP;
   // address of this device's partial-sum array (allocation-free entry point)
@@ -219,12 +227,14 @@ svmc_status svmc_create(const svmc_lattice* lats, int32_t n_lats, const svmc_mod
   c->prec = m->conv_prec;
   c->L = m->n_conv;
   c->C = m->channels;
+  c->nmlp = m->n_mlp;
   c->emb_len = 4LL * c->C;
   if (m->per_site_embed) {
     c->emb_len = 0;
     for (auto& l : c->lats) c->emb_len += 4LL * l.Lx * l.Ly * c->C;
   }
-  int64_t np = c->emb_len + 9LL * c->L * c->C * c->C + (int64_t)c->L * c->C;
+  int64_t np = c->emb_len + 9LL * c->L * c->C * c->C + (int64_t)c->L * c->C +
+               (int64_t)c->nmlp * (c->C * c->C + c->C);
   for (auto& l : c->lats) np += (int64_t)c->C * (l.n_up + l.n_dn) + l.n_up + l.n_dn;
   c->nparams = np;
   *out = c;
@@ -260,7 +270,10 @@ svmc_status svmc_set_params(svmc_ctx* ctx, const double* theta, const double* co
   const long long EL = ctx->emb_len;
   const double* K = E + EL;
   const double* Bc = K + 9LL * L * C * C;
-  const double* rest = Bc + (long long)L * C;
+  const int NM = ctx->nmlp;
+  const double* MW = Bc + (long long)L * C;           // site-wise weights [NM][C][C]
+  const double* MB = MW + (long long)NM * C * C;      // site-wise biases [NM][C]
+  const double* rest = MB + (long long)NM * C;
   // values the device uses: rnd for the embedding and conv bias (feature
   // type; BF16 in the BF16 modes), rnd_w for the conv weights (FP16 in F16X2)
   auto rnd = [&](double x) -> double {
@@ -280,14 +293,15 @@ svmc_status svmc_set_params(svmc_ctx* ctx, const double* theta, const double* co
   };
   // embedding and conv bias in the feature type
   const int tfb = ctx->tf_bytes();
-  std::vector<char> eb((size_t)EL * tfb), bb((size_t)L * C * tfb);
+  std::vector<char> eb((size_t)EL * tfb), bb((size_t)(L + NM) * C * tfb);
   for (long long k = 0; k < EL; ++k) {
     if (tfb == 8) ((double*)eb.data())[k] = E[k];
     else ((float*)eb.data())[k] = (float)rnd_e(E[k]);
   }
-  for (int k = 0; k < L * C; ++k) {
-    if (tfb == 8) ((double*)bb.data())[k] = Bc[k];
-    else ((float*)bb.data())[k] = (float)rnd(Bc[k]);
+  for (int k = 0; k < (L + NM) * C; ++k) {
+    const double v = k < L * C ? Bc[k] : MB[k - L * C];
+    if (tfb == 8) ((double*)bb.data())[k] = v;
+    else ((float*)bb.data())[k] = (float)rnd(v);
   }
   // conv kernels as MFMA B fragments
   const bool bf = P == PREC_BF16 || P == PREC_BF16X3 || P == PREC_F16X2;
@@ -314,8 +328,34 @@ svmc_status svmc_set_params(svmc_ctx* ctx, const double* theta, const double* co
             else if (P == PREC_F16X2) ((_Float16*)bp.data())[idx] = (_Float16)(float)v;
             else ((uint16_t*)bp.data())[idx] = f32_to_bf16_rne((float)v);
           }
+  // site-wise weights as B fragments of one tap: [m][q][nt][lane]
+  const int QM = (C + KC - 1) / KC;
+  std::vector<char> bpm((size_t)std::max(NM, 1) * QM * NT * 64 * per * esz, 0);
+  for (int m = 0; m < NM; ++m)
+    for (int q = 0; q < QM; ++q)
+      for (int nt = 0; nt < NT; ++nt)
+        for (int lane = 0; lane < 64; ++lane)
+          for (int e = 0; e < per; ++e) {
+            const int kap = bf ? 32 * q + 8 * (lane >> 4) + e : 4 * q + (lane >> 4);
+            const int n = 16 * nt + (lane & 15);
+            const double v = (kap < C && n < C) ? MW[((long long)m * C + kap) * C + n] : 0.0;
+            const size_t idx = ((((size_t)m * QM + q) * NT + nt) * 64 + lane) * per + e;
+            if (P == PREC_F64) ((double*)bpm.data())[idx] = v;
+            else if (P == PREC_F32) ((float*)bpm.data())[idx] = (float)v;
+            else if (P == PREC_F16X2) ((_Float16*)bpm.data())[idx] = (_Float16)(float)v;
+            else ((uint16_t*)bpm.data())[idx] = f32_to_bf16_rne((float)v);
+          }
   // FP64 copies of what the forward uses, for the backward
   std::vector<double> gk(9ULL * L * C * C), gbias((size_t)L * C), ge((size_t)EL);
+  std::vector<double> gmw((size_t)std::max(NM, 1) * C * C, 0.0), gmb((size_t)std::max(NM, 1) * C, 0.0);
+  for (long long k = 0; k < (long long)NM * C * C; ++k) gmw[k] = rnd_w(MW[k]);
+  for (long long k = 0; k < (long long)NM * C; ++k) gmb[k] = rnd(MB[k]);
+  if ((s = ctx->hip(ctx->gMW.ensure(gmw.size() * 8), "alloc")) || (s = ctx->hip(ctx->gMB.ensure(gmb.size() * 8), "alloc")) ||
+      (s = ctx->hip(hipMemcpy(ctx->gMW.p, gmw.data(), gmw.size() * 8, hipMemcpyHostToDevice), "upload")) ||
+      (s = ctx->hip(hipMemcpy(ctx->gMB.p, gmb.data(), gmb.size() * 8, hipMemcpyHostToDevice), "upload")) ||
+      (s = ctx->hip(ctx->Bmlp.ensure(bpm.size()), "alloc")) ||
+      (s = ctx->hip(hipMemcpy(ctx->Bmlp.p, bpm.data(), bpm.size(), hipMemcpyHostToDevice), "upload")))
+    return s;
   for (size_t k = 0; k < gk.size(); ++k) gk[k] = rnd_w(K[k]);
   for (size_t k = 0; k < gbias.size(); ++k) gbias[k] = rnd(Bc[k]);
   for (size_t k = 0; k < ge.size(); ++k) ge[k] = rnd_e(E[k]);
@@ -377,7 +417,7 @@ static svmc_status rebuild_dets(svmc_ctx* ctx, hipStream_t st) {
   const Bufs bf = ctx->bufs();
   svmc_status s;
   for (auto& lt : ctx->ld) {
-    if ((s = ctx->hip(launch_rows(ctx->prec, lt, bf, ctx->L, ctx->C, st), "rows"))) return s;
+    if ((s = ctx->hip(launch_rows(ctx->prec, lt, bf, ctx->planes(), ctx->C, st), "rows"))) return s;
     if ((s = ctx->hip(launch_gj(lt, bf, st), "inverse"))) return s;
   }
   ctx->prepared = false;
@@ -392,7 +432,7 @@ static svmc_status prepare(svmc_ctx* ctx, hipStream_t st) {
   if (!ctx->dets_fresh && (s = rebuild_dets(ctx, st))) return s;
   const Bufs bf = ctx->bufs();
   for (auto& lt : ctx->ld) {
-    if ((s = ctx->hip(launch_rows(ctx->prec, lt, bf, ctx->L, ctx->C, st), "rows"))) return s;
+    if ((s = ctx->hip(launch_rows(ctx->prec, lt, bf, ctx->planes(), ctx->C, st), "rows"))) return s;
     if ((s = ctx->hip(launch_gp(lt, bf, ctx->C, st), "G/P precompute"))) return s;
   }
   ctx->prepared = true;
@@ -413,7 +453,7 @@ svmc_status svmc_load_walkers(svmc_ctx* ctx, const int64_t* counts, const int8_t
   const int L = ctx->L, C = ctx->C, tfb = ctx->tf_bytes();
   std::vector<LatDev> d(nl);
   long long w0 = 0, o_occ = 0, o_lab = 0, o_pos = 0, o_feat = 0, o_inv = 0, o_m = 0, o_pt = 0;
-  long long poff = ctx->emb_len + 9LL * L * C * C + (long long)L * C;
+  long long poff = ctx->emb_len + 9LL * L * C * C + (long long)L * C + (long long)ctx->nmlp * (C * C + C);
   long long emb_off = 0;
   size_t h0max = 0;
   for (size_t l = 0; l < nl; ++l) {
@@ -447,7 +487,7 @@ svmc_status svmc_load_walkers(svmc_ctx* ctx, const int64_t* counts, const int8_t
     o_occ += nw * N;
     o_lab += nw * 2 * N;
     o_pos += nw * 2 * nm;
-    o_feat += nw * (long long)L * N * C;
+    o_feat += nw * (long long)ctx->planes() * N * C;
     o_inv += nw * 2 * nm * nm;
     o_m += nw * 2 * N * nm;
     o_pt += nw * 2 * nm * C;
@@ -534,7 +574,7 @@ svmc_status svmc_local_energy(svmc_ctx* ctx, svmc_path path, double* eloc, int32
   if ((s = ctx->hip(ctx->ratio_tmp.ensure((size_t)ctx->Wtot * stride * 8), "alloc"))) return s;
   // chunk storage: configurations per chunk from a 2 GiB budget for the
   // largest lattice (at least one walker's worth of configurations)
-  const int tfb = ctx->tf_bytes(), L = ctx->L, C = ctx->C;
+  const int tfb = ctx->tf_bytes(), L = ctx->planes(), C = ctx->C;   // L: feature planes
   size_t per = 0;
   long long nmx = 1, Nmx = 1, wmx = 1;
   for (auto& lt : ctx->ld) {
@@ -658,7 +698,7 @@ static svmc_status refresh_list(svmc_ctx* ctx, const Bufs& bf, WalkerSel sel, in
   svmc_status s;
   for (auto& lt : ctx->ld) {
     if ((s = ctx->hip(launch_drift(lt, bf, sel, st), "drift check")) ||
-        (s = ctx->hip(launch_rows(ctx->prec, lt, bf, ctx->L, ctx->C, st, sel), "rows")) ||
+        (s = ctx->hip(launch_rows(ctx->prec, lt, bf, ctx->planes(), ctx->C, st, sel), "rows")) ||
         (s = ctx->hip(launch_gj(lt, bf, st, sel), "inverse")) ||
         (s = ctx->hip(launch_gp(lt, bf, ctx->C, st, sel), "G/P precompute")) ||
         (s = ctx->hip(launch_clear_nacc(lt, bf, sel, st), "clear")))
@@ -805,9 +845,14 @@ svmc_status svmc_grad_logpsi(svmc_ctx* ctx, const double* vjp_w, void* out_v, sv
   ga.K = ctx->gK.as<double>();
   ga.B = ctx->gB.as<double>();
   ga.E = ctx->gE.as<double>();
+  ga.M = ctx->nmlp;
+  ga.MW = ctx->gMW.as<double>();
+  ga.MB = ctx->gMB.as<double>();
   ga.nparams = np;
   ga.off_convw = ctx->emb_len;
   ga.off_convb = ga.off_convw + 9LL * ctx->L * ctx->C * ctx->C;
+  ga.off_mlpw = ga.off_convb + (long long)ctx->L * ctx->C;
+  ga.off_mlpb = ga.off_mlpw + (long long)ctx->nmlp * ctx->C * ctx->C;
   ga.ncmax = ncmax;
   ga.nsmax = nsmax;
   if ((s = ctx->hip(ctx->g_dH.ensure((size_t)chunk * ncmax * 8), "alloc gradient scratch"))) return s;

@@ -135,7 +135,7 @@ __global__ __launch_bounds__(64 * ELOC_NW) __attribute__((amdgpu_waves_per_eu(3)
   // this block's hops: a contiguous slice of the canonical order
   const int h0 = (int)(((long long)H * slice) / out.slices), h1 = (int)(((long long)H * (slice + 1)) / out.slices);
 
-  const Tf* featw = (const Tf*)bf.feat + lt.feat_off + wl * (long long)md.L * N * C;
+  const Tf* featw = (const Tf*)bf.feat + lt.feat_off + wl * (long long)feat_planes(md) * N * C;
   const double* Gw = bf.G + lt.g_off + wl * 2LL * N * nm;
   const double* PTw = bf.PT + lt.pt_off + wl * 2LL * nm * C;
   const int KM = lt.Gx * lt.Gy;

@@ -302,6 +302,7 @@ static __global__ void k_full_post(int pass, int nc, const int32_t* __restrict__
   }
 }
 
+// bytes per configuration of a chunk; L = feature planes per configuration
 size_t full_config_bytes(const LatDev& lt, int L, int C, int tfb) {
   size_t b = (size_t)lt.N + (size_t)(L + 1) * lt.N * C * tfb + 4 * sizeof(double) + 16;
   if (lt.nmax > 128)
@@ -314,7 +315,7 @@ hipError_t launch_eloc_full(int prec, const ModelDev& md, const LatDev& lt, cons
   if (lt.nw == 0) return hipSuccess;
   if (lt.N > 4096 || lt.nmax > 512) return hipErrorInvalidValue;
   hipError_t e;
-  const int L = md.L, C = md.C, N = lt.N;
+  const int L = feat_planes(md), C = md.C, N = lt.N;   // L: feature planes, the last feeds the rows
   const int tfb = prec == PREC_F64 ? 8 : 4;
   // hop counts -> configuration offsets (host prefix sum)
   hipLaunchKernelGGL(k_full_count, dim3((unsigned)lt.nw), dim3(64), 0, st, lt, bf, fs.cnt);

@@ -5,6 +5,10 @@
 //   d log|det Phi| = tr(Phi^-1 dPhi), so
 //     dW[c][m] = sum_k H_L[pos_k][c] Phi^-1[m][k],   db[m] = sum_k Phi^-1[m][k],
 //     dH_L[pos_k] += (W Phi^-1)[:, k] = P[:, k]      (P is the low-rank precompute).
+// Site-wise layers, m = M-1 .. 0, with H_{L+m+1} = act(z), z = H_{L+m} W_m + b_m
+// (no residual), H_L the conv output (the projection then reads H_{L+M}):
+//     dz = dH * act'(z),  dW_m[ci][co] = sum_s H_{L+m}[s][ci] dz[s][co],
+//     db_m = sum_s dz[s],  dH_{L+m}[s] = W_m dz[s].
 // Conv stack, l = L .. 1, with H_l = H_{l-1} + act(z_l), z_l = conv_l(H_{l-1}) + b_l:
 //     dz = dH_l * act'(z_l)                 (z_l recomputed from the cached H_{l-1})
 //     dK_l[t][ci][co] = sum_s dz[s][co] H_{l-1}[s + off_t][ci],   db_l = sum_s dz[s]
@@ -69,8 +73,8 @@ __global__ __launch_bounds__(256) void k_grad(const LatDev* __restrict__ lats, i
   const int8_t* occ = bf.occ + lt.occ_off + wl * N;
   const int16_t* lab = bf.lab + lt.lab_off + wl * 2LL * N;
   const int16_t* pos = bf.pos + lt.pos_off + wl * 2LL * nm;
-  const Tf* feat = (const Tf*)bf.feat + lt.feat_off + wl * (long long)L * NC;
-  const Tf* HL = feat + (long long)(L - 1) * NC;
+  const Tf* feat = (const Tf*)bf.feat + lt.feat_off + wl * (long long)(L + ga.M) * NC;
+  const Tf* HL = feat + (long long)(L + ga.M - 1) * NC;     // the projection's input
   const double* PTw = bf.PT + lt.pt_off + wl * 2LL * nm * C;
   const int n0 = lt.n[0], n1 = lt.n[1];
   for (int e = tid; e < 9 * N; e += NTH) {
@@ -145,6 +149,88 @@ __global__ __launch_bounds__(256) void k_grad(const LatDev* __restrict__ lats, i
     dH[e] = v;
   }
   __syncthreads();
+
+  // ---- site-wise layers, last first
+  for (int m = ga.M - 1; m >= 0; --m) {
+    const double* Wm = ga.MW + (long long)m * C * C;
+    const double* bm = ga.MB + (long long)m * C;
+    for (int e = tid; e < NC; e += NTH) hp[e] = (double)feat[(long long)(L - 1 + m) * NC + e];
+    __syncthreads();
+    const int wave = tid >> 6, lane = tid & 63, lj = lane & 15, lk = lane >> 4;
+    const int nct = (C + 15) / 16, ntr = (N + 15) / 16, ksc = C / 4;
+    // (1) z = H W + b, dz = dH * act'(z): tiles of 16 sites x 16 outputs
+    for (int tt = wave; tt < ntr * nct; tt += NTH / 64) {
+      const int ti = tt / nct, tj = tt - ti * nct;
+      const int si = 16 * ti + lj, co = 16 * tj + lj;
+      v4d acc = v4d{0.0, 0.0, 0.0, 0.0};
+      for (int u = 0; u < ksc; ++u) {
+        const int ci = 4 * u + lk;
+        const double a = si < N ? hp[si * C + ci] : 0.0;
+        const double b = co < C ? Wm[ci * C + co] : 0.0;
+        mfma(acc, a, b);
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int so = 16 * ti + lk + 4 * v;
+        if (so < N && co < C) dz[so * C + co] = dH[so * C + co] * act_deriv(ga.act, acc[v] + bm[co]);
+      }
+    }
+    __syncthreads();
+    // (2) dW_m[ci][co] = sum_s H[s][ci] dz[s][co]: tiles of 16 inputs x 16 outputs, K over the sites
+    double* dW = row + ga.off_mlpw + (long long)m * C * C;
+    for (int tt = wave; tt < nct * nct; tt += NTH / 64) {
+      const int tci = tt / nct, tco = tt - tci * nct;
+      const int ci = 16 * tci + lj, co = 16 * tco + lj;
+      v4d acc = v4d{0.0, 0.0, 0.0, 0.0};
+      for (int s0 = 0; s0 < N; s0 += 16) {
+        double a[4], b[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int sk = s0 + 4 * u + lk;
+          a[u] = (sk < N && ci < C) ? hp[sk * C + ci] : 0.0;
+          b[u] = (sk < N && co < C) ? dz[sk * C + co] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) mfma(acc, a[u], b[u]);
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int cio = 16 * tci + lk + 4 * v;
+        if (cio < C && co < C) dW[(long long)cio * C + co] = acc[v];
+      }
+    }
+    {
+      // db_m[co] = sum_s dz[s][co]
+      const int parts = NTH / C, co = tid % C, part = tid / C;
+      double acc = 0.0;
+      for (int s = part; s < N; s += parts) acc += dz[s * C + co];
+      gred[tid] = acc;
+      __syncthreads();
+      if (tid < C) {
+        double t = 0.0;
+        for (int q = 0; q < parts; ++q) t += gred[q * C + tid];
+        row[ga.off_mlpb + (long long)m * C + tid] = t;
+      }
+    }
+    // (3) dH[s][ci] = sum_co W_m[ci][co] dz[s][co]
+    for (int tt = wave; tt < ntr * nct; tt += NTH / 64) {
+      const int ti = tt / nct, tj = tt - ti * nct;
+      const int si = 16 * ti + lj, ci = 16 * tj + lj;
+      v4d acc = v4d{0.0, 0.0, 0.0, 0.0};
+      for (int u = 0; u < ksc; ++u) {
+        const int cq = 4 * u + lk;
+        const double a = si < N ? dz[si * C + cq] : 0.0;
+        const double b = ci < C ? Wm[ci * C + cq] : 0.0;
+        mfma(acc, a, b);
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int so = 16 * ti + lk + 4 * v;
+        if (so < N && ci < C) dH[so * C + ci] = acc[v];
+      }
+    }
+    __syncthreads();
+  }
 
   // ---- conv stack, last layer first
   for (int l = L; l >= 1; --l) {

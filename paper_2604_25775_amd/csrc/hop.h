@@ -380,6 +380,45 @@ SVMC_DEV int tab_site(const AxisTab& t, int ux, int uy, int Lx) {
   return tab_get(t, 32 + ux - t.bx) + Lx * tab_get(t, 48 + uy - t.by);
 }
 
+// Site-wise layer tile on the LDS grid: the 16 sites' own records (record
+// `site` of this lane; the all-zero record for padding rows).  In PREC_F16X2
+// the record's FP16 planes are the MFMA operands directly; the products and
+// their order are those of mlp_tile on the same values.
+template <int P, int C>
+SVMC_DEV void mlp_tile_grid(const typename PrecT<P>::Tf* __restrict__ grid, int site,
+                            const typename PrecT<P>::Tb* __restrict__ Bm, int lane,
+                            typename PrecT<P>::Acc (&acc)[MlpCfg<P, C>::NT]) {
+  typedef typename PrecT<P>::Tf Tf;
+  typedef MlpCfg<P, C> MC;
+  constexpr int SP = SiteStride<Tf, C>::value;
+  if constexpr (GridPlanes<P>::value) {
+    const int g = lane >> 4;
+#pragma unroll
+    for (int nt = 0; nt < MC::NT; ++nt)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[nt][v] = 0;
+#pragma unroll
+    for (int q = 0; q < MC::Q; ++q) {
+      typename PrecT<P>::Tb b[MC::NT];
+#pragma unroll
+      for (int nt = 0; nt < MC::NT; ++nt) b[nt] = Bm[(q * MC::NT + nt) * 64 + lane];
+      const int k0 = 32 * q + 8 * g;
+      v8h hi = {}, lo = {};
+      if (k0 < C) {
+        const char* rec = reinterpret_cast<const char*>(grid) + site * SP * (int)sizeof(Tf) + 2 * k0;
+        hi = *reinterpret_cast<const v8h*>(rec);
+        lo = *reinterpret_cast<const v8h*>(rec + 2 * C);
+      }
+#pragma unroll
+      for (int nt = 0; nt < MC::NT; ++nt) mfma(acc[nt], b[nt], hi);
+#pragma unroll
+      for (int nt = 0; nt < MC::NT; ++nt) mfma(acc[nt], b[nt], lo);
+    }
+  } else {
+    mlp_tile<P, C>(grid + site * SP, Bm, lane, acc);
+  }
+}
+
 // Incremental conv stack for one hop, computed by the NW wavefronts of the
 // workgroup (wave = this thread's wavefront); `tab` = axis_tab of the hop.  On return (after a barrier)
 // the scratch starts with D = H'_L - H_L on the layer-L box as Tf
@@ -579,55 +618,52 @@ SVMC_DEV void hop_features(const ModelDev& md, const LatDev& lt, const HopGeom& 
     }
     }
     __syncthreads();
-    const Tf* HL = featw + (long long)(L - 1) * N * C;
+    // the cached features the new ones replace: the last plane (conv layer L,
+    // or the last site-wise layer)
+    const int M = md.M, FL = L + M - 1;
+    const Tf* HL = featw + (long long)FL * N * C;
+    typedef typename DType<P>::type DT;
+    // this tile's new values replace the old ones on the grid (and go to
+    // cache plane cp on accept)
+    auto put_tile = [&](int ti, int s, int cp) {
+      const int site = gsite[ti];
 #pragma unroll
-    for (int ti = 0; ti < MAXT; ++ti) {
-      const int t = wave + NW * ti;
-      if (t >= T) break;
-      const int r = 16 * t + (lane & 15);
-      int ux, uy;
-      box_site(r, olx, owx, mow, oly, ux, uy);
-      const int s = tab_site(tab, ux, uy, Lx);     // every lane active
-      if (gsite[ti] < 0) continue;
-      if (l < L) {
-        // H'_l replaces H'_{l-1} on the box (and goes to the cache on accept)
-        const int site = gsite[ti];
+      for (int nt = 0; nt < CC::NT; ++nt) {
+        if constexpr (PL) {
+          const int n0 = 16 * nt + OutMap<P>::chan(lane, 0);
+          if (n0 >= C) continue;
+          const float4 v4 = {acc[ti][nt][0], acc[ti][nt][1], acc[ti][nt][2], acc[ti][nt][3]};
+          grid_put4<P, C>(grid, site, n0, v4);
+          if (commit) *reinterpret_cast<float4*>(commit + ((long long)cp * N + s) * C + n0) = v4;
+        } else {
 #pragma unroll
-        for (int nt = 0; nt < CC::NT; ++nt) {
-          if constexpr (PL) {
-            const int n0 = 16 * nt + OutMap<P>::chan(lane, 0);
-            if (n0 >= C) continue;
-            const float4 v4 = {acc[ti][nt][0], acc[ti][nt][1], acc[ti][nt][2], acc[ti][nt][3]};
-            grid_put4<P, C>(grid, site, n0, v4);
-            if (commit) *reinterpret_cast<float4*>(commit + ((long long)(l - 1) * N + s) * C + n0) = v4;
-          } else {
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-              const int n = 16 * nt + OutMap<P>::chan(lane, v);
-              if (n >= C) continue;
-              grid[site * SP + n] = acc[ti][nt][v];
-              if (commit) commit[((long long)(l - 1) * N + s) * C + n] = acc[ti][nt][v];
-            }
+          for (int v = 0; v < 4; ++v) {
+            const int n = 16 * nt + OutMap<P>::chan(lane, v);
+            if (n >= C) continue;
+            grid[site * SP + n] = acc[ti][nt][v];
+            if (commit) commit[((long long)cp * N + s) * C + n] = acc[ti][nt][v];
           }
         }
-      } else {
-        // D = H'_L - H_L, densely [m][C + 4] at the start of the scratch
-        typedef typename DType<P>::type DT;
-        DT* D = reinterpret_cast<DT*>(grid);
-        if constexpr (PL) {
+      }
+    };
+    // D = H'_F - H_F (F the last plane), densely [m][C + 4] at the start of
+    // the scratch
+    auto put_D = [&](int ti, int r, int s) {
+      DT* D = reinterpret_cast<DT*>(grid);
+      if constexpr (PL) {
 #pragma unroll
-          for (int nt = 0; nt < CC::NT; ++nt) {
-            const int n0 = 16 * nt + OutMap<P>::chan(lane, 0);
-            if (!FULLC && n0 >= C) continue;
-            const long long gi = (long long)s * C + n0;
-            const float4 old = *reinterpret_cast<const float4*>(HL + gi);
-            const float4 nw = {acc[ti][nt][0], acc[ti][nt][1], acc[ti][nt][2], acc[ti][nt][3]};
-            const float4 d = {(float)((double)nw.x - (double)old.x), (float)((double)nw.y - (double)old.y),
-                              (float)((double)nw.z - (double)old.z), (float)((double)nw.w - (double)old.w)};
-            *reinterpret_cast<float4*>(D + r * DStride<C>::value + n0) = d;
-            if (commit) *reinterpret_cast<float4*>(commit + (long long)(L - 1) * N * C + gi) = nw;
-          }
-        } else
+        for (int nt = 0; nt < CC::NT; ++nt) {
+          const int n0 = 16 * nt + OutMap<P>::chan(lane, 0);
+          if (!FULLC && n0 >= C) continue;
+          const long long gi = (long long)s * C + n0;
+          const float4 old = *reinterpret_cast<const float4*>(HL + gi);
+          const float4 nw = {acc[ti][nt][0], acc[ti][nt][1], acc[ti][nt][2], acc[ti][nt][3]};
+          const float4 d = {(float)((double)nw.x - (double)old.x), (float)((double)nw.y - (double)old.y),
+                            (float)((double)nw.z - (double)old.z), (float)((double)nw.w - (double)old.w)};
+          *reinterpret_cast<float4*>(D + r * DStride<C>::value + n0) = d;
+          if (commit) *reinterpret_cast<float4*>(commit + (long long)FL * N * C + gi) = nw;
+        }
+      } else {
 #pragma unroll
         for (int nt = 0; nt < CC::NT; ++nt)
 #pragma unroll
@@ -637,8 +673,71 @@ SVMC_DEV void hop_features(const ModelDev& md, const LatDev& lt, const HopGeom& 
             const long long gi = (long long)s * C + n;
             const Tf old = HL[gi];
             D[r * DStride<C>::value + n] = (DT)((double)acc[ti][nt][v] - (double)old);
-            if (commit) commit[(long long)(L - 1) * N * C + gi] = acc[ti][nt][v];
+            if (commit) commit[(long long)FL * N * C + gi] = acc[ti][nt][v];
           }
+      }
+    };
+    const bool dnow = l == L && M == 0;
+#pragma unroll
+    for (int ti = 0; ti < MAXT; ++ti) {
+      const int t = wave + NW * ti;
+      if (t >= T) break;
+      const int r = 16 * t + (lane & 15);
+      int ux, uy;
+      box_site(r, olx, owx, mow, oly, ux, uy);
+      const int s = tab_site(tab, ux, uy, Lx);     // every lane active
+      if (gsite[ti] < 0) continue;
+      if (!dnow) put_tile(ti, s, l - 1);
+      else put_D(ti, r, s);
+    }
+    if (l == L && M > 0) {
+      // the site-wise layers (Sec. II.B, site-wise MLP equation) on the
+      // layer-L box: each wavefront runs its own tiles, a site reading only
+      // its own record, so the wavefronts do not wait for each other
+      for (int m = 0; m < M; ++m) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const Tb* Bm = (const Tb*)md.Bmlp + (long long)m * MlpCfg<P, C>::Q * CC::NT * 64;
+        const Tf* mb = (const Tf*)md.bias + (long long)(L + m) * C;
+#pragma unroll
+        for (int ti = 0; ti < MAXT; ++ti) {
+          const int t = wave + NW * ti;
+          if (t >= T) break;
+          mlp_tile_grid<P, C>(grid, gsite[ti] >= 0 ? gsite[ti] : zsite, Bm, lane, acc[ti]);
+#pragma unroll
+          for (int nt = 0; nt < CC::NT; ++nt)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              const int n = 16 * nt + OutMap<P>::chan(lane, v);
+              acc[ti][nt][v] = n < C ? mlp_out<P, Tf>(md.act, Tf(acc[ti][nt][v] + mb[n])) : Tf(0);
+            }
+        }
+        if (m + 1 == M) break;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+        for (int ti = 0; ti < MAXT; ++ti) {
+          const int t = wave + NW * ti;
+          if (t >= T) break;
+          const int r = 16 * t + (lane & 15);
+          int ux, uy;
+          box_site(r, olx, owx, mow, oly, ux, uy);
+          const int s = tab_site(tab, ux, uy, Lx);
+          if (gsite[ti] >= 0) put_tile(ti, s, L + m);
+        }
+      }
+      __syncthreads();    // every wavefront is done with the grid: D may overwrite it
+#pragma unroll
+      for (int ti = 0; ti < MAXT; ++ti) {
+        const int t = wave + NW * ti;
+        if (t >= T) break;
+        const int r = 16 * t + (lane & 15);
+        int ux, uy;
+        box_site(r, olx, owx, mow, oly, ux, uy);
+        const int s = tab_site(tab, ux, uy, Lx);
+        if (gsite[ti] >= 0) put_D(ti, r, s);
       }
     }
     if (l < L) {

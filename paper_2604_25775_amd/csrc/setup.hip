@@ -128,7 +128,7 @@ __global__ __launch_bounds__(256) void k_forward_fused(LatDev lt, Bufs bf, Model
   const int N = lt.N, Lx = lt.Lx, Ly = lt.Ly, GX = Lx + 2, GG = GX * (Ly + 2), L = md.L;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int8_t* occ = bf.occ + lt.occ_off + wl * N;
-  Tf* featw = (Tf*)bf.feat + lt.feat_off + wl * (long long)L * N * C;
+  Tf* featw = (Tf*)bf.feat + lt.feat_off + wl * (long long)feat_planes(md) * N * C;
   // records of site s: itself and its halo copies (periodic axes)
   auto records = [&](int s, int (&r)[4]) -> int {
     const int x = s % Lx, y = s / Lx;
@@ -237,6 +237,52 @@ __global__ __launch_bounds__(256) void k_forward_fused(LatDev lt, Bufs bf, Model
   }
 }
 
+// One site-wise layer m (Sec. II.B, site-wise MLP equation) over every site
+// of every walker of a lattice: dst = act(src W_m + b_m) per site, no
+// residual, rounded like every cached feature.  One wavefront per 16-site
+// tile, four per block; blockIdx.y = walker.  src / dst: planes of the
+// feature cache (walker stride `stride`).
+template <int P, int C>
+__global__ __launch_bounds__(256) void k_mlp_layer(LatDev lt, ModelDev md, int m,
+                                                   const typename PrecT<P>::Tf* __restrict__ src,
+                                                   typename PrecT<P>::Tf* __restrict__ dst, long long stride) {
+  typedef typename PrecT<P>::Tf Tf;
+  typedef typename PrecT<P>::Tb Tb;
+  typedef MlpCfg<P, C> MC;
+  const int lane = threadIdx.x & 63;
+  const int tile = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int N = lt.N;
+  if (tile * 16 >= N) return;
+  const long long wl = blockIdx.y;
+  const Tf* S = src + wl * stride;
+  Tf* D = dst + wl * stride;
+  const Tb* Bm = (const Tb*)md.Bmlp + (long long)m * MC::Q * MC::NT * 64;
+  const Tf* bias = (const Tf*)md.bias + (long long)(md.L + m) * C;
+  const int s = tile * 16 + (lane & 15);
+  typename PrecT<P>::Acc acc[MC::NT];
+  mlp_tile<P, C>(s < N ? S + (long long)s * C : nullptr, Bm, lane, acc);
+  if (s >= N) return;
+#pragma unroll
+  for (int nt = 0; nt < MC::NT; ++nt)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int n = 16 * nt + OutMap<P>::chan(lane, v);
+      if (n < C) D[(long long)s * C + n] = mlp_out<P, Tf>(md.act, Tf(acc[nt][v] + bias[n]));
+    }
+}
+
+template <int P, int C>
+static hipError_t mlp_layers(const LatDev& lt, const Bufs& bf, const ModelDev& md, hipStream_t st) {
+  typedef typename PrecT<P>::Tf Tf;
+  const long long NC = (long long)lt.N * C, fs = (long long)feat_planes(md) * NC;
+  Tf* feat = (Tf*)bf.feat + lt.feat_off;
+  const dim3 grid((unsigned)((lt.N + 63) / 64), (unsigned)lt.nw);
+  for (int m = 0; m < md.M; ++m)
+    hipLaunchKernelGGL((k_mlp_layer<P, C>), grid, dim3(256), 0, st, lt, md, m,
+                       feat + (long long)(md.L - 1 + m) * NC, feat + (long long)(md.L + m) * NC, fs);
+  return hipGetLastError();
+}
+
 template <int P, int C>
 size_t fused_smem(const LatDev& lt) {
   typedef typename PrecT<P>::Tf Tf;
@@ -254,13 +300,15 @@ static hipError_t forward_impl(const LatDev& lt, const Bufs& bf, const ModelDev&
     hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)fsm);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(kern, dim3((unsigned)lt.nw), dim3(256), fsm, st, lt, bf, md);
-    return hipGetLastError();
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return mlp_layers<P, C>(lt, bf, md, st);
   }
   const long long NC = (long long)lt.N * C;
   Tf* h0 = (Tf*)h0tmp;
   hipLaunchKernelGGL(k_embed<Tf>, dim3(4096), dim3(256), 0, st, lt, bf, md, h0);
   Tf* feat = (Tf*)bf.feat + lt.feat_off;
-  const long long fs = (long long)md.L * NC;
+  const long long fs = (long long)feat_planes(md) * NC;
   const dim3 grid((unsigned)((lt.N + 64 * FWD_TPW - 1) / (64 * FWD_TPW)), (unsigned)lt.nw);
   for (int l = 0; l < md.L; ++l) {
     const Tf* src = l == 0 ? h0 : feat + (long long)(l - 1) * NC;
@@ -268,7 +316,9 @@ static hipError_t forward_impl(const LatDev& lt, const Bufs& bf, const ModelDev&
     hipLaunchKernelGGL((k_forward_layer<P, C>), grid, dim3(256), 0, st, lt, md, l, src, ss,
                        feat + (long long)l * NC, fs);
   }
-  return hipGetLastError();
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return mlp_layers<P, C>(lt, bf, md, st);
 }
 
 hipError_t SVMC_CAT3(forward_, SVMC_INST_P, SVMC_INST_C)(const LatDev& lt, const Bufs& bf, const ModelDev& md,

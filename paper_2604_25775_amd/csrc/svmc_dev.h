@@ -49,7 +49,7 @@ struct LatDev {
   long long occ_off;   // int8  [N]
   long long lab_off;   // int16 [2][N]     label of the electron at a site, -1
   long long pos_off;   // int16 [2][nmax]  site of each label
-  long long feat_off;  // Tf    [L][N][C]  H_1..H_L
+  long long feat_off;  // Tf    [L + M][N][C]  H_1..H_L, then the M site-wise layers' outputs
   long long inv_off;   // f64   [2][nmax][nmax]  Phi^-1[m][k]
   long long m_off;     // f64   [2][N][nmax]     orbital rows of all sites
   long long g_off;     // f64   [2][N][nmax]     G = M Phi^-1
@@ -81,13 +81,18 @@ struct Bufs {
 };
 
 // Network constants.  Bpack holds the conv kernels pre-arranged as MFMA B
-// fragments: [layer][chunk q][out-tile nt][lane] of PrecT<P>::Tb.
+// fragments: [layer][chunk q][out-tile nt][lane] of PrecT<P>::Tb; Bmlp the
+// site-wise layers' C x C weights in the same arrangement (one tap).
 struct ModelDev {
   int L, C, act;
+  int M;               // site-wise layers after the conv stack
   const void* Bpack;
+  const void* Bmlp;
   const void* embed;   // Tf [4][C], or per lattice [N][4][C] (LatDev::emb_off)
-  const void* bias;    // Tf [L][C]
+  const void* bias;    // Tf [L + M][C]: conv biases, then the site-wise biases
 };
+// feature planes cached per walker: the conv layers, then the site-wise ones
+__host__ __device__ inline int feat_planes(const ModelDev& md) { return md.L + md.M; }
 
 template <int P> struct PrecT;
 template <> struct PrecT<PREC_F64> {
@@ -111,6 +116,13 @@ template <int P, int C> struct ConvCfg {
   static constexpr int K = 9 * C;
   static constexpr int Q = (K + KC - 1) / KC;   // K chunks per layer
   static constexpr int NT = (C + 15) / 16;      // 16-wide output tiles
+};
+// the same for a site-wise layer (one tap: K = C)
+template <int P, int C> struct MlpCfg {
+  static constexpr int KC = PrecT<P>::KC;
+  static constexpr int K = C;
+  static constexpr int Q = (K + KC - 1) / KC;
+  static constexpr int NT = (C + 15) / 16;
 };
 
 // ---------------------------------------------------------------------------
@@ -222,6 +234,13 @@ template <int P, class T> SVMC_DEV T layer_out(int act, T x, T z) {
 // the same with the activation fixed at compile time (FP32 features)
 template <int P, int A> SVMC_DEV float layer_out_c(float x, float z) {
   const float y = x + act_c<A>(z);
+  if constexpr (P == PREC_F16X2) return pair_round(y);
+  return y;
+}
+// Output of a site-wise layer: act(z), no residual, rounded to an FP16 pair
+// in PREC_F16X2 like every other cached feature.
+template <int P, class T> SVMC_DEV T mlp_out(int act, T z) {
+  const T y = act_fn<T>(act, z);
   if constexpr (P == PREC_F16X2) return pair_round(y);
   return y;
 }
@@ -394,6 +413,51 @@ SVMC_DEV void conv_tile_regb(const typename PrecT<P>::Tf* __restrict__ src, cons
       Tf a = off >= 0 ? src[off + c] : Tf(0);
 #pragma unroll
       for (int nt = 0; nt < CC::NT; ++nt) mfma(acc[nt], breg[q][nt], a);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Site-wise layer tile (Sec. II.B, site-wise MLP equation): 16 sites x C
+// outputs of acc[site][n] = sum_c x_site[c] W[c][n], weights as the A operand
+// as in the conv tiles (OutMap gives the result layout).  x: this lane's
+// site's C features in memory (FP32 / FP64 values; FP16 pairs in F16X2), or
+// nullptr for a padding row.  Bm: the layer's packed B fragments
+// [chunk q][out-tile nt][lane].  The chunk order is that of the conv tiles,
+// so every kernel that evaluates a site-wise layer (forward over all sites,
+// incremental update on a box) gives identical values for identical inputs.
+// ---------------------------------------------------------------------------
+template <int P, int C>
+SVMC_DEV void mlp_tile(const typename PrecT<P>::Tf* x, const typename PrecT<P>::Tb* __restrict__ Bm, int lane,
+                       typename PrecT<P>::Acc (&acc)[MlpCfg<P, C>::NT]) {
+  typedef typename PrecT<P>::Tf Tf;
+  typedef MlpCfg<P, C> MC;
+  const int g = lane >> 4;
+#pragma unroll
+  for (int nt = 0; nt < MC::NT; ++nt)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) acc[nt][v] = 0;
+#pragma unroll
+  for (int q = 0; q < MC::Q; ++q) {
+    typename PrecT<P>::Tb b[MC::NT];
+#pragma unroll
+    for (int nt = 0; nt < MC::NT; ++nt) b[nt] = Bm[(q * MC::NT + nt) * 64 + lane];
+    if constexpr (Mma16<P>::value) {
+      const int k0 = 32 * q + 8 * g;
+      float xv[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) xv[e] = 0.0f;
+      if (x && k0 < C) {
+        const float4* p4 = reinterpret_cast<const float4*>(x + k0);
+        const float4 x0 = p4[0], x1 = p4[1];
+        xv[0] = x0.x; xv[1] = x0.y; xv[2] = x0.z; xv[3] = x0.w;
+        xv[4] = x1.x; xv[5] = x1.y; xv[6] = x1.z; xv[7] = x1.w;
+      }
+      mma_chunk16<P, MC::NT>(acc, xv, b);
+    } else {
+      const Tf a = x ? x[4 * q + g] : Tf(0);
+#pragma unroll
+      for (int nt = 0; nt < MC::NT; ++nt) mfma(acc[nt], b[nt], a);
     }
   }
 }

@@ -37,7 +37,9 @@ SVMC_DEV int pick_walker(const WalkerSel& s, const LatDev& lt, long long z, long
   wl = z;
   return 1;
 }
-hipError_t launch_rows(int prec, const LatDev& lt, const Bufs& bf, int L, int C, hipStream_t st,
+// Orbital rows from the last of the `planes` cached feature planes (conv
+// layers, then site-wise layers).
+hipError_t launch_rows(int prec, const LatDev& lt, const Bufs& bf, int planes, int C, hipStream_t st,
                        WalkerSel sel = WalkerSel{nullptr, nullptr});
 hipError_t launch_gj(const LatDev& lt, const Bufs& bf, hipStream_t st, WalkerSel sel = WalkerSel{nullptr, nullptr});
 hipError_t launch_gp(const LatDev& lt, const Bufs& bf, int C, hipStream_t st,
@@ -100,10 +102,13 @@ hipError_t launch_fill_i64(int64_t* p, long long n, int64_t v, hipStream_t st);
 // grad.hip: d log|psi| / d theta, one row per walker
 struct GradArgs {
   int L, C, act, lds;     // lds: H_{l-1} of a walker in LDS (else hs)
+  int M;                  // site-wise layers after the conv stack
   const double* K;        // [L][9][C][C] conv weights as the forward uses them
   const double* B;        // [L][C]
   const double* E;        // [4][C]
-  long long nparams, off_convw, off_convb;
+  const double* MW;       // [M][C][C] site-wise weights as the forward uses them
+  const double* MB;       // [M][C]
+  long long nparams, off_convw, off_convb, off_mlpw, off_mlpb;
   long long w_begin;      // first walker of the launch
   long long ncmax;        // per-walker scratch stride (max N * C)
   long long nsmax;        // sites of the largest lattice (neighbour table in LDS)

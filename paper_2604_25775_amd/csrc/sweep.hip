@@ -216,7 +216,7 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(3))) void k
   __syncthreads();
 
   // ---- ratio
-  Tf* featw = (Tf*)bf.feat + lt.feat_off + wl * (long long)md.L * N * C;
+  Tf* featw = (Tf*)bf.feat + lt.feat_off + wl * (long long)feat_planes(md) * N * C;
   const double* Gw = bf.G + lt.g_off + wl * 2LL * N * nm;
   const double* PTw = bf.PT + lt.pt_off + wl * 2LL * nm * C;
   const HopGeom g = hop_geom(lt, md.L, sp, i, d);

@@ -26,7 +26,7 @@ def build(lats, model: wl.Model, walkers, seed_params=0, seed_occ=1, backflow=0.
     occs = occ_list or [wl.random_occupations(l, n, seed=seed_occ + 100 * k)
                         for k, (l, n) in enumerate(zip(lats, walkers))]
     ctx = ScaleVMC(lats, model.n_conv, model.channels, model.act, model.conv_prec, model.refresh_every,
-                   per_site_embed=model.per_site_embed)
+                   per_site_embed=model.per_site_embed, n_mlp=model.n_mlp)
     ctx.set_params_from(params)
     flat = np.concatenate([o.reshape(-1) for o in occs]).astype(np.int8)
     ctx.load(list(walkers), flat)

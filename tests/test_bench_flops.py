@@ -20,7 +20,7 @@ DX = [1, -1, 0, 0, 1, 1, -1, -1]
 DY = [0, 0, 1, -1, 1, -1, 1, -1]
 
 
-def brute_flops(lat, occ, L, C):
+def brute_flops(lat, occ, L, C, n_mlp=0):
     W, N = occ.shape
     Lx, Ly = lat.Lx, lat.Ly
     nd = 8 if lat.tp != 0.0 else 4
@@ -60,6 +60,7 @@ def brute_flops(lat, occ, L, C):
                         for l in range(1, L + 1):
                             conv += len(ball(x, y, l) | ball(*pj, l)) * 9 * C * C * 2
                         box = ball(x, y, L) | ball(*pj, L)
+                        conv += len(box) * n_mlp * C * C * 2
                         for tau in (0, 1):
                             k = sum(1 for (bx, by) in box if (g[by, bx] >> tau) & 1)
                             r = min(k, C + (1 if tau == sp else 0))
@@ -77,9 +78,10 @@ CASES = [
 
 
 @pytest.mark.parametrize("name,lat,L,C", CASES, ids=[c[0] for c in CASES])
-def test_lowrank_flops_match_brute_force(name, lat, L, C):
+@pytest.mark.parametrize("n_mlp", [0, 3])
+def test_lowrank_flops_match_brute_force(name, lat, L, C, n_mlp):
     occ = wl.random_occupations(lat, 3, seed=4)
-    got = bench.lowrank_flops(lat, occ, L, C)
-    ref = brute_flops(lat, occ, L, C)
+    got = bench.lowrank_flops(lat, occ, L, C, n_mlp)
+    ref = brute_flops(lat, occ, L, C, n_mlp)
     assert got[0] == pytest.approx(ref[0], rel=1e-12)
     assert got[1] == pytest.approx(ref[1], rel=1e-12)

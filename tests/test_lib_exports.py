@@ -41,8 +41,9 @@ def test_status_strings_without_device():
 
 def test_model_descriptor_checks_without_device():
     """svmc_create rejects network shapes before it touches a device: a kernel
-    width other than 3 and site-wise MLP layers are not built
-    (SVMC_ERR_UNSUPPORTED), a per-site flag outside {0, 1} is invalid."""
+    width other than 3 and more than 8 site-wise MLP layers are not built
+    (SVMC_ERR_UNSUPPORTED), a negative layer count and a per-site flag
+    outside {0, 1} are invalid."""
     from paper_2604_25775_amd import _lib
     if not os.path.exists(_lib.LIB_PATH):
         pytest.skip("library not built")
@@ -58,7 +59,8 @@ def test_model_descriptor_checks_without_device():
 
     assert create(ksize=5) == 5
     assert create(ksize=1) == 5
-    assert create(n_mlp=4) == 5
+    assert create(n_mlp=9) == 5
+    assert create(n_mlp=-1) == 1
     assert create(per_site_embed=2) == 1
     assert create(channels=12) == 5
     assert create(refresh_every=0) == 1
