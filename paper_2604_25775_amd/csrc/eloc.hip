@@ -22,14 +22,18 @@ inline __host__ __device__ int align16(int x) { return (x + 15) & ~15; }
 
 constexpr int ELOC_NW = 2;     // wavefronts per workgroup
 
-__host__ __device__ inline ElocLds eloc_layout(int N, int maxhops, int Gx, int Gy, int L, int C, int tfb) {
+// the one-conv-layer instance serves (see k_eloc_lowrank's SMALL)
+inline bool eloc_small(const ModelDev& md, const ElocOut& out) { return md.L == 1 && out.row_form_max >= 16; }
+
+__host__ __device__ inline ElocLds eloc_layout(int N, int maxhops, int Gx, int Gy, int L, int C, int tfb,
+                                               bool rows_only) {
   ElocLds o;
   o.occ = 0;
   o.lab = align16(N);
   o.hops = o.lab + align16(4 * N);
   o.red = o.hops + align16(2 * maxhops);
   o.scratch = o.red + 64;
-  o.wave_bytes = hop_scratch(Gx, Gy, L, C, tfb).bytes;
+  o.wave_bytes = hop_scratch(Gx, Gy, L, C, tfb, rows_only).bytes;
   return o;
 }
 
@@ -100,8 +104,12 @@ SVMC_DEV void eloc_block(long long b, int S, long long& w, int& slice) {
   w = (r / S) * 8 + xcd;
 }
 
-template <int P, int C>
-__global__ __launch_bounds__(64 * ELOC_NW) __attribute__((amdgpu_waves_per_eu(3))) void k_eloc_lowrank(
+// SMALL: the instance for one conv layer, whose update boxes hold at most
+// 4 x 4 sites, so at most 16 changed rows per spin: the row form always
+// applies, the column form and the registers of larger boxes are left out,
+// and more wavefronts fit per SIMD.
+template <int P, int C, bool SMALL>
+__global__ __launch_bounds__(64 * ELOC_NW) __attribute__((amdgpu_waves_per_eu(SMALL ? 4 : 3))) void k_eloc_lowrank(
     ModelDev md, const LatDev* __restrict__ lats, int nlats, Bufs bf, ElocOut out, long long Wtot) {
   typedef typename PrecT<P>::Tf Tf;
   constexpr int NW = ELOC_NW, NTH = 64 * NW;
@@ -116,13 +124,13 @@ __global__ __launch_bounds__(64 * ELOC_NW) __attribute__((amdgpu_waves_per_eu(3)
   const long long wl = w - lt.w0;
   const int N = lt.N, nm = lt.nmax;
   const int tid = threadIdx.x, wv = uniform_i(tid >> 6);
-  const ElocLds lay = eloc_layout(N, lt.maxhops, lt.Gx, lt.Gy, md.L, C, (int)sizeof(Tf));
+  const ElocLds lay = eloc_layout(N, lt.maxhops, lt.Gx, lt.Gy, md.L, C, (int)sizeof(Tf), SMALL);
   int8_t* occ_s = (int8_t*)(smem + lay.occ);
   int16_t* lab_s = (int16_t*)(smem + lay.lab);
   uint16_t* hops = (uint16_t*)(smem + lay.hops);
   double* red = (double*)(smem + lay.red);
   char* scratch = smem + lay.scratch;
-  const HopScratch hsc = hop_scratch(lt.Gx, lt.Gy, md.L, C, (int)sizeof(Tf));
+  const HopScratch hsc = hop_scratch(lt.Gx, lt.Gy, md.L, C, (int)sizeof(Tf), SMALL);
   hop_scratch_init<P>(md, scratch, hsc);
 
   const int8_t* occ_g = bf.occ + lt.occ_off + wl * N;
@@ -158,7 +166,8 @@ __global__ __launch_bounds__(64 * ELOC_NW) __attribute__((amdgpu_waves_per_eu(3)
       const HopGeom g = hop_geom(lt, md.L, sp, i, d);
       int olx, owx, oly, owy;
       const AxisTab tab = axis_tab(g, md.L, lane);
-      hop_features<P, C, NW>(md, lt, g, occ_s, featw, (Tf*)nullptr, scratch, hsc, tab, olx, owx, oly, owy);
+      hop_features<P, C, NW, SMALL ? 1 : 7>(md, lt, g, occ_s, featw, (Tf*)nullptr, scratch, hsc, tab, olx, owx, oly,
+                                            owy);
       // wavefront wv: determinant of spin wv
       int hpos;
       const int K = hop_klist(lt, g, tab, occ_s, lab_s, wv, olx, owx, oly, owy, kl, hpos, lane);
@@ -168,7 +177,7 @@ __global__ __launch_bounds__(64 * ELOC_NW) __attribute__((amdgpu_waves_per_eu(3)
       // 16) instead of the column form of size C + 1
       const int Ko = hop_kcount(lt, g, tab, occ_s, 1 - wv, olx, owx, oly, owy, lane);
       const int KM = uniform_i(max(K, Ko));
-      if (KM <= out.row_form_max) {
+      if (SMALL || KM <= out.row_form_max) {
         const v4d racc = hop_det_row_build<C>(kl, K, (const typename DType<P>::type*)scratch, PTt, lane);
         __syncthreads();    // both matrices built: their staging may overwrite D
         double* rstage = (double*)scratch + wv * 16 * 17;
@@ -189,10 +198,12 @@ __global__ __launch_bounds__(64 * ELOC_NW) __attribute__((amdgpu_waves_per_eu(3)
           };
           const double dt = KM <= 8 ? pair(IntC<8>()) : pair(IntC<16>());
           if ((lane & 31) == 0) misc[lane >> 5] = dt;
-          if (lane == 0) misc[2] = 1.0;
+          // (the one-layer instance cannot meet more than 16 rows; if a
+          // caller broke that, the ratio is flagged rather than wrong)
+          if (lane == 0) misc[2] = (SMALL && KM > 16) ? NAN : 1.0;
         }
         __syncthreads();
-      } else {
+      } else if constexpr (!SMALL) {
       v4d dacc[DetTiles<C>::I][DetTiles<C>::J];
       hop_det_build<C>(kl, K, wv == sp, hpos, (const typename DType<P>::type*)scratch, PTt, Gj, lane, dacc);
       __syncthreads();      // both matrices built: their staging may overwrite D
@@ -252,7 +263,9 @@ __global__ __launch_bounds__(64 * ELOC_NW) __attribute__((amdgpu_waves_per_eu(3)
 template <int P, int C>
 static hipError_t eloc_impl(const ModelDev& md, const LatDev* lats_dev, int nlats, long long W, const Bufs& bf,
                             const ElocOut& out, size_t smem, hipStream_t st) {
-  auto kern = k_eloc_lowrank<P, C>;
+  // one conv layer with the row form allowed up to 16 rows: every hop takes
+  // the row form, so the smaller instance serves
+  auto kern = eloc_small(md, out) ? k_eloc_lowrank<P, C, true> : k_eloc_lowrank<P, C, false>;
   hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
   if (e != hipSuccess) return e;
   const long long nblk = ((W + 7) / 8) * 8 * out.slices;
@@ -290,11 +303,11 @@ hipError_t noalloc_scratch_init(int dev) {
 
 double* noalloc_scratch(int dev) { return (dev >= 0 && dev < kMaxDevices) ? g_scratch_ptr[dev] : nullptr; }
 
-size_t eloc_lowrank_smem(const LatDev* lats, int nlats, int prec, int L, int C) {
+size_t eloc_lowrank_smem(const LatDev* lats, int nlats, int prec, int L, int C, bool rows_only) {
   const int tfb = prec == PREC_F64 ? 8 : 4;
   size_t mx = 0;
   for (int l = 0; l < nlats; ++l) {
-    const ElocLds o = eloc_layout(lats[l].N, lats[l].maxhops, lats[l].Gx, lats[l].Gy, L, C, tfb);
+    const ElocLds o = eloc_layout(lats[l].N, lats[l].maxhops, lats[l].Gx, lats[l].Gy, L, C, tfb, rows_only);
     mx = std::max(mx, (size_t)o.scratch + (size_t)o.wave_bytes);
   }
   return mx;
@@ -311,7 +324,7 @@ __global__ void k_eloc_sum(const double* __restrict__ part, int S, long long W, 
 
 hipError_t launch_eloc_lowrank(int prec, const ModelDev& md, const LatDev* lats_dev, const LatDev* lats_host,
                                int nlats, long long W, const Bufs& bf, const ElocOut& out, hipStream_t st) {
-  const size_t smem = eloc_lowrank_smem(lats_host, nlats, prec, md.L, md.C);
+  const size_t smem = eloc_lowrank_smem(lats_host, nlats, prec, md.L, md.C, eloc_small(md, out));
   if (smem > 160 * 1024) return hipErrorInvalidValue;
   hipError_t e = hipErrorInvalidValue;
 #define SVMC_EL(P_, C_) \

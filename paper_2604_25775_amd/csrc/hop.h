@@ -119,14 +119,15 @@ struct HopScratch {
   int klists, misc, bias, emb, bytes;
 };
 __host__ __device__ inline int align16i(int x) { return (x + 15) & ~15; }
-__host__ __device__ inline HopScratch hop_scratch(int Gx, int Gy, int L, int C, int tfb) {
+// rows_only: the caller stages only row-form matrices (16 x 17 per wavefront)
+__host__ __device__ inline HopScratch hop_scratch(int Gx, int Gy, int L, int C, int tfb, bool rows_only = false) {
   HopScratch h;
   const int SP = C + 16 / tfb;
   const int ox = Gx < 2 * L + 2 ? Gx : 2 * L + 2, oy = Gy < 2 * L + 2 ? Gy : 2 * L + 2;
   const int gb = (Gx * Gy + 1) * SP * tfb, db = ox * oy * (C + 4) * tfb;
   // two determinant stagings: column form (C + 1) x (C + 2) or row form
   // 16 x 17 doubles per wavefront, whichever is larger
-  const int sc = (C + 1) * (C + 2), sr = 16 * 17;
+  const int sc = rows_only ? 0 : (C + 1) * (C + 2), sr = 16 * 17;
   const int sb = 2 * (sc > sr ? sc : sr) * 8;
   const int rb = gb > db ? gb : db;
   h.klists = align16i(rb > sb ? rb : sb);
@@ -429,7 +430,10 @@ SVMC_DEV void mlp_tile_grid(const typename PrecT<P>::Tf* __restrict__ grid, int 
 // are requested, the new values are formed (still in registers), a barrier,
 // then they replace the layer input on the grid and the ring of the next
 // input box is filled from the cache.
-template <int P, int C, int NW>
+// MAXTILES: 16-site tiles of the largest layer box the caller allows (7 for
+// up to four conv layers: at most 10 x 10 sites; 1 for one conv layer: at
+// most 4 x 4), which sizes the registers holding a layer's results.
+template <int P, int C, int NW, int MAXTILES = 7>
 SVMC_DEV void hop_features(const ModelDev& md, const LatDev& lt, const HopGeom& h, const int8_t* occ_s,
                            const typename PrecT<P>::Tf* featw,
                            typename PrecT<P>::Tf* commit, char* scratch, const HopScratch& hs,
@@ -539,7 +543,7 @@ SVMC_DEV void hop_features(const ModelDev& md, const LatDev& lt, const HopGeom& 
     // finished reading the grid of this layer (at most 7 tiles: the layer-L
     // box of L <= 4 has at most 10 x 10 sites).  The lane's site is the same
     // in all four slots v (OutMap).
-    constexpr int MAXT = (7 + NW - 1) / NW;
+    constexpr int MAXT = (MAXTILES + NW - 1) / NW;
     Acc acc[MAXT][CC::NT];
     int gsite[MAXT];               // grid record of the lane's site, -1 for padding rows
 #pragma unroll

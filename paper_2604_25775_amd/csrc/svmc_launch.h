@@ -57,7 +57,7 @@ struct ElocOut {
   int slices;       // workgroups per walker
   int row_form_max; // hops whose spins both change at most this many rows (0, 8 or 16) use the row form
 };
-size_t eloc_lowrank_smem(const LatDev* lats_host, int nlats, int prec, int L, int C);
+size_t eloc_lowrank_smem(const LatDev* lats_host, int nlats, int prec, int L, int C, bool rows_only);
 // Allocation-free local energies: the per-slice partial sums live in a fixed
 // device array of kNoAllocPartials doubles (8 MiB) per device.
 // noalloc_scratch_init looks its address up for device `dev` (which must be
