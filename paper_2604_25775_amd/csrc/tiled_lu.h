@@ -84,6 +84,12 @@ SVMC_DEV void tiled_gj(double (&x)[R][R], int n, GjShared<R>& sh, double& logabs
     if (tid == 0) { sh.perm[p] = pi; sh.pvs[p] = pv; }
     __syncthreads();
     const double inv = 1.0 / pv;
+    // this thread's entries of the pivot row, read once per step
+    double r[R];
+#pragma unroll
+    for (int b = 0; b < R; ++b) r[b] = sh.rowbuf[buf][tx + 16 * b];
+    // column p sits in register column bp of the threads with tx = p mod 16
+    const bool pcol = tx == (p & 15);
 #pragma unroll
     for (int a = 0; a < R; ++a) {
       const int k = ty + 16 * a;
@@ -94,10 +100,13 @@ SVMC_DEV void tiled_gj(double (&x)[R][R], int n, GjShared<R>& sh, double& logabs
       for (int b = 0; b < R; ++b) {
         const int m = tx + 16 * b;
         if (INVERT) {
-          if (isp) x[a][b] = (m == p) ? inv : x[a][b] * inv;
-          else x[a][b] = (m == p) ? -f : fma(-f, sh.rowbuf[buf][m], x[a][b]);
+          // selects, not branches: the pivot row is scaled, every other row
+          // eliminates column p, and column p takes the new inverse column
+          const double upd = isp ? x[a][b] * inv : fma(-f, r[b], x[a][b]);
+          const double newc = isp ? inv : -f;
+          x[a][b] = (b == bp && pcol) ? newc : upd;
         } else if (live && m > p) {
-          x[a][b] = fma(-f, sh.rowbuf[buf][m], x[a][b]);
+          x[a][b] = fma(-f, r[b], x[a][b]);
         }
       }
       if (isp) used[a] = true;
