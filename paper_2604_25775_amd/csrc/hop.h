@@ -1018,8 +1018,9 @@ SVMC_DEV void hop_det_stage(const v4d (&acc)[DetTiles<C>::I][DetTiles<C>::J], co
       }
   if (hopspin) {
     const int kh = K > 0 ? kl[hpos] & 0xffff : 0;
-    if (lane < C) stage[lane * RS + C] = K > 0 ? PTt[kh * C + lane] : 0.0;
-    else if (lane == C) stage[C * RS + C] = K > 0 ? Gj[kh] : 1.0;
+    const double pv = PTt[kh * C + (lane < C ? lane : 0)], gv = Gj[kh];    // unconditional loads
+    if (lane < C) stage[lane * RS + C] = K > 0 ? pv : 0.0;
+    else if (lane == C) stage[C * RS + C] = K > 0 ? gv : 1.0;
   }
   // lanes read rows other lanes wrote: order the accesses for the compiler
   // (the hardware keeps a wavefront's LDS operations in order)
@@ -1208,15 +1209,20 @@ SVMC_DEV v4d hop_det_row_build(const int* kl, int K_in, const DT* Dbuf, const do
   constexpr int SD = DStride<C>::value;
   const int K = uniform_i(K_in);
   const int li = lane & 15, lk = lane >> 4;
-  const int e = li < K ? kl[li] : 0;
-  const int mrow = (e >> 16) * SD, kcol = e & 0xffff;
+  const bool ok = li < K;
+  const int e = kl[ok ? li : 0];
+  const int mrow = ok ? (e >> 16) * SD : 0, kcol = ok ? e & 0xffff : 0;
+  // all operands requested at once (unconditional loads from valid
+  // addresses, masked afterwards), then the C / 4 k-steps
+  double av[C / 4], bv[C / 4];
+#pragma unroll
+  for (int q = 0; q < C / 4; ++q) {
+    av[q] = (double)Dbuf[mrow + 4 * q + lk];
+    bv[q] = PTt[kcol * C + 4 * q + lk];
+  }
   v4d acc = v4d{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-  for (int c0 = 0; c0 < C; c0 += 4) {
-    const double av = li < K ? (double)Dbuf[mrow + c0 + lk] : 0.0;
-    const double bv = li < K ? PTt[kcol * C + c0 + lk] : 0.0;
-    mfma(acc, av, bv);
-  }
+  for (int q = 0; q < C / 4; ++q) mfma(acc, ok ? av[q] : 0.0, ok ? bv[q] : 0.0);
   return acc;
 }
 // Adds E and stages the matrix row-major [KS][KS + 1] (KS = 8 or 16 >= K);
@@ -1226,13 +1232,14 @@ SVMC_DEV void hop_det_row_stage(const v4d& acc, const int* kl, int K_in, bool ho
                                 const double* __restrict__ Gj, double* stage, int lane) {
   const int K = uniform_i(K_in), hpos = uniform_i(hpos_in);
   const int li = lane & 15, lk = lane >> 4;
-  const int kcol = li < K ? kl[li] & 0xffff : 0;
+  const int kcol = li < K ? kl[li < K ? li : 0] & 0xffff : 0;
+  const double gk = Gj[kcol];       // unconditional (valid address), used on the mover's row
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
     const int r = lk + 4 * v, c = li;
     if (r >= KS || c >= KS) continue;
     double val;
-    if (r < K && c < K) val = acc[v] + ((hopspin && r == hpos) ? Gj[kcol] : (r == c ? 1.0 : 0.0));
+    if (r < K && c < K) val = acc[v] + ((hopspin && r == hpos) ? gk : (r == c ? 1.0 : 0.0));
     else val = r == c ? 1.0 : 0.0;
     stage[r * (KS + 1) + c] = val;
   }
