@@ -295,7 +295,7 @@ svmc_status svmc_get_launch(const svmc_ctx* ctx, svmc_launch* launch);
 /* Autotuner of the low-rank local-energy launch shape (svmc_launch): times
  * svmc_local_energy(LOWRANK) on the loaded walkers for slices in
  * {1, 2, 4, 8, 16, 24, 32} x row_form_max in {0, 8, 16} and keeps, among
- * the shapes within 2 % of the fastest, the one with the fewest slices and
+ * the shapes within 0.5 % of the fastest, the one with the fewest slices and
  * then the largest row-form limit (so that timing noise does not flip the
  * choice between runs).  cache_path (may be NULL): a text file; a line
  * for the same shape key (lattices, network, precision, walker count,

@@ -975,14 +975,14 @@ svmc_status svmc_tune(svmc_ctx* ctx, const char* cache_path, int32_t* slices_out
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  // among the shapes within 2 % of the fastest (timing noise), the fewest
-  // slices per walker, then the largest row-form limit: the choice does not
-  // flip between runs on differences the timer cannot resolve
+  // among the shapes within 0.5 % of the fastest (timing noise), the
+  // fewest slices per walker, then the largest row-form limit: the choice
+  // does not flip between runs on differences the timer cannot resolve
   if (!s) {
     bool have = false;
     for (int v = 0; v < nv; ++v) {
       const int c = cand[v % 7], rf = forms[v / 7];
-      if (tv[v] > 1.02f * best_ms) continue;
+      if (tv[v] > 1.005f * best_ms) continue;
       if (!have || c < best || (c == best && rf > best_rf)) {
         best = c;
         best_rf = rf;

@@ -107,8 +107,9 @@ SVMC_DEV void eloc_block(long long b, int S, long long& w, int& slice) {
 // SMALL: the instance for one conv layer, whose update boxes hold at most
 // 4 x 4 sites, so at most 16 changed rows per spin: the row form always
 // applies, the column form and the registers of larger boxes are left out,
-// and more wavefronts fit per SIMD.
-template <int P, int C, bool SMALL>
+// and more wavefronts fit per SIMD.  MLP: the instance for networks with
+// site-wise layers (the others do not carry that code).
+template <int P, int C, bool SMALL, bool MLP>
 __global__ __launch_bounds__(64 * ELOC_NW) __attribute__((amdgpu_waves_per_eu(SMALL ? 4 : 3))) void k_eloc_lowrank(
     ModelDev md, const LatDev* __restrict__ lats, int nlats, Bufs bf, ElocOut out, long long Wtot) {
   typedef typename PrecT<P>::Tf Tf;
@@ -166,8 +167,8 @@ __global__ __launch_bounds__(64 * ELOC_NW) __attribute__((amdgpu_waves_per_eu(SM
       const HopGeom g = hop_geom(lt, md.L, sp, i, d);
       int olx, owx, oly, owy;
       const AxisTab tab = axis_tab(g, md.L, lane);
-      hop_features<P, C, NW, SMALL ? 1 : 7>(md, lt, g, occ_s, featw, (Tf*)nullptr, scratch, hsc, tab, olx, owx, oly,
-                                            owy);
+      hop_features<P, C, NW, SMALL ? 1 : 7, MLP>(md, lt, g, occ_s, featw, (Tf*)nullptr, scratch, hsc, tab, olx, owx,
+                                                 oly, owy);
       // wavefront wv: determinant of spin wv
       int hpos;
       const int K = hop_klist(lt, g, tab, occ_s, lab_s, wv, olx, owx, oly, owy, kl, hpos, lane);
@@ -265,7 +266,9 @@ static hipError_t eloc_impl(const ModelDev& md, const LatDev* lats_dev, int nlat
                             const ElocOut& out, size_t smem, hipStream_t st) {
   // one conv layer with the row form allowed up to 16 rows: every hop takes
   // the row form, so the smaller instance serves
-  auto kern = eloc_small(md, out) ? k_eloc_lowrank<P, C, true> : k_eloc_lowrank<P, C, false>;
+  const bool sm = eloc_small(md, out), ml = md.M > 0;
+  auto kern = sm ? (ml ? k_eloc_lowrank<P, C, true, true> : k_eloc_lowrank<P, C, true, false>)
+                 : (ml ? k_eloc_lowrank<P, C, false, true> : k_eloc_lowrank<P, C, false, false>);
   hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
   if (e != hipSuccess) return e;
   const long long nblk = ((W + 7) / 8) * 8 * out.slices;

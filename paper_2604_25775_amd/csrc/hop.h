@@ -432,8 +432,10 @@ SVMC_DEV void mlp_tile_grid(const typename PrecT<P>::Tf* __restrict__ grid, int 
 // input box is filled from the cache.
 // MAXTILES: 16-site tiles of the largest layer box the caller allows (7 for
 // up to four conv layers: at most 10 x 10 sites; 1 for one conv layer: at
-// most 4 x 4), which sizes the registers holding a layer's results.
-template <int P, int C, int NW, int MAXTILES = 7>
+// most 4 x 4), which sizes the registers holding a layer's results.  MLP:
+// the network may have site-wise layers (md.M > 0); without them the
+// site-wise stage is not compiled in.
+template <int P, int C, int NW, int MAXTILES = 7, bool MLP = false>
 SVMC_DEV void hop_features(const ModelDev& md, const LatDev& lt, const HopGeom& h, const int8_t* occ_s,
                            const typename PrecT<P>::Tf* featw,
                            typename PrecT<P>::Tf* commit, char* scratch, const HopScratch& hs,
@@ -624,7 +626,7 @@ SVMC_DEV void hop_features(const ModelDev& md, const LatDev& lt, const HopGeom& 
     __syncthreads();
     // the cached features the new ones replace: the last plane (conv layer L,
     // or the last site-wise layer)
-    const int M = md.M, FL = L + M - 1;
+    const int M = MLP ? md.M : 0, FL = L + M - 1;
     const Tf* HL = featw + (long long)FL * N * C;
     typedef typename DType<P>::type DT;
     // this tile's new values replace the old ones on the grid (and go to
@@ -694,7 +696,7 @@ SVMC_DEV void hop_features(const ModelDev& md, const LatDev& lt, const HopGeom& 
       if (!dnow) put_tile(ti, s, l - 1);
       else put_D(ti, r, s);
     }
-    if (l == L && M > 0) {
+    if (MLP && l == L && M > 0) {
       // the site-wise layers (Sec. II.B, site-wise MLP equation) on the
       // layer-L box: each wavefront runs its own tiles, a site reading only
       // its own record, so the wavefronts do not wait for each other

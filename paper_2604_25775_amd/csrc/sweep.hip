@@ -154,7 +154,8 @@ SVMC_DEV bool gj_inverse_rot(double (&a)[RM], int r_in, int lane, int* perm, int
 
 #ifdef SVMC_INST_P
 // Proposal sa.q of every walker (one workgroup of two wavefronts per walker).
-template <int P, int C>
+// MLP: the instance for networks with site-wise layers.
+template <int P, int C, bool MLP>
 __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(3))) void k_step_propose(ModelDev md, const LatDev* __restrict__ lats, int nlats,
                                                       Bufs bf, StepArgs sa) {
   typedef typename PrecT<P>::Tf Tf;
@@ -222,7 +223,7 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(3))) void k
   const HopGeom g = hop_geom(lt, md.L, sp, i, d);
   const AxisTab tab = axis_tab(g, md.L, lane);
   int olx, owx, oly, owy;
-  hop_features<P, C, NW>(md, lt, g, occ_s, featw, (Tf*)nullptr, scratch, hsc, tab, olx, owx, oly, owy);
+  hop_features<P, C, NW, 7, MLP>(md, lt, g, occ_s, featw, (Tf*)nullptr, scratch, hsc, tab, olx, owx, oly, owy);
   const int KM = lt.Gx * lt.Gy;
   int* kl = (int*)(scratch + hsc.klists) + wv * KM;
   double* misc = (double*)(scratch + hsc.misc);
@@ -305,7 +306,7 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(3))) void k
   const bool fallback = misc[6] == 0.0 || misc[7] == 0.0;
 
   // ---- commit: the box features recomputed with write-back (D fresh in LDS)
-  hop_features<P, C, NW>(md, lt, g, occ_s, featw, featw, scratch, hsc, tab, olx, owx, oly, owy);
+  hop_features<P, C, NW, 7, MLP>(md, lt, g, occ_s, featw, featw, scratch, hsc, tab, olx, owx, oly, owy);
   {
     const int nv = owx * owy * (C + 4) * (int)sizeof(DT) / 16;
     const float4* src = reinterpret_cast<const float4*>(scratch);
@@ -571,7 +572,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
 template <int P, int C>
 static hipError_t step_impl(const ModelDev& md, const LatDev* lats_dev, int nlats, long long W, const Bufs& bf,
                             const StepArgs& sa, size_t smem_p, size_t smem_u, int upd_blocks, hipStream_t st) {
-  auto kp = k_step_propose<P, C>;
+  auto kp = md.M > 0 ? k_step_propose<P, C, true> : k_step_propose<P, C, false>;
   auto ku = k_step_update<P, C>;
   hipError_t e = hipFuncSetAttribute((const void*)kp, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem_p);
   if (e != hipSuccess) return e;
