@@ -1,6 +1,8 @@
-"""Lattice geometry and the connected configurations of the Hubbard
-Hamiltonian (Sec. III, Hubbard Hamiltonian: nearest-neighbour hopping t,
-next-nearest-neighbour hopping t', on-site U).
+"""Lattice geometry and the connected configurations of the Hubbard and t-J
+Hamiltonians (Sec. III: nearest-neighbour hopping t, next-nearest-neighbour
+hopping t', on-site U; in the t-J model the hops are Gutzwiller-projected,
+so none may create a doubly occupied site, and J S_i.S_j on nearest-neighbour
+bonds adds the spin exchanges).
 
 Site index s = x + Lx*y.  Periodic axes wrap; open axes drop neighbours that
 fall off the lattice.  A periodic axis must have length >= 3 so that its +
@@ -48,10 +50,23 @@ class Hop:
     t: float       # hopping amplitude of the bond (t or t')
 
 
+@dataclass(frozen=True)
+class Exchange:
+    """Spin exchange across a nearest-neighbour bond (t-J model, the
+    transverse part of J S_i.S_j): the up electron at i and the down electron
+    at j trade sites."""
+    i: int         # site of the up electron (it moves to j)
+    j: int         # site of the down electron (it moves to i)
+    d: int         # direction of j from i, 0..3
+    t: float       # J / 2: the local-energy term is -t * R, as for a hop
+
+
 def hops(lat, occ) -> list:
     """All configurations connected to ``occ`` by one hopping term, in the
     canonical order: spin up before down, source site ascending, direction
-    in DIRS order (the four next-nearest directions only when t' != 0)."""
+    in DIRS order (the four next-nearest directions only when t' != 0).  In
+    the t-J model a hop onto a site that holds the other spin is left out
+    (the Gutzwiller projector gives it amplitude zero)."""
     nd = 8 if lat.tp != 0.0 else 4
     out = []
     for spin in (0, 1):
@@ -61,14 +76,42 @@ def hops(lat, occ) -> list:
                 continue
             for d in range(nd):
                 j = neighbour(lat, i, *DIRS[d])
-                if j < 0 or occ[j] & bit:
+                if j < 0 or (occ[j] != 0 if lat.tj else occ[j] & bit):
                     continue
                 out.append(Hop(spin, i, j, d, lat.t if d < 4 else lat.tp))
     return out
 
 
-def apply_hop(occ, h: Hop):
+def exchanges(lat, occ) -> list:
+    """The spin exchanges of the t-J model (none otherwise): every
+    nearest-neighbour bond with an up electron alone on one end and a down
+    electron alone on the other, listed once from its up end, up site
+    ascending, direction in DIRS order."""
+    if not lat.tj:
+        return []
+    out = []
+    for i in range(lat.N):
+        if occ[i] != 1:
+            continue
+        for d in range(4):
+            j = neighbour(lat, i, *DIRS[d])
+            if j >= 0 and occ[j] == 2:
+                out.append(Exchange(i, j, d, 0.5 * lat.J))
+    return out
+
+
+def connections(lat, occ) -> list:
+    """The canonical order of the connected configurations: the hops, then
+    the spin exchanges."""
+    return hops(lat, occ) + exchanges(lat, occ)
+
+
+def apply_hop(occ, h):
+    """The configuration reached by a Hop or an Exchange."""
     o = occ.copy()
+    if isinstance(h, Exchange):
+        o[h.i], o[h.j] = occ[h.j], occ[h.i]
+        return o
     bit = 1 << h.spin
     o[h.i] -= bit
     o[h.j] += bit

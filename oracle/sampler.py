@@ -7,7 +7,8 @@ Proposal p of walker w draws one Philox block (counter (w, step, 0, 0)):
 an electron index e over all N_up + N_dn electrons (labels of spin up first),
 a direction d in {+x, -x, +y, -y} and a uniform u.  The move is rejected
 without evaluation when the target site is off the lattice or already holds
-an electron of the same spin; otherwise it is accepted iff u < R^2 with R the
+an electron of the same spin (in the t-J model: any electron, since the
+Gutzwiller projector gives a doubly occupied site amplitude zero); otherwise it is accepted iff u < R^2 with R the
 amplitude ratio, here recomputed in full.  Electron labels keep their
 identity: an accepted move changes the site of label e only.  One sweep is N
 proposals.
@@ -47,7 +48,7 @@ def metropolis(lat, params, occ, pos, walker: int, seed: int, step0: int,
             bit = 1 << spin
             i = int(pos[spin][k])
             j = neighbour(lat, i, *DIRS[d])
-            if j < 0 or occ[j] & bit:
+            if j < 0 or (occ[j] != 0 if lat.tj else occ[j] & bit):
                 continue
             new = occ.copy()
             new[i] -= bit

@@ -13,7 +13,12 @@ from oracle.energy import local_energy
 CODE_DIRS = 8
 
 
-def hop_code(h):
+def hop_code(h, N):
+    """The library's code of a connected configuration: (i << 4) | (spin << 3)
+    | d for a hop, ((N + i) << 4) | d for a spin exchange from up site i."""
+    from oracle.lattice import Exchange
+    if isinstance(h, Exchange):
+        return ((N + h.i) << 4) | h.d
     return (h.i << 4) | (h.spin << 3) | h.d
 
 
@@ -66,7 +71,7 @@ def check_walkers(ctx, lats, params, occs, model, tol_ratio, tol_eloc, path="low
                 assert sign[w] == s_ref, (li, k, sign[w], s_ref)
                 worst["logpsi"] = max(worst["logpsi"], abs(la[w] - l_ref) / max(1.0, abs(l_ref)))
             assert nh[w] == len(hs), (li, k, nh[w], len(hs))
-            codes = [hop_code(h) for h in hs]
+            codes = [hop_code(h, lat.N) for h in hs]
             assert list(code[w, :len(hs)]) == codes, (li, k)
             floor = 1e-3 * np.sqrt(np.mean(R_ref ** 2)) if len(hs) else 1.0
             for r, rr in zip(rat[w, :len(hs)], R_ref):

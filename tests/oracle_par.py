@@ -23,11 +23,11 @@ def _init(lat, params, li, act):
 
 def _ratio(task):
     from oracle.ansatz import log_psi
-    from oracle.energy import jw_sign
+    from oracle.energy import connection_sign
     from oracle.lattice import apply_hop
     occ, h, s0, l0 = task
     s1, l1 = log_psi(_P["lat"], _P["params"], apply_hop(occ, h), _P["li"], _P["act"])
-    return jw_sign(occ, h.spin, h.i, h.j) * s1 * s0 * np.exp(l1 - l0)
+    return connection_sign(occ, h) * s1 * s0 * np.exp(l1 - l0)
 
 
 def _logpsi(occ):
@@ -54,18 +54,19 @@ def local_energies(lat, params, occs, li: int = 0, act: str = "tanh"):
     """[(E_loc, hops, ratios, (sign, log|psi|))] of each occupation, every hop
     ratio recomputed in full by the oracle, the hops of all walkers spread
     over the pool."""
-    from oracle.lattice import hops
+    from oracle.energy import diagonal_energy
+    from oracle.lattice import connections
     occs = [np.asarray(o) for o in occs]
     with _pool(len(occs), lat, params, li, act) as pool:
         ref = pool.map(_logpsi, occs)
-        hs = [hops(lat, o) for o in occs]
+        hs = [connections(lat, o) for o in occs]
         tasks = [(o, h, s0, l0) for o, hh, (s0, l0) in zip(occs, hs, ref) for h in hh]
         R = pool.map(_ratio, tasks, chunksize=max(1, len(tasks) // (8 * procs(len(tasks)))))
     out, k = [], 0
     for o, hh, r0 in zip(occs, hs, ref):
         r = np.array(R[k:k + len(hh)])
         k += len(hh)
-        e = lat.U * float(np.sum(o == 3))
+        e = diagonal_energy(lat, o)
         for h, x in zip(hh, r):
             e += -h.t * x
         out.append((e, hh, r, r0))

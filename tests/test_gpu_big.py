@@ -87,7 +87,7 @@ def test_32x32_448_full_batch_sampled():
         assert abs(la[k] - l_ref) <= 1e-6 * max(1.0, abs(l_ref)), (k, la[k], l_ref)
         hs = hops(lat, occ[k])
         assert nh[k] == len(hs)
-        assert list(code[k, :len(hs)]) == [hop_code(h) for h in hs]
+        assert list(code[k, :len(hs)]) == [hop_code(h, lat.N) for h in hs]
         rms = np.sqrt(np.mean(rat[k, :nh[k]] ** 2))
         for hh in rng.choice(len(hs), 6, replace=False):
             h = hs[hh]

@@ -45,7 +45,7 @@ def compare_sampled(ctx, lat, params, occ, sample, model, tol_ratio, tol_eloc, t
         assert sign[k] == s_ref, k
         worst["logpsi"] = max(worst["logpsi"], abs(la[k] - l_ref) / max(1.0, abs(l_ref)))
         assert nh[k] == len(hs), (k, nh[k], len(hs))
-        assert list(code[k, :len(hs)]) == [hop_code(h) for h in hs], k
+        assert list(code[k, :len(hs)]) == [hop_code(h, lat.N) for h in hs], k
         floor = 1e-3 * np.sqrt(np.mean(R_ref ** 2))
         for r, rr in zip(rat[k, :len(hs)], R_ref):
             worst["ratio"] = max(worst["ratio"], rel_err(r, rr, floor))

@@ -24,7 +24,10 @@ import numpy as np
 # --------------------------------------------------------------------------
 @dataclass(frozen=True)
 class Lattice:
-    """A Lx x Ly Hubbard lattice; site index s = x + Lx*y (x fastest)."""
+    """A Lx x Ly lattice; site index s = x + Lx*y (x fastest).  The Hubbard
+    model by default; ``tj`` = 1 selects the t-J model (no doubly occupied
+    site, exchange coupling ``J`` on nearest-neighbour bonds, staggered
+    pinning field ``h_pin`` on the column x = 0); U is then unused."""
     Lx: int
     Ly: int
     pbc_x: int = 1
@@ -34,6 +37,9 @@ class Lattice:
     U: float = 8.0
     n_up: int = 1
     n_dn: int = 1
+    tj: int = 0
+    J: float = 0.0
+    h_pin: float = 0.0
 
     @property
     def N(self) -> int:
@@ -291,13 +297,18 @@ def f16_pair(x: np.ndarray) -> np.ndarray:
 # occupations
 # --------------------------------------------------------------------------
 def random_occupations(lat: Lattice, n_walkers: int, seed: int = 1) -> np.ndarray:
-    """[n_walkers, N] int8, value n_up + 2 n_dn, exact electron counts."""
+    """[n_walkers, N] int8, value n_up + 2 n_dn, exact electron counts (for
+    the t-J model no site doubly occupied)."""
     rng = np.random.Generator(np.random.PCG64(seed))
     N = lat.N
     occ = np.zeros((n_walkers, N), dtype=np.int8)
     for w in range(n_walkers):
-        up = rng.permutation(N)[: lat.n_up]
-        dn = rng.permutation(N)[: lat.n_dn]
+        if lat.tj:
+            perm = rng.permutation(N)
+            up, dn = perm[: lat.n_up], perm[lat.n_up: lat.n_up + lat.n_dn]
+        else:
+            up = rng.permutation(N)[: lat.n_up]
+            dn = rng.permutation(N)[: lat.n_dn]
         occ[w, up] += 1
         occ[w, dn] += 2
     return occ
