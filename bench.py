@@ -106,7 +106,8 @@ def lowrank_flops(lat, occ: np.ndarray, L: int, C: int, n_mlp: int = 0):
     conv work, same precision); per spin, k electrons
     of the new configuration lie within distance L, the determinant-lemma
     matrix has rank r = min(k, C + [moving spin]), its assembly costs k C r
-    and its LU r^3 / 3 multiply-adds."""
+    and its LU r^3 / 3 multiply-adds.  t-J lattices: hops only onto empty
+    sites, and the spin exchanges, with both spins moving."""
     W, N = occ.shape
     Lx, Ly = lat.Lx, lat.Ly
     nd = 8 if lat.tp != 0.0 else 4
@@ -157,51 +158,59 @@ def lowrank_flops(lat, occ: np.ndarray, L: int, C: int, n_mlp: int = 0):
         wi = np.arange(W)[:, None]
         return (s[wi, Y0 + wy, X0 + wx] - s[wi, Y0, X0 + wx] - s[wi, Y0 + wy, X0] + s[wi, Y0, X0])
 
-    for sp in (0, 1):
-        mine = ups if sp == 0 else dns
-        for d in range(nd):
-            xj, yj = xs + DX[d], ys + DY[d]
-            okx = (xj >= 0) & (xj < Lx) if not lat.pbc_x else np.ones_like(xj, bool)
-            oky = (yj >= 0) & (yj < Ly) if not lat.pbc_y else np.ones_like(yj, bool)
-            ok = okx & oky
-            xjw, yjw = xj % Lx, yj % Ly
-            jsite = np.where(ok, xjw + Lx * yjw, 0)
-            src = mine.reshape(W, N)
-            valid = (src == 1) & ok[None, :] & (src[:, jsite] == 0)     # [W, N]
-            nh = valid.sum()
-            if nh == 0:
-                continue
-            # conv work: layer l recomputes the union of the two Chebyshev
-            # balls of radius l (a rectangle for nearest-neighbour hops; for
-            # diagonal hops counted from per-site masks)
-            diag = DX[d] != 0 and DY[d] != 0
-            for l in range(1, L + 1):
-                if diag:
-                    if l not in balls:
-                        balls[l] = ball_mask(l)
-                    sites = (balls[l] | balls[l][jsite]).sum(axis=1)
-                else:
-                    _, wx = axis_range(xs, xj, l, Lx, lat.pbc_x)
-                    _, wy = axis_range(ys, yj, l, Ly, lat.pbc_y)
-                    sites = wx * wy
-                conv += float((valid * sites[None, :]).sum()) * 9 * C * C * 2
-                if l == L:
-                    conv += float((valid * sites[None, :]).sum()) * n_mlp * C * C * 2
+    occ2 = occ.reshape(W, N)
+    # kinds of connection: hops of spin 0 and 1, then (t-J) spin exchanges,
+    # whose two moving spins both take the larger column form
+    kinds = [(0, d) for d in range(nd)] + [(1, d) for d in range(nd)]
+    if lat.tj:
+        kinds += [(2, d) for d in range(4)]
+    for sp, d in kinds:
+        xj, yj = xs + DX[d], ys + DY[d]
+        okx = (xj >= 0) & (xj < Lx) if not lat.pbc_x else np.ones_like(xj, bool)
+        oky = (yj >= 0) & (yj < Ly) if not lat.pbc_y else np.ones_like(yj, bool)
+        ok = okx & oky
+        xjw, yjw = xj % Lx, yj % Ly
+        jsite = np.where(ok, xjw + Lx * yjw, 0)
+        if sp == 2:
+            valid = (occ2 == 1) & ok[None, :] & (occ2[:, jsite] == 2)
+        else:
+            src = (ups if sp == 0 else dns).reshape(W, N)
+            free = (occ2[:, jsite] == 0) if lat.tj else (src[:, jsite] == 0)
+            valid = (src == 1) & ok[None, :] & free                # [W, N]
+        nh = valid.sum()
+        if nh == 0:
+            continue
+        # conv work: layer l recomputes the union of the two Chebyshev
+        # balls of radius l (a rectangle for nearest-neighbour hops; for
+        # diagonal hops counted from per-site masks)
+        diag = DX[d] != 0 and DY[d] != 0
+        for l in range(1, L + 1):
             if diag:
-                if L not in balls:
-                    balls[L] = ball_mask(L)
-                uni = (balls[L] | balls[L][jsite]).astype(np.int64)          # [N(site i), N]
-                ku = ups.reshape(W, N) @ uni.T
-                kd = dns.reshape(W, N) @ uni.T
+                if l not in balls:
+                    balls[l] = ball_mask(l)
+                sites = (balls[l] | balls[l][jsite]).sum(axis=1)
             else:
-                x0, wx = axis_range(xs, xj, L, Lx, lat.pbc_x)
-                y0, wy = axis_range(ys, yj, L, Ly, lat.pbc_y)
-                ku = box_count(sat_u, x0[None, :], wx[None, :], y0[None, :], wy[None, :])
-                kd = box_count(sat_d, x0[None, :], wx[None, :], y0[None, :], wy[None, :])
-            for tau, k in ((0, ku), (1, kd)):
-                r = np.minimum(k, C + (1 if tau == sp else 0))
-                fma = k * C * r + r ** 3 / 3.0
-                det += 2.0 * float((valid * fma).sum())
+                _, wx = axis_range(xs, xj, l, Lx, lat.pbc_x)
+                _, wy = axis_range(ys, yj, l, Ly, lat.pbc_y)
+                sites = wx * wy
+            conv += float((valid * sites[None, :]).sum()) * 9 * C * C * 2
+            if l == L:
+                conv += float((valid * sites[None, :]).sum()) * n_mlp * C * C * 2
+        if diag:
+            if L not in balls:
+                balls[L] = ball_mask(L)
+            uni = (balls[L] | balls[L][jsite]).astype(np.int64)          # [N(site i), N]
+            ku = ups.reshape(W, N) @ uni.T
+            kd = dns.reshape(W, N) @ uni.T
+        else:
+            x0, wx = axis_range(xs, xj, L, Lx, lat.pbc_x)
+            y0, wy = axis_range(ys, yj, L, Ly, lat.pbc_y)
+            ku = box_count(sat_u, x0[None, :], wx[None, :], y0[None, :], wy[None, :])
+            kd = box_count(sat_d, x0[None, :], wx[None, :], y0[None, :], wy[None, :])
+        for tau, k in ((0, ku), (1, kd)):
+            r = np.minimum(k, C + (1 if tau == sp or sp == 2 else 0))
+            fma = k * C * r + r ** 3 / 3.0
+            det += 2.0 * float((valid * fma).sum())
     return conv, det
 
 
@@ -220,17 +229,26 @@ def ctx_hops(lat, occ):
     xs, ys = np.meshgrid(np.arange(lat.Lx), np.arange(lat.Ly))
     xs, ys = xs.ravel(), ys.ravel()
     cnt = np.zeros(W, np.int64)
+
+    def target(d):
+        xj, yj = xs + DX[d], ys + DY[d]
+        ok = np.ones(N, bool)
+        if not lat.pbc_x:
+            ok &= (xj >= 0) & (xj < lat.Lx)
+        if not lat.pbc_y:
+            ok &= (yj >= 0) & (yj < lat.Ly)
+        return ok, (xj % lat.Lx) + lat.Lx * (yj % lat.Ly)
+
     for sp in (0, 1):
         mine = ((occ >> sp) & 1).astype(bool)
         for d in range(nd):
-            xj, yj = xs + DX[d], ys + DY[d]
-            ok = np.ones(N, bool)
-            if not lat.pbc_x:
-                ok &= (xj >= 0) & (xj < lat.Lx)
-            if not lat.pbc_y:
-                ok &= (yj >= 0) & (yj < lat.Ly)
-            j = (xj % lat.Lx) + lat.Lx * (yj % lat.Ly)
-            cnt += np.sum(mine & ok[None, :] & ~mine[:, j], axis=1)
+            ok, j = target(d)
+            free = (occ[:, j] == 0) if lat.tj else ~mine[:, j]
+            cnt += np.sum(mine & ok[None, :] & free, axis=1)
+    if lat.tj:
+        for d in range(4):
+            ok, j = target(d)
+            cnt += np.sum((occ == 1) & ok[None, :] & (occ[:, j] == 2), axis=1)
     return cnt
 
 
@@ -279,6 +297,7 @@ SPEEDUP_ROWS = [
     ("16x16, 1 conv layer", "c3", 1, 8192, 1024, {}),
     ("16x16, 1 conv layer + 4 site-wise layers, SiLU", "c3", 1, 8192, 1024, {"n_mlp": 4, "act": "silu"}),
     ("32x32 448+448, 4 conv layers", "c5", None, 1024, 4, {}),
+    ("16x8 t-J cylinder 56+56, 1 conv layer + 4 site-wise layers, SiLU", "tj", None, 8192, 1024, {}),
 ]
 
 

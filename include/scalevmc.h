@@ -78,14 +78,25 @@ typedef enum { SVMC_ACT_TANH = 0, SVMC_ACT_SILU = 1 } svmc_act;
 typedef enum { SVMC_FP64 = 0, SVMC_FP32 = 1, SVMC_BF16 = 2, SVMC_BF16X3 = 3, SVMC_F16X2 = 4 } svmc_prec;
 typedef enum { SVMC_PATH_LOWRANK = 0, SVMC_PATH_FULL = 1 } svmc_path;
 
-/* Hubbard lattice (Sec. III, Hubbard Hamiltonian): Lx x Ly sites, periodic or
- * open per axis (a periodic axis needs length >= 3), hopping t (nearest
- * neighbours) and tp (next-nearest; 0 disables those hops), on-site U,
- * electrons per spin n_up, n_dn (each <= N). */
+/* Lattice and Hamiltonian (Sec. III): Lx x Ly sites, periodic or open per
+ * axis (a periodic axis needs length >= 3), hopping t (nearest neighbours)
+ * and tp (next-nearest; 0 disables those hops), electrons per spin n_up,
+ * n_dn (each <= N).
+ * tj = 0: Hubbard model, on-site U; J and h_pin must be 0.
+ * tj = 1: t-J model.  The Gutzwiller projection removes doubly occupied
+ *   sites: no hop onto an occupied site is a connected configuration, the
+ *   sampler rejects such moves, and a walker holding a doubly occupied site
+ *   is flagged SVMC_W_BADCOUNT.  J S_i.S_j on every nearest-neighbour bond
+ *   (S = the spin-1/2 operator of the site, no density term); a pinning
+ *   field h_pin (-1)^y S^z on the sites of the column x = 0 (the staggered
+ *   field on the left edge of a cylinder).  U is not used.  At most 2048
+ *   sites and n_up + n_dn <= N. */
 typedef struct {
   int32_t Lx, Ly, pbc_x, pbc_y;
   double t, tp, U;
   int32_t n_up, n_dn;
+  double J, h_pin;
+  int32_t tj, reserved;    /* reserved: set to 0 */
 } svmc_lattice;
 
 /* Network shape (Sec. II.B): an embedding layer, n_conv residual ksize x
@@ -147,7 +158,9 @@ svmc_status svmc_load_walkers(svmc_ctx* ctx, const int64_t* walkers_per_lattice,
 int64_t svmc_num_walkers(const svmc_ctx* ctx);
 
 /* Row stride of the per-hop outputs of svmc_local_energy: the largest number
- * of hops any walker can have, (n_up + n_dn) * (tp != 0 ? 8 : 4), over lattices. */
+ * of connected configurations any walker can have over the lattices,
+ * (n_up + n_dn) * (tp != 0 ? 8 : 4) hops, plus 4 min(n_up, n_dn) spin
+ * exchanges in the t-J model. */
 int32_t svmc_max_hops(const svmc_ctx* ctx);
 
 /* log|psi| and its sign for every walker.  sign: canonical sign, i.e. with the
@@ -163,7 +176,7 @@ svmc_status svmc_log_psi(svmc_ctx* ctx, double* sign, double* logabs,
  * changed since the last one; calling it explicitly always recomputes. */
 svmc_status svmc_prepare(svmc_ctx* ctx, hipStream_t stream);
 
-/* Local energies (Sec. II.A) with the Hubbard Hamiltonian (Sec. III).
+/* Local energies (Sec. II.A) with the Hubbard or t-J Hamiltonian (Sec. III).
  * path LOWRANK: incremental features + Woodbury ratios against the cached
  * inverses (Sec. II.C); FULL: every connected configuration recomputed from
  * scratch (full network forward and an FP64 LU per spin) - the O(N^4)
@@ -172,12 +185,18 @@ svmc_status svmc_prepare(svmc_ctx* ctx, hipStream_t stream);
  *   n_hops   device [W] int32   number of connected configurations
  *   hop_code device [W][svmc_max_hops] int32, code = (i << 4) | (spin << 3) | d
  *            with i the site the electron leaves, spin 0 up / 1 down, and d the
- *            direction +x, -x, +y, -y, +x+y, +x-y, -x+y, -x-y (0..7)
+ *            direction +x, -x, +y, -y, +x+y, +x-y, -x+y, -x-y (0..7); a spin
+ *            exchange (t-J) has code ((N + i) << 4) | d: the up electron on
+ *            site i and the down electron on its neighbour in direction d
+ *            (0..3) trade sites
  *   ratio    device [W][svmc_max_hops] FP64: det ratio with the moving
  *            electron keeping its row ("in-place"), so that the Hamiltonian
- *            term of the hop is -t_ij * ratio.
+ *            term of the hop is -t_ij * ratio; for an exchange both spins'
+ *            movers keep their rows and the term is -(J/2) * ratio.
  * Hops are listed spin up first, source site ascending, directions in the
- * order above.  The U term is U * (number of doubly occupied sites). */
+ * order above, then the exchanges, up site ascending.  The diagonal term is
+ * U * (number of doubly occupied sites) for the Hubbard model; for the t-J
+ * model J sum S^z_i S^z_j over the bonds plus the pinning field. */
 svmc_status svmc_local_energy(svmc_ctx* ctx, svmc_path path, double* eloc,
                               int32_t* n_hops, int32_t* hop_code, double* ratio,
                               hipStream_t stream);

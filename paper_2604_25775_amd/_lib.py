@@ -28,7 +28,8 @@ EXPORTS = [
 class Lattice(ct.Structure):
     _fields_ = [("Lx", ct.c_int32), ("Ly", ct.c_int32), ("pbc_x", ct.c_int32), ("pbc_y", ct.c_int32),
                 ("t", ct.c_double), ("tp", ct.c_double), ("U", ct.c_double),
-                ("n_up", ct.c_int32), ("n_dn", ct.c_int32)]
+                ("n_up", ct.c_int32), ("n_dn", ct.c_int32),
+                ("J", ct.c_double), ("h_pin", ct.c_double), ("tj", ct.c_int32), ("reserved", ct.c_int32)]
 
 
 class Model(ct.Structure):

@@ -59,7 +59,8 @@ class ScaleVMC:
         arr = (_lib.Lattice * len(self.lattices))()
         for k, l in enumerate(self.lattices):
             arr[k] = _lib.Lattice(l.Lx, l.Ly, int(l.pbc_x), int(l.pbc_y), float(l.t), float(l.tp),
-                                  float(l.U), l.n_up, l.n_dn)
+                                  float(l.U), l.n_up, l.n_dn, float(getattr(l, "J", 0.0)),
+                                  float(getattr(l, "h_pin", 0.0)), int(getattr(l, "tj", 0)), 0)
         m = _lib.Model(n_conv, channels, ACT[act], PREC[conv_prec], refresh_every, ksize, n_mlp,
                        int(bool(per_site_embed)))
         h = ct.c_void_p()

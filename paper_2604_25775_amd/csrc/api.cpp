@@ -79,6 +79,13 @@ float f16_pair(float x) {
 
 }  // namespace
 
+// Bound on the connected configurations of one walker: every electron hops
+// in at most 4 (t' = 0) or 8 directions; in the t-J model every lone up
+// electron also exchanges with at most 4 down neighbours.
+static int lattice_max_hops(const svmc_lattice& l) {
+  return (l.n_up + l.n_dn) * (l.tp != 0.0 ? 8 : 4) + (l.tj ? 4 * std::min(l.n_up, l.n_dn) : 0);
+}
+
 struct svmc_ctx {
   std::vector<svmc_lattice> lats;
   svmc_model model{};
@@ -153,7 +160,7 @@ struct svmc_ctx {
   }
   int max_hops() const {
     int m = 0;
-    for (auto& l : lats) m = std::max(m, (l.n_up + l.n_dn) * (l.tp != 0.0 ? 8 : 4));
+    for (auto& l : lats) m = std::max(m, lattice_max_hops(l));
     return m;
   }
   int max_elec() const {
@@ -176,8 +183,20 @@ static svmc_status check_lattice(const svmc_lattice& l, std::string& why) {
     return SVMC_ERR_INVALID_ARG;
   }
   if (std::max(l.n_up, l.n_dn) > 512) { why = "more than 512 electrons per spin"; return SVMC_ERR_UNSUPPORTED; }
-  if (!std::isfinite(l.t) || !std::isfinite(l.tp) || !std::isfinite(l.U)) {
+  if (!std::isfinite(l.t) || !std::isfinite(l.tp) || !std::isfinite(l.U) || !std::isfinite(l.J) ||
+      !std::isfinite(l.h_pin)) {
     why = "non-finite Hamiltonian parameter";
+    return SVMC_ERR_INVALID_ARG;
+  }
+  if (l.tj != 0 && l.tj != 1) { why = "tj must be 0 (Hubbard) or 1 (t-J)"; return SVMC_ERR_INVALID_ARG; }
+  if (l.reserved != 0) { why = "svmc_lattice.reserved must be 0"; return SVMC_ERR_INVALID_ARG; }
+  if (!l.tj && (l.J != 0.0 || l.h_pin != 0.0)) {
+    why = "J and h_pin belong to the t-J model (tj = 1)";
+    return SVMC_ERR_INVALID_ARG;
+  }
+  if (l.tj && N > 2048) { why = "t-J lattices hold at most 2048 sites"; return SVMC_ERR_UNSUPPORTED; }
+  if (l.tj && l.n_up + l.n_dn > N) {
+    why = "t-J: more electrons than sites (every site holds at most one)";
     return SVMC_ERR_INVALID_ARG;
   }
   return SVMC_OK;
@@ -464,13 +483,14 @@ svmc_status svmc_load_walkers(svmc_ctx* ctx, const int64_t* counts, const int8_t
     x.n[0] = s.n_up; x.n[1] = s.n_dn;
     x.nmax = std::max(std::max(s.n_up, s.n_dn), 1);
     x.nd = s.tp != 0.0 ? 8 : 4;
-    x.maxhops = (s.n_up + s.n_dn) * x.nd;
+    x.maxhops = lattice_max_hops(s);
     const int G = 2 * L + 4;
     x.torus_x = (x.pbc_x && s.Lx < G) ? 1 : 0;
     x.torus_y = (x.pbc_y && s.Ly < G) ? 1 : 0;
     x.Gx = x.torus_x ? s.Lx : G;
     x.Gy = x.torus_y ? s.Ly : G;
     x.t = s.t; x.tp = s.tp; x.U = s.U;
+    x.tj = s.tj; x.J = s.J; x.hpin = s.h_pin;
     x.w0 = w0; x.nw = counts[l];
     x.occ_off = o_occ; x.lab_off = o_lab; x.pos_off = o_pos; x.feat_off = o_feat;
     x.inv_off = o_inv; x.m_off = o_m; x.g_off = o_m; x.pt_off = o_pt;
@@ -919,11 +939,12 @@ svmc_status svmc_tune(svmc_ctx* ctx, const char* cache_path, int32_t* slices_out
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
     return ctx->fail(SVMC_ERR_HIP, "device query");
-  key << "dev=" << prop.gcnArchName << " L=" << ctx->L << " C=" << ctx->C << " prec=" << ctx->prec;
+  key << "dev=" << prop.gcnArchName << " L=" << ctx->L << " C=" << ctx->C << " M=" << ctx->nmlp
+      << " prec=" << ctx->prec;
   for (size_t l = 0; l < ctx->lats.size(); ++l) {
     const svmc_lattice& a = ctx->lats[l];
     key << " lat=" << a.Lx << "x" << a.Ly << ":" << a.pbc_x << a.pbc_y << ":" << a.n_up << "+" << a.n_dn
-        << ":" << (a.tp != 0.0 ? 8 : 4) << ":" << ctx->counts[l];
+        << ":" << (a.tp != 0.0 ? 8 : 4) << (a.tj ? ":tJ" : "") << ":" << ctx->counts[l];
   }
   const std::string k = key.str();
   if (cache_path) {

@@ -53,40 +53,24 @@ SVMC_DEV int block_excl_scan(int v, int* tmp, int& total) {
   return off + incl - v;
 }
 
-// Enumerate the walker's hops into `hops` (16-bit code (i << 4) | (spin << 3)
-// | d, N <= 4096); returns the count.  At most `cap` codes are stored (a
-// walker with a wrong electron count may have more).  All threads of the
-// block take part.
+// Enumerate the walker's connected configurations into `hops` (16-bit codes
+// of conn_code, canonical order); returns the count.  At most `cap` codes
+// are stored (a walker with a wrong electron count may have more).  All
+// threads of the block take part.
 SVMC_DEV int enumerate_hops(const LatDev& lt, const int8_t* occ_s, uint16_t* hops, int* tmp, int cap) {
-  const int N = lt.N, nd = lt.nd, tid = threadIdx.x;
-  const int items = 2 * N;
+  const int items = conn_items(lt), tid = threadIdx.x;
   const int per = (items + blockDim.x - 1) / blockDim.x;
   const int e0 = tid * per;
   int cnt = 0;
-  for (int e = e0; e < min(items, e0 + per); ++e) {
-    const int sp = e / N, i = e % N;
-    if (!((occ_s[i] >> sp) & 1)) continue;
-    const int xi = i % lt.Lx, yi = i / lt.Lx;
-    for (int d = 0; d < nd; ++d) {
-      int x = xi + dir_dx(d), y = yi + dir_dy(d);
-      if (lt.pbc_x) x = imod(x, lt.Lx); else if (x < 0 || x >= lt.Lx) continue;
-      if (lt.pbc_y) y = imod(y, lt.Ly); else if (y < 0 || y >= lt.Ly) continue;
-      if ((occ_s[x + lt.Lx * y] >> sp) & 1) continue;
-      ++cnt;
-    }
-  }
+  for (int e = e0; e < min(items, e0 + per); ++e) cnt += __popc(conn_mask(lt, occ_s, e));
   int total;
   int off = block_excl_scan(cnt, tmp, total);
   for (int e = e0; e < min(items, e0 + per); ++e) {
-    const int sp = e / N, i = e % N;
-    if (!((occ_s[i] >> sp) & 1)) continue;
-    const int xi = i % lt.Lx, yi = i / lt.Lx;
-    for (int d = 0; d < nd; ++d) {
-      int x = xi + dir_dx(d), y = yi + dir_dy(d);
-      if (lt.pbc_x) x = imod(x, lt.Lx); else if (x < 0 || x >= lt.Lx) continue;
-      if (lt.pbc_y) y = imod(y, lt.Ly); else if (y < 0 || y >= lt.Ly) continue;
-      if ((occ_s[x + lt.Lx * y] >> sp) & 1) continue;
-      if (off < cap) hops[off] = (uint16_t)((i << 4) | (sp << 3) | d);
+    unsigned m = conn_mask(lt, occ_s, e);
+    while (m) {
+      const int d = __ffs(m) - 1;
+      m &= m - 1;
+      if (off < cap) hops[off] = (uint16_t)conn_code(lt, e, d);
       ++off;
     }
   }
@@ -162,9 +146,11 @@ __global__ __launch_bounds__(64 * ELOC_NW) __attribute__((amdgpu_waves_per_eu(SM
       // lane index through an opaque copy (see hop_features)
       int lane;
       asm volatile("v_mov_b32 %0, %1" : "=v"(lane) : "v"((int)threadIdx.x & 63));
-      const int code = uniform_i(hops[hh]);
-      const int i = code >> 4, sp = (code >> 3) & 1, d = code & 7;
-      const HopGeom g = hop_geom(lt, md.L, sp, i, d);
+      const Conn cn = conn_decode(lt, uniform_i(hops[hh]));
+      const int sp = cn.sp;
+      // the hop's amplitude waits in LDS for the end of the hop
+      if (tid == 0) misc[4] = conn_amp(lt, cn);
+      const HopGeom g = hop_geom(lt, md.L, sp, cn.i, cn.d, cn.ex);
       int olx, owx, oly, owy;
       const AxisTab tab = axis_tab(g, md.L, lane);
       hop_features<P, C, NW, SMALL ? 1 : 7, MLP>(md, lt, g, occ_s, featw, (Tf*)nullptr, scratch, hsc, tab, olx, owx,
@@ -173,7 +159,10 @@ __global__ __launch_bounds__(64 * ELOC_NW) __attribute__((amdgpu_waves_per_eu(SM
       int hpos;
       const int K = hop_klist(lt, g, tab, occ_s, lab_s, wv, olx, owx, oly, owy, kl, hpos, lane);
       const double* PTt = PTw + (long long)wv * nm * C;
-      const double* Gj = Gw + ((long long)wv * N + g.j) * nm;
+      // spin wv's moving electron (a hop: spin sp, i -> j; an exchange: both
+      // spins, the down electron j -> i) and the G row of its new site
+      const bool mv = wv == sp || cn.ex;
+      const double* Gj = Gw + ((long long)wv * N + (wv == sp ? g.j : g.i)) * nm;
       // few changed rows in both spins: the row form (K x K, padded to 8 or
       // 16) instead of the column form of size C + 1
       const int Ko = hop_kcount(lt, g, tab, occ_s, 1 - wv, olx, owx, oly, owy, lane);
@@ -182,8 +171,8 @@ __global__ __launch_bounds__(64 * ELOC_NW) __attribute__((amdgpu_waves_per_eu(SM
         const v4d racc = hop_det_row_build<C>(kl, K, (const typename DType<P>::type*)scratch, PTt, lane);
         __syncthreads();    // both matrices built: their staging may overwrite D
         double* rstage = (double*)scratch + wv * 16 * 17;
-        if (KM <= 8) hop_det_row_stage<8>(racc, kl, K, wv == sp, hpos, Gj, rstage, lane);
-        else hop_det_row_stage<16>(racc, kl, K, wv == sp, hpos, Gj, rstage, lane);
+        if (KM <= 8) hop_det_row_stage<8>(racc, kl, K, mv, hpos, Gj, rstage, lane);
+        else hop_det_row_stage<16>(racc, kl, K, mv, hpos, Gj, rstage, lane);
         __syncthreads();
         if (wv == 0) {
           // both K x K determinants in wavefront 0, one matrix per half
@@ -201,19 +190,24 @@ __global__ __launch_bounds__(64 * ELOC_NW) __attribute__((amdgpu_waves_per_eu(SM
           if ((lane & 31) == 0) misc[lane >> 5] = dt;
           // (the one-layer instance cannot meet more than 16 rows; if a
           // caller broke that, the ratio is flagged rather than wrong)
-          if (lane == 0) misc[2] = (SMALL && KM > 16) ? NAN : 1.0;
+          if (lane == 0) {
+            misc[2] = (SMALL && KM > 16) ? NAN : 1.0;
+            misc[3] = 1.0;
+          }
         }
         __syncthreads();
       } else if constexpr (!SMALL) {
       v4d dacc[DetTiles<C>::I][DetTiles<C>::J];
-      hop_det_build<C>(kl, K, wv == sp, hpos, (const typename DType<P>::type*)scratch, PTt, Gj, lane, dacc);
+      hop_det_build<C>(kl, K, mv, hpos, (const typename DType<P>::type*)scratch, PTt, Gj, lane, dacc);
       __syncthreads();      // both matrices built: their staging may overwrite D
       double* stage = (double*)scratch + wv * (C + 1) * DetTiles<C>::RS;
-      hop_det_stage<C>(dacc, kl, K, wv == sp, hpos, PTt, Gj, stage, lane);
-      // the moving spin's matrix is brought to C x C by one elimination step
-      if (wv == sp) {
+      hop_det_stage<C>(dacc, kl, K, mv, hpos, PTt, Gj, stage, lane);
+      // a moving spin's matrix is brought to C x C by one elimination step
+      if (mv) {
         const double f = hop_det_reduce<C>(stage, lane);
-        if (lane == 0) misc[2] = f;
+        if (lane == 0) misc[wv == sp ? 2 : 3] = f;
+      } else if (lane == 0) {
+        misc[3] = 1.0;
       }
       // each wavefront factors its own spin's C x C matrix (its own staging
       // area: no barrier with the other wavefront), two lanes per row
@@ -231,12 +225,14 @@ __global__ __launch_bounds__(64 * ELOC_NW) __attribute__((amdgpu_waves_per_eu(SM
       __syncthreads();
       }
       if (tid == 0) {
-        const double R = misc[0] * misc[1] * misc[2];
-        *part_s += -(d < 4 ? lt.t : lt.tp) * R;
+        // misc[2], misc[3]: the moving spins' reduction factors (1 where
+        // none was taken)
+        const double R = misc[0] * misc[1] * misc[2] * misc[3];
+        *part_s += -misc[4] * R;
         nonfinite |= !isfinite(R);
         if (out.ratio) {
           out.ratio[w * out.stride + hh] = R;
-          out.code[w * out.stride + hh] = code;
+          out.code[w * out.stride + hh] = hops[hh];
         }
       }
     }
@@ -245,10 +241,8 @@ __global__ __launch_bounds__(64 * ELOC_NW) __attribute__((amdgpu_waves_per_eu(SM
     double part = *part_s;
     if (nonfinite) atomicOr(bf.flags + w, 2);
     if (slice == 0) {
-      // the U term and the per-walker outputs go with slice 0
-      int ndbl = 0;
-      for (int s = 0; s < N; ++s) ndbl += occ_s[s] == 3;
-      part += lt.U * ndbl;
+      // the diagonal term and the per-walker outputs go with slice 0
+      part += diag_energy(lt, occ_s);
       if (out.nhops) out.nhops[w] = H;
     }
     out.part[w * out.slices + slice] = bad ? NAN : part;

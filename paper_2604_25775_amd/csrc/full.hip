@@ -8,7 +8,7 @@
 // configuration and every configuration one hop away, listed walker by
 // walker in canonical hop order and processed in chunks:
 //   1. k_full_configs writes each configuration's occupation bytes (and the
-//      walker, hop index and Jordan-Wigner sign of its hop);
+//      walker, hop index and Jordan-Wigner sign of its hop or spin exchange);
 //   2. the forward of the cold setup (embedding, every conv layer over all
 //      sites) runs on the chunk as if it were a batch of walkers;
 //   3. k_full_det builds both Slater blocks of each configuration (rows of
@@ -28,28 +28,15 @@
 
 namespace svmc {
 
-// Finds hop number h of the walker (canonical order); wave 0 only.
-SVMC_DEV bool find_hop(const LatDev& lt, const int8_t* occ_s, int h, int& sp_o, int& i_o, int& d_o, int lane) {
-  const int N = lt.N, nd = lt.nd;
+// Finds connection number h of the walker (canonical order, conn_mask
+// items); one wavefront.  Returns its item e and direction d.
+SVMC_DEV bool find_conn(const LatDev& lt, const int8_t* occ_s, int h, int& e_o, int& d_o, int lane) {
+  const int items = conn_items(lt);
   int seen = 0;
-  for (int base = 0; base < 2 * N; base += 64) {
+  for (int base = 0; base < items; base += 64) {
     const int e = base + lane;
-    int cnt = 0;
-    unsigned valid = 0;
-    if (e < 2 * N) {
-      const int sp = e / N, i = e % N;
-      if ((occ_s[i] >> sp) & 1) {
-        const int xi = i % lt.Lx, yi = i / lt.Lx;
-        for (int d = 0; d < nd; ++d) {
-          int x = xi + dir_dx(d), y = yi + dir_dy(d);
-          if (lt.pbc_x) x = imod(x, lt.Lx); else if (x < 0 || x >= lt.Lx) continue;
-          if (lt.pbc_y) y = imod(y, lt.Ly); else if (y < 0 || y >= lt.Ly) continue;
-          if ((occ_s[x + lt.Lx * y] >> sp) & 1) continue;
-          valid |= 1u << d;
-          ++cnt;
-        }
-      }
-    }
+    const unsigned valid = e < items ? conn_mask(lt, occ_s, e) : 0u;
+    const int cnt = __popc(valid);
     const int incl = wave_incl_scan(cnt, lane);
     const int tot = __shfl(incl, 63, 64);
     if (h < seen + tot) {
@@ -59,17 +46,12 @@ SVMC_DEV bool find_hop(const LatDev& lt, const int8_t* occ_s, int h, int& sp_o, 
       const int src = __ffsll((long long)b) - 1;
       int dsel = -1;
       if (mine) {
-        int r = h - excl;
-        for (int d = 0; d < 8; ++d)
-          if ((valid >> d) & 1) {
-            if (r == 0) { dsel = d; break; }
-            --r;
-          }
+        unsigned m = valid;
+        for (int r = h - excl; r > 0; --r) m &= m - 1;
+        dsel = __ffs(m) - 1;
       }
-      const int e_src = __shfl(e, src, 64);
+      e_o = __shfl(e, src, 64);
       d_o = __shfl(dsel, src, 64);
-      sp_o = e_src / N;
-      i_o = e_src % N;
       return true;
     }
     seen += tot;
@@ -77,11 +59,11 @@ SVMC_DEV bool find_hop(const LatDev& lt, const int8_t* occ_s, int h, int& sp_o, 
   return false;
 }
 
-// E_loc = U * doubles - sum_h t_h ratio_h, hops in canonical order.
+// E_loc = diagonal term - sum_h amp_h ratio_h, connections in canonical order.
 static __global__ void k_full_reduce(LatDev lt, Bufs bf, const double* ratio_tmp, int stride, ElocOut out) {
   const long long wl = blockIdx.x;
   const long long w = lt.w0 + wl;
-  const int N = lt.N, nd = lt.nd;
+  const int N = lt.N;
   __shared__ int8_t occ_s[4096];
   const int8_t* occ_g = bf.occ + lt.occ_off + wl * N;
   for (int s = threadIdx.x; s < N; s += blockDim.x) occ_s[s] = occ_g[s];
@@ -89,56 +71,42 @@ static __global__ void k_full_reduce(LatDev lt, Bufs bf, const double* ratio_tmp
   if (threadIdx.x != 0) return;
   const bool bad = (bf.flags[w] & (1 | 8)) != 0;
   double e = 0.0;
-  int ndbl = 0;
-  for (int s = 0; s < N; ++s) ndbl += occ_s[s] == 3;
   int hh = 0;
-  for (int sp = 0; sp < 2; ++sp)
-    for (int i = 0; i < N; ++i) {
-      if (!((occ_s[i] >> sp) & 1)) continue;
-      const int xi = i % lt.Lx, yi = i / lt.Lx;
-      for (int d = 0; d < nd; ++d) {
-        int x = xi + dir_dx(d), y = yi + dir_dy(d);
-        if (lt.pbc_x) x = imod(x, lt.Lx); else if (x < 0 || x >= lt.Lx) continue;
-        if (lt.pbc_y) y = imod(y, lt.Ly); else if (y < 0 || y >= lt.Ly) continue;
-        if ((occ_s[x + lt.Lx * y] >> sp) & 1) continue;
-        const double r = (bad || hh >= stride) ? NAN : ratio_tmp[wl * stride + hh];
-        e += -(d < 4 ? lt.t : lt.tp) * r;
-        if (out.ratio && hh < out.stride) {
-          out.ratio[w * out.stride + hh] = r;
-          out.code[w * out.stride + hh] = (i << 4) | (sp << 3) | d;
-        }
-        ++hh;
+  const int items = conn_items(lt);
+  for (int it = 0; it < items; ++it) {
+    unsigned m = conn_mask(lt, occ_s, it);
+    while (m) {
+      const int d = __ffs(m) - 1;
+      m &= m - 1;
+      const int code = conn_code(lt, it, d);
+      const double r = (bad || hh >= stride) ? NAN : ratio_tmp[wl * stride + hh];
+      e += -conn_amp(lt, conn_decode(lt, code)) * r;
+      if (out.ratio && hh < out.stride) {
+        out.ratio[w * out.stride + hh] = r;
+        out.code[w * out.stride + hh] = code;
       }
+      ++hh;
     }
-  out.eloc[w] = bad ? NAN : lt.U * ndbl + e;
+  }
+  out.eloc[w] = bad ? NAN : diag_energy(lt, occ_s) + e;
   if (out.nhops) out.nhops[w] = min(hh, out.stride);
 }
 
-// Hops per walker (lattice-local), one wavefront per walker.
+// Connections per walker (lattice-local), one wavefront per walker.
 static __global__ __launch_bounds__(64) void k_full_count(LatDev lt, Bufs bf, int32_t* cnt) {
   const long long wl = blockIdx.x;
-  const int N = lt.N, nd = lt.nd, lane = threadIdx.x;
+  const int N = lt.N, lane = threadIdx.x;
   const int8_t* occ = bf.occ + lt.occ_off + wl * N;
   int c = 0;
-  for (int e = lane; e < 2 * N; e += 64) {
-    const int sp = e / N, i = e - sp * N;
-    if (!((occ[i] >> sp) & 1)) continue;
-    const int xi = i % lt.Lx, yi = i / lt.Lx;
-    for (int d = 0; d < nd; ++d) {
-      int x = xi + dir_dx(d), y = yi + dir_dy(d);
-      if (lt.pbc_x) x = imod(x, lt.Lx); else if (x < 0 || x >= lt.Lx) continue;
-      if (lt.pbc_y) y = imod(y, lt.Ly); else if (y < 0 || y >= lt.Ly) continue;
-      if ((occ[x + lt.Lx * y] >> sp) & 1) continue;
-      ++c;
-    }
-  }
+  for (int e = lane; e < conn_items(lt); e += 64) c += __popc(conn_mask(lt, occ, e));
   c = wave_sum_i(c);
   if (lane == 0) cnt[wl] = c;
 }
 
 // Configuration g = c0 + blockIdx.x of the listing: walker wl with
 // off[wl] <= g < off[wl + 1]; slot g - off[wl] = 0 is the walker's own
-// configuration, slot 1 + h its hop h (canonical order).  One wavefront.
+// configuration, slot 1 + h its connection h (canonical order).  One
+// wavefront.
 static __global__ __launch_bounds__(64) void k_full_configs(LatDev lt, Bufs bf, const long long* __restrict__ off,
                                                             long long c0, int8_t* __restrict__ occ_h,
                                                             int32_t* __restrict__ cfg_w, int32_t* __restrict__ cfg_h,
@@ -158,22 +126,27 @@ static __global__ __launch_bounds__(64) void k_full_configs(LatDev lt, Bufs bf, 
   __syncthreads();
   double jw = 1.0;
   if (h >= 0) {
-    int sp = 0, i = 0, d = 0;
-    find_hop(lt, occ_s, h, sp, i, d, lane);
-    int xj = i % lt.Lx + dir_dx(d), yj = i / lt.Lx + dir_dy(d);
-    if (lt.pbc_x) xj = imod(xj, lt.Lx);
-    if (lt.pbc_y) yj = imod(yj, lt.Ly);
-    const int j = xj + lt.Lx * yj;
-    // same-spin electrons strictly between i and j in site order
-    const int a = min(i, j), b = max(i, j);
+    int e = 0, d = 0;
+    find_conn(lt, occ_s, h, e, d, lane);
+    const Conn cn = conn_decode(lt, conn_code(lt, e, d));
+    const int i = cn.i, j = conn_target(lt, i, d);
+    // electrons strictly between i and j in site order, of the moving spin
+    // (a hop) or of both spins (an exchange: the product of both signs)
+    const int a = min(i, j), b = max(i, j), mask = cn.ex ? 3 : 1 << cn.sp;
     int between = 0;
-    for (int s = a + 1 + lane; s < b; s += 64) between += (occ_s[s] >> sp) & 1;
+    for (int s = a + 1 + lane; s < b; s += 64) between += __popc(occ_s[s] & mask);
     between = wave_sum_i(between);
     jw = (between & 1) ? -1.0 : 1.0;
     __syncthreads();
     if (lane == 0) {
-      occ_s[i] -= (int8_t)(1 << sp);
-      occ_s[j] += (int8_t)(1 << sp);
+      if (cn.ex) {
+        const int8_t oi = occ_s[i];
+        occ_s[i] = occ_s[j];
+        occ_s[j] = oi;
+      } else {
+        occ_s[i] -= (int8_t)(1 << cn.sp);
+        occ_s[j] += (int8_t)(1 << cn.sp);
+      }
     }
     __syncthreads();
   }

@@ -19,6 +19,102 @@ namespace svmc {
 SVMC_DEV int dir_dx(int d) { return (d == 0 || d == 4 || d == 5) ? 1 : ((d == 1 || d == 6 || d == 7) ? -1 : 0); }
 SVMC_DEV int dir_dy(int d) { return (d == 2 || d == 4 || d == 6) ? 1 : ((d == 3 || d == 5 || d == 7) ? -1 : 0); }
 
+// ---------------------------------------------------------------------------
+// Connected configurations of the Hamiltonians of Sec. III, in canonical
+// order.  Items e in [0, 2N): the electron of spin e / N on site e % N,
+// hopping in directions 0 .. nd-1 (+x, -x, +y, -y, then the diagonals when
+// t' != 0) to a site without an electron of that spin (t-J: to an empty
+// site, the Gutzwiller projection); items e in [2N, 3N), t-J only: the spin
+// exchange of the lone up electron on site e - 2N with a lone down electron
+// on a nearest-neighbour site (directions 0..3).  Codes: (i << 4) | (spin
+// << 3) | d for a hop, ((N + i) << 4) | d for an exchange (N <= 2048 then).
+// ---------------------------------------------------------------------------
+SVMC_DEV int conn_items(const LatDev& lt) { return lt.tj ? 3 * lt.N : 2 * lt.N; }
+
+// site at direction d from i, or -1 off an open edge
+SVMC_DEV int conn_target(const LatDev& lt, int i, int d) {
+  int x = i % lt.Lx + dir_dx(d), y = i / lt.Lx + dir_dy(d);
+  if (lt.pbc_x) x = imod(x, lt.Lx); else if (x < 0 || x >= lt.Lx) return -1;
+  if (lt.pbc_y) y = imod(y, lt.Ly); else if (y < 0 || y >= lt.Ly) return -1;
+  return x + lt.Lx * y;
+}
+
+// valid directions of item e as a bit mask
+SVMC_DEV unsigned conn_mask(const LatDev& lt, const int8_t* occ, int e) {
+  const int N = lt.N;
+  unsigned m = 0;
+  if (e < 2 * N) {
+    const int sp = e >= N ? 1 : 0, i = e - sp * N;
+    if (!((occ[i] >> sp) & 1)) return 0;
+    for (int d = 0; d < lt.nd; ++d) {
+      const int j = conn_target(lt, i, d);
+      if (j < 0) continue;
+      const int o = occ[j];
+      if (lt.tj ? o != 0 : ((o >> sp) & 1)) continue;
+      m |= 1u << d;
+    }
+  } else {
+    const int i = e - 2 * N;
+    if (occ[i] != 1) return 0;
+    for (int d = 0; d < 4; ++d) {
+      const int j = conn_target(lt, i, d);
+      if (j >= 0 && occ[j] == 2) m |= 1u << d;
+    }
+  }
+  return m;
+}
+
+SVMC_DEV int conn_code(const LatDev& lt, int e, int d) {
+  const int N = lt.N;
+  if (e >= 2 * N) return ((e - N) << 4) | d;
+  const int sp = e >= N ? 1 : 0;
+  return ((e - sp * N) << 4) | (sp << 3) | d;
+}
+
+// Decoded code: ex = spin exchange (sp = 0: the up electron leaves i).
+struct Conn {
+  int i, sp, d, ex;
+};
+SVMC_DEV Conn conn_decode(const LatDev& lt, int code) {
+  Conn c;
+  const int a = code >> 4;
+  c.ex = a >= lt.N ? 1 : 0;
+  c.i = c.ex ? a - lt.N : a;
+  c.sp = c.ex ? 0 : (code >> 3) & 1;
+  c.d = code & 7;
+  return c;
+}
+
+// Hopping amplitude of a connection: the local-energy term is -amp * R with
+// R the in-place ratio (for a spin exchange both spins move in place and
+// the matrix element of (J/2)(S+S- + S-S+) is -(J/2) times the product of
+// the two spins' signs, so amp = J/2).
+SVMC_DEV double conn_amp(const LatDev& lt, const Conn& c) { return c.ex ? 0.5 * lt.J : (c.d < 4 ? lt.t : lt.tp); }
+
+// Diagonal part of the local energy: U per doubly occupied site (Hubbard);
+// t-J: J S^z_i S^z_j over nearest-neighbour bonds (each once, via the +x and
+// +y neighbours) plus the staggered pinning field hpin (-1)^y S^z on the
+// column x = 0.  One thread.
+SVMC_DEV double diag_energy(const LatDev& lt, const int8_t* occ) {
+  const int N = lt.N;
+  if (!lt.tj) {
+    int ndbl = 0;
+    for (int s = 0; s < N; ++s) ndbl += occ[s] == 3;
+    return lt.U * ndbl;
+  }
+  auto sz = [&](int s) { return 0.5 * (double)((occ[s] & 1) - ((occ[s] >> 1) & 1)); };
+  double zz = 0.0, pin = 0.0;
+  for (int s = 0; s < N; ++s) {
+    const double z = sz(s);
+    if (z == 0.0) continue;
+    const int a = conn_target(lt, s, 0), b = conn_target(lt, s, 2);
+    if (a >= 0) zz += z * sz(a);
+    if (b >= 0) zz += z * sz(b);
+  }
+  for (int y = 0; y < lt.Ly; ++y) pin += (y & 1 ? -1.0 : 1.0) * sz(lt.Lx * y);
+  return lt.J * zz + lt.hpin * pin;
+}
+
 // q / w for 0 <= q < 1087 and 1 <= w <= 64 as (q * m) >> 16 with
 // m = 65536 / w + 1 (checked exhaustively over that range).  Box widths are
 // at most 2L + 4 and box sizes at most (2L + 4)^2 sites.
@@ -66,15 +162,20 @@ SVMC_DEV void box_site(int q, int lx, int w, int m, int ly, int& ux, int& uy) {
 }
 
 
+// One connected configuration seen as a local move: sites i and j change.
+// A hop of spin sigma: occupation codes change by di = -(1 << sigma) at i
+// and -di at j.  A spin exchange (sigma = 0): the up electron goes i -> j
+// and the down electron j -> i, di = +1 at i and -1 at j; di > 0 marks it.
 struct HopGeom {
-  int i, j, sigma, d;
+  int i, j, sigma, d, di;
   Axis ax, ay;
   int xi, yi, dx, dy;
 };
 
-SVMC_DEV HopGeom hop_geom(const LatDev& lt, int L, int sigma, int i, int d) {
+SVMC_DEV HopGeom hop_geom(const LatDev& lt, int L, int sigma, int i, int d, int ex = 0) {
   HopGeom h;
   h.i = i; h.sigma = sigma; h.d = d;
+  h.di = ex ? 1 : -(1 << sigma);
   h.dx = dir_dx(d); h.dy = dir_dy(d);
   h.xi = i % lt.Lx; h.yi = i / lt.Lx;
   const int xj = lt.pbc_x ? imod(h.xi + h.dx, lt.Lx) : h.xi + h.dx;
@@ -460,7 +561,6 @@ SVMC_DEV void hop_features(const ModelDev& md, const LatDev& lt, const HopGeom& 
   // the window hold zeros); otherwise taps go through the coordinate table
   const bool win = !(lt.torus_x | lt.torus_y);
   Tf* grid = (Tf*)scratch;
-  const int bit = 1 << h.sigma;
   constexpr int V = 16 / sizeof(Tf);          // elements per 16-byte vector
   constexpr int CV = C / V;
   constexpr int QB = RegB<P, C>::value ? CC::Q : 1;
@@ -512,8 +612,8 @@ SVMC_DEV void hop_features(const ModelDev& md, const LatDev& lt, const HopGeom& 
       const int site = (int)((tab_gy(tab, uy) >> 8) & 0xFFu) * Gx + (int)((tab_gx(tab, ux) >> 8) & 0xFFu);
       if (e >= tot) continue;
       int o = occ_s[s];
-      if (s == h.i) o -= bit;
-      if (s == h.j) o += bit;
+      if (s == h.i) o += h.di;
+      if (s == h.j) o -= h.di;
       // one shared table: its LDS copy; per-site tables from memory
       const float4 ev = lt.emb_ss == 0
                             ? *reinterpret_cast<const float4*>((const Tf*)(scratch + hs.emb) + o * C + cv * V)
@@ -787,15 +887,18 @@ SVMC_DEV void hop_features(const ModelDev& md, const LatDev& lt, const HopGeom& 
 
 // Changed-row list of spin tau (one wavefront): every electron of spin tau
 // in the new configuration on the layer-L box, entry (m << 16) | label, m
-// indexing the box.  The moving electron keeps its label at its new site.
-// Returns the list length; *hpos gets the mover's position (tau = sigma).
+// indexing the box.  A moving electron keeps its label at its new site.
+// Returns the list length; *hpos gets the mover's position (-1 if spin tau
+// does not move: tau != sigma of a hop).
 SVMC_DEV int hop_klist(const LatDev& lt, const HopGeom& h, const AxisTab& tab, const int8_t* occ_s,
                        const int16_t* lab_s, int tau, int olx, int owx, int oly, int owy, int* kl, int& hpos,
                        int lane) {
   const int N = lt.N, Lx = lt.Lx;
   const int cnt = owx * owy;
   const int mow = kMagic16[owx];
-  const int bit = 1 << h.sigma;
+  // the moving electron of spin tau: from msrc to mdst (mdst = -1: none)
+  const int mdst = tau == h.sigma ? h.j : (h.di > 0 ? h.i : -1);
+  const int msrc = tau == h.sigma ? h.i : h.j;
   int nk = 0;
   hpos = -1;
   for (int base = 0; base < cnt; base += 64) {
@@ -807,15 +910,15 @@ SVMC_DEV int hop_klist(const LatDev& lt, const HopGeom& h, const AxisTab& tab, c
     if (m < cnt) {
       s = sl;
       o = occ_s[s];
-      if (s == h.i) o -= bit;
-      if (s == h.j) o += bit;
+      if (s == h.i) o += h.di;
+      if (s == h.j) o -= h.di;
     }
     const bool pred = m < cnt && ((o >> tau) & 1);
     const unsigned long long mask = __ballot(pred);
     const int idx = nk + __popcll(mask & ((1ULL << lane) - 1ULL));
-    const bool mover = pred && tau == h.sigma && s == h.j;
+    const bool mover = pred && s == mdst;
     if (pred) {
-      const int k = mover ? lab_s[h.sigma * N + h.i] : lab_s[tau * N + s];
+      const int k = mover ? lab_s[tau * N + msrc] : lab_s[tau * N + s];
       kl[idx] = (m << 16) | k;
     }
     const unsigned long long mm = __ballot(mover);
@@ -829,7 +932,7 @@ SVMC_DEV int hop_klist(const LatDev& lt, const HopGeom& h, const AxisTab& tab, c
 // box (the length hop_klist would return), one wavefront, every lane active.
 SVMC_DEV int hop_kcount(const LatDev& lt, const HopGeom& h, const AxisTab& tab, const int8_t* occ_s, int tau,
                         int olx, int owx, int oly, int owy, int lane) {
-  const int Lx = lt.Lx, cnt = owx * owy, mow = kMagic16[owx], bit = 1 << h.sigma;
+  const int Lx = lt.Lx, cnt = owx * owy, mow = kMagic16[owx];
   int nk = 0;
   for (int base = 0; base < cnt; base += 64) {
     const int m = base + lane;
@@ -839,8 +942,8 @@ SVMC_DEV int hop_kcount(const LatDev& lt, const HopGeom& h, const AxisTab& tab, 
     int o = 0;
     if (m < cnt) {
       o = occ_s[s];
-      if (s == h.i) o -= bit;
-      if (s == h.j) o += bit;
+      if (s == h.i) o += h.di;
+      if (s == h.j) o -= h.di;
     }
     nk += __popcll(__ballot(m < cnt && ((o >> tau) & 1)));
   }

@@ -349,7 +349,7 @@ __global__ void k_labels(LatDev lt, Bufs bf) {
   for (int sp = 0; sp < 2; ++sp)
     for (int k = cnt[sp]; k < nm; ++k) pos[sp * nm + k] = -1;
   bool bad = cnt[0] != lt.n[0] || cnt[1] != lt.n[1];
-  for (int s = 0; s < N; ++s) bad |= (occ[s] < 0 || occ[s] > 3);
+  for (int s = 0; s < N; ++s) bad |= (occ[s] < 0 || occ[s] > 3 || (lt.tj && occ[s] == 3));
   const long long w = lt.w0 + wl;
   bf.flags[w] = bad ? 8 : 0;
   bf.nacc[w] = 0;

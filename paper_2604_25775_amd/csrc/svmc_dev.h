@@ -41,10 +41,12 @@ struct LatDev {
   int n[2];       // electrons per spin
   int nmax;       // max(n[0], n[1]), leading dimension of per-spin matrices
   int nd;         // hop directions: 4 (t' = 0) or 8
-  int maxhops;    // (n0 + n1) * nd
+  int maxhops;    // (n0 + n1) * nd, plus 4 min(n0, n1) spin exchanges (t-J)
   int torus_x, torus_y;   // incremental boxes wrap (axis shorter than 2L+4)
   int Gx, Gy;             // incremental grid extent per axis
   double t, tp, U;
+  int tj;              // 1: t-J model (Gutzwiller projection, exchange J, pinning field hpin)
+  double J, hpin;
   long long w0, nw;
   long long occ_off;   // int8  [N]
   long long lab_off;   // int16 [2][N]     label of the electron at a site, -1

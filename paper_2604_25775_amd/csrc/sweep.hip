@@ -1,6 +1,8 @@
 // Metropolis sampling of |psi|^2 with single-electron nearest-neighbour moves
 // (Sec. II.A: configurations drawn by Markov chain Monte Carlo), with the
-// local update of Sec. II.C for both the ratio and the accepted move.
+// local update of Sec. II.C for both the ratio and the accepted move.  In
+// the t-J model (Sec. III) a move onto an occupied site is rejected without
+// evaluation: the Gutzwiller projection gives it amplitude zero.
 //
 // The sweep is step-synchronous across walkers: proposal q of every walker
 // is one launch of k_step_propose (one workgroup per walker), followed by
@@ -200,7 +202,8 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(3))) void k
     if (lt.pbc_x) x = imod(x, lt.Lx); else ok = ok && x >= 0 && x < lt.Lx;
     if (lt.pbc_y) y = imod(y, lt.Ly); else ok = ok && y >= 0 && y < lt.Ly;
     const int tgt = ok ? uniform_i(occ_g[x + lt.Lx * y]) : 0;
-    if (!ok || ((tgt >> sp) & 1)) {                                   // uniform
+    // (t-J: the Gutzwiller projection also rejects a site of the other spin)
+    if (!ok || (lt.tj ? tgt != 0 : ((tgt >> sp) & 1))) {              // uniform
       if (tid == 0) hdr[HD_ACC] = 0;
       return;
     }

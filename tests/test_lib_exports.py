@@ -65,3 +65,33 @@ def test_model_descriptor_checks_without_device():
     assert create(channels=12) == 5
     assert create(refresh_every=0) == 1
     assert not h.value
+
+
+def test_tj_lattice_descriptor_checks_without_device():
+    """svmc_create rejects t-J descriptor errors before it touches a device:
+    J or h_pin on a Hubbard lattice, a model flag outside {0, 1}, a nonzero
+    reserved field, more electrons than sites and a non-finite J are invalid;
+    a t-J lattice above 2048 sites (the exchange codes' range) is not
+    supported."""
+    from paper_2604_25775_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.skip("library not built")
+    lib = _lib.load()
+    h = ctypes.c_void_p()
+    m = _lib.Model(2, 8, 0, 0, 32, 3, 0, 0)
+
+    def create(**kw):
+        f = dict(Lx=8, Ly=4, pbc_x=0, pbc_y=1, t=1.0, tp=0.2, U=0.0, n_up=14, n_dn=14, J=1.0 / 3.0, h_pin=0.5,
+                 tj=1, reserved=0)
+        f.update(kw)
+        lat = (_lib.Lattice * 1)(_lib.Lattice(*[f[k] for k, _ in _lib.Lattice._fields_]))
+        return lib.svmc_create(lat, 1, ctypes.byref(m), ctypes.byref(h))
+
+    assert create(tj=0) == 1
+    assert create(tj=0, J=0.0) == 1                  # h_pin without the t-J model
+    assert create(tj=2) == 1
+    assert create(reserved=1) == 1
+    assert create(n_up=17, n_dn=16) == 1
+    assert create(J=float("inf")) == 1
+    assert create(Lx=64, Ly=40, n_up=100, n_dn=100) == 5
+    assert not h.value

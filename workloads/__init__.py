@@ -105,6 +105,12 @@ CONFIGS = {
         Model(4, 32, "tanh", "bf16"), sweeps=0, stripe=True,
         description="Hubbard 32x32 periodic-x/open-y, U=8, 448+448, "
                     "stripe-seeded, 4 conv layers x 32 channels, BF16 conv"),
+    "tj": Workload(
+        "tj", [Lattice(16, 8, 0, 1, 1.0, 0.2, 0.0, 56, 56, tj=1, J=1.0 / 3.0, h_pin=0.5)], [8192],
+        Model(1, 32, "silu", "f16x2", n_mlp=4), sweeps=8,
+        description="t-J 16x8 cylinder (open x, periodic y), J=1/3, t'=0.2, staggered pinning "
+                    "field 0.5 on the x=0 column, 56+56 (1/8 doping); one conv layer + four "
+                    "site-wise layers x 32 channels, SiLU, f16x2 conv"),
 }
 
 
