@@ -368,6 +368,62 @@ def stripe_occupations(lat: Lattice, n_walkers: int, seed: int = 1,
     return occ
 
 
+def symmetry_group(lat: Lattice, gens) -> tuple:
+    """A lattice symmetry group and a one-dimensional representation of it,
+    generated by ``gens``: a list of (kind, chi) with kind "tx" / "ty"
+    (translation by one site along a periodic axis; ("tx", k) form: a tuple
+    ("tx", step)), "mx" / "my" (mirror x -> Lx-1-x, y -> Ly-1-y) or "flip"
+    (exchange of the two spins), chi its character (+1 or -1).  Returns
+    (elements, chis): elements [(perm, flip)] with the identity first, perm
+    a tuple mapping site s to perm[s]; chis the characters (products along
+    the generating words).  Input preparation only: the group and its
+    characters are data for the symmetric amplitude, nothing of the method."""
+    N, Lx, Ly = lat.N, lat.Lx, lat.Ly
+
+    def site(x, y):
+        return (x % Lx) + Lx * (y % Ly)
+
+    def gen_perm(kind):
+        name, step = (kind if isinstance(kind, tuple) else (kind, 1))
+        out = []
+        for s in range(N):
+            x, y = s % Lx, s // Lx
+            if name == "tx":
+                out.append(site(x + step, y))
+            elif name == "ty":
+                out.append(site(x, y + step))
+            elif name == "mx":
+                out.append(site(Lx - 1 - x, y))
+            elif name == "my":
+                out.append(site(x, Ly - 1 - y))
+            elif name == "flip":
+                out.append(s)
+            else:
+                raise ValueError(kind)
+        return tuple(out), name == "flip"
+
+    gl = [(gen_perm(k), float(c)) for k, c in gens]
+    ident = (tuple(range(N)), False)
+    elems = {ident: 1.0}
+    order = [ident]
+    frontier = [ident]
+    while frontier:
+        nxt = []
+        for (perm, flip) in frontier:
+            for (gp, gf), c in gl:
+                q = (tuple(gp[perm[s]] for s in range(N)), flip != gf)
+                chi = elems[(perm, flip)] * c
+                if q in elems:
+                    if elems[q] != chi:
+                        raise ValueError("characters are not a representation of the group")
+                    continue
+                elems[q] = chi
+                order.append(q)
+                nxt.append(q)
+        frontier = nxt
+    return order, [elems[g] for g in order]
+
+
 def occupations(wl: Workload, lat_index: int = 0, n_walkers: int | None = None,
                 seed: int | None = None) -> np.ndarray:
     lat = wl.lattices[lat_index]
