@@ -375,6 +375,46 @@ def speedup_table(prec, log):
 # ---------------------------------------------------------------------------
 # one launch over a mixed batch of lattices (ragged hop counts)
 # ---------------------------------------------------------------------------
+def symmetric_eloc(prec, log, wname="c3", W=1024):
+    """Local energy of the symmetry-projected amplitude at the bench lattice:
+    D2 (both mirrors) x spin inversion, 8 elements, on W base walkers (the
+    seeded occupations), i.e. 8 W copies through the low-rank kernels plus
+    the combination; base walkers per second."""
+    import torch
+    import workloads as wls
+    from paper_2604_25775_amd.api import ScaleVMC
+    wl = wls.get(wname)
+    lat = wl.lattices[0]
+    model = replace(wl.model, conv_prec=prec)
+    params = wls.quantise_params(wls.random_params([lat], model, seed=wl.seed_params), prec)
+    G, chi = wls.symmetry_group(lat, [("mx", 1.0), ("my", 1.0), ("flip", 1.0)])
+    occ = wls.occupations(wl, 0, n_walkers=W)
+    ctx = ScaleVMC([lat], model.n_conv, model.channels, model.act, prec, model.refresh_every, n_mlp=model.n_mlp)
+    ctx.set_params_from(params)
+    ctx.set_symmetry(G, chi)
+    cp = ctx.sym_expand(torch.from_numpy(occ).cuda())
+    ctx.load([W * len(G)], cp)
+    ctx.tune()
+    ctx.local_energy_sym()
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for _ in range(3):
+        ctx.prepare()
+        e, _, _ = ctx.local_energy_sym()
+    t1.record()
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / 3
+    ok = bool(torch.isfinite(e).all().item())
+    del ctx
+    row = {"workload": f"{wname} lattice, {W} walkers x |G| = {len(G)} (mirrors x, y; spin inversion)",
+           "group_order": len(G), "walkers": W, "ms": round(ms, 3),
+           "eloc_sym_per_s": round(W / (ms / 1e3), 1), "copies_eloc_per_s": round(W * len(G) / (ms / 1e3), 1),
+           "all_finite": ok}
+    log(f"[bench] symmetric E_loc (|G| = {len(G)}): {ms:.2f} ms for {W} walkers -> "
+        f"{row['eloc_sym_per_s']:.1f} E_sym/s ({row['copies_eloc_per_s']:.1f} copies/s)")
+    return row
+
+
 def mixed_launch(log, wname="c4"):
     """E_loc/s of the mixed-lattice workload in one launch (after the
     workload's thermalising sweeps), against the same walkers evaluated one
@@ -664,6 +704,7 @@ def main():
     if not a.no_speedup_table:
         extra["speedup_table"] = speedup_table(a.prec, log)
         extra["mixed_lattice_launch"] = mixed_launch(log)
+        extra["symmetric_eloc"] = symmetric_eloc(a.prec, log)
 
     cpu = None
     if not a.no_cpu and a.cpu_sample > 0:

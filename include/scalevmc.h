@@ -63,7 +63,9 @@ typedef enum {
   SVMC_W_SINGULAR = 1,   /* a Slater block has a zero pivot: psi = 0 */
   SVMC_W_NONFINITE = 2,  /* a NaN/Inf appeared in log|psi| or a ratio */
   SVMC_W_DRIFT = 4,      /* Woodbury-updated inverse drifted beyond 1e-8 */
-  SVMC_W_BADCOUNT = 8    /* occupation does not hold n_up/n_dn electrons */
+  SVMC_W_BADCOUNT = 8,   /* occupation does not hold n_up/n_dn electrons */
+  SVMC_W_SYMMETRY = 16   /* symmetric batch: the copies are not the images of
+                            copy 0 under the group (svmc_local_energy_sym) */
 } svmc_walker_flag;
 
 typedef enum { SVMC_ACT_TANH = 0, SVMC_ACT_SILU = 1 } svmc_act;
@@ -292,6 +294,41 @@ svmc_status svmc_grad_logpsi(svmc_ctx* ctx, const double* vjp_w, void* out,
 
 /* Per-walker flag bits (svmc_walker_flag), device [W] int32. */
 svmc_status svmc_walker_flags(svmc_ctx* ctx, int32_t* flags, hipStream_t stream);
+
+/* Symmetry projection (App. B, symmetrized wavefunction):
+ *   psi_sym(n) = sum over g of Pi(n, g) chi_g psi(g n).
+ * A group element g maps site s to perm[g][s] and, if flip[g], exchanges the
+ * two spins; U_g |n> = Pi(n, g) |g n> on Fock states (mapped creation
+ * operators put back into the canonical order: spin-up block first,
+ * ascending site).  chi: the characters (any finite reals; +-1 for a
+ * one-dimensional representation).
+ *
+ * svmc_set_symmetry: host arrays perm [n_g][N] int32, flip [n_g] int32 (0/1),
+ * chi [n_g] FP64, copied.  One-lattice contexts only (UNSUPPORTED
+ * otherwise).  INVALID_ARG unless element 0 is the identity, every perm is a
+ * permutation, flips have n_up == n_dn, and every element is a symmetry of
+ * the Hamiltonian: nearest and next-nearest bonds map to bonds of the same
+ * kind and the t-J pinning field is kept.  n_g = 0 removes the group.
+ *
+ * svmc_sym_expand: device occ [W][N] int8 -> device out [W n_g][N], walker
+ * k n_g + g = g n_k.  Load the result with svmc_load_walkers.
+ *
+ * svmc_local_energy_sym: for a loaded batch of W n_g walkers laid out as
+ * svmc_sym_expand writes them, device eloc / sign / logabs [W] (sign,
+ * logabs may be NULL): the local energy of psi_sym,
+ *   E_sym(n) = sum_g w_g E_loc(g n),  w_g = Pi(n, g) chi_g psi(g n) / psi_sym(n)
+ * (the copies' low-rank local energies; exact because every U_g commutes
+ * with H), and sign and log|psi_sym(n)|.  A walker whose copies are not
+ * the images of copy 0 (e.g. after svmc_sweep moved them independently), or
+ * with a BADCOUNT copy, gets NaN and SVMC_W_SYMMETRY on copy 0.  psi_sym = 0
+ * gives E NaN, sign 0, logabs -inf.  Sampling |psi_sym|^2 is not provided:
+ * walkers from svmc_sweep (|psi|^2) serve by reweighting with
+ * |psi_sym / psi|^2.  INVALID_ARG if the walker count is not a multiple of
+ * n_g; STATE without a group or walkers. */
+svmc_status svmc_set_symmetry(svmc_ctx* ctx, int32_t n_g, const int32_t* perm, const int32_t* flip,
+                              const double* chi);
+svmc_status svmc_sym_expand(svmc_ctx* ctx, int64_t W, const int8_t* occ, int8_t* out, hipStream_t stream);
+svmc_status svmc_local_energy_sym(svmc_ctx* ctx, double* eloc, double* sign, double* logabs, hipStream_t stream);
 
 /* Launch shape of the low-rank local-energy kernel (not a step of the
  * method; results agree to rounding across shapes):

@@ -224,6 +224,37 @@ class ScaleVMC:
         self._check(self.lib.svmc_get_launch(self.h, ct.byref(ln)), "get_launch")
         return {"slices": int(ln.slices), "row_form_max": int(ln.row_form_max)}
 
+    def set_symmetry(self, group, chi):
+        """Symmetry group for the projected amplitude (svmc_set_symmetry):
+        group = [(perm, flip)] with the identity first, chi the characters."""
+        N = self.lattices[0].N
+        n = len(group)
+        perm = np.ascontiguousarray(np.array([list(p) for p, _ in group], dtype=np.int32).reshape(n, N))
+        flip = np.ascontiguousarray(np.array([int(bool(f)) for _, f in group], dtype=np.int32))
+        ch = np.ascontiguousarray(np.array(chi, dtype=np.float64))
+        self._check(self.lib.svmc_set_symmetry(self.h, n, perm.ctypes.data, flip.ctypes.data, ch.ctypes.data),
+                    "set_symmetry")
+        self._sym_n = n
+
+    def sym_expand(self, occ: torch.Tensor) -> torch.Tensor:
+        """[W, N] int8 device occupations -> their copies [W n_g, N] (svmc_sym_expand)."""
+        N = self.lattices[0].N
+        occ = occ.to(self.device, torch.int8).contiguous().reshape(-1, N)
+        out = torch.empty(occ.shape[0] * self._sym_n, N, dtype=torch.int8, device=self.device)
+        self._check(self.lib.svmc_sym_expand(self.h, occ.shape[0], _ptr(occ), _ptr(out), _stream()), "sym_expand")
+        return out
+
+    def local_energy_sym(self):
+        """(E_sym, sign, log|psi_sym|) [W / n_g] of the loaded symmetric batch
+        (svmc_local_energy_sym)."""
+        K = self.num_walkers // self._sym_n
+        e = torch.empty(K, dtype=torch.float64, device=self.device)
+        sg = torch.empty(K, dtype=torch.float64, device=self.device)
+        la = torch.empty(K, dtype=torch.float64, device=self.device)
+        self._check(self.lib.svmc_local_energy_sym(self.h, _ptr(e), _ptr(sg), _ptr(la), _stream()),
+                    "local_energy_sym")
+        return e, sg, la
+
     def update_params(self, theta: torch.Tensor):
         """Upload a new flat parameter vector (same base orbitals) and rebuild
         the walkers' caches at their current configurations."""

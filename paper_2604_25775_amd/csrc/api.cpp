@@ -116,6 +116,10 @@ struct svmc_ctx {
   DevBuf gK, gB, gE;                 // conv weights, conv bias, embedding (FP64, forward's rounding)
   DevBuf gMW, gMB;                   // site-wise weights and biases (FP64, forward's rounding)
   DevBuf g_rows, g_dH, g_hs, g_dzs, g_vjp;  // gradient scratch
+  // symmetry projection: group (site permutations, spin flips, characters)
+  // and the copies' local energies, signs and log|psi|
+  int sym_n = 0;
+  DevBuf sym_perm, sym_flip, sym_chi, sym_e, sym_s, sym_l;
   std::vector<int64_t> counts;
 
   svmc_status fail(svmc_status s, const std::string& m) {
@@ -903,6 +907,99 @@ svmc_status svmc_grad_logpsi(svmc_ctx* ctx, const double* vjp_w, void* out_v, sv
   }
   if (!jac && f32) return ctx->hip(launch_to_f32(ctx->g_vjp.as<double>(), (float*)out_v, np, st), "FP32 sum");
   return SVMC_OK;
+}
+
+// Site of lattice l at direction d from s, or -1 off an open edge (host).
+static int host_target(const svmc_lattice& l, int s, int d) {
+  static const int dx[8] = {1, -1, 0, 0, 1, 1, -1, -1}, dy[8] = {0, 0, 1, -1, 1, -1, 1, -1};
+  int x = s % l.Lx + dx[d], y = s / l.Lx + dy[d];
+  if (l.pbc_x) x = ((x % l.Lx) + l.Lx) % l.Lx; else if (x < 0 || x >= l.Lx) return -1;
+  if (l.pbc_y) y = ((y % l.Ly) + l.Ly) % l.Ly; else if (y < 0 || y >= l.Ly) return -1;
+  return x + l.Lx * y;
+}
+
+svmc_status svmc_set_symmetry(svmc_ctx* ctx, int32_t n_g, const int32_t* perm, const int32_t* flip, const double* chi) {
+  if (!ctx) return SVMC_ERR_INVALID_ARG;
+  if (n_g == 0) {
+    ctx->sym_n = 0;
+    return SVMC_OK;
+  }
+  if (ctx->lats.size() != 1) return ctx->fail(SVMC_ERR_UNSUPPORTED, "symmetry projection needs a one-lattice context");
+  if (n_g < 0 || !perm || !flip || !chi) return ctx->fail(SVMC_ERR_INVALID_ARG, "bad group description");
+  const svmc_lattice& l = ctx->lats[0];
+  const int N = l.Lx * l.Ly, nd = l.tp != 0.0 ? 8 : 4;
+  for (int g = 0; g < n_g; ++g) {
+    const int32_t* p = perm + (size_t)g * N;
+    std::vector<char> seen((size_t)N, 0);
+    for (int s = 0; s < N; ++s) {
+      if (p[s] < 0 || p[s] >= N || seen[(size_t)p[s]]) return ctx->fail(SVMC_ERR_INVALID_ARG, "perm is not a permutation");
+      seen[(size_t)p[s]] = 1;
+    }
+    if (flip[g] != 0 && flip[g] != 1) return ctx->fail(SVMC_ERR_INVALID_ARG, "flip must be 0 or 1");
+    if (flip[g] && l.n_up != l.n_dn) return ctx->fail(SVMC_ERR_INVALID_ARG, "spin flip needs n_up == n_dn");
+    if (!std::isfinite(chi[g])) return ctx->fail(SVMC_ERR_INVALID_ARG, "non-finite character");
+    if (g == 0) {
+      bool id = !flip[0];
+      for (int s = 0; s < N; ++s) id = id && p[s] == s;
+      if (!id) return ctx->fail(SVMC_ERR_INVALID_ARG, "the first group element must be the identity");
+    }
+    // a symmetry of the Hamiltonian: bonds go to bonds of the same kind
+    // (nearest / next-nearest), and the t-J pinning field is kept
+    for (int s = 0; s < N; ++s)
+      for (int d = 0; d < nd; ++d) {
+        const int j = host_target(l, s, d);
+        if (j < 0) continue;
+        bool found = false;
+        for (int d2 = (d < 4 ? 0 : 4); d2 < (d < 4 ? 4 : 8) && !found; ++d2) found = host_target(l, p[s], d2) == p[j];
+        if (!found) return ctx->fail(SVMC_ERR_INVALID_ARG, "a group element does not map bonds to bonds");
+      }
+    if (l.tj && l.h_pin != 0.0)
+      for (int s = 0; s < N; ++s) {
+        auto field = [&](int q) { return q % l.Lx == 0 ? ((q / l.Lx) & 1 ? -1 : 1) : 0; };
+        if (field(p[s]) * (flip[g] ? -1 : 1) != field(s))
+          return ctx->fail(SVMC_ERR_INVALID_ARG, "a group element does not keep the pinning field");
+      }
+  }
+  svmc_status st;
+  if ((st = ctx->hip(ctx->sym_perm.ensure((size_t)n_g * N * 4), "alloc")) ||
+      (st = ctx->hip(ctx->sym_flip.ensure((size_t)n_g * 4), "alloc")) ||
+      (st = ctx->hip(ctx->sym_chi.ensure((size_t)n_g * 8), "alloc")))
+    return st;
+  if ((st = ctx->hip(hipMemcpy(ctx->sym_perm.p, perm, (size_t)n_g * N * 4, hipMemcpyHostToDevice), "copy")) ||
+      (st = ctx->hip(hipMemcpy(ctx->sym_flip.p, flip, (size_t)n_g * 4, hipMemcpyHostToDevice), "copy")) ||
+      (st = ctx->hip(hipMemcpy(ctx->sym_chi.p, chi, (size_t)n_g * 8, hipMemcpyHostToDevice), "copy")))
+    return st;
+  ctx->sym_n = n_g;
+  return SVMC_OK;
+}
+
+svmc_status svmc_sym_expand(svmc_ctx* ctx, int64_t W, const int8_t* occ, int8_t* out, hipStream_t st) {
+  if (!ctx) return SVMC_ERR_INVALID_ARG;
+  if (ctx->sym_n == 0) return ctx->fail(SVMC_ERR_STATE, "no symmetry group set");
+  if (W < 0 || (W > 0 && (!occ || !out))) return ctx->fail(SVMC_ERR_INVALID_ARG, "bad batch");
+  const svmc_lattice& l = ctx->lats[0];
+  return ctx->hip(launch_sym_expand(l.Lx * l.Ly, ctx->sym_n, ctx->sym_perm.as<int32_t>(), ctx->sym_flip.as<int32_t>(),
+                                    W, occ, out, st),
+                  "symmetry expansion");
+}
+
+svmc_status svmc_local_energy_sym(svmc_ctx* ctx, double* eloc, double* sign, double* logabs, hipStream_t st) {
+  if (!ctx) return SVMC_ERR_INVALID_ARG;
+  if (ctx->sym_n == 0) return ctx->fail(SVMC_ERR_STATE, "no symmetry group set");
+  if (!ctx->have_walkers) return ctx->fail(SVMC_ERR_STATE, "no walkers loaded");
+  if (!eloc) return ctx->fail(SVMC_ERR_INVALID_ARG, "eloc is null");
+  if (ctx->Wtot % ctx->sym_n) return ctx->fail(SVMC_ERR_INVALID_ARG, "walker count is not a multiple of the group order");
+  svmc_status s;
+  const size_t W = (size_t)ctx->Wtot;
+  if ((s = ctx->hip(ctx->sym_e.ensure(W * 8), "alloc")) || (s = ctx->hip(ctx->sym_s.ensure(W * 8), "alloc")) ||
+      (s = ctx->hip(ctx->sym_l.ensure(W * 8), "alloc")))
+    return s;
+  if ((s = svmc_local_energy(ctx, SVMC_PATH_LOWRANK, ctx->sym_e.as<double>(), nullptr, nullptr, nullptr, st))) return s;
+  if ((s = svmc_log_psi(ctx, ctx->sym_s.as<double>(), ctx->sym_l.as<double>(), st))) return s;
+  return ctx->hip(launch_sym_combine(ctx->ld[0], ctx->sym_n, ctx->sym_perm.as<int32_t>(), ctx->sym_flip.as<int32_t>(),
+                                     ctx->sym_chi.as<double>(), ctx->bufs(), ctx->sym_e.as<double>(),
+                                     ctx->sym_s.as<double>(), ctx->sym_l.as<double>(), eloc, sign, logabs, st),
+                  "symmetric local energy");
 }
 
 svmc_status svmc_walker_flags(svmc_ctx* ctx, int32_t* flags, hipStream_t st) {

@@ -46,6 +46,14 @@ hipError_t launch_gp(const LatDev& lt, const Bufs& bf, int C, hipStream_t st,
                      WalkerSel sel = WalkerSel{nullptr, nullptr});
 hipError_t launch_logpsi(const LatDev& lt, const Bufs& bf, double* sign, double* logabs, hipStream_t st);
 
+// sym.hip: copies of a batch under a symmetry group, and the symmetric
+// amplitude and local energy from the copies' values
+hipError_t launch_sym_expand(int N, int nG, const int32_t* perm, const int32_t* flip, long long W, const int8_t* in,
+                             int8_t* out, hipStream_t st);
+hipError_t launch_sym_combine(const LatDev& lt, int nG, const int32_t* perm, const int32_t* flip, const double* chi,
+                              const Bufs& bf, const double* e, const double* sg, const double* la, double* eloc,
+                              double* sign_out, double* logabs_out, hipStream_t st);
+
 // eloc.hip: low-rank local energies over all walkers of all lattices in one launch
 struct ElocOut {
   double* eloc;
