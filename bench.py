@@ -405,13 +405,23 @@ def symmetric_eloc(prec, log, wname="c3", W=1024):
     torch.cuda.synchronize()
     ms = t0.elapsed_time(t1) / 3
     ok = bool(torch.isfinite(e).all().item())
+    # one sweep of |psi_sym|^2 (N proposals per walker, every copy moved)
+    t0.record()
+    n_acc = ctx.sweep_sym(1, wl.seed_mc, 0)
+    t1.record()
+    torch.cuda.synchronize()
+    sweep_ms = t0.elapsed_time(t1)
+    acc_rate = float(n_acc[::len(G)].sum().item()) / (W * lat.N)
+    e2, _, _ = ctx.local_energy_sym()
+    ok = ok and bool(torch.isfinite(e2).all().item())
     del ctx
     row = {"workload": f"{wname} lattice, {W} walkers x |G| = {len(G)} (mirrors x, y; spin inversion)",
            "group_order": len(G), "walkers": W, "ms": round(ms, 3),
            "eloc_sym_per_s": round(W / (ms / 1e3), 1), "copies_eloc_per_s": round(W * len(G) / (ms / 1e3), 1),
-           "all_finite": ok}
+           "sym_sweep_ms": round(sweep_ms, 2), "sym_accept_rate": round(acc_rate, 4), "all_finite": ok}
     log(f"[bench] symmetric E_loc (|G| = {len(G)}): {ms:.2f} ms for {W} walkers -> "
-        f"{row['eloc_sym_per_s']:.1f} E_sym/s ({row['copies_eloc_per_s']:.1f} copies/s)")
+        f"{row['eloc_sym_per_s']:.1f} E_sym/s ({row['copies_eloc_per_s']:.1f} copies/s); "
+        f"one |psi_sym|^2 sweep {sweep_ms:.1f} ms, accept rate {acc_rate:.3f}")
     return row
 
 

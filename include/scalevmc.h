@@ -321,7 +321,7 @@ svmc_status svmc_walker_flags(svmc_ctx* ctx, int32_t* flags, hipStream_t stream)
  * with H), and sign and log|psi_sym(n)|.  A walker whose copies are not
  * the images of copy 0 (e.g. after svmc_sweep moved them independently), or
  * with a BADCOUNT copy, gets NaN and SVMC_W_SYMMETRY on copy 0.  psi_sym = 0
- * gives E NaN, sign 0, logabs -inf.  Sampling |psi_sym|^2 is not provided:
+ * gives E NaN, sign 0, logabs -inf.  svmc_sweep_sym samples |psi_sym|^2;
  * walkers from svmc_sweep (|psi|^2) serve by reweighting with
  * |psi_sym / psi|^2.  INVALID_ARG if the walker count is not a multiple of
  * n_g; STATE without a group or walkers. */
@@ -329,6 +329,20 @@ svmc_status svmc_set_symmetry(svmc_ctx* ctx, int32_t n_g, const int32_t* perm, c
                               const double* chi);
 svmc_status svmc_sym_expand(svmc_ctx* ctx, int64_t W, const int8_t* occ, int8_t* out, hipStream_t stream);
 svmc_status svmc_local_energy_sym(svmc_ctx* ctx, double* eloc, double* sign, double* logabs, hipStream_t stream);
+
+/* Metropolis sampling of |psi_sym|^2 (App. B with Sec. II.A) on a batch laid
+ * out as svmc_sym_expand writes it: symmetric walker k draws the proposal
+ * of the ordinary sampler (svmc_sweep) from the Philox block with counter
+ * (k, step0 + q) and its copy 0's labels; the move is mapped to every copy
+ * (site i -> perm[g][i], spin exchanged under flip), each copy's ratio
+ * comes from the local update (Sec. II.C), and the move is accepted for all
+ * copies iff u < |psi_sym(n') / psi_sym(n)|^2 with
+ *   psi_sym(n') / psi_sym(n) = (+-) sum_g a_g R_g / sum_g a_g,  a_g = Pi(n, g) chi_g psi(g n),
+ * so the copies stay images of copy 0.  n_accept: device [W n_g] int64 or
+ * NULL, incremented per copy.  Errors as svmc_sweep, plus STATE without a
+ * group and INVALID_ARG if the walker count is not a multiple of n_g. */
+svmc_status svmc_sweep_sym(svmc_ctx* ctx, int32_t n_sweeps, uint64_t seed, uint64_t step0, int64_t* n_accept,
+                           hipStream_t stream);
 
 /* Launch shape of the low-rank local-energy kernel (not a step of the
  * method; results agree to rounding across shapes):

@@ -14,6 +14,10 @@ The local energy of psi_sym is taken from its plain definition,
 every psi_sym(n') recomputed in full (|G| network evaluations each).  The
 oracle does not assume that G is a symmetry of the Hamiltonian.
 
+Sampling |psi_sym|^2 uses the proposals of oracle.sampler (the same Philox
+block, counter (walker, step)); the ratio psi_sym(n') / psi_sym(n) is
+recomputed in full.
+
 Test infrastructure: used by the tests, never by the library.
 """
 from __future__ import annotations
@@ -22,7 +26,8 @@ import numpy as np
 
 from .ansatz import log_psi
 from .energy import connection_sign, diagonal_energy
-from .lattice import apply_hop, connections
+from .lattice import DIRS, apply_hop, connections, neighbour
+from .philox import proposal_draw
 
 
 def apply_symmetry(occ, perm, flip: bool):
@@ -95,3 +100,40 @@ def local_energy_sym(lat, params, occ, group, chi, lat_index: int = 0, act: str 
             continue
         e += -h.t * connection_sign(occ, h) * s1 * s0 * np.exp(l1 - l0)
     return e
+
+
+def metropolis_sym(lat, params, occ, pos, walker: int, seed: int, step0: int, n_sweeps: int,
+                   group, chi, lat_index: int = 0, act: str = "tanh"):
+    """n_sweeps Metropolis sweeps of |psi_sym|^2 on one walker: proposals as
+    in oracle.sampler.metropolis, accepted iff u < (psi_sym(n') / psi_sym(n))^2
+    (rejected while psi_sym(n) = 0).  Returns (occ, pos, n_accept)."""
+    occ = np.array(occ, dtype=np.int8)
+    pos = [p.copy() for p in pos]
+    n_up, n_dn = lat.n_up, lat.n_dn
+    ne = n_up + n_dn
+    if ne == 0:
+        return occ, pos, 0
+    s0, l0 = log_psi_sym(lat, params, occ, group, chi, lat_index, act)
+    n_acc = 0
+    for sweep in range(n_sweeps):
+        for p in range(lat.N):
+            step = step0 + sweep * lat.N + p
+            e, d, u = proposal_draw(seed, walker, step, ne)
+            spin, k = (0, e) if e < n_up else (1, e - n_up)
+            bit = 1 << spin
+            i = int(pos[spin][k])
+            j = neighbour(lat, i, *DIRS[d])
+            if j < 0 or (occ[j] != 0 if lat.tj else occ[j] & bit):
+                continue
+            new = occ.copy()
+            new[i] -= bit
+            new[j] += bit
+            s1, l1 = log_psi_sym(lat, params, new, group, chi, lat_index, act)
+            if s0 == 0.0 or s1 == 0.0:
+                continue
+            if u < float(np.exp(2.0 * (l1 - l0))):
+                occ = new
+                pos[spin][k] = j
+                s0, l0 = s1, l1
+                n_acc += 1
+    return occ, pos, n_acc

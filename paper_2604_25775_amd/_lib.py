@@ -22,7 +22,7 @@ EXPORTS = [
     "svmc_sweep", "svmc_refresh", "svmc_get_state", "svmc_grad_logpsi", "svmc_walker_flags",
     "svmc_status_string", "svmc_last_error", "svmc_tune", "svmc_sweep_async",
     "svmc_local_energy_noalloc", "svmc_set_launch", "svmc_get_launch",
-    "svmc_set_symmetry", "svmc_sym_expand", "svmc_local_energy_sym",
+    "svmc_set_symmetry", "svmc_sym_expand", "svmc_local_energy_sym", "svmc_sweep_sym",
 ]
 
 
@@ -89,6 +89,7 @@ def load(path: str | None = None):
         "svmc_set_symmetry": (i32, [vp, i32, vp, vp, vp]),
         "svmc_sym_expand": (i32, [vp, i64, vp, vp, vp]),
         "svmc_local_energy_sym": (i32, [vp, vp, vp, vp, vp]),
+        "svmc_sweep_sym": (i32, [vp, i32, u64, u64, vp, vp]),
     }
     for name, (res, args) in proto.items():
         f = getattr(lib, name)

@@ -255,6 +255,14 @@ class ScaleVMC:
                     "local_energy_sym")
         return e, sg, la
 
+    def sweep_sym(self, n_sweeps: int, seed: int, step0: int):
+        """Metropolis sweeps of |psi_sym|^2 (svmc_sweep_sym); accepted moves per copy."""
+        n_accept = torch.zeros(self.num_walkers, dtype=torch.int64, device=self.device)
+        self.state_version += 1
+        self._check(self.lib.svmc_sweep_sym(self.h, int(n_sweeps), ct.c_uint64(seed), ct.c_uint64(step0),
+                                            _ptr(n_accept), _stream()), "sweep_sym")
+        return n_accept
+
     def update_params(self, theta: torch.Tensor):
         """Upload a new flat parameter vector (same base orbitals) and rebuild
         the walkers' caches at their current configurations."""

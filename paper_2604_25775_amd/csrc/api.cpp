@@ -120,6 +120,7 @@ struct svmc_ctx {
   // and the copies' local energies, signs and log|psi|
   int sym_n = 0;
   DevBuf sym_perm, sym_flip, sym_chi, sym_e, sym_s, sym_l;
+  DevBuf sym_move, sym_ratio, sym_acc, sym_u, sym_pi;   // symmetric sampling
   std::vector<int64_t> counts;
 
   svmc_status fail(svmc_status s, const std::string& m) {
@@ -732,7 +733,8 @@ static svmc_status refresh_list(svmc_ctx* ctx, const Bufs& bf, WalkerSel sel, in
 }
 
 static svmc_status sweep_steps(svmc_ctx* ctx, int32_t n_sweeps, uint64_t seed, uint64_t step0,
-                               const uint64_t* step0_dev, int64_t* n_accept, const StepSizes& z, hipStream_t st) {
+                               const uint64_t* step0_dev, int64_t* n_accept, const StepSizes& z, hipStream_t st,
+                               bool sym = false) {
   const int every = ctx->model.refresh_every;
   const Bufs bf = ctx->bufs();
   const ModelDev md = ctx->mdev();
@@ -756,6 +758,23 @@ static svmc_status sweep_steps(svmc_ctx* ctx, int32_t n_sweeps, uint64_t seed, u
   ctx->dets_fresh = false;
   svmc_status s;
   if ((s = ctx->hip(launch_fill_i32(cnt, 4, 0, st), "counter reset"))) return s;
+  const int nG = ctx->sym_n;
+  if (sym) {
+    // symmetric sampling: moves drawn per symmetric walker and mapped to its
+    // copies, a ratio-only pass, the decision on psi_sym, then the commit
+    const size_t W = (size_t)ctx->Wtot;
+    if ((s = ctx->hip(ctx->sym_move.ensure(W * 4), "alloc")) || (s = ctx->hip(ctx->sym_ratio.ensure(W * 8), "alloc")) ||
+        (s = ctx->hip(ctx->sym_acc.ensure(W * 4), "alloc")) || (s = ctx->hip(ctx->sym_u.ensure(W * 8), "alloc")) ||
+        (s = ctx->hip(ctx->sym_pi.ensure(W * 8), "alloc")))
+      return s;
+    if ((s = ctx->hip(launch_sym_signs(ctx->ld[0], nG, ctx->sym_perm.as<int32_t>(), ctx->sym_flip.as<int32_t>(), bf,
+                                       ctx->sym_pi.as<double>(), st),
+                      "symmetry signs")))
+      return s;
+    sa.sym_move = ctx->sym_move.as<int32_t>();
+    sa.sym_ratio = ctx->sym_ratio.as<double>();
+    sa.sym_acc = ctx->sym_acc.as<int32_t>();
+  }
   // per proposal index: every walker proposes, the walkers that accepted are
   // updated, and walkers that reached `every` accepted moves are rebuilt in
   // FP64 before their next proposal
@@ -763,6 +782,24 @@ static svmc_status sweep_steps(svmc_ctx* ctx, int32_t n_sweeps, uint64_t seed, u
     sa.q = q;
     sa.count = cnt + (q & 1);
     sa.count_next = cnt + ((q + 1) & 1);
+    if (sym) {
+      const int32_t* perm = ctx->sym_perm.as<int32_t>();
+      const int32_t* flip = ctx->sym_flip.as<int32_t>();
+      sa.sym_mode = 1;
+      if ((s = ctx->hip(launch_sym_draw(ctx->ld[0], nG, perm, flip, bf, seed, step0 + (uint64_t)q,
+                                        ctx->sym_move.as<int32_t>(), ctx->sym_u.as<double>(), st),
+                        "symmetric draw")) ||
+          (s = ctx->hip(launch_sweep_step(ctx->prec, md, ctx->lats_dev.as<LatDev>(), ctx->ld.data(),
+                                          (int)ctx->ld.size(), ctx->Wtot, bf, sa, st),
+                        "symmetric ratios")) ||
+          (s = ctx->hip(launch_sym_decide(ctx->ld[0], nG, perm, flip, ctx->sym_chi.as<double>(), bf,
+                                          ctx->sym_move.as<int32_t>(), ctx->sym_ratio.as<double>(),
+                                          ctx->sym_u.as<double>(), ctx->sym_pi.as<double>(),
+                                          ctx->sym_acc.as<int32_t>(), st),
+                        "symmetric decision")))
+        return s;
+      sa.sym_mode = 2;
+    }
     if ((s = ctx->hip(launch_sweep_step(ctx->prec, md, ctx->lats_dev.as<LatDev>(), ctx->ld.data(),
                                         (int)ctx->ld.size(), ctx->Wtot, bf, sa, st),
                       "sweep step")))
@@ -790,6 +827,22 @@ svmc_status svmc_sweep(svmc_ctx* ctx, int32_t n_sweeps, uint64_t seed, uint64_t 
   if ((s = sweep_workspace(ctx, false, z))) return s;
   if (!ctx->prepared && (s = prepare(ctx, st))) return s;
   return sweep_steps(ctx, n_sweeps, seed, step0, nullptr, n_accept, z, st);
+}
+
+svmc_status svmc_sweep_sym(svmc_ctx* ctx, int32_t n_sweeps, uint64_t seed, uint64_t step0, int64_t* n_accept,
+                           hipStream_t st) {
+  if (!ctx) return SVMC_ERR_INVALID_ARG;
+  if (ctx->sym_n == 0) return ctx->fail(SVMC_ERR_STATE, "no symmetry group set");
+  if (!ctx->have_walkers) return ctx->fail(SVMC_ERR_STATE, "no walkers loaded");
+  if (ctx->Wtot % ctx->sym_n) return ctx->fail(SVMC_ERR_INVALID_ARG, "walker count is not a multiple of the group order");
+  if (n_sweeps < 0) return ctx->fail(SVMC_ERR_INVALID_ARG, "negative sweep count");
+  if (n_sweeps == 0) return SVMC_OK;
+  if ((long long)n_sweeps * ctx->ld[0].N > (1LL << 40)) return ctx->fail(SVMC_ERR_INVALID_ARG, "too many sweeps");
+  StepSizes z;
+  svmc_status s;
+  if ((s = sweep_workspace(ctx, false, z))) return s;
+  if (!ctx->prepared && (s = prepare(ctx, st))) return s;
+  return sweep_steps(ctx, n_sweeps, seed, step0, nullptr, n_accept, z, st, true);
 }
 
 svmc_status svmc_sweep_async(svmc_ctx* ctx, int32_t n_sweeps, uint64_t seed, const uint64_t* step0_dev,

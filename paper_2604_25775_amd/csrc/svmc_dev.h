@@ -141,6 +141,24 @@ SVMC_DEV double readlane_d(double x, int lane) {
 
 SVMC_DEV int uniform_i(int x) { return __builtin_amdgcn_readfirstlane(x); }
 
+// Philox4x64-10 counter-based generator (Salmon et al., SC'11): ten rounds
+// on the counter c with key (k0, k1); the Metropolis proposals draw one block
+// each.
+SVMC_DEV void philox4x64_10(unsigned long long (&c)[4], unsigned long long k0, unsigned long long k1) {
+  const unsigned long long M0 = 0xD2E7470EE14C6C93ULL, M1 = 0xCA5A826395121157ULL;
+  const unsigned long long W0 = 0x9E3779B97F4A7C15ULL, W1 = 0xBB67AE8584CAA73BULL;
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const unsigned long long lo0 = M0 * c[0], hi0 = __umul64hi(M0, c[0]);
+    const unsigned long long lo1 = M1 * c[2], hi1 = __umul64hi(M1, c[2]);
+    const unsigned long long n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+    c[0] = n0; c[1] = lo1; c[2] = n2; c[3] = lo0;
+    k0 += W0;
+    k1 += W1;
+  }
+}
+
+
 // Maximum of an unsigned key over the wavefront with DPP lane exchanges
 // (quad swaps, half-row and row mirrors, then row broadcasts 15 and 31);
 // lane 63 ends with the maximum, which is returned to every lane.

@@ -53,6 +53,14 @@ hipError_t launch_sym_expand(int N, int nG, const int32_t* perm, const int32_t* 
 hipError_t launch_sym_combine(const LatDev& lt, int nG, const int32_t* perm, const int32_t* flip, const double* chi,
                               const Bufs& bf, const double* e, const double* sg, const double* la, double* eloc,
                               double* sign_out, double* logabs_out, hipStream_t st);
+hipError_t launch_sym_signs(const LatDev& lt, int nG, const int32_t* perm, const int32_t* flip, const Bufs& bf,
+                            double* pi, hipStream_t st);
+hipError_t launch_sym_draw(const LatDev& lt, int nG, const int32_t* perm, const int32_t* flip, const Bufs& bf,
+                           unsigned long long seed, unsigned long long step, int32_t* move, double* u,
+                           hipStream_t st);
+hipError_t launch_sym_decide(const LatDev& lt, int nG, const int32_t* perm, const int32_t* flip, const double* chi,
+                             const Bufs& bf, const int32_t* move, const double* ratio, const double* u, double* pi,
+                             int32_t* acc, hipStream_t st);
 
 // eloc.hip: low-rank local energies over all walkers of all lattices in one launch
 struct ElocOut {
@@ -95,6 +103,14 @@ struct StepArgs {
   int32_t* urgent_list;  // [W] walkers to rebuild before their next proposal
   int32_t* urgent_count; // their number (cleared by the host sequence each step)
   int refresh_every;
+  // symmetric sampling (sym.hip drives it): 0 = draw and decide in the
+  // proposal kernel; 1 = the move of walker w is sym_move[w] ((i << 4) |
+  // (spin << 3) | d, or -1 for none) and only its ratio is written to
+  // sym_ratio[w]; 2 = the same move, accepted iff sym_acc[w] != 0
+  int sym_mode = 0;
+  const int32_t* sym_move = nullptr;
+  double* sym_ratio = nullptr;
+  const int32_t* sym_acc = nullptr;
 };
 struct StepSizes {
   size_t smem_propose, smem_update, stage_bytes;

@@ -106,20 +106,6 @@ SVMC_DEV int box_index(const LatDev& lt, int s, int olx, int owx, int oly, int o
   return (dx >= 0 && dx < owx && dy >= 0 && dy < owy) ? dx + owx * dy : -1;
 }
 
-SVMC_DEV void philox4x64_10(unsigned long long (&c)[4], unsigned long long k0, unsigned long long k1) {
-  const unsigned long long M0 = 0xD2E7470EE14C6C93ULL, M1 = 0xCA5A826395121157ULL;
-  const unsigned long long W0 = 0x9E3779B97F4A7C15ULL, W1 = 0xBB67AE8584CAA73BULL;
-#pragma unroll
-  for (int r = 0; r < 10; ++r) {
-    const unsigned long long lo0 = M0 * c[0], hi0 = __umul64hi(M0, c[0]);
-    const unsigned long long lo1 = M1 * c[2], hi1 = __umul64hi(M1, c[2]);
-    const unsigned long long n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
-    c[0] = n0; c[1] = lo1; c[2] = n2; c[3] = lo0;
-    k0 += W0;
-    k1 += W1;
-  }
-}
-
 // Gauss-Jordan inverse of an r x r FP64 matrix in one wavefront (r <= RM),
 // rows in lanes with rotating columns: at step p the current column is a[0];
 // the pivot row is scaled, the other rows eliminate it, every row shifts left
@@ -178,33 +164,49 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(3))) void k
   // runtime spin would move it to scratch memory
   const int n_up = lt.n[0], n_dn = lt.n[1], ne = n_up + n_dn;
   const long long qend = (long long)sa.n_sweeps * N;
-  if (sa.q >= qend || ne == 0 || (bf.flags[w] & (1 | 2 | 8))) {
-    if (tid == 0) hdr[HD_ACC] = 0;
+  const int mv = sa.sym_mode ? uniform_i(sa.sym_move[w]) : 0;
+  if (sa.q >= qend || ne == 0 || (bf.flags[w] & (1 | 2 | 8)) || mv < 0) {
+    if (tid == 0) {
+      hdr[HD_ACC] = 0;
+      if (sa.sym_mode == 1) sa.sym_ratio[w] = 0.0;
+    }
     return;
   }
-  // ---- draw (identical in every thread)
-  const unsigned long long step0 = sa.step0_dev ? *sa.step0_dev : sa.step0;
-  unsigned long long ctr[4] = {(unsigned long long)w, step0 + (unsigned long long)sa.q, 0ULL, 0ULL};
-  philox4x64_10(ctr, sa.seed, 0ULL);
-  const int e = (int)__umul64hi(ctr[0], (unsigned long long)ne);
-  const int d = (int)(ctr[1] >> 62);
-  const double u = (double)(ctr[2] >> 11) * 0x1.0p-53;
-  const int sp = e < n_up ? 0 : 1;
-  const int k = sp == 0 ? e : e - n_up;
   int8_t* occ_g = bf.occ + lt.occ_off + wl * N;
   int16_t* lab_g = bf.lab + lt.lab_off + wl * 2LL * N;
   int16_t* pos_g = bf.pos + lt.pos_off + wl * 2LL * nm;
-  const int i = uniform_i(pos_g[sp * nm + k]);
+  // ---- draw (identical in every thread), or the move given
+  int d, sp, k, i;
+  double u = 0.0;
+  if (sa.sym_mode == 0) {
+    const unsigned long long step0 = sa.step0_dev ? *sa.step0_dev : sa.step0;
+    unsigned long long ctr[4] = {(unsigned long long)w, step0 + (unsigned long long)sa.q, 0ULL, 0ULL};
+    philox4x64_10(ctr, sa.seed, 0ULL);
+    const int e = (int)__umul64hi(ctr[0], (unsigned long long)ne);
+    d = (int)(ctr[1] >> 62);
+    u = (double)(ctr[2] >> 11) * 0x1.0p-53;
+    sp = e < n_up ? 0 : 1;
+    k = sp == 0 ? e : e - n_up;
+    i = uniform_i(pos_g[sp * nm + k]);
+  } else {
+    i = mv >> 4;
+    sp = (mv >> 3) & 1;
+    d = mv & 7;
+    k = uniform_i(lab_g[sp * N + i]);
+  }
   const int bit = 1 << sp;
   {
     int x = i % lt.Lx + dir_dx(d), y = i / lt.Lx + dir_dy(d);
-    bool ok = true;
+    bool ok = k >= 0;
     if (lt.pbc_x) x = imod(x, lt.Lx); else ok = ok && x >= 0 && x < lt.Lx;
     if (lt.pbc_y) y = imod(y, lt.Ly); else ok = ok && y >= 0 && y < lt.Ly;
     const int tgt = ok ? uniform_i(occ_g[x + lt.Lx * y]) : 0;
     // (t-J: the Gutzwiller projection also rejects a site of the other spin)
     if (!ok || (lt.tj ? tgt != 0 : ((tgt >> sp) & 1))) {              // uniform
-      if (tid == 0) hdr[HD_ACC] = 0;
+      if (tid == 0) {
+        hdr[HD_ACC] = 0;
+        if (sa.sym_mode == 1) sa.sym_ratio[w] = 0.0;
+      }
       return;
     }
   }
@@ -243,7 +245,14 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(3))) void k
   __syncthreads();
   const double R0 = misc[0], R1 = misc[1];
   const double R = R0 * R1;
-  if (!(u < R * R)) {                                                 // uniform
+  if (sa.sym_mode == 1) {
+    if (tid == 0) {
+      sa.sym_ratio[w] = R;
+      hdr[HD_ACC] = 0;
+    }
+    return;
+  }
+  if (sa.sym_mode == 2 ? sa.sym_acc[w] == 0 : !(u < R * R)) {         // uniform
     if (tid == 0) hdr[HD_ACC] = 0;
     return;
   }
@@ -582,7 +591,9 @@ static hipError_t step_impl(const ModelDev& md, const LatDev* lats_dev, int nlat
   e = hipFuncSetAttribute((const void*)ku, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem_u);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(kp, dim3((unsigned)W), dim3(128), smem_p, st, md, lats_dev, nlats, bf, sa);
-  hipLaunchKernelGGL(ku, dim3((unsigned)upd_blocks), dim3(256), smem_u, st, md.L, lats_dev, nlats, bf, sa);
+  // (the ratio-only pass of symmetric sampling changes nothing to update)
+  if (sa.sym_mode != 1)
+    hipLaunchKernelGGL(ku, dim3((unsigned)upd_blocks), dim3(256), smem_u, st, md.L, lats_dev, nlats, bf, sa);
   return hipGetLastError();
 }
 

@@ -136,3 +136,41 @@ def test_sym_f16x2_16x16_d2_spin_inversion():
         assert sg[k] == np.sign(np.sum(a))
         assert abs(la[k] - l_ref) <= 1e-6 * abs(l_ref)
         assert abs(e[k] - e_ref) <= 1e-4 * max(1.0, abs(e_ref))
+
+
+@pytest.mark.parametrize("name,lat,gens,model", CASES, ids=[c[0] for c in CASES])
+def test_sym_sampler_chain_matches_oracle(name, lat, gens, model):
+    """svmc_sweep_sym against the oracle's |psi_sym|^2 chain (plain psi_sym
+    ratios): copy 0's occupations, labels and accept counts bit-exact; every
+    copy accepted the same moves and stays the image of copy 0; E_sym after
+    the sweeps against the plain definition."""
+    from oracle.sampler import initial_labels
+    from oracle.symmetry import metropolis_sym
+    from test_gpu_sweep import SEED, STEP0
+    G, chi = wl.symmetry_group(lat, gens)
+    occ = wl.random_occupations(lat, 3, seed=12)
+    say(f"[sym sweep f64] {name}: |G| = {len(G)}")
+    ctx, params, _ = sym_ctx(lat, model, G, chi, occ, backflow=0.5)
+    n_acc = ctx.sweep_sym(2, SEED, STEP0).cpu().numpy()
+    o, pos = ctx.state()
+    o = o.cpu().numpy().reshape(-1, lat.N)
+    pos = pos.cpu().numpy()
+    total = 0
+    new = []
+    for k in range(len(occ)):
+        o_ref, p_ref, a_ref = metropolis_sym(lat, params, occ[k], initial_labels(lat, occ[k]), k, SEED, STEP0, 2,
+                                             G, chi, act=model.act)
+        w0 = k * len(G)
+        assert np.array_equal(o[w0], o_ref), k
+        for sp, n in ((0, lat.n_up), (1, lat.n_dn)):
+            assert np.array_equal(pos[w0, sp, :n].astype(np.int64), p_ref[sp]), (k, sp)
+        assert (n_acc[w0:w0 + len(G)] == a_ref).all(), (k, n_acc[w0:w0 + len(G)], a_ref)
+        total += a_ref
+        new.append(o_ref)
+    assert total > 0
+    say(f"  {total} accepted moves")
+    e, sg, la = (x.cpu().numpy() for x in ctx.local_energy_sym())
+    assert not (ctx.flags().cpu().numpy() & 16).any()
+    for k in range(len(occ)):
+        e_ref = local_energy_sym(lat, params, new[k], G, chi, 0, model.act)
+        assert abs(e[k] - e_ref) <= 1e-9 * max(1.0, abs(e_ref)), (k, e[k], e_ref)

@@ -119,3 +119,61 @@ def test_symmetric_local_energy_equals_h_psi_and_weighted_copies(lat, gens):
             num += a * local_energy(lat, p, gn, 0, "silu")
             den += a
         assert num / den == pytest.approx(e, abs=1e-10 * (1 + abs(e)))
+
+
+@pytest.mark.parametrize("lat,gname", [(HUB, "ty_flip_odd"), (HUB3, "mx_odd_my")])
+def test_fermion_sign_update_along_a_hop(lat, gname):
+    """Pi(n', g) = Pi(n, g) jw_n(h) jw_gn(g h) for a hop h: the relation the
+    symmetric sampler keeps Pi up to date with."""
+    from oracle.energy import jw_sign
+    from oracle.lattice import apply_hop, hops
+    G, _ = wl.symmetry_group(lat, GENS[gname])
+    for occ in wl.random_occupations(lat, 4, seed=9):
+        for h in hops(lat, occ):
+            for perm, flip in G:
+                gocc = apply_symmetry(occ, perm, flip)
+                sp2 = h.spin ^ int(flip)
+                lhs = fermion_sign(apply_hop(occ, h), perm, flip)
+                rhs = (fermion_sign(occ, perm, flip) * jw_sign(occ, h.spin, h.i, h.j)
+                       * jw_sign(gocc, sp2, perm[h.i], perm[h.j]))
+                assert lhs == rhs
+
+
+def test_symmetric_sampler_histogram_chi2():
+    """metropolis_sym samples |psi_sym|^2 (chi^2 against the exact
+    distribution on a 36-state lattice)."""
+    from oracle.sampler import initial_labels
+    from oracle.symmetry import metropolis_sym
+    lat = wl.Lattice(2, 3, 0, 1, 1.0, 0.0, 4.0, 1, 1)
+    G, chi = wl.symmetry_group(lat, [("mx", -1.0), ("my", 1.0)])      # total variation 0.3 from |psi|^2
+    p = wl.random_params([lat], wl.Model(1, 4), seed=8, backflow=1.0)
+    states = []
+    for a in range(lat.N):
+        for b in range(lat.N):
+            o = np.zeros(lat.N, dtype=np.int8)
+            o[a] += 1
+            o[b] += 2
+            states.append(o)
+    v = np.array([log_psi_sym(lat, p, o, G, chi) for o in states])
+    w = np.where(v[:, 0] != 0.0, np.exp(2 * v[:, 1]), 0.0)
+    prob = w / w.sum()
+    key = {o.tobytes(): k for k, o in enumerate(states)}
+    counts = np.zeros(len(states))
+    init = wl.random_occupations(lat, 8, seed=3)
+    for wk in range(8):
+        o, pos = init[wk], initial_labels(lat, init[wk])
+        o, pos, _ = metropolis_sym(lat, p, o, pos, wk, 99, 0, 10, G, chi)
+        for blk in range(100):
+            o, pos, _ = metropolis_sym(lat, p, o, pos, wk, 99, (blk + 1) * 4 * lat.N, 4, G, chi)
+            counts[key[o.tobytes()]] += 1
+    n = counts.sum()
+    exp = n * prob
+    mask = exp > 5
+    chi2 = np.sum((counts[mask] - exp[mask]) ** 2 / exp[mask])
+    dof = mask.sum() - 1
+    assert chi2 < dof + 8 * np.sqrt(2 * dof) + 20
+    # |psi_sym|^2 differs from |psi|^2 here, so the test tells them apart
+    w0 = np.array([np.exp(2 * log_psi(lat, p, o)[1]) for o in states])
+    exp0 = n * w0 / w0.sum()
+    m0 = exp0 > 5
+    assert np.sum((counts[m0] - exp0[m0]) ** 2 / exp0[m0]) > 4 * (m0.sum() + 8 * np.sqrt(2 * m0.sum()) + 20)
