@@ -314,11 +314,14 @@ svmc_status svmc_walker_flags(svmc_ctx* ctx, int32_t* flags, hipStream_t stream)
  * k n_g + g = g n_k.  Load the result with svmc_load_walkers.
  *
  * svmc_local_energy_sym: for a loaded batch of W n_g walkers laid out as
- * svmc_sym_expand writes them, device eloc / sign / logabs [W] (sign,
- * logabs may be NULL): the local energy of psi_sym,
+ * svmc_sym_expand writes them, device eloc / sign / logabs [W] and weights
+ * [W n_g] (sign, logabs, weights may be NULL): the local energy of psi_sym,
  *   E_sym(n) = sum_g w_g E_loc(g n),  w_g = Pi(n, g) chi_g psi(g n) / psi_sym(n)
  * (the copies' low-rank local energies; exact because every U_g commutes
- * with H), and sign and log|psi_sym(n)|.  A walker whose copies are not
+ * with H), sign and log|psi_sym(n)|, and the copies' weights w_g, so that
+ * d log|psi_sym(n)| / d theta = sum_g w_g d log|psi(g n)| / d theta: the
+ * gradient is svmc_grad_logpsi with vjp_w[k n_g + g] = c_k w_g for upstream
+ * weights c_k.  A walker whose copies are not
  * the images of copy 0 (e.g. after svmc_sweep moved them independently), or
  * with a BADCOUNT copy, gets NaN and SVMC_W_SYMMETRY on copy 0.  psi_sym = 0
  * gives E NaN, sign 0, logabs -inf.  svmc_sweep_sym samples |psi_sym|^2;
@@ -328,7 +331,8 @@ svmc_status svmc_walker_flags(svmc_ctx* ctx, int32_t* flags, hipStream_t stream)
 svmc_status svmc_set_symmetry(svmc_ctx* ctx, int32_t n_g, const int32_t* perm, const int32_t* flip,
                               const double* chi);
 svmc_status svmc_sym_expand(svmc_ctx* ctx, int64_t W, const int8_t* occ, int8_t* out, hipStream_t stream);
-svmc_status svmc_local_energy_sym(svmc_ctx* ctx, double* eloc, double* sign, double* logabs, hipStream_t stream);
+svmc_status svmc_local_energy_sym(svmc_ctx* ctx, double* eloc, double* sign, double* logabs, double* weights,
+                                  hipStream_t stream);
 
 /* Metropolis sampling of |psi_sym|^2 (App. B with Sec. II.A) on a batch laid
  * out as svmc_sym_expand writes it: symmetric walker k draws the proposal

@@ -88,7 +88,7 @@ def load(path: str | None = None):
         "svmc_get_launch": (i32, [vp, ct.POINTER(Launch)]),
         "svmc_set_symmetry": (i32, [vp, i32, vp, vp, vp]),
         "svmc_sym_expand": (i32, [vp, i64, vp, vp, vp]),
-        "svmc_local_energy_sym": (i32, [vp, vp, vp, vp, vp]),
+        "svmc_local_energy_sym": (i32, [vp, vp, vp, vp, vp, vp]),
         "svmc_sweep_sym": (i32, [vp, i32, u64, u64, vp, vp]),
     }
     for name, (res, args) in proto.items():

@@ -244,16 +244,17 @@ class ScaleVMC:
         self._check(self.lib.svmc_sym_expand(self.h, occ.shape[0], _ptr(occ), _ptr(out), _stream()), "sym_expand")
         return out
 
-    def local_energy_sym(self):
+    def local_energy_sym(self, weights: bool = False):
         """(E_sym, sign, log|psi_sym|) [W / n_g] of the loaded symmetric batch
-        (svmc_local_energy_sym)."""
+        (svmc_local_energy_sym), and the copies' weights [W] if asked."""
         K = self.num_walkers // self._sym_n
         e = torch.empty(K, dtype=torch.float64, device=self.device)
         sg = torch.empty(K, dtype=torch.float64, device=self.device)
         la = torch.empty(K, dtype=torch.float64, device=self.device)
-        self._check(self.lib.svmc_local_energy_sym(self.h, _ptr(e), _ptr(sg), _ptr(la), _stream()),
+        wt = torch.empty(self.num_walkers, dtype=torch.float64, device=self.device) if weights else None
+        self._check(self.lib.svmc_local_energy_sym(self.h, _ptr(e), _ptr(sg), _ptr(la), _ptr(wt), _stream()),
                     "local_energy_sym")
-        return e, sg, la
+        return (e, sg, la, wt) if weights else (e, sg, la)
 
     def sweep_sym(self, n_sweeps: int, seed: int, step0: int):
         """Metropolis sweeps of |psi_sym|^2 (svmc_sweep_sym); accepted moves per copy."""

@@ -1036,7 +1036,8 @@ svmc_status svmc_sym_expand(svmc_ctx* ctx, int64_t W, const int8_t* occ, int8_t*
                   "symmetry expansion");
 }
 
-svmc_status svmc_local_energy_sym(svmc_ctx* ctx, double* eloc, double* sign, double* logabs, hipStream_t st) {
+svmc_status svmc_local_energy_sym(svmc_ctx* ctx, double* eloc, double* sign, double* logabs, double* weights,
+                                  hipStream_t st) {
   if (!ctx) return SVMC_ERR_INVALID_ARG;
   if (ctx->sym_n == 0) return ctx->fail(SVMC_ERR_STATE, "no symmetry group set");
   if (!ctx->have_walkers) return ctx->fail(SVMC_ERR_STATE, "no walkers loaded");
@@ -1051,7 +1052,8 @@ svmc_status svmc_local_energy_sym(svmc_ctx* ctx, double* eloc, double* sign, dou
   if ((s = svmc_log_psi(ctx, ctx->sym_s.as<double>(), ctx->sym_l.as<double>(), st))) return s;
   return ctx->hip(launch_sym_combine(ctx->ld[0], ctx->sym_n, ctx->sym_perm.as<int32_t>(), ctx->sym_flip.as<int32_t>(),
                                      ctx->sym_chi.as<double>(), ctx->bufs(), ctx->sym_e.as<double>(),
-                                     ctx->sym_s.as<double>(), ctx->sym_l.as<double>(), eloc, sign, logabs, st),
+                                     ctx->sym_s.as<double>(), ctx->sym_l.as<double>(), eloc, sign, logabs, weights,
+                                     st),
                   "symmetric local energy");
 }
 

@@ -52,7 +52,7 @@ hipError_t launch_sym_expand(int N, int nG, const int32_t* perm, const int32_t* 
                              int8_t* out, hipStream_t st);
 hipError_t launch_sym_combine(const LatDev& lt, int nG, const int32_t* perm, const int32_t* flip, const double* chi,
                               const Bufs& bf, const double* e, const double* sg, const double* la, double* eloc,
-                              double* sign_out, double* logabs_out, hipStream_t st);
+                              double* sign_out, double* logabs_out, double* wts, hipStream_t st);
 hipError_t launch_sym_signs(const LatDev& lt, int nG, const int32_t* perm, const int32_t* flip, const Bufs& bf,
                             double* pi, hipStream_t st);
 hipError_t launch_sym_draw(const LatDev& lt, int nG, const int32_t* perm, const int32_t* flip, const Bufs& bf,

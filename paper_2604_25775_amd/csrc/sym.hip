@@ -82,7 +82,7 @@ static __global__ __launch_bounds__(256) void k_sym_combine(LatDev lt, int nG, c
                                                             const double* __restrict__ e,
                                                             const double* __restrict__ sg,
                                                             const double* __restrict__ la, double* eloc,
-                                                            double* sign_out, double* logabs_out) {
+                                                            double* sign_out, double* logabs_out, double* wts) {
   const long long k = blockIdx.x;
   const int N = lt.N, tid = threadIdx.x;
   const long long w0 = lt.w0 + k * nG;               // global index of copy 0
@@ -101,11 +101,13 @@ static __global__ __launch_bounds__(256) void k_sym_combine(LatDev lt, int nG, c
     if (tid == 0) {
       bad |= !image || (bf.flags[w0 + g] & 8) != 0;
       const double s = sg[w0 + g];
+      double a = 0.0;
       if (s != 0.0) {
-        const double a = pi * chi[g] * s * exp(la[w0 + g] - lmax);
+        a = pi * chi[g] * s * exp(la[w0 + g] - lmax);
         acc_w += a;
         acc_e += a * e[w0 + g];
       }
+      if (wts) wts[w0 + g] = a;
     }
   }
   if (tid == 0) {
@@ -114,6 +116,9 @@ static __global__ __launch_bounds__(256) void k_sym_combine(LatDev lt, int nG, c
     eloc[k] = (bad || tot == 0.0) ? NAN : acc_e / tot;
     if (sign_out) sign_out[k] = bad ? NAN : (tot > 0.0 ? 1.0 : (tot < 0.0 ? -1.0 : 0.0));
     if (logabs_out) logabs_out[k] = bad ? NAN : (tot == 0.0 ? -INFINITY : lmax + log(fabs(tot)));
+    // w_g = Pi chi psi(g n) / psi_sym(n): d log|psi_sym| = sum_g w_g d log|psi(g n)|
+    if (wts)
+      for (int g = 0; g < nG; ++g) wts[w0 + g] = (bad || tot == 0.0) ? NAN : wts[w0 + g] / tot;
   }
 }
 
@@ -275,11 +280,11 @@ hipError_t launch_sym_decide(const LatDev& lt, int nG, const int32_t* perm, cons
 
 hipError_t launch_sym_combine(const LatDev& lt, int nG, const int32_t* perm, const int32_t* flip, const double* chi,
                               const Bufs& bf, const double* e, const double* sg, const double* la, double* eloc,
-                              double* sign_out, double* logabs_out, hipStream_t st) {
+                              double* sign_out, double* logabs_out, double* wts, hipStream_t st) {
   const long long K = lt.nw / nG;
   if (K == 0) return hipSuccess;
   hipLaunchKernelGGL(k_sym_combine, dim3((unsigned)K), dim3(256), 0, st, lt, nG, perm, flip, chi, bf, e, sg, la, eloc,
-                     sign_out, logabs_out);
+                     sign_out, logabs_out, wts);
   return hipGetLastError();
 }
 

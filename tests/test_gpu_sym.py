@@ -174,3 +174,34 @@ def test_sym_sampler_chain_matches_oracle(name, lat, gens, model):
     for k in range(len(occ)):
         e_ref = local_energy_sym(lat, params, new[k], G, chi, 0, model.act)
         assert abs(e[k] - e_ref) <= 1e-9 * max(1.0, abs(e_ref)), (k, e[k], e_ref)
+
+
+def test_sym_gradient_weights_match_finite_differences():
+    """d log|psi_sym| / d theta from svmc_grad_logpsi with the copies'
+    weights (vjp = w_g) against central differences of the oracle's plain
+    log|psi_sym| on a sample of parameters of every kind."""
+    from oracle.grad import pack, unpack
+    name, lat, gens, model = CASES[0]
+    G, chi = wl.symmetry_group(lat, gens)
+    occ = wl.random_occupations(lat, 2, seed=21)
+    ctx, params, _ = sym_ctx(lat, model, G, chi, occ, backflow=0.5)
+    _, _, _, wts = ctx.local_energy_sym(weights=True)
+    theta = pack(params)
+    rng = np.random.default_rng(4)
+    idx = np.unique(np.concatenate([rng.choice(theta.size, 60, replace=False), [0, theta.size - 1]]))
+    for k in range(len(occ)):
+        v = torch.zeros(ctx.num_walkers, dtype=torch.float64, device="cuda")
+        v[k * len(G):(k + 1) * len(G)] = wts[k * len(G):(k + 1) * len(G)]
+        g = ctx.grad_logpsi(v).cpu().numpy()
+        h = 1e-5
+        fd = np.empty(len(idx))
+        for n, j in enumerate(idx):
+            tp, tm = theta.copy(), theta.copy()
+            tp[j] += h
+            tm[j] -= h
+            fd[n] = (log_psi_sym(lat, unpack(tp, params), occ[k], G, chi, 0, model.act)[1]
+                     - log_psi_sym(lat, unpack(tm, params), occ[k], G, chi, 0, model.act)[1]) / (2 * h)
+        scale = max(1.0, float(np.max(np.abs(fd))))
+        err = float(np.max(np.abs(g[idx] - fd))) / scale
+        say(f"  walker {k}: gradient vs finite differences {err:.2e}")
+        assert err <= 1e-7
