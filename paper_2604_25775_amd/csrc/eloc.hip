@@ -139,7 +139,15 @@ __global__ __launch_bounds__(64 * ELOC_NW) __attribute__((amdgpu_waves_per_eu(SM
   // as a register it is held by every lane through the hop loop (and spilled
   // around the conv, one scratch store per hop)
   double* part_s = red + 7;
-  if (tid == 0) *part_s = 0.0;
+  // the hopping amplitudes t, t' and J/2 (an exchange) in LDS, read by
+  // thread 0 per hop: as values they stay live through the hop loop
+  double* amp_s = red + 1;
+  if (tid == 0) {
+    *part_s = 0.0;
+    amp_s[0] = lt.t;
+    amp_s[1] = lt.tp;
+    amp_s[2] = 0.5 * lt.J;
+  }
   bool nonfinite = false;
   if (!bad) {
     for (int hh = h0; hh < h1; ++hh) {
@@ -149,7 +157,7 @@ __global__ __launch_bounds__(64 * ELOC_NW) __attribute__((amdgpu_waves_per_eu(SM
       const Conn cn = conn_decode(lt, uniform_i(hops[hh]));
       const int sp = cn.sp;
       // the hop's amplitude waits in LDS for the end of the hop
-      if (tid == 0) misc[4] = conn_amp(lt, cn);
+      if (tid == 0) misc[4] = amp_s[cn.ex ? 2 : (cn.d < 4 ? 0 : 1)];
       const HopGeom g = hop_geom(lt, md.L, sp, cn.i, cn.d, cn.ex);
       int olx, owx, oly, owy;
       const AxisTab tab = axis_tab(g, md.L, lane);
