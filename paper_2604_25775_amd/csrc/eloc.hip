@@ -91,13 +91,16 @@ SVMC_DEV void eloc_block(long long b, int S, long long& w, int& slice) {
 // SMALL: the instance for one conv layer, whose update boxes hold at most
 // 4 x 4 sites, so at most 16 changed rows per spin: the row form always
 // applies, the column form and the registers of larger boxes are left out,
-// and more wavefronts fit per SIMD.  MLP: the instance for networks with
+// and more wavefronts fit per SIMD.  Its workgroups are one wavefront, which
+// evaluates a hop alone (conv tiles, both spins' change lists and row-form
+// matrices, both determinants): twice the hops in flight per CU, and no
+// barrier waits on another wavefront.  MLP: the instance for networks with
 // site-wise layers (the others do not carry that code).
 template <int P, int C, bool SMALL, bool MLP>
-__global__ __launch_bounds__(64 * ELOC_NW) __attribute__((amdgpu_waves_per_eu(SMALL ? 4 : 3))) void k_eloc_lowrank(
-    ModelDev md, const LatDev* __restrict__ lats, int nlats, Bufs bf, ElocOut out, long long Wtot) {
+__global__ __launch_bounds__(SMALL ? 64 : 64 * ELOC_NW) __attribute__((amdgpu_waves_per_eu(SMALL ? 4 : 3))) void
+k_eloc_lowrank(ModelDev md, const LatDev* __restrict__ lats, int nlats, Bufs bf, ElocOut out, long long Wtot) {
   typedef typename PrecT<P>::Tf Tf;
-  constexpr int NW = ELOC_NW, NTH = 64 * NW;
+  constexpr int NW = SMALL ? 1 : ELOC_NW, NTH = 64 * NW;
   extern __shared__ __attribute__((aligned(16))) char smem[];
   long long w;
   int slice;
@@ -163,74 +166,112 @@ __global__ __launch_bounds__(64 * ELOC_NW) __attribute__((amdgpu_waves_per_eu(SM
       const AxisTab tab = axis_tab(g, md.L, lane);
       hop_features<P, C, NW, SMALL ? 1 : 7, MLP>(md, lt, g, occ_s, featw, (Tf*)nullptr, scratch, hsc, tab, olx, owx,
                                                  oly, owy);
-      // wavefront wv: determinant of spin wv
-      int hpos;
-      const int K = hop_klist(lt, g, tab, occ_s, lab_s, wv, olx, owx, oly, owy, kl, hpos, lane);
-      const double* PTt = PTw + (long long)wv * nm * C;
-      // spin wv's moving electron (a hop: spin sp, i -> j; an exchange: both
-      // spins, the down electron j -> i) and the G row of its new site
-      const bool mv = wv == sp || cn.ex;
-      const double* Gj = Gw + ((long long)wv * N + (wv == sp ? g.j : g.i)) * nm;
-      // few changed rows in both spins: the row form (K x K, padded to 8 or
-      // 16) instead of the column form of size C + 1
-      const int Ko = hop_kcount(lt, g, tab, occ_s, 1 - wv, olx, owx, oly, owy, lane);
-      const int KM = uniform_i(max(K, Ko));
-      if (SMALL || KM <= out.row_form_max) {
-        const v4d racc = hop_det_row_build<C>(kl, K, (const typename DType<P>::type*)scratch, PTt, lane);
-        __syncthreads();    // both matrices built: their staging may overwrite D
-        double* rstage = (double*)scratch + wv * 16 * 17;
-        if (KM <= 8) hop_det_row_stage<8>(racc, kl, K, mv, hpos, Gj, rstage, lane);
-        else hop_det_row_stage<16>(racc, kl, K, mv, hpos, Gj, rstage, lane);
-        __syncthreads();
-        if (wv == 0) {
-          // both K x K determinants in wavefront 0, one matrix per half
-          auto pair = [&](auto ks) {
-            constexpr int KS = decltype(ks)::value;
-            const double* sr = (const double*)scratch + (lane >> 5) * 16 * 17 +
-                               ((lane & 31) < KS ? (lane & 31) : 0) * (KS + 1);
-            double a[KS];
+      if constexpr (SMALL) {
+        // one wavefront: both spins' change lists and row-form matrices
+        // (at most 16 rows each), then both determinants at once
+        int Kt[2], hp[2];
+        v4d racc[2];
 #pragma unroll
-            for (int c2 = 0; c2 < KS; ++c2) a[c2] = (lane & 31) < KS ? sr[c2] : 0.0;
-            __builtin_amdgcn_wave_barrier();
-            return lu_det_pair<KS>(a, lane);
-          };
-          const double dt = KM <= 8 ? pair(IntC<8>()) : pair(IntC<16>());
-          if ((lane & 31) == 0) misc[lane >> 5] = dt;
-          // (the one-layer instance cannot meet more than 16 rows; if a
-          // caller broke that, the ratio is flagged rather than wrong)
-          if (lane == 0) {
-            misc[2] = (SMALL && KM > 16) ? NAN : 1.0;
-            misc[3] = 1.0;
-          }
+        for (int q = 0; q < 2; ++q) Kt[q] = hop_klist(lt, g, tab, occ_s, lab_s, q, olx, owx, oly, owy, kl + q * KM, hp[q], lane);
+        const int KMx = uniform_i(max(Kt[0], Kt[1]));
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+          racc[q] = hop_det_row_build<C>(kl + q * KM, Kt[q], (const typename DType<P>::type*)scratch,
+                                         PTw + (long long)q * nm * C, lane);
+        __syncthreads();    // both matrices built: their staging may overwrite D
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          const bool mvq = q == sp || cn.ex;
+          const double* Gq = Gw + ((long long)q * N + (q == sp ? g.j : g.i)) * nm;
+          double* rstage = (double*)scratch + q * 16 * 17;
+          if (KMx <= 8) hop_det_row_stage<8>(racc[q], kl + q * KM, Kt[q], mvq, hp[q], Gq, rstage, lane);
+          else hop_det_row_stage<16>(racc[q], kl + q * KM, Kt[q], mvq, hp[q], Gq, rstage, lane);
         }
         __syncthreads();
-      } else if constexpr (!SMALL) {
-      v4d dacc[DetTiles<C>::I][DetTiles<C>::J];
-      hop_det_build<C>(kl, K, mv, hpos, (const typename DType<P>::type*)scratch, PTt, Gj, lane, dacc);
-      __syncthreads();      // both matrices built: their staging may overwrite D
-      double* stage = (double*)scratch + wv * (C + 1) * DetTiles<C>::RS;
-      hop_det_stage<C>(dacc, kl, K, mv, hpos, PTt, Gj, stage, lane);
-      // a moving spin's matrix is brought to C x C by one elimination step
-      if (mv) {
-        const double f = hop_det_reduce<C>(stage, lane);
-        if (lane == 0) misc[wv == sp ? 2 : 3] = f;
-      } else if (lane == 0) {
-        misc[3] = 1.0;
-      }
-      // each wavefront factors its own spin's C x C matrix (its own staging
-      // area: no barrier with the other wavefront), two lanes per row
-      {
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        const int r = lane >> 1;
-        const double* sr = stage + (r < C ? r : 0) * DetTiles<C>::RS + (lane & 1);
-        double a[C / 2];
+        auto pair = [&](auto ks) {
+          constexpr int KS = decltype(ks)::value;
+          const double* sr = (const double*)scratch + (lane >> 5) * 16 * 17 +
+                             ((lane & 31) < KS ? (lane & 31) : 0) * (KS + 1);
+          double a[KS];
 #pragma unroll
-        for (int j = 0; j < C / 2; ++j) a[j] = r < C ? sr[2 * j] : 0.0;
-        __builtin_amdgcn_wave_barrier();
-        const double dt = lu_det_split<C>(a, lane);
-        if (lane == 0) misc[wv] = dt;
-      }
-      __syncthreads();
+          for (int c2 = 0; c2 < KS; ++c2) a[c2] = (lane & 31) < KS ? sr[c2] : 0.0;
+          __builtin_amdgcn_wave_barrier();
+          return lu_det_pair<KS>(a, lane);
+        };
+        const double dt = KMx <= 8 ? pair(IntC<8>()) : pair(IntC<16>());
+        if ((lane & 31) == 0) misc[lane >> 5] = dt;
+        // (more than 16 rows cannot occur with one conv layer; if a caller
+        // broke that, the ratio is flagged rather than wrong)
+        if (lane == 0) {
+          misc[2] = KMx > 16 ? NAN : 1.0;
+          misc[3] = 1.0;
+        }
+        __syncthreads();
+      } else {
+        // wavefront wv: determinant of spin wv
+        int hpos;
+        const int K = hop_klist(lt, g, tab, occ_s, lab_s, wv, olx, owx, oly, owy, kl, hpos, lane);
+        const double* PTt = PTw + (long long)wv * nm * C;
+        // spin wv's moving electron (a hop: spin sp, i -> j; an exchange: both
+        // spins, the down electron j -> i) and the G row of its new site
+        const bool mv = wv == sp || cn.ex;
+        const double* Gj = Gw + ((long long)wv * N + (wv == sp ? g.j : g.i)) * nm;
+        // few changed rows in both spins: the row form (K x K, padded to 8 or
+        // 16) instead of the column form of size C + 1
+        const int Ko = hop_kcount(lt, g, tab, occ_s, 1 - wv, olx, owx, oly, owy, lane);
+        const int KM = uniform_i(max(K, Ko));
+        if (KM <= out.row_form_max) {
+          const v4d racc = hop_det_row_build<C>(kl, K, (const typename DType<P>::type*)scratch, PTt, lane);
+          __syncthreads();    // both matrices built: their staging may overwrite D
+          double* rstage = (double*)scratch + wv * 16 * 17;
+          if (KM <= 8) hop_det_row_stage<8>(racc, kl, K, mv, hpos, Gj, rstage, lane);
+          else hop_det_row_stage<16>(racc, kl, K, mv, hpos, Gj, rstage, lane);
+          __syncthreads();
+          if (wv == 0) {
+            // both K x K determinants in wavefront 0, one matrix per half
+            auto pair = [&](auto ks) {
+              constexpr int KS = decltype(ks)::value;
+              const double* sr = (const double*)scratch + (lane >> 5) * 16 * 17 +
+                                 ((lane & 31) < KS ? (lane & 31) : 0) * (KS + 1);
+              double a[KS];
+#pragma unroll
+              for (int c2 = 0; c2 < KS; ++c2) a[c2] = (lane & 31) < KS ? sr[c2] : 0.0;
+              __builtin_amdgcn_wave_barrier();
+              return lu_det_pair<KS>(a, lane);
+            };
+            const double dt = KM <= 8 ? pair(IntC<8>()) : pair(IntC<16>());
+            if ((lane & 31) == 0) misc[lane >> 5] = dt;
+            if (lane == 0) misc[2] = misc[3] = 1.0;
+          }
+          __syncthreads();
+        } else {
+          v4d dacc[DetTiles<C>::I][DetTiles<C>::J];
+          hop_det_build<C>(kl, K, mv, hpos, (const typename DType<P>::type*)scratch, PTt, Gj, lane, dacc);
+          __syncthreads();      // both matrices built: their staging may overwrite D
+          double* stage = (double*)scratch + wv * (C + 1) * DetTiles<C>::RS;
+          hop_det_stage<C>(dacc, kl, K, mv, hpos, PTt, Gj, stage, lane);
+          // a moving spin's matrix is brought to C x C by one elimination step
+          if (mv) {
+            const double f = hop_det_reduce<C>(stage, lane);
+            if (lane == 0) misc[wv == sp ? 2 : 3] = f;
+          } else if (lane == 0) {
+            misc[3] = 1.0;
+          }
+          // each wavefront factors its own spin's C x C matrix (its own staging
+          // area: no barrier with the other wavefront), two lanes per row
+          {
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            const int r = lane >> 1;
+            const double* sr = stage + (r < C ? r : 0) * DetTiles<C>::RS + (lane & 1);
+            double a[C / 2];
+#pragma unroll
+            for (int j = 0; j < C / 2; ++j) a[j] = r < C ? sr[2 * j] : 0.0;
+            __builtin_amdgcn_wave_barrier();
+            const double dt = lu_det_split<C>(a, lane);
+            if (lane == 0) misc[wv] = dt;
+          }
+          __syncthreads();
+        }
       }
       if (tid == 0) {
         // misc[2], misc[3]: the moving spins' reduction factors (1 where
@@ -274,7 +315,8 @@ static hipError_t eloc_impl(const ModelDev& md, const LatDev* lats_dev, int nlat
   hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
   if (e != hipSuccess) return e;
   const long long nblk = ((W + 7) / 8) * 8 * out.slices;
-  hipLaunchKernelGGL(kern, dim3((unsigned)nblk), dim3(64 * ELOC_NW), smem, st, md, lats_dev, nlats, bf, out, W);
+  hipLaunchKernelGGL(kern, dim3((unsigned)nblk), dim3(sm ? 64 : 64 * ELOC_NW), smem, st, md, lats_dev, nlats, bf, out,
+                     W);
   return hipGetLastError();
 }
 
