@@ -172,10 +172,12 @@ svmc_status svmc_log_psi(svmc_ctx* ctx, double* sign, double* logabs,
                          hipStream_t stream);
 
 /* Low-rank precompute for every walker from its current features and
- * inverses: orbital rows of all sites M_s, G_s = M_s Phi_s^-1 and
+ * inverses: G_s = M_s Phi_s^-1 for the orbital rows M_s of all sites and
  * P_s = W_s Phi_s^-1 (the factors of the determinant-lemma matrices,
- * Sec. II.C).  svmc_local_energy(LOWRANK) runs it by itself when walkers
- * changed since the last one; calling it explicitly always recomputes. */
+ * Sec. II.C), with M_s = base_s + b_s + H_L W_s taken apart
+ * (G_s = (base_s + b_s) Phi_s^-1 + H_L P_s), so M_s itself is not formed.
+ * svmc_local_energy(LOWRANK) runs it by itself when walkers changed since
+ * the last one; calling it explicitly always recomputes. */
 svmc_status svmc_prepare(svmc_ctx* ctx, hipStream_t stream);
 
 /* Local energies (Sec. II.A) with the Hubbard or t-J Hamiltonian (Sec. III).

@@ -449,16 +449,15 @@ static svmc_status rebuild_dets(svmc_ctx* ctx, hipStream_t st) {
   return SVMC_OK;
 }
 
-// Low-rank precompute: rows of every site from the current features, then
-// G = M Phi^-1 and P^T (inverses first rebuilt if moves made them stale).
+// Low-rank precompute: G = M Phi^-1 and P^T from the current features and
+// inverses (inverses first rebuilt if moves made them stale); the rows M of
+// every site are not formed (G = (base + b) Phi^-1 + H_L P).
 static svmc_status prepare(svmc_ctx* ctx, hipStream_t st) {
   svmc_status s;
   if (!ctx->dets_fresh && (s = rebuild_dets(ctx, st))) return s;
   const Bufs bf = ctx->bufs();
-  for (auto& lt : ctx->ld) {
-    if ((s = ctx->hip(launch_rows(ctx->prec, lt, bf, ctx->planes(), ctx->C, st), "rows"))) return s;
-    if ((s = ctx->hip(launch_gp(lt, bf, ctx->C, st), "G/P precompute"))) return s;
-  }
+  for (auto& lt : ctx->ld)
+    if ((s = ctx->hip(launch_gp(ctx->prec, lt, bf, ctx->planes(), ctx->C, st), "G/P precompute"))) return s;
   ctx->prepared = true;
   return SVMC_OK;
 }
@@ -725,7 +724,7 @@ static svmc_status refresh_list(svmc_ctx* ctx, const Bufs& bf, WalkerSel sel, in
     if ((s = ctx->hip(launch_drift(lt, bf, sel, st), "drift check")) ||
         (s = ctx->hip(launch_rows(ctx->prec, lt, bf, ctx->planes(), ctx->C, st, sel), "rows")) ||
         (s = ctx->hip(launch_gj(lt, bf, st, sel), "inverse")) ||
-        (s = ctx->hip(launch_gp(lt, bf, ctx->C, st, sel), "G/P precompute")) ||
+        (s = ctx->hip(launch_gp(ctx->prec, lt, bf, ctx->planes(), ctx->C, st, sel), "G/P precompute")) ||
         (s = ctx->hip(launch_clear_nacc(lt, bf, sel, st), "clear")))
       return s;
   }

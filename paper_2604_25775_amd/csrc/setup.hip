@@ -641,94 +641,185 @@ __global__ __launch_bounds__(256) void k_gj_big(LatDev lt, Bufs bf, WalkerSel se
   }
 }
 
-// G_s = M_s Y_s (rows 0..N-1 of the stacked left factor [M_s; W_s]) and
-// P_s^T = (W_s Y_s)^T (rows N..N+C-1), Y_s = Phi_s^-1, on the FP64 matrix
-// cores: one workgroup of four wavefronts per (walker, spin); a wavefront
-// task is a 32 x 32 output block (two row tiles by two column tiles, four
-// 16 x 16 x 4 accumulators), its operands read from global memory (L2), four
+// G_s = M_s Y_s and P_s = W_s Y_s (Y_s = Phi_s^-1) without the row buffer:
+// M_s = B_s + 1 b_s + H_L W_s, so G_s = (B_s + 1 b_s) Y_s + H_L P_s, a product
+// with inner dimension n_s + C whose left factor is the lattice's base
+// orbitals plus bias (shared by all walkers: L2-resident) and the walker's
+// final features.  On the FP64 matrix cores: one workgroup of four
+// wavefronts per (walker, spin); wavefront w takes the 32-column blocks
+// w, w + 4, ...: it first forms its block of P (C x 32, inner dimension n_s)
+// into LDS and into P^T, then every 32 x 32 block of G in that column range
+// (two row tiles by two column tiles, four 16 x 16 x 4 accumulators), four
 // k-steps at a time.  Columns m >= n_s are not written.
-SVMC_DEV void gp_one(const LatDev& lt, const Bufs& bf, int C, long long wl, int sp) {
+template <class Tf>
+SVMC_DEV void gp_one(const LatDev& lt, const Bufs& bf, int C, int planes, long long wl, int sp,
+                     double (*Ps)[32]) {
   const int N = lt.N, nm = lt.nmax;
   const int n = lt.n[sp];
   if (n == 0) return;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int lj = lane & 15, lk = lane >> 4;
-  const int rows = N + C;
-  const double* M = bf.M + lt.m_off + wl * 2LL * N * nm + (long long)sp * N * nm;
+  const Tf* H = (const Tf*)bf.feat + lt.feat_off + wl * (long long)planes * N * C + (long long)(planes - 1) * N * C;
   const double* W = lt.W + (long long)sp * C * nm;
+  const double* base = lt.base + (long long)sp * N * nm;
+  const double* bb = lt.b + sp * nm;
   const double* Y = bf.inv + lt.inv_off + wl * 2LL * nm * nm + (long long)sp * nm * nm;
   double* G = bf.G + lt.g_off + wl * 2LL * N * nm + (long long)sp * N * nm;
   double* PT = bf.PT + lt.pt_off + wl * 2LL * nm * C + (long long)sp * nm * C;
-  const int nbr = (rows + 31) / 32, nbc = (n + 31) / 32;
-  const bool vec = (nm & 1) == 0;          // rows of M and W start 16-byte aligned
-  for (int task = wave; task < nbr * nbc; task += 4) {
-    const int r0 = 32 * (task / nbc), c0 = 32 * (task % nbc);
-    // this lane's A rows (one per row tile) and B columns (one per column tile)
-    const double* arow[2];
-    bool aok[2], bok[2];
+  const int nbc = (n + 31) / 32;
+  const bool vec = (nm & 1) == 0;          // rows of B_s and W_s start 16-byte aligned
+  for (int cb = wave; cb < nbc; cb += 4) {
+    const int c0 = 32 * cb;
+    bool bok[2];
 #pragma unroll
-    for (int u = 0; u < 2; ++u) {
-      const int r = r0 + 16 * u + lj;
-      aok[u] = r < rows;
-      arow[u] = r < N ? M + (long long)r * nm : W + (long long)(aok[u] ? r - N : 0) * nm;
-      bok[u] = c0 + 16 * u + lj < n;
-    }
-    v4d acc[2][2];
-#pragma unroll
-    for (int u = 0; u < 2; ++u)
-#pragma unroll
-      for (int t = 0; t < 2; ++t) acc[u][t] = v4d{0.0, 0.0, 0.0, 0.0};
-    // k runs in blocks of 16; within a block lane group lk takes k = 4 lk + e
-    // in product e (any order of k is the same sum as long as A and B agree),
-    // so each lane reads four consecutive elements of its A row at once
-    for (int k0 = 0; k0 < n; k0 += 16) {
-      double a[2][4], b[4][2];
+    for (int u = 0; u < 2; ++u) bok[u] = c0 + 16 * u + lj < n;
+    // B operand over the orbital index: k = k0 + 4 lk + e in product e of a
+    // block of 16 (any order of k gives the same sum when A and B agree)
+    auto load_y = [&](int k0, double (&b)[4][2]) {
       const int ka = k0 + 4 * lk;
 #pragma unroll
+      for (int e = 0; e < 4; ++e)
+#pragma unroll
+        for (int t = 0; t < 2; ++t) b[e][t] = (ka + e < n && bok[t]) ? Y[(long long)(ka + e) * nm + c0 + 16 * t + lj] : 0.0;
+    };
+    auto load_row = [&](const double* row, bool ok, int k0, double (&a)[4]) {
+      const int ka = k0 + 4 * lk;
+      if (vec && ok && ka + 3 < n) {
+        const double2 x0 = *reinterpret_cast<const double2*>(row + ka);
+        const double2 x1 = *reinterpret_cast<const double2*>(row + ka + 2);
+        a[0] = x0.x; a[1] = x0.y; a[2] = x1.x; a[3] = x1.y;
+      } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) a[e] = (ok && ka + e < n) ? row[ka + e] : 0.0;
+      }
+    };
+    // ---- P block: rows c < C of W_s Y_s, columns c0 .. c0 + 31
+    {
+      v4d acc[2][2];
+#pragma unroll
+      for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int t = 0; t < 2; ++t) acc[u][t] = v4d{0.0, 0.0, 0.0, 0.0};
+      bool aok[2];
+      const double* arow[2];
+#pragma unroll
       for (int u = 0; u < 2; ++u) {
-        if (vec && aok[u] && ka + 3 < n) {
-          const double2 x0 = *reinterpret_cast<const double2*>(arow[u] + ka);
-          const double2 x1 = *reinterpret_cast<const double2*>(arow[u] + ka + 2);
-          a[u][0] = x0.x; a[u][1] = x0.y; a[u][2] = x1.x; a[u][3] = x1.y;
-        } else {
+        aok[u] = 16 * u + lj < C;
+        arow[u] = W + (long long)(aok[u] ? 16 * u + lj : 0) * nm;
+      }
+      for (int k0 = 0; k0 < n; k0 += 16) {
+        double a[2][4], b[4][2];
 #pragma unroll
-          for (int e = 0; e < 4; ++e) a[u][e] = (aok[u] && ka + e < n) ? arow[u][ka + e] : 0.0;
-        }
+        for (int u = 0; u < 2; ++u) load_row(arow[u], aok[u], k0, a[u]);
+        load_y(k0, b);
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+#pragma unroll
+          for (int u = 0; u < 2; ++u)
+#pragma unroll
+            for (int t = 0; t < 2; ++t) mfma(acc[u][t], a[u][e], b[e][t]);
       }
 #pragma unroll
-      for (int e = 0; e < 4; ++e)
+      for (int u = 0; u < 2; ++u)
 #pragma unroll
-        for (int t = 0; t < 2; ++t)
-          b[e][t] = (ka + e < n && bok[t]) ? Y[(long long)(ka + e) * nm + c0 + 16 * t + lj] : 0.0;
+        for (int t = 0; t < 2; ++t) {
+          const int m = c0 + 16 * t + lj;
 #pragma unroll
-      for (int e = 0; e < 4; ++e)
-#pragma unroll
-        for (int u = 0; u < 2; ++u)
-#pragma unroll
-          for (int t = 0; t < 2; ++t) mfma(acc[u][t], a[u][e], b[e][t]);
+          for (int v = 0; v < 4; ++v) {
+            const int c = 16 * u + lk + 4 * v;
+            if (c < C) {
+              Ps[c][16 * t + lj] = m < n ? acc[u][t][v] : 0.0;
+              if (m < n) PT[(long long)m * C + c] = acc[u][t][v];
+            }
+          }
+        }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
+    // ---- G blocks in this column range: (B_s + 1 b_s) Y_s + H_L P_s, 32
+    // rows at a time (two row tiles share each B fragment; four would spill
+    // at this register budget)
+    constexpr int RT = 2;
+    for (int r0 = 0; r0 < N; r0 += 16 * RT) {
+      bool aok[RT];
+      const double* arow[RT];
 #pragma unroll
-    for (int u = 0; u < 2; ++u)
-#pragma unroll
-      for (int t = 0; t < 2; ++t) {
-        const int c = c0 + 16 * t + lj;
-        if (c >= n) continue;
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int r = r0 + 16 * u + lk + 4 * v;
-          if (r < N) G[(long long)r * nm + c] = acc[u][t][v];
-          else if (r < rows) PT[(long long)c * C + (r - N)] = acc[u][t][v];
-        }
+      for (int u = 0; u < RT; ++u) {
+        const int r = r0 + 16 * u + lj;
+        aok[u] = r < N;
+        arow[u] = base + (long long)(aok[u] ? r : 0) * nm;
       }
+      v4d acc[RT][2];
+#pragma unroll
+      for (int u = 0; u < RT; ++u)
+#pragma unroll
+        for (int t = 0; t < 2; ++t) acc[u][t] = v4d{0.0, 0.0, 0.0, 0.0};
+      for (int k0 = 0; k0 < n; k0 += 16) {
+        double a[RT][4], b[4][2], bk[4];
+        const int ka = k0 + 4 * lk;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) bk[e] = ka + e < n ? bb[ka + e] : 0.0;
+#pragma unroll
+        for (int u = 0; u < RT; ++u) {
+          load_row(arow[u], aok[u], k0, a[u]);
+#pragma unroll
+          for (int e = 0; e < 4; ++e) a[u][e] = aok[u] ? a[u][e] + bk[e] : 0.0;
+        }
+        load_y(k0, b);
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+#pragma unroll
+          for (int u = 0; u < RT; ++u)
+#pragma unroll
+            for (int t = 0; t < 2; ++t) mfma(acc[u][t], a[u][e], b[e][t]);
+      }
+      // the features' part: inner index c over the channels, four at a time
+      for (int q = 0; 4 * q < C; ++q) {
+        const int c = 4 * q + lk;
+        double a[RT], b[2];
+#pragma unroll
+        for (int u = 0; u < RT; ++u) {
+          const int r = r0 + 16 * u + lj;
+          a[u] = (r < N && c < C) ? (double)H[(long long)r * C + c] : 0.0;
+        }
+#pragma unroll
+        for (int t = 0; t < 2; ++t) b[t] = c < C ? Ps[c][16 * t + lj] : 0.0;
+#pragma unroll
+        for (int u = 0; u < RT; ++u)
+#pragma unroll
+          for (int t = 0; t < 2; ++t) mfma(acc[u][t], a[u], b[t]);
+      }
+#pragma unroll
+      for (int u = 0; u < RT; ++u)
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+          const int m = c0 + 16 * t + lj;
+          if (m >= n) continue;
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int r = r0 + 16 * u + lk + 4 * v;
+            if (r < N) G[(long long)r * nm + m] = acc[u][t][v];
+          }
+        }
+    }
+    // this wavefront's P block is read by no one else; the next column
+    // block overwrites it only after every read above
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
 }
-__global__ __launch_bounds__(256) void k_gp(LatDev lt, Bufs bf, int C, WalkerSel sel) {
+template <class Tf>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_gp(LatDev lt, Bufs bf, int C, int planes,
+                                                                                 WalkerSel sel) {
+  __shared__ double ps[4][32][32];               // each wavefront's block of P
   const int sp = blockIdx.y;
   for (long long z = blockIdx.x;; z += gridDim.x) {
     long long wl;
     const int r = pick_walker(sel, lt, z, wl);    // uniform in the block
     if (r == 0) break;
-    if (r == 1) gp_one(lt, bf, C, wl, sp);
+    if (r == 1) gp_one<Tf>(lt, bf, C, planes, wl, sp, ps[threadIdx.x >> 6]);
   }
 }
 
@@ -804,10 +895,12 @@ hipError_t launch_gj(const LatDev& lt, const Bufs& bf, hipStream_t st, WalkerSel
   return hipGetLastError();
 }
 
-hipError_t launch_gp(const LatDev& lt, const Bufs& bf, int C, hipStream_t st, WalkerSel sel) {
+hipError_t launch_gp(int prec, const LatDev& lt, const Bufs& bf, int planes, int C, hipStream_t st, WalkerSel sel) {
   if (lt.nw == 0) return hipSuccess;
+  if (C > 32) return hipErrorInvalidValue;
   const dim3 grid((unsigned)walker_slots(lt, sel, 256), 2);
-  hipLaunchKernelGGL(k_gp, grid, dim3(256), 0, st, lt, bf, C, sel);
+  if (prec == PREC_F64) hipLaunchKernelGGL(k_gp<double>, grid, dim3(256), 0, st, lt, bf, C, planes, sel);
+  else hipLaunchKernelGGL(k_gp<float>, grid, dim3(256), 0, st, lt, bf, C, planes, sel);
   return hipGetLastError();
 }
 

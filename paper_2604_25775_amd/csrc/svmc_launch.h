@@ -42,7 +42,7 @@ SVMC_DEV int pick_walker(const WalkerSel& s, const LatDev& lt, long long z, long
 hipError_t launch_rows(int prec, const LatDev& lt, const Bufs& bf, int planes, int C, hipStream_t st,
                        WalkerSel sel = WalkerSel{nullptr, nullptr});
 hipError_t launch_gj(const LatDev& lt, const Bufs& bf, hipStream_t st, WalkerSel sel = WalkerSel{nullptr, nullptr});
-hipError_t launch_gp(const LatDev& lt, const Bufs& bf, int C, hipStream_t st,
+hipError_t launch_gp(int prec, const LatDev& lt, const Bufs& bf, int planes, int C, hipStream_t st,
                      WalkerSel sel = WalkerSel{nullptr, nullptr});
 hipError_t launch_logpsi(const LatDev& lt, const Bufs& bf, double* sign, double* logabs, hipStream_t st);
 
