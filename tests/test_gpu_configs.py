@@ -5,6 +5,14 @@ name, at their full sizes, in the launch configuration the benchmark times.
   FP64, 256 walkers x 20 Metropolis sweeps of 16 proposals: the chains
   (occupations, electron positions, accept counts) bit-exact with the
   oracle's sampler, then every walker's E_loc and hop ratios at 1e-10.
+* 8x8 periodic, t' = -0.2, U = 8, 28 + 28, 4 layers x 16 channels, FP32
+  conv, 4096 walkers after the workload's 8 thermalising sweeps: the
+  low-rank E_loc of every walker equal to the full-recompute path's to 1e-5
+  (both use the same FP32 conv; they differ by the FP32 rounding of the
+  low-rank path's feature differences, 2^-24 relative per element), and 16
+  walkers spread over the batch against the FP64 oracle (E_loc 1e-4, hop
+  ratios 1e-3, log|psi| 1e-6). Here the layer-4 box covers the whole
+  lattice, so every ratio takes the column form of the determinant lemma.
 * 16x16 periodic-x / open-y, 112 + 112, 4 layers x 32 channels, the
   benchmark's f16x2 conv mode and parameters, 8192 walkers after the
   benchmark's 8 thermalising sweeps, at the slice count the autotuner picks:
@@ -78,6 +86,30 @@ def test_c1_256_walkers_20_sweeps_fp64_bit_exact():
     say(f"  chains bit-exact; accept rate {n_acc.sum() / (W * ns * lat.N):.3f}")
     assert not ctx.flags().cpu().numpy().any()
     compare_sampled(ctx, lat, params, o2, range(W), model, 1e-10, 1e-10, 1e-10)
+
+
+def test_c2_fp32_4096_lowrank_vs_full_and_oracle():
+    w = wl.get("c2")
+    lat = w.lattices[0]
+    model = w.model
+    W = w.walkers[0]
+    say(f"[c2] 8x8 t'=-0.2 FP32 conv, {W} walkers, {w.sweeps} sweeps")
+    occ = wl.occupations(w, 0, n_walkers=W)
+    ctx, params, _ = build([lat], model, [W], occ_list=[occ])
+    nacc = ctx.sweep(w.sweeps, w.seed_mc, 0)
+    torch.cuda.synchronize()
+    say(f"  accept rate {float(nacc.double().mean()) / (w.sweeps * lat.N):.3f}")
+    o, _ = ctx.state()
+    occ = o.cpu().numpy().reshape(W, lat.N)
+    assert not (ctx.flags().cpu().numpy() & (1 | 2 | 8)).any()
+    e_low = ctx.local_energy("lowrank").cpu().numpy()
+    e_full = ctx.local_energy("full").cpu().numpy()
+    assert np.isfinite(e_low).all() and np.isfinite(e_full).all()
+    d = np.abs(e_full - e_low) / np.maximum(1.0, np.abs(e_low))
+    say(f"  low-rank vs full-recompute, all {W} walkers: max {d.max():.2e}")
+    assert d.max() <= 1e-5
+    sample = [int(k) for k in np.linspace(0, W - 1, 16)]
+    compare_sampled(ctx, lat, params, occ, sample, model, 1e-3, 1e-4, 1e-6)
 
 
 def test_c3_f16x2_bench_mode_8192_after_sweeps_tuned():
