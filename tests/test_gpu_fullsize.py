@@ -11,6 +11,10 @@ the oracle evaluates one by one, plus properties checked on every walker.
   workload's 8 thermalising sweeps: sampled walkers of every lattice against
   the oracle (every ratio 1e-3, E_loc 1e-4), and the gradient rows of those
   walkers against the oracle's autograd gradient.
+* The same three lattices and network shape in FP64, two walkers each in
+  one batch: the library's gradient rows against central differences of
+  the library's own log|psi| (parameters moved by +-h, the context reloaded)
+  on parameters of every kind, no oracle involved.
 """
 import numpy as np
 import pytest
@@ -84,3 +88,42 @@ def test_mixed_lattices_2048_each_with_gradient():
         say(f"  gradient lattice {li}: max err / scale {err:.2e}")
         assert err <= 2e-5
         w0 += counts[li]
+
+
+def test_c4_lattices_gradient_by_finite_differences_of_the_library():
+    from oracle.grad import pack, unpack
+    w = wl.get("c4")
+    lats = w.lattices
+    model = wl.Model(4, 24, "tanh", "f64")
+    counts = [2] * len(lats)
+    say("[fullsize] mixed 8x8/12x12/16x8, 4 x 24 FP64: gradient vs central differences")
+    occs = [wl.occupations(w, li, n_walkers=c) for li, c in enumerate(counts)]
+    ctx, params, _ = build(lats, model, counts, occ_list=occs, backflow=0.5)
+    flat = np.concatenate([o.reshape(-1) for o in occs]).astype(np.int8)
+    J = ctx.grad_logpsi().cpu().numpy()
+    theta = pack(params)
+    assert J.shape == (sum(counts), theta.size)
+    rng = np.random.default_rng(5)
+    # every kind of parameter: embedding, conv kernels and biases, each
+    # lattice's projection (the tail of the vector), plus random indices
+    n_conv = params.conv_w.size + params.conv_b.size
+    idx = np.unique(np.concatenate([[0, params.embed.size, params.embed.size + params.conv_w.size,
+                                     params.embed.size + n_conv, theta.size - 1],
+                                    rng.choice(theta.size, 40, replace=False)]))
+    h = 1e-5
+    fd = np.empty((sum(counts), len(idx)))
+    for n, j in enumerate(idx):
+        la = []
+        for dh in (h, -h):
+            tp = theta.copy()
+            tp[j] += dh
+            ctx.set_params_from(unpack(tp, params))
+            ctx.load(counts, flat)
+            la.append(ctx.log_psi()[1].cpu().numpy())
+        fd[:, n] = (la[0] - la[1]) / (2 * h)
+    ctx.set_params_from(params)
+    for k in range(sum(counts)):
+        scale = max(1.0, float(np.max(np.abs(fd[k]))))
+        err = float(np.max(np.abs(J[k, idx] - fd[k]))) / scale
+        say(f"  walker {k}: max |J - FD| / scale {err:.2e}")
+        assert err <= 1e-6
