@@ -77,6 +77,9 @@ def to_occ(lat, b):
     wl.Lattice(2, 4, 0, 1, 1.0, 0.0, 4.0, 3, 2),
     wl.Lattice(2, 4, 0, 1, 1.0, 0.3, 6.0, 2, 2),
     wl.Lattice(3, 3, 1, 1, 1.0, -0.25, 4.0, 2, 2),
+    # spin-polarised sectors: the empty spin's determinant is 1
+    wl.Lattice(2, 4, 0, 1, 1.0, 0.3, 6.0, 3, 0),
+    wl.Lattice(3, 3, 1, 1, 1.0, -0.25, 4.0, 0, 3),
 ])
 def test_local_energy_equals_h_psi(lat):
     p = wl.random_params([lat], wl.Model(2, 4), seed=5, backflow=0.5)
@@ -89,15 +92,20 @@ def test_local_energy_equals_h_psi(lat):
         psi[k] = s * np.exp(la)
     Hpsi = H @ psi
     scale = np.max(np.abs(psi))
-    # every configuration for the smallest sector, a seeded subset otherwise
+    # every configuration for the smallest sector, a seeded subset otherwise;
+    # E_loc is undefined on exact nodes (psi = 0, which the symmetric
+    # polarised sectors have), where they carry no weight either
     rng = np.random.default_rng(0)
+    nodes = {k for k in range(len(states)) if psi[k] == 0.0}
+    assert len(nodes) < len(states) // 2
     pick = range(len(states)) if len(states) <= 800 else rng.choice(len(states), 400, replace=False)
+    pick = [k for k in pick if k not in nodes]
     eloc = {}
     for k in pick:
         e = local_energy(lat, p, to_occ(lat, states[k]))
         eloc[k] = e
         assert e * psi[k] == pytest.approx(Hpsi[k], abs=1e-11 * scale * (1 + abs(e)))
-    if len(eloc) == len(states):
+    if len(eloc) + len(nodes) == len(states):
         w = psi ** 2
         e_var = sum(w[k] * eloc[k] for k in eloc) / w.sum()
         assert e_var == pytest.approx(psi @ Hpsi / (psi @ psi), rel=1e-12)

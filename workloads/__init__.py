@@ -207,6 +207,8 @@ def plane_wave_orbitals(lat: Lattice, n: int) -> np.ndarray:
     for e, kx, ky, fx, fy in cand[:n]:
         # site s = x + Lx*y  ->  outer(fy, fx).ravel()
         cols.append(np.outer(fy, fx).reshape(-1))
+    if not cols:                               # a spin without electrons
+        return np.zeros((lat.N, 0))
     return np.stack(cols, axis=1)
 
 
