@@ -11,6 +11,13 @@ block of label columns.
   walkers: the oracle evaluates log|psi| and a sample of hop ratios of
   sampled walkers (a full E_loc there costs it minutes); E_loc of every
   walker must equal U * doubles - t * sum of its own reported ratios.
+* The per-spin limit of the library, 512 + 512 at half filling on a 32x32
+  torus, FP64 (2 layers x 8 channels): log|psi| and E_loc at 1e-10 and
+  every hop ratio at 1e-9 of one walker against the oracle (its hops spread over host
+  processes); after one sweep of two walkers the maintained state (G and P
+  by Woodbury over four column blocks, log|psi| by ratio products) equals a
+  context loaded fresh from the new configurations; 513 electrons of one
+  spin are refused.
 """
 import numpy as np
 import pytest
@@ -26,6 +33,7 @@ from oracle.ansatz import log_psi  # noqa: E402
 from oracle.energy import jw_sign  # noqa: E402
 from oracle.lattice import apply_hop, hops  # noqa: E402
 from oracle.sampler import initial_labels, metropolis  # noqa: E402
+from oracle_par import local_energies  # noqa: E402
 
 SEED = 424242
 
@@ -105,3 +113,45 @@ def test_32x32_448_full_batch_sampled():
     say(f"  sweep: accept rate {n_acc.mean() / lat.N:.3f}, flags {int(np.count_nonzero(f))}")
     assert not (f & (1 | 2 | 8)).any()
     assert n_acc.sum() > 0
+
+
+def test_512_electrons_per_spin_limit():
+    from paper_2604_25775_amd._lib import SvmcError
+    from paper_2604_25775_amd.api import ScaleVMC
+    lat = wl.Lattice(32, 32, 1, 1, 1.0, 0.0, 4.0, 512, 512)
+    model = wl.Model(2, 8, "tanh", "f64", 32)
+    say("[big] 32x32 512+512 FP64 (the per-spin limit)")
+    occ = wl.random_occupations(lat, 2, seed=17)
+    ctx, params, _ = build([lat], model, [2], occ_list=[occ], backflow=0.3)
+    assert not ctx.flags().cpu().numpy().any()
+    eloc, nh, code, rat = (t.cpu().numpy() for t in ctx.local_energy(ratios=True))
+    sign, la = (t.cpu().numpy() for t in ctx.log_psi())
+    e_ref, hs, R_ref, (s_ref, l_ref) = local_energies(lat, params, [occ[0]], 0, model.act)[0]
+    assert sign[0] == s_ref
+    assert abs(la[0] - l_ref) <= 1e-10 * max(1.0, abs(l_ref)), (la[0], l_ref)
+    assert nh[0] == len(hs)
+    assert list(code[0, :len(hs)]) == [hop_code(h, lat.N) for h in hs]
+    floor = 1e-3 * np.sqrt(np.mean(R_ref ** 2))
+    err = max(abs(r - rr) / max(abs(rr), floor) for r, rr in zip(rat[0, :len(hs)], R_ref))
+    # the FP64 bound of the smaller cases, widened for 512-row eliminations
+    # on both sides (rounding grows with the order; measured 8.5e-11)
+    assert err <= 1e-9, err
+    assert abs(eloc[0] - e_ref) <= 1e-10 * max(1.0, abs(e_ref)), (eloc[0], e_ref)
+    say(f"  walker 0: {len(hs)} ratios (max err {err:.1e}), E_loc and log|psi| agree")
+    n_acc = ctx.sweep(1, SEED, 0).cpu().numpy()
+    assert n_acc.sum() > 0
+    assert not (ctx.flags().cpu().numpy() & (1 | 2 | 8)).any()
+    o, _ = ctx.state()
+    o = o.cpu().numpy().reshape(2, lat.N)
+    e1 = ctx.local_energy().cpu().numpy()
+    s1, l1 = (t.cpu().numpy() for t in ctx.log_psi())
+    ctx2, _, _ = build([lat], model, [2], occ_list=[o], backflow=0.3)
+    e2 = ctx2.local_energy().cpu().numpy()
+    s2, l2 = (t.cpu().numpy() for t in ctx2.log_psi())
+    assert np.array_equal(s1, s2)
+    assert np.max(np.abs(l1 - l2) / np.maximum(1.0, np.abs(l2))) <= 1e-10
+    assert np.max(np.abs(e1 - e2) / np.maximum(1.0, np.abs(e2))) <= 1e-9
+    say(f"  sweep: accepted {n_acc.tolist()}, maintained state equals a fresh load")
+    with pytest.raises(SvmcError) as err:
+        ScaleVMC([wl.Lattice(32, 32, 1, 1, 1.0, 0.0, 4.0, 513, 511)], 2, 8)
+    assert err.value.status == 5                  # SVMC_ERR_UNSUPPORTED
