@@ -282,29 +282,54 @@ __global__ __launch_bounds__(256) void k_grad(const LatDev* __restrict__ lats, i
       }
     }
     __syncthreads();
-    // (2) dK[t][ci][co] = sum_s H_{l-1}[nb(s, t)][ci] dz[s][co]: per tap, tiles of
-    // 16 inputs x 16 outputs, K over the sites
+    // (2) dK[t][ci][co] = sum_s H_{l-1}[nb(s, t)][ci] dz[s][co]: tiles of 16
+    // inputs x 16 outputs, K over the sites.  A wavefront holds the tiles of
+    // all taps of its group (every tap when there are at least as many tiles
+    // as wavefronts), so each block of dz is read once per group rather than
+    // once per tap; each tap's accumulator takes the same products in the
+    // same order as in a loop over single taps.
     double* dK = row + ga.off_convw + (long long)(l - 1) * 9 * C * C;
-    for (int tt = wave; tt < 9 * nct * nct; tt += NTH / 64) {
-      const int t = tt / (nct * nct), r2 = tt - t * nct * nct, tci = r2 / nct, tco = r2 - tci * nct;
-      const int ci = 16 * tci + lj, co = 16 * tco + lj;
-      v4d acc = v4d{0.0, 0.0, 0.0, 0.0};
-      for (int s0 = 0; s0 < N; s0 += 16) {
-        double a[4], b[4];                          // four k-steps' operands in flight
+    {
+      const int ntl = nct * nct;
+      const int tg = ntl >= NTH / 64 ? 1 : (NTH / 64) / ntl;      // tap groups per tile
+      const int gs = (9 + tg - 1) / tg;                            // taps per group
+      for (int it = wave; it < ntl * tg; it += NTH / 64) {
+        const int r2 = it / tg, g = it - r2 * tg, tci = r2 / nct, tco = r2 - tci * nct;
+        const int t0 = g * gs, t1 = min(9, t0 + gs);
+        const int ci = 16 * tci + lj, co = 16 * tco + lj;
+        v4d acc[9];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int sk = s0 + 4 * u + lk;
-          const int nb = sk < N ? nbt[t * N + sk] : -1;
-          a[u] = (nb >= 0 && ci < C) ? hp[nb * C + ci] : 0.0;
-          b[u] = (sk < N && co < C) ? dz[sk * C + co] : 0.0;
+        for (int t = 0; t < 9; ++t) acc[t] = v4d{0.0, 0.0, 0.0, 0.0};
+        for (int s0 = 0; s0 < N; s0 += 16) {
+          double b[4];                              // this block of dz, shared by the taps
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int sk = s0 + 4 * u + lk;
+            b[u] = (sk < N && co < C) ? dz[sk * C + co] : 0.0;
+          }
+#pragma unroll
+          for (int t = 0; t < 9; ++t) {
+            if (t < t0 || t >= t1) continue;      // uniform
+            double a[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              const int sk = s0 + 4 * u + lk;
+              const int nb = sk < N ? nbt[t * N + sk] : -1;
+              a[u] = (nb >= 0 && ci < C) ? hp[nb * C + ci] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) mfma(acc[t], a[u], b[u]);
+          }
         }
 #pragma unroll
-        for (int u = 0; u < 4; ++u) mfma(acc, a[u], b[u]);
-      }
+        for (int t = 0; t < 9; ++t) {
+          if (t < t0 || t >= t1) continue;
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int cio = 16 * tci + lk + 4 * v;
-        if (cio < C && co < C) dK[((long long)t * C + cio) * C + co] = acc[v];
+          for (int v = 0; v < 4; ++v) {
+            const int cio = 16 * tci + lk + 4 * v;
+            if (cio < C && co < C) dK[((long long)t * C + cio) * C + co] = acc[t][v];
+          }
+        }
       }
     }
     {
