@@ -24,8 +24,9 @@
 //
 // One workgroup per walker: H_{l-1} of the walker lives in LDS when N C
 // doubles fit (two workgroups per CU at 16x16, C = 32), else in a global
-// scratch; dz and dH are global scratch (L2-resident); the
-// site neighbours per tap are a table in LDS.  dW and the three products of
+// scratch; dz and dH are global scratch (per walker 2 N C doubles, which do
+// not stay in L2 with hundreds of walkers in flight: their re-reads bound the
+// kernel); the site neighbours per tap are a table in LDS.  dW and the three products of
 // each layer (z, dK, the transposed conv) run on the FP64 matrix cores
 // (16 x 16 x 4 tiles); the sums over sites for db, db_l and dE are spread
 // over the workgroup and combined in LDS.
