@@ -10,6 +10,12 @@
   1e-10.
 * An empty batch is refused by the library with an error, before any
   kernel runs.
+* The site limits of the 16-bit connection codes: a 64x64 Hubbard torus
+  with t' (4096 sites, hop codes up to (4095 << 4) | 15) and a 64x32 t-J
+  cylinder (2048 sites, exchange codes up to ((2048 + 2047) << 4) | 3), 40 +
+  40 electrons, FP64: every code, ratio, E_loc and log|psi| of a walker at
+  1e-10 against the oracle (its connections spread over host processes),
+  and after one sweep the maintained state equal to a fresh load.
 """
 import numpy as np
 import pytest
@@ -96,3 +102,52 @@ def test_empty_batch_refused():
     # argument, else as "no walkers"; either way an invalid argument)
     with pytest.raises(SvmcError, match="invalid argument"):
         ctx.load([0], np.zeros(0, dtype=np.int8))
+
+
+@pytest.mark.parametrize("lat", [
+    wl.Lattice(64, 64, 1, 1, 1.0, -0.2, 4.0, 40, 40),
+    wl.Lattice(64, 32, 0, 1, 1.0, 0.2, 0.0, 40, 40, tj=1, J=1.0 / 3.0, h_pin=0.5),
+], ids=["hubbard_64x64", "tj_64x32"])
+def test_connection_code_site_limits(lat):
+    from gpu_util import hop_code
+    from oracle_par import local_energies
+    model = wl.Model(1, 8, "tanh", "f64", 32)
+    say(f"[edge] {lat.Lx}x{lat.Ly} {'t-J' if lat.tj else 'Hubbard'} {lat.n_up}+{lat.n_dn}: codes at the 16-bit limit")
+    # a walker with electrons on the last sites, so the largest codes occur
+    occ = wl.random_occupations(lat, 2, seed=8)
+    for o in occ:
+        for sp, bit in ((0, 1), (1, 2)):
+            if not (o[lat.N - 1 - sp] & bit):
+                k = np.nonzero((o & bit) != 0)[0][0]
+                if lat.tj and o[lat.N - 1 - sp] != 0:
+                    continue
+                o[k] &= ~bit
+                o[lat.N - 1 - sp] |= bit
+    ctx, params, _ = build([lat], model, [2], occ_list=[occ], backflow=0.3)
+    assert not ctx.flags().cpu().numpy().any()
+    eloc, nh, code, rat = (t.cpu().numpy() for t in ctx.local_energy(ratios=True))
+    sign, la = (t.cpu().numpy() for t in ctx.log_psi())
+    e_ref, cs, R_ref, (s_ref, l_ref) = local_energies(lat, params, [occ[0]], 0, model.act)[0]
+    assert sign[0] == s_ref
+    assert abs(la[0] - l_ref) <= 1e-10 * max(1.0, abs(l_ref))
+    codes = [hop_code(c, lat.N) for c in cs]
+    assert nh[0] == len(cs) and list(code[0, :len(cs)]) == codes
+    assert max(codes) >= (((2 * lat.N if lat.tj else lat.N) - 64) << 4)
+    floor = 1e-3 * np.sqrt(np.mean(R_ref ** 2))
+    err = max(abs(r - rr) / max(abs(rr), floor) for r, rr in zip(rat[0, :len(cs)], R_ref))
+    assert err <= 1e-10, err
+    assert abs(eloc[0] - e_ref) <= 1e-10 * max(1.0, abs(e_ref))
+    say(f"  {len(cs)} connections (largest code {max(codes)}), max ratio err {err:.1e}")
+    n_acc = ctx.sweep(1, SEED, 0).cpu().numpy()
+    assert n_acc.sum() > 0
+    assert not (ctx.flags().cpu().numpy() & (1 | 2 | 8)).any()
+    o, _ = ctx.state()
+    o = o.cpu().numpy().reshape(2, lat.N)
+    e1 = ctx.local_energy().cpu().numpy()
+    l1 = ctx.log_psi()[1].cpu().numpy()
+    ctx2, _, _ = build([lat], model, [2], occ_list=[o], backflow=0.3)
+    e2 = ctx2.local_energy().cpu().numpy()
+    l2 = ctx2.log_psi()[1].cpu().numpy()
+    assert np.max(np.abs(l1 - l2) / np.maximum(1.0, np.abs(l2))) <= 1e-10
+    assert np.max(np.abs(e1 - e2) / np.maximum(1.0, np.abs(e2))) <= 1e-9
+    say(f"  sweep: accepted {n_acc.tolist()}, maintained state equals a fresh load")
