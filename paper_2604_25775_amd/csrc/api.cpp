@@ -374,7 +374,9 @@ svmc_status svmc_set_params(svmc_ctx* ctx, const double* theta, const double* co
   std::vector<double> gmw((size_t)std::max(NM, 1) * C * C, 0.0), gmb((size_t)std::max(NM, 1) * C, 0.0);
   for (long long k = 0; k < (long long)NM * C * C; ++k) gmw[k] = rnd_w(MW[k]);
   for (long long k = 0; k < (long long)NM * C; ++k) gmb[k] = rnd(MB[k]);
-  if ((s = ctx->hip(ctx->gMW.ensure(gmw.size() * 8), "alloc")) || (s = ctx->hip(ctx->gMB.ensure(gmb.size() * 8), "alloc")) ||
+  // (read by the gradient in runs of 8 doubles, like the conv weights: slack)
+  if ((s = ctx->hip(ctx->gMW.ensure((gmw.size() + 8) * 8), "alloc")) ||
+      (s = ctx->hip(ctx->gMB.ensure(gmb.size() * 8), "alloc")) ||
       (s = ctx->hip(hipMemcpy(ctx->gMW.p, gmw.data(), gmw.size() * 8, hipMemcpyHostToDevice), "upload")) ||
       (s = ctx->hip(hipMemcpy(ctx->gMB.p, gmb.data(), gmb.size() * 8, hipMemcpyHostToDevice), "upload")) ||
       (s = ctx->hip(ctx->Bmlp.ensure(bpm.size()), "alloc")) ||
@@ -383,7 +385,10 @@ svmc_status svmc_set_params(svmc_ctx* ctx, const double* theta, const double* co
   for (size_t k = 0; k < gk.size(); ++k) gk[k] = rnd_w(K[k]);
   for (size_t k = 0; k < gbias.size(); ++k) gbias[k] = rnd(Bc[k]);
   for (size_t k = 0; k < ge.size(); ++k) ge[k] = rnd_e(E[k]);
-  if ((s = ctx->hip(ctx->gK.ensure(gk.size() * 8), "alloc")) || (s = ctx->hip(ctx->gB.ensure(gbias.size() * 8), "alloc")) ||
+  // (the gradient reads the conv weights in runs of 8 doubles that may pass
+  // the end of the array by up to 7 - C / 4 values, masked: 8 doubles of slack)
+  if ((s = ctx->hip(ctx->gK.ensure((gk.size() + 8) * 8), "alloc")) ||
+      (s = ctx->hip(ctx->gB.ensure(gbias.size() * 8), "alloc")) ||
       (s = ctx->hip(ctx->gE.ensure(ge.size() * 8), "alloc")) ||
       (s = ctx->hip(hipMemcpy(ctx->gK.p, gk.data(), gk.size() * 8, hipMemcpyHostToDevice), "upload")) ||
       (s = ctx->hip(hipMemcpy(ctx->gB.p, gbias.data(), gbias.size() * 8, hipMemcpyHostToDevice), "upload")) ||
@@ -932,7 +937,8 @@ svmc_status svmc_grad_logpsi(svmc_ctx* ctx, const double* vjp_w, void* out_v, sv
   ga.ncmax = ncmax;
   ga.nsmax = nsmax;
   if ((s = ctx->hip(ctx->g_dH.ensure((size_t)chunk * ncmax * 8), "alloc gradient scratch"))) return s;
-  if ((s = ctx->hip(ctx->g_dzs.ensure((size_t)chunk * ncmax * 8), "alloc gradient scratch"))) return s;
+  // (dz is read in runs of 8 doubles: 8 doubles of slack past the last walker)
+  if ((s = ctx->hip(ctx->g_dzs.ensure(((size_t)chunk * ncmax + 8) * 8), "alloc gradient scratch"))) return s;
   if (!ga.lds && (s = ctx->hip(ctx->g_hs.ensure((size_t)chunk * ncmax * 8), "alloc gradient scratch"))) return s;
   // rows are formed in FP64: in the caller's buffer for an FP64 Jacobian, else
   // in scratch (then summed for the VJP, or rounded to FP32)

@@ -159,6 +159,7 @@ __global__ __launch_bounds__(256) void k_grad(const LatDev* __restrict__ lats, i
     __syncthreads();
     const int wave = tid >> 6, lane = tid & 63, lj = lane & 15, lk = lane >> 4;
     const int nct = (C + 15) / 16, ntr = (N + 15) / 16, ksc = C / 4;
+    constexpr int GQ = 8;            // k-steps over the channels at most (C <= 32)
     // (1) z = H W + b, dz = dH * act'(z): tiles of 16 sites x 16 outputs
     for (int tt = wave; tt < ntr * nct; tt += NTH / 64) {
       const int ti = tt / nct, tj = tt - ti * nct;
@@ -218,12 +219,19 @@ __global__ __launch_bounds__(256) void k_grad(const LatDev* __restrict__ lats, i
       const int ti = tt / nct, tj = tt - ti * nct;
       const int si = 16 * ti + lj, ci = 16 * tj + lj;
       v4d acc = v4d{0.0, 0.0, 0.0, 0.0};
-      for (int u = 0; u < ksc; ++u) {
-        const int cq = 4 * u + lk;
-        const double a = si < N ? dz[si * C + cq] : 0.0;
-        const double b = ci < C ? Wm[ci * C + cq] : 0.0;
-        mfma(acc, a, b);
+      // k-step u takes channel ksc * lk + u in lane group lk, as in the
+      // transposed conv: each lane's operands are contiguous runs
+      const double* drow = dz + (si < N ? si : 0) * C + ksc * lk;
+      const double* wrow = Wm + (ci < C ? ci : 0) * C + ksc * lk;
+      double dv[GQ], wv[GQ];
+#pragma unroll
+      for (int u = 0; u < GQ; ++u) {
+        dv[u] = drow[u];
+        wv[u] = wrow[u];
       }
+#pragma unroll
+      for (int u = 0; u < GQ; ++u)
+        if (u < ksc) mfma(acc, si < N ? dv[u] : 0.0, ci < C ? wv[u] : 0.0);
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int so = 16 * ti + lk + 4 * v;
@@ -357,16 +365,24 @@ __global__ __launch_bounds__(256) void k_grad(const LatDev* __restrict__ lats, i
         acc[v] = (so < N && ci < C) ? dH[so * C + ci] : 0.0;
       }
       double a[2][GQ], b[2][GQ];
+      // k-step u takes channel ksc * lk + u in lane group lk: each lane's
+      // channels are consecutive, so its operands of a tap are contiguous
+      // runs (wide loads; the sum over channels in another order)
       auto load = [&](int t, double (&aa)[GQ], double (&bb)[GQ]) {
         const int src = si < N ? nbt[(8 - t) * N + si] : -1;      // tap 8 - t: the opposite offset
-        const double* drow = dz + (src >= 0 ? src : 0) * C;
-        const double* kt = Kl + ((long long)t * C + ci) * C;
+        const double* drow = dz + (src >= 0 ? src : 0) * C + ksc * lk;
+        const double* kt = Kl + ((long long)t * C + (ci < C ? ci : 0)) * C + ksc * lk;
+        double dv[GQ], kv[GQ];
 #pragma unroll
         for (int u = 0; u < GQ; ++u) {
-          const int cq = 4 * u + lk;
+          dv[u] = drow[u];
+          kv[u] = kt[u];
+        }
+#pragma unroll
+        for (int u = 0; u < GQ; ++u) {
           const bool ok = u < ksc;
-          aa[u] = (ok && src >= 0) ? drow[cq] : 0.0;
-          bb[u] = (ok && ci < C) ? kt[cq] : 0.0;
+          aa[u] = (ok && src >= 0) ? dv[u] : 0.0;
+          bb[u] = (ok && ci < C) ? kv[u] : 0.0;
         }
       };
       load(0, a[0], b[0]);
