@@ -939,7 +939,8 @@ svmc_status svmc_grad_logpsi(svmc_ctx* ctx, const double* vjp_w, void* out_v, sv
   if ((s = ctx->hip(ctx->g_dH.ensure((size_t)chunk * ncmax * 8), "alloc gradient scratch"))) return s;
   // (dz is read in runs of 8 doubles: 8 doubles of slack past the last walker)
   if ((s = ctx->hip(ctx->g_dzs.ensure(((size_t)chunk * ncmax + 8) * 8), "alloc gradient scratch"))) return s;
-  if (!ga.lds && (s = ctx->hip(ctx->g_hs.ensure((size_t)chunk * ncmax * 8), "alloc gradient scratch"))) return s;
+  if (!ga.lds && (s = ctx->hip(ctx->g_hs.ensure(((size_t)chunk * ncmax + 8) * 8), "alloc gradient scratch")))
+    return s;
   // rows are formed in FP64: in the caller's buffer for an FP64 Jacobian, else
   // in scratch (then summed for the VJP, or rounded to FP32)
   const bool direct = jac && !f32;

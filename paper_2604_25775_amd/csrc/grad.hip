@@ -165,9 +165,16 @@ __global__ __launch_bounds__(256) void k_grad(const LatDev* __restrict__ lats, i
       const int ti = tt / nct, tj = tt - ti * nct;
       const int si = 16 * ti + lj, co = 16 * tj + lj;
       v4d acc = v4d{0.0, 0.0, 0.0, 0.0};
-      for (int u = 0; u < ksc; ++u) {
-        const int ci = 4 * u + lk;
-        const double a = si < N ? hp[si * C + ci] : 0.0;
+      // input channel ksc * lk + u at k-step u (contiguous H runs, as in the conv)
+      const double* hrow = hp + (si < N ? si : 0) * C + ksc * lk;
+      double hv[GQ];
+#pragma unroll
+      for (int u = 0; u < GQ; ++u) hv[u] = hrow[u];
+#pragma unroll
+      for (int u = 0; u < GQ; ++u) {
+        if (u >= ksc) break;                        // uniform
+        const int ci = ksc * lk + u;
+        const double a = si < N ? hv[u] : 0.0;
         const double b = co < C ? Wm[ci * C + co] : 0.0;
         mfma(acc, a, b);
       }
@@ -265,15 +272,19 @@ __global__ __launch_bounds__(256) void k_grad(const LatDev* __restrict__ lats, i
       // operands of tap t + 1 are requested before the products of tap t
       double a[2][GQ], b[2][GQ];
       auto load = [&](int t, double (&aa)[GQ], double (&bb)[GQ]) {
+        // k-step u takes input channel ksc * lk + u in lane group lk: the
+        // H_{l-1} operands of a lane are a contiguous run (wide reads)
         const int nb = si < N ? nbt[t * N + si] : -1;
-        const double* hrow = hp + (nb >= 0 ? nb : 0) * C;
-        const double* kt = Kl + (long long)t * C * C + co;
+        const double* hrow = hp + (nb >= 0 ? nb : 0) * C + ksc * lk;
+        const double* kt = Kl + (long long)t * C * C + co + ksc * lk * C;
+        double hv[GQ];
+#pragma unroll
+        for (int u = 0; u < GQ; ++u) hv[u] = hrow[u];
 #pragma unroll
         for (int u = 0; u < GQ; ++u) {
-          const int ci = 4 * u + lk;
           const bool ok = u < ksc;
-          aa[u] = (ok && nb >= 0) ? hrow[ci] : 0.0;
-          bb[u] = (ok && co < C) ? kt[ci * C] : 0.0;
+          aa[u] = (ok && nb >= 0) ? hv[u] : 0.0;
+          bb[u] = (ok && co < C) ? kt[u * C] : 0.0;
         }
       };
       load(0, a[0], b[0]);
