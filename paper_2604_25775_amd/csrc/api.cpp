@@ -528,7 +528,7 @@ svmc_status svmc_load_walkers(svmc_ctx* ctx, const int64_t* counts, const int8_t
       (s = ctx->hip(ctx->pos.ensure(o_pos * 2), "alloc")) || (s = ctx->hip(ctx->feat.ensure(o_feat * tfb), "alloc feat")) ||
       (s = ctx->hip(ctx->inv.ensure(o_inv * 8), "alloc inv")) ||
       (s = ctx->hip(ctx->M.ensure(std::max((size_t)o_m * 8, h0max)), "alloc M")) ||
-      (s = ctx->hip(ctx->G.ensure(o_m * 8), "alloc G")) || (s = ctx->hip(ctx->PT.ensure(o_pt * 8), "alloc PT")) ||
+      (s = ctx->hip(ctx->G.ensure(o_m * 8), "alloc G")) || (s = ctx->hip(ctx->PT.ensure((o_pt + 8) * 8), "alloc PT")) ||   // slack: the update reads P^T rows in runs
       (s = ctx->hip(ctx->ldet.ensure(Wt * 16), "alloc")) || (s = ctx->hip(ctx->sgn.ensure(Wt * 16), "alloc")) ||
       (s = ctx->hip(ctx->flags.ensure(Wt * 4), "alloc")) || (s = ctx->hip(ctx->nacc.ensure(Wt * 4), "alloc")) ||
       (s = ctx->hip(ctx->lats_dev.ensure(nl * sizeof(LatDev)), "alloc")))

@@ -508,16 +508,20 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
         const int ntj = (n + 15) / 16;
         for (int tj = wave; tj < ntj; tj += NTH / 64) {
           const int kc = 16 * tj + lj;
+          const int kcc = kc < n ? kc : n - 1;
+          // contraction index c2 = KS * lk + qq: a lane's W operands are a
+          // contiguous run of its P^T row (wide loads; past the row's end
+          // masked, slack after the array), its E operands a run of an E row
+          const double* prow = PTt + (long long)kcc * C + KS * lk;
+          double pv[KS];
+#pragma unroll
+          for (int qq = 0; qq < KS; ++qq) pv[qq] = prow[qq];
+          const double gv = gjs[kcc] - (kc == kmv ? 1.0 : 0.0);
           double bw[KS];
 #pragma unroll
           for (int qq = 0; qq < KS; ++qq) {
-            const int c2 = 4 * qq + lk;
-            double v = 0.0;
-            if (kc < n) {
-              if (c2 < C) v = PTt[(long long)kc * C + c2];
-              else if (c2 == C && hs) v = gjs[kc] - (kc == kmv ? 1.0 : 0.0);
-            }
-            bw[qq] = v;
+            const int c2 = KS * lk + qq;
+            bw[qq] = kc >= n ? 0.0 : c2 < C ? pv[qq] : (c2 == C && hs) ? gv : 0.0;
           }
           for (int ti = 0; 16 * ti < ns; ++ti) {
             v4d acc;
@@ -526,9 +530,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
               const int sr = 16 * ti + lk + 4 * v;
               acc[v] = (sr < ns && kc < n) ? Gt[(long long)(s0 + sr) * nm + kc] : 0.0;
             }
-            const double* er = ec + (16 * ti + lj) * ECS + lk;
+            const double* er = ec + (16 * ti + lj) * ECS + KS * lk;
 #pragma unroll
-            for (int qq = 0; qq < KS; ++qq) mfma(acc, er[4 * qq], bw[qq]);
+            for (int qq = 0; qq < KS; ++qq) mfma(acc, er[qq], bw[qq]);
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
               const int sr = 16 * ti + lk + 4 * v;
@@ -544,16 +548,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     // 16 rows of P^T before it writes them, and no other wavefront touches them
     for (int ti = wave; 16 * ti < n; ti += NTH / 64) {
       const int kr = 16 * ti + lj;
+      const int krc = kr < n ? kr : n - 1;
+      // contraction index c2 = KS * lk + q, as in the G update: contiguous runs
+      const double* prow = PTt + (long long)krc * C + KS * lk;
+      double pv[KS];
+#pragma unroll
+      for (int q = 0; q < KS; ++q) pv[q] = prow[q];
+      const double gv = gjs[krc] - (kr == kmv ? 1.0 : 0.0);
       double av[KS];
 #pragma unroll
       for (int q = 0; q < KS; ++q) {
-        const int c2 = 4 * q + lk;
-        double v = 0.0;
-        if (kr < n) {
-          if (c2 < C) v = PTt[(long long)kr * C + c2];
-          else if (c2 == C && hs) v = gjs[kr] - (kr == kmv ? 1.0 : 0.0);
-        }
-        av[q] = v;
+        const int c2 = KS * lk + q;
+        av[q] = kr >= n ? 0.0 : c2 < C ? pv[q] : (c2 == C && hs) ? gv : 0.0;
       }
       v4d pacc[CT];
 #pragma unroll
@@ -562,7 +568,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
         const int col = 16 * tj + lj;
 #pragma unroll
         for (int q = 0; q < KS; ++q) {
-          const int c2 = 4 * q + lk;
+          const int c2 = KS * lk + q;
           const double b2 = (c2 < RA && col < C) ? ainv[col * RA + c2] : 0.0;
           mfma(pacc[tj], av[q], b2);
         }
