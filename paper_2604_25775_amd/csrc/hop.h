@@ -1318,12 +1318,14 @@ SVMC_DEV v4d hop_det_row_build(const int* kl, int K_in, const DT* Dbuf, const do
   const int e = kl[ok ? li : 0];
   const int mrow = ok ? (e >> 16) * SD : 0, kcol = ok ? e & 0xffff : 0;
   // all operands requested at once (unconditional loads from valid
-  // addresses, masked afterwards), then the C / 4 k-steps
+  // addresses, masked afterwards), then the C / 4 k-steps; k-step q takes
+  // channel (C / 4) lk + q in lane group lk, so a lane's operands are
+  // contiguous runs of its D row and P^T row (wide loads)
   double av[C / 4], bv[C / 4];
 #pragma unroll
   for (int q = 0; q < C / 4; ++q) {
-    av[q] = (double)Dbuf[mrow + 4 * q + lk];
-    bv[q] = PTt[kcol * C + 4 * q + lk];
+    av[q] = (double)Dbuf[mrow + (C / 4) * lk + q];
+    bv[q] = PTt[kcol * C + (C / 4) * lk + q];
   }
   v4d acc = v4d{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
