@@ -11,6 +11,11 @@ the oracle evaluates one by one, plus properties checked on every walker.
   workload's 8 thermalising sweeps: sampled walkers of every lattice against
   the oracle (every ratio 1e-3, E_loc 1e-4), and the gradient rows of those
   walkers against the oracle's autograd gradient.
+* The benchmark workload (16x16, 4 x 32, f16x2, 8192 walkers after a
+  sweep): the VJP with random weights, formed launch by launch over the
+  walkers, against J^T v from the library's own Jacobian rows (1e-12 of the
+  largest |entry|), and two sampled rows against the oracle's autograd
+  gradient (2e-5, the FP32-feature bound).
 * The same three lattices and network shape in FP64, two walkers each in
   one batch: the library's gradient rows against central differences of
   the library's own log|psi| (parameters moved by +-h, the context reloaded)
@@ -127,3 +132,32 @@ def test_c4_lattices_gradient_by_finite_differences_of_the_library():
         err = float(np.max(np.abs(J[k, idx] - fd[k]))) / scale
         say(f"  walker {k}: max |J - FD| / scale {err:.2e}")
         assert err <= 1e-6
+
+
+def test_headline_vjp_against_jacobian_rows():
+    from oracle.grad import autograd_grad
+    w = wl.get("c3")
+    lat = w.lattices[0]
+    model = wl.Model(4, 32, "tanh", "f16x2", 32)
+    W = w.walkers[0]
+    say(f"[fullsize] 16x16 f16x2, {W} walkers: VJP against the Jacobian rows")
+    occ = wl.occupations(w, 0, n_walkers=W)
+    ctx, params, _ = build([lat], model, [W], occ_list=[occ])
+    ctx.sweep(1, w.seed_mc, 0)
+    o, _ = ctx.state()
+    o = o.cpu().numpy().reshape(W, lat.N)
+    v = torch.from_numpy(np.random.default_rng(3).standard_normal(W)).cuda()
+    g = ctx.grad_logpsi(v)
+    J = ctx.grad_logpsi()
+    ref = J.t().matmul(v)
+    scale = float(ref.abs().max())
+    err = float((g - ref).abs().max()) / scale
+    say(f"  VJP vs J^T v: max err / max |entry| {err:.2e}")
+    assert err <= 1e-12
+    Jh = J[[0, W - 1]].cpu().numpy()
+    del J
+    for row, k in zip(Jh, (0, W - 1)):
+        gr = autograd_grad(lat, params, o[k], 0, model.act)[1]
+        e = float(np.max(np.abs(row - gr))) / max(1.0, float(np.max(np.abs(gr))))
+        say(f"  walker {k}: row vs oracle autograd {e:.2e}")
+        assert e <= 2e-5
